@@ -1,0 +1,80 @@
+"""ORACLE -- test infrastructure only.
+
+One optimisation step of Eq. 1 (Sec. 3) for a synthetic workload: render the
+reference under the sampled cameras and lights, render the latent model,
+score the image loss (Sec. 5.3), differentiate it w.r.t. the latent
+parameters (vertex positions and level-0 texels) and apply Adam (Sec. 5.3).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import render as R
+
+
+def cameras(w):
+    """float32 MVPs and eyes of a workload's views (Sec. 3 camera sampling)."""
+    mvp, eye = R.look_at_mvp(w.dirs, w.dist, w.fov_deg, w.width, w.height)
+    return mvp.astype(np.float32), eye.astype(np.float32)
+
+
+def _levels(tex, param=None):
+    return R.texture_levels(tex.data, tex.fmt, param)
+
+
+def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True):
+    params = params or {}
+    if pos is None:
+        pos = torch.as_tensor(scene.mesh.pos, dtype=R.F64)
+    kd = _levels(scene.kd, params.get("kd"))
+    nm = _levels(scene.normal, params.get("normal"))
+    orm = _levels(scene.orm, params.get("orm")) if scene.orm is not None else None
+    return R.render(scene.mesh, scene.model, kd, nm, orm, pos, mvp32,
+                    np.asarray(eye, dtype=np.float64), np.asarray(w.light_dir, dtype=np.float64),
+                    np.asarray(w.light_rgb, dtype=np.float64), w.width, w.height, aa=aa)
+
+
+def reference_image(w, mvp32=None, eye=None):
+    if mvp32 is None:
+        mvp32, eye = cameras(w)
+    with torch.no_grad():
+        return render_scene(w.ref, mvp32, eye, w)["image"]
+
+
+def latent_params(w):
+    """float64 leaf tensors of the optimised latent parameters."""
+    out = {}
+    s = w.latent
+    for name in w.optimize:
+        if name == "pos":
+            out["pos"] = torch.tensor(s.mesh.pos, dtype=R.F64, requires_grad=True)
+        else:
+            tex = getattr(s, name)
+            assert tex.fmt == "f32", "only float32 maps are optimised"
+            out[name] = torch.tensor(tex.data, dtype=R.F64, requires_grad=True)
+    return out
+
+
+def loss_and_grads(w, ref_img, mvp32=None, eye=None, params=None, aa=True):
+    """Forward + backward of the latent render: (loss, grads, render dict)."""
+    if mvp32 is None:
+        mvp32, eye = cameras(w)
+    params = params if params is not None else latent_params(w)
+    out = render_scene(w.latent, mvp32, eye, w, pos=params.get("pos"), params=params, aa=aa)
+    loss = R.image_loss(out["image"], ref_img, w.loss)
+    leaves = [params[k] for k in params]
+    gl = torch.autograd.grad(loss, leaves, allow_unused=True)
+    grads = {k: (g if g is not None else torch.zeros_like(params[k])) for k, g in zip(params, gl)}
+    return loss.detach(), grads, out
+
+
+def adam_update(params, grads, state, t, lr):
+    """Adam on every parameter (Sec. 5.3); state maps name -> (m, v)."""
+    new = {}
+    for k, p in params.items():
+        m, v = state.get(k, (np.zeros(p.shape), np.zeros(p.shape)))
+        pn, m, v = R.adam(p.detach().numpy(), grads[k].numpy(), m, v, t, lr)
+        state[k] = (m, v)
+        new[k] = pn
+    return new, state

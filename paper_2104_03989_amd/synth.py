@@ -1,0 +1,377 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only draws and lays out inputs: geodesic spheres, their UV
+parameterisation, radial displacement fields, value-noise texture maps and
+random view/light directions.  It holds none of the render loop's arithmetic
+(no projection, rasterization, shading, loss or optimiser step), so that the
+GPU path and the FP64 oracle can both consume the same inputs while sharing no
+computation.
+
+The paper's assets (Smithsonian scans, the Paragon character, Moana) are not
+available; the shapes below stand in for them with the triangle counts,
+texture sizes and view counts of the experiments in Sec. 4.1 (normal-map
+baking, complex materials, displacement baking).
+
+Every random draw goes through ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BASE_SEED = 2104_03989
+
+
+def seed_for(config: int, item: int) -> int:
+    """Seed of input ``item`` of workload ``config``."""
+    return BASE_SEED + config * 1000 + item
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# Geodesic sphere of frequency nu: 20 nu^2 triangles, 10 nu^2 + 2 vertices.
+# ---------------------------------------------------------------------------
+
+_T = (1.0 + 5.0 ** 0.5) / 2.0
+_ICO_V = np.array(
+    [(-1, _T, 0), (1, _T, 0), (-1, -_T, 0), (1, -_T, 0),
+     (0, -1, _T), (0, 1, _T), (0, -1, -_T), (0, 1, -_T),
+     (_T, 0, -1), (_T, 0, 1), (-_T, 0, -1), (-_T, 0, 1)], dtype=np.float64)
+_ICO_F = np.array(
+    [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+     (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+     (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+     (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)], dtype=np.int64)
+
+
+def _pole_rotation() -> np.ndarray:
+    # rotate about z so that corner 0 lies on +y (and corner 3 on -y): every
+    # frequency then has a vertex exactly at each pole of the UV mapping
+    a = _ICO_V[0] / np.linalg.norm(_ICO_V[0])
+    ang = math.atan2(a[0], a[1])
+    c, s = math.cos(ang), math.sin(ang)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+_ICO_V = _ICO_V @ _pole_rotation().T
+
+
+def geodesic_sphere(nu: int):
+    """Unit geodesic sphere: each icosahedron face split into nu^2 triangles.
+
+    Returns (dirs [V,3] float64 unit vectors, tri [T,3] int32), triangles
+    wound counter-clockwise seen from outside.  nu = 2^k gives the same
+    counts as an icosphere subdivided k times.
+    """
+    nu = int(nu)
+    if nu < 1:
+        raise ValueError("nu must be >= 1")
+    ii, jj = [], []
+    for i in range(nu + 1):
+        for j in range(nu + 1 - i):
+            ii.append(i)
+            jj.append(j)
+    ii = np.array(ii, dtype=np.int64)
+    jj = np.array(jj, dtype=np.int64)
+    npf = ii.size
+    local = -np.ones((nu + 1, nu + 1), dtype=np.int64)
+    local[ii, jj] = np.arange(npf)
+    # integer barycentric weights on the 12 icosahedron corners
+    keys = np.zeros((20 * npf, 12), dtype=np.int32)
+    for f, (a, b, c) in enumerate(_ICO_F):
+        rows = slice(f * npf, (f + 1) * npf)
+        keys[rows, a] += (nu - ii - jj).astype(np.int32)
+        keys[rows, b] += ii.astype(np.int32)
+        keys[rows, c] += jj.astype(np.int32)
+    uniq, inverse = np.unique(keys, axis=0, return_inverse=True)
+    inverse = inverse.reshape(-1)
+    pts = uniq.astype(np.float64) @ _ICO_V
+    dirs = pts / np.linalg.norm(pts, axis=1, keepdims=True)
+    # local triangles of one face
+    up = [(local[i, j], local[i + 1, j], local[i, j + 1])
+          for i in range(nu) for j in range(nu - i)]
+    down = [(local[i + 1, j], local[i + 1, j + 1], local[i, j + 1])
+            for i in range(nu - 1) for j in range(nu - 1 - i)]
+    loc = np.array(up + down, dtype=np.int64)
+    tris = np.concatenate([inverse[f * npf + loc] for f in range(20)], axis=0)
+    assert dirs.shape[0] == 10 * nu * nu + 2
+    assert tris.shape[0] == 20 * nu * nu
+    return dirs, tris.astype(np.int32)
+
+
+def sphere_uv(dirs: np.ndarray, tri: np.ndarray):
+    """Equirectangular UVs with a separate UV index buffer.
+
+    u = 0.5 + atan2(z, x) / 2pi, v = acos(y) / pi.  Triangles straddling the
+    u seam get u + 1 on their low side (texture lookups wrap in u); a pole
+    corner takes the mean u of its triangle's two other corners.  Returns
+    (uv [Vt,2] float32, uv_tri [T,3] int32).
+    """
+    y = np.clip(dirs[:, 1], -1.0, 1.0)
+    u = 0.5 + np.arctan2(dirs[:, 2], dirs[:, 0]) / (2.0 * math.pi)
+    v = np.arccos(y) / math.pi
+    pole = np.abs(np.abs(y) - 1.0) < 1e-12
+    cu = u[tri].copy()
+    cv = v[tri].copy()
+    cpole = pole[tri]
+    big = 1e9
+    lo = np.where(cpole, big, cu).min(axis=1)
+    hi = np.where(cpole, -big, cu).max(axis=1)
+    seam = (hi - lo) > 0.5
+    fix = seam[:, None] & (cu < 0.5) & ~cpole
+    cu = np.where(fix, cu + 1.0, cu)
+    n_np = (~cpole).sum(axis=1)
+    mean_u = np.where(cpole, 0.0, cu).sum(axis=1) / np.maximum(n_np, 1)
+    cu = np.where(cpole, mean_u[:, None], cu)
+    corners = np.stack([cu.reshape(-1), cv.reshape(-1)], axis=1)
+    uniq, inv = np.unique(corners, axis=0, return_inverse=True)
+    return uniq.astype(np.float32), inv.reshape(-1, 3).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Radial displacement fields
+# ---------------------------------------------------------------------------
+
+def _real_sh(lmax: int, dirs: np.ndarray) -> np.ndarray:
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(dirs[:, 2], -1.0, 1.0))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    cols = []
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                cols.append(math.sqrt(2.0) * (-1) ** m * y.real)
+            elif m < 0:
+                cols.append(math.sqrt(2.0) * (-1) ** m * y.imag)
+            else:
+                cols.append(y.real)
+    return np.stack(cols, axis=1)
+
+
+def sh_radius(dirs: np.ndarray, seed: int, lmax: int = 6, sigma: float = 0.05):
+    """r = 1 + sum_{l<=lmax,m} c_lm Y_lm(d), c_lm ~ N(0, sigma^2)."""
+    basis = _real_sh(lmax, dirs)
+    c = _rng(seed).normal(0.0, sigma, size=basis.shape[1])
+    return 1.0 + basis @ c
+
+
+class _Noise3:
+    """Seeded 3-D value noise in [-1, 1] on the integer lattice."""
+
+    def __init__(self, seed: int):
+        g = _rng(seed)
+        self.perm = g.permutation(256).astype(np.int64)
+        self.vals = g.uniform(-1.0, 1.0, size=256)
+
+    def _lat(self, ix, iy, iz):
+        p = self.perm
+        h = p[(p[(p[ix & 255] + iy) & 255] + iz) & 255]
+        return self.vals[h]
+
+    def __call__(self, pts: np.ndarray) -> np.ndarray:
+        f = np.floor(pts)
+        i = f.astype(np.int64)
+        t = pts - f
+        s = t * t * (3.0 - 2.0 * t)
+        out = np.zeros(pts.shape[0])
+        for dx in (0, 1):
+            wx = s[:, 0] if dx else 1.0 - s[:, 0]
+            for dy in (0, 1):
+                wy = s[:, 1] if dy else 1.0 - s[:, 1]
+                for dz in (0, 1):
+                    wz = s[:, 2] if dz else 1.0 - s[:, 2]
+                    out += wx * wy * wz * self._lat(i[:, 0] + dx, i[:, 1] + dy, i[:, 2] + dz)
+        return out
+
+
+def fbm_radius(dirs: np.ndarray, seed: int, octaves: int = 6, amp: float = 0.1):
+    """r = 1 + amp * sum_{o<octaves} 0.5^o * vnoise(2^(o+1) d)."""
+    n = _Noise3(seed)
+    acc = np.zeros(dirs.shape[0])
+    for o in range(octaves):
+        acc += 0.5 ** o * n(dirs * 2.0 ** (o + 1))
+    return 1.0 + amp * acc
+
+
+# ---------------------------------------------------------------------------
+# Texture maps (value noise on an 8x8 lattice, periodic in u)
+# ---------------------------------------------------------------------------
+
+def _interp_matrix(size: int, cells: int, periodic: bool) -> np.ndarray:
+    x = (np.arange(size) + 0.5) / size * cells - 0.5
+    x0 = np.floor(x).astype(np.int64)
+    t = x - x0
+    s = t * t * (3.0 - 2.0 * t)
+    n = cells if periodic else cells + 1
+    m = np.zeros((size, n))
+    for off, w in ((0, 1.0 - s), (1, s)):
+        idx = x0 + off
+        idx = np.mod(idx, cells) if periodic else np.clip(idx + 0, 0, cells)
+        np.add.at(m, (np.arange(size), idx), w)
+    return m
+
+
+def value_noise_map(size: int, channels: int, seed: int, cells: int = 8) -> np.ndarray:
+    """[size, size, channels] float64 in [0, 1); row index is v, column is u."""
+    g = _rng(seed)
+    lat = g.uniform(0.0, 1.0, size=(channels, cells + 1, cells))
+    wu = _interp_matrix(size, cells, periodic=True)
+    wv = _interp_matrix(size, cells, periodic=False)
+    out = np.einsum("vi,cij,uj->vuc", wv, lat, wu)
+    return np.clip(out, 0.0, np.nextafter(1.0, 0.0))
+
+
+def to_rgba8(rgb: np.ndarray) -> np.ndarray:
+    """Quantise [0,1) colours to RGBA8 (alpha 255)."""
+    q = np.clip(np.floor(rgb * 256.0), 0, 255).astype(np.uint8)
+    a = np.full(rgb.shape[:2] + (1,), 255, dtype=np.uint8)
+    return np.concatenate([q[..., :3], a], axis=-1)
+
+
+def detail_normal_map(size: int, seed: int, tilt: float = 0.2) -> np.ndarray:
+    """Tangent-space normals (tilt*(2n-1), tilt*(2n-1), sqrt(1-x^2-y^2))."""
+    n = value_noise_map(size, 2, seed)
+    xy = tilt * (2.0 * n - 1.0)
+    z = np.sqrt(1.0 - (xy ** 2).sum(-1, keepdims=True))
+    return np.concatenate([xy, z], axis=-1)
+
+
+def flat_normal_map(size: int) -> np.ndarray:
+    out = np.zeros((size, size, 3))
+    out[..., 2] = 1.0
+    return out
+
+
+def orm_map(size: int, seed: int, r_lo: float = 0.2, r_hi: float = 0.8) -> np.ndarray:
+    """(gamma=0, roughness in [r_lo, r_hi], metalness in [0,1))."""
+    n = value_noise_map(size, 2, seed)
+    g = np.zeros((size, size, 1))
+    r = r_lo + (r_hi - r_lo) * n[..., :1]
+    m = n[..., 1:2]
+    return np.concatenate([g, r, m], axis=-1)
+
+
+# ---------------------------------------------------------------------------
+# Views and lights
+# ---------------------------------------------------------------------------
+
+def random_unit(n: int, seed: int) -> np.ndarray:
+    """n directions uniform on the unit sphere (normalised N(0, I3))."""
+    g = _rng(seed).normal(size=(n, 3))
+    return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+# ---------------------------------------------------------------------------
+# Scenes
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Mesh:
+    pos: np.ndarray      # [V,3] float32
+    tri: np.ndarray      # [T,3] int32
+    uv: np.ndarray       # [Vt,2] float32
+    uv_tri: np.ndarray   # [T,3] int32
+
+
+@dataclasses.dataclass
+class Texture:
+    """Level-0 texel data; rows are v, columns are u."""
+    data: np.ndarray     # [S,S,C] float32, or [S,S,4] uint8 for RGBA8
+    fmt: str             # "f32" or "rgba8"
+
+
+@dataclasses.dataclass
+class Scene:
+    mesh: Mesh
+    model: str           # "blinn_phong" or "ggx"
+    kd: Texture
+    normal: Texture
+    orm: Texture | None
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    ref: Scene
+    latent: Scene
+    dirs: np.ndarray        # [B,3] camera directions (eye = dist * dir)
+    light_dir: np.ndarray   # [B,3] unit, towards the light
+    light_rgb: np.ndarray   # [B,3]
+    width: int
+    height: int
+    dist: float
+    fov_deg: float
+    loss: str               # "l1", "l1_tonemap", "l2", "l2_tonemap"
+    lr: float
+    optimize: tuple         # names among "pos", "kd", "normal", "orm"
+
+
+def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> Mesh:
+    dirs, tri = geodesic_sphere(nu)
+    uv, uv_tri = sphere_uv(dirs, tri)
+    r = np.ones(dirs.shape[0]) if radius_fn is None else radius_fn(dirs)
+    pos = dirs * r[:, None]
+    if jitter > 0.0:
+        pos = pos + _rng(seed).normal(0.0, jitter, size=pos.shape)
+    return Mesh(pos.astype(np.float32), tri, uv, uv_tri)
+
+
+def _f32(x):
+    return Texture(np.ascontiguousarray(x, dtype=np.float32), "f32")
+
+
+def workload_plain_step(views: int = 4, res: int = 256, map_size: int = 256,
+                        ref_nu: int = 32, lat_nu: int = 8) -> Workload:
+    """Plain single step: icosphere(3x) vs SH-displaced icosphere(5x), Lambert
+    + Blinn-Phong, RGBA8 base colour shared and fixed, FP32 normal map
+    optimised from flat, 4 views at 256^2, one directional light, L1 loss."""
+    c = 1
+    kd = Texture(to_rgba8(value_noise_map(map_size, 3, seed_for(c, 1))), "rgba8")
+    ref_mesh = sphere_mesh(ref_nu, lambda d: sh_radius(d, seed_for(c, 2)))
+    lat_mesh = sphere_mesh(lat_nu, None, jitter=0.01, seed=seed_for(c, 3))
+    ref = Scene(ref_mesh, "blinn_phong", kd, _f32(detail_normal_map(map_size, seed_for(c, 4))), None)
+    lat = Scene(lat_mesh, "blinn_phong", kd, _f32(flat_normal_map(map_size)), None)
+    dirs = random_unit(views, seed_for(c, 5))
+    light = np.repeat(random_unit(1, seed_for(c, 6)), views, axis=0)
+    return Workload("plain_step", ref, lat, dirs, light, np.ones((views, 3)), res, res,
+                    3.0, 45.0, "l1", 1e-3, ("pos", "normal"))
+
+
+def workload_paper_loop(views: int = 8, res: int = 512, map_size: int = 2048,
+                        ref_nu: int = 122, lat_nu: int = 19) -> Workload:
+    """Paper-scale loop: ~300k-tri fbm sphere with 2048^2 base colour
+    (RGBA8), normal and ORM maps under GGX; ~7k-tri latent resampled on the
+    same fbm surface with 2048^2 FP32 normal and base-colour maps; 8 views
+    at 512^2, one random directional light per view, tonemapped L1."""
+    c = 2
+    rad = lambda d: fbm_radius(d, seed_for(c, 1))
+    ref_mesh = sphere_mesh(ref_nu, rad)
+    lat_mesh = sphere_mesh(lat_nu, rad)
+    kd_ref = Texture(to_rgba8(value_noise_map(map_size, 3, seed_for(c, 2))), "rgba8")
+    ref = Scene(ref_mesh, "ggx", kd_ref, _f32(detail_normal_map(map_size, seed_for(c, 3))),
+                _f32(orm_map(map_size, seed_for(c, 4))))
+    kd_lat = _rng(seed_for(c, 5)).uniform(0.0, 1.0, size=(map_size, map_size, 3))
+    orm_lat = np.array([0.0, 0.5, 0.0]).reshape(1, 1, 3)
+    lat = Scene(lat_mesh, "ggx", _f32(kd_lat), _f32(flat_normal_map(map_size)), _f32(orm_lat))
+    dirs = random_unit(views, seed_for(c, 6))
+    light = random_unit(views, seed_for(c, 7))
+    return Workload("paper_loop", ref, lat, dirs, light, np.ones((views, 3)), res, res,
+                    3.0, 45.0, "l1_tonemap", 2e-3, ("pos", "kd", "normal"))
+
+
+def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:
+    """Same scene with fewer views and/or another resolution (test sizes)."""
+    out = dataclasses.replace(w)
+    if views is not None:
+        out.dirs = w.dirs[:views]
+        out.light_dir = w.light_dir[:views]
+        out.light_rgb = w.light_rgb[:views]
+    if res is not None:
+        out.width = out.height = res
+    return out

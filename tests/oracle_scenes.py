@@ -1,0 +1,58 @@
+"""Small hand-built scenes for the oracle pins (input layout only)."""
+import numpy as np
+
+from paper_2104_03989_amd import synth
+
+
+def const_tex(value, size=4):
+    v = np.asarray(value, dtype=np.float32)
+    return synth.Texture(np.tile(v, (size, size, 1)), "f32")
+
+
+def flat_normals(size=4):
+    return synth.Texture(synth.flat_normal_map(size).astype(np.float32), "f32")
+
+
+def quad_mesh(z=0.0, half=1.0):
+    pos = np.array([(-half, -half, z), (half, -half, z), (-half, half, z), (half, half, z)],
+                   dtype=np.float32)
+    tri = np.array([(0, 1, 3), (0, 3, 2)], dtype=np.int32)
+    uv = ((pos[:, :2] / half + 1.0) / 2.0).astype(np.float32)
+    return synth.Mesh(pos, tri, uv, tri.copy())
+
+
+def workload(ref, latent, dirs, light, W, H, loss="l1", optimize=("pos",), light_rgb=None):
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    B = dirs.shape[0]
+    light = np.asarray(light, dtype=np.float64).reshape(-1, 3)
+    light = light / np.linalg.norm(light, axis=1, keepdims=True)
+    if light.shape[0] == 1:
+        light = np.repeat(light, B, axis=0)
+    rgb = np.ones((B, 3)) if light_rgb is None else np.asarray(light_rgb, dtype=np.float64)
+    return synth.Workload("test", ref, latent, dirs, light, rgb, W, H, 3.0, 45.0, loss, 1e-3,
+                          tuple(optimize))
+
+
+def tiny_sphere_workload(model="blinn_phong", nu=2, res=24, views=1, tex=8, loss="l1",
+                         seed=0):
+    g = np.random.default_rng(seed)
+    ref_mesh = synth.sphere_mesh(nu + 1, lambda d: synth.sh_radius(d, 100 + seed, lmax=3, sigma=0.08))
+    lat_mesh = synth.sphere_mesh(nu, lambda d: synth.sh_radius(d, 200 + seed, lmax=3, sigma=0.05))
+    def tex3(lo, hi):
+        return synth.Texture(g.uniform(lo, hi, size=(tex, tex, 3)).astype(np.float32), "f32")
+    def nmap(tilt):
+        return synth.Texture(synth.detail_normal_map(tex, 300 + seed, tilt).astype(np.float32), "f32")
+    orm_ref = orm_lat = None
+    if model == "ggx":
+        orm_ref = synth.Texture(synth.orm_map(tex, 400 + seed).astype(np.float32), "f32")
+        o = synth.orm_map(tex, 500 + seed)
+        o[..., 0] = g.uniform(0.0, 0.3, size=(tex, tex))
+        orm_lat = synth.Texture(o.astype(np.float32), "f32")
+    ref = synth.Scene(ref_mesh, model, tex3(0.1, 0.9), nmap(0.2), orm_ref)
+    lat = synth.Scene(lat_mesh, model, tex3(0.1, 0.9), nmap(0.1), orm_lat)
+    dirs = synth.random_unit(views, 600 + seed)
+    light = synth.random_unit(views, 700 + seed)
+    # light roughly from the camera side so that most pixels are lit
+    light = light + 1.5 * dirs
+    opt = ("pos", "kd", "normal", "orm") if model == "ggx" else ("pos", "kd", "normal")
+    return workload(ref, lat, dirs, light, res, res, loss=loss, optimize=opt)
