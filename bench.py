@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the appearance-driven simplification step on one MI355X.
+
+A step is one pass of the whole render loop: sample cameras and lights
+(drawn ahead of time, resident in HBM), render the reference model, render
+the latent model with its loss, run the hand-written backward pass into
+vertex positions and texels, and apply Adam.  The workload is the
+paper-scale loop: a ~300k-triangle fbm-displaced sphere with 2048^2 base
+colour, normal and ORM maps under GGX as the reference, a ~7k-triangle
+latent sphere with 2048^2 float32 base-colour and normal maps and full mip
+chains, 8 views of 512x512 per step, one random directional light per view,
+L1 loss on tone-mapped colours.  Inputs are seeded synthetic stand-ins for
+the paper's scanned assets.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one
+GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_step(w, ctx, adr, torch, np, n_steps, seed):
+    """Upload the workload and return (step(t) closure, state)."""
+    ref_mesh = adr.DeviceMesh(w.ref.mesh)
+    ref_mat = adr.DeviceMaterial(w.ref, ctx=ctx)
+    lat_mesh = adr.DeviceMesh(w.latent.mesh)
+    lat_mat = adr.DeviceMaterial(w.latent, ctx=ctx)
+    B, H, W = w.dirs.shape[0], w.height, w.width
+    # cameras and lights of every step, drawn on the host ahead of time
+    g = np.random.Generator(np.random.PCG64(seed))
+    dirs = g.normal(size=(n_steps, B, 3))
+    lights = g.normal(size=(n_steps, B, 3))
+    lights /= np.linalg.norm(lights, axis=2, keepdims=True)
+    mvps, eyes = [], []
+    for t in range(n_steps):
+        m, e = adr.views_build(dirs[t], w.dist, w.fov_deg, W, H)
+        mvps.append(m)
+        eyes.append(e)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    mvp_d, eye_d, light_d = dev(np.stack(mvps)), dev(np.stack(eyes)), dev(lights)
+    rgb_d = dev(np.ones((n_steps, B, 3)))
+    views = [adr.DeviceViews(mvp_d[t], eye_d[t], light_d[t], rgb_d[t], W, H) for t in range(n_steps)]
+    # optimised parameters: positions and level 0 of the F32 maps
+    params = []
+    grads = {"pos": torch.zeros_like(lat_mesh.pos)}
+    params.append((lat_mesh.pos, grads["pos"]))
+    for name in ("kd", "normal", "orm"):
+        if name not in w.optimize:
+            grads[name] = None
+            continue
+        tex = getattr(lat_mat, name)
+        grads[name] = tex.grad_buffer()
+        n0 = tex.size * tex.size
+        params.append((tex.data[:n0], grads[name][:n0]))
+    adam = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
+    n_params = sum(p.numel() for p, _ in params)
+    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, views[0])
+    lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_out["image"], loss=w.loss,
+                             flags=adr.FWD_BUILD_MIPS, want_image=False, want_tri_id=True)
+
+    def step(t):
+        v = views[t % n_steps]
+        adr.render_fwd(ctx, ref_mesh, ref_mat, v, outputs=ref_out)
+        adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_out["image"], loss=w.loss,
+                       flags=adr.FWD_BUILD_MIPS, outputs=lat_out)
+        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads)
+        lr = w.lr * 10.0 ** (-0.0002 * t)
+        adr.adam_step(ctx, adam, t + 1, lr)
+
+    state = dict(ref_mesh=ref_mesh, lat_mesh=lat_mesh, lat_mat=lat_mat, lat_out=lat_out,
+                 ref_out=ref_out, n_params=n_params, views=views, adam=adam)
+    return step, state
+
+
+def algorithmic_bytes(stage, w, st, covered_latent):
+    """Compulsory HBM bytes of one launch of a stage (pixel, vertex and
+    parameter streams; texel re-reads that hit in cache are not counted)."""
+    B, H, W = w.dirs.shape[0], w.height, w.width
+    px = B * H * W
+    if stage == "adam":
+        return 32.0 * st["n_params"]                      # read p,g,m,v; write p,m,v,g
+    if stage == "shade_bwd":
+        return covered_latent * (8 + 12)                  # visibility key + dL/dcolour
+    if stage == "aa_bwd":
+        return px * (8 + 12 + 12 + 12)                    # key, colour, dL/dimage, dL/dcolour
+    if stage == "aa_loss":
+        return px * (8 + 12 + 12 + 12) / 2.0              # per render (two per step, averaged)
+    if stage == "shade":
+        return px * (8 + 12)                              # key in, colour out
+    return None
+
+
+def cpu_baseline(w, np, torch):
+    """The FP64 oracle on two of the step's views (full meshes and maps)."""
+    from oracle import loop as OL
+    from paper_2104_03989_amd import synth
+    w1 = synth.scaled(w, views=2)
+    t0 = time.perf_counter()
+    mvp32, eye = OL.cameras(w1)
+    ref = OL.reference_image(w1, mvp32, eye)
+    params = OL.latent_params(w1)
+    loss, grads, _ = OL.loss_and_grads(w1, ref, mvp32, eye, params)
+    OL.adam_update(params, grads, {}, 1, w1.lr)
+    dt = time.perf_counter() - t0
+    return dict(value=2 * w1.width * w1.height / dt / 1e6, unit="Mpix/s", cores=torch.get_num_threads(),
+                kind="oracle", sample="2 of the 8 views of one step (full 300k/7k-triangle meshes, "
+                "2048^2 maps, 512x512): reference render, latent render, loss, backward, Adam",
+                seconds=round(dt, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without stage events")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2104_03989_amd import adr, synth
+
+    torch.cuda.set_device(0)
+    _log("generating workload")
+    w = synth.workload_paper_loop()
+    B, H, W = w.dirs.shape[0], w.height, w.width
+    ctx = adr.Context(0)
+    n_steps = args.warmup + args.steps
+    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(2, 100))
+    torch.cuda.synchronize()
+    covered = int((st["lat_out"]["tri_id"] > 0).sum())
+    _log(f"warmup {args.warmup}")
+    for t in range(args.warmup):
+        step(t)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        ctx.profile(True)
+        ctx.profile_read()
+    _log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, n_steps):
+        step(t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = ctx.profile_read() if not args.no_profile else {}
+    loss = float(st["lat_out"]["loss"][0])
+    ms_step = dt / args.steps * 1e3
+    mpix = B * H * W * args.steps / dt / 1e6
+    # dominant stage and its roofline
+    roof = None
+    prof = {}
+    if stages:
+        prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1] > 0}
+        per_step = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
+        dom = max(per_step, key=per_step.get)
+        ms, cnt = stages[dom]
+        avg_ms = ms / cnt
+        by = algorithmic_bytes(dom, w, st, covered)
+        if by is not None:
+            ach = by / (avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": by}
+        else:
+            roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        _log("oracle baseline")
+        cpu = cpu_baseline(w, np, torch)
+    rec = {
+        "metric": "fwd+bwd Mpix/s (latent pixels per second, reference render and Adam included)",
+        "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "steps_per_s": round(1e3 / ms_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale loop: 297,680-tri GGX reference, 7,220-tri latent, "
+                               "2048^2 maps, 8 views x 512x512, tone-mapped L1, Adam",
+                   "views": B, "res": [W, H], "ref_tris": int(w.ref.mesh.tri.shape[0]),
+                   "latent_tris": int(w.latent.mesh.tri.shape[0]), "params": st["n_params"],
+                   "final_loss": round(loss, 6)},
+        "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

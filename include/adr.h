@@ -1,0 +1,278 @@
+/*
+ * adr.h -- C ABI of an MI355X (gfx950) implementation of the per-step
+ * differentiable render loop of appearance-driven 3D model simplification
+ * (Hasselgren, Munkberg, Lehtinen, Aittala, Laine: "Appearance-Driven
+ * Automatic 3D Model Simplification").
+ *
+ * One optimisation step of the paper's objective (Sec. 3, Eq. 1) is
+ *   adr_render_fwd(reference)  -> reference images I_ref(c, l)
+ *   adr_render_fwd(latent)     -> latent images I_theta(c, l), image loss
+ *   adr_render_bwd(latent)     -> dL/dtheta for vertex positions and texels
+ *   adr_adam_step(theta)       -> Adam update (Sec. 5.3)
+ * and adr_job_submit / adr_job_poll run whole optimisations (the paper's
+ * statement of the problem: reference model, view/light distribution and
+ * initial latent mesh and maps in, optimised mesh and maps out) inside the
+ * library.
+ *
+ * Conventions
+ *  - Pointers documented "device" are HIP device allocations (any allocator,
+ *    e.g. PyTorch's); "host" pointers are ordinary CPU memory.
+ *  - Every call validates its arguments before it launches anything and
+ *    returns ADR_E_INVALID (with a message in adr_last_error()) on a bad
+ *    shape, pointer or enum.  No C++ exception and no abort crosses the ABI.
+ *  - render/adam calls enqueue work on `stream` and return without waiting;
+ *    asynchronous HIP faults surface as ADR_E_HIP at the next synchronising
+ *    call.  They BORROW caller memory until that stream work completes.
+ *  - A context owns only scratch memory (grown on demand) and must be used
+ *    by one host thread and one stream at a time; use one context per
+ *    stream for concurrent work.
+ *  - Images are [B, H, W, 3] float32 with row 0 at the bottom of the
+ *    picture; vertex arrays are [n, 3] float32 row-major.
+ */
+#ifndef ADR_H
+#define ADR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t adr_status;
+#define ADR_OK 0
+#define ADR_PENDING 1            /* job queued or running */
+#define ADR_E_INVALID (-1)       /* bad shape, pointer or enum */
+#define ADR_E_NOMEM (-2)         /* device or host allocation failed */
+#define ADR_E_HIP (-3)           /* a HIP runtime call failed */
+#define ADR_E_OVER_BUDGET (-4)   /* job can never fit the context's HBM budget */
+#define ADR_E_NOTFOUND (-5)      /* unknown job id */
+#define ADR_E_NONFINITE (-6)     /* job stopped on a non-finite loss or gradient */
+#define ADR_E_UNIMPL (-7)        /* combination not implemented */
+
+typedef struct adr_ctx adr_ctx;
+typedef void* adr_stream;        /* hipStream_t; NULL = the legacy default stream */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* adr_last_error(void);
+
+/* Context on HIP device `device`.  hbm_budget_bytes bounds the memory the job
+ * server may keep resident (0 = free memory at creation minus 4 GiB). */
+adr_status adr_ctx_create(int32_t device, uint64_t hbm_budget_bytes, adr_ctx** out);
+adr_status adr_ctx_destroy(adr_ctx* ctx);
+
+/* ------------------------------------------------------------------ data */
+
+#define ADR_TEX_F32 0            /* float32 texels, `channels` of them */
+#define ADR_TEX_RGBA8 1          /* 4 x uint8 unorm texels (x/255), rgb used */
+
+/* A square power-of-two texture with its mip chain, level-major and
+ * contiguous: level l has s_l = max(1, size >> l) rows of s_l texels, row r
+ * holding texel rows v, starting at texel offset sum_{k<l} s_k^2.  Texel
+ * centres sit at (i + 0.5) / s_l; lookups wrap in u and clamp in v. */
+typedef struct adr_texture {
+  void* data;                    /* device */
+  int32_t size;                  /* level-0 width = height, power of two, 1..16384 */
+  int32_t levels;                /* 1 .. log2(size) + 1 */
+  int32_t channels;              /* F32: 1 or 3; RGBA8: 4 */
+  int32_t format;                /* ADR_TEX_F32 or ADR_TEX_RGBA8 */
+} adr_texture;
+
+/* Triangle mesh with a separate UV index buffer (UV seams do not split
+ * position vertices).  Triangles are listed counter-clockwise seen from
+ * outside; both windings are rasterized. */
+typedef struct adr_mesh {
+  const float* pos;              /* device [n_pos, 3] */
+  const int32_t* tri;            /* device [n_tri, 3] indices into pos */
+  const float* uv;               /* device [n_uv, 2] */
+  const int32_t* uv_tri;         /* device [n_tri, 3] indices into uv */
+  const int32_t* adj;            /* device [n_tri, 3]: triangle across the edge opposite
+                                    corner k, -1 on a boundary (adr_mesh_adjacency) */
+  int32_t n_pos, n_tri, n_uv;
+} adr_mesh;
+
+#define ADR_SHADE_BLINN_PHONG 0  /* E max(0,n.l) (kd + 0.04 max(0,n.h)^32) */
+#define ADR_SHADE_GGX 1          /* diffuse + isotropic GGX lobe, Sec. 5.2 */
+
+/* Materials of Sec. 5.2: base colour k_d, tangent-space normal map and, for
+ * GGX, the (gamma, roughness, metalness) map with
+ * k_s = (1-m) 0.04 + m k_d and k_s' = (1-gamma) k_s. */
+typedef struct adr_material {
+  int32_t model;                 /* ADR_SHADE_* */
+  adr_texture kd;                /* F32 3 channels or RGBA8 */
+  adr_texture normal;            /* F32 3 channels, tangent space (x along T, y along N x T, z along N) */
+  adr_texture orm;               /* F32 3 channels (gamma, r, m); GGX only */
+} adr_material;
+
+/* B cameras and directional lights (Sec. 3: random camera and light per
+ * iteration). */
+typedef struct adr_views {
+  const float* mvp;              /* device [B, 16], row-major clip = M [p, 1] (OpenGL clip space) */
+  const float* eye;              /* device [B, 3] camera position */
+  const float* light_dir;        /* device [B, 3] unit vector towards the light */
+  const float* light_rgb;        /* device [B, 3] light radiance */
+  int32_t n_views, width, height;/* 1..4096 views, 1..4096 pixels per side */
+} adr_views;
+
+#define ADR_LOSS_L1 0            /* mean |x - ref| */
+#define ADR_LOSS_L1_TONEMAP 1    /* mean |T(x) - T(ref)|, T(x) = Gamma_sRGB(log(x + 1)), Sec. 5.3 */
+#define ADR_LOSS_L2 2            /* mean (x - ref)^2 (aggregate geometry, Sec. 4.4) */
+#define ADR_LOSS_L2_TONEMAP 3    /* mean (T(x) - T(ref))^2 */
+
+/* Forward outputs, caller-owned device buffers.  vis, color and (when a
+ * reference image is given) dimage are the state adr_render_bwd reads; the
+ * G-buffer itself is never stored, the backward pass recomputes it. */
+typedef struct adr_fwd_out {
+  uint64_t* vis;                 /* [B,H,W] required: depth << 32 | (triangle + 1), empty
+                                    pixels 0xFFFFFFFF00000000 */
+  float* color;                  /* [B,H,W,3] required: shaded colour before antialiasing */
+  float* image;                  /* [B,H,W,3] nullable: antialiased image */
+  float* dimage;                 /* [B,H,W,3] required with a reference: dL/d image */
+  float* loss;                   /* [1] required with a reference: the image loss */
+  int32_t* tri_id;               /* [B,H,W] nullable: 0 empty, else triangle + 1 */
+  uint32_t* coverage;            /* [B,H,W] nullable: covering triangles before the depth test */
+} adr_fwd_out;
+
+#define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
+#define ADR_FWD_NO_AA 2          /* skip silhouette antialiasing (image = color) */
+
+/* Render B views of a mesh (Sec. 3 and 5.2): vertex normals and tangents
+ * (Sec. 5.1), fixed-point rasterization, perspective-correct interpolation,
+ * trilinear texture lookups, deferred shading, silhouette antialiasing and,
+ * if ref_image is not NULL, the image loss of Sec. 5.3 against it.
+ * ref_image: device [B,H,W,3] or NULL.  out: see adr_fwd_out.
+ * Returns ADR_E_INVALID on bad arguments, ADR_E_NOMEM if scratch cannot
+ * grow, ADR_E_HIP on a failed launch. */
+adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                          const adr_views* views, const float* ref_image, int32_t loss_kind,
+                          const adr_fwd_out* out, int32_t flags, adr_stream stream);
+
+/* Gradient buffers, caller-owned device memory.  Each is accumulated into
+ * (+=).  Map gradients use the full mip-chain layout of their texture:
+ * level 0 receives the gradient w.r.t. the level-0 texels (coarser levels
+ * being box averages of level 0), levels 1.. are scratch that must be zero
+ * on entry and are left zero. */
+typedef struct adr_grads {
+  float* pos;                    /* [n_pos,3] nullable */
+  float* vnormal;                /* [n_pos,3] nullable: OVERWRITTEN with dL/d(smooth vertex
+                                    normals), the part of pos's gradient that flows through them */
+  float* kd;                     /* nullable; F32 kd only */
+  float* normal;                 /* nullable */
+  float* orm;                    /* nullable; GGX only */
+} adr_grads;
+
+/* Hand-written adjoint of adr_render_fwd w.r.t. vertex positions and F32
+ * texels (Sec. 3: gradients of the loss w.r.t. the latent parameters).
+ * saved: the adr_fwd_out of the forward call with the same arguments
+ * (vis, color and dimage are read).  dloss: device [1] scale of the loss
+ * gradient (NULL = 1).  Return values as adr_render_fwd. */
+adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                          const adr_views* views, const adr_fwd_out* saved,
+                          const float* dloss, const adr_grads* grads, int32_t flags,
+                          adr_stream stream);
+
+/* One optimised tensor for adr_adam_step: n floats each, device. */
+typedef struct adr_param {
+  float* param;
+  float* grad;                   /* set to zero on exit */
+  float* m;
+  float* v;
+  int64_t n;
+} adr_param;
+
+/* Bias-corrected Adam (Sec. 5.3, "with default parameters": beta1 0.9,
+ * beta2 0.999, eps 1e-8) over n_params tensors in one launch; t is the
+ * 1-based step.  params: host array of descriptors.  Zeroes each gradient. */
+adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params, int32_t t,
+                         float lr, float beta1, float beta2, float eps, adr_stream stream);
+
+/* Rebuild levels 1.. of a texture from level 0 (2x2 box average; RGBA8
+ * rounds (a+b+c+d+2)/4).  Device work on `stream`. */
+adr_status adr_mip_build(adr_ctx* ctx, const adr_texture* tex, adr_stream stream);
+
+/* Stage timing.  When enabled, every render/adam call brackets each of its
+ * kernel stages with HIP events on the call's stream; adr_ctx_profile_read
+ * waits for them, returns per stage the summed milliseconds and the number
+ * of launches since the last read, and starts a new window.  Stages:
+ * 0 vertex frame, 1 transform, 2 raster, 3 shade, 4 antialias+loss,
+ * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
+ * 9 adam, 10 mip build.  ms and count: host arrays of ADR_N_STAGES. */
+#define ADR_N_STAGES 11
+adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
+adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
+
+/* Host helpers (no device work). */
+/* adj[t*3+k] = triangle sharing the edge opposite corner k of t, or -1. */
+adr_status adr_mesh_adjacency(const int32_t* tri, int32_t n_tri, int32_t* adj);
+/* Camera matrices for eye = dist * dir[b] / |dir[b]| looking at the origin,
+ * up +y (+z when the view direction is within 0.999 of +-y), vertical field
+ * of view fov_deg, aspect width/height, OpenGL projection with near 0.1,
+ * far 10.  dirs [B,3] host; mvp [B,16] and eye [B,3] host outputs. */
+adr_status adr_views_build(const float* dirs, int32_t n, float dist, float fov_deg,
+                           int32_t width, int32_t height, float* mvp, float* eye);
+
+/* ------------------------------------------------------------- job server */
+
+/* A whole simplification job (host pointers, deep-copied at admission). */
+typedef struct adr_job_desc {
+  /* reference model (fixed) */
+  const float* ref_pos; const int32_t* ref_tri; const float* ref_uv; const int32_t* ref_uv_tri;
+  int32_t ref_n_pos, ref_n_tri, ref_n_uv;
+  int32_t model;                 /* ADR_SHADE_* for both reference and latent */
+  const void* ref_kd; int32_t ref_kd_size, ref_kd_format;     /* level 0 only */
+  const float* ref_normal; int32_t ref_normal_size;           /* F32 x3 level 0 */
+  const float* ref_orm; int32_t ref_orm_size;                 /* F32 x3 level 0, GGX */
+  /* initial latent model */
+  const float* lat_pos; const int32_t* lat_tri; const float* lat_uv; const int32_t* lat_uv_tri;
+  int32_t lat_n_pos, lat_n_tri, lat_n_uv;
+  const void* lat_kd; int32_t lat_kd_size, lat_kd_format;
+  const float* lat_normal; int32_t lat_normal_size;
+  const float* lat_orm; int32_t lat_orm_size;
+  int32_t opt_mask;              /* bit 0 pos, 1 kd, 2 normal, 3 orm */
+  /* view / light distribution: per step, n_views directions uniform on the
+   * sphere at distance dist and one random unit light per view (or the same
+   * light for all views if light_per_view == 0), drawn from a counter-based
+   * generator seeded with `seed` */
+  uint64_t seed;
+  int32_t n_views, width, height, light_per_view;
+  float dist, fov_deg;
+  /* optimisation */
+  int32_t n_steps, loss_kind;
+  float lr0, lr_decay_k;         /* lr_t = lr0 10^(-k (t-1)) */
+} adr_job_desc;
+
+#define ADR_JOB_QUEUED 0
+#define ADR_JOB_RUNNING 1
+#define ADR_JOB_DONE 2
+#define ADR_JOB_FAILED 3
+
+typedef struct adr_job_status {
+  int32_t state;                 /* ADR_JOB_* */
+  int32_t step;                  /* completed steps */
+  float last_loss;
+  float p50_ms, p99_ms;          /* per-step latency, enqueue to completion */
+  uint64_t device_bytes;         /* resident footprint */
+} adr_job_status;
+
+typedef struct adr_job_result {  /* host buffers the caller allocates */
+  float* pos;                    /* [lat_n_pos,3] */
+  void* kd;                      /* level 0 of the latent kd */
+  float* normal;                 /* level 0 */
+  float* orm;                    /* level 0 (if GGX) */
+} adr_job_result;
+
+/* Queue a job.  Returns ADR_E_OVER_BUDGET if its footprint can never fit the
+ * context's budget.  The server thread starts on the first submit. */
+adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_id);
+
+/* State of a job.  With out != NULL and state DONE, copies the optimised
+ * latent model into the caller's host buffers and releases the job (a later
+ * poll returns ADR_E_NOTFOUND).  Returns ADR_OK, ADR_PENDING (queued or
+ * running), ADR_E_NONFINITE (failed), ADR_E_NOTFOUND. */
+adr_status adr_job_poll(adr_ctx* ctx, uint64_t job_id, adr_job_status* st, adr_job_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADR_H */

@@ -1,0 +1,360 @@
+"""Python binding of the C ABI in include/adr.h (argument marshalling only).
+
+Device memory comes from PyTorch; every step of the render loop runs in the
+HIP kernels of libadr.so.  Importing this module fails loudly if the library
+has not been built (``python -m paper_2104_03989_amd.csrc.build`` or
+``__graft_entry__.build()``): there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python paper_2104_03989_amd/csrc/build.py)")
+_lib = C.CDLL(LIB_PATH)
+
+OK, PENDING = 0, 1
+E_INVALID, E_NOMEM, E_HIP, E_OVER_BUDGET, E_NOTFOUND, E_NONFINITE, E_UNIMPL = -1, -2, -3, -4, -5, -6, -7
+TEX_F32, TEX_RGBA8 = 0, 1
+SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
+LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
+FWD_BUILD_MIPS, FWD_NO_AA = 1, 2
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
+EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
+           "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
+           "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read")
+N_STAGES = 11
+STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build")
+
+
+class AdrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adr error {code}: {msg}")
+        self.code = code
+
+
+P = C.c_void_p
+I32 = C.c_int32
+
+
+class Texture_(C.Structure):
+    _fields_ = [("data", P), ("size", I32), ("levels", I32), ("channels", I32), ("format", I32)]
+
+
+class Mesh_(C.Structure):
+    _fields_ = [("pos", P), ("tri", P), ("uv", P), ("uv_tri", P), ("adj", P),
+                ("n_pos", I32), ("n_tri", I32), ("n_uv", I32)]
+
+
+class Material_(C.Structure):
+    _fields_ = [("model", I32), ("kd", Texture_), ("normal", Texture_), ("orm", Texture_)]
+
+
+class Views_(C.Structure):
+    _fields_ = [("mvp", P), ("eye", P), ("light_dir", P), ("light_rgb", P),
+                ("n_views", I32), ("width", I32), ("height", I32)]
+
+
+class FwdOut_(C.Structure):
+    _fields_ = [("vis", P), ("color", P), ("image", P), ("dimage", P), ("loss", P),
+                ("tri_id", P), ("coverage", P)]
+
+
+class Grads_(C.Structure):
+    _fields_ = [("pos", P), ("vnormal", P), ("kd", P), ("normal", P), ("orm", P)]
+
+
+class Param_(C.Structure):
+    _fields_ = [("param", P), ("grad", P), ("m", P), ("v", P), ("n", C.c_int64)]
+
+
+class JobDesc_(C.Structure):
+    _fields_ = [("ref_pos", P), ("ref_tri", P), ("ref_uv", P), ("ref_uv_tri", P),
+                ("ref_n_pos", I32), ("ref_n_tri", I32), ("ref_n_uv", I32), ("model", I32),
+                ("ref_kd", P), ("ref_kd_size", I32), ("ref_kd_format", I32),
+                ("ref_normal", P), ("ref_normal_size", I32),
+                ("ref_orm", P), ("ref_orm_size", I32),
+                ("lat_pos", P), ("lat_tri", P), ("lat_uv", P), ("lat_uv_tri", P),
+                ("lat_n_pos", I32), ("lat_n_tri", I32), ("lat_n_uv", I32),
+                ("lat_kd", P), ("lat_kd_size", I32), ("lat_kd_format", I32),
+                ("lat_normal", P), ("lat_normal_size", I32),
+                ("lat_orm", P), ("lat_orm_size", I32),
+                ("opt_mask", I32),
+                ("seed", C.c_uint64),
+                ("n_views", I32), ("width", I32), ("height", I32), ("light_per_view", I32),
+                ("dist", C.c_float), ("fov_deg", C.c_float),
+                ("n_steps", I32), ("loss_kind", I32),
+                ("lr0", C.c_float), ("lr_decay_k", C.c_float)]
+
+
+class JobStatus_(C.Structure):
+    _fields_ = [("state", I32), ("step", I32), ("last_loss", C.c_float), ("p50_ms", C.c_float),
+                ("p99_ms", C.c_float), ("device_bytes", C.c_uint64)]
+
+
+class JobResult_(C.Structure):
+    _fields_ = [("pos", P), ("kd", P), ("normal", P), ("orm", P)]
+
+
+_lib.adr_last_error.restype = C.c_char_p
+_lib.adr_ctx_create.argtypes = [I32, C.c_uint64, C.POINTER(P)]
+_lib.adr_ctx_destroy.argtypes = [P]
+_lib.adr_render_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_), P, I32,
+                                C.POINTER(FwdOut_), I32, P]
+_lib.adr_render_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_),
+                                C.POINTER(FwdOut_), P, C.POINTER(Grads_), I32, P]
+_lib.adr_adam_step.argtypes = [P, C.POINTER(Param_), I32, I32, C.c_float, C.c_float, C.c_float,
+                               C.c_float, P]
+_lib.adr_mip_build.argtypes = [P, C.POINTER(Texture_), P]
+_lib.adr_mesh_adjacency.argtypes = [P, I32, P]
+_lib.adr_views_build.argtypes = [P, I32, C.c_float, C.c_float, I32, I32, P, P]
+_lib.adr_job_submit.argtypes = [P, C.POINTER(JobDesc_), C.POINTER(C.c_uint64)]
+_lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(JobResult_)]
+_lib.adr_ctx_profile.argtypes = [P, I32]
+_lib.adr_ctx_profile_read.argtypes = [P, P, P]
+for _n in EXPORTS[1:]:
+    getattr(_lib, _n).restype = I32
+
+
+def _check(code):
+    if code < 0:
+        raise AdrError(code, _lib.adr_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- host helpers
+
+def mesh_adjacency(tri: np.ndarray) -> np.ndarray:
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    adj = np.zeros_like(tri)
+    _check(_lib.adr_mesh_adjacency(_ptr(tri), tri.shape[0], _ptr(adj)))
+    return adj
+
+
+def views_build(dirs: np.ndarray, dist: float, fov_deg: float, width: int, height: int):
+    dirs = np.ascontiguousarray(dirs, dtype=np.float32)
+    n = dirs.shape[0]
+    mvp = np.zeros((n, 16), dtype=np.float32)
+    eye = np.zeros((n, 3), dtype=np.float32)
+    _check(_lib.adr_views_build(_ptr(dirs), n, dist, fov_deg, width, height, _ptr(mvp), _ptr(eye)))
+    return mvp, eye
+
+
+# ---------------------------------------------------------------- context
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = P()
+        _check(_lib.adr_ctx_create(device, hbm_budget, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def profile(self, enable: bool = True):
+        _check(_lib.adr_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, launches)} since the last read."""
+        ms = np.zeros(N_STAGES, dtype=np.float64)
+        cnt = np.zeros(N_STAGES, dtype=np.int64)
+        _check(_lib.adr_ctx_profile_read(self.h, ms.ctypes.data, cnt.ctypes.data))
+        return {STAGES[k]: (float(ms[k]), int(cnt[k])) for k in range(N_STAGES)}
+
+    def close(self):
+        if self.h:
+            _lib.adr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- device data
+
+def chain_texels(size: int, levels: int) -> int:
+    return sum((size >> l) ** 2 for l in range(levels))
+
+
+class DeviceTexture:
+    """A square texture with its mip chain in one device tensor."""
+
+    def __init__(self, level0: np.ndarray, fmt: str, device="cuda", levels: int | None = None,
+                 ctx: Context | None = None):
+        S = level0.shape[0]
+        assert level0.shape[1] == S and S & (S - 1) == 0, "square power-of-two texture"
+        self.size = S
+        self.levels = int(math.log2(S)) + 1 if levels is None else levels
+        n = chain_texels(S, self.levels)
+        if fmt == "rgba8":
+            self.fmt, self.channels = TEX_RGBA8, 4
+            self.data = torch.zeros(n, 4, dtype=torch.uint8, device=device)
+            self.data[:S * S] = torch.from_numpy(np.ascontiguousarray(level0, dtype=np.uint8).reshape(-1, 4))
+        else:
+            self.fmt = TEX_F32
+            self.channels = level0.shape[2]
+            self.data = torch.zeros(n, self.channels, dtype=torch.float32, device=device)
+            self.data[:S * S] = torch.from_numpy(np.ascontiguousarray(level0, dtype=np.float32).reshape(-1, self.channels))
+        if ctx is not None and self.levels > 1:
+            mip_build(ctx, self)
+
+    @property
+    def level0(self):
+        return self.data[:self.size * self.size]
+
+    def struct(self):
+        return Texture_(self.data.data_ptr(), self.size, self.levels, self.channels, self.fmt)
+
+    def grad_buffer(self):
+        assert self.fmt == TEX_F32
+        return torch.zeros_like(self.data)
+
+
+class DeviceMesh:
+    def __init__(self, mesh, device="cuda"):
+        self.pos = torch.from_numpy(np.ascontiguousarray(mesh.pos, dtype=np.float32)).to(device)
+        self.tri = torch.from_numpy(np.ascontiguousarray(mesh.tri, dtype=np.int32)).to(device)
+        self.uv = torch.from_numpy(np.ascontiguousarray(mesh.uv, dtype=np.float32)).to(device)
+        self.uv_tri = torch.from_numpy(np.ascontiguousarray(mesh.uv_tri, dtype=np.int32)).to(device)
+        self.adj = torch.from_numpy(mesh_adjacency(mesh.tri)).to(device)
+
+    def struct(self, pos=None):
+        p = self.pos if pos is None else pos
+        return Mesh_(p.data_ptr(), self.tri.data_ptr(), self.uv.data_ptr(), self.uv_tri.data_ptr(),
+                     self.adj.data_ptr(), p.shape[0], self.tri.shape[0], self.uv.shape[0])
+
+
+class DeviceMaterial:
+    def __init__(self, scene, device="cuda", ctx: Context | None = None):
+        self.model = SHADE_GGX if scene.model == "ggx" else SHADE_BLINN_PHONG
+        self.kd = DeviceTexture(scene.kd.data, scene.kd.fmt, device, ctx=ctx)
+        self.normal = DeviceTexture(scene.normal.data, scene.normal.fmt, device, ctx=ctx)
+        self.orm = DeviceTexture(scene.orm.data, scene.orm.fmt, device, ctx=ctx) if scene.orm is not None else None
+
+    def struct(self):
+        orm = self.orm.struct() if self.orm is not None else Texture_()
+        return Material_(self.model, self.kd.struct(), self.normal.struct(), orm)
+
+
+class DeviceViews:
+    def __init__(self, mvp, eye, light_dir, light_rgb, width, height, device="cuda"):
+        f = lambda x: x if torch.is_tensor(x) else torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(device)
+        self.mvp = f(mvp).reshape(-1, 16)
+        self.eye = f(eye).reshape(-1, 3)
+        self.light_dir = f(light_dir).reshape(-1, 3)
+        self.light_rgb = f(light_rgb).reshape(-1, 3)
+        self.n = self.mvp.shape[0]
+        self.width, self.height = width, height
+
+    def struct(self):
+        return Views_(self.mvp.data_ptr(), self.eye.data_ptr(), self.light_dir.data_ptr(),
+                      self.light_rgb.data_ptr(), self.n, self.width, self.height)
+
+
+# ---------------------------------------------------------------- calls
+
+def mip_build(ctx: Context, tex: DeviceTexture, stream=None):
+    t = tex.struct()
+    _check(_lib.adr_mip_build(ctx.h, C.byref(t), _stream(stream)))
+
+
+def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, ref=None,
+               loss: str = "l1", flags: int = 0, pos=None, want_image=True, want_tri_id=False,
+               want_coverage=False, stream=None, outputs: dict | None = None):
+    """Returns a dict with vis, color, image, dimage, loss, tri_id, coverage
+    (``outputs``: a dict returned by an earlier call, reused in place)."""
+    B, H, W = views.n, views.height, views.width
+    dev = mesh.tri.device
+    if outputs is not None:
+        out = outputs
+    else:
+        out = dict(vis=torch.empty(B, H, W, dtype=torch.int64, device=dev),
+                   color=torch.empty(B, H, W, 3, dtype=torch.float32, device=dev))
+        out["image"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if want_image else None
+        out["tri_id"] = torch.empty(B, H, W, dtype=torch.int32, device=dev) if want_tri_id else None
+        out["coverage"] = torch.empty(B, H, W, dtype=torch.int32, device=dev) if want_coverage else None
+        if ref is not None:
+            out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
+            out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)
+        else:
+            out["dimage"] = out["loss"] = None
+    fo = FwdOut_(*[_ptr(out[k]) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage")])
+    ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
+    _check(_lib.adr_render_fwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref),
+                               LOSS[loss], C.byref(fo), flags, _stream(stream)))
+    return out
+
+
+def render_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, saved: dict,
+               grads: dict, dloss=None, flags: int = 0, pos=None, stream=None):
+    """Accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'] (tensors or None)."""
+    fo = FwdOut_(*[_ptr(saved.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage")])
+    g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm")])
+    ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
+    _check(_lib.adr_render_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(fo),
+                               _ptr(dloss), C.byref(g), flags, _stream(stream)))
+
+
+def adam_step(ctx: Context, params: list, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+    """params: list of (param, grad, m, v) float32 device tensors of equal size."""
+    arr = (Param_ * max(len(params), 1))()
+    for k, (p, g, m, v) in enumerate(params):
+        arr[k] = Param_(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel())
+    _check(_lib.adr_adam_step(ctx.h, arr, len(params), t, lr, beta1, beta2, eps, _stream(stream)))
+
+
+class RenderLoss(torch.autograd.Function):
+    """Image loss of a latent render against a reference image; the backward
+    is adr_render_bwd.  Differentiable inputs: pos [V,3], and the level-0
+    slices of the F32 maps ``kd``, ``normal``, ``orm``.
+    forward(pos, kd0, normal0, orm0, ctx, mesh, mat, views, ref, loss, flags)."""
+
+    @staticmethod
+    def forward(fctx, pos, kd0, normal0, orm0, ctx, mesh, mat, views, ref, loss, flags):
+        out = render_fwd(ctx, mesh, mat, views, ref=ref, loss=loss, flags=flags, pos=pos, want_image=False)
+        fctx.state = (ctx, mesh, mat, views, flags, out)
+        fctx.save_for_backward(pos)
+        return out["loss"][0].clone()
+
+    @staticmethod
+    def backward(fctx, gout):
+        ctx, mesh, mat, views, flags, out = fctx.state
+        (pos,) = fctx.saved_tensors
+        grads = {"pos": torch.zeros_like(pos) if fctx.needs_input_grad[0] else None}
+        for k, name in ((1, "kd"), (2, "normal"), (3, "orm")):
+            tex = getattr(mat, name)
+            grads[name] = tex.grad_buffer() if fctx.needs_input_grad[k] and tex is not None else None
+        dl = gout.reshape(1).to(torch.float32).contiguous()
+        render_bwd(ctx, mesh, mat, views, out, grads, dloss=dl, flags=flags, pos=pos)
+        res = [grads["pos"]]
+        for name in ("kd", "normal", "orm"):
+            g = grads[name]
+            tex = getattr(mat, name)
+            res.append(None if g is None else g[:tex.size * tex.size])
+        return (*res, None, None, None, None, None, None, None)

@@ -1,0 +1,320 @@
+// Silhouette antialiasing (Sec. 5.2, "Antialiasing": the operator of Laine et
+// al. 2020 that gives visibility gradients at silhouettes), fused with the
+// image loss of Sec. 5.3, and its adjoint.
+//
+// For two horizontally or vertically adjacent pixels whose triangle ids
+// differ, the front triangle F is the one with the smaller visibility key
+// (empty pixels have the largest key); P is the pixel F is visible at, Q the
+// other one.  Among F's oriented edges 0, 1, 2 the first one that Q lies
+// outside of (integer edge test with the top-left rule) and that is a
+// silhouette edge (a boundary edge, or one whose neighbouring triangle has
+// the other screen orientation in this view) is the crossing edge a->b.
+// With e(X) the float edge function of the projected edge at the NDC centre
+// of pixel X, s = clamp(e(P) / (e(P) - e(Q)), 0, 1); a box filter one pixel
+// wide gives out(Q) += (s - 1/2)(c(P) - c(Q)) if s > 1/2 and
+// out(P) += (1/2 - s)(c(Q) - c(P)) if s < 1/2.  All terms use the colours
+// before antialiasing, so each pixel gathers its own four pairs and no
+// atomics or ordering are involved in the forward pass.
+//
+// Loss: mean over B*H*W*3 of |T(out) - T(ref)| (or the square), with
+// T(x) = Gamma(log(x + 1)) and Gamma the sRGB transfer function
+// (12.92 x for x <= 0.0031308, 1.055 x^(1/2.4) - 0.055 above), or T(x) = x.
+#include "dev.h"
+
+namespace adr {
+
+struct AAArgs {
+  MeshD m;
+  ViewsD v;
+  const int4* snap;
+  const double4* clip;
+  const int8_t* orient;
+  const uint64_t* vis;
+  const float* color;
+  int tiles_x, tiles_y;
+  int no_aa;
+};
+
+// The crossing edge of pair (P, Q) for front triangle F, or false.
+struct Cross {
+  int va, vb;    // vertex indices, F on the left of a->b
+  float s;       // crossing parameter from P towards Q (clamped)
+  bool clamped;  // s was outside [0, 1]
+  double eP, eQ, den;
+  double aP[2], bP[2], aQ[2], bQ[2];  // projected a, b relative to the centres of P and Q
+};
+
+// Projected corner relative to the NDC point X: (x - w X.x) / w, (y - w X.y) / w
+// (float64, from the float64 clip coordinates: edges of pixel-sized
+// triangles are short, and their edge functions cancel in float32).
+__device__ __forceinline__ void rel_proj(double4 c, double Xx, double Xy, double out[2]) {
+  double iw = 1.0 / c.w;
+  out[0] = (c.x - c.w * Xx) * iw;
+  out[1] = (c.y - c.w * Xy) * iw;
+}
+
+__device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi, int Pj, int Qi,
+                                           int Qj, Cross& x) {
+  const int* tri = a.m.tri + 3 * F;
+  int v[3] = {tri[0], tri[1], tri[2]};
+  const int4* sv = a.snap + (int64_t)b * a.m.n_pos;
+  int4 s0 = sv[v[0]], s1 = sv[v[1]], s2 = sv[v[2]];
+  int64_t A = (int64_t)(s1.x - s0.x) * (s2.y - s0.y) - (int64_t)(s1.y - s0.y) * (s2.x - s0.x);
+  int vid[3] = {0, 1, 2};
+  int X[3] = {s0.x, s1.x, s2.x}, Y[3] = {s0.y, s1.y, s2.y};
+  if (A < 0) {
+    vid[1] = 2; vid[2] = 1;
+    X[1] = s2.x; X[2] = s1.x;
+    Y[1] = s2.y; Y[2] = s1.y;
+  }
+  int64_t qx = 256 * (int64_t)Qi + 128, qy = 256 * (int64_t)Qj + 128;
+  int8_t of = a.orient[(int64_t)b * a.m.n_tri + F];
+  for (int k = 0; k < 3; ++k) {
+    int j = k == 2 ? 0 : k + 1, l = k == 0 ? 2 : k - 1;
+    int64_t dx = (int64_t)X[l] - X[j], dy = (int64_t)Y[l] - Y[j];
+    int64_t e = dx * (qy - Y[j]) - dy * (qx - X[j]);
+    bool tl = dy < 0 || (dy == 0 && dx < 0);
+    bool inside = e > 0 || (e == 0 && tl);
+    if (inside) continue;
+    int nb = a.m.adj[3 * F + vid[k]];
+    bool sil = nb < 0 || a.orient[(int64_t)b * a.m.n_tri + nb] != of;
+    if (!sil) continue;
+    x.va = v[vid[j]];
+    x.vb = v[vid[l]];
+    double4 ca = a.clip[(int64_t)b * a.m.n_pos + x.va];
+    double4 cb = a.clip[(int64_t)b * a.m.n_pos + x.vb];
+    double Px = 2.0 * ((double)Pi + 0.5) / (double)a.v.W - 1.0;
+    double Py = 2.0 * ((double)Pj + 0.5) / (double)a.v.H - 1.0;
+    double Qx = 2.0 * ((double)Qi + 0.5) / (double)a.v.W - 1.0;
+    double Qy = 2.0 * ((double)Qj + 0.5) / (double)a.v.H - 1.0;
+    // e(X) = (b - a) x (X - a) = a' x b' with a' = a - X, b' = b - X
+    rel_proj(ca, Px, Py, x.aP);
+    rel_proj(cb, Px, Py, x.bP);
+    rel_proj(ca, Qx, Qy, x.aQ);
+    rel_proj(cb, Qx, Qy, x.bQ);
+    x.eP = x.aP[0] * x.bP[1] - x.aP[1] * x.bP[0];
+    x.eQ = x.aQ[0] * x.bQ[1] - x.aQ[1] * x.bQ[0];
+    x.den = x.eP - x.eQ;
+    if (x.den == 0.0) return false;
+    double s = x.eP / x.den;
+    x.clamped = !(s >= 0.0 && s <= 1.0);
+    x.s = (float)fmin(fmax(s, 0.0), 1.0);
+    return true;
+  }
+  return false;
+}
+
+// Pair between pixel (i,j) and its neighbour (ni,nj): which side is P and
+// the crossing, or false if the pair does not blend.
+struct Pair {
+  bool self_is_P;
+  Cross x;
+};
+__device__ __forceinline__ bool eval_pair(const AAArgs& a, int b, int i, int j, uint64_t kself, int ni,
+                                          int nj, uint64_t knb, Pair& pr) {
+  if ((uint32_t)kself == (uint32_t)knb) return false;
+  bool selfP = kself < knb;
+  uint64_t kF = selfP ? kself : knb;
+  int F = (int)(uint32_t)kF - 1;
+  pr.self_is_P = selfP;
+  if (selfP) return find_cross(a, b, F, i, j, ni, nj, pr.x);
+  return find_cross(a, b, F, ni, nj, i, j, pr.x);
+}
+
+__device__ __forceinline__ f3 ldc(const float* c, int64_t o) { return mk(c[3 * o], c[3 * o + 1], c[3 * o + 2]); }
+
+__device__ __forceinline__ float srgb(float x) {
+  return x <= 0.0031308f ? 12.92f * x : 1.055f * powf(x, 1.0f / 2.4f) - 0.055f;
+}
+__device__ __forceinline__ float srgb_d(float x) {
+  return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * powf(x, 1.0f / 2.4f - 1.0f);
+}
+__device__ __forceinline__ float tmap(float x) { return srgb(log1pf(x)); }
+__device__ __forceinline__ float tmap_d(float x) { return srgb_d(log1pf(x)) / (1.0f + x); }
+
+__global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __restrict__ ref,
+                                                     int loss_kind, float* __restrict__ image,
+                                                     float* __restrict__ dimage,
+                                                     float* __restrict__ partial) {
+  __shared__ float red[4];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  float lsum = 0.f;
+  if (p.ok) {
+    int64_t base = (int64_t)p.b * a.v.H * a.v.W;
+    int64_t o = base + (int64_t)p.j * a.v.W + p.i;
+    f3 c = ldc(a.color, o);
+    f3 out = c;
+    if (!a.no_aa) {
+      uint64_t k = a.vis[o];
+      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+      for (int q = 0; q < 4; ++q) {
+        int ni = p.i + di[q], nj = p.j + dj[q];
+        if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
+        int64_t on = base + (int64_t)nj * a.v.W + ni;
+        Pair pr;
+        if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[on], pr)) continue;
+        float s = pr.x.s;
+        if (pr.self_is_P) {
+          if (s < 0.5f) out += (0.5f - s) * (ldc(a.color, on) - c);
+        } else {
+          if (s > 0.5f) out += (s - 0.5f) * (ldc(a.color, on) - c);
+        }
+      }
+    }
+    if (image) st3(image, o, out);
+    if (ref) {
+      f3 r = ldc(ref, o);
+      bool tm = loss_kind == ADR_LOSS_L1_TONEMAP || loss_kind == ADR_LOSS_L2_TONEMAP;
+      bool l1 = loss_kind == ADR_LOSS_L1 || loss_kind == ADR_LOSS_L1_TONEMAP;
+      float inv_n = 1.0f / (3.0f * (float)a.v.B * (float)a.v.H * (float)a.v.W);
+      float ov[3] = {out.x, out.y, out.z}, rv[3] = {r.x, r.y, r.z}, gd[3];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        float d = tm ? tmap(ov[ch]) - tmap(rv[ch]) : ov[ch] - rv[ch];
+        float dt = tm ? tmap_d(ov[ch]) : 1.0f;
+        if (l1) {
+          lsum += fabsf(d);
+          gd[ch] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * dt * inv_n;
+        } else {
+          lsum += d * d;
+          gd[ch] = 2.f * d * dt * inv_n;
+        }
+      }
+      st3(dimage, o, mk(gd[0], gd[1], gd[2]));
+    }
+  }
+  if (ref) {
+    // block reduction in a fixed order (deterministic)
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+__global__ void k_loss_reduce(const float* __restrict__ partial, int n, float inv_n,
+                              float* __restrict__ loss) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += (double)partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = (float)(red[0] * (double)inv_n);
+}
+
+// Adjoint: each pixel gathers dL/dc of its own colour from its four pairs;
+// the gradient of a pair's crossing parameter s w.r.t. the clip coordinates
+// of its edge is scattered once, by the left (or lower) pixel of the pair.
+__global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
+                                                const float* __restrict__ dloss,
+                                                float* __restrict__ gcolor, float* __restrict__ dclip) {
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  if (!p.ok) return;
+  float scale = dloss ? dloss[0] : 1.0f;
+  int64_t base = (int64_t)p.b * a.v.H * a.v.W;
+  int64_t o = base + (int64_t)p.j * a.v.W + p.i;
+  f3 gself = scale * ldc(dimage, o);
+  f3 gc = gself;
+  if (!a.no_aa) {
+    uint64_t k = a.vis[o];
+    f3 c = ldc(a.color, o);
+    const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    for (int q = 0; q < 4; ++q) {
+      int ni = p.i + di[q], nj = p.j + dj[q];
+      if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
+      int64_t on = base + (int64_t)nj * a.v.W + ni;
+      Pair pr;
+      if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[on], pr)) continue;
+      float s = pr.x.s;
+      f3 cn = ldc(a.color, on);
+      f3 gn = scale * ldc(dimage, on);
+      float g_s = 0.f;
+      // out(Q) += (s - 1/2)(c(P) - c(Q)) for s > 1/2; out(P) += (1/2 - s)(c(Q) - c(P)) for s < 1/2
+      f3 cP = pr.self_is_P ? c : cn, cQ = pr.self_is_P ? cn : c;
+      f3 gP = pr.self_is_P ? gself : gn, gQ = pr.self_is_P ? gn : gself;
+      if (s > 0.5f) {
+        float w = s - 0.5f;
+        gc += (pr.self_is_P ? w : -w) * gQ;
+        g_s = dot(gQ, cP - cQ);
+      } else if (s < 0.5f) {
+        float w = 0.5f - s;
+        gc += (pr.self_is_P ? -w : w) * gP;
+        g_s = -dot(gP, cQ - cP);
+      }
+      bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
+      if (!owner || pr.x.clamped || g_s == 0.f) continue;
+      // s = eP / (eP - eQ)
+      double id2 = 1.0 / (pr.x.den * pr.x.den);
+      double g_eP = -g_s * pr.x.eQ * id2, g_eQ = g_s * pr.x.eP * id2;
+      double4 ca = a.clip[(int64_t)p.b * a.m.n_pos + pr.x.va];
+      double4 cb = a.clip[(int64_t)p.b * a.m.n_pos + pr.x.vb];
+      double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
+      double ax = ca.x * iwa, ay = ca.y * iwa, bx = cb.x * iwb, by = cb.y * iwb;
+      // e(X) = a'_x b'_y - a'_y b'_x, a' = a - X, b' = b - X
+      double g_ax = g_eP * pr.x.bP[1] + g_eQ * pr.x.bQ[1];
+      double g_ay = -g_eP * pr.x.bP[0] - g_eQ * pr.x.bQ[0];
+      double g_bx = -g_eP * pr.x.aP[1] - g_eQ * pr.x.aQ[1];
+      double g_by = g_eP * pr.x.aP[0] + g_eQ * pr.x.aQ[0];
+      float* da = dclip + 4 * ((int64_t)p.b * a.m.n_pos + pr.x.va);
+      float* db = dclip + 4 * ((int64_t)p.b * a.m.n_pos + pr.x.vb);
+      atomicAdd(da + 0, (float)(g_ax * iwa));
+      atomicAdd(da + 1, (float)(g_ay * iwa));
+      atomicAdd(da + 3, (float)(-(g_ax * ax + g_ay * ay) * iwa));
+      atomicAdd(db + 0, (float)(g_bx * iwb));
+      atomicAdd(db + 1, (float)(g_by * iwb));
+      atomicAdd(db + 3, (float)(-(g_bx * bx + g_by * by) * iwb));
+    }
+  }
+  st3(gcolor, o, gc);
+}
+
+static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                      const float* color, int no_aa) {
+  AAArgs a;
+  a.m = m;
+  a.v = v;
+  a.snap = reinterpret_cast<const int4*>(s.snap);
+  a.clip = reinterpret_cast<const double4*>(s.clip);
+  a.orient = s.orient;
+  a.vis = vis;
+  a.color = color;
+  a.tiles_x = (v.W + 15) / 16;
+  a.tiles_y = (v.H + 15) / 16;
+  a.no_aa = no_aa;
+  return a;
+}
+
+hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
+                              const uint64_t* vis, const float* color, const float* ref,
+                              int loss_kind, int no_aa, float* image, float* dimage, float* loss,
+                              hipStream_t st) {
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa);
+  int nb = a.tiles_x * a.tiles_y * v.B;
+  if (!image && !ref) return hipSuccess;
+  hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage,
+                     s.partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !ref) return e;
+  float inv_n = 1.0f;  // partials hold sums; the mean's 1/N is applied here
+  double n = 3.0 * (double)v.B * v.H * v.W;
+  inv_n = (float)(1.0 / n);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, s.partial, nb, inv_n, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                         const float* color, const float* dimage, const float* dloss, int no_aa,
+                         hipStream_t st) {
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa);
+  int nb = a.tiles_x * a.tiles_y * v.B;
+  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.dclip);
+  return hipGetLastError();
+}
+
+}  // namespace adr

@@ -1,0 +1,504 @@
+// C ABI of the render loop: argument validation, context scratch and the
+// stream-ordered launch sequences of one forward and one backward pass.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+#include "jobs.h"
+
+using namespace adr;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+adr_status fail(adr_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+adr_status hip_fail(hipError_t e, const char* where) {
+  return fail(ADR_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << (l + 1)) <= x) ++l;
+  return l;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- context
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct Span {
+  hipEvent_t a, b;
+  int stage;
+};
+
+struct adr_ctx {
+  int device = 0;
+  uint64_t budget = 0;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr;
+  adr::JobServer* jobs = nullptr;
+  bool prof = false;
+  std::vector<Span> spans;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+hipEvent_t take_event(adr_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel stage with events on its stream while profiling is on.
+struct StageTimer {
+  adr_ctx* c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(adr_ctx* c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
+    if (c->prof && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) {
+      c->pool.push_back(a);
+      return;
+    }
+    (void)hipEventRecord(b, st);
+    c->spans.push_back({a, b, stage});
+  }
+};
+
+
+adr_status ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return ADR_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);  // synchronises the device: no work still uses it
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.p, cap);
+  if (e != hipSuccess) return fail(ADR_E_NOMEM, "hipMalloc(%zu): %s", cap, hipGetErrorString(e));
+  b.cap = cap;
+  return ADR_OK;
+}
+
+void release(Buf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+// Validates a texture; requires_f32 forbids RGBA8; ch3 requires 3 channels.
+adr_status check_tex(const adr_texture& t, const char* name, bool allow_rgba8, Tex& out) {
+  if (!t.data) return fail(ADR_E_INVALID, "%s: data is NULL", name);
+  if (!pow2(t.size) || t.size > 16384) return fail(ADR_E_INVALID, "%s: size %d is not a power of two in [1,16384]", name, t.size);
+  int maxl = ilog2(t.size) + 1;
+  if (t.levels < 1 || t.levels > maxl) return fail(ADR_E_INVALID, "%s: levels %d outside [1,%d]", name, t.levels, maxl);
+  if (t.format == ADR_TEX_RGBA8) {
+    if (!allow_rgba8) return fail(ADR_E_INVALID, "%s: RGBA8 not allowed here", name);
+    if (t.channels != 4) return fail(ADR_E_INVALID, "%s: RGBA8 needs channels = 4", name);
+  } else if (t.format == ADR_TEX_F32) {
+    if (t.channels != 3 && t.channels != 1) return fail(ADR_E_INVALID, "%s: F32 channels must be 1 or 3", name);
+  } else {
+    return fail(ADR_E_INVALID, "%s: unknown format %d", name, t.format);
+  }
+  out.data = t.data;
+  out.size = t.size;
+  out.levels = t.levels;
+  out.channels = t.channels;
+  out.fmt = t.format;
+  int off = 0;
+  for (int l = 0; l <= kMaxLevels; ++l) {
+    out.off[l] = off;
+    if (l < t.levels) off += (t.size >> l) * (t.size >> l);
+  }
+  return ADR_OK;
+}
+
+adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                        const adr_views* views, MeshD& m, ViewsD& v, Tex& kd, Tex& nm, Tex& orm) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (!mesh || !mat || !views) return fail(ADR_E_INVALID, "mesh, material and views are required");
+  if (mesh->n_pos < 0 || mesh->n_tri < 0 || mesh->n_uv < 0) return fail(ADR_E_INVALID, "negative mesh size");
+  if (mesh->n_tri > 0 && (!mesh->pos || !mesh->tri || !mesh->uv || !mesh->uv_tri || !mesh->adj))
+    return fail(ADR_E_INVALID, "mesh arrays pos, tri, uv, uv_tri and adj are required");
+  if (mesh->n_tri > 0 && (mesh->n_pos < 1 || mesh->n_uv < 1)) return fail(ADR_E_INVALID, "triangles without vertices");
+  if ((int64_t)views->n_views * mesh->n_tri > 0x7fffffffLL || (int64_t)views->n_views * mesh->n_pos > 0x7fffffffLL)
+    return fail(ADR_E_INVALID, "views x mesh size exceeds 2^31");
+  if (views->n_views < 1 || views->n_views > 4096) return fail(ADR_E_INVALID, "n_views %d outside [1,4096]", views->n_views);
+  if (views->width < 1 || views->width > 4096 || views->height < 1 || views->height > 4096)
+    return fail(ADR_E_INVALID, "image size %dx%d outside [1,4096]", views->width, views->height);
+  if (!views->mvp || !views->eye || !views->light_dir || !views->light_rgb) return fail(ADR_E_INVALID, "views arrays are required");
+  if (mat->model != ADR_SHADE_BLINN_PHONG && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "unknown shading model %d", mat->model);
+  adr_status s;
+  if ((s = check_tex(mat->kd, "kd", true, kd)) != ADR_OK) return s;
+  if (kd.fmt == ADR_TEX_F32 && kd.channels != 3) return fail(ADR_E_INVALID, "kd: F32 needs 3 channels");
+  if ((s = check_tex(mat->normal, "normal", false, nm)) != ADR_OK) return s;
+  if (nm.channels != 3) return fail(ADR_E_INVALID, "normal: needs 3 channels");
+  if (mat->model == ADR_SHADE_GGX) {
+    if ((s = check_tex(mat->orm, "orm", false, orm)) != ADR_OK) return s;
+    if (orm.channels != 3) return fail(ADR_E_INVALID, "orm: needs 3 channels");
+  } else {
+    orm = kd;
+  }
+  m.pos = mesh->pos;
+  m.tri = mesh->tri;
+  m.uv = mesh->uv;
+  m.uv_tri = mesh->uv_tri;
+  m.adj = mesh->adj;
+  m.n_pos = mesh->n_pos;
+  m.n_tri = mesh->n_tri;
+  m.n_uv = mesh->n_uv;
+  v.mvp = views->mvp;
+  v.eye = views->eye;
+  v.light_dir = views->light_dir;
+  v.light_rgb = views->light_rgb;
+  v.B = views->n_views;
+  v.W = views->width;
+  v.H = views->height;
+  return ADR_OK;
+}
+
+adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool bwd, Scratch& s) {
+  size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
+  size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
+  adr_status r;
+  if ((r = ensure(ctx->clip, B * V * 32)) || (r = ensure(ctx->snap, B * V * 16)) ||
+      (r = ensure(ctx->orient, B * T)) || (r = ensure(ctx->nacc, V * 24)) ||
+      (r = ensure(ctx->tacc, V * 24)) || (r = ensure(ctx->nrm, V * 12)) ||
+      (r = ensure(ctx->tan, V * 12)) || (r = ensure(ctx->big, B * T * 4)) ||
+      (r = ensure(ctx->big_cnt, B * 4)) || (r = ensure(ctx->partial, tiles * 4)))
+    return r;
+  if (bwd) {
+    if ((r = ensure(ctx->gcolor, B * v.W * v.H * 12)) || (r = ensure(ctx->dclip, B * V * 16)) ||
+        (r = ensure(ctx->dattr, V * 36)))
+      return r;
+  }
+  s.clip = (double*)ctx->clip.p;
+  s.snap = (int*)ctx->snap.p;
+  s.orient = (int8_t*)ctx->orient.p;
+  s.nacc = (double*)ctx->nacc.p;
+  s.tacc = (double*)ctx->tacc.p;
+  s.nrm = (float*)ctx->nrm.p;
+  s.tan = (float*)ctx->tan.p;
+  s.big = (uint32_t*)ctx->big.p;
+  s.big_cnt = (uint32_t*)ctx->big_cnt.p;
+  s.partial = (float*)ctx->partial.p;
+  s.gcolor = (float*)ctx->gcolor.p;
+  s.dclip = (float*)ctx->dclip.p;
+  s.dattr = (float*)ctx->dattr.p;
+  s.n_partial = (int)tiles;
+  return ADR_OK;
+}
+
+}  // namespace
+
+#define HIPCHK(x, where)                         \
+  do {                                           \
+    hipError_t e_ = (x);                         \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+#define TIMED(stage, x, where)                   \
+  do {                                           \
+    StageTimer t_(ctx, stage, st);               \
+    HIPCHK(x, where);                            \
+  } while (0)
+
+extern "C" {
+
+const char* adr_last_error(void) { return g_err; }
+
+adr_status adr_ctx_create(int32_t device, uint64_t hbm_budget_bytes, adr_ctx** out) {
+  if (!out) return fail(ADR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n), "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(ADR_E_INVALID, "device %d outside [0,%d)", device, n);
+  HIPCHK(hipSetDevice(device), "hipSetDevice");
+  adr_ctx* c = new (std::nothrow) adr_ctx();
+  if (!c) return fail(ADR_E_NOMEM, "context allocation");
+  c->device = device;
+  if (hbm_budget_bytes == 0) {
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+    const uint64_t reserve = 4ull << 30;
+    hbm_budget_bytes = fr > reserve ? fr - reserve : fr / 2;
+  }
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return ADR_OK;
+}
+
+adr_status adr_ctx_destroy(adr_ctx* ctx) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  (void)hipSetDevice(ctx->device);
+  adr::jobs_destroy(ctx->jobs);
+  ctx->jobs = nullptr;
+  (void)hipDeviceSynchronize();
+  Buf* bufs[] = {&ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
+  for (Buf* b : bufs) release(*b);
+  for (const Span& sp : ctx->spans) {
+    (void)hipEventDestroy(sp.a);
+    (void)hipEventDestroy(sp.b);
+  }
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return ADR_OK;
+}
+
+adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                          const adr_views* views, const float* ref_image, int32_t loss_kind,
+                          const adr_fwd_out* out, int32_t flags, adr_stream stream) {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm;
+  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if (!out || !out->vis || !out->color) return fail(ADR_E_INVALID, "out->vis and out->color are required");
+  if (ref_image) {
+    if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
+    if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
+  }
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA)) return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  if (flags & ADR_FWD_BUILD_MIPS) {
+    const Tex* maps[3] = {&kd, &nm, &orm};
+    int nmaps = mat->model == ADR_SHADE_GGX ? 3 : 2;
+    for (int k = 0; k < nmaps; ++k)
+      if (maps[k]->fmt == ADR_TEX_F32) TIMED(10, launch_mip_build(*maps[k], st), "mip build");
+  }
+  int64_t npx = (int64_t)v.B * v.W * v.H;
+  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  TIMED(1, launch_xform(m, v, s, st), "transform");
+  TIMED(2, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
+  TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
+  TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
+  TIMED(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
+                            (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st),
+         "antialias/loss");
+  return ADR_OK;
+}
+
+adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                          const adr_views* views, const adr_fwd_out* saved, const float* dloss,
+                          const adr_grads* grads, int32_t flags, adr_stream stream) {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm;
+  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if (!saved || !saved->vis || !saved->color || !saved->dimage)
+    return fail(ADR_E_INVALID, "saved->vis, color and dimage are required");
+  if (!grads) return fail(ADR_E_INVALID, "grads is NULL");
+  if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
+  if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA)) return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, true, s)) != ADR_OK) return r;
+  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  TIMED(1, launch_xform(m, v, s, st), "transform");
+  TIMED(1, launch_orient(m, v, s, st), "orientation");
+  TIMED(5, launch_fill_f32(s.dclip, 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), 0.f, st), "clear");
+  TIMED(5, launch_fill_f32(s.dattr, 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1), 0.f, st), "clear");
+  TIMED(5, launch_aa_bwd(m, v, s, saved->vis, saved->color, saved->dimage, dloss,
+                       (flags & ADR_FWD_NO_AA) ? 1 : 0, st),
+         "antialias adjoint");
+  TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
+                            saved->vis, st),
+        "shading adjoint");
+  if (grads->kd) TIMED(7, launch_mip_adjoint(kd, grads->kd, st), "mip adjoint");
+  if (grads->normal) TIMED(7, launch_mip_adjoint(nm, grads->normal, st), "mip adjoint");
+  if (grads->orm) TIMED(7, launch_mip_adjoint(orm, grads->orm, st), "mip adjoint");
+  if (m.n_pos > 0 && (grads->pos || grads->vnormal))
+    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
+  return ADR_OK;
+}
+
+adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  ctx->prof = enable != 0;
+  return ADR_OK;
+}
+
+adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count) {
+  if (!ctx || !ms || !count) return fail(ADR_E_INVALID, "ctx, ms and count are required");
+  for (int k = 0; k < ADR_N_STAGES; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  for (const Span& sp : ctx->spans) {
+    HIPCHK(hipEventSynchronize(sp.b), "hipEventSynchronize");
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, sp.a, sp.b), "hipEventElapsedTime");
+    ms[sp.stage] += t;
+    count[sp.stage] += 1;
+    ctx->pool.push_back(sp.a);
+    ctx->pool.push_back(sp.b);
+  }
+  ctx->spans.clear();
+  return ADR_OK;
+}
+
+adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params, int32_t t,
+                         float lr, float beta1, float beta2, float eps, adr_stream stream) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (n_params < 0 || (n_params > 0 && !params)) return fail(ADR_E_INVALID, "bad params");
+  if (t < 1) return fail(ADR_E_INVALID, "t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(ADR_E_INVALID, "bad Adam hyper-parameters");
+  for (int k = 0; k < n_params; ++k) {
+    if (params[k].n < 0) return fail(ADR_E_INVALID, "param %d: negative size", k);
+    if (params[k].n > 0 && (!params[k].param || !params[k].grad || !params[k].m || !params[k].v))
+      return fail(ADR_E_INVALID, "param %d: NULL pointer", k);
+  }
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(9, launch_adam(params, n_params, t, lr, beta1, beta2, eps, st), "adam");
+  return ADR_OK;
+}
+
+adr_status adr_mip_build(adr_ctx* ctx, const adr_texture* tex, adr_stream stream) {
+  if (!ctx || !tex) return fail(ADR_E_INVALID, "ctx and tex are required");
+  Tex t;
+  adr_status r = check_tex(*tex, "tex", true, t);
+  if (r != ADR_OK) return r;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(10, launch_mip_build(t, st), "mip build");
+  return ADR_OK;
+}
+
+adr_status adr_mesh_adjacency(const int32_t* tri, int32_t n_tri, int32_t* adj) {
+  if (n_tri < 0 || (n_tri > 0 && (!tri || !adj))) return fail(ADR_E_INVALID, "bad arguments");
+  std::unordered_map<uint64_t, std::pair<int64_t, int32_t>> first;  // edge -> (t*3+k, count)
+  first.reserve((size_t)n_tri * 2);
+  for (int64_t i = 0; i < 3 * (int64_t)n_tri; ++i) adj[i] = -1;
+  std::vector<int64_t> partner(3 * (size_t)n_tri, -1);
+  for (int32_t t = 0; t < n_tri; ++t) {
+    for (int k = 0; k < 3; ++k) {
+      uint32_t a = (uint32_t)tri[3 * t + (k + 1) % 3], b = (uint32_t)tri[3 * t + (k + 2) % 3];
+      uint64_t key = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+      auto it = first.find(key);
+      if (it == first.end()) {
+        first.emplace(key, std::make_pair((int64_t)3 * t + k, 1));
+      } else {
+        if (it->second.second == 1) partner[3 * (size_t)t + k] = it->second.first;
+        it->second.second += 1;
+      }
+    }
+  }
+  // an edge shared by exactly two triangles links them; otherwise -1
+  for (int32_t t = 0; t < n_tri; ++t) {
+    for (int k = 0; k < 3; ++k) {
+      int64_t p = partner[3 * (size_t)t + k];
+      if (p < 0) continue;
+      uint32_t a = (uint32_t)tri[3 * t + (k + 1) % 3], b = (uint32_t)tri[3 * t + (k + 2) % 3];
+      uint64_t key = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+      if (first[key].second != 2) continue;
+      adj[3 * (int64_t)t + k] = (int32_t)(p / 3);
+      adj[p] = t;
+    }
+  }
+  return ADR_OK;
+}
+
+adr_status adr_views_build(const float* dirs, int32_t n, float dist, float fov_deg, int32_t width,
+                           int32_t height, float* mvp, float* eye) {
+  if (n < 0 || (n > 0 && (!dirs || !mvp || !eye)) || width < 1 || height < 1 || !(dist > 0.f) ||
+      !(fov_deg > 0.f && fov_deg < 180.f))
+    return fail(ADR_E_INVALID, "bad arguments");
+  const double nearp = 0.1, farp = 10.0;
+  double fy = 1.0 / tan(fov_deg * M_PI / 360.0);
+  double aspect = (double)width / (double)height;
+  double P[4][4] = {{fy / aspect, 0, 0, 0},
+                    {0, fy, 0, 0},
+                    {0, 0, (farp + nearp) / (nearp - farp), 2 * farp * nearp / (nearp - farp)},
+                    {0, 0, -1, 0}};
+  for (int b = 0; b < n; ++b) {
+    double d[3] = {dirs[3 * b], dirs[3 * b + 1], dirs[3 * b + 2]};
+    double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(len > 0.0)) return fail(ADR_E_INVALID, "direction %d is zero", b);
+    double e[3] = {dist * d[0] / len, dist * d[1] / len, dist * d[2] / len};
+    double el = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    double f[3] = {-e[0] / el, -e[1] / el, -e[2] / el};
+    double up[3] = {0, 1, 0};
+    if (fabs(f[1]) > 0.999) { up[1] = 0; up[2] = 1; }
+    double s[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    double sl = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    for (double& x : s) x /= sl;
+    double u[3] = {s[1] * f[2] - s[2] * f[1], s[2] * f[0] - s[0] * f[2], s[0] * f[1] - s[1] * f[0]};
+    double V[4][4] = {{s[0], s[1], s[2], -(s[0] * e[0] + s[1] * e[1] + s[2] * e[2])},
+                      {u[0], u[1], u[2], -(u[0] * e[0] + u[1] * e[1] + u[2] * e[2])},
+                      {-f[0], -f[1], -f[2], f[0] * e[0] + f[1] * e[1] + f[2] * e[2]},
+                      {0, 0, 0, 1}};
+    for (int r = 0; r < 4; ++r)
+      for (int c = 0; c < 4; ++c) {
+        double acc = 0;
+        for (int k = 0; k < 4; ++k) acc += P[r][k] * V[k][c];
+        mvp[16 * b + 4 * r + c] = (float)acc;
+      }
+    for (int k = 0; k < 3; ++k) eye[3 * b + k] = (float)e[k];
+  }
+  return ADR_OK;
+}
+
+adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_id) {
+  if (!ctx || !desc || !job_id) return fail(ADR_E_INVALID, "ctx, desc and job_id are required");
+  if (!ctx->jobs) {
+    ctx->jobs = adr::jobs_create(ctx, ctx->device, ctx->budget);
+    if (!ctx->jobs) return fail(ADR_E_NOMEM, "job server");
+  }
+  char msg[256] = "";
+  adr_status r = adr::jobs_submit(ctx->jobs, desc, job_id, msg, sizeof(msg));
+  if (r != ADR_OK) return fail(r, "%s", msg);
+  return ADR_OK;
+}
+
+adr_status adr_job_poll(adr_ctx* ctx, uint64_t job_id, adr_job_status* st, adr_job_result* out) {
+  if (!ctx || !st) return fail(ADR_E_INVALID, "ctx and st are required");
+  if (!ctx->jobs) return fail(ADR_E_NOTFOUND, "no jobs");
+  char msg[256] = "";
+  adr_status r = adr::jobs_poll(ctx->jobs, job_id, st, out, msg, sizeof(msg));
+  if (r < 0) return fail(r, "%s", msg);
+  return r;
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+// Device-side helpers: small vector algebra, the XCD-aware block order and
+// texture addressing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace adr {
+
+struct f3 {
+  float x, y, z;
+};
+__device__ __forceinline__ f3 mk(float x, float y, float z) { return {x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a) { return {-a.x, -a.y, -a.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ f3 operator*(f3 a, f3 b) { return {a.x * b.x, a.y * b.y, a.z * b.z}; }
+__device__ __forceinline__ f3& operator+=(f3& a, f3 b) {
+  a.x += b.x; a.y += b.y; a.z += b.z;
+  return a;
+}
+__device__ __forceinline__ f3& operator-=(f3& a, f3 b) {
+  a.x -= b.x; a.y -= b.y; a.z -= b.z;
+  return a;
+}
+__device__ __forceinline__ float dot(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross(f3 a, f3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ float sum3(f3 a) { return a.x + a.y + a.z; }
+__device__ __forceinline__ f3 ld3(const float* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ void st3(float* p, int64_t i, f3 v) {
+  p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z;
+}
+__device__ __forceinline__ void atomic_add3(float* p, int64_t i, f3 v) {
+  atomicAdd(p + 3 * i, v.x);
+  atomicAdd(p + 3 * i + 1, v.y);
+  atomicAdd(p + 3 * i + 2, v.z);
+}
+
+// x / |x|; vectors with |x|^2 <= 1e-20 pass unchanged.
+__device__ __forceinline__ f3 safe_normalize(f3 x) {
+  float n2 = dot(x, x);
+  return n2 > 1e-20f ? rsqrtf(n2) * x : x;
+}
+// Adjoint of safe_normalize at x for the output gradient g.
+__device__ __forceinline__ f3 safe_normalize_bwd(f3 x, f3 g) {
+  float n2 = dot(x, x);
+  if (!(n2 > 1e-20f)) return g;
+  float inv = rsqrtf(n2);
+  f3 y = inv * x;
+  return inv * (g - dot(g, y) * y);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of an MI355X; each XCD
+// has its own L2.  This maps the hardware block id to a logical tile id so
+// that every XCD works through one contiguous range of tiles (neighbouring
+// pixels share texels and triangles through that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  int xcd = bid & 7, idx = bid >> 3;
+  int per = nb >> 3, rem = nb & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+// Pixel of thread `tid` (0..255) in 16x16 tile `tile`: each 64-wide wave
+// covers an 8x8 block.
+struct Pix {
+  int b, i, j;
+  bool ok;
+};
+__device__ __forceinline__ Pix tile_pixel(int tile, int tid, int tiles_x, int tiles_y, int W, int H) {
+  int per_view = tiles_x * tiles_y;
+  Pix p;
+  p.b = tile / per_view;
+  int r = tile - p.b * per_view;
+  int ty = r / tiles_x, tx = r - ty * tiles_x;
+  int wave = tid >> 6, lane = tid & 63;
+  p.i = tx * 16 + (wave & 1) * 8 + (lane & 7);
+  p.j = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+  p.ok = p.i < W && p.j < H;
+  return p;
+}
+
+// ---- textures ----
+
+__device__ __forceinline__ f3 tex_fetch(const Tex& t, int texel) {
+  if (t.fmt == ADR_TEX_RGBA8) {
+    uchar4 q = reinterpret_cast<const uchar4*>(t.data)[texel];
+    const float s = 1.0f / 255.0f;
+    return {q.x * s, q.y * s, q.z * s};
+  }
+  const float* d = reinterpret_cast<const float*>(t.data);
+  if (t.channels == 3) return ld3(d, texel);
+  float v = d[texel];
+  return {v, 0.f, 0.f};
+}
+
+// Bilinear footprint of (u, v) at level l: four texel indices and weights.
+struct Bil {
+  int idx[4];      // t00, t10, t01, t11
+  float fx, fy;    // fractional position
+  int s;           // level size
+};
+__device__ __forceinline__ Bil bil_footprint(const Tex& t, int l, float u, float v) {
+  Bil b;
+  int s = t.size >> l;
+  if (s < 1) s = 1;
+  b.s = s;
+  float x = u * (float)s - 0.5f;
+  float y = v * (float)s - 0.5f;
+  float x0f = floorf(x), y0f = floorf(y);
+  b.fx = x - x0f;
+  b.fy = y - y0f;
+  int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
+  int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
+  int c0 = x0 % s; if (c0 < 0) c0 += s;
+  int c1 = c0 + 1; if (c1 == s) c1 = 0;
+  int r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
+  int r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);
+  int o = t.off[l];
+  b.idx[0] = o + r0 * s + c0;
+  b.idx[1] = o + r0 * s + c1;
+  b.idx[2] = o + r1 * s + c0;
+  b.idx[3] = o + r1 * s + c1;
+  return b;
+}
+
+struct BilVal {
+  f3 val, du, dv;  // value and derivatives w.r.t. u and v
+};
+__device__ __forceinline__ BilVal bil_eval(const Tex& t, const Bil& b) {
+  f3 t00 = tex_fetch(t, b.idx[0]), t10 = tex_fetch(t, b.idx[1]);
+  f3 t01 = tex_fetch(t, b.idx[2]), t11 = tex_fetch(t, b.idx[3]);
+  float fx = b.fx, fy = b.fy;
+  BilVal r;
+  f3 a = t00 + fx * (t10 - t00);
+  f3 c = t01 + fx * (t11 - t01);
+  r.val = a + fy * (c - a);
+  float s = (float)b.s;
+  r.du = s * ((1.f - fy) * (t10 - t00) + fy * (t11 - t01));
+  r.dv = s * ((1.f - fx) * (t01 - t00) + fx * (t11 - t10));
+  return r;
+}
+
+// Level selection of a trilinear lookup.
+struct Lod {
+  int l0;
+  float f;         // weight of level l0 + 1
+  bool has1;       // l0 + 1 exists
+  bool grad;       // the LOD is differentiable here (not clamped, max > 0)
+  bool use_x;      // max taken from the x derivative
+  float m;         // max(|duv/dx|^2, |duv/dy|^2) in level-0 texels
+};
+__device__ __forceinline__ Lod lod_select(const Tex& t, float ux, float vx, float uy, float vy) {
+  float S = (float)t.size;
+  float sx2 = (ux * S) * (ux * S) + (vx * S) * (vx * S);
+  float sy2 = (uy * S) * (uy * S) + (vy * S) * (vy * S);
+  Lod r;
+  r.use_x = sx2 >= sy2;
+  float m = r.use_x ? sx2 : sy2;
+  r.m = m;
+  float lod_raw = m > 0.f ? 0.5f * log2f(m) : 0.f;
+  float L1 = (float)(t.levels - 1);
+  r.grad = m > 0.f && lod_raw >= 0.f && lod_raw <= L1;
+  float lod = fminf(fmaxf(lod_raw, 0.f), L1);
+  int l0 = (int)floorf(lod);
+  if (l0 > t.levels - 1) l0 = t.levels - 1;
+  r.l0 = l0;
+  r.has1 = l0 + 1 < t.levels;
+  r.f = r.has1 ? lod - (float)l0 : 0.f;
+  return r;
+}
+
+struct TriSample {
+  f3 val;
+  f3 du, dv;       // d value / d(u, v)
+};
+__device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, const Lod& L) {
+  Bil b0 = bil_footprint(t, L.l0, u, v);
+  BilVal a = bil_eval(t, b0);
+  TriSample r{a.val, a.du, a.dv};
+  if (L.has1) {
+    Bil b1 = bil_footprint(t, L.l0 + 1, u, v);
+    BilVal c = bil_eval(t, b1);
+    float f = L.f;
+    r.val = a.val + f * (c.val - a.val);
+    r.du = a.du + f * (c.du - a.du);
+    r.dv = a.dv + f * (c.dv - a.dv);
+  }
+  return r;
+}
+
+}  // namespace adr

@@ -1,0 +1,88 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "adr.h"
+
+namespace adr {
+
+constexpr uint64_t kKeyEmpty = 0xFFFFFFFF00000000ull;
+constexpr int kZMax = 16777215;
+constexpr int kMaxLevels = 15;
+constexpr int kSmallBBox = 256;    // triangles with a pixel bbox up to this are walked per thread
+constexpr int kBigTile = 16;       // big-triangle tiles are kBigTile x kBigTile pixels
+
+// Texture as the kernels see it: level offsets in texels precomputed.
+struct Tex {
+  const void* data;
+  int size, levels, channels, fmt;
+  int off[kMaxLevels + 1];
+};
+
+struct MeshD {
+  const float* pos;
+  const int* tri;
+  const float* uv;
+  const int* uv_tri;
+  const int* adj;
+  int n_pos, n_tri, n_uv;
+};
+
+struct ViewsD {
+  const float* mvp;
+  const float* eye;
+  const float* light_dir;
+  const float* light_rgb;
+  int B, W, H;
+};
+
+// Per-call scratch owned by the context.
+struct Scratch {
+  double* clip;       // [B,V,4] clip coordinates in float64 (interpolation, antialiasing)
+  int* snap;          // [B,V,4]
+  int8_t* orient;     // [B,T]
+  double* nacc;       // [V,3] unnormalised vertex normals (float64)
+  double* tacc;       // [V,3] unnormalised vertex tangents (float64)
+  float* nrm;         // [V,3]
+  float* tan;         // [V,3]
+  uint32_t* big;      // [B,T] big-triangle lists (per view segments of T)
+  uint32_t* big_cnt;  // [B]
+  float* partial;     // loss partials
+  float* gcolor;      // [B,H,W,3] dL/d(colour before AA)
+  float* dclip;       // [B,V,4]
+  float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
+  int n_partial;
+};
+
+// ---- launchers (stream-ordered, no host sync) ----
+hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st);
+hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st);
+hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B,
+                            hipStream_t st);
+hipError_t launch_orient(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st);
+hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis,
+                         uint32_t* cov, hipStream_t st);
+hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
+                            const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
+                            float* color, int32_t* tri_id, hipStream_t st);
+hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
+                              const uint64_t* vis, const float* color, const float* ref,
+                              int loss_kind, int no_aa, float* image, float* dimage, float* loss,
+                              hipStream_t st);
+hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                         const float* color, const float* dimage, const float* dloss, int no_aa,
+                         hipStream_t st);
+hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
+                            const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
+                            const Scratch& s, const uint64_t* vis, hipStream_t st);
+hipError_t launch_mip_adjoint(const Tex& t, float* g, hipStream_t st);
+hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
+                           float* gvnormal, hipStream_t st);
+hipError_t launch_mip_build(const Tex& t, hipStream_t st);
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_adam(const adr_param* params, int n, int t, float lr, float b1, float b2,
+                       float eps, hipStream_t st);
+
+}  // namespace adr

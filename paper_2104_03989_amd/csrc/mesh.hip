@@ -1,0 +1,194 @@
+// Mesh operations (Sec. 5.1, "Tangent space"): smooth vertex normals and
+// UV tangents recomputed from the positions every step, and the adjoint that
+// folds gradients w.r.t. clip coordinates, interpolated attributes, normals
+// and tangents back into vertex positions.
+//   n_v = normalize(sum_{f at v} (p1 - p0) x (p2 - p0))
+//   t_f = (e1 dv2 - e2 dv1) / (du1 dv2 - du2 dv1)   (skipped if |r| < 1e-12)
+//   t_v = normalize(sum_{f at v} t_f)
+#include "dev.h"
+
+namespace adr {
+
+// The frame stage runs in float64: around a UV pole the per-face tangents
+// nearly cancel, and a float32 sum there loses the tangent's direction.  The
+// stage is per face and per vertex, so float64 costs nothing measurable.
+struct d3 {
+  double x, y, z;
+};
+__device__ __forceinline__ d3 dmk(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double ddot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 dcross(d3 a, d3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 dld3f(const float* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ d3 dld3(const double* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ void datomic3(double* p, int64_t i, d3 v) {
+  atomicAdd(p + 3 * i, v.x);
+  atomicAdd(p + 3 * i + 1, v.y);
+  atomicAdd(p + 3 * i + 2, v.z);
+}
+__device__ __forceinline__ void fatomic3(float* p, int64_t i, d3 v) {
+  atomicAdd(p + 3 * i, (float)v.x);
+  atomicAdd(p + 3 * i + 1, (float)v.y);
+  atomicAdd(p + 3 * i + 2, (float)v.z);
+}
+// x / |x| in float64; |x|^2 <= 1e-20 passes unchanged.
+__device__ __forceinline__ d3 dnormalize(d3 x) {
+  double n2 = ddot(x, x);
+  return n2 > 1e-20 ? (1.0 / sqrt(n2)) * x : x;
+}
+__device__ __forceinline__ d3 dnormalize_bwd(d3 x, d3 g) {
+  double n2 = ddot(x, x);
+  if (!(n2 > 1e-20)) return g;
+  double inv = 1.0 / sqrt(n2);
+  d3 y = inv * x;
+  return inv * (g - ddot(g, y) * y);
+}
+
+struct FaceFrame {
+  d3 e1, e2, fn, tf;
+  bool tan_ok;
+  double r, d1v, d2v;
+};
+
+__device__ __forceinline__ FaceFrame face_frame(const MeshD& m, int t) {
+  int i0 = m.tri[3 * t], i1 = m.tri[3 * t + 1], i2 = m.tri[3 * t + 2];
+  int u0 = m.uv_tri[3 * t], u1 = m.uv_tri[3 * t + 1], u2 = m.uv_tri[3 * t + 2];
+  d3 p0 = dld3f(m.pos, i0), p1 = dld3f(m.pos, i1), p2 = dld3f(m.pos, i2);
+  FaceFrame f;
+  f.e1 = p1 - p0;
+  f.e2 = p2 - p0;
+  f.fn = dcross(f.e1, f.e2);
+  double d1u = (double)m.uv[2 * u1] - (double)m.uv[2 * u0], d1v = (double)m.uv[2 * u1 + 1] - (double)m.uv[2 * u0 + 1];
+  double d2u = (double)m.uv[2 * u2] - (double)m.uv[2 * u0], d2v = (double)m.uv[2 * u2 + 1] - (double)m.uv[2 * u0 + 1];
+  f.r = d1u * d2v - d2u * d1v;
+  f.d1v = d1v;
+  f.d2v = d2v;
+  f.tan_ok = fabs(f.r) >= 1e-12;
+  f.tf = f.tan_ok ? (1.0 / f.r) * (d2v * f.e1 - d1v * f.e2) : dmk(0.0, 0.0, 0.0);
+  return f;
+}
+
+__global__ void k_face_accum(MeshD m, double* __restrict__ nacc, double* __restrict__ tacc) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_tri) return;
+  FaceFrame f = face_frame(m, t);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int v = m.tri[3 * t + k];
+    datomic3(nacc, v, f.fn);
+    if (f.tan_ok) datomic3(tacc, v, f.tf);
+  }
+}
+
+__global__ void k_vertex_normalize(int n, const double* __restrict__ nacc, const double* __restrict__ tacc,
+                                   float* __restrict__ nrm, float* __restrict__ tan) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  d3 a = dnormalize(dld3(nacc, v)), b = dnormalize(dld3(tacc, v));
+  st3(nrm, v, mk((float)a.x, (float)a.y, (float)a.z));
+  st3(tan, v, mk((float)b.x, (float)b.y, (float)b.z));
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.0;
+}
+
+__global__ void k_fill(float* __restrict__ p, int64_t n, float val) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = val;
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st) {
+  int64_t n = 3 * (int64_t)m.n_pos;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.nacc, n);
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.tacc, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (m.n_tri > 0) {
+    hipLaunchKernelGGL(k_face_accum, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.nacc, s.tacc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_vertex_normalize, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m.n_pos,
+                     s.nacc, s.tacc, s.nrm, s.tan);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- adjoint
+
+// Per vertex: the clip-space gradient of every view through its MVP, the
+// gradient of the interpolated world position, and the normalize adjoints
+// of the vertex normal and tangent (stored back into dattr for the face pass).
+__global__ void k_vertex_bwd(MeshD m, ViewsD v, const float* __restrict__ dclip,
+                             float* __restrict__ dattr, const double* __restrict__ nacc,
+                             const double* __restrict__ tacc, float* __restrict__ gpos,
+                             float* __restrict__ gvn) {
+  int vi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (vi >= m.n_pos) return;
+  f3 g = ld3(dattr, 3 * vi);  // d(world position)
+  for (int b = 0; b < v.B; ++b) {
+    const float* M = v.mvp + 16 * b;
+    const float* dc = dclip + 4 * ((int64_t)b * m.n_pos + vi);
+    float c0 = dc[0], c1 = dc[1], c2 = dc[2], c3 = dc[3];
+    g.x += M[0] * c0 + M[4] * c1 + M[8] * c2 + M[12] * c3;
+    g.y += M[1] * c0 + M[5] * c1 + M[9] * c2 + M[13] * c3;
+    g.z += M[2] * c0 + M[6] * c1 + M[10] * c2 + M[14] * c3;
+  }
+  if (gpos) atomic_add3(gpos, vi, g);
+  f3 gn = ld3(dattr, 3 * vi + 1);
+  f3 gt = ld3(dattr, 3 * vi + 2);
+  if (gvn) st3(gvn, vi, gn);
+  d3 an = dnormalize_bwd(dld3(nacc, vi), dmk(gn.x, gn.y, gn.z));
+  d3 at = dnormalize_bwd(dld3(tacc, vi), dmk(gt.x, gt.y, gt.z));
+  st3(dattr, 3 * vi + 1, mk((float)an.x, (float)an.y, (float)an.z));
+  st3(dattr, 3 * vi + 2, mk((float)at.x, (float)at.y, (float)at.z));
+}
+
+// Per face: adjoint of the face normal (cross product) and face tangent.
+__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __restrict__ gpos) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m.n_tri) return;
+  int i0 = m.tri[3 * t], i1 = m.tri[3 * t + 1], i2 = m.tri[3 * t + 2];
+  FaceFrame f = face_frame(m, t);
+  d3 gfn = dld3f(dattr, 3 * i0 + 1) + dld3f(dattr, 3 * i1 + 1) + dld3f(dattr, 3 * i2 + 1);
+  d3 g1 = dcross(f.e2, gfn);   // d/d e1 of e1 x e2
+  d3 g2 = dcross(gfn, f.e1);   // d/d e2
+  if (f.tan_ok) {
+    d3 gtf = dld3f(dattr, 3 * i0 + 2) + dld3f(dattr, 3 * i1 + 2) + dld3f(dattr, 3 * i2 + 2);
+    double inv = 1.0 / f.r;
+    g1 = g1 + (f.d2v * inv) * gtf;
+    g2 = g2 - (f.d1v * inv) * gtf;
+  }
+  fatomic3(gpos, i1, g1);
+  fatomic3(gpos, i2, g2);
+  fatomic3(gpos, i0, dmk(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z)));
+}
+
+hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
+                           float* gvnormal, hipStream_t st) {
+  hipLaunchKernelGGL(k_vertex_bwd, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m, v, s.dclip,
+                     s.dattr, s.nacc, s.tacc, gpos, gvnormal);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !gpos || m.n_tri == 0) return e;
+  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos);
+  return hipGetLastError();
+}
+
+}  // namespace adr

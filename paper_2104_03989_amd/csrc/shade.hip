@@ -1,0 +1,574 @@
+// Deferred shading of the rasterized views (Sec. 5.2) and its hand-written
+// adjoint.  Per pixel the G-buffer (position, normal, tangent, bitangent,
+// texture coordinates and their screen derivatives) is formed in registers
+// from the visibility key and the clip coordinates and never stored: the
+// backward kernel recomputes it.
+//
+// Interpolation: with h_k = (x, y, w) of corner k in clip space and the pixel
+// centre p = (px, py, 1) in NDC, D_k = (h_{k+1} x h_{k+2}) . p and
+// lambda_k = D_k / sum D are the perspective-correct barycentrics; their
+// screen derivatives are (a_k - lambda_k sum a) / sum D with a_k the x
+// component of h_{k+1} x h_{k+2} (likewise y), times 2/W (2/H) per pixel.
+// The determinant is evaluated after moving every corner onto the pixel's
+// ray, g_k = (x_k - w_k px, y_k - w_k py), which leaves it unchanged:
+// D_k = g_{k+1} x g_{k+2} (2-D cross product); for pixel-sized triangles the
+// plain triple product cancels badly.
+// Textures: isotropic LOD = 0.5 log2 max(|duv/dx|^2, |duv/dy|^2) in level-0
+// texels, trilinear lookups (wrap u, clamp v); the LOD is differentiated
+// where it is not clamped.  Shading: normal-mapped frame N, T' =
+// normalize(T - (N.T) N), B = N x T'; Blinn-Phong E max(0,n.l)(kd + 0.04
+// max(0,n.h)^32) or the GGX model of Sec. 5.2 with k_s = (1-m) 0.04 + m k_d
+// and k_s' = (1-gamma) k_s.
+#include "dev.h"
+
+namespace adr {
+
+constexpr float kPi = 3.14159265358979323846f;
+
+// The barycentric set-up runs in float64 from float64 clip coordinates:
+// for pixel-sized or thin triangles the screen derivatives of lambda are
+// ill-conditioned, and float32 clip coordinates alone move the texture LOD
+// by ~1e-4 there.  It is ~60 float64 operations per pixel.
+struct PixelGeom {
+  int v[3];        // position indices
+  int t[3];        // uv indices
+  double w[3];     // clip w
+  double gx[3], gy[3];  // x - w px, y - w py
+  double a[3], b[3];    // dD/dpx, dD/dpy
+  double S, px, py;
+  float lam[3], lx[3], ly[3];
+  float sx, sy;
+  f3 x, Ni, T;
+  float u, v_, ux, vx, uy, vy;
+  f3 N, T1, Tp, Bt;
+};
+
+__device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, const double4* clip,
+                                           const float* nrm, const float* tan, int b, int i,
+                                           int j, int tri, PixelGeom& g) {
+  g.px = 2.0 * ((double)i + 0.5) / (double)vw.W - 1.0;
+  g.py = 2.0 * ((double)j + 0.5) / (double)vw.H - 1.0;
+  g.sx = 2.0f / (float)vw.W;
+  g.sy = 2.0f / (float)vw.H;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    g.v[c] = m.tri[3 * tri + c];
+    g.t[c] = m.uv_tri[3 * tri + c];
+    double4 q = clip[(int64_t)b * m.n_pos + g.v[c]];
+    g.w[c] = q.w;
+    g.gx[c] = q.x - q.w * g.px;
+    g.gy[c] = q.y - q.w * g.py;
+  }
+  double D[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
+    D[c] = g.gx[j1] * g.gy[k1] - g.gy[j1] * g.gx[k1];
+    g.a[c] = g.w[k1] * g.gy[j1] - g.w[j1] * g.gy[k1];
+    g.b[c] = g.w[j1] * g.gx[k1] - g.w[k1] * g.gx[j1];
+  }
+  g.S = D[0] + D[1] + D[2];
+  double iS = 1.0 / g.S;
+  double A = g.a[0] + g.a[1] + g.a[2];
+  double Bs = g.b[0] + g.b[1] + g.b[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double lam = D[c] * iS;
+    g.lam[c] = (float)lam;
+    g.lx[c] = (float)((g.a[c] - lam * A) * iS * (2.0 / vw.W));
+    g.ly[c] = (float)((g.b[c] - lam * Bs) * iS * (2.0 / vw.H));
+  }
+  // attributes relative to corner 0 (sum lambda = 1, sum of derivatives = 0):
+  // a = a0 + sum_c lambda_c (a_c - a0), da = sum_c dlambda_c (a_c - a0)
+  g.x = ld3(m.pos, g.v[0]);
+  g.Ni = ld3(nrm, g.v[0]);
+  g.T = ld3(tan, g.v[0]);
+  float u0 = m.uv[2 * g.t[0]], v0 = m.uv[2 * g.t[0] + 1];
+  g.u = u0;
+  g.v_ = v0;
+  g.ux = g.vx = g.uy = g.vy = 0.f;
+#pragma unroll
+  for (int c = 1; c < 3; ++c) {
+    g.x += g.lam[c] * (ld3(m.pos, g.v[c]) - ld3(m.pos, g.v[0]));
+    g.Ni += g.lam[c] * (ld3(nrm, g.v[c]) - ld3(nrm, g.v[0]));
+    g.T += g.lam[c] * (ld3(tan, g.v[c]) - ld3(tan, g.v[0]));
+    float du = m.uv[2 * g.t[c]] - u0, dv = m.uv[2 * g.t[c] + 1] - v0;
+    g.u += g.lam[c] * du;
+    g.v_ += g.lam[c] * dv;
+    g.ux += g.lx[c] * du;
+    g.vx += g.lx[c] * dv;
+    g.uy += g.ly[c] * du;
+    g.vy += g.ly[c] * dv;
+  }
+  g.N = safe_normalize(g.Ni);
+  g.T1 = g.T - dot(g.N, g.T) * g.N;
+  g.Tp = safe_normalize(g.T1);
+  g.Bt = cross(g.N, g.Tp);
+}
+
+// ------------------------------------------------------------------ BRDFs
+
+__device__ __forceinline__ f3 blinn_phong(f3 n, f3 v, f3 l, f3 kd, f3 E) {
+  f3 h = safe_normalize(l + v);
+  float nl = fmaxf(dot(n, l), 0.f);
+  float nh = fmaxf(dot(n, h), 0.f);
+  float nh2 = nh * nh, nh4 = nh2 * nh2, nh8 = nh4 * nh4, nh16 = nh8 * nh8, nh32 = nh16 * nh16;
+  return nl * (E * (kd + mk(0.04f * nh32, 0.04f * nh32, 0.04f * nh32)));
+}
+
+__device__ __forceinline__ void blinn_phong_bwd(f3 n, f3 v, f3 l, f3 kd, f3 E, f3 gc, f3& gn,
+                                                f3& gv, f3& gkd) {
+  f3 hu = l + v;
+  f3 h = safe_normalize(hu);
+  float NL = dot(n, l), NH = dot(n, h);
+  float nl = fmaxf(NL, 0.f), nh = fmaxf(NH, 0.f);
+  float nh2 = nh * nh, nh4 = nh2 * nh2, nh8 = nh4 * nh4, nh16 = nh8 * nh8, nh31 = nh16 * nh8 * nh4 * nh2 * nh;
+  float p32 = nh31 * nh;
+  f3 Eg = E * gc;
+  gkd = nl * Eg;
+  float g_nl = dot(Eg, kd) + 0.04f * p32 * sum3(Eg);
+  float g_nh = nl * 0.04f * sum3(Eg) * 32.f * nh31;
+  float g_NL = NL >= 0.f ? g_nl : 0.f;
+  float g_NH = NH >= 0.f ? g_nh : 0.f;
+  gn = g_NL * l + g_NH * h;
+  gv = safe_normalize_bwd(hu, g_NH * n);
+}
+
+struct GGX {
+  f3 h, hu;
+  float NL, NV, NH, VH, nl, nv, nh, vh, nlc;
+  float r, alpha, a2, C, den, D, k, dl, dv, G1l, G1v, G, Q, w5;
+  bool rok, nhpos;
+  f3 ks, F0, F, diffuse, spec;
+};
+
+__device__ __forceinline__ void ggx_eval(f3 n, f3 v, f3 l, f3 kd, f3 orm, GGX& s) {
+  float gamma = orm.x, rough = orm.y, metal = orm.z;
+  s.rok = rough >= 0.08f && rough <= 1.0f;
+  s.r = fminf(fmaxf(rough, 0.08f), 1.0f);
+  s.alpha = s.r * s.r;
+  s.a2 = s.alpha * s.alpha;
+  s.hu = l + v;
+  s.h = safe_normalize(s.hu);
+  s.NL = dot(n, l);
+  s.NV = dot(n, v);
+  s.NH = dot(n, s.h);
+  s.VH = dot(v, s.h);
+  s.nl = fmaxf(s.NL, 0.f);
+  s.nv = fmaxf(s.NV, 1e-4f);
+  s.nh = fmaxf(s.NH, 0.f);
+  s.vh = fmaxf(s.VH, 0.f);
+  s.nlc = fmaxf(s.nl, 1e-4f);
+  // (n.h)^2 (a^2 - 1) + 1 = a^2 (n.h)^2 + |n x h|^2 for unit n, h; the
+  // second form avoids the cancellation of 1 - (n.h)^2 near the highlight.
+  s.nhpos = s.NH > 0.f;
+  f3 nxh = cross(n, s.h);
+  s.C = dot(nxh, nxh);
+  s.den = s.nhpos ? s.a2 * s.nh * s.nh + s.C : 1.0f;
+  s.D = s.a2 / (kPi * s.den * s.den);
+  s.k = 0.5f * s.alpha;
+  s.dl = s.nl * (1.f - s.k) + s.k;
+  s.dv = s.nv * (1.f - s.k) + s.k;
+  s.G1l = s.nl / s.dl;
+  s.G1v = s.nv / s.dv;
+  s.G = s.G1l * s.G1v;
+  s.ks = mk((1.f - metal) * 0.04f + metal * kd.x, (1.f - metal) * 0.04f + metal * kd.y,
+            (1.f - metal) * 0.04f + metal * kd.z);
+  s.F0 = (1.f - gamma) * s.ks;
+  float om = 1.f - s.vh, om2 = om * om;
+  s.w5 = om2 * om2 * om;
+  s.F = s.F0 + s.w5 * (mk(1.f, 1.f, 1.f) - s.F0);
+  s.Q = s.D * s.G / (4.f * s.nlc * s.nv);
+  s.spec = s.Q * s.F;
+  s.diffuse = ((1.f - metal) / kPi) * kd;
+}
+
+__device__ __forceinline__ f3 ggx(f3 n, f3 v, f3 l, f3 kd, f3 orm, f3 E) {
+  GGX s;
+  ggx_eval(n, v, l, kd, orm, s);
+  return s.nl * (E * (s.diffuse + s.spec));
+}
+
+__device__ __forceinline__ void ggx_bwd(f3 n, f3 v, f3 l, f3 kd, f3 orm, f3 E, f3 gc, f3& gn,
+                                        f3& gv, f3& gkd, f3& gorm) {
+  GGX s;
+  ggx_eval(n, v, l, kd, orm, s);
+  float gamma = orm.x, metal = orm.z;
+  f3 Eg = E * gc;
+  f3 ginner = s.nl * Eg;
+  float g_nl = dot(Eg, s.diffuse + s.spec);
+  // diffuse = kd (1-m) / pi
+  gkd = ((1.f - metal) / kPi) * ginner;
+  float g_m = -dot(ginner, kd) / kPi;
+  // spec = Q F
+  f3 gF = s.Q * ginner;
+  float gQ = dot(ginner, s.F);
+  float inv4 = 1.f / (4.f * s.nlc * s.nv);
+  float gD = gQ * s.G * inv4;
+  float gG = gQ * s.D * inv4;
+  float g_nlc = -gQ * s.Q / s.nlc;
+  float g_nv = -gQ * s.Q / s.nv;
+  // F = F0 + w5 (1 - F0)
+  f3 gF0 = (1.f - s.w5) * gF;
+  float g_w5 = dot(gF, mk(1.f, 1.f, 1.f) - s.F0);
+  float om = 1.f - s.vh, om2 = om * om;
+  float g_vh = -5.f * om2 * om2 * g_w5;
+  // F0 = (1 - gamma) ks, ks = (1-m) 0.04 + m kd
+  float g_gamma = -dot(gF0, s.ks);
+  f3 gks = (1.f - gamma) * gF0;
+  g_m += dot(gks, kd - mk(0.04f, 0.04f, 0.04f));
+  gkd += metal * gks;
+  // G = G1(nl) G1(nv), G1(x) = x / (x (1-k) + k)
+  float gG1l = gG * s.G1v, gG1v = gG * s.G1l;
+  g_nl += gG1l * s.k / (s.dl * s.dl);
+  g_nv += gG1v * s.k / (s.dv * s.dv);
+  float g_k = -gG1l * s.nl * (1.f - s.nl) / (s.dl * s.dl) - gG1v * s.nv * (1.f - s.nv) / (s.dv * s.dv);
+  // D = a2 / (pi den^2)
+  float g_a2 = gD / (kPi * s.den * s.den);
+  float g_den = -2.f * gD * s.D / s.den;
+  float g_NH = 0.f, g_C = 0.f;
+  if (s.nhpos) {
+    g_a2 += g_den * s.nh * s.nh;
+    g_NH = g_den * 2.f * s.a2 * s.nh;
+    g_C = g_den;
+  }
+  float g_alpha = 0.5f * g_k + 2.f * s.alpha * g_a2;
+  float g_r = 2.f * s.r * g_alpha;
+  gorm = mk(g_gamma, s.rok ? g_r : 0.f, g_m);
+  // clamps
+  if (s.nl >= 1e-4f) g_nl += g_nlc;
+  float g_NL = s.NL >= 0.f ? g_nl : 0.f;
+  float g_NV = s.NV >= 1e-4f ? g_nv : 0.f;
+  float g_VH = s.VH >= 0.f ? g_vh : 0.f;
+  // dot products and |n x h|^2
+  gn = g_NL * l + g_NV * v + g_NH * s.h;
+  gv = g_NV * n + g_VH * s.h;
+  f3 gh = g_NH * n + g_VH * v;
+  if (g_C != 0.f) {
+    float nh_ = dot(n, s.h);
+    gn += (2.f * g_C) * (dot(s.h, s.h) * n - nh_ * s.h);
+    gh += (2.f * g_C) * (dot(n, n) * s.h - nh_ * n);
+  }
+  gv += safe_normalize_bwd(s.hu, gh);
+}
+
+// -------------------------------------------------------------- forward
+
+struct ShadeArgs {
+  MeshD m;
+  ViewsD v;
+  int model;
+  Tex kd, nm, orm;
+  const double4* clip;
+  const float* nrm;
+  const float* tan;
+  const uint64_t* vis;
+  int tiles_x, tiles_y;
+};
+
+__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restrict__ color,
+                                                   int32_t* __restrict__ tri_id) {
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  if (!p.ok) return;
+  int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
+  uint64_t key = a.vis[o];
+  uint32_t id = (uint32_t)key;
+  if (tri_id) tri_id[o] = (int32_t)id;
+  if (id == 0u) {
+    st3(color, o, mk(0.f, 0.f, 0.f));
+    return;
+  }
+  PixelGeom g;
+  pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
+  Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
+  f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
+  Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
+  f3 nt = tex_trilinear(a.nm, g.u, g.v_, Ln).val;
+  f3 n = safe_normalize(nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N);
+  f3 eye = ld3(a.v.eye, p.b);
+  f3 vdir = safe_normalize(eye - g.x);
+  f3 l = ld3(a.v.light_dir, p.b);
+  f3 E = ld3(a.v.light_rgb, p.b);
+  f3 c;
+  if (a.model == ADR_SHADE_GGX) {
+    Lod Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
+    f3 orm = tex_trilinear(a.orm, g.u, g.v_, Lo).val;
+    c = ggx(n, vdir, l, kd, orm, E);
+  } else {
+    c = blinn_phong(n, vdir, l, kd, E);
+  }
+  st3(color, o, c);
+}
+
+// -------------------------------------------------------------- backward
+
+// Adjoint of one trilinear lookup: texel gradients (if gtex != NULL) and the
+// gradients w.r.t. (u, v) and the screen derivatives (ux, vx, uy, vy).
+struct UVGrad {
+  float u, v, ux, vx, uy, vy;
+};
+
+__device__ __forceinline__ void scatter_bil(const Tex& t, float* gtex, const Bil& b, float wl, f3 gs) {
+  float fx = b.fx, fy = b.fy;
+  float w[4] = {(1.f - fx) * (1.f - fy), fx * (1.f - fy), (1.f - fx) * fy, fx * fy};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    f3 gq = (wl * w[q]) * gs;
+    if (t.channels == 3) atomic_add3(gtex, b.idx[q], gq);
+    else atomicAdd(gtex + b.idx[q], gq.x);
+  }
+}
+
+__device__ __forceinline__ void tex_bwd(const Tex& t, float* gtex, const PixelGeom& g,
+                                        const Lod& L, f3 gs, UVGrad& G) {
+  Bil b0 = bil_footprint(t, L.l0, g.u, g.v_);
+  BilVal a = bil_eval(t, b0);
+  f3 du = a.du, dvv = a.dv;
+  float w0 = 1.f;
+  if (L.has1) {
+    Bil b1 = bil_footprint(t, L.l0 + 1, g.u, g.v_);
+    BilVal c = bil_eval(t, b1);
+    float f = L.f;
+    du = a.du + f * (c.du - a.du);
+    dvv = a.dv + f * (c.dv - a.dv);
+    w0 = 1.f - f;
+    if (L.grad) {
+      // lod = 0.5 log2(m), m = max over x/y of |duv * size|^2
+      float g_m = dot(gs, c.val - a.val) * 0.5f / (L.m * 0.69314718055994531f);
+      float S2 = (float)t.size * (float)t.size;
+      if (L.use_x) {
+        G.ux += g_m * 2.f * g.ux * S2;
+        G.vx += g_m * 2.f * g.vx * S2;
+      } else {
+        G.uy += g_m * 2.f * g.uy * S2;
+        G.vy += g_m * 2.f * g.vy * S2;
+      }
+    }
+    if (gtex) scatter_bil(t, gtex, b1, f, gs);
+  }
+  if (gtex) scatter_bil(t, gtex, b0, w0, gs);
+  G.u += dot(gs, du);
+  G.v += dot(gs, dvv);
+}
+
+// Per-corner vertex gradients of one pixel: for corner c, acc[12c + 0..8]
+// go to d(world position, normal, tangent) of vertex c and acc[12c + 9..11]
+// to d(clip x, y, w) of vertex c in this view.
+constexpr int kVtxAcc = 36;
+
+// Adjoint of one pixel.  Texel gradients are scattered here; the vertex
+// gradients are returned in acc for the wave-level reduction.  Returns false
+// if the pixel contributes nothing.
+__device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
+                                                const float* __restrict__ gcolor,
+                                                float* __restrict__ gkd, float* __restrict__ gnm,
+                                                float* __restrict__ gorm, float* acc, int& tri,
+                                                int* vtx) {
+  int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
+  uint32_t id = (uint32_t)a.vis[o];
+  if (id == 0u) return false;
+  f3 gc = mk(gcolor[3 * o], gcolor[3 * o + 1], gcolor[3 * o + 2]);
+  if (gc.x == 0.f && gc.y == 0.f && gc.z == 0.f) return false;
+  tri = (int)id - 1;
+  PixelGeom g;
+  pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
+  Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
+  f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
+  Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
+  f3 nt = tex_trilinear(a.nm, g.u, g.v_, Ln).val;
+  f3 mraw = nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N;
+  f3 n = safe_normalize(mraw);
+  f3 eye = ld3(a.v.eye, p.b);
+  f3 vraw = eye - g.x;
+  f3 vdir = safe_normalize(vraw);
+  f3 l = ld3(a.v.light_dir, p.b);
+  f3 E = ld3(a.v.light_rgb, p.b);
+  f3 gn, gv, gkdv, gormv = mk(0.f, 0.f, 0.f);
+  Lod Lo;
+  if (a.model == ADR_SHADE_GGX) {
+    Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
+    f3 orm = tex_trilinear(a.orm, g.u, g.v_, Lo).val;
+    ggx_bwd(n, vdir, l, kd, orm, E, gc, gn, gv, gkdv, gormv);
+  } else {
+    blinn_phong_bwd(n, vdir, l, kd, E, gc, gn, gv, gkdv);
+  }
+  // textures
+  UVGrad G{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  tex_bwd(a.kd, gkd, g, Lk, gkdv, G);
+  // normal map: n = normalize(nt.x T' + nt.y B + nt.z N)
+  f3 gm = safe_normalize_bwd(mraw, gn);
+  f3 gnt = mk(dot(gm, g.Tp), dot(gm, g.Bt), dot(gm, g.N));
+  tex_bwd(a.nm, gnm, g, Ln, gnt, G);
+  if (a.model == ADR_SHADE_GGX) tex_bwd(a.orm, gorm, g, Lo, gormv, G);
+  // frame: B = N x T', T' = normalize(T1), T1 = T - (N.T) N, N = normalize(Ni)
+  f3 gTp = nt.x * gm;
+  f3 gBt = nt.y * gm;
+  f3 gN = nt.z * gm;
+  gN += cross(g.Tp, gBt);
+  gTp += cross(gBt, g.N);
+  f3 gT1 = safe_normalize_bwd(g.T1, gTp);
+  float sNT = dot(g.N, g.T);
+  f3 gT = gT1;
+  float g_s = -dot(gT1, g.N);
+  gN += (-sNT) * gT1;
+  gN += g_s * g.T;
+  gT += g_s * g.N;
+  f3 gNi = safe_normalize_bwd(g.Ni, gN);
+  // view vector
+  f3 gx = -safe_normalize_bwd(vraw, gv);
+  // interpolation: attributes -> barycentrics and vertex attribute gradients
+  // (relative to corner 0, as in the forward pass: the barycentrics sum to
+  // one, so a common offset of the three lambda gradients has no effect)
+  float glam[3], glx[3], gly[3];
+  f3 P0 = ld3(a.m.pos, g.v[0]), N0 = ld3(a.nrm, g.v[0]), T0 = ld3(a.tan, g.v[0]);
+  float u0 = a.m.uv[2 * g.t[0]], v0 = a.m.uv[2 * g.t[0] + 1];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int vi = g.v[c];
+    f3 P = ld3(a.m.pos, vi) - P0, Nv = ld3(a.nrm, vi) - N0, Tv = ld3(a.tan, vi) - T0;
+    float uu = a.m.uv[2 * g.t[c]] - u0, vv = a.m.uv[2 * g.t[c] + 1] - v0;
+    glam[c] = dot(P, gx) + dot(Nv, gNi) + dot(Tv, gT) + uu * G.u + vv * G.v;
+    glx[c] = uu * G.ux + vv * G.vx;
+    gly[c] = uu * G.uy + vv * G.vy;
+    float lc = g.lam[c];
+    float* da = acc + 12 * c;
+    da[0] = lc * gx.x; da[1] = lc * gx.y; da[2] = lc * gx.z;
+    da[3] = lc * gNi.x; da[4] = lc * gNi.y; da[5] = lc * gNi.z;
+    da[6] = lc * gT.x; da[7] = lc * gT.y; da[8] = lc * gT.z;
+    vtx[c] = vi;
+  }
+  // barycentrics (float64, like the forward set-up):
+  // lambda_c = D_c / S, lx_c = (a_c - lambda_c A) / S * sx, ly_c likewise
+  double iS = 1.0 / g.S;
+  double A = g.a[0] + g.a[1] + g.a[2];
+  double Bs = g.b[0] + g.b[1] + g.b[2];
+  double gA = 0.0, gB = 0.0, gS = 0.0;
+  double ga[3], gb[3], gD[3], dlam[3], dglam[3];
+  double sxd = 2.0 / a.v.W, syd = 2.0 / a.v.H;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
+    dlam[c] = (g.gx[j1] * g.gy[k1] - g.gy[j1] * g.gx[k1]) * iS;
+    dglam[c] = glam[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double gu_ = glx[c] * sxd, gw_ = gly[c] * syd;
+    double uc = (g.a[c] - dlam[c] * A) * iS, wc = (g.b[c] - dlam[c] * Bs) * iS;
+    ga[c] = gu_ * iS;
+    gb[c] = gw_ * iS;
+    dglam[c] += -(gu_ * A + gw_ * Bs) * iS;
+    gA += -gu_ * dlam[c] * iS;
+    gB += -gw_ * dlam[c] * iS;
+    gS += -(gu_ * uc + gw_ * wc) * iS;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    ga[c] += gA;
+    gb[c] += gB;
+    gS += -dglam[c] * dlam[c] * iS;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) gD[c] = dglam[c] * iS + gS;
+  // D_c = gx_j gy_k - gy_j gx_k, a_c = w_k gy_j - w_j gy_k, b_c = w_j gx_k - w_k gx_j
+  double ggx[3] = {0.0, 0.0, 0.0}, ggy[3] = {0.0, 0.0, 0.0}, gw[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
+    ggx[j1] += gD[c] * g.gy[k1] - gb[c] * g.w[k1];
+    ggx[k1] += -gD[c] * g.gy[j1] + gb[c] * g.w[j1];
+    ggy[j1] += -gD[c] * g.gx[k1] + ga[c] * g.w[k1];
+    ggy[k1] += gD[c] * g.gx[j1] - ga[c] * g.w[j1];
+    gw[k1] += ga[c] * g.gy[j1] - gb[c] * g.gx[j1];
+    gw[j1] += -ga[c] * g.gy[k1] + gb[c] * g.gx[k1];
+  }
+  // g = (x - w px, y - w py)
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[12 * c + 9] = (float)ggx[c];
+    acc[12 * c + 10] = (float)ggy[c];
+    acc[12 * c + 11] = (float)(gw[c] - ggx[c] * g.px - ggy[c] * g.py);
+  }
+  return true;
+}
+
+// Pixels of one 64-wide wave (an 8x8 block) mostly lie on a few triangles,
+// so their vertex gradients hit the same few addresses.  Lanes are grouped
+// by triangle; each group's 36 sums are formed with cross-lane shuffles and
+// written by 36 lanes with one atomic each, instead of 36 atomics per pixel
+// on the same addresses.
+__global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, const float* __restrict__ gcolor,
+                                                   float* __restrict__ gkd, float* __restrict__ gnm,
+                                                   float* __restrict__ gorm, float* __restrict__ dclip,
+                                                   float* __restrict__ dattr) {
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  float acc[kVtxAcc];
+  int tri = -1;
+  int vtx[3] = {0, 0, 0};
+  bool act = p.ok && shade_bwd_pixel(a, p, gcolor, gkd, gnm, gorm, acc, tri, vtx);
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(act);
+  while (todo) {
+    int leader = __ffsll((long long)todo) - 1;
+    int tl = __shfl(tri, leader);
+    bool mine = act && tri == tl;
+    todo &= ~__ballot(mine);
+    float mysum = 0.f;
+#pragma unroll
+    for (int k = 0; k < kVtxAcc; ++k) {
+      float x = mine ? acc[k] : 0.f;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+      if (lane == k) mysum = x;
+    }
+    int v0 = __shfl(vtx[0], leader), v1 = __shfl(vtx[1], leader), v2 = __shfl(vtx[2], leader);
+    if (lane < kVtxAcc && mysum != 0.f) {
+      int c = lane / 12, comp = lane - 12 * c;
+      int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
+      float* dst = comp < 9 ? dattr + 9 * (int64_t)vi + comp
+                            : dclip + 4 * ((int64_t)p.b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
+      atomicAdd(dst, mysum);
+    }
+  }
+}
+
+static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
+                           const Tex& orm, const Scratch& s, const uint64_t* vis) {
+  ShadeArgs a;
+  a.m = m;
+  a.v = v;
+  a.model = model;
+  a.kd = kd;
+  a.nm = nm;
+  a.orm = orm;
+  a.clip = reinterpret_cast<const double4*>(s.clip);
+  a.nrm = s.nrm;
+  a.tan = s.tan;
+  a.vis = vis;
+  a.tiles_x = (v.W + 15) / 16;
+  a.tiles_y = (v.H + 15) / 16;
+  return a;
+}
+
+hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
+                            const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
+                            float* color, int32_t* tri_id, hipStream_t st) {
+  ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
+  int nb = a.tiles_x * a.tiles_y * v.B;
+  hipLaunchKernelGGL(k_shade_fwd, dim3(nb), dim3(256), 0, st, a, color, tri_id);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
+                            const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
+                            const Scratch& s, const uint64_t* vis, hipStream_t st) {
+  ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
+  int nb = a.tiles_x * a.tiles_y * v.B;
+  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, s.gcolor, gkd, gnm, gorm,
+                     s.dclip, s.dattr);
+  return hipGetLastError();
+}
+
+}  // namespace adr

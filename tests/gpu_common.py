@@ -1,0 +1,74 @@
+"""Shared set-up of GPU parity tests: the same seeded inputs go to the HIP
+path (through the C ABI) and to the oracle.  Cameras come from the oracle
+so that no oracle input is produced by the code under test."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import loop as OL
+from oracle import render as R
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).reshape(-1)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    n = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (n if n > 0 else 1.0))
+
+
+class GpuScene:
+    """A workload uploaded for the HIP path."""
+
+    def __init__(self, w, ctx, mvp32=None, eye=None):
+        from paper_2104_03989_amd import adr
+        self.adr = adr
+        self.w = w
+        self.ctx = ctx
+        if mvp32 is None:
+            mvp32, eye = OL.cameras(w)
+        self.mvp32, self.eye = mvp32, eye
+        self.views = adr.DeviceViews(mvp32, eye, w.light_dir, w.light_rgb, w.width, w.height)
+        self.ref_mesh = adr.DeviceMesh(w.ref.mesh)
+        self.ref_mat = adr.DeviceMaterial(w.ref, ctx=ctx)
+        self.lat_mesh = adr.DeviceMesh(w.latent.mesh)
+        self.lat_mat = adr.DeviceMaterial(w.latent, ctx=ctx)
+
+    def render(self, which="latent", ref=None, flags=0, **kw):
+        adr = self.adr
+        mesh = self.lat_mesh if which == "latent" else self.ref_mesh
+        mat = self.lat_mat if which == "latent" else self.ref_mat
+        out = adr.render_fwd(self.ctx, mesh, mat, self.views, ref=ref, loss=self.w.loss, flags=flags, **kw)
+        torch.cuda.synchronize()
+        return out
+
+    def grads(self, out, names=("pos", "kd", "normal", "orm")):
+        adr = self.adr
+        g = {"pos": torch.zeros_like(self.lat_mesh.pos) if "pos" in names else None}
+        for n in ("kd", "normal", "orm"):
+            tex = getattr(self.lat_mat, n)
+            g[n] = tex.grad_buffer() if (n in names and tex is not None and tex.fmt == adr.TEX_F32) else None
+        adr.render_bwd(self.ctx, self.lat_mesh, self.lat_mat, self.views, out, g)
+        torch.cuda.synchronize()
+        res = {}
+        for n, t in g.items():
+            if t is None:
+                continue
+            if n == "pos":
+                res[n] = t.cpu().numpy()
+            else:
+                tex = getattr(self.lat_mat, n)
+                res[n] = t[:tex.size * tex.size].cpu().numpy().reshape(tex.size, tex.size, -1)
+                res[n + "_coarse_max"] = float(t[tex.size * tex.size:].abs().max()) if t.shape[0] > tex.size ** 2 else 0.0
+        return res
+
+
+def oracle_keys(w, scene, mvp32):
+    """Oracle visibility of every view: keys [B,H,W] uint64, coverage."""
+    keys, cov = [], []
+    for b in range(mvp32.shape[0]):
+        sv = R.snap(scene.mesh.pos, mvp32[b], w.width, w.height)
+        k, c, _ = R.raster(scene.mesh.tri, sv, w.width, w.height)
+        keys.append(k)
+        cov.append(c)
+    return np.stack(keys), np.stack(cov)

@@ -1,0 +1,230 @@
+"""Parity of the HIP path (called through the C ABI) with the FP64 oracle on
+the same seeded inputs: visibility and coverage bit-exact, forward images
+within 1e-5 absolute, gradients within 1e-4 relative L2."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import loop as OL
+from oracle import render as R
+from paper_2104_03989_amd import synth
+from tests import oracle_scenes as S
+from tests.gpu_common import GpuScene, oracle_keys, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 1e-5
+GRAD_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2104_03989_amd import adr
+    c = adr.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _vis_np(out):
+    return out["vis"].cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------------ visibility
+
+@pytest.mark.parametrize("seed", range(4))
+def test_visibility_random_triangles_bit_exact(ctx, seed):
+    from paper_2104_03989_amd import adr
+    _say("visibility random", seed)
+    g = np.random.default_rng(seed)
+    W, H = [(16, 16), (37, 29), (64, 48), (100, 7)][seed]
+    V, T = 60, 80
+    xy = g.uniform(-1.3, 1.3, size=(V, 2))
+    big = g.random(V) < 0.3
+    xy[big] *= 4.0                      # some triangles far larger than the screen
+    for v in range(0, V, 4):            # vertices exactly on pixel centres
+        xy[v, 0] = 2 * (g.integers(0, W) + 0.5) / W - 1
+        xy[v, 1] = 2 * (g.integers(0, H) + 0.5) / H - 1
+    pos = np.concatenate([xy, g.uniform(-0.9, 0.9, size=(V, 1))], 1).astype(np.float32)
+    tri = g.integers(0, V, size=(T, 3)).astype(np.int32)
+    mesh = synth.Mesh(pos, tri, np.zeros((1, 2), np.float32), np.zeros_like(tri))
+    scene = synth.Scene(mesh, "blinn_phong", S.const_tex((1, 1, 1)), S.flat_normals(), None)
+    mvp = np.tile(np.eye(4, dtype=np.float32), (2, 1, 1))
+    mvp[1] = np.diag([1.0, -1.0, 1.0, 1.0]).astype(np.float32)   # a mirrored view
+    w = S.workload(scene, scene, [(0, 0, 1), (0, 0, 1)], [(0, 0, 1)], W, H)
+    gs = GpuScene(w, ctx, mvp, np.zeros((2, 3), np.float32))
+    out = gs.render("latent", want_tri_id=True, want_coverage=True)
+    keys, cov = oracle_keys(w, scene, mvp)
+    assert np.array_equal(_vis_np(out), keys)
+    assert np.array_equal(out["coverage"].cpu().numpy().astype(np.uint32), cov)
+    assert np.array_equal(out["tri_id"].cpu().numpy(), R.key_tri(keys).astype(np.int32))
+
+
+@pytest.mark.parametrize("name", ["plain", "paper"])
+def test_visibility_workload_meshes_bit_exact(ctx, name):
+    _say("visibility workload", name)
+    if name == "plain":
+        w = synth.workload_plain_step()
+    else:
+        w = synth.scaled(synth.workload_paper_loop(map_size=64), views=3)
+    mvp32, eye = OL.cameras(w)
+    gs = GpuScene(w, ctx, mvp32, eye)
+    for which, scene in (("latent", w.latent), ("ref", w.ref)):
+        out = gs.render(which, want_coverage=True)
+        keys, cov = oracle_keys(w, scene, mvp32)
+        assert np.array_equal(_vis_np(out), keys), which
+        assert np.array_equal(out["coverage"].cpu().numpy().astype(np.uint32), cov), which
+
+
+def test_empty_mesh_renders_background(ctx):
+    _say("empty mesh")
+    mesh = synth.Mesh(np.zeros((3, 3), np.float32), np.zeros((0, 3), np.int32),
+                      np.zeros((1, 2), np.float32), np.zeros((0, 3), np.int32))
+    scene = synth.Scene(mesh, "blinn_phong", S.const_tex((1, 1, 1)), S.flat_normals(), None)
+    w = S.workload(scene, scene, [(0, 0, 1)], [(0, 0, 1)], 19, 23)
+    gs = GpuScene(w, ctx)
+    ref = torch.zeros(1, 23, 19, 3, device="cuda")
+    out = gs.render("latent", ref=ref, want_tri_id=True)
+    assert (out["tri_id"] == 0).all()
+    assert float(out["image"].abs().max()) == 0.0
+    assert float(out["loss"][0]) == 0.0
+
+
+# ------------------------------------------------------------------ forward
+
+def _fwd_case(ctx, w, tonemapped):
+    mvp32, eye = OL.cameras(w)
+    gs = GpuScene(w, ctx, mvp32, eye)
+    o_ref = OL.render_scene(w.ref, mvp32, eye, w)
+    g_ref = gs.render("ref")
+    B, H, W = w.dirs.shape[0], w.height, w.width
+    keys, _ = oracle_keys(w, w.ref, mvp32)
+    assert np.array_equal(_vis_np(g_ref), keys)
+    for k in ("color", "image"):
+        got = g_ref[k].cpu().numpy().reshape(B, H * W, 3).astype(np.float64)
+        exp = o_ref[k].detach().numpy()
+        if tonemapped:
+            got_t = R.tonemap(torch.from_numpy(got)).numpy()
+            exp_t = R.tonemap(torch.from_numpy(exp)).numpy()
+            assert np.abs(got_t - exp_t).max() < FWD_TOL, k
+            assert (np.abs(got - exp) / np.maximum(np.abs(exp), 1.0)).max() < 1e-4, k
+        else:
+            assert np.abs(got - exp).max() < FWD_TOL, k
+    return gs, o_ref, g_ref
+
+
+def test_forward_plain_step_small(ctx):
+    _say("forward plain small")
+    w = synth.scaled(synth.workload_plain_step(), views=2, res=96)
+    _fwd_case(ctx, w, tonemapped=False)
+
+
+def test_forward_plain_step_full(ctx):
+    _say("forward plain full")
+    _fwd_case(ctx, synth.workload_plain_step(), tonemapped=False)
+
+
+def test_forward_ggx_ragged(ctx):
+    _say("forward ggx ragged")
+    w = synth.scaled(synth.workload_paper_loop(map_size=64, ref_nu=24, lat_nu=6), views=2)
+    w.width, w.height = 77, 53
+    _fwd_case(ctx, w, tonemapped=True)
+
+
+# ------------------------------------------------------------------ loss + gradients
+
+def _grad_case(ctx, w, names):
+    mvp32, eye = OL.cameras(w)
+    gs = GpuScene(w, ctx, mvp32, eye)
+    ref = OL.reference_image(w, mvp32, eye)
+    B, H, W = w.dirs.shape[0], w.height, w.width
+    ref_dev = ref.reshape(B, H, W, 3).to(torch.float32).cuda().contiguous()
+    loss_o, grads_o, _ = OL.loss_and_grads(w, ref, mvp32, eye)
+    out = gs.render("latent", ref=ref_dev)
+    loss_g = float(out["loss"][0])
+    assert abs(loss_g - float(loss_o)) <= 1e-5 * abs(float(loss_o)) + 1e-9
+    g = gs.grads(out, names)
+    for n in names:
+        e = rel_l2(g[n], grads_o[n].numpy())
+        _say(f"  grad {n}: rel-L2 {e:.3g}")
+        assert e < GRAD_TOL, (n, e)
+        if n != "pos":
+            assert g[n + "_coarse_max"] == 0.0
+    return gs, g, grads_o
+
+
+def test_gradients_plain_step_small(ctx):
+    _say("gradients plain small")
+    w = synth.scaled(synth.workload_plain_step(map_size=64), views=2, res=64)
+    _grad_case(ctx, w, ("pos", "normal"))
+
+
+def test_gradients_ggx_small(ctx):
+    _say("gradients ggx small")
+    w = S.tiny_sphere_workload("ggx", nu=3, res=40, views=2, tex=16, loss="l1_tonemap", seed=3)
+    _grad_case(ctx, w, ("pos", "kd", "normal", "orm"))
+
+
+def test_gradients_blinn_phong_l2(ctx):
+    _say("gradients bp l2")
+    w = S.tiny_sphere_workload("blinn_phong", nu=3, res=48, views=3, tex=32, loss="l2", seed=4)
+    _grad_case(ctx, w, ("pos", "kd", "normal"))
+
+
+def test_gradients_paper_loop_reduced(ctx):
+    _say("gradients paper reduced")
+    w = synth.scaled(synth.workload_paper_loop(map_size=256, ref_nu=40, lat_nu=10), views=2, res=128)
+    _grad_case(ctx, w, ("pos", "kd", "normal"))
+
+
+# ------------------------------------------------------------------ optimiser, mips
+
+def test_adam_matches_oracle(ctx):
+    from paper_2104_03989_amd import adr
+    _say("adam")
+    g = np.random.default_rng(0)
+    n = 1003  # ragged: a float4 body and a scalar tail
+    p, gr = g.normal(size=n), g.normal(size=n)
+    m, v = g.normal(size=n) * 0.1, np.abs(g.normal(size=n)) * 0.01
+    T = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in (p, gr, m, v)]
+    q = torch.tensor(g.normal(size=64), dtype=torch.float32, device="cuda")
+    q0 = q.cpu().numpy().astype(np.float64)
+    Q = [q, torch.ones_like(q), torch.zeros_like(q), torch.zeros_like(q)]
+    adr.adam_step(ctx, [tuple(T), tuple(Q)], 7, 1e-3)
+    torch.cuda.synchronize()
+    p32, g32, m32, v32 = (x.astype(np.float32).astype(np.float64) for x in (p, gr, m, v))
+    pe, me, ve = R.adam(p32, g32, m32, v32, 7, 1e-3)
+    assert np.abs(T[0].cpu().numpy() - pe).max() < 1e-6
+    assert np.abs(T[2].cpu().numpy() - me).max() < 1e-6
+    assert np.abs(T[3].cpu().numpy() - ve).max() < 1e-6
+    assert float(T[1].abs().max()) == 0.0
+    pq, _, _ = R.adam(q0, np.ones(64), np.zeros(64), np.zeros(64), 7, 1e-3)
+    assert np.abs(Q[0].cpu().numpy() - pq).max() < 1e-6
+
+
+def test_mip_chains(ctx):
+    from paper_2104_03989_amd import adr
+    _say("mips")
+    g = np.random.default_rng(1)
+    q = g.integers(0, 256, size=(32, 32, 4)).astype(np.uint8)
+    t = adr.DeviceTexture(q, "rgba8", ctx=ctx)
+    torch.cuda.synchronize()
+    ints = [q.astype(np.int64)]
+    for _ in range(5):
+        x = ints[-1]
+        s = x.shape[0] // 2
+        ints.append((x.reshape(s, 2, s, 2, 4).sum(axis=(1, 3)) + 2) // 4)
+    exp = np.concatenate([x.reshape(-1, 4) for x in ints]).astype(np.uint8)
+    assert np.array_equal(t.data.cpu().numpy(), exp)
+    f = g.uniform(size=(64, 64, 3)).astype(np.float32)
+    tf = adr.DeviceTexture(f, "f32", ctx=ctx)
+    torch.cuda.synchronize()
+    lv = R.mip_chain_f32(torch.from_numpy(f.astype(np.float64)))
+    exp = np.concatenate([x.reshape(-1, 3).numpy() for x in lv])
+    assert np.abs(tf.data.cpu().numpy() - exp).max() < 1e-6
