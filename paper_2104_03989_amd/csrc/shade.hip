@@ -352,19 +352,135 @@ __device__ __forceinline__ void tex_bwd(const Tex& t, float* gtex, const PixelGe
   G.v += dot(gs, dvv);
 }
 
+// ---- wave-aggregated texel-gradient scatter ----
+//
+// The 64 pixels of a wave (an 8x8 block) sample overlapping bilinear
+// footprints: at the level the LOD picks, texels are about pixel-sized, so
+// the wave touches roughly (8+1)^2 texels of a level where its lanes would
+// issue 64 x 4 atomics per channel.  Per level present in the wave, the
+// lanes' contributions are summed into an LDS window covering the wave's
+// footprint (LDS atomics), and the window's nonzero texel-channels are then
+// added to HBM once each.  A footprint larger than the window (a UV seam,
+// very oblique sampling) falls back to direct atomics.
+
+constexpr int kWinFloats = 3072;  // per wave: 32 x 32 texels x 3 channels
+
+struct TexScatter {
+  float u, v;
+  int l0;
+  float f;
+  bool has1;
+  f3 gs;
+};
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
+  return x;
+}
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Unwrapped bilinear footprint at level l: rows r0 <= r1 (clamped), columns
+// c0 and c0 + 1 with c0 in [0, s) (c0 + 1 may equal s: wraps to 0).
+struct Foot {
+  int r0, r1, c0, s;
+  float fx, fy;
+};
+__device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
+  Foot q;
+  int s = t.size >> l;
+  if (s < 1) s = 1;
+  q.s = s;
+  float x = u * (float)s - 0.5f, y = v * (float)s - 0.5f;
+  float x0f = floorf(x), y0f = floorf(y);
+  q.fx = x - x0f;
+  q.fy = y - y0f;
+  int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
+  int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
+  int c0 = x0 % s;
+  if (c0 < 0) c0 += s;
+  q.c0 = c0;
+  q.r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
+  q.r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);
+  return q;
+}
+
+__device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool act, const TexScatter& ts,
+                                 float* win) {
+  const int BIG = 1 << 20;
+  const int lane = threadIdx.x & 63;
+  const int C = t.channels;
+  bool done0 = !act, done1 = !(act && ts.has1);
+  while (true) {
+    int my = min(done0 ? BIG : ts.l0, done1 ? BIG : ts.l0 + 1);
+    int lev = wave_min_i(my);
+    if (lev >= BIG) break;
+    bool use0 = !done0 && ts.l0 == lev;
+    bool use1 = !done1 && ts.l0 + 1 == lev;
+    bool part = use0 || use1;
+    float wl = use0 ? (ts.has1 ? 1.f - ts.f : 1.f) : ts.f;
+    done0 = done0 || use0;
+    done1 = done1 || use1;
+    Foot q = foot_at(t, lev, ts.u, ts.v);
+    int rmin = wave_min_i(part ? q.r0 : BIG), rmax = wave_max_i(part ? q.r1 : -1);
+    int cmin = wave_min_i(part ? q.c0 : BIG), cmax = wave_max_i(part ? q.c0 + 1 : -1);
+    int hh = rmax - rmin + 1, ww = cmax - cmin + 1;
+    float w[4] = {(1.f - q.fx) * (1.f - q.fy), q.fx * (1.f - q.fy), (1.f - q.fx) * q.fy, q.fx * q.fy};
+    int rr[4] = {q.r0, q.r0, q.r1, q.r1}, cc[4] = {q.c0, q.c0 + 1, q.c0, q.c0 + 1};
+    float gsv[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
+    int off = t.off[lev];
+    if (hh * ww * C <= kWinFloats) {
+      int n = hh * ww * C;
+      for (int k = lane; k < n; k += 64) win[k] = 0.f;
+      wave_sync();
+      if (part) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          int cell = ((rr[k] - rmin) * ww + (cc[k] - cmin)) * C;
+          for (int ch = 0; ch < C; ++ch) atomicAdd(win + cell + ch, wl * w[k] * gsv[ch]);
+        }
+      }
+      wave_sync();
+      for (int k = lane; k < n; k += 64) {
+        float val = win[k];
+        if (val != 0.f) {
+          int texel = k / C, ch = k - texel * C;
+          int r = rmin + texel / ww, c = cmin + texel % ww;
+          if (c >= q.s) c -= q.s;
+          atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
+        }
+      }
+      wave_sync();
+    } else if (part) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int c = cc[k] >= q.s ? cc[k] - q.s : cc[k];
+        for (int ch = 0; ch < C; ++ch)
+          atomicAdd(gtex + (int64_t)(off + rr[k] * q.s + c) * C + ch, wl * w[k] * gsv[ch]);
+      }
+    }
+  }
+}
+
 // Per-corner vertex gradients of one pixel: for corner c, acc[12c + 0..8]
 // go to d(world position, normal, tangent) of vertex c and acc[12c + 9..11]
 // to d(clip x, y, w) of vertex c in this view.
 constexpr int kVtxAcc = 36;
 
-// Adjoint of one pixel.  Texel gradients are scattered here; the vertex
-// gradients are returned in acc for the wave-level reduction.  Returns false
-// if the pixel contributes nothing.
+// Adjoint of one pixel.  The vertex gradients are returned in acc and the
+// three texture lookups' sample gradients in ts (kd, normal, orm), both for
+// the wave-level scatter.  Returns false if the pixel contributes nothing.
 __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
-                                                const float* __restrict__ gcolor,
-                                                float* __restrict__ gkd, float* __restrict__ gnm,
-                                                float* __restrict__ gorm, float* acc, int& tri,
-                                                int* vtx) {
+                                                const float* __restrict__ gcolor, float* acc,
+                                                int& tri, int* vtx, TexScatter* ts) {
   int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
   uint32_t id = (uint32_t)a.vis[o];
   if (id == 0u) return false;
@@ -395,12 +511,15 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   }
   // textures
   UVGrad G{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  tex_bwd(a.kd, gkd, g, Lk, gkdv, G);
+  tex_bwd(a.kd, nullptr, g, Lk, gkdv, G);
   // normal map: n = normalize(nt.x T' + nt.y B + nt.z N)
   f3 gm = safe_normalize_bwd(mraw, gn);
   f3 gnt = mk(dot(gm, g.Tp), dot(gm, g.Bt), dot(gm, g.N));
-  tex_bwd(a.nm, gnm, g, Ln, gnt, G);
-  if (a.model == ADR_SHADE_GGX) tex_bwd(a.orm, gorm, g, Lo, gormv, G);
+  tex_bwd(a.nm, nullptr, g, Ln, gnt, G);
+  if (a.model == ADR_SHADE_GGX) tex_bwd(a.orm, nullptr, g, Lo, gormv, G);
+  ts[0] = TexScatter{g.u, g.v_, Lk.l0, Lk.f, Lk.has1, gkdv};
+  ts[1] = TexScatter{g.u, g.v_, Ln.l0, Ln.f, Ln.has1, gnt};
+  if (a.model == ADR_SHADE_GGX) ts[2] = TexScatter{g.u, g.v_, Lo.l0, Lo.f, Lo.has1, gormv};
   // frame: B = N x T', T' = normalize(T1), T1 = T - (N.T) N, N = normalize(Ni)
   f3 gTp = nt.x * gm;
   f3 gBt = nt.y * gm;
@@ -502,12 +621,18 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, const float* __r
                                                    float* __restrict__ gkd, float* __restrict__ gnm,
                                                    float* __restrict__ gorm, float* __restrict__ dclip,
                                                    float* __restrict__ dattr) {
+  __shared__ float win_all[4][kWinFloats];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   float acc[kVtxAcc];
   int tri = -1;
   int vtx[3] = {0, 0, 0};
-  bool act = p.ok && shade_bwd_pixel(a, p, gcolor, gkd, gnm, gorm, acc, tri, vtx);
+  TexScatter ts[3];
+  bool act = p.ok && shade_bwd_pixel(a, p, gcolor, acc, tri, vtx, ts);
+  float* win = win_all[threadIdx.x >> 6];
+  if (gkd) wave_scatter_tex(a.kd, gkd, act, ts[0], win);
+  if (gnm) wave_scatter_tex(a.nm, gnm, act, ts[1], win);
+  if (gorm && a.model == ADR_SHADE_GGX) wave_scatter_tex(a.orm, gorm, act, ts[2], win);
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(act);
   while (todo) {
