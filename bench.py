@@ -123,6 +123,83 @@ def cpu_baseline(w, np, torch):
                 seconds=round(dt, 2))
 
 
+def serve_pool(n, g):
+    """Workloads of the served mix: reference 20k-735k and target 1k-20k
+    triangles (log-uniform), 1024^2 maps, 8 views of 512x512."""
+    from paper_2104_03989_amd import synth
+
+    def nu_for(tris):
+        return max(2, int(round(math.sqrt(tris / 20.0))))
+    pool = []
+    for _ in range(n):
+        rt = math.exp(g.uniform(math.log(20e3), math.log(735e3)))
+        lt = math.exp(g.uniform(math.log(1e3), math.log(20e3)))
+        pool.append(synth.workload_paper_loop(views=8, res=512, map_size=1024, ref_nu=nu_for(rt),
+                                              lat_nu=nu_for(lt)))
+    return pool
+
+
+def serve(args):
+    """Served mode: jobs shaped like the served workload arrive as a Poisson
+    stream; the job server admits them by HBM budget and interleaves their
+    steps.  Reports jobs/hr, steps/s and per-step p50/p99 latency, and the
+    steps/s of the same jobs run one at a time."""
+    import numpy as np
+    from paper_2104_03989_amd import adr, synth
+
+    g = np.random.Generator(np.random.PCG64(synth.seed_for(5, 0)))
+    pool = serve_pool(args.serve_pool, g)
+    n_jobs = args.serve_jobs
+    arrivals = np.cumsum(g.exponential(1.0 / args.serve_rate, size=n_jobs))
+    ctx = adr.Context(0)
+    # one job alone first (warm-up, and the one-at-a-time reference)
+    t0 = time.perf_counter()
+    jid = adr.job_submit(ctx, pool[0], n_steps=args.serve_steps, seed=1)
+    while True:
+        st, _ = adr.job_poll(ctx, jid)
+        if st["state"] == adr.JOB_DONE:
+            break
+        if st["code"] < 0:
+            raise RuntimeError(st.get("error"))
+        time.sleep(0.002)
+    adr.job_poll(ctx, jid, pool[0])
+    alone_steps_s = args.serve_steps / (time.perf_counter() - t0)
+    _log(f"one job alone: {alone_steps_s:.1f} steps/s")
+    t0 = time.perf_counter()
+    submitted, done, lat = {}, {}, []
+    k = 0
+    while len(done) < n_jobs:
+        now = time.perf_counter() - t0
+        while k < n_jobs and arrivals[k] <= now:
+            w = pool[k % len(pool)]
+            submitted[adr.job_submit(ctx, w, n_steps=args.serve_steps, seed=1000 + k)] = w
+            k += 1
+        for jid, w in list(submitted.items()):
+            if jid in done:
+                continue
+            st, res = adr.job_poll(ctx, jid, w)
+            if st["code"] < 0:
+                _log(f"job {jid} failed: {st.get('error')}")
+                done[jid] = st
+            elif st["state"] == adr.JOB_DONE:
+                done[jid] = st
+        time.sleep(0.002)
+    wall = time.perf_counter() - t0
+    steps = sum(s["step"] for s in done.values())
+    p50 = float(np.median([s["p50_ms"] for s in done.values()]))
+    p99 = float(np.max([s["p99_ms"] for s in done.values()]))
+    rec = {"metric": "served jobs/hr with p50/p99 step ms", "value": round(n_jobs / wall * 3600, 1),
+           "unit": "jobs/hr", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "steps_per_s": round(steps / wall, 1), "one_at_a_time_steps_per_s": round(alone_steps_s, 1),
+           "p50_step_ms": round(p50, 3), "p99_step_ms": round(p99, 3), "wall_s": round(wall, 2),
+           "config": {"workload": "served: Poisson arrivals, reference 20k-735k tris, target 1k-20k tris, "
+                                  "1024^2 maps, 8 views x 512x512, GGX, tone-mapped L1",
+                      "rate_per_s": args.serve_rate, "jobs": n_jobs, "steps_per_job": args.serve_steps,
+                      "mesh_pool": len(pool)}}
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,11 +207,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
+    ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-jobs", type=int, default=16)
+    ap.add_argument("--serve-steps", type=int, default=200)
+    ap.add_argument("--serve-pool", type=int, default=4)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.serve:
+        serve(args)
+        return
 
     import numpy as np
     import torch

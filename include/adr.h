@@ -261,6 +261,15 @@ typedef struct adr_job_result {  /* host buffers the caller allocates */
   float* orm;                    /* level 0 (if GGX) */
 } adr_job_result;
 
+/* The cameras and lights a job draws at step `step` (0-based): for view b,
+ * direction and light are unit vectors from three normal deviates each
+ * (Box-Muller on SplitMix64 uniforms u_i = (mix(seed + (i+1) 0x9E3779B97F4A7C15)
+ * >> 11) 2^-53, i = (step n_views + b) 8 + k, k 0..3 for the direction and
+ * 4..7 for the light; with light_per_view == 0 every view of a step uses
+ * view 0's light).  dirs, lights: host [n_views,3].  Host-only. */
+adr_status adr_job_views(uint64_t seed, int32_t step, int32_t n_views, int32_t light_per_view,
+                         float* dirs, float* lights);
+
 /* Queue a job.  Returns ADR_E_OVER_BUDGET if its footprint can never fit the
  * context's budget.  The server thread starts on the first submit. */
 adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_id);
@@ -268,7 +277,9 @@ adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_
 /* State of a job.  With out != NULL and state DONE, copies the optimised
  * latent model into the caller's host buffers and releases the job (a later
  * poll returns ADR_E_NOTFOUND).  Returns ADR_OK, ADR_PENDING (queued or
- * running), ADR_E_NONFINITE (failed), ADR_E_NOTFOUND. */
+ * running), ADR_E_NONFINITE (stopped on a non-finite loss), ADR_E_HIP (could
+ * not be admitted or stepped; adr_last_error says why), ADR_E_NOTFOUND.  A
+ * failed job is released by the poll that reports it. */
 adr_status adr_job_poll(adr_ctx* ctx, uint64_t job_id, adr_job_status* st, adr_job_result* out);
 
 #ifdef __cplusplus

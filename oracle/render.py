@@ -353,8 +353,11 @@ def srgb(x):
 
 
 def tonemap(x):
-    """x' = Gamma(log(x + 1))."""
-    return srgb(torch.log(x + 1.0))
+    """x' = Gamma(log(x + 1)) for x >= 0, extended as an odd function,
+    T(x) = sign(x) T(|x|), to the negative radiance that freely optimised
+    texels can produce (smooth through 0, where T(x) = 12.92 x)."""
+    a = torch.abs(x)
+    return torch.sign(x) * srgb(torch.log(a + 1.0))
 
 
 def image_loss(img, ref, kind: str):
@@ -433,7 +436,8 @@ def antialias(color: torch.Tensor, clip: torch.Tensor, pairs, W: int, H: int):
     to [0,1] is where the edge crosses the segment from P to Q.  A box filter
     one pixel wide gives: if s > 1/2, out(Q) += (s - 1/2)(c(P) - c(Q)); if
     s < 1/2, out(P) += (1/2 - s)(c(Q) - c(P)).  All contributions are formed
-    from the un-antialiased colours, so their order does not matter.
+    from the un-antialiased colours, so their order does not matter.  A pixel
+    whose received weights sum to W > 1 has its contributions scaled by 1/W.
     """
     P, Q, va, vb = pairs
     if P.size == 0:
@@ -460,9 +464,14 @@ def antialias(color: torch.Tensor, clip: torch.Tensor, pairs, W: int, H: int):
     cP, cQ = color[P_t], color[Q_t]
     wq = torch.clamp(s - 0.5, min=0.0)[:, None]
     wp = torch.clamp(0.5 - s, min=0.0)[:, None]
-    out = color.index_add(0, Q_t, wq * (cP - cQ))
-    out = out.index_add(0, P_t, wp * (cQ - cP))
-    return out
+    # Weights a pixel receives from several pairs can sum past 1 (several
+    # edges of sub-pixel triangles cross near it); they are then scaled by
+    # 1 / sum so that every output stays a convex blend of colours.
+    wsum = torch.zeros(color.shape[0], 1, dtype=color.dtype)
+    wsum = wsum.index_add(0, Q_t, wq).index_add(0, P_t, wp)
+    acc = torch.zeros_like(color).index_add(0, Q_t, wq * (cP - cQ)).index_add(0, P_t, wp * (cQ - cP))
+    scale = 1.0 / torch.clamp(wsum, min=1.0)
+    return color + acc * scale
 
 
 # ---------------------------------------------------------------------------

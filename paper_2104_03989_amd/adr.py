@@ -32,7 +32,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
-           "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read")
+           "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views")
 N_STAGES = 11
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build")
@@ -358,3 +358,94 @@ class RenderLoss(torch.autograd.Function):
             tex = getattr(mat, name)
             res.append(None if g is None else g[:tex.size * tex.size])
         return (*res, None, None, None, None, None, None, None)
+
+
+# ---------------------------------------------------------------- job server
+
+_lib.adr_job_views.argtypes = [C.c_uint64, I32, I32, I32, P, P]
+_lib.adr_job_views.restype = I32
+
+
+def job_views(seed: int, step: int, n_views: int, light_per_view: bool = True):
+    dirs = np.zeros((n_views, 3), dtype=np.float32)
+    lights = np.zeros((n_views, 3), dtype=np.float32)
+    _check(_lib.adr_job_views(seed, step, n_views, 1 if light_per_view else 0, _ptr(dirs), _ptr(lights)))
+    return dirs, lights
+
+
+def _tex_arg(tex):
+    if tex is None:
+        return None, 0, TEX_F32
+    if tex.fmt == "rgba8":
+        a = np.ascontiguousarray(tex.data, dtype=np.uint8)
+        return a, a.shape[0], TEX_RGBA8
+    a = np.ascontiguousarray(tex.data, dtype=np.float32)
+    return a, a.shape[0], TEX_F32
+
+
+def job_submit(ctx: Context, w, n_steps: int, seed: int, lr_decay_k: float = 0.0002,
+               light_per_view: bool = True) -> int:
+    """Queue a whole optimisation of workload ``w`` (host arrays are copied)."""
+    keep = []
+    def arr(x, dt):
+        a = np.ascontiguousarray(x, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+    ref, lat = w.ref, w.latent
+    rkd, rkd_s, rkd_f = _tex_arg(ref.kd)
+    lkd, lkd_s, lkd_f = _tex_arg(lat.kd)
+    rn, rn_s, _ = _tex_arg(ref.normal)
+    ln, ln_s, _ = _tex_arg(lat.normal)
+    ro, ro_s, _ = _tex_arg(ref.orm)
+    lo, lo_s, _ = _tex_arg(lat.orm)
+    keep += [x for x in (rkd, lkd, rn, ln, ro, lo) if x is not None]
+    mask = sum(1 << k for k, n in enumerate(("pos", "kd", "normal", "orm")) if n in w.optimize)
+    d = JobDesc_()
+    d.ref_pos, d.ref_tri = arr(ref.mesh.pos, np.float32), arr(ref.mesh.tri, np.int32)
+    d.ref_uv, d.ref_uv_tri = arr(ref.mesh.uv, np.float32), arr(ref.mesh.uv_tri, np.int32)
+    d.ref_n_pos, d.ref_n_tri, d.ref_n_uv = ref.mesh.pos.shape[0], ref.mesh.tri.shape[0], ref.mesh.uv.shape[0]
+    d.model = SHADE_GGX if ref.model == "ggx" else SHADE_BLINN_PHONG
+    d.ref_kd, d.ref_kd_size, d.ref_kd_format = _ptr(rkd), rkd_s, rkd_f
+    d.ref_normal, d.ref_normal_size = _ptr(rn), rn_s
+    d.ref_orm, d.ref_orm_size = (_ptr(ro), ro_s) if ro is not None else (None, 0)
+    d.lat_pos, d.lat_tri = arr(lat.mesh.pos, np.float32), arr(lat.mesh.tri, np.int32)
+    d.lat_uv, d.lat_uv_tri = arr(lat.mesh.uv, np.float32), arr(lat.mesh.uv_tri, np.int32)
+    d.lat_n_pos, d.lat_n_tri, d.lat_n_uv = lat.mesh.pos.shape[0], lat.mesh.tri.shape[0], lat.mesh.uv.shape[0]
+    d.lat_kd, d.lat_kd_size, d.lat_kd_format = _ptr(lkd), lkd_s, lkd_f
+    d.lat_normal, d.lat_normal_size = _ptr(ln), ln_s
+    d.lat_orm, d.lat_orm_size = (_ptr(lo), lo_s) if lo is not None else (None, 0)
+    d.opt_mask = mask
+    d.seed = seed
+    d.n_views, d.width, d.height = w.dirs.shape[0], w.width, w.height
+    d.light_per_view = 1 if light_per_view else 0
+    d.dist, d.fov_deg = w.dist, w.fov_deg
+    d.n_steps, d.loss_kind = n_steps, LOSS[w.loss]
+    d.lr0, d.lr_decay_k = w.lr, lr_decay_k
+    jid = C.c_uint64(0)
+    _check(_lib.adr_job_submit(ctx.h, C.byref(d), C.byref(jid)))
+    return int(jid.value)
+
+
+def job_poll(ctx: Context, job_id: int, w=None):
+    """(status dict, result dict or None).  With ``w`` (the submitted
+    workload, for the result shapes) a finished job's latent model is
+    returned and the job is released."""
+    st = JobStatus_()
+    res = None
+    out = None
+    if w is not None:
+        lat = w.latent
+        res = {"pos": np.zeros_like(lat.mesh.pos, dtype=np.float32),
+               "kd": np.zeros_like(lat.kd.data),
+               "normal": np.zeros_like(lat.normal.data, dtype=np.float32),
+               "orm": np.zeros_like(lat.orm.data, dtype=np.float32) if lat.orm is not None else None}
+        out = JobResult_(_ptr(res["pos"]), _ptr(res["kd"]), _ptr(res["normal"]), _ptr(res["orm"]))
+    code = _lib.adr_job_poll(ctx.h, job_id, C.byref(st), C.byref(out) if out is not None else None)
+    if code < 0 and code not in (E_NONFINITE, E_HIP):
+        _check(code)
+    status = {"code": code, "state": st.state, "step": st.step, "loss": st.last_loss,
+              "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "device_bytes": st.device_bytes}
+    if code < 0:   # the job failed and has been released
+        status["state"] = JOB_FAILED
+        status["error"] = _lib.adr_last_error().decode()
+    return status, (res if (code == OK and st.state == JOB_DONE and w is not None) else None)

@@ -129,8 +129,52 @@ __device__ __forceinline__ float srgb(float x) {
 __device__ __forceinline__ float srgb_d(float x) {
   return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * powf(x, 1.0f / 2.4f - 1.0f);
 }
-__device__ __forceinline__ float tmap(float x) { return srgb(log1pf(x)); }
-__device__ __forceinline__ float tmap_d(float x) { return srgb_d(log1pf(x)) / (1.0f + x); }
+// T(x) = sign(x) Gamma(log(1 + |x|)): the paper's tone map for x >= 0,
+// extended as an odd function to the negative radiance that freely optimised
+// texels can produce.
+__device__ __forceinline__ float tmap(float x) { return copysignf(srgb(log1pf(fabsf(x))), x); }
+__device__ __forceinline__ float tmap_d(float x) {
+  float a = fabsf(x);
+  return srgb_d(log1pf(a)) / (1.0f + a);
+}
+
+// Weight pixel (i, j) receives from the pair with its neighbour, and the
+// neighbour's index; 0 if the pair does not blend into this pixel.
+__device__ __forceinline__ float received(const AAArgs& a, int b, int i, int j, uint64_t k, int ni, int nj,
+                                          uint64_t kn) {
+  Pair pr;
+  if (!eval_pair(a, b, i, j, k, ni, nj, kn, pr)) return 0.f;
+  float s = pr.x.s;
+  if (pr.self_is_P) return s < 0.5f ? 0.5f - s : 0.f;
+  return s > 0.5f ? s - 0.5f : 0.f;
+}
+
+// Received antialiasing of pixel (i, j): total weight W and
+// acc = sum_k w_k (c_k - c); the output is c + acc / max(1, W), a convex
+// blend even where several edges of sub-pixel triangles cross.
+struct Recv {
+  float W;
+  f3 acc;
+};
+__device__ __forceinline__ Recv recv_stats(const AAArgs& a, int b, int i, int j) {
+  const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+  int64_t base = (int64_t)b * a.v.H * a.v.W;
+  int64_t o = base + (int64_t)j * a.v.W + i;
+  uint64_t k = a.vis[o];
+  f3 c = ldc(a.color, o);
+  Recv r{0.f, mk(0.f, 0.f, 0.f)};
+  for (int q = 0; q < 4; ++q) {
+    int ni = i + di[q], nj = j + dj[q];
+    if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
+    int64_t on = base + (int64_t)nj * a.v.W + ni;
+    float w = received(a, b, i, j, k, ni, nj, a.vis[on]);
+    if (w > 0.f) {
+      r.W += w;
+      r.acc += w * (ldc(a.color, on) - c);
+    }
+  }
+  return r;
+}
 
 __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __restrict__ ref,
                                                      int loss_kind, float* __restrict__ image,
@@ -146,21 +190,8 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
     f3 c = ldc(a.color, o);
     f3 out = c;
     if (!a.no_aa) {
-      uint64_t k = a.vis[o];
-      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-      for (int q = 0; q < 4; ++q) {
-        int ni = p.i + di[q], nj = p.j + dj[q];
-        if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
-        int64_t on = base + (int64_t)nj * a.v.W + ni;
-        Pair pr;
-        if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[on], pr)) continue;
-        float s = pr.x.s;
-        if (pr.self_is_P) {
-          if (s < 0.5f) out += (0.5f - s) * (ldc(a.color, on) - c);
-        } else {
-          if (s > 0.5f) out += (s - 0.5f) * (ldc(a.color, on) - c);
-        }
-      }
+      Recv r = recv_stats(a, p.b, p.i, p.j);
+      if (r.W > 0.f) out += (1.0f / fmaxf(r.W, 1.0f)) * r.acc;
     }
     if (image) st3(image, o, out);
     if (ref) {
@@ -207,7 +238,11 @@ __global__ void k_loss_reduce(const float* __restrict__ partial, int n, float in
   if (threadIdx.x == 0) loss[0] = (float)(red[0] * (double)inv_n);
 }
 
-// Adjoint: each pixel gathers dL/dc of its own colour from its four pairs;
+// Adjoint.  With out(r) = c(r) + acc(r) / M(r), M = max(1, W):
+//   d out(r) / d c(r) = 1 - W(r)/M(r),  d out(r) / d c(k) = w_k / M(r),
+//   d out(r) / d w_k = (c(k) - c(r)) / M(r) - [W > 1] acc(r) / W(r)^2.
+// Each pixel gathers dL/dc of its own colour (as receiver and as source of
+// its four pairs; a receiver's W and acc are recomputed from its own pairs);
 // the gradient of a pair's crossing parameter s w.r.t. the clip coordinates
 // of its edge is scattered once, by the left (or lower) pixel of the pair.
 __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
@@ -224,6 +259,9 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   if (!a.no_aa) {
     uint64_t k = a.vis[o];
     f3 c = ldc(a.color, o);
+    Recv rs = recv_stats(a, p.b, p.i, p.j);
+    float Ms = fmaxf(rs.W, 1.0f);
+    gc = (1.0f - rs.W / Ms) * gself;
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
     for (int q = 0; q < 4; ++q) {
       int ni = p.i + di[q], nj = p.j + dj[q];
@@ -232,21 +270,22 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       Pair pr;
       if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[on], pr)) continue;
       float s = pr.x.s;
+      if (s == 0.5f) continue;
+      // the receiver is Q for s > 1/2 (w = s - 1/2) and P for s < 1/2 (w = 1/2 - s)
+      bool recv_Q = s > 0.5f;
+      bool self_recv = recv_Q ? !pr.self_is_P : pr.self_is_P;
+      float w = recv_Q ? s - 0.5f : 0.5f - s;
       f3 cn = ldc(a.color, on);
       f3 gn = scale * ldc(dimage, on);
-      float g_s = 0.f;
-      // out(Q) += (s - 1/2)(c(P) - c(Q)) for s > 1/2; out(P) += (1/2 - s)(c(Q) - c(P)) for s < 1/2
-      f3 cP = pr.self_is_P ? c : cn, cQ = pr.self_is_P ? cn : c;
-      f3 gP = pr.self_is_P ? gself : gn, gQ = pr.self_is_P ? gn : gself;
-      if (s > 0.5f) {
-        float w = s - 0.5f;
-        gc += (pr.self_is_P ? w : -w) * gQ;
-        g_s = dot(gQ, cP - cQ);
-      } else if (s < 0.5f) {
-        float w = 0.5f - s;
-        gc += (pr.self_is_P ? -w : w) * gP;
-        g_s = -dot(gP, cQ - cP);
-      }
+      Recv rr = self_recv ? rs : recv_stats(a, p.b, ni, nj);
+      float Mr = fmaxf(rr.W, 1.0f);
+      f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
+      f3 c_r = self_recv ? c : cn, c_src = self_recv ? cn : c;
+      if (!self_recv) gc += (w / Mr) * gn;      // this pixel is the source
+      f3 dw = (1.0f / Mr) * (c_src - c_r);
+      if (rr.W > 1.0f) dw -= (1.0f / (rr.W * rr.W)) * rr.acc;
+      float g_w = dot(g_r, dw);
+      float g_s = recv_Q ? g_w : -g_w;
       bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
       if (!owner || pr.x.clamped || g_s == 0.f) continue;
       // s = eP / (eP - eQ)

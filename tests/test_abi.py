@@ -61,3 +61,23 @@ def test_invalid_arguments_are_rejected():
     assert e.value.code == adr.E_INVALID
     with pytest.raises(adr.AdrError):
         adr.views_build(np.ones((1, 3)), -1.0, 45.0, 64, 64)
+
+
+def test_splitmix64_reference_values():
+    # the first outputs of SplitMix64 seeded with 0, as published with the
+    # generator (Vigna's splitmix64.c test vector)
+    from oracle import sampling as Sm
+    outs = [Sm.splitmix64_output((0 + (i + 1) * Sm.GAMMA) & Sm.M64) for i in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+@pytest.mark.parametrize("per_view", [True, False])
+def test_job_views_match_oracle_sampler(per_view):
+    from oracle import sampling as Sm
+    from paper_2104_03989_amd import adr
+    for seed, step, B in ((0, 0, 3), (12345, 7, 8), (2**63 + 5, 1999, 4)):
+        d, l = adr.job_views(seed, step, B, per_view)
+        d2, l2 = Sm.step_views(seed, step, B, per_view)
+        assert np.abs(d - np.array(d2)).max() < 1e-6
+        assert np.abs(l - np.array(l2)).max() < 1e-6
+        assert np.abs(np.linalg.norm(d, axis=1) - 1).max() < 1e-6

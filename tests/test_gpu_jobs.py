@@ -1,0 +1,138 @@
+"""The job server behind adr_job_submit / adr_job_poll: a job's result is the
+same alone and mixed with other jobs, one job step matches the oracle,
+admission rejects jobs over budget, and a non-finite job fails cleanly."""
+import sys
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import loop as OL
+from oracle import render as R
+from oracle import sampling as Sm
+from paper_2104_03989_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _small(seed_shift=0, res=48, views=2):
+    w = synth.scaled(synth.workload_plain_step(map_size=32, ref_nu=12, lat_nu=4), views=views, res=res)
+    if seed_shift:
+        w.latent.mesh.pos = (w.latent.mesh.pos * (1.0 + 0.01 * seed_shift)).astype(np.float32)
+    return w
+
+
+def _wait(ctx, ids_w, timeout=120.0):
+    from paper_2104_03989_amd import adr
+    results, status = {}, {}
+    t0 = time.time()
+    pending = dict(ids_w)
+    while pending:
+        assert time.time() - t0 < timeout, "jobs did not finish"
+        for jid, w in list(pending.items()):
+            st, res = adr.job_poll(ctx, jid, w)
+            if st["code"] == adr.OK and st["state"] == adr.JOB_DONE:
+                results[jid], status[jid] = res, st
+                del pending[jid]
+            elif st["code"] < 0:
+                status[jid] = st
+                del pending[jid]
+        time.sleep(0.01)
+    return results, status
+
+
+def test_job_alone_equals_mixed():
+    from paper_2104_03989_amd import adr
+    _say("job alone vs mixed")
+    ctx = adr.Context(0)
+    w = _small()
+    a = adr.job_submit(ctx, w, n_steps=6, seed=11)
+    res, st = _wait(ctx, {a: w})
+    alone = res[a]
+    assert st[a]["step"] == 6 and st[a]["p50_ms"] > 0 and st[a]["p99_ms"] >= st[a]["p50_ms"]
+    others = {adr.job_submit(ctx, _small(k, res=64, views=3), n_steps=5 + k, seed=100 + k): _small(k, 64, 3)
+              for k in range(1, 4)}
+    b = adr.job_submit(ctx, w, n_steps=6, seed=11)
+    res2, st2 = _wait(ctx, {b: w, **others})
+    mixed = res2[b]
+    for k in ("pos", "normal"):
+        assert np.abs(alone[k] - mixed[k]).max() < 5e-6, k
+    assert not np.array_equal(alone["pos"], w.latent.mesh.pos)
+    assert all(s["code"] == adr.OK for s in st2.values())
+    ctx.close()
+
+
+def test_job_first_step_matches_oracle():
+    from paper_2104_03989_amd import adr
+    _say("job step vs oracle")
+    ctx = adr.Context(0)
+    w = _small(res=40)
+    seed = 77
+    jid = adr.job_submit(ctx, w, n_steps=1, seed=seed)
+    res, st = _wait(ctx, {jid: w})
+    got = res[jid]
+    # the oracle draws the same cameras and lights from its own sampler
+    dirs, lights = Sm.step_views(seed, 0, w.dirs.shape[0], True)
+    w.dirs = np.array(dirs, dtype=np.float32).astype(np.float64)
+    w.light_dir = np.array(lights, dtype=np.float32).astype(np.float64)
+    mvp32, eye = OL.cameras(w)
+    ref = OL.reference_image(w, mvp32, eye)
+    params = OL.latent_params(w)
+    loss, grads, _ = OL.loss_and_grads(w, ref, mvp32, eye, params)
+    assert abs(st[jid]["loss"] - float(loss)) <= 1e-5 * float(loss)
+    new, _ = OL.adam_update(params, grads, {}, 1, w.lr)
+    for k, name in (("pos", "pos"), ("normal", "normal")):
+        d = np.abs(got[k].reshape(-1) - new[name].reshape(-1))
+        assert np.median(d) < 1e-3 * w.lr, k
+        assert (d < 0.05 * w.lr).mean() > 0.995, k
+    ctx.close()
+
+
+def test_job_over_budget_is_rejected():
+    from paper_2104_03989_amd import adr
+    _say("job over budget")
+    ctx = adr.Context(0, hbm_budget=64 << 10)
+    with pytest.raises(adr.AdrError) as e:
+        adr.job_submit(ctx, _small(), n_steps=3, seed=1)
+    assert e.value.code == adr.E_OVER_BUDGET
+    ctx.close()
+
+
+def test_invalid_job_is_rejected():
+    from paper_2104_03989_amd import adr
+    ctx = adr.Context(0)
+    with pytest.raises(adr.AdrError) as e:
+        adr.job_submit(ctx, _small(), n_steps=0, seed=1)
+    assert e.value.code == adr.E_INVALID
+    with pytest.raises(adr.AdrError) as e:
+        adr.job_poll(ctx, 12345)
+    assert e.value.code == adr.E_NOTFOUND
+    ctx.close()
+
+
+def test_nonfinite_job_fails_and_others_finish():
+    from paper_2104_03989_amd import adr
+    _say("job non-finite")
+    ctx = adr.Context(0)
+    bad = _small()
+    # the first Adam step (infinite learning rate) makes the base colour
+    # non-finite, so the second step's loss is NaN (non-finite positions would
+    # only drop triangles, and a NaN normal shades black through max(0, n.l))
+    bad.lr = float("inf")
+    kd = bad.latent.kd.data[..., :3].astype(np.float32) / 255.0
+    bad.latent = synth.Scene(bad.latent.mesh, bad.latent.model, synth.Texture(kd, "f32"),
+                             bad.latent.normal, bad.latent.orm)
+    bad.optimize = ("kd",)
+    good = _small(2)
+    jb = adr.job_submit(ctx, bad, n_steps=4, seed=3)
+    jg = adr.job_submit(ctx, good, n_steps=4, seed=4)
+    res, st = _wait(ctx, {jb: bad, jg: good})
+    assert st[jb]["code"] == adr.E_NONFINITE
+    assert st[jg]["code"] == adr.OK and jg in res
+    ctx.close()

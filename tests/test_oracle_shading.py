@@ -289,3 +289,33 @@ def test_identical_latent_and_reference_give_zero_loss_and_gradient():
     assert float(loss) == 0.0
     for g in grads.values():
         assert float(g.abs().max()) == 0.0
+
+
+def test_tonemap_odd_extension_to_negative_radiance():
+    x = torch.linspace(0, 20, 401, dtype=R.F64)
+    assert torch.equal(R.tonemap(-x), -R.tonemap(x))
+    # smooth through zero: slope 12.92 on both sides
+    h = torch.tensor([1e-9, -1e-9], dtype=R.F64)
+    assert torch.allclose(R.tonemap(h) / h, torch.full_like(h, 12.92), rtol=1e-6)
+
+
+def test_aa_of_subpixel_triangle_stays_convex():
+    # a triangle much smaller than a pixel that still covers one pixel centre:
+    # edges cross all four segments next to that pixel, whose received
+    # weights then sum past 1 and are normalised; every output stays in the
+    # range of the colours and the tiny triangle's pixel tends to background
+    W = H = 9
+    cx, cy = 2 * (4 + 0.5) / W - 1, 2 * (4 + 0.5) / H - 1
+    e = 0.25 * 2 / W
+    pos = np.array([(cx - e, cy - e, 0.5), (cx + e, cy - e, 0.5), (cx, cy + e, 0.5)], dtype=np.float32)
+    tri = np.array([(0, 1, 2)], dtype=np.int32)
+    sv = R.snap(pos, np.eye(4, dtype=np.float32), W, H)
+    keys, cov, orient = R.raster(tri, sv, W, H)
+    assert cov.sum() == 1
+    color = torch.as_tensor((R.key_tri(keys).reshape(-1) > 0).astype(np.float64))[:, None].repeat(1, 3)
+    clip = torch.as_tensor(np.concatenate([pos, np.ones((3, 1))], 1), dtype=R.F64)
+    pairs = R.aa_pairs(keys, tri, sv, orient, R.adjacency(tri))
+    assert pairs[0].size >= 3
+    out = R.antialias(color, clip, pairs, W, H)[:, 0].numpy()
+    assert out.min() >= 0.0 and out.max() <= 1.0
+    assert out[4 * W + 4] < 0.5
