@@ -7,10 +7,13 @@ parameters (vertex positions and level-0 texels) and apply Adam (Sec. 5.3).
 """
 from __future__ import annotations
 
+import types
+
 import numpy as np
 import torch
 
 from . import render as R
+from . import tess as T
 
 
 def cameras(w):
@@ -23,7 +26,7 @@ def _levels(tex, param=None):
     return R.texture_levels(tex.data, tex.fmt, param)
 
 
-def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True):
+def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True, frozen=None):
     params = params or {}
     if pos is None:
         pos = torch.as_tensor(scene.mesh.pos, dtype=R.F64)
@@ -32,7 +35,41 @@ def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True):
     orm = _levels(scene.orm, params.get("orm")) if scene.orm is not None else None
     return R.render(scene.mesh, scene.model, kd, nm, orm, pos, mvp32,
                     np.asarray(eye, dtype=np.float64), np.asarray(w.light_dir, dtype=np.float64),
-                    np.asarray(w.light_rgb, dtype=np.float64), w.width, w.height, aa=aa)
+                    np.asarray(w.light_rgb, dtype=np.float64), w.width, w.height, aa=aa, frozen=frozen)
+
+
+def tess_table(w):
+    """The oracle's own tessellation of the latent base mesh (Sec. 5.1)."""
+    m = w.latent.mesh
+    key = (id(m), w.tess_levels)
+    if getattr(w, "_oracle_tess", (None,))[0] != key:
+        w._oracle_tess = (key, T.build(m.tri, m.uv_tri, m.uv, m.pos.shape[0], w.tess_levels))
+    return w._oracle_tess[1]
+
+
+def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True):
+    """Latent render; with tessellation the base positions and the
+    displacement map are mapped to displaced positions first (Eq. 3).
+    The renderer's vertex format is float32: the displaced positions are
+    rounded to it (``round32``), and the adjoint passes through the
+    rounding unchanged."""
+    params = params or {}
+    if not w.tess_levels:
+        return render_scene(w.latent, mvp32, eye, w, pos=params.get("pos"), params=params, aa=aa,
+                            frozen=frozen)
+    table = tess_table(w)
+    base = w.latent.mesh
+    pos0 = params.get("pos", torch.as_tensor(base.pos, dtype=R.F64))
+    disp = params.get("disp", torch.as_tensor(w.disp.data, dtype=R.F64))
+    vd = T.displaced_positions(pos0, base, table, disp)
+    if round32:
+        vd = vd + (vd.detach().to(torch.float32).to(R.F64) - vd.detach())
+    mesh = types.SimpleNamespace(pos=None, tri=table["tri"], uv=table["uv"], uv_tri=table["uv_tri"])
+    scene = types.SimpleNamespace(mesh=mesh, model=w.latent.model, kd=w.latent.kd,
+                                  normal=w.latent.normal, orm=w.latent.orm)
+    out = render_scene(scene, mvp32, eye, w, pos=vd, params=params, aa=aa, frozen=frozen)
+    out["pos"] = vd
+    return out
 
 
 def reference_image(w, mvp32=None, eye=None):
@@ -49,6 +86,8 @@ def latent_params(w):
     for name in w.optimize:
         if name == "pos":
             out["pos"] = torch.tensor(s.mesh.pos, dtype=R.F64, requires_grad=True)
+        elif name == "disp":
+            out["disp"] = torch.tensor(w.disp.data, dtype=R.F64, requires_grad=True)
         else:
             tex = getattr(s, name)
             assert tex.fmt == "f32", "only float32 maps are optimised"
@@ -61,7 +100,7 @@ def loss_and_grads(w, ref_img, mvp32=None, eye=None, params=None, aa=True):
     if mvp32 is None:
         mvp32, eye = cameras(w)
     params = params if params is not None else latent_params(w)
-    out = render_scene(w.latent, mvp32, eye, w, pos=params.get("pos"), params=params, aa=aa)
+    out = render_latent(w, mvp32, eye, params, aa=aa)
     loss = R.image_loss(out["image"], ref_img, w.loss)
     leaves = [params[k] for k in params]
     gl = torch.autograd.grad(loss, leaves, allow_unused=True)

@@ -494,11 +494,14 @@ def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = 
 def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tensor,
            mvp32: np.ndarray, eye: np.ndarray, light_dir: np.ndarray, light_rgb: np.ndarray,
            W: int, H: int, adj: np.ndarray | None = None, aa: bool = True,
-           keep_gbuf: bool = False):
+           keep_gbuf: bool = False, frozen: dict | None = None):
     """Render B views.  ``pos`` is float64 [V,3] (may require grad); the
     visibility uses its float32 rounding (R1).  Returns a dict with
     image [B,H*W,3] (antialiased), color [B,H*W,3], keys [B,H,W] uint64,
-    coverage [B,H,W] and per-view AA pair lists."""
+    coverage [B,H,W] and per-view AA pair lists.  ``frozen``: the output of
+    an earlier call whose visibility and antialiasing pairs are reused (the
+    loss is then a smooth function of the positions, for finite
+    differences)."""
     tri_np = np.asarray(mesh.tri, dtype=np.int64)
     tri = torch.from_numpy(tri_np)
     uv = _t(mesh.uv)
@@ -514,7 +517,10 @@ def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tenso
         M = _t(mvp32[b].astype(np.float64))
         clip = torch.cat([pos, torch.ones(pos.shape[0], 1, dtype=F64)], dim=1) @ M.T
         sv = snap(pos32, mvp32[b], W, H)
-        keys, cov, orient = raster(tri_np, sv, W, H)
+        if frozen is None:
+            keys, cov, orient = raster(tri_np, sv, W, H)
+        else:
+            keys, cov = frozen["keys"][b], frozen["coverage"][b]
         ids = key_tri(keys).reshape(-1)
         pix = np.nonzero(ids)[0]
         color = torch.zeros(H * W, 3, dtype=F64)
@@ -565,7 +571,7 @@ def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tenso
                 gbufs.append(dict(pix=pix, lam=lam.detach(), x=x.detach(), N=N.detach(),
                                   uv=uvp.detach(), duv_dx=duv_dx.detach(), duv_dy=duv_dy.detach(),
                                   n=n.detach(), kd=kd.detach()))
-        pairs = aa_pairs(keys, tri_np, sv, orient, adj)
+        pairs = aa_pairs(keys, tri_np, sv, orient, adj) if frozen is None else frozen["pairs"][b]
         img = antialias(color, clip, pairs, W, H) if aa else color
         images.append(img)
         colors.append(color)

@@ -309,7 +309,9 @@ class Workload:
     fov_deg: float
     loss: str               # "l1", "l1_tonemap", "l2", "l2_tonemap"
     lr: float
-    optimize: tuple         # names among "pos", "kd", "normal", "orm"
+    optimize: tuple         # names among "pos", "kd", "normal", "orm", "disp"
+    disp: Texture | None = None   # [S,S,1] f32 displacement map of a tessellated latent
+    tess_levels: int = 0          # midpoint subdivisions of the latent (base) mesh
 
 
 def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> Mesh:
@@ -363,6 +365,25 @@ def workload_paper_loop(views: int = 8, res: int = 512, map_size: int = 2048,
     light = random_unit(views, seed_for(c, 7))
     return Workload("paper_loop", ref, lat, dirs, light, np.ones((views, 3)), res, res,
                     3.0, 45.0, "l1_tonemap", 2e-3, ("pos", "kd", "normal"))
+
+
+def workload_displacement(views: int = 8, res: int = 512, map_size: int = 1024,
+                          ref_nu: int = 136, base_nu: int = 7, levels: int = 3) -> Workload:
+    """Differentiation-heavy loop: a 980-tri base mesh resampled on an fbm
+    sphere, tessellated three times (62,720 tris) and displaced along its
+    interpolated normals by a 1024^2 FP32 map (initialised to 0), with a
+    1024^2 FP32 normal map; the reference is a 369,920-tri fbm sphere; 8 views
+    at 512^2 with a light per view, Lambert + Blinn-Phong, L1 loss."""
+    c = 3
+    rad = lambda d: fbm_radius(d, seed_for(c, 1))
+    kd = _f32(np.full((1, 1, 3), 0.7))
+    ref = Scene(sphere_mesh(ref_nu, rad), "blinn_phong", kd, _f32(flat_normal_map(1)), None)
+    lat = Scene(sphere_mesh(base_nu, rad), "blinn_phong", kd, _f32(flat_normal_map(map_size)), None)
+    disp = _f32(np.zeros((map_size, map_size, 1)))
+    dirs = random_unit(views, seed_for(c, 2))
+    light = random_unit(views, seed_for(c, 3))
+    return Workload("displacement", ref, lat, dirs, light, np.ones((views, 3)), res, res,
+                    3.0, 45.0, "l1", 1e-3, ("pos", "disp", "normal"), disp, levels)
 
 
 def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:

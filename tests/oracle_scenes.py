@@ -56,3 +56,27 @@ def tiny_sphere_workload(model="blinn_phong", nu=2, res=24, views=1, tex=8, loss
     light = light + 1.5 * dirs
     opt = ("pos", "kd", "normal", "orm") if model == "ggx" else ("pos", "kd", "normal")
     return workload(ref, lat, dirs, light, res, res, loss=loss, optimize=opt)
+
+
+def tess_crop_workload(res=32, views=2, disp_size=16, seed=0, levels=3):
+    """The 64-triangle crop of the displacement loop: one base triangle
+    (tessellated `levels` times) displaced by a random map, against a tilted
+    textured reference triangle."""
+    g = np.random.default_rng(seed)
+    pos = np.array([[-0.9, -0.8, 0.0], [1.0, -0.6, 0.1], [-0.3, 0.9, -0.05]], np.float32)
+    tri = np.array([[0, 1, 2]], np.int32)
+    uv = np.array([[0.1, 0.1], [0.9, 0.2], [0.3, 0.85]], np.float32)
+    base = synth.Mesh(pos, tri, uv, tri.copy())
+    ref_pos = pos * np.float32(0.95) + np.array([0.03, -0.02, 0.1], np.float32)
+    ref_mesh = synth.Mesh(ref_pos.astype(np.float32), tri, uv, tri.copy())
+    kd_ref = synth.Texture(g.uniform(0.2, 0.9, size=(8, 8, 3)).astype(np.float32), "f32")
+    ref = synth.Scene(ref_mesh, "blinn_phong", kd_ref, flat_normals(), None)
+    nm = synth.Texture(synth.detail_normal_map(disp_size, 900 + seed, 0.1).astype(np.float32), "f32")
+    lat = synth.Scene(base, "blinn_phong", const_tex((0.6, 0.5, 0.4)), nm, None)
+    disp = synth.Texture(g.normal(0.0, 0.04, size=(disp_size, disp_size, 1)).astype(np.float32), "f32")
+    dirs = np.array([[0.1, 0.15, 1.0], [-0.25, 0.1, 1.0], [0.2, -0.3, 1.0]])[:views]
+    light = np.array([[0.3, 0.4, 1.0]])
+    w = workload(ref, lat, dirs, light, res, res, loss="l1", optimize=("pos", "disp", "normal"))
+    w.disp = disp
+    w.tess_levels = levels
+    return w
