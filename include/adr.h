@@ -190,6 +190,49 @@ adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params
  * rounds (a+b+c+d+2)/4).  Device work on `stream`. */
 adr_status adr_mip_build(adr_ctx* ctx, const adr_texture* tex, adr_stream stream);
 
+/* ------------------------------------------------ tessellation + displacement */
+
+/* Displacement mapping on a tessellated base mesh (Sec. 5.1 Eq. 3): each
+ * tessellated vertex v is p = sum_c w_c P[vidx_c] displaced along
+ * n = normalize(sum_c w_c N[vidx_c]) by a bilinear level-0 lookup of the
+ * scalar displacement map at duv (N = smooth vertex normals of the base
+ * mesh, recomputed from its positions).  The table comes from
+ * adr_tess_build (edge-midpoint subdivision applied `levels` times; the
+ * canonical numbering is documented in the implementation). */
+typedef struct adr_tess {
+  const int32_t* vidx;           /* device [n_vert,3] base vertices */
+  const float* w;                /* device [n_vert,3] weights (dyadic, sum 1) */
+  const float* duv;              /* device [n_vert,2] displacement-map coordinates */
+  int32_t n_vert;
+} adr_tess;
+
+/* Host: sizes of the tessellated mesh (vertices, triangles = n_tri 4^levels,
+ * UVs = n_tri (2^levels+1)(2^levels+2)/2).  levels 0..6. */
+adr_status adr_tess_counts(const int32_t* tri, int32_t n_tri, int32_t n_pos, int32_t levels,
+                           int64_t* n_vert, int64_t* n_tri_out, int64_t* n_uv_out);
+/* Host: the table (vidx, w, duv) and the tessellated topology (tess_tri into
+ * the tessellated vertices, tess_uv / tess_uv_tri), all host arrays sized by
+ * adr_tess_counts.  Inputs: tri [n_tri,3] into n_pos positions, uv_tri
+ * [n_tri,3] into uv [n_uv,2].  UVs of lattice points are the float32
+ * rounding of their float64 barycentric combination.  ADR_E_INVALID for
+ * out-of-range indices, levels outside 0..6 or outputs beyond int32 range;
+ * nothing is written then. */
+adr_status adr_tess_build(const int32_t* tri, const int32_t* uv_tri, const float* uv, int32_t n_tri,
+                          int32_t n_pos, int32_t n_uv, int32_t levels, int32_t* vidx, float* w,
+                          float* duv, int32_t* tess_tri, float* tess_uv, int32_t* tess_uv_tri);
+/* Tessellated, displaced positions pos_out [n_vert,3] (device) from the base
+ * mesh (pos, tri, uv, uv_tri used) and the F32 1-channel displacement map.
+ * Computed in float64 and rounded once to float32.  Device work on `stream`;
+ * scratch (base vertex frame) lives in the context. */
+adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
+                        const adr_texture* disp, float* pos_out, adr_stream stream);
+/* Adjoint: accumulates dL/d base positions (g_base_pos [n_pos,3], through the
+ * base vertex normals too) and dL/d displacement texels (g_disp, level-0
+ * layout, nullable) from dL/d pos_out (g_pos_out [n_vert,3]). */
+adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
+                        const adr_texture* disp, const float* g_pos_out, float* g_base_pos,
+                        float* g_disp, adr_stream stream);
+
 /* Stage timing.  When enabled, every render/adam call brackets each of its
  * kernel stages with HIP events on the call's stream; adr_ctx_profile_read
  * waits for them, returns per stage the summed milliseconds and the number

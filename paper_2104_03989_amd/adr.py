@@ -32,7 +32,8 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
-           "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views")
+           "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
+           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd")
 N_STAGES = 11
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build")
@@ -79,6 +80,10 @@ class Param_(C.Structure):
     _fields_ = [("param", P), ("grad", P), ("m", P), ("v", P), ("n", C.c_int64)]
 
 
+class Tess_(C.Structure):
+    _fields_ = [("vidx", P), ("w", P), ("duv", P), ("n_vert", I32)]
+
+
 class JobDesc_(C.Structure):
     _fields_ = [("ref_pos", P), ("ref_tri", P), ("ref_uv", P), ("ref_uv_tri", P),
                 ("ref_n_pos", I32), ("ref_n_tri", I32), ("ref_n_uv", I32), ("model", I32),
@@ -123,6 +128,10 @@ _lib.adr_job_submit.argtypes = [P, C.POINTER(JobDesc_), C.POINTER(C.c_uint64)]
 _lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(JobResult_)]
 _lib.adr_ctx_profile.argtypes = [P, I32]
 _lib.adr_ctx_profile_read.argtypes = [P, P, P]
+_lib.adr_tess_counts.argtypes = [P, I32, I32, I32, P, P, P]
+_lib.adr_tess_build.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P, P, P, P]
+_lib.adr_tess_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P]
+_lib.adr_tess_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P, P, P]
 for _n in EXPORTS[1:]:
     getattr(_lib, _n).restype = I32
 
@@ -449,3 +458,64 @@ def job_poll(ctx: Context, job_id: int, w=None):
         status["state"] = JOB_FAILED
         status["error"] = _lib.adr_last_error().decode()
     return status, (res if (code == OK and st.state == JOB_DONE and w is not None) else None)
+
+
+# ---------------------------------------------------------------- displacement mapping
+
+def tess_build(tri: np.ndarray, uv_tri: np.ndarray, uv: np.ndarray, n_pos: int, levels: int) -> dict:
+    """Host tables of the fixed edge-midpoint tessellation (Sec. 5.1)."""
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    uv_tri = np.ascontiguousarray(uv_tri, dtype=np.int32)
+    uv = np.ascontiguousarray(uv, dtype=np.float32)
+    nv, nt, nu = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(_lib.adr_tess_counts(_ptr(tri), tri.shape[0], n_pos, levels, C.byref(nv), C.byref(nt),
+                                C.byref(nu)))
+    out = dict(vidx=np.zeros((nv.value, 3), np.int32), w=np.zeros((nv.value, 3), np.float32),
+               duv=np.zeros((nv.value, 2), np.float32), tri=np.zeros((nt.value, 3), np.int32),
+               uv=np.zeros((nu.value, 2), np.float32), uv_tri=np.zeros((nt.value, 3), np.int32))
+    _check(_lib.adr_tess_build(_ptr(tri), _ptr(uv_tri), _ptr(uv), tri.shape[0], n_pos, uv.shape[0], levels,
+                               _ptr(out["vidx"]), _ptr(out["w"]), _ptr(out["duv"]), _ptr(out["tri"]),
+                               _ptr(out["uv"]), _ptr(out["uv_tri"])))
+    return out
+
+
+class DeviceTess:
+    """A base mesh, its tessellation tables and the tessellated mesh (whose
+    positions ``tess_fwd`` rewrites)."""
+
+    def __init__(self, base, levels: int, device="cuda"):
+        self.base = DeviceMesh(base, device)
+        t = tess_build(base.tri, base.uv_tri, base.uv, base.pos.shape[0], levels)
+        self.levels = levels
+        f = lambda a: torch.from_numpy(a).to(device)
+        self.vidx, self.w, self.duv = f(t["vidx"]), f(t["w"]), f(t["duv"])
+        self.n_vert = t["vidx"].shape[0]
+        self.mesh = DeviceMesh.__new__(DeviceMesh)
+        self.mesh.pos = torch.zeros(self.n_vert, 3, dtype=torch.float32, device=device)
+        self.mesh.tri, self.mesh.uv, self.mesh.uv_tri = f(t["tri"]), f(t["uv"]), f(t["uv_tri"])
+        self.mesh.adj = f(mesh_adjacency(t["tri"]))
+        self.tables = t
+
+    def struct(self):
+        return Tess_(self.vidx.data_ptr(), self.w.data_ptr(), self.duv.data_ptr(), self.n_vert)
+
+
+def tess_fwd(ctx: Context, ts: DeviceTess, disp: DeviceTexture, base_pos=None, out=None, stream=None):
+    """Displaced tessellated positions v + disp(uv) n (Eq. 3)."""
+    b = ts.base.struct(base_pos)
+    t = ts.struct()
+    d = disp.struct()
+    out = ts.mesh.pos if out is None else out
+    _check(_lib.adr_tess_fwd(ctx.h, C.byref(b), C.byref(t), C.byref(d), _ptr(out), _stream(stream)))
+    return out
+
+
+def tess_bwd(ctx: Context, ts: DeviceTess, disp: DeviceTexture, g_pos, g_base_pos, g_disp,
+             base_pos=None, stream=None):
+    """Accumulates dL/d(base positions) and dL/d(displacement level 0) from
+    dL/d(tessellated positions)."""
+    b = ts.base.struct(base_pos)
+    t = ts.struct()
+    d = disp.struct()
+    _check(_lib.adr_tess_bwd(ctx.h, C.byref(b), C.byref(t), C.byref(d), _ptr(g_pos), _ptr(g_base_pos),
+                             _ptr(g_disp), _stream(stream)))

@@ -25,6 +25,12 @@ adr_status fail(adr_status code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+adr_status adr::report(adr_status code, const char* msg) { return fail(code, "%s", msg); }
+
+namespace {
+
 adr_status hip_fail(hipError_t e, const char* where) {
   return fail(ADR_E_HIP, "%s: %s", where, hipGetErrorString(e));
 }
@@ -348,6 +354,77 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (grads->orm) TIMED(7, launch_mip_adjoint(orm, grads->orm, st), "mip adjoint");
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
     TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
+  return ADR_OK;
+}
+
+static adr_status check_tess(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
+                             const adr_texture* disp, MeshD& m, TessD& ts, Tex& d) {
+  if (!ctx || !base || !tess || !disp) return fail(ADR_E_INVALID, "ctx, base, tess and disp are required");
+  if (base->n_pos < 1 || base->n_tri < 1 || !base->pos || !base->tri)
+    return fail(ADR_E_INVALID, "base mesh needs positions and triangles");
+  if (tess->n_vert < 0 || (tess->n_vert > 0 && (!tess->vidx || !tess->w || !tess->duv)))
+    return fail(ADR_E_INVALID, "tessellation table arrays are required");
+  adr_status r = check_tex(*disp, "disp", false, d);
+  if (r != ADR_OK) return r;
+  if (d.channels != 1) return fail(ADR_E_INVALID, "disp: needs 1 channel");
+  m.pos = base->pos;
+  m.tri = base->tri;
+  m.uv = base->uv;
+  m.uv_tri = base->uv_tri;
+  m.adj = base->adj;
+  m.n_pos = base->n_pos;
+  m.n_tri = base->n_tri;
+  m.n_uv = base->n_uv;
+  // the frame stage only needs uv for tangents; the base mesh is given them
+  if (!m.uv || !m.uv_tri) return fail(ADR_E_INVALID, "base mesh needs uv and uv_tri");
+  ts.vidx = tess->vidx;
+  ts.w = tess->w;
+  ts.duv = tess->duv;
+  ts.n = tess->n_vert;
+  return ADR_OK;
+}
+
+adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
+                        const adr_texture* disp, float* pos_out, adr_stream stream) {
+  MeshD m;
+  TessD ts;
+  Tex d;
+  adr_status r = check_tess(ctx, base, tess, disp, m, ts, d);
+  if (r != ADR_OK) return r;
+  if (ts.n > 0 && !pos_out) return fail(ADR_E_INVALID, "pos_out is required");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  ViewsD v{};
+  v.B = 1;
+  v.W = v.H = 1;
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  TIMED(0, launch_tess_fwd(m, ts, s.nacc, d, pos_out, st), "tessellation");
+  return ADR_OK;
+}
+
+adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
+                        const adr_texture* disp, const float* g_pos_out, float* g_base_pos,
+                        float* g_disp, adr_stream stream) {
+  MeshD m;
+  TessD ts;
+  Tex d;
+  adr_status r = check_tess(ctx, base, tess, disp, m, ts, d);
+  if (r != ADR_OK) return r;
+  if ((ts.n > 0 && !g_pos_out) || !g_base_pos) return fail(ADR_E_INVALID, "g_pos_out and g_base_pos are required");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  ViewsD v{};
+  v.B = 1;
+  v.W = v.H = 1;
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, true, s)) != ADR_OK) return r;
+  TIMED(8, launch_vertex_frame(m, s, st), "vertex frame");
+  TIMED(8, launch_fill_f32(s.dattr, 9 * (int64_t)m.n_pos, 0.f, st), "clear");
+  TIMED(8, launch_tess_bwd(m, ts, s.nacc, d, g_pos_out, g_base_pos, s.dattr, g_disp, st), "tessellation adjoint");
+  v.B = 0;  // no clip-space gradients: only the normal adjoint is folded into positions
+  TIMED(8, launch_mesh_bwd(m, v, s, g_base_pos, nullptr, st), "mesh adjoint");
   return ADR_OK;
 }
 

@@ -54,6 +54,43 @@ __device__ __forceinline__ f3 safe_normalize_bwd(f3 x, f3 g) {
   return inv * (g - dot(g, y) * y);
 }
 
+// float64 vectors (vertex frame, displacement).
+struct d3 {
+  double x, y, z;
+};
+__device__ __forceinline__ d3 dmk(double x, double y, double z) { return {x, y, z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator*(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double ddot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ d3 dcross(d3 a, d3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ d3 dld3f(const float* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ d3 dld3(const double* p, int i) { return {p[3 * i], p[3 * i + 1], p[3 * i + 2]}; }
+__device__ __forceinline__ void datomic3(double* p, int64_t i, d3 v) {
+  atomicAdd(p + 3 * i, v.x);
+  atomicAdd(p + 3 * i + 1, v.y);
+  atomicAdd(p + 3 * i + 2, v.z);
+}
+__device__ __forceinline__ void fatomic3(float* p, int64_t i, d3 v) {
+  atomicAdd(p + 3 * i, (float)v.x);
+  atomicAdd(p + 3 * i + 1, (float)v.y);
+  atomicAdd(p + 3 * i + 2, (float)v.z);
+}
+// x / |x| in float64; |x|^2 <= 1e-20 passes unchanged.
+__device__ __forceinline__ d3 dnormalize(d3 x) {
+  double n2 = ddot(x, x);
+  return n2 > 1e-20 ? (1.0 / sqrt(n2)) * x : x;
+}
+__device__ __forceinline__ d3 dnormalize_bwd(d3 x, d3 g) {
+  double n2 = ddot(x, x);
+  if (!(n2 > 1e-20)) return g;
+  double inv = 1.0 / sqrt(n2);
+  d3 y = inv * x;
+  return inv * (g - ddot(g, y) * y);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; each XCD
 // has its own L2.  This maps the hardware block id to a logical tile id so
 // that every XCD works through one contiguous range of tiles (neighbouring

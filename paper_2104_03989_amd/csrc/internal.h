@@ -56,7 +56,21 @@ struct Scratch {
   int n_partial;
 };
 
+struct TessD {
+  const int* vidx;    // [Vt,3]
+  const float* w;     // [Vt,3]
+  const float* duv;   // [Vt,2]
+  int n;
+};
+
+// Records `msg` as the calling thread's last error and returns `code`.
+adr_status report(adr_status code, const char* msg);
+
 // ---- launchers (stream-ordered, no host sync) ----
+hipError_t launch_tess_fwd(const MeshD& base, const TessD& ts, const double* nacc, const Tex& disp,
+                           float* out, hipStream_t st);
+hipError_t launch_tess_bwd(const MeshD& base, const TessD& ts, const double* nacc, const Tex& disp,
+                           const float* gout, float* gbase, float* dattr, float* gdisp, hipStream_t st);
 hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st);
 hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st);
 hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B,

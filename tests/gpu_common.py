@@ -72,3 +72,60 @@ def oracle_keys(w, scene, mvp32):
         keys.append(k)
         cov.append(c)
     return np.stack(keys), np.stack(cov)
+
+
+class TessGpuScene(GpuScene):
+    """A workload whose latent is a tessellated, displaced base mesh: the
+    latent render runs tess_fwd first, the gradients end in tess_bwd."""
+
+    def __init__(self, w, ctx, mvp32=None, eye=None):
+        super().__init__(w, ctx, mvp32, eye)
+        adr = self.adr
+        self.ts = adr.DeviceTess(w.latent.mesh, w.tess_levels)
+        self.disp = adr.DeviceTexture(w.disp.data, "f32", levels=1)
+        self.lat_mesh = self.ts.mesh
+
+    def render(self, which="latent", ref=None, flags=0, **kw):
+        if which == "latent":
+            self.adr.tess_fwd(self.ctx, self.ts, self.disp)
+        return super().render(which, ref, flags, **kw)
+
+    def grads(self, out, names=("pos", "disp", "normal")):
+        adr = self.adr
+        g = {"pos": torch.zeros_like(self.ts.mesh.pos)}
+        for n in ("kd", "normal", "orm"):
+            tex = getattr(self.lat_mat, n)
+            g[n] = tex.grad_buffer() if (n in names and tex is not None and tex.fmt == adr.TEX_F32) else None
+        adr.render_bwd(self.ctx, self.ts.mesh, self.lat_mat, self.views, out, g)
+        g_base = torch.zeros_like(self.ts.base.pos)
+        g_disp = torch.zeros_like(self.disp.data)
+        adr.tess_bwd(self.ctx, self.ts, self.disp, g["pos"], g_base, g_disp)
+        torch.cuda.synchronize()
+        S = self.disp.size
+        res = {"pos": g_base.cpu().numpy(), "disp": g_disp.cpu().numpy().reshape(S, S, 1)}
+        for n in ("kd", "normal", "orm"):
+            t = g[n]
+            if t is None:
+                continue
+            tex = getattr(self.lat_mat, n)
+            res[n] = t[:tex.size * tex.size].cpu().numpy().reshape(tex.size, tex.size, -1)
+            res[n + "_coarse_max"] = float(t[tex.size * tex.size:].abs().max()) if t.shape[0] > tex.size ** 2 else 0.0
+        return res
+
+
+def oracle_tess_keys(w, mvp32):
+    """Oracle visibility of the tessellated, displaced latent of every view."""
+    from oracle import tess as T
+    table = OL.tess_table(w)
+    base = w.latent.mesh
+    with torch.no_grad():
+        vd = T.displaced_positions(torch.as_tensor(base.pos, dtype=R.F64), base, table,
+                                   torch.as_tensor(w.disp.data, dtype=R.F64))
+    pos32 = vd.numpy().astype(np.float32)
+    keys, cov = [], []
+    for b in range(mvp32.shape[0]):
+        sv = R.snap(pos32, mvp32[b], w.width, w.height)
+        k, c, _ = R.raster(table["tri"], sv, w.width, w.height)
+        keys.append(k)
+        cov.append(c)
+    return np.stack(keys), np.stack(cov), vd.numpy()
