@@ -37,8 +37,16 @@ def _log(*a):
 def build_step(w, ctx, adr, torch, np, n_steps, seed):
     """Upload the workload and return (step(t) closure, state)."""
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
+    ref_mesh.precompute_frame(ctx)          # the reference does not move
     ref_mat = adr.DeviceMaterial(w.ref, ctx=ctx)
-    lat_mesh = adr.DeviceMesh(w.latent.mesh)
+    ts = disp = None
+    if w.tess_levels:
+        ts = adr.DeviceTess(w.latent.mesh, w.tess_levels)
+        disp = adr.DeviceTexture(w.disp.data, "f32", levels=1)
+        lat_mesh = ts.mesh
+        adr.tess_fwd(ctx, ts, disp)
+    else:
+        lat_mesh = adr.DeviceMesh(w.latent.mesh)
     lat_mat = adr.DeviceMaterial(w.latent, ctx=ctx)
     B, H, W = w.dirs.shape[0], w.height, w.width
     # cameras and lights of every step, drawn on the host ahead of time
@@ -58,7 +66,14 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed):
     # optimised parameters: positions and level 0 of the F32 maps
     params = []
     grads = {"pos": torch.zeros_like(lat_mesh.pos)}
-    params.append((lat_mesh.pos, grads["pos"]))
+    if ts is None:
+        params.append((lat_mesh.pos, grads["pos"]))
+    else:
+        # base positions and the displacement map (Eq. 3); the tessellated
+        # positions are recomputed every step
+        g_base = torch.zeros_like(ts.base.pos)
+        g_disp = torch.zeros_like(disp.data)
+        params += [(ts.base.pos, g_base), (disp.data, g_disp)]
     for name in ("kd", "normal", "orm"):
         if name not in w.optimize:
             grads[name] = None
@@ -75,10 +90,14 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed):
 
     def step(t):
         v = views[t % n_steps]
+        if ts is not None:
+            adr.tess_fwd(ctx, ts, disp)
         adr.render_fwd(ctx, ref_mesh, ref_mat, v, outputs=ref_out)
         adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_out["image"], loss=w.loss,
                        flags=adr.FWD_BUILD_MIPS, outputs=lat_out)
         adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads)
+        if ts is not None:
+            adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
         lr = w.lr * 10.0 ** (-0.0002 * t)
         adr.adam_step(ctx, adam, t + 1, lr)
 
@@ -87,15 +106,38 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed):
     return step, state
 
 
+TEXEL_C = 1.25   # compulsory texels per covered pixel per mip level at ~1 texel per pixel
+
+
+def optimised_maps(w):
+    """(name, bytes per texel) of the optimised F32 maps larger than 1x1."""
+    out = []
+    for name in ("kd", "normal", "orm"):
+        tex = getattr(w.latent, name)
+        if name in w.optimize and tex is not None and tex.data.shape[0] > 1:
+            out.append((name, 4 * tex.data.shape[2]))
+    return out
+
+
 def algorithmic_bytes(stage, w, st, covered_latent):
-    """Compulsory HBM bytes of one launch of a stage (pixel, vertex and
-    parameter streams; texel re-reads that hit in cache are not counted)."""
+    """Compulsory HBM bytes of one launch of a stage's kernel.
+
+    shade_bwd (pixel adjoint): per pixel its visibility key (8 B) and the
+    record header it writes (16 B); per covered pixel dL/dcolour (12 B) and a
+    16-B sample record per optimised map.
+    tex_bwd (texel scatter): the records back (16 B per pixel, 16 B per
+    covered pixel and map) and, per covered pixel and map, TEXEL_C texels at
+    each of the two trilinear levels, each a read-modify-write of its
+    gradient (2 x B_t)."""
     B, H, W = w.dirs.shape[0], w.height, w.width
     px = B * H * W
+    maps = optimised_maps(w)
     if stage == "adam":
         return 32.0 * st["n_params"]                      # read p,g,m,v; write p,m,v,g
     if stage == "shade_bwd":
-        return covered_latent * (8 + 12)                  # visibility key + dL/dcolour
+        return px * (8 + 16) + covered_latent * (12 + 16 * len(maps))
+    if stage == "tex_bwd":
+        return px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)
     if stage == "aa_bwd":
         return px * (8 + 12 + 12 + 12)                    # key, colour, dL/dimage, dL/dcolour
     if stage == "aa_loss":
@@ -105,11 +147,12 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     return None
 
 
-def cpu_baseline(w, np, torch):
-    """The FP64 oracle on two of the step's views (full meshes and maps)."""
+def cpu_baseline(w, np, torch, views):
+    """The FP64 oracle on one step of the workload (``views`` of its views,
+    full meshes and maps)."""
     from oracle import loop as OL
     from paper_2104_03989_amd import synth
-    w1 = synth.scaled(w, views=2)
+    w1 = synth.scaled(w, views=views)
     t0 = time.perf_counter()
     mvp32, eye = OL.cameras(w1)
     ref = OL.reference_image(w1, mvp32, eye)
@@ -117,10 +160,11 @@ def cpu_baseline(w, np, torch):
     loss, grads, _ = OL.loss_and_grads(w1, ref, mvp32, eye, params)
     OL.adam_update(params, grads, {}, 1, w1.lr)
     dt = time.perf_counter() - t0
-    return dict(value=2 * w1.width * w1.height / dt / 1e6, unit="Mpix/s", cores=torch.get_num_threads(),
-                kind="oracle", sample="2 of the 8 views of one step (full 300k/7k-triangle meshes, "
-                "2048^2 maps, 512x512): reference render, latent render, loss, backward, Adam",
-                seconds=round(dt, 2))
+    B = w.dirs.shape[0]
+    return dict(value=round(views * w1.width * w1.height / dt / 1e6, 4), unit="Mpix/s",
+                cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{views} of the {B} views of one step at full size: reference render, latent "
+                       "render, loss, backward, Adam", seconds=round(dt, 2))
 
 
 def serve_pool(n, g):
@@ -200,11 +244,46 @@ def serve(args):
     ctx.close()
 
 
+WORKLOADS = {
+    "paper": ("paper-scale loop: 297,680-tri GGX reference, 7,220-tri latent, 2048^2 maps, "
+              "8 views x 512x512, tone-mapped L1, Adam"),
+    "displacement": ("displacement loop: 369,920-tri reference, 980-tri base tessellated to 62,720 tris "
+                     "and displaced by a 1024^2 map, 1024^2 normal map, 8 views x 512x512, L1, Adam"),
+    "plain": ("plain single step: 20,480-tri SH reference, 1,280-tri latent, 256^2 maps, 4 views x 256x256, "
+              "Blinn-Phong, L1, Adam"),
+}
+
+
+def make_workload(name):
+    from paper_2104_03989_amd import synth
+    if name == "paper":
+        return synth.workload_paper_loop(), 2
+    if name == "displacement":
+        return synth.workload_displacement(), 3
+    return synth.workload_plain_step(), 1
+
+
+def calibrate_copy(np, torch, nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "launches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="paper")
+    ap.add_argument("--cpu-views", type=int, default=8, help="views of the oracle's timed step")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device copy three times (HBM counter scale) and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
@@ -227,12 +306,15 @@ def main():
     from paper_2104_03989_amd import adr, synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy(np, torch)
+        return
     _log("generating workload")
-    w = synth.workload_paper_loop()
+    w, cfg = make_workload(args.workload)
     B, H, W = w.dirs.shape[0], w.height, w.width
     ctx = adr.Context(0)
     n_steps = args.warmup + args.steps
-    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(2, 100))
+    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100))
     torch.cuda.synchronize()
     covered = int((st["lat_out"]["tri_id"] > 0).sum())
     _log(f"warmup {args.warmup}")
@@ -255,10 +337,11 @@ def main():
     mpix = B * H * W * args.steps / dt / 1e6
     # dominant stage and its roofline
     roof = None
-    prof = {}
+    prof, stage_step = {}, {}
     if stages:
         prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1] > 0}
         per_step = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
+        stage_step = {k: round(v, 4) for k, v in per_step.items()}
         dom = max(per_step, key=per_step.get)
         ms, cnt = stages[dom]
         avg_ms = ms / cnt
@@ -274,19 +357,18 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         _log("oracle baseline")
-        cpu = cpu_baseline(w, np, torch)
+        cpu = cpu_baseline(w, np, torch, min(args.cpu_views, B))
     rec = {
         "metric": "fwd+bwd Mpix/s (latent pixels per second, reference render and Adam included)",
         "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "steps_per_s": round(1e3 / ms_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "paper-scale loop: 297,680-tri GGX reference, 7,220-tri latent, "
-                               "2048^2 maps, 8 views x 512x512, tone-mapped L1, Adam",
+        "config": {"workload": WORKLOADS[args.workload],
                    "views": B, "res": [W, H], "ref_tris": int(w.ref.mesh.tri.shape[0]),
-                   "latent_tris": int(w.latent.mesh.tri.shape[0]), "params": st["n_params"],
+                   "latent_tris": int(st["lat_mesh"].tri.shape[0]), "params": st["n_params"],
                    "final_loss": round(loss, 6)},
-        "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof,
+        "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()

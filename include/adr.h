@@ -89,6 +89,13 @@ typedef struct adr_mesh {
   const int32_t* adj;            /* device [n_tri, 3]: triangle across the edge opposite
                                     corner k, -1 on a boundary (adr_mesh_adjacency) */
   int32_t n_pos, n_tri, n_uv;
+  /* Optional vertex frame (both or neither), device [n_pos, 3] unit smooth
+   * normals and UV tangents as adr_mesh_frame returns them for these
+   * positions (Sec. 5.1, "Tangent space").  When set, adr_render_fwd skips
+   * the frame stage: for a mesh whose positions do not change, such as the
+   * reference model.  adr_render_bwd always recomputes the frame. */
+  const float* nrm;
+  const float* tan;
 } adr_mesh;
 
 #define ADR_SHADE_BLINN_PHONG 0  /* E max(0,n.l) (kd + 0.04 max(0,n.h)^32) */
@@ -186,6 +193,14 @@ typedef struct adr_param {
 adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params, int32_t t,
                          float lr, float beta1, float beta2, float eps, adr_stream stream);
 
+/* Smooth vertex normals and UV tangents of a mesh (Sec. 5.1, "Tangent
+ * space": normals from area-weighted face normals, tangents from the UV
+ * Jacobian, both normalised), into device arrays nrm_out and tan_out
+ * [n_pos, 3]; mesh->nrm and mesh->tan are ignored.  Device work on
+ * `stream`. */
+adr_status adr_mesh_frame(adr_ctx* ctx, const adr_mesh* mesh, float* nrm_out, float* tan_out,
+                          adr_stream stream);
+
 /* Rebuild levels 1.. of a texture from level 0 (2x2 box average; RGBA8
  * rounds (a+b+c+d+2)/4).  Device work on `stream`. */
 adr_status adr_mip_build(adr_ctx* ctx, const adr_texture* tex, adr_stream stream);
@@ -228,9 +243,10 @@ adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
                         const adr_texture* disp, float* pos_out, adr_stream stream);
 /* Adjoint: accumulates dL/d base positions (g_base_pos [n_pos,3], through the
  * base vertex normals too) and dL/d displacement texels (g_disp, level-0
- * layout, nullable) from dL/d pos_out (g_pos_out [n_vert,3]). */
+ * layout, nullable) from dL/d pos_out (g_pos_out [n_vert,3], device), which
+ * is consumed: set to zero on exit, ready for the next step's accumulation. */
 adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
-                        const adr_texture* disp, const float* g_pos_out, float* g_base_pos,
+                        const adr_texture* disp, float* g_pos_out, float* g_base_pos,
                         float* g_disp, adr_stream stream);
 
 /* Stage timing.  When enabled, every render/adam call brackets each of its
@@ -239,8 +255,9 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
  * of launches since the last read, and starts a new window.  Stages:
  * 0 vertex frame, 1 transform, 2 raster, 3 shade, 4 antialias+loss,
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
- * 9 adam, 10 mip build.  ms and count: host arrays of ADR_N_STAGES. */
-#define ADR_N_STAGES 11
+ * 9 adam, 10 mip build, 11 texel adjoint.  ms and count: host arrays of
+ * ADR_N_STAGES. */
+#define ADR_N_STAGES 12
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
 

@@ -33,10 +33,10 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
-           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd")
-N_STAGES = 11
+           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame")
+N_STAGES = 12
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
-          "mip_adjoint", "mesh_bwd", "adam", "mip_build")
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd")
 
 
 class AdrError(RuntimeError):
@@ -55,7 +55,7 @@ class Texture_(C.Structure):
 
 class Mesh_(C.Structure):
     _fields_ = [("pos", P), ("tri", P), ("uv", P), ("uv_tri", P), ("adj", P),
-                ("n_pos", I32), ("n_tri", I32), ("n_uv", I32)]
+                ("n_pos", I32), ("n_tri", I32), ("n_uv", I32), ("nrm", P), ("tan", P)]
 
 
 class Material_(C.Structure):
@@ -128,6 +128,7 @@ _lib.adr_job_submit.argtypes = [P, C.POINTER(JobDesc_), C.POINTER(C.c_uint64)]
 _lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(JobResult_)]
 _lib.adr_ctx_profile.argtypes = [P, I32]
 _lib.adr_ctx_profile_read.argtypes = [P, P, P]
+_lib.adr_mesh_frame.argtypes = [P, C.POINTER(Mesh_), P, P, P]
 _lib.adr_tess_counts.argtypes = [P, I32, I32, I32, P, P, P]
 _lib.adr_tess_build.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P, P, P, P]
 _lib.adr_tess_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P]
@@ -251,11 +252,24 @@ class DeviceMesh:
         self.uv = torch.from_numpy(np.ascontiguousarray(mesh.uv, dtype=np.float32)).to(device)
         self.uv_tri = torch.from_numpy(np.ascontiguousarray(mesh.uv_tri, dtype=np.int32)).to(device)
         self.adj = torch.from_numpy(mesh_adjacency(mesh.tri)).to(device)
+        self.nrm = self.tan = None
+
+    def precompute_frame(self, ctx: "Context", stream=None):
+        """Compute the vertex frame once; later forward renders of these
+        positions reuse it (for a mesh that does not move)."""
+        nrm = torch.empty_like(self.pos)
+        tan = torch.empty_like(self.pos)
+        m = self.struct()
+        _check(_lib.adr_mesh_frame(ctx.h, C.byref(m), _ptr(nrm), _ptr(tan), _stream(stream)))
+        self.nrm, self.tan = nrm, tan
+        return nrm, tan
 
     def struct(self, pos=None):
         p = self.pos if pos is None else pos
+        fr = (self.nrm, self.tan) if (pos is None and self.nrm is not None) else (None, None)
         return Mesh_(p.data_ptr(), self.tri.data_ptr(), self.uv.data_ptr(), self.uv_tri.data_ptr(),
-                     self.adj.data_ptr(), p.shape[0], self.tri.shape[0], self.uv.shape[0])
+                     self.adj.data_ptr(), p.shape[0], self.tri.shape[0], self.uv.shape[0],
+                     _ptr(fr[0]), _ptr(fr[1]))
 
 
 class DeviceMaterial:
@@ -491,6 +505,7 @@ class DeviceTess:
         self.vidx, self.w, self.duv = f(t["vidx"]), f(t["w"]), f(t["duv"])
         self.n_vert = t["vidx"].shape[0]
         self.mesh = DeviceMesh.__new__(DeviceMesh)
+        self.mesh.nrm = self.mesh.tan = None
         self.mesh.pos = torch.zeros(self.n_vert, 3, dtype=torch.float32, device=device)
         self.mesh.tri, self.mesh.uv, self.mesh.uv_tri = f(t["tri"]), f(t["uv"]), f(t["uv_tri"])
         self.mesh.adj = f(mesh_adjacency(t["tri"]))
@@ -513,7 +528,7 @@ def tess_fwd(ctx: Context, ts: DeviceTess, disp: DeviceTexture, base_pos=None, o
 def tess_bwd(ctx: Context, ts: DeviceTess, disp: DeviceTexture, g_pos, g_base_pos, g_disp,
              base_pos=None, stream=None):
     """Accumulates dL/d(base positions) and dL/d(displacement level 0) from
-    dL/d(tessellated positions)."""
+    dL/d(tessellated positions) ``g_pos``, which is zeroed (consumed)."""
     b = ts.base.struct(base_pos)
     t = ts.struct()
     d = disp.struct()

@@ -60,7 +60,7 @@ struct Span {
 struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec;
   adr::JobServer* jobs = nullptr;
   bool prof = false;
   std::vector<Span> spans;
@@ -195,7 +195,8 @@ adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* 
   return ADR_OK;
 }
 
-adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool bwd, Scratch& s) {
+adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool bwd, Scratch& s,
+                           int tex_slots = 0) {
   size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
   size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
   adr_status r;
@@ -209,6 +210,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
     if ((r = ensure(ctx->gcolor, B * v.W * v.H * 12)) || (r = ensure(ctx->dclip, B * V * 16)) ||
         (r = ensure(ctx->dattr, V * 36)))
       return r;
+    if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
   }
   s.clip = (double*)ctx->clip.p;
   s.snap = (int*)ctx->snap.p;
@@ -223,6 +225,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
   s.gcolor = (float*)ctx->gcolor.p;
   s.dclip = (float*)ctx->dclip.p;
   s.dattr = (float*)ctx->dattr.p;
+  s.texrec = (float4*)ctx->texrec.p;
   s.n_partial = (int)tiles;
   return ADR_OK;
 }
@@ -272,7 +275,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   adr::jobs_destroy(ctx->jobs);
   ctx->jobs = nullptr;
   (void)hipDeviceSynchronize();
-  Buf* bufs[] = {&ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+  Buf* bufs[] = {&ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
@@ -305,11 +308,18 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (flags & ADR_FWD_BUILD_MIPS) {
     const Tex* maps[3] = {&kd, &nm, &orm};
     int nmaps = mat->model == ADR_SHADE_GGX ? 3 : 2;
+    MipSet ms{};
     for (int k = 0; k < nmaps; ++k)
-      if (maps[k]->fmt == ADR_TEX_F32) TIMED(10, launch_mip_build(*maps[k], st), "mip build");
+      if (maps[k]->fmt == ADR_TEX_F32 && maps[k]->levels > 1) ms.t[ms.n++] = *maps[k];
+    TIMED(10, launch_mip_build_set(ms, st), "mip build");
   }
   int64_t npx = (int64_t)v.B * v.W * v.H;
-  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  if (mesh->nrm && mesh->tan) {
+    s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
+    s.tan = const_cast<float*>(mesh->tan);
+  } else {
+    TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  }
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(2, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
   TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
@@ -337,7 +347,9 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
-  if ((r = prepare_scratch(ctx, m, v, true, s)) != ADR_OK) return r;
+  if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm))) !=
+      ADR_OK)
+    return r;
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(1, launch_orient(m, v, s, st), "orientation");
@@ -349,9 +361,19 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
                             saved->vis, st),
         "shading adjoint");
-  if (grads->kd) TIMED(7, launch_mip_adjoint(kd, grads->kd, st), "mip adjoint");
-  if (grads->normal) TIMED(7, launch_mip_adjoint(nm, grads->normal, st), "mip adjoint");
-  if (grads->orm) TIMED(7, launch_mip_adjoint(orm, grads->orm, st), "mip adjoint");
+  TIMED(11, launch_tex_bwd(v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, st),
+        "texel adjoint");
+  {
+    MipSet ms{};
+    const Tex* maps[3] = {&kd, &nm, &orm};
+    float* gs[3] = {grads->kd, grads->normal, grads->orm};
+    for (int k = 0; k < 3; ++k)
+      if (gs[k] && maps[k]->levels > 1) {
+        ms.t[ms.n] = *maps[k];
+        ms.g[ms.n++] = gs[k];
+      }
+    TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+  }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
     TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
   return ADR_OK;
@@ -405,7 +427,7 @@ adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
 }
 
 adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
-                        const adr_texture* disp, const float* g_pos_out, float* g_base_pos,
+                        const adr_texture* disp, float* g_pos_out, float* g_base_pos,
                         float* g_disp, adr_stream stream) {
   MeshD m;
   TessD ts;
@@ -425,6 +447,29 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
   TIMED(8, launch_tess_bwd(m, ts, s.nacc, d, g_pos_out, g_base_pos, s.dattr, g_disp, st), "tessellation adjoint");
   v.B = 0;  // no clip-space gradients: only the normal adjoint is folded into positions
   TIMED(8, launch_mesh_bwd(m, v, s, g_base_pos, nullptr, st), "mesh adjoint");
+  return ADR_OK;
+}
+
+adr_status adr_mesh_frame(adr_ctx* ctx, const adr_mesh* mesh, float* nrm_out, float* tan_out,
+                          adr_stream stream) {
+  if (!ctx || !mesh) return fail(ADR_E_INVALID, "ctx and mesh are required");
+  if (mesh->n_pos < 0 || mesh->n_tri < 0 || mesh->n_uv < 0) return fail(ADR_E_INVALID, "negative mesh size");
+  if (mesh->n_pos > 0 && (!nrm_out || !tan_out)) return fail(ADR_E_INVALID, "nrm_out and tan_out are required");
+  if (mesh->n_tri > 0 && (!mesh->pos || !mesh->tri || !mesh->uv || !mesh->uv_tri))
+    return fail(ADR_E_INVALID, "mesh needs pos, tri, uv and uv_tri");
+  MeshD m{mesh->pos, mesh->tri, mesh->uv, mesh->uv_tri, mesh->adj, mesh->n_pos, mesh->n_tri, mesh->n_uv};
+  if (m.n_pos == 0) return ADR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  ViewsD v{};
+  v.B = 1;
+  v.W = v.H = 1;
+  Scratch s;
+  adr_status r;
+  if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  s.nrm = nrm_out;
+  s.tan = tan_out;
+  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   return ADR_OK;
 }
 

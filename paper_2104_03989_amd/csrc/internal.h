@@ -11,7 +11,8 @@ namespace adr {
 constexpr uint64_t kKeyEmpty = 0xFFFFFFFF00000000ull;
 constexpr int kZMax = 16777215;
 constexpr int kMaxLevels = 15;
-constexpr int kSmallBBox = 256;    // triangles with a pixel bbox up to this are walked per thread
+constexpr int kTinyBBox = 64;      // pixel bbox up to this: walked by one thread
+constexpr int kMedBBox = 4096;     // up to this: walked by a whole wave; larger: tile-binned
 constexpr int kBigTile = 16;       // big-triangle tiles are kBigTile x kBigTile pixels
 
 // Texture as the kernels see it: level offsets in texels precomputed.
@@ -53,7 +54,15 @@ struct Scratch {
   float* gcolor;      // [B,H,W,3] dL/d(colour before AA)
   float* dclip;       // [B,V,4]
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
+  float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
   int n_partial;
+};
+
+// Up to three texture chains (a material's maps) and their gradient buffers.
+struct MipSet {
+  Tex t[3];
+  float* g[3];
+  int n;
 };
 
 struct TessD {
@@ -70,7 +79,7 @@ adr_status report(adr_status code, const char* msg);
 hipError_t launch_tess_fwd(const MeshD& base, const TessD& ts, const double* nacc, const Tex& disp,
                            float* out, hipStream_t st);
 hipError_t launch_tess_bwd(const MeshD& base, const TessD& ts, const double* nacc, const Tex& disp,
-                           const float* gout, float* gbase, float* dattr, float* gdisp, hipStream_t st);
+                           float* gout, float* gbase, float* dattr, float* gdisp, hipStream_t st);
 hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st);
 hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st);
 hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B,
@@ -88,10 +97,15 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st);
+// Number of texture-gradient slots (maps with a gradient buffer).
+int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm);
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
                             const Scratch& s, const uint64_t* vis, hipStream_t st);
-hipError_t launch_mip_adjoint(const Tex& t, float* g, hipStream_t st);
+hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
+                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st);
+hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st);
+hipError_t launch_mip_build_set(const MipSet& ms, hipStream_t st);
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
                            float* gvnormal, hipStream_t st);
 hipError_t launch_mip_build(const Tex& t, hipStream_t st);

@@ -172,6 +172,7 @@ size_t job_bytes(const adr_job_desc& d) {
   add(d.ref_n_uv * 8);
   add(d.ref_n_tri * 12);
   add(d.ref_n_tri * 12);
+  add(d.ref_n_pos * 24);  // reference vertex frame, computed once
   add(d.lat_n_pos * 12);
   add(d.lat_n_tri * 12);
   add(d.lat_n_uv * 8);
@@ -307,6 +308,13 @@ adr_status admit(JobServer* s, Job& j, hipStream_t st, adr_ctx* ctx) {
           up((void*)m.adj, adj.data(), nt * 12);
   };
   mesh(j.ref_mesh, j.ref_pos, j.ref_tri, j.ref_uv, j.ref_uv_tri, j.ref_adj, d.ref_n_pos, d.ref_n_tri, d.ref_n_uv);
+  {
+    // the reference never moves: its vertex frame is computed once here
+    float* frame = (float*)take((size_t)d.ref_n_pos * 24);
+    ok &= adr_mesh_frame(ctx, &j.ref_mesh, frame, frame + 3 * (size_t)d.ref_n_pos, (adr_stream)st) == ADR_OK;
+    j.ref_mesh.nrm = frame;
+    j.ref_mesh.tan = frame + 3 * (size_t)d.ref_n_pos;
+  }
   mesh(j.lat_mesh, j.lat_pos, j.lat_tri, j.lat_uv, j.lat_uv_tri, j.lat_adj, d.lat_n_pos, d.lat_n_tri, d.lat_n_uv);
   auto tex = [&](JobTex& t, const void* src, int size, int fmt) {
     t.size = size;

@@ -13,10 +13,11 @@
 // Everything here is integer or correctly rounded float32 in a fixed order,
 // so the visibility buffer is bit-exact and independent of launch order.
 //
-// Work split: a triangle whose pixel bounding box holds at most kSmallBBox
+// Work split: a triangle whose pixel bounding box holds at most kTinyBBox
 // pixel centres is walked by one thread (most triangles of dense meshes are
-// pixel-sized); larger ones go to a per-view list that a second kernel bins
-// against 16x16 tiles in LDS and resolves one pixel per thread.
+// pixel-sized), one of up to kMedBBox by all lanes of its wave together;
+// larger ones go to a per-view list that a second kernel bins against 16x16
+// tiles in LDS and resolves one pixel per thread.
 // This file is compiled with -ffp-contract=off.
 #include "dev.h"
 
@@ -150,39 +151,70 @@ __global__ void k_clear(uint64_t* __restrict__ vis, uint32_t* __restrict__ cov, 
   if (gid < B) big_cnt[gid] = 0u;
 }
 
-__global__ void k_raster_small(MeshD m, ViewsD v, const int4* __restrict__ snap,
-                               int8_t* __restrict__ orient, uint32_t* __restrict__ big,
-                               uint32_t* __restrict__ big_cnt, unsigned long long* __restrict__ vis,
-                               uint32_t* __restrict__ cov) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= v.B * m.n_tri) return;
-  int b = gid / m.n_tri, t = gid - b * m.n_tri;
-  int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
+__device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j, int W,
+                                             unsigned long long* __restrict__ vv, uint32_t* __restrict__ cv) {
+  const int px = 256 * i + 128, py = 256 * j + 128;
+  if (!covers(s, px, py)) return;
+  unsigned long long key = ((unsigned long long)depth_at(s, px, py) << 32) | (uint32_t)(t + 1);
+  int64_t o = (int64_t)j * W + i;
+  if (cv) atomicAdd(cv + o, 1u);
+  atomicMin(vv + o, key);
+}
+
+// One thread per triangle and view.  A triangle whose pixel bounding box
+// holds at most kTinyBBox pixel centres is walked by its thread; up to
+// kMedBBox the whole wave walks it, one pixel per lane (the triangle's set-up
+// is recomputed from wave-uniform indices); larger ones go to the view's
+// list for the tile kernel.
+__global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const int4* __restrict__ snap,
+                                                      int8_t* __restrict__ orient, uint32_t* __restrict__ big,
+                                                      uint32_t* __restrict__ big_cnt,
+                                                      unsigned long long* __restrict__ vis,
+                                                      uint32_t* __restrict__ cov) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  int area = 0, b = 0, t = 0;
   Setup s;
-  if (!setup_tri(snap + (int64_t)b * m.n_pos, c, s)) {
-    orient[gid] = 0;
-    return;
+  BBox bb{0, -1, 0, -1};
+  if (gid < v.B * m.n_tri) {
+    b = gid / m.n_tri;
+    t = gid - b * m.n_tri;
+    int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
+    if (setup_tri(snap + (int64_t)b * m.n_pos, c, s)) {
+      orient[gid] = s.flip ? -1 : 1;
+      bb = pixel_bbox(s, v.W, v.H);
+      if (bb.i1 >= bb.i0 && bb.j1 >= bb.j0) area = (bb.i1 - bb.i0 + 1) * (bb.j1 - bb.j0 + 1);
+    } else {
+      orient[gid] = 0;
+    }
   }
-  orient[gid] = s.flip ? -1 : 1;
-  BBox bb = pixel_bbox(s, v.W, v.H);
-  if (bb.i1 < bb.i0 || bb.j1 < bb.j0) return;
-  int nx = bb.i1 - bb.i0 + 1, ny = bb.j1 - bb.j0 + 1;
-  if (nx * ny > kSmallBBox) {
+  const int64_t HW = (int64_t)v.W * v.H;
+  if (area > kMedBBox) {
     uint32_t slot = atomicAdd(big_cnt + b, 1u);
     big[(int64_t)b * m.n_tri + slot] = (uint32_t)t;
-    return;
+  } else if (area > 0 && area <= kTinyBBox) {
+    unsigned long long* vv = vis + b * HW;
+    uint32_t* cv = cov ? cov + b * HW : nullptr;
+    for (int j = bb.j0; j <= bb.j1; ++j)
+      for (int i = bb.i0; i <= bb.i1; ++i) raster_pixel(s, t, i, j, v.W, vv, cv);
   }
-  unsigned long long* vv = vis + (int64_t)b * v.W * v.H;
-  uint32_t* cv = cov ? cov + (int64_t)b * v.W * v.H : nullptr;
-  for (int j = bb.j0; j <= bb.j1; ++j) {
-    int py = 256 * j + 128;
-    for (int i = bb.i0; i <= bb.i1; ++i) {
-      int px = 256 * i + 128;
-      if (!covers(s, px, py)) continue;
-      unsigned long long key = ((unsigned long long)depth_at(s, px, py) << 32) | (uint32_t)(t + 1);
-      int64_t o = (int64_t)j * v.W + i;
-      if (cv) atomicAdd(cv + o, 1u);
-      atomicMin(vv + o, key);
+  // medium triangles of this wave, one after the other, by all its lanes
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(area > kTinyBBox && area <= kMedBBox);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int g = __builtin_amdgcn_readlane(gid, leader);
+    const int bw = g / m.n_tri, tw = g - bw * m.n_tri;
+    Setup sw;
+    int3 c = make_int3(m.tri[3 * tw], m.tri[3 * tw + 1], m.tri[3 * tw + 2]);
+    setup_tri(snap + (int64_t)bw * m.n_pos, c, sw);  // succeeded for the leader
+    const BBox bw_ = pixel_bbox(sw, v.W, v.H);
+    const int nx = bw_.i1 - bw_.i0 + 1, n = nx * (bw_.j1 - bw_.j0 + 1);
+    unsigned long long* vv = vis + bw * HW;
+    uint32_t* cv = cov ? cov + bw * HW : nullptr;
+    for (int q = lane; q < n; q += 64) {
+      const int jj = q / nx;
+      raster_pixel(sw, tw, bw_.i0 + (q - jj * nx), bw_.j0 + jj, v.W, vv, cv);
     }
   }
 }

@@ -363,7 +363,7 @@ __device__ __forceinline__ void tex_bwd(const Tex& t, float* gtex, const PixelGe
 // added to HBM once each.  A footprint larger than the window (a UV seam,
 // very oblique sampling) falls back to direct atomics.
 
-constexpr int kWinFloats = 3072;  // per wave: 32 x 32 texels x 3 channels
+constexpr int kWinTex = 1024;  // per wave: e.g. 18 x 18 texels x 3 channels
 
 struct TexScatter {
   float u, v;
@@ -373,16 +373,24 @@ struct TexScatter {
   f3 gs;
 };
 
-__device__ __forceinline__ int wave_min_i(int x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off));
-  return x;
+// Wave-wide min / max of an int, called from converged code (all 64 lanes
+// active).  Within each row of 16 lanes two quad permutations and row
+// rotations by 4 and 8 (DPP operands: VALU only, no LDS traffic) leave the
+// row's result in every lane; the four rows are combined from scalar reads
+// of lanes 0, 16, 32 and 48.
+template <bool kMin>
+__device__ __forceinline__ int wave_reduce_i(int x) {
+  auto op = [](int a, int b) { return kMin ? min(a, b) : max(a, b); };
+  x = op(x, __builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  x = op(x, __builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  x = op(x, __builtin_amdgcn_update_dpp(x, x, 0x124, 0xF, 0xF, false));  // row_ror:4
+  x = op(x, __builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false));  // row_ror:8
+  const int a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 16);
+  const int c = __builtin_amdgcn_readlane(x, 32), d = __builtin_amdgcn_readlane(x, 48);
+  return op(op(a, b), op(c, d));
 }
-__device__ __forceinline__ int wave_max_i(int x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
-  return x;
-}
+__device__ __forceinline__ int wave_min_i(int x) { return wave_reduce_i<true>(x); }
+__device__ __forceinline__ int wave_max_i(int x) { return wave_reduce_i<false>(x); }
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -413,6 +421,34 @@ __device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
   return q;
 }
 
+// DPP lane moves (converged code): lane i receives x from the lane that the
+// control word CTRL names; a lane without a source keeps its own value.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+
+// One merge step between paired lanes: a receiver (recv) adds the values of
+// its partner (reached with TO_RECV) when both hold the same cell key, and
+// that partner (send, reaching the receiver with TO_SEND) then drops out
+// (key -1).  Keys of lanes without a contribution are -1.
+template <int TO_RECV, int TO_SEND>
+__device__ __forceinline__ void merge_step(bool recv, bool send, int& key, float (&v)[12]) {
+  const int pk_r = dpp_i<TO_RECV>(key);
+  const int pk_s = dpp_i<TO_SEND>(key);
+  const bool take = recv && key >= 0 && pk_r == key;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const float pv = dpp_f<TO_RECV>(v[i]);
+    v[i] += take ? pv : 0.f;
+  }
+  if (send && key >= 0 && pk_s == key) key = -1;
+}
+
 __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool act, const TexScatter& ts,
                                  float* win) {
   const int BIG = 1 << 20;
@@ -437,15 +473,51 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
     int rr[4] = {q.r0, q.r0, q.r1, q.r1}, cc[4] = {q.c0, q.c0 + 1, q.c0, q.c0 + 1};
     float gsv[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
     int off = t.off[lev];
-    if (hh * ww * C <= kWinFloats) {
+    if (hh * ww * C <= kWinTex) {
       int n = hh * ww * C;
       for (int k = lane; k < n; k += 64) win[k] = 0.f;
+      // The per-lane contributions (4 corners x 3 channels) of lanes that
+      // share a bilinear cell are first merged across lanes with DPP moves
+      // (pairs, quads and eights along x, then pairs of pixel rows), since
+      // the cost of the LDS atomics grows with the number of active lanes.
+      int key = part ? (((q.r0 << 1) | (q.r1 != q.r0 ? 1 : 0)) << 15) | q.c0 : -1;
+      float v[12];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float wk = part ? wl * w[k] : 0.f;
+        v[3 * k] = wk * gsv[0];
+        v[3 * k + 1] = wk * gsv[1];
+        v[3 * k + 2] = wk * gsv[2];
+      }
+      merge_step<0xB1, 0xB1>((lane & 1) == 0, (lane & 1) == 1, key, v);    // quad_perm [1,0,3,2]
+      merge_step<0x4E, 0x4E>((lane & 3) == 0, (lane & 3) == 2, key, v);    // quad_perm [2,3,0,1]
+      merge_step<0x104, 0x114>((lane & 7) == 0, (lane & 7) == 4, key, v);  // row_shl:4 / row_shr:4
+      merge_step<0x108, 0x118>((lane & 8) == 0, (lane & 8) != 0, key, v);  // row_shl:8 / row_shr:8
       wave_sync();
-      if (part) {
+      if (key >= 0) {
+        // Lanes still sharing a cell update its texels and channels in a
+        // rotated order, so that one instruction rarely hits one address
+        // from several lanes.
+        const int px = lane & 7, py = lane >> 3;
+        const int qr = (px & 1) | ((py & 1) << 1);
+        const int rot = C == 3 ? ((px >> 1) & 1) + ((py >> 1) & 1) : 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          int cell = ((rr[k] - rmin) * ww + (cc[k] - cmin)) * C;
-          for (int ch = 0; ch < C; ++ch) atomicAdd(win + cell + ch, wl * w[k] * gsv[ch]);
+          const int kk = k ^ qr;
+          const int cell = (((kk & 2 ? q.r1 : q.r0) - rmin) * ww + ((kk & 1 ? q.c0 + 1 : q.c0) - cmin)) * C;
+          const float v0 = kk == 0 ? v[0] : (kk == 1 ? v[3] : (kk == 2 ? v[6] : v[9]));
+          if (C == 3) {
+            const float v1 = kk == 0 ? v[1] : (kk == 1 ? v[4] : (kk == 2 ? v[7] : v[10]));
+            const float v2 = kk == 0 ? v[2] : (kk == 1 ? v[5] : (kk == 2 ? v[8] : v[11]));
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+              int c = ch + rot;
+              c = c >= 3 ? c - 3 : c;
+              atomicAdd(win + cell + c, c == 0 ? v0 : (c == 1 ? v1 : v2));
+            }
+          } else {
+            atomicAdd(win + cell, v0);
+          }
         }
       }
       wave_sync();
@@ -613,15 +685,60 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
 }
 
 // Pixels of one 64-wide wave (an 8x8 block) mostly lie on a few triangles,
-// so their vertex gradients hit the same few addresses.  Lanes are grouped
-// by triangle; each group's 36 sums are formed with cross-lane shuffles and
-// written by 36 lanes with one atomic each, instead of 36 atomics per pixel
-// on the same addresses.
-__global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, const float* __restrict__ gcolor,
-                                                   float* __restrict__ gkd, float* __restrict__ gnm,
-                                                   float* __restrict__ gorm, float* __restrict__ dclip,
+// so their vertex gradients hit the same few addresses.  Each lane writes
+// its 36 per-corner values to the wave's LDS window as a 36 x 64 table (row
+// stride 65 floats: the 36 rows read by one instruction fall in different
+// banks); then, per triangle present in the wave, lane k < 36 sums column
+// entries of row k over the lanes on that triangle and issues one atomic.
+// The member loops of all triangles together visit each lane once.
+constexpr int kAccStride = 65;
+constexpr int kVtxTable = kVtxAcc * kAccStride;  // floats per wave
+
+__device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, bool act, int tri,
+                                                    const int* vtx, const float* acc, float* win,
+                                                    float* __restrict__ dclip, float* __restrict__ dattr) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(act);
+  if (!todo) return;
+#pragma unroll
+  for (int k = 0; k < kVtxAcc; ++k) win[k * kAccStride + lane] = act ? acc[k] : 0.f;
+  wave_sync();
+  while (todo) {
+    int leader = __ffsll((long long)todo) - 1;
+    int tl = __shfl(tri, leader);
+    unsigned long long mine = __ballot(act && tri == tl);
+    todo &= ~mine;
+    int v0 = __shfl(vtx[0], leader), v1 = __shfl(vtx[1], leader), v2 = __shfl(vtx[2], leader);
+    if (lane < kVtxAcc) {
+      const float* row = win + lane * kAccStride;
+      float sum = 0.f;
+      for (unsigned long long m = mine; m; m &= m - 1) sum += row[__ffsll((long long)m) - 1];
+      if (sum != 0.f) {
+        int c = lane / 12, comp = lane - 12 * c;
+        int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
+        float* dst = comp < 9 ? dattr + 9 * (int64_t)vi + comp
+                              : dclip + 4 * ((int64_t)b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
+        atomicAdd(dst, sum);
+      }
+    }
+  }
+  wave_sync();
+}
+
+// Texture-sample records handed from the pixel adjoint to the texel
+// scatter, per pixel of the view batch: rec[0] = (u, v, packed levels, 0)
+// with byte k of the packed levels the lower mip level l0 of gradient slot
+// k (255: no contribution), and rec[1 + k] = (dL/dsample, weight of level
+// l0 + 1) of slot k.
+struct TexSlots {
+  int kd, nm, orm;  // slot of each map, -1 without a gradient buffer
+  int n;
+};
+
+__global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, const float* __restrict__ gcolor,
+                                                   float4* __restrict__ rec, float* __restrict__ dclip,
                                                    float* __restrict__ dattr) {
-  __shared__ float win_all[4][kWinFloats];
+  __shared__ float table_all[4][kVtxTable];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   float acc[kVtxAcc];
@@ -629,33 +746,52 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, const float* __r
   int vtx[3] = {0, 0, 0};
   TexScatter ts[3];
   bool act = p.ok && shade_bwd_pixel(a, p, gcolor, acc, tri, vtx, ts);
+  if (p.ok && sl.n > 0) {
+    const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
+    const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
+    uint32_t lv = 0xFFFFFFFFu;
+    if (act) {
+      const int slot[3] = {sl.kd, sl.nm, sl.orm};
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        if (slot[m] < 0) continue;
+        lv &= ~(0xFFu << (8 * slot[m]));
+        lv |= (uint32_t)ts[m].l0 << (8 * slot[m]);
+        rec[(1 + slot[m]) * P + o] = make_float4(ts[m].gs.x, ts[m].gs.y, ts[m].gs.z, ts[m].has1 ? ts[m].f : 0.f);
+      }
+    }
+    rec[o] = make_float4(act ? ts[0].u : 0.f, act ? ts[0].v : 0.f, __uint_as_float(lv), 0.f);
+  }
+  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], dclip, dattr);
+}
+
+// Texel-gradient scatter of the recorded samples: a kernel of its own with
+// few registers, so that enough waves are resident to hide the latency of
+// the LDS atomics of the window accumulation.
+struct TexBwdArgs {
+  Tex t[3];
+  float* g[3];
+  int n;
+  const float4* rec;
+  ViewsD v;
+  int tiles_x, tiles_y;
+};
+
+__global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
+  __shared__ float win_all[4][kWinTex];
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
+  const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
+  float4 r0 = p.ok ? a.rec[o] : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
+  const uint32_t lv = __float_as_uint(r0.z);
   float* win = win_all[threadIdx.x >> 6];
-  if (gkd) wave_scatter_tex(a.kd, gkd, act, ts[0], win);
-  if (gnm) wave_scatter_tex(a.nm, gnm, act, ts[1], win);
-  if (gorm && a.model == ADR_SHADE_GGX) wave_scatter_tex(a.orm, gorm, act, ts[2], win);
-  const int lane = threadIdx.x & 63;
-  unsigned long long todo = __ballot(act);
-  while (todo) {
-    int leader = __ffsll((long long)todo) - 1;
-    int tl = __shfl(tri, leader);
-    bool mine = act && tri == tl;
-    todo &= ~__ballot(mine);
-    float mysum = 0.f;
-#pragma unroll
-    for (int k = 0; k < kVtxAcc; ++k) {
-      float x = mine ? acc[k] : 0.f;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-      if (lane == k) mysum = x;
-    }
-    int v0 = __shfl(vtx[0], leader), v1 = __shfl(vtx[1], leader), v2 = __shfl(vtx[2], leader);
-    if (lane < kVtxAcc && mysum != 0.f) {
-      int c = lane / 12, comp = lane - 12 * c;
-      int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
-      float* dst = comp < 9 ? dattr + 9 * (int64_t)vi + comp
-                            : dclip + 4 * ((int64_t)p.b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
-      atomicAdd(dst, mysum);
-    }
+  for (int k = 0; k < a.n; ++k) {
+    const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
+    const bool act = p.ok && l0 != 0xFF;
+    float4 rk = act ? a.rec[(1 + k) * P + o] : make_float4(0.f, 0.f, 0.f, 0.f);
+    TexScatter ts{r0.x, r0.y, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
+    wave_scatter_tex(a.t[k], a.g[k], act, ts, win);
   }
 }
 
@@ -686,13 +822,50 @@ hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Te
   return hipGetLastError();
 }
 
+int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm) {
+  return (gkd ? 1 : 0) + (gnm ? 1 : 0) + ((gorm && model == ADR_SHADE_GGX) ? 1 : 0);
+}
+
+// Gradient slots in the order kd, normal, orm (maps with a gradient buffer).
+static int make_slots(int model, const Tex& kd, const Tex& nm, const Tex& orm, float* gkd, float* gnm,
+                      float* gorm, TexSlots& sl, TexBwdArgs& tb) {
+  sl = TexSlots{-1, -1, -1, 0};
+  tb = TexBwdArgs{};
+  auto add = [&](int& slot, const Tex& t, float* g) {
+    slot = sl.n++;
+    tb.t[slot] = t;
+    tb.g[slot] = g;
+  };
+  if (gkd) add(sl.kd, kd, gkd);
+  if (gnm) add(sl.nm, nm, gnm);
+  if (gorm && model == ADR_SHADE_GGX) add(sl.orm, orm, gorm);
+  tb.n = sl.n;
+  return sl.n;
+}
+
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
                             const Scratch& s, const uint64_t* vis, hipStream_t st) {
   ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
   int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, s.gcolor, gkd, gnm, gorm,
-                     s.dclip, s.dattr);
+  TexSlots sl;
+  TexBwdArgs tb;
+  make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb);
+  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.dclip, s.dattr);
+  return hipGetLastError();
+}
+
+hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
+                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st) {
+  TexSlots sl;
+  TexBwdArgs tb;
+  if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb) == 0) return hipSuccess;
+  tb.rec = s.texrec;
+  tb.v = v;
+  tb.tiles_x = (v.W + 15) / 16;
+  tb.tiles_y = (v.H + 15) / 16;
+  int nb = tb.tiles_x * tb.tiles_y * v.B;
+  hipLaunchKernelGGL(k_tex_bwd, dim3(nb), dim3(256), 0, st, tb);
   return hipGetLastError();
 }
 

@@ -97,12 +97,13 @@ __global__ void k_tess_fwd(MeshD base, TessD ts, const double* __restrict__ nacc
 }
 
 __global__ void k_tess_bwd(MeshD base, TessD ts, const double* __restrict__ nacc, Tex disp,
-                           const float* __restrict__ gout, float* __restrict__ gbase,
+                           float* __restrict__ gout, float* __restrict__ gbase,
                            float* __restrict__ dattr, float* __restrict__ gdisp) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= ts.n) return;
   d3 g = dld3f(gout, v);
   if (g.x == 0.0 && g.y == 0.0 && g.z == 0.0) return;
+  st3(gout, v, mk(0.f, 0.f, 0.f));  // consumed
   TessV tv = tess_vertex(base, ts, nacc, v);
   d3 n = dnormalize(tv.m);
   DBil b = disp_footprint(disp, ts.duv[2 * v], ts.duv[2 * v + 1]);
@@ -134,7 +135,7 @@ hipError_t launch_tess_fwd(const MeshD& base, const TessD& ts, const double* nac
 }
 
 hipError_t launch_tess_bwd(const MeshD& base, const TessD& ts, const double* nacc, const Tex& disp,
-                           const float* gout, float* gbase, float* dattr, float* gdisp, hipStream_t st) {
+                           float* gout, float* gbase, float* dattr, float* gdisp, hipStream_t st) {
   if (ts.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_tess_bwd, dim3((ts.n + 255) / 256), dim3(256), 0, st, base, ts, nacc, disp, gout,
                      gbase, dattr, gdisp);

@@ -1,24 +1,10 @@
 // Mip chains of the optimised maps (each level a 2x2 box average of the one
 // below; Sec. 4.2 treats the mip chain as the texture representation) and
 // the adjoint that pushes coarse-level texel gradients down to level 0.
+// RGBA8: (a + b + c + d + 2) >> 2 per channel; F32: ((a + b) + (c + d)) / 4.
 #include "dev.h"
 
 namespace adr {
-
-__global__ void k_mip_down_f32(float* __restrict__ d, int src_off, int dst_off, int s_dst, int C) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  int n = s_dst * s_dst;
-  if (idx >= n) return;
-  int r = idx / s_dst, c = idx - r * s_dst;
-  int s_src = 2 * s_dst;
-  const float* src = d + (int64_t)src_off * C;
-  float* dst = d + (int64_t)dst_off * C;
-  int64_t t00 = (int64_t)(2 * r) * s_src + 2 * c, t01 = t00 + 1, t10 = t00 + s_src, t11 = t10 + 1;
-  for (int ch = 0; ch < C; ++ch) {
-    float a = src[t00 * C + ch], b = src[t01 * C + ch], e = src[t10 * C + ch], f = src[t11 * C + ch];
-    dst[(int64_t)idx * C + ch] = ((a + b) + (e + f)) * 0.25f;
-  }
-}
 
 __global__ void k_mip_down_rgba8(uchar4* __restrict__ d, int src_off, int dst_off, int s_dst) {
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,51 +23,205 @@ __global__ void k_mip_down_rgba8(uchar4* __restrict__ d, int src_off, int dst_of
   d[dst_off + idx] = o;
 }
 
+// ------------------------------------------------------------------ F32 chains
+// Float chains are built and differentiated in two launches for all maps of
+// a material: a tile kernel in which each block owns a kMipTile^2 tile of
+// level 0 and the levels 1..log2(kMipTile) above it (kept in LDS between
+// levels), and a one-block-per-map kernel for the few coarse levels above.
+// Both produce exactly the per-level box filter and its adjoint.
+constexpr int kMipTile = 32;
+constexpr int kMipTileLevels = 5;  // log2(kMipTile)
+
+__device__ __forceinline__ int ilog2i(int x) { return 31 - __clz(x); }
+
+__global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.y];
+  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
+  const int L = min(t.levels - 1, ilog2i(T));
+  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
+  const int C = t.channels, tid = threadIdx.x;
+  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
+  __shared__ float lds[2][256 * 4];
+  float* d = (float*)t.data;
+  int s = T >> 1;
+  if (tid < s * s) {
+    int r = tid / s, c = tid - r * s;
+    int64_t t00 = (int64_t)(by * T + 2 * r) * S + bx * T + 2 * c;
+    int64_t o = (int64_t)t.off[1] + (int64_t)(by * s + r) * (S >> 1) + bx * s + c;
+    for (int ch = 0; ch < C; ++ch) {
+      float a = d[t00 * C + ch], b = d[(t00 + 1) * C + ch];
+      float e = d[(t00 + S) * C + ch], f = d[(t00 + S + 1) * C + ch];
+      float v = ((a + b) + (e + f)) * 0.25f;
+      lds[0][tid * C + ch] = v;
+      d[o * C + ch] = v;
+    }
+  }
+  for (int l = 2; l <= L; ++l) {
+    const int sp = s;
+    s >>= 1;
+    __syncthreads();
+    const float* src = lds[l & 1];
+    float* dst = lds[(l + 1) & 1];
+    if (tid < s * s) {
+      int r = tid / s, c = tid - r * s;
+      int k00 = 2 * r * sp + 2 * c;
+      int64_t o = (int64_t)t.off[l] + (int64_t)(by * s + r) * (S >> l) + bx * s + c;
+      for (int ch = 0; ch < C; ++ch) {
+        float a = src[k00 * C + ch], b = src[(k00 + 1) * C + ch];
+        float e = src[(k00 + sp) * C + ch], f = src[(k00 + sp + 1) * C + ch];
+        float v = ((a + b) + (e + f)) * 0.25f;
+        dst[tid * C + ch] = v;
+        d[o * C + ch] = v;
+      }
+    }
+  }
+}
+
+// Levels above the tile range, one block per map, level by level.
+__global__ __launch_bounds__(256) void k_mip_build_top(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.x];
+  const int S = t.size, C = t.channels;
+  float* d = (float*)t.data;
+  for (int l = kMipTileLevels + 1; l < t.levels; ++l) {
+    const int s = S >> l, sp = 2 * s;
+    for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x) {
+      int r = idx / s, c = idx - r * s;
+      int64_t t00 = (int64_t)t.off[l - 1] + (int64_t)(2 * r) * sp + 2 * c;
+      int64_t o = (int64_t)t.off[l] + idx;
+      for (int ch = 0; ch < C; ++ch) {
+        float a = d[t00 * C + ch], b = d[(t00 + 1) * C + ch];
+        float e = d[(t00 + sp) * C + ch], f = d[(t00 + sp + 1) * C + ch];
+        d[o * C + ch] = ((a + b) + (e + f)) * 0.25f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Adjoint of the coarse levels above the tile range: level l pushes a
+// quarter of each texel's gradient to its four children and is cleared.
+__global__ __launch_bounds__(256) void k_mip_adjoint_top(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.x];
+  const int S = t.size, C = t.channels;
+  float* g = ms.g[blockIdx.x];
+  for (int l = t.levels - 1; l > kMipTileLevels; --l) {
+    const int s = S >> l, sc = 2 * s;
+    for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x) {
+      int r = idx / s, c = idx - r * s;
+      int64_t k00 = (int64_t)t.off[l - 1] + (int64_t)(2 * r) * sc + 2 * c;
+      int64_t kids[4] = {k00, k00 + 1, k00 + sc, k00 + sc + 1};
+      int64_t o = (int64_t)t.off[l] + idx;
+      for (int ch = 0; ch < C; ++ch) {
+        float w = 0.25f * g[o * C + ch];
+        for (int k = 0; k < 4; ++k) g[kids[k] * C + ch] += w;
+        g[o * C + ch] = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Adjoint within a level-0 tile: the tile's levels L..1 (L <= 5) folded
+// down through LDS (each level adds a quarter of its parent's folded value)
+// and added to level 0; the tile's coarse texels are cleared.
+__global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.y];
+  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
+  const int L = min(t.levels - 1, ilog2i(T));
+  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
+  const int C = t.channels, tid = threadIdx.x;
+  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
+  float* g = ms.g[blockIdx.y];
+  __shared__ float lds[2][256 * 4];
+  // level L of the tile has no parent inside it
+  int s = T >> L;
+  float* cur = lds[L & 1];
+  if (tid < s * s) {
+    int r = tid / s, c = tid - r * s;
+    int64_t o = (int64_t)t.off[L] + (int64_t)(by * s + r) * (S >> L) + bx * s + c;
+    for (int ch = 0; ch < C; ++ch) {
+      cur[tid * C + ch] = g[o * C + ch];
+      g[o * C + ch] = 0.f;
+    }
+  }
+  for (int l = L - 1; l >= 1; --l) {
+    const int sp = s;
+    s <<= 1;
+    __syncthreads();
+    const float* par = lds[(l + 1) & 1];
+    float* dst = lds[l & 1];
+    if (tid < s * s) {
+      int r = tid / s, c = tid - r * s;
+      int kp = (r >> 1) * sp + (c >> 1);
+      int64_t o = (int64_t)t.off[l] + (int64_t)(by * s + r) * (S >> l) + bx * s + c;
+      for (int ch = 0; ch < C; ++ch) {
+        float v = g[o * C + ch] + 0.25f * par[kp * C + ch];
+        dst[tid * C + ch] = v;
+        g[o * C + ch] = 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  const float* par = lds[1];
+  const int sp = T >> 1;
+  for (int k = tid; k < T * T; k += blockDim.x) {
+    int r = k / T, c = k - r * T;
+    int kp = (r >> 1) * sp + (c >> 1);
+    int64_t o = (int64_t)(by * T + r) * S + bx * T + c;
+    for (int ch = 0; ch < C; ++ch) g[o * C + ch] += 0.25f * par[kp * C + ch];
+  }
+}
+
+static int max_tiles(const MipSet& ms) {
+  int n = 0;
+  for (int k = 0; k < ms.n; ++k) {
+    int T = ms.t[k].size < kMipTile ? ms.t[k].size : kMipTile;
+    int nt = ms.t[k].size / T;
+    n = nt * nt > n ? nt * nt : n;
+  }
+  return n;
+}
+
+static bool has_top(const MipSet& ms) {
+  for (int k = 0; k < ms.n; ++k)
+    if (ms.t[k].levels > kMipTileLevels + 1) return true;
+  return false;
+}
+
+hipError_t launch_mip_build_set(const MipSet& ms, hipStream_t st) {
+  if (ms.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mip_build_tiles, dim3(max_tiles(ms), ms.n), dim3(256), 0, st, ms);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !has_top(ms)) return e;
+  hipLaunchKernelGGL(k_mip_build_top, dim3(ms.n), dim3(256), 0, st, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st) {
+  if (ms.n == 0) return hipSuccess;
+  if (has_top(ms)) {
+    hipLaunchKernelGGL(k_mip_adjoint_top, dim3(ms.n), dim3(256), 0, st, ms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_mip_adjoint_tiles, dim3(max_tiles(ms), ms.n), dim3(256), 0, st, ms);
+  return hipGetLastError();
+}
+
+// RGBA8 chains (read-only maps, built once): one launch per level.
 hipError_t launch_mip_build(const Tex& t, hipStream_t st) {
+  if (t.fmt != ADR_TEX_RGBA8) {
+    MipSet ms{};
+    ms.t[0] = t;
+    ms.n = 1;
+    return launch_mip_build_set(ms, st);
+  }
   for (int l = 1; l < t.levels; ++l) {
     int s = t.size >> l;
     if (s < 1) break;
     int n = s * s;
-    if (t.fmt == ADR_TEX_RGBA8) {
-      hipLaunchKernelGGL(k_mip_down_rgba8, dim3((n + 255) / 256), dim3(256), 0, st,
-                         (uchar4*)t.data, t.off[l - 1], t.off[l], s);
-    } else {
-      hipLaunchKernelGGL(k_mip_down_f32, dim3((n + 255) / 256), dim3(256), 0, st, (float*)t.data,
-                         t.off[l - 1], t.off[l], s, t.channels);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
-// Level l -> l-1: every texel of level l adds a quarter of its gradient to
-// its four children and is cleared.
-__global__ void k_mip_adjoint(float* __restrict__ g, int par_off, int child_off, int s_par, int C) {
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= s_par * s_par) return;
-  int r = idx / s_par, c = idx - r * s_par;
-  int s_ch = 2 * s_par;
-  float* par = g + (int64_t)par_off * C;
-  float* ch = g + (int64_t)child_off * C;
-  int64_t t00 = (int64_t)(2 * r) * s_ch + 2 * c;
-  int64_t kids[4] = {t00, t00 + 1, t00 + s_ch, t00 + s_ch + 1};
-  for (int q = 0; q < C; ++q) {
-    float v = par[(int64_t)idx * C + q];
-    if (v != 0.f) {
-      float w = 0.25f * v;
-      for (int k = 0; k < 4; ++k) ch[kids[k] * C + q] += w;
-      par[(int64_t)idx * C + q] = 0.f;
-    }
-  }
-}
-
-hipError_t launch_mip_adjoint(const Tex& t, float* g, hipStream_t st) {
-  for (int l = t.levels - 1; l >= 1; --l) {
-    int s = t.size >> l;
-    int n = s * s;
-    hipLaunchKernelGGL(k_mip_adjoint, dim3((n + 255) / 256), dim3(256), 0, st, g, t.off[l],
-                       t.off[l - 1], s, t.channels);
+    hipLaunchKernelGGL(k_mip_down_rgba8, dim3((n + 255) / 256), dim3(256), 0, st,
+                       (uchar4*)t.data, t.off[l - 1], t.off[l], s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -228,3 +228,35 @@ def test_mip_chains(ctx):
     lv = R.mip_chain_f32(torch.from_numpy(f.astype(np.float64)))
     exp = np.concatenate([x.reshape(-1, 3).numpy() for x in lv])
     assert np.abs(tf.data.cpu().numpy() - exp).max() < 1e-6
+
+
+@pytest.mark.parametrize("S,levels,C", [(1, 1, 3), (2, 2, 1), (16, 5, 3), (64, 7, 1), (256, 4, 3), (2048, 12, 3)])
+def test_f32_mip_chain_exact(ctx, S, levels, C):
+    # every level the float32 box filter ((a + b) + (c + d)) / 4 of the one
+    # below, bit for bit, for full and partial chains and small maps
+    from paper_2104_03989_amd import adr
+    _say("f32 mips", S, levels, C)
+    f = np.random.default_rng(S + C).uniform(size=(S, S, C)).astype(np.float32)
+    t = adr.DeviceTexture(f, "f32", levels=levels, ctx=ctx)
+    torch.cuda.synchronize()
+    exp = [f]
+    for _ in range(1, levels):
+        x = exp[-1]
+        exp.append(((x[0::2, 0::2] + x[0::2, 1::2]) + (x[1::2, 0::2] + x[1::2, 1::2])) * np.float32(0.25))
+    exp = np.concatenate([x.reshape(-1, C) for x in exp])
+    assert np.array_equal(t.data.cpu().numpy(), exp)
+
+
+def test_precomputed_frame_matches_recomputed(ctx):
+    from paper_2104_03989_amd import adr
+    _say("precomputed frame")
+    w = synth.scaled(synth.workload_paper_loop(map_size=64, ref_nu=40), views=2, res=96)
+    gs = GpuScene(w, ctx)
+    a = gs.render("ref")
+    nrm, tan = gs.ref_mesh.precompute_frame(ctx)
+    b = gs.render("ref")
+    assert np.array_equal(a["image"].cpu().numpy(), b["image"].cpu().numpy())
+    pos = torch.as_tensor(w.ref.mesh.pos, dtype=R.F64)
+    on = R.vertex_normals(pos, torch.as_tensor(w.ref.mesh.tri.astype(np.int64))).numpy()
+    assert np.abs(nrm.cpu().numpy() - on).max() < 1e-6
+    assert np.abs(np.linalg.norm(tan.cpu().numpy(), axis=1) - 1).max() < 1e-5

@@ -84,8 +84,10 @@ def test_tess_adjoint_matches_autograd(ctx):
     g[::7] = 0.0                                   # some vertices without gradient
     g_base = torch.zeros_like(ts.base.pos)
     g_disp = torch.zeros_like(disp.data)
-    adr.tess_bwd(ctx, ts, disp, torch.from_numpy(g.astype(np.float32)).cuda(), g_base, g_disp)
+    g_dev = torch.from_numpy(g.astype(np.float32)).cuda()
+    adr.tess_bwd(ctx, ts, disp, g_dev, g_base, g_disp)
     torch.cuda.synchronize()
+    assert float(g_dev.abs().max()) == 0.0         # the input gradient is consumed
     table = OL.tess_table(w)
     pos = torch.tensor(m.pos, dtype=R.F64, requires_grad=True)
     d = torch.tensor(w.disp.data, dtype=R.F64, requires_grad=True)
