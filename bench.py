@@ -34,7 +34,7 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(w, ctx, adr, torch, np, n_steps, seed):
+def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False):
     """Upload the workload and return (step(t) closure, state)."""
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
     ref_mesh.precompute_frame(ctx)          # the reference does not move
@@ -84,18 +84,19 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed):
         params.append((tex.data[:n0], grads[name][:n0]))
     adam = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
     n_params = sum(p.numel() for p, _ in params)
-    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, views[0])
+    dflag = adr.DETERMINISTIC if det else 0
+    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, views[0], flags=dflag)
     lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_out["image"], loss=w.loss,
-                             flags=adr.FWD_BUILD_MIPS, want_image=False, want_tri_id=True)
+                             flags=adr.FWD_BUILD_MIPS | dflag, want_image=False, want_tri_id=True)
 
     def step(t):
         v = views[t % n_steps]
         if ts is not None:
             adr.tess_fwd(ctx, ts, disp)
-        adr.render_fwd(ctx, ref_mesh, ref_mat, v, outputs=ref_out)
+        adr.render_fwd(ctx, ref_mesh, ref_mat, v, outputs=ref_out, flags=dflag)
         adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_out["image"], loss=w.loss,
-                       flags=adr.FWD_BUILD_MIPS, outputs=lat_out)
-        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads)
+                       flags=adr.FWD_BUILD_MIPS | dflag, outputs=lat_out)
+        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=dflag)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
         lr = w.lr * 10.0 ** (-0.0002 * t)
@@ -284,6 +285,8 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=8, help="views of the oracle's timed step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device copy three times (HBM counter scale) and exit")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="bit-reproducible gradients (fixed-point vertex sums, sorted texel sums)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
@@ -314,7 +317,7 @@ def main():
     B, H, W = w.dirs.shape[0], w.height, w.width
     ctx = adr.Context(0)
     n_steps = args.warmup + args.steps
-    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100))
+    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic)
     torch.cuda.synchronize()
     covered = int((st["lat_out"]["tri_id"] > 0).sum())
     _log(f"warmup {args.warmup}")
@@ -367,6 +370,7 @@ def main():
         "config": {"workload": WORKLOADS[args.workload],
                    "views": B, "res": [W, H], "ref_tris": int(w.ref.mesh.tri.shape[0]),
                    "latent_tris": int(st["lat_mesh"].tri.shape[0]), "params": st["n_params"],
+                   "gradient_mode": "deterministic" if args.deterministic else "atomic",
                    "final_loss": round(loss, 6)},
         "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
     }

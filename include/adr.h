@@ -142,6 +142,14 @@ typedef struct adr_fwd_out {
 
 #define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
 #define ADR_FWD_NO_AA 2          /* skip silhouette antialiasing (image = color) */
+#define ADR_DETERMINISTIC 4      /* fwd and bwd: results identical bit for bit from run to run.
+                                    Vertex-side sums (frame, clip and attribute adjoints, face
+                                    terms) use 64-bit fixed point (2^-40 resolution, |sum| below
+                                    2^23); texel gradients are a segmented reduction: all
+                                    contributions sorted by texel (stable radix sort on a fixed
+                                    emission order) and summed in that order.  Slower; the
+                                    texel path needs 24 + 8 bytes per pixel, map, level and
+                                    corner of scratch. */
 
 /* Render B views of a mesh (Sec. 3 and 5.2): vertex normals and tangents
  * (Sec. 5.1), fixed-point rasterization, perspective-correct interpolation,
@@ -255,9 +263,9 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
  * of launches since the last read, and starts a new window.  Stages:
  * 0 vertex frame, 1 transform, 2 raster, 3 shade, 4 antialias+loss,
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
- * 9 adam, 10 mip build, 11 texel adjoint.  ms and count: host arrays of
- * ADR_N_STAGES. */
-#define ADR_N_STAGES 12
+ * 9 adam, 10 mip build, 11 texel adjoint, 12 buffer clears and
+ * conversions.  ms and count: host arrays of ADR_N_STAGES. */
+#define ADR_N_STAGES 13
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
 

@@ -27,16 +27,16 @@ E_INVALID, E_NOMEM, E_HIP, E_OVER_BUDGET, E_NOTFOUND, E_NONFINITE, E_UNIMPL = -1
 TEX_F32, TEX_RGBA8 = 0, 1
 SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
 LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
-FWD_BUILD_MIPS, FWD_NO_AA = 1, 2
+FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC = 1, 2, 4
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame")
-N_STAGES = 12
+N_STAGES = 13
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
-          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd")
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear")
 
 
 class AdrError(RuntimeError):

@@ -247,7 +247,8 @@ __global__ void k_loss_reduce(const float* __restrict__ partial, int n, float in
 // of its edge is scattered once, by the left (or lower) pixel of the pair.
 __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
                                                 const float* __restrict__ dloss,
-                                                float* __restrict__ gcolor, float* __restrict__ dclip) {
+                                                float* __restrict__ gcolor, float* __restrict__ dclip,
+                                                unsigned long long* __restrict__ fclip) {
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   if (!p.ok) return;
@@ -300,14 +301,21 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       double g_ay = -g_eP * pr.x.bP[0] - g_eQ * pr.x.bQ[0];
       double g_bx = -g_eP * pr.x.aP[1] - g_eQ * pr.x.aQ[1];
       double g_by = g_eP * pr.x.aP[0] + g_eQ * pr.x.aQ[0];
-      float* da = dclip + 4 * ((int64_t)p.b * a.m.n_pos + pr.x.va);
-      float* db = dclip + 4 * ((int64_t)p.b * a.m.n_pos + pr.x.vb);
-      atomicAdd(da + 0, (float)(g_ax * iwa));
-      atomicAdd(da + 1, (float)(g_ay * iwa));
-      atomicAdd(da + 3, (float)(-(g_ax * ax + g_ay * ay) * iwa));
-      atomicAdd(db + 0, (float)(g_bx * iwb));
-      atomicAdd(db + 1, (float)(g_by * iwb));
-      atomicAdd(db + 3, (float)(-(g_bx * bx + g_by * by) * iwb));
+      const int64_t oa = 4 * ((int64_t)p.b * a.m.n_pos + pr.x.va);
+      const int64_t ob = 4 * ((int64_t)p.b * a.m.n_pos + pr.x.vb);
+      const double ga[3] = {g_ax * iwa, g_ay * iwa, -(g_ax * ax + g_ay * ay) * iwa};
+      const double gb[3] = {g_bx * iwb, g_by * iwb, -(g_bx * bx + g_by * by) * iwb};
+      const int comp[3] = {0, 1, 3};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (fclip) {
+          fix_add(fclip + oa + comp[k], ga[k]);
+          fix_add(fclip + ob + comp[k], gb[k]);
+        } else {
+          atomicAdd(dclip + oa + comp[k], (float)ga[k]);
+          atomicAdd(dclip + ob + comp[k], (float)gb[k]);
+        }
+      }
     }
   }
   st3(gcolor, o, gc);
@@ -352,7 +360,8 @@ hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, cons
                          hipStream_t st) {
   AAArgs a = make_aa(m, v, s, vis, color, no_aa);
   int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.dclip);
+  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.dclip,
+                     s.det ? s.fix_clip : nullptr);
   return hipGetLastError();
 }
 

@@ -61,6 +61,8 @@ struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
   Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec;
+  Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
+      det_part;
   adr::JobServer* jobs = nullptr;
   bool prof = false;
   std::vector<Span> spans;
@@ -196,7 +198,7 @@ adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* 
 }
 
 adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool bwd, Scratch& s,
-                           int tex_slots = 0) {
+                           int tex_slots = 0, bool det = false) {
   size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
   size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
   adr_status r;
@@ -211,6 +213,38 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
         (r = ensure(ctx->dattr, V * 36)))
       return r;
     if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
+  }
+  s.det = det;
+  if (det) {
+    if ((r = ensure(ctx->fix_n, V * 24)) || (r = ensure(ctx->fix_t, V * 24))) return r;
+    s.fix_n = (unsigned long long*)ctx->fix_n.p;
+    s.fix_t = (unsigned long long*)ctx->fix_t.p;
+    if (bwd) {
+      if ((r = ensure(ctx->fix_attr, V * 72)) || (r = ensure(ctx->fix_clip, B * V * 32)) ||
+          (r = ensure(ctx->fix_pos, V * 24)))
+        return r;
+      s.fix_attr = (unsigned long long*)ctx->fix_attr.p;
+      s.fix_clip = (unsigned long long*)ctx->fix_clip.p;
+      s.fix_pos = (unsigned long long*)ctx->fix_pos.p;
+      if (tex_slots > 0) {
+        const int64_t E = det_entries(v, tex_slots);
+        if (E >= (int64_t)0xFFFFFFFF) return fail(ADR_E_INVALID, "deterministic mode: view batch too large (%lld texel terms)", (long long)E);
+        const int64_t hw = radix_hist_words(E), tiles = (E + 2047) / 2048;
+        if ((r = ensure(ctx->det_k0, E * 4)) || (r = ensure(ctx->det_v0, E * 4)) || (r = ensure(ctx->det_k1, E * 4)) ||
+            (r = ensure(ctx->det_v1, E * 4)) || (r = ensure(ctx->det_vals, E * 16)) ||
+            (r = ensure(ctx->det_hist, hw * 4)) || (r = ensure(ctx->det_tmp, scan_tmp_words(hw) * 4 + 4)) ||
+            (r = ensure(ctx->det_part, tiles * 32)))
+          return r;
+        s.det_k0 = (uint32_t*)ctx->det_k0.p;
+        s.det_v0 = (uint32_t*)ctx->det_v0.p;
+        s.det_k1 = (uint32_t*)ctx->det_k1.p;
+        s.det_v1 = (uint32_t*)ctx->det_v1.p;
+        s.det_vals = (float4*)ctx->det_vals.p;
+        s.det_hist = (uint32_t*)ctx->det_hist.p;
+        s.det_tmp = (uint32_t*)ctx->det_tmp.p;
+        s.det_part = (float4*)ctx->det_part.p;
+      }
+    }
   }
   s.clip = (double*)ctx->clip.p;
   s.snap = (int*)ctx->snap.p;
@@ -275,7 +309,9 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   adr::jobs_destroy(ctx->jobs);
   ctx->jobs = nullptr;
   (void)hipDeviceSynchronize();
-  Buf* bufs[] = {&ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+  Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
+                 &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
+                 &ctx->det_part, &ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
@@ -300,11 +336,12 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
     if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
   }
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA)) return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC))
+    return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
-  if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  if ((r = prepare_scratch(ctx, m, v, false, s, 0, (flags & ADR_DETERMINISTIC) != 0)) != ADR_OK) return r;
   if (flags & ADR_FWD_BUILD_MIPS) {
     const Tex* maps[3] = {&kd, &nm, &orm};
     int nmaps = mat->model == ADR_SHADE_GGX ? 3 : 2;
@@ -321,7 +358,7 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   }
   TIMED(1, launch_xform(m, v, s, st), "transform");
-  TIMED(2, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
+  TIMED(12, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
   TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
   TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
   TIMED(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
@@ -343,24 +380,36 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (!grads) return fail(ADR_E_INVALID, "grads is NULL");
   if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
   if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA)) return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC))
+    return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  const bool det = (flags & ADR_DETERMINISTIC) != 0;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
-  if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm))) !=
+  if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm), det)) !=
       ADR_OK)
     return r;
+  const int64_t n_clip = 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), n_attr = 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1);
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(1, launch_orient(m, v, s, st), "orientation");
-  TIMED(5, launch_fill_f32(s.dclip, 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), 0.f, st), "clear");
-  TIMED(5, launch_fill_f32(s.dattr, 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1), 0.f, st), "clear");
+  if (det) {
+    TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
+    TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
+  } else {
+    TIMED(12, launch_fill_f32(s.dclip, n_clip, 0.f, st), "clear");
+    TIMED(12, launch_fill_f32(s.dattr, n_attr, 0.f, st), "clear");
+  }
   TIMED(5, launch_aa_bwd(m, v, s, saved->vis, saved->color, saved->dimage, dloss,
                        (flags & ADR_FWD_NO_AA) ? 1 : 0, st),
          "antialias adjoint");
   TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
                             saved->vis, st),
         "shading adjoint");
+  if (det) {
+    TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, st), "fixed point");
+    TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, st), "fixed point");
+  }
   TIMED(11, launch_tex_bwd(v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, st),
         "texel adjoint");
   {

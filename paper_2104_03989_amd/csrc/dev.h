@@ -91,6 +91,21 @@ __device__ __forceinline__ d3 dnormalize_bwd(d3 x, d3 g) {
   return inv * (g - ddot(g, y) * y);
 }
 
+// Deterministic accumulation: a value is scaled by 2^40, rounded to a 64-bit
+// integer and added with an integer atomic; integer (wrap-around) addition
+// does not depend on the order of the additions, so the sum is the same on
+// every run.  Resolution 2^-40 (9.1e-13), range +-2^23 (8.4e6) per sum.
+constexpr double kFixScale = 1099511627776.0;
+__device__ __forceinline__ void fix_add(unsigned long long* p, double v) {
+  atomicAdd(p, (unsigned long long)__double2ll_rn(v * kFixScale));
+}
+__device__ __forceinline__ double fix_val(unsigned long long x) { return (double)(long long)x / kFixScale; }
+__device__ __forceinline__ void fix_add3(unsigned long long* p, int64_t i, d3 v) {
+  fix_add(p + 3 * i, v.x);
+  fix_add(p + 3 * i + 1, v.y);
+  fix_add(p + 3 * i + 2, v.z);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; each XCD
 // has its own L2.  This maps the hardware block id to a logical tile id so
 // that every XCD works through one contiguous range of tiles (neighbouring

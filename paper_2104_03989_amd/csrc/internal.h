@@ -56,6 +56,16 @@ struct Scratch {
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
   float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
   int n_partial;
+  // deterministic mode (fixed-point vertex accumulators, sorted texel sums)
+  bool det;
+  unsigned long long* fix_n;     // [V,3] frame accumulators
+  unsigned long long* fix_t;     // [V,3]
+  unsigned long long* fix_attr;  // [V,9]
+  unsigned long long* fix_clip;  // [B,V,4]
+  unsigned long long* fix_pos;   // [V,3]
+  uint32_t *det_k0, *det_v0, *det_k1, *det_v1, *det_hist, *det_tmp;
+  float4* det_vals;              // [entries]
+  float4* det_part;              // [2 tiles]
 };
 
 // Up to three texture chains (a material's maps) and their gradient buffers.
@@ -97,6 +107,14 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st);
+// Deterministic-mode sizes and helpers.
+int64_t det_entries(const ViewsD& v, int slots);
+int64_t radix_hist_words(int64_t n);
+int64_t scan_tmp_words(int64_t n);
+hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, hipStream_t st);
+
 // Number of texture-gradient slots (maps with a gradient buffer).
 int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm);
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,

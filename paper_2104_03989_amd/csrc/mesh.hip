@@ -37,22 +37,38 @@ __device__ __forceinline__ FaceFrame face_frame(const MeshD& m, int t) {
   return f;
 }
 
-__global__ void k_face_accum(MeshD m, double* __restrict__ nacc, double* __restrict__ tacc) {
+// fn/ft non-null: deterministic mode, fixed-point accumulators.
+__global__ void k_face_accum(MeshD m, double* __restrict__ nacc, double* __restrict__ tacc,
+                             unsigned long long* __restrict__ fn, unsigned long long* __restrict__ ft) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_tri) return;
   FaceFrame f = face_frame(m, t);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     int v = m.tri[3 * t + k];
-    datomic3(nacc, v, f.fn);
-    if (f.tan_ok) datomic3(tacc, v, f.tf);
+    if (fn) {
+      fix_add3(fn, v, f.fn);
+      if (f.tan_ok) fix_add3(ft, v, f.tf);
+    } else {
+      datomic3(nacc, v, f.fn);
+      if (f.tan_ok) datomic3(tacc, v, f.tf);
+    }
   }
 }
 
-__global__ void k_vertex_normalize(int n, const double* __restrict__ nacc, const double* __restrict__ tacc,
-                                   float* __restrict__ nrm, float* __restrict__ tan) {
+__global__ void k_vertex_normalize(int n, double* __restrict__ nacc, double* __restrict__ tacc,
+                                   const unsigned long long* __restrict__ fn,
+                                   const unsigned long long* __restrict__ ft, float* __restrict__ nrm,
+                                   float* __restrict__ tan) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
+  if (fn) {  // the adjoint reads the unnormalised sums as float64
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      nacc[3 * v + k] = fix_val(fn[3 * v + k]);
+      tacc[3 * v + k] = fix_val(ft[3 * v + k]);
+    }
+  }
   d3 a = dnormalize(dld3(nacc, v)), b = dnormalize(dld3(tacc, v));
   st3(nrm, v, mk((float)a.x, (float)a.y, (float)a.z));
   st3(tan, v, mk((float)b.x, (float)b.y, (float)b.z));
@@ -62,6 +78,43 @@ __global__ void k_fill_f64(double* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = 0.0;
+}
+
+__global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0ull;
+}
+
+__global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = (float)fix_val(src[i]);
+}
+
+__global__ void k_fix_add_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] += (float)fix_val(src[i]);
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  return (unsigned)blocks;
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
 }
 
 __global__ void k_fill(float* __restrict__ p, int64_t n, float val) {
@@ -83,16 +136,23 @@ hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st)
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.nacc, n);
-  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.tacc, n);
+  unsigned long long* fn = s.det ? s.fix_n : nullptr;
+  unsigned long long* ft = s.det ? s.fix_t : nullptr;
+  if (s.det) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, fn, n);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, ft, n);
+  } else {
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.nacc, n);
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.tacc, n);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (m.n_tri > 0) {
-    hipLaunchKernelGGL(k_face_accum, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.nacc, s.tacc);
+    hipLaunchKernelGGL(k_face_accum, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.nacc, s.tacc, fn, ft);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_vertex_normalize, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m.n_pos,
-                     s.nacc, s.tacc, s.nrm, s.tan);
+                     s.nacc, s.tacc, fn, ft, s.nrm, s.tan);
   return hipGetLastError();
 }
 
@@ -127,7 +187,8 @@ __global__ void k_vertex_bwd(MeshD m, ViewsD v, const float* __restrict__ dclip,
 }
 
 // Per face: adjoint of the face normal (cross product) and face tangent.
-__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __restrict__ gpos) {
+__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __restrict__ gpos,
+                           unsigned long long* __restrict__ fpos) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_tri) return;
   int i0 = m.tri[3 * t], i1 = m.tri[3 * t + 1], i2 = m.tri[3 * t + 2];
@@ -141,9 +202,16 @@ __global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __re
     g1 = g1 + (f.d2v * inv) * gtf;
     g2 = g2 - (f.d1v * inv) * gtf;
   }
-  fatomic3(gpos, i1, g1);
-  fatomic3(gpos, i2, g2);
-  fatomic3(gpos, i0, dmk(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z)));
+  const d3 g0 = dmk(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z));
+  if (fpos) {
+    fix_add3(fpos, i1, g1);
+    fix_add3(fpos, i2, g2);
+    fix_add3(fpos, i0, g0);
+  } else {
+    fatomic3(gpos, i1, g1);
+    fatomic3(gpos, i2, g2);
+    fatomic3(gpos, i0, g0);
+  }
 }
 
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
@@ -152,7 +220,16 @@ hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, fl
                      s.dattr, s.nacc, s.tacc, gpos, gvnormal);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !gpos || m.n_tri == 0) return e;
-  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos);
+  if (!s.det) {
+    hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos, nullptr);
+    return hipGetLastError();
+  }
+  // deterministic: face terms summed in fixed point, then added once per vertex
+  const int64_t n = 3 * (int64_t)m.n_pos;
+  if ((e = launch_fill_u64(s.fix_pos, n, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos, s.fix_pos);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fix_add_f32, dim3(grid_for(n)), dim3(256), 0, st, s.fix_pos, gpos, n);
   return hipGetLastError();
 }
 

@@ -696,7 +696,9 @@ constexpr int kVtxTable = kVtxAcc * kAccStride;  // floats per wave
 
 __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, bool act, int tri,
                                                     const int* vtx, const float* acc, float* win,
-                                                    float* __restrict__ dclip, float* __restrict__ dattr) {
+                                                    float* __restrict__ dclip, float* __restrict__ dattr,
+                                                    unsigned long long* __restrict__ fclip,
+                                                    unsigned long long* __restrict__ fattr) {
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(act);
   if (!todo) return;
@@ -716,9 +718,10 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
       if (sum != 0.f) {
         int c = lane / 12, comp = lane - 12 * c;
         int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
-        float* dst = comp < 9 ? dattr + 9 * (int64_t)vi + comp
-                              : dclip + 4 * ((int64_t)b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
-        atomicAdd(dst, sum);
+        const int64_t o = comp < 9 ? 9 * (int64_t)vi + comp
+                                   : 4 * ((int64_t)b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
+        if (fattr) fix_add(comp < 9 ? fattr + o : fclip + o, (double)sum);
+        else atomicAdd(comp < 9 ? dattr + o : dclip + o, sum);
       }
     }
   }
@@ -737,7 +740,8 @@ struct TexSlots {
 
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, const float* __restrict__ gcolor,
                                                    float4* __restrict__ rec, float* __restrict__ dclip,
-                                                   float* __restrict__ dattr) {
+                                                   float* __restrict__ dattr, unsigned long long* __restrict__ fclip,
+                                                   unsigned long long* __restrict__ fattr) {
   __shared__ float table_all[4][kVtxTable];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
@@ -762,7 +766,7 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
     }
     rec[o] = make_float4(act ? ts[0].u : 0.f, act ? ts[0].v : 0.f, __uint_as_float(lv), 0.f);
   }
-  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], dclip, dattr);
+  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], dclip, dattr, fclip, fattr);
 }
 
 // Texel-gradient scatter of the recorded samples: a kernel of its own with
@@ -851,12 +855,181 @@ hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Te
   TexSlots sl;
   TexBwdArgs tb;
   make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb);
-  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.dclip, s.dattr);
+  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.dclip, s.dattr,
+                     s.det ? s.fix_clip : nullptr, s.det ? s.fix_attr : nullptr);
+  return hipGetLastError();
+}
+
+// ---- deterministic texel gradients: segmented reduction ----
+//
+// Every (pixel, map, level, corner) contribution is written at a position
+// fixed by those four indices, with its texel as key (texels of the slots'
+// chains numbered one after the other; pixels without it get the key
+// `total`).  A stable radix sort by key groups each texel's contributions in
+// that fixed order; each group is summed in that order: within a tile of
+// 2048 sorted entries by one thread per piece, and a group that crosses tile
+// boundaries by adding its pieces tile after tile.
+
+struct TexDetArgs {
+  TexBwdArgs tb;
+  uint32_t base[4];  // first key of each slot; base[n] = total
+  int64_t E;         // entries = n * P * 8
+};
+
+__global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ idx, float4* __restrict__ vals) {
+  const TexBwdArgs& tb = a.tb;
+  const int64_t P = (int64_t)tb.v.B * tb.v.H * tb.v.W;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= P) return;
+  const float4 r0 = tb.rec[o];
+  const uint32_t lv = __float_as_uint(r0.z);
+  const uint32_t none = a.base[tb.n];
+  for (int k = 0; k < tb.n; ++k) {
+    const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
+    float4 rk = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (l0 != 0xFF) rk = tb.rec[(1 + k) * P + o];
+    const Tex& t = tb.t[k];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const bool on = l0 != 0xFF && (j == 0 || rk.w > 0.f);
+      const float wl = j == 0 ? 1.f - rk.w : rk.w;
+      Foot q = foot_at(t, on ? l0 + j : 0, r0.x, r0.y);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t e = (((int64_t)k * P + o) * 2 + j) * 4 + c;
+        uint32_t key = none;
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (on) {
+          const int r = c & 2 ? q.r1 : q.r0;
+          int cc = c & 1 ? q.c0 + 1 : q.c0;
+          cc = cc >= q.s ? cc - q.s : cc;
+          const float w = wl * (c & 1 ? q.fx : 1.f - q.fx) * (c & 2 ? q.fy : 1.f - q.fy);
+          key = a.base[k] + (uint32_t)(t.off[l0 + j] + r * q.s + cc);
+          val = make_float4(w * rk.x, w * rk.y, w * rk.z, 0.f);
+        }
+        keys[e] = key;
+        idx[e] = (uint32_t)e;
+        vals[e] = val;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void det_store(const TexDetArgs& a, uint32_t key, float4 sum) {
+  int k = 0;
+  while (k + 1 < a.tb.n && key >= a.base[k + 1]) ++k;
+  const Tex& t = a.tb.t[k];
+  float* g = a.tb.g[k] + (int64_t)(key - a.base[k]) * t.channels;
+  g[0] += sum.x;
+  if (t.channels == 3) {
+    g[1] += sum.y;
+    g[2] += sum.z;
+  }
+}
+
+// Pieces of groups within each tile of 2048 sorted entries.  part[2 tile]
+// receives the sum of the tile's first piece when its group began in an
+// earlier tile, part[2 tile + 1] that of its last piece when its group
+// began in this tile and goes on into the next one.
+constexpr int kDetTile = 2048;
+
+__global__ __launch_bounds__(256) void k_tex_det_pieces(TexDetArgs a, const uint32_t* __restrict__ sk,
+                                                        const uint32_t* __restrict__ si,
+                                                        const float4* __restrict__ vals,
+                                                        float4* __restrict__ part) {
+  const int64_t tb0 = (int64_t)blockIdx.x * kDetTile;
+  const int64_t te = min(tb0 + kDetTile, a.E);
+  const uint32_t none = a.base[a.tb.n];
+  for (int64_t i = tb0 + threadIdx.x; i < te; i += blockDim.x) {
+    const uint32_t key = sk[i];
+    if (key >= none) continue;
+    if (i > tb0 && sk[i - 1] == key) continue;  // not the start of a piece
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+    int64_t j = i;
+    for (; j < te && sk[j] == key; ++j) {
+      const float4 v = vals[si[j]];
+      sum.x += v.x;
+      sum.y += v.y;
+      sum.z += v.z;
+    }
+    const bool from_prev = i == tb0 && i > 0 && sk[i - 1] == key;
+    const bool into_next = j == te && te < a.E && sk[te] == key;
+    if (from_prev) part[2 * blockIdx.x] = sum;
+    else if (into_next) part[2 * blockIdx.x + 1] = sum;
+    else det_store(a, key, sum);
+  }
+}
+
+// Groups that cross tiles: started in tile b, continued by the first pieces
+// of the following tiles, added in tile order.
+__global__ __launch_bounds__(256) void k_tex_det_join(TexDetArgs a, const uint32_t* __restrict__ sk,
+                                                      const float4* __restrict__ part, int64_t tiles) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= tiles) return;
+  const int64_t te = min((b + 1) * kDetTile, a.E);
+  if (te >= a.E) return;
+  const uint32_t key = sk[te - 1];
+  if (key >= a.base[a.tb.n] || sk[te] != key) return;
+  // the group must start inside tile b: the keys are sorted, so if the key
+  // before the tile is the same, the whole tile continues an earlier group
+  const int64_t tb0 = b * kDetTile;
+  if (tb0 > 0 && sk[tb0 - 1] == key) return;
+  float4 sum = part[2 * b + 1];
+  for (int64_t c = b + 1; c < tiles; ++c) {
+    const float4 v = part[2 * c];
+    sum.x += v.x;
+    sum.y += v.y;
+    sum.z += v.z;
+    const int64_t ce = min((c + 1) * kDetTile, a.E);
+    if (ce >= a.E || sk[ce] != key) break;
+  }
+  det_store(a, key, sum);
+}
+
+hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                             uint32_t* hist, uint32_t* tmp, bool* in_first, hipStream_t st);
+
+int64_t det_entries(const ViewsD& v, int slots) { return (int64_t)slots * v.B * v.H * v.W * 8; }
+
+hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
+                              float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st) {
+  TexSlots sl;
+  TexDetArgs a{};
+  if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, a.tb) == 0) return hipSuccess;
+  a.tb.rec = s.texrec;
+  a.tb.v = v;
+  uint32_t total = 0;
+  for (int k = 0; k < a.tb.n; ++k) {
+    a.base[k] = total;
+    total += (uint32_t)a.tb.t[k].off[a.tb.t[k].levels];
+  }
+  a.base[a.tb.n] = total;
+  a.E = det_entries(v, a.tb.n);
+  const int64_t P = (int64_t)v.B * v.H * v.W;
+  hipLaunchKernelGGL(k_tex_det_emit, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, a, s.det_k0, s.det_v0,
+                     s.det_vals);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int bits = 1;
+  while (bits < 32 && (1ull << bits) <= total) ++bits;
+  bool first;
+  if ((e = launch_radix_sort(s.det_k0, s.det_v0, s.det_k1, s.det_v1, a.E, bits, s.det_hist, s.det_tmp, &first,
+                             st)) != hipSuccess)
+    return e;
+  const uint32_t* sk = first ? s.det_k0 : s.det_k1;
+  const uint32_t* si = first ? s.det_v0 : s.det_v1;
+  const int64_t tiles = (a.E + kDetTile - 1) / kDetTile;
+  hipLaunchKernelGGL(k_tex_det_pieces, dim3((unsigned)tiles), dim3(256), 0, st, a, sk, si, s.det_vals, s.det_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tex_det_join, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st, a, sk, s.det_part,
+                     tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
                           float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st) {
+  if (s.det) return launch_tex_bwd_det(v, model, kd, nm, orm, gkd, gnm, gorm, s, st);
   TexSlots sl;
   TexBwdArgs tb;
   if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb) == 0) return hipSuccess;

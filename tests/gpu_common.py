@@ -42,13 +42,13 @@ class GpuScene:
         torch.cuda.synchronize()
         return out
 
-    def grads(self, out, names=("pos", "kd", "normal", "orm")):
+    def grads(self, out, names=("pos", "kd", "normal", "orm"), flags=0):
         adr = self.adr
         g = {"pos": torch.zeros_like(self.lat_mesh.pos) if "pos" in names else None}
         for n in ("kd", "normal", "orm"):
             tex = getattr(self.lat_mat, n)
             g[n] = tex.grad_buffer() if (n in names and tex is not None and tex.fmt == adr.TEX_F32) else None
-        adr.render_bwd(self.ctx, self.lat_mesh, self.lat_mat, self.views, out, g)
+        adr.render_bwd(self.ctx, self.lat_mesh, self.lat_mat, self.views, out, g, flags=flags)
         torch.cuda.synchronize()
         res = {}
         for n, t in g.items():
