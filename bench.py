@@ -29,6 +29,85 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Stages whose timing brackets exactly one kernel (roofline candidates), with
+# that kernel and the source files that define it.
+SINGLE_KERNEL_STAGES = {
+    "tex_bwd": ("adr::k_tex_bwd", ["shade.hip"]),
+    "shade_bwd": ("adr::k_shade_bwd", ["shade.hip"]),
+    "aa_bwd": ("adr::k_aa_bwd", ["aa.hip"]),
+    "shade": ("adr::k_shade_fwd", ["shade.hip"]),
+    "adam": ("adr::k_adam", ["adam.hip"]),
+}
+COMMON_SOURCES = ["dev.h", "internal.h"]
+
+
+def kernel_sources_sha(files):
+    """sha256 over a kernel's source files and the shared headers."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2104_03989_amd", "csrc")
+    for f in list(files) + COMMON_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "adr.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(workload, stage):
+    """HBM bytes per launch of a stage's kernel from the committed counter
+    summary, or None if absent or if the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
+    if stage not in SINGLE_KERNEL_STAGES or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    k = d.get("kernels", {}).get(SINGLE_KERNEL_STAGES[stage][0])
+    if not k or k.get("sources_sha256") != kernel_sources_sha(SINGLE_KERNEL_STAGES[stage][1]):
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
+def summarize_pmc(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Writes profiles/pmc_traffic_<workload>.json from rocprofv3 --pmc runs:
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the bench, each scaled by
+    the ratio of known bytes to the same counter on a 1 GiB device copy."""
+    import csv
+    import re
+
+    def load(d, counter):
+        out = {}
+        for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
+            if r["Counter_Name"] != counter:
+                continue
+            n = re.sub(r"\(.*", "", r["Kernel_Name"])
+            out.setdefault(n, []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+
+    def copy_scale(d, counter):
+        v = load(d, counter).get("__amd_rocclr_copyBuffer", [])
+        v = [x for x in v if x > 1e8]
+        return (1 << 30) / (sum(v) / len(v))
+
+    sf, sw = copy_scale(copy_fetch_dir, "FETCH_SIZE"), copy_scale(copy_write_dir, "WRITE_SIZE")
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    kernels = {}
+    for stage, (name, files) in SINGLE_KERNEL_STAGES.items():
+        if name not in fetch or name not in write:
+            continue
+        f = sum(fetch[name]) / len(fetch[name]) * sf
+        w = sum(write[name]) / len(write[name]) * sw
+        kernels[name] = {"stage": stage, "fetch_bytes_per_launch": round(f), "write_bytes_per_launch": round(w),
+                         "hbm_bytes_per_launch": round(f + w), "launches": len(fetch[name]),
+                         "sources_sha256": kernel_sources_sha(files)}
+    out = {"workload": workload, "copy_scale_fetch": round(sf, 4), "copy_scale_write": round(sw, 4),
+           "counters": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch)",
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(path)
+
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -148,24 +227,29 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     return None
 
 
-def cpu_baseline(w, np, torch, views):
-    """The FP64 oracle on one step of the workload (``views`` of its views,
-    full meshes and maps)."""
+def cpu_baseline(w, np, torch, views, min_seconds=10.0, max_steps=4):
+    """The FP64 oracle on whole steps of the workload (``views`` of its
+    views, full meshes and maps), repeated until about min_seconds."""
     from oracle import loop as OL
     from paper_2104_03989_amd import synth
     w1 = synth.scaled(w, views=views)
     t0 = time.perf_counter()
-    mvp32, eye = OL.cameras(w1)
-    ref = OL.reference_image(w1, mvp32, eye)
+    steps = 0
+    state = {}
     params = OL.latent_params(w1)
-    loss, grads, _ = OL.loss_and_grads(w1, ref, mvp32, eye, params)
-    OL.adam_update(params, grads, {}, 1, w1.lr)
+    while steps < max_steps and (steps == 0 or time.perf_counter() - t0 < min_seconds):
+        mvp32, eye = OL.cameras(w1)
+        ref = OL.reference_image(w1, mvp32, eye)
+        loss, grads, _ = OL.loss_and_grads(w1, ref, mvp32, eye, params)
+        new, state = OL.adam_update(params, grads, state, steps + 1, w1.lr)
+        params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in new.items()}
+        steps += 1
     dt = time.perf_counter() - t0
     B = w.dirs.shape[0]
-    return dict(value=round(views * w1.width * w1.height / dt / 1e6, 4), unit="Mpix/s",
+    return dict(value=round(steps * views * w1.width * w1.height / dt / 1e6, 4), unit="Mpix/s",
                 cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{views} of the {B} views of one step at full size: reference render, latent "
-                       "render, loss, backward, Adam", seconds=round(dt, 2))
+                sample=f"{steps} full steps ({views} of the {B} views each, full-size meshes and maps): "
+                       "reference render, latent render, loss, backward, Adam", seconds=round(dt, 2))
 
 
 def serve_pool(n, g):
@@ -287,6 +371,8 @@ def main():
                     help="run a 1 GiB device copy three times (HBM counter scale) and exit")
     ap.add_argument("--deterministic", action="store_true",
                     help="bit-reproducible gradients (fixed-point vertex sums, sorted texel sums)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/pmc_traffic_<workload>.json from rocprofv3 --pmc output and exit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
@@ -301,6 +387,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve(args)
+        return
+    if args.pmc_summary:
+        summarize_pmc(args.workload, *args.pmc_summary)
         return
 
     import numpy as np
@@ -338,25 +427,23 @@ def main():
     loss = float(st["lat_out"]["loss"][0])
     ms_step = dt / args.steps * 1e3
     mpix = B * H * W * args.steps / dt / 1e6
-    # dominant stage and its roofline
+    # the dominant single-kernel stage and its roofline
     roof = None
     prof, stage_step = {}, {}
     if stages:
         prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1] > 0}
         per_step = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
         stage_step = {k: round(v, 4) for k, v in per_step.items()}
-        dom = max(per_step, key=per_step.get)
+        cands = {k: v for k, v in per_step.items() if k in SINGLE_KERNEL_STAGES}
+        dom = max(cands, key=cands.get)
         ms, cnt = stages[dom]
         avg_ms = ms / cnt
         by = algorithmic_bytes(dom, w, st, covered)
-        if by is not None:
-            ach = by / (avg_ms * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                    "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": by}
-        else:
-            roof = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": None, "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+        ach = by / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": SINGLE_KERNEL_STAGES[dom][0], "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": pmc_traffic(args.workload, dom), "avg_launch_ms": round(avg_ms, 4),
+                "bytes_per_launch": by}
     cpu = None
     if not args.no_cpu_baseline:
         _log("oracle baseline")

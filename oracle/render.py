@@ -19,7 +19,7 @@ this module.  It shares no code with the GPU path.  The forward pass is
 written out in float64 torch CPU ops; the backward pass is torch autograd of
 that forward pass, i.e. the exact derivative of the function defined here.
 
-Readings taken where the paper is silent (also listed in the design doc):
+Readings taken where the paper is silent:
   * visibility: the integer rules R1-R6 in raster.c;
   * camera: look-at from dist * dir to the origin, up +y (or +z when the view
     direction is within 0.999 of +-y), OpenGL perspective with near 0.1 and
