@@ -113,7 +113,7 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False):
+def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False):
     """Upload the workload and return (step(t) closure, state)."""
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
     ref_mesh.precompute_frame(ctx)          # the reference does not move
@@ -168,6 +168,22 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False):
     lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_out["image"], loss=w.loss,
                              flags=adr.FWD_BUILD_MIPS | dflag, want_image=False, want_tri_id=True)
 
+    # uniform Laplacian regularizer (absolute form: the latent starts as a
+    # resampled sphere), lambda_0 by the heuristic, then the recursive decay
+    lap = None
+    if laplacian:
+        base = ts.base if ts is not None else lat_mesh
+        ring = adr.DeviceOneRing(base.tri.cpu().numpy(), base.pos.shape[0])
+        ld = torch.zeros(1, device="cuda")
+        adr.laplacian(ctx, ring, base.pos, loss=ld)
+        torch.cuda.synchronize()
+        lam0 = 0.25 * float(lat_out["loss"][0]) / max(float(ld[0]), 1e-30)
+        lams = [lam0]
+        for i in range(1, n_steps):
+            lams.append((lams[-1] - 0.02 * lam0) * 10.0 ** (-1e-6 * i) + 0.02 * lam0)
+        g_lap = g_base if ts is not None else grads["pos"]
+        lap = (ring, base, lams, g_lap)
+
     def step(t):
         v = views[t % n_steps]
         if ts is not None:
@@ -178,6 +194,9 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False):
         adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=dflag)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
+        if lap is not None:
+            ring, base, lams, g_lap = lap
+            adr.laplacian(ctx, ring, base.pos, None, lams[t % n_steps], g_pos=g_lap)
         lr = w.lr * 10.0 ** (-0.0002 * t)
         adr.adam_step(ctx, adam, t + 1, lr)
 
@@ -373,6 +392,8 @@ def main():
                     help="bit-reproducible gradients (fixed-point vertex sums, sorted texel sums)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/pmc_traffic_<workload>.json from rocprofv3 --pmc output and exit")
+    ap.add_argument("--laplacian", action="store_true",
+                    help="add the uniform Laplacian regularizer with the heuristic lambda_0 and its schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
@@ -406,7 +427,8 @@ def main():
     B, H, W = w.dirs.shape[0], w.height, w.width
     ctx = adr.Context(0)
     n_steps = args.warmup + args.steps
-    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic)
+    step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic,
+                          laplacian=args.laplacian)
     torch.cuda.synchronize()
     covered = int((st["lat_out"]["tri_id"] > 0).sum())
     _log(f"warmup {args.warmup}")
@@ -458,6 +480,7 @@ def main():
                    "views": B, "res": [W, H], "ref_tris": int(w.ref.mesh.tri.shape[0]),
                    "latent_tris": int(st["lat_mesh"].tri.shape[0]), "params": st["n_params"],
                    "gradient_mode": "deterministic" if args.deterministic else "atomic",
+                   "laplacian": bool(args.laplacian),
                    "final_loss": round(loss, 6)},
         "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
     }

@@ -257,6 +257,32 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
                         const adr_texture* disp, float* g_pos_out, float* g_base_pos,
                         float* g_disp, adr_stream stream);
 
+/* ------------------------------------------------ Laplacian regularizer */
+
+/* One-ring neighbour lists (CSR) of a mesh's position vertices, device. */
+typedef struct adr_one_ring {
+  const int32_t* offs;           /* [n_pos + 1] */
+  const int32_t* nbr;            /* [offs[n_pos]] neighbours of vertex i in offs[i]..offs[i+1], ascending */
+  int32_t n_pos;
+} adr_one_ring;
+
+/* Host: the one-ring (vertices sharing an edge) of every vertex, sorted
+ * ascending.  offs: host [n_pos + 1]; nbr: host array of at least the count
+ * (at most 6 n_tri), or NULL to only count; *n_nbr receives the count.
+ * ADR_E_INVALID on out-of-range indices. */
+adr_status adr_mesh_one_ring(const int32_t* tri, int32_t n_tri, int32_t n_pos, int32_t* offs, int32_t* nbr,
+                             int64_t* n_nbr);
+
+/* Uniform Laplacian regularizer (Sec. 5.3, "Objective function"):
+ * delta_i = v_i - mean of its one-ring, L = (1/n) sum |delta_i - delta_ref_i|^2
+ * (delta_ref NULL: absolute, delta_ref = 0).  Optional outputs (device):
+ * delta_out [n_pos,3] receives delta (e.g. of the initial mesh, for the
+ * relative form), loss [1] receives L, g_pos [n_pos,3] is accumulated with
+ * lambda dL/dpos.  pos, delta_ref: device [n_pos,3].  The adjoint is a gather
+ * over the one-ring (no atomics).  Device work on `stream`. */
+adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* pos, const float* delta_ref,
+                         float lambda, float* delta_out, float* loss, float* g_pos, adr_stream stream);
+
 /* Stage timing.  When enabled, every render/adam call brackets each of its
  * kernel stages with HIP events on the call's stream; adr_ctx_profile_read
  * waits for them, returns per stage the summed milliseconds and the number

@@ -33,7 +33,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
-           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame")
+           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian")
 N_STAGES = 13
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear")
@@ -84,6 +84,10 @@ class Tess_(C.Structure):
     _fields_ = [("vidx", P), ("w", P), ("duv", P), ("n_vert", I32)]
 
 
+class OneRing_(C.Structure):
+    _fields_ = [("offs", P), ("nbr", P), ("n_pos", I32)]
+
+
 class JobDesc_(C.Structure):
     _fields_ = [("ref_pos", P), ("ref_tri", P), ("ref_uv", P), ("ref_uv_tri", P),
                 ("ref_n_pos", I32), ("ref_n_tri", I32), ("ref_n_uv", I32), ("model", I32),
@@ -128,6 +132,8 @@ _lib.adr_job_submit.argtypes = [P, C.POINTER(JobDesc_), C.POINTER(C.c_uint64)]
 _lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(JobResult_)]
 _lib.adr_ctx_profile.argtypes = [P, I32]
 _lib.adr_ctx_profile_read.argtypes = [P, P, P]
+_lib.adr_mesh_one_ring.argtypes = [P, I32, I32, P, P, P]
+_lib.adr_laplacian.argtypes = [P, C.POINTER(OneRing_), P, P, C.c_float, P, P, P, P]
 _lib.adr_mesh_frame.argtypes = [P, C.POINTER(Mesh_), P, P, P]
 _lib.adr_tess_counts.argtypes = [P, I32, I32, I32, P, P, P]
 _lib.adr_tess_build.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P, P, P, P]
@@ -534,3 +540,36 @@ def tess_bwd(ctx: Context, ts: DeviceTess, disp: DeviceTexture, g_pos, g_base_po
     d = disp.struct()
     _check(_lib.adr_tess_bwd(ctx.h, C.byref(b), C.byref(t), C.byref(d), _ptr(g_pos), _ptr(g_base_pos),
                              _ptr(g_disp), _stream(stream)))
+
+
+# ---------------------------------------------------------------- Laplacian regularizer
+
+def mesh_one_ring(tri: np.ndarray, n_pos: int):
+    """Host CSR (offs [n_pos+1], nbr) of the sorted one-rings."""
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    offs = np.zeros(n_pos + 1, np.int32)
+    n = C.c_int64()
+    _check(_lib.adr_mesh_one_ring(_ptr(tri), tri.shape[0], n_pos, _ptr(offs), None, C.byref(n)))
+    nbr = np.zeros(max(n.value, 1), np.int32)
+    _check(_lib.adr_mesh_one_ring(_ptr(tri), tri.shape[0], n_pos, _ptr(offs), _ptr(nbr), C.byref(n)))
+    return offs, nbr[:n.value]
+
+
+class DeviceOneRing:
+    def __init__(self, tri: np.ndarray, n_pos: int, device="cuda"):
+        offs, nbr = mesh_one_ring(tri, n_pos)
+        self.offs = torch.from_numpy(offs).to(device)
+        self.nbr = torch.from_numpy(nbr if nbr.size else np.zeros(1, np.int32)).to(device)
+        self.n_pos = n_pos
+
+    def struct(self):
+        return OneRing_(self.offs.data_ptr(), self.nbr.data_ptr(), self.n_pos)
+
+
+def laplacian(ctx: Context, ring: DeviceOneRing, pos, delta_ref=None, lam: float = 1.0, delta_out=None,
+              loss=None, g_pos=None, stream=None):
+    """Uniform Laplacian regularizer (Sec. 5.3): optional delta, loss and
+    g_pos += lam dL/dpos outputs (device tensors)."""
+    r = ring.struct()
+    _check(_lib.adr_laplacian(ctx.h, C.byref(r), _ptr(pos), _ptr(delta_ref), float(lam), _ptr(delta_out),
+                              _ptr(loss), _ptr(g_pos), _stream(stream)))

@@ -8,6 +8,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <cmath>
+
 #include "internal.h"
 #include "jobs.h"
 
@@ -62,7 +64,7 @@ struct adr_ctx {
   uint64_t budget = 0;
   Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
-      det_part;
+      det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
   bool prof = false;
   std::vector<Span> spans;
@@ -311,7 +313,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
-                 &ctx->det_part, &ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
@@ -519,6 +521,25 @@ adr_status adr_mesh_frame(adr_ctx* ctx, const adr_mesh* mesh, float* nrm_out, fl
   s.nrm = nrm_out;
   s.tan = tan_out;
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  return ADR_OK;
+}
+
+adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* pos, const float* delta_ref,
+                         float lambda, float* delta_out, float* loss, float* g_pos, adr_stream stream) {
+  if (!ctx || !ring) return fail(ADR_E_INVALID, "ctx and ring are required");
+  const int n = ring->n_pos;
+  if (n < 0) return fail(ADR_E_INVALID, "negative vertex count");
+  if (n > 0 && (!ring->offs || !ring->nbr || !pos)) return fail(ADR_E_INVALID, "ring offs/nbr and pos are required");
+  if (!std::isfinite(lambda)) return fail(ADR_E_INVALID, "lambda is not finite");
+  if (n == 0) return ADR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  adr_status r;
+  if ((r = ensure(ctx->lap_r, (size_t)n * 12)) || (r = ensure(ctx->lap_part, (size_t)((n + 255) / 256) * 8)))
+    return r;
+  TIMED(8, launch_laplacian(n, pos, ring->offs, ring->nbr, delta_ref, lambda, (float*)ctx->lap_r.p,
+                            (double*)ctx->lap_part.p, delta_out, loss, g_pos, st),
+        "laplacian");
   return ADR_OK;
 }
 

@@ -107,6 +107,10 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st);
+hipError_t launch_laplacian(int n, const float* pos, const int* offs, const int* nbr, const float* dref,
+                            float lambda, float* r, double* part, float* dout, float* loss, float* gpos,
+                            hipStream_t st);
+
 // Deterministic-mode sizes and helpers.
 int64_t det_entries(const ViewsD& v, int slots);
 int64_t radix_hist_words(int64_t n);
