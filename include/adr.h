@@ -142,6 +142,11 @@ typedef struct adr_fwd_out {
 
 #define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
 #define ADR_FWD_NO_AA 2          /* skip silhouette antialiasing (image = color) */
+#define ADR_INDEPENDENT_MIPS 8   /* every mip level of the F32 maps is its own latent variable
+                                    (Sec. 4.2): bwd leaves each level's gradient in place (no
+                                    mip adjoint), so levels >= 1 of the gradients are outputs and
+                                    Adam runs over whole chains; fwd rejects it together with
+                                    ADR_FWD_BUILD_MIPS */
 #define ADR_DETERMINISTIC 4      /* fwd and bwd: results identical bit for bit from run to run.
                                     Vertex-side sums (frame, clip and attribute adjoints, face
                                     terms) use 64-bit fixed point (2^-40 resolution, |sum| below
@@ -166,7 +171,8 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
  * (+=).  Map gradients use the full mip-chain layout of their texture:
  * level 0 receives the gradient w.r.t. the level-0 texels (coarser levels
  * being box averages of level 0), levels 1.. are scratch that must be zero
- * on entry and are left zero. */
+ * on entry and are left zero; with ADR_INDEPENDENT_MIPS every level receives
+ * the gradient w.r.t. its own texels. */
 typedef struct adr_grads {
   float* pos;                    /* [n_pos,3] nullable */
   float* vnormal;                /* [n_pos,3] nullable: OVERWRITTEN with dL/d(smooth vertex

@@ -23,7 +23,7 @@ def cameras(w):
 
 
 def _levels(tex, param=None):
-    return R.texture_levels(tex.data, tex.fmt, param)
+    return R.texture_levels(tex.data, tex.fmt, param, getattr(tex, "chain", None))
 
 
 def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True, frozen=None):
@@ -91,7 +91,8 @@ def latent_params(w):
         else:
             tex = getattr(s, name)
             assert tex.fmt == "f32", "only float32 maps are optimised"
-            out[name] = torch.tensor(tex.data, dtype=R.F64, requires_grad=True)
+            src = tex.chain if getattr(tex, "chain", None) is not None else tex.data
+            out[name] = torch.tensor(src, dtype=R.F64, requires_grad=True)
     return out
 
 

@@ -482,11 +482,22 @@ def _t(x, dtype=F64):
     return torch.as_tensor(np.asarray(x), dtype=dtype)
 
 
-def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = None):
+def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = None, chain=None):
     """Mip chain of a map; ``param`` (float64 level 0) replaces the data when
-    the map is being differentiated."""
+    the map is being differentiated.  With ``chain`` (all levels,
+    level-major [N,C]) the levels are independent variables (Sec. 4.2) and
+    ``param``, if given, is that whole chain."""
     if fmt == "rgba8":
         return mip_chain_rgba8(tex_data)
+    if chain is not None:
+        flat = param if param is not None else _t(chain)
+        S = tex_data.shape[0]
+        out, off = [], 0
+        for l in range(int(math.log2(S)) + 1):
+            s = S >> l
+            out.append(flat[off:off + s * s].reshape(s, s, flat.shape[1]))
+            off += s * s
+        return out
     base = param if param is not None else _t(tex_data)
     return mip_chain_f32(base)
 

@@ -27,7 +27,7 @@ E_INVALID, E_NOMEM, E_HIP, E_OVER_BUDGET, E_NOTFOUND, E_NONFINITE, E_UNIMPL = -1
 TEX_F32, TEX_RGBA8 = 0, 1
 SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
 LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
-FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC = 1, 2, 4
+FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC, INDEPENDENT_MIPS = 1, 2, 4, 8
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
@@ -221,7 +221,7 @@ class DeviceTexture:
     """A square texture with its mip chain in one device tensor."""
 
     def __init__(self, level0: np.ndarray, fmt: str, device="cuda", levels: int | None = None,
-                 ctx: Context | None = None):
+                 ctx: Context | None = None, chain: np.ndarray | None = None):
         S = level0.shape[0]
         assert level0.shape[1] == S and S & (S - 1) == 0, "square power-of-two texture"
         self.size = S
@@ -236,7 +236,11 @@ class DeviceTexture:
             self.channels = level0.shape[2]
             self.data = torch.zeros(n, self.channels, dtype=torch.float32, device=device)
             self.data[:S * S] = torch.from_numpy(np.ascontiguousarray(level0, dtype=np.float32).reshape(-1, self.channels))
-        if ctx is not None and self.levels > 1:
+        if chain is not None:
+            # independent mip levels (Sec. 4.2): every level given
+            assert self.fmt == TEX_F32 and chain.shape == (n, self.channels)
+            self.data.copy_(torch.from_numpy(np.ascontiguousarray(chain, dtype=np.float32)))
+        elif ctx is not None and self.levels > 1:
             mip_build(ctx, self)
 
     @property
@@ -281,9 +285,10 @@ class DeviceMesh:
 class DeviceMaterial:
     def __init__(self, scene, device="cuda", ctx: Context | None = None):
         self.model = SHADE_GGX if scene.model == "ggx" else SHADE_BLINN_PHONG
-        self.kd = DeviceTexture(scene.kd.data, scene.kd.fmt, device, ctx=ctx)
-        self.normal = DeviceTexture(scene.normal.data, scene.normal.fmt, device, ctx=ctx)
-        self.orm = DeviceTexture(scene.orm.data, scene.orm.fmt, device, ctx=ctx) if scene.orm is not None else None
+        tex = lambda t: DeviceTexture(t.data, t.fmt, device, ctx=ctx, chain=getattr(t, "chain", None))
+        self.kd = tex(scene.kd)
+        self.normal = tex(scene.normal)
+        self.orm = tex(scene.orm) if scene.orm is not None else None
 
     def struct(self):
         orm = self.orm.struct() if self.orm is not None else Texture_()

@@ -247,8 +247,8 @@ __global__ void k_loss_reduce(const float* __restrict__ partial, int n, float in
 // of its edge is scattered once, by the left (or lower) pixel of the pair.
 __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
                                                 const float* __restrict__ dloss,
-                                                float* __restrict__ gcolor, float* __restrict__ dclip,
-                                                unsigned long long* __restrict__ fclip) {
+                                                float* __restrict__ gcolor,
+                                                unsigned long long* __restrict__ fclip, bool det) {
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   if (!p.ok) return;
@@ -308,13 +308,8 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       const int comp[3] = {0, 1, 3};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        if (fclip) {
-          fix_add(fclip + oa + comp[k], ga[k]);
-          fix_add(fclip + ob + comp[k], gb[k]);
-        } else {
-          atomicAdd(dclip + oa + comp[k], (float)ga[k]);
-          atomicAdd(dclip + ob + comp[k], (float)gb[k]);
-        }
+        acc_add(fclip + oa + comp[k], ga[k], det);
+        acc_add(fclip + ob + comp[k], gb[k], det);
       }
     }
   }
@@ -360,8 +355,7 @@ hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, cons
                          hipStream_t st) {
   AAArgs a = make_aa(m, v, s, vis, color, no_aa);
   int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.dclip,
-                     s.det ? s.fix_clip : nullptr);
+  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.fix_clip, s.det);
   return hipGetLastError();
 }
 

@@ -217,17 +217,19 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
     if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
   }
   s.det = det;
+  if (bwd) {
+    if ((r = ensure(ctx->fix_attr, V * 72)) || (r = ensure(ctx->fix_clip, B * V * 32)) ||
+        (r = ensure(ctx->fix_pos, V * 24)))
+      return r;
+    s.fix_attr = (unsigned long long*)ctx->fix_attr.p;
+    s.fix_clip = (unsigned long long*)ctx->fix_clip.p;
+    s.fix_pos = (unsigned long long*)ctx->fix_pos.p;
+  }
   if (det) {
     if ((r = ensure(ctx->fix_n, V * 24)) || (r = ensure(ctx->fix_t, V * 24))) return r;
     s.fix_n = (unsigned long long*)ctx->fix_n.p;
     s.fix_t = (unsigned long long*)ctx->fix_t.p;
     if (bwd) {
-      if ((r = ensure(ctx->fix_attr, V * 72)) || (r = ensure(ctx->fix_clip, B * V * 32)) ||
-          (r = ensure(ctx->fix_pos, V * 24)))
-        return r;
-      s.fix_attr = (unsigned long long*)ctx->fix_attr.p;
-      s.fix_clip = (unsigned long long*)ctx->fix_clip.p;
-      s.fix_pos = (unsigned long long*)ctx->fix_pos.p;
       if (tex_slots > 0) {
         const int64_t E = det_entries(v, tex_slots);
         if (E >= (int64_t)0xFFFFFFFF) return fail(ADR_E_INVALID, "deterministic mode: view batch too large (%lld texel terms)", (long long)E);
@@ -338,8 +340,10 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
     if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
   }
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC))
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if ((flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
+    return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
@@ -382,7 +386,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (!grads) return fail(ADR_E_INVALID, "grads is NULL");
   if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
   if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC))
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   const bool det = (flags & ADR_DETERMINISTIC) != 0;
   hipStream_t st = (hipStream_t)stream;
@@ -395,23 +399,16 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(1, launch_orient(m, v, s, st), "orientation");
-  if (det) {
-    TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
-    TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
-  } else {
-    TIMED(12, launch_fill_f32(s.dclip, n_clip, 0.f, st), "clear");
-    TIMED(12, launch_fill_f32(s.dattr, n_attr, 0.f, st), "clear");
-  }
+  TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
+  TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
   TIMED(5, launch_aa_bwd(m, v, s, saved->vis, saved->color, saved->dimage, dloss,
                        (flags & ADR_FWD_NO_AA) ? 1 : 0, st),
          "antialias adjoint");
   TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
                             saved->vis, st),
         "shading adjoint");
-  if (det) {
-    TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, st), "fixed point");
-    TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, st), "fixed point");
-  }
+  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, det, st), "accumulator conversion");
+  TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, det, st), "accumulator conversion");
   TIMED(11, launch_tex_bwd(v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, st),
         "texel adjoint");
   {
@@ -423,7 +420,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
         ms.t[ms.n] = *maps[k];
         ms.g[ms.n++] = gs[k];
       }
-    TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+    if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
   }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
     TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");

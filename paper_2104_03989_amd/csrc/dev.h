@@ -106,6 +106,22 @@ __device__ __forceinline__ void fix_add3(unsigned long long* p, int64_t i, d3 v)
   fix_add(p + 3 * i + 2, v.z);
 }
 
+// Vertex-side adjoint accumulators: 8-byte slots holding fixed point in
+// deterministic mode and float64 otherwise (float32 sums of per-pixel terms
+// cancel badly where the tangent frame is ill-conditioned, e.g. at UV poles).
+__device__ __forceinline__ void acc_add(unsigned long long* p, double v, bool det) {
+  if (det) fix_add(p, v);
+  else atomicAdd(reinterpret_cast<double*>(p), v);
+}
+__device__ __forceinline__ void acc_add3(unsigned long long* p, int64_t i, d3 v, bool det) {
+  acc_add(p + 3 * i, v.x, det);
+  acc_add(p + 3 * i + 1, v.y, det);
+  acc_add(p + 3 * i + 2, v.z, det);
+}
+__device__ __forceinline__ double acc_val(unsigned long long x, bool det) {
+  return det ? fix_val(x) : __longlong_as_double((long long)x);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; each XCD
 // has its own L2.  This maps the hardware block id to a logical tile id so
 // that every XCD works through one contiguous range of tiles (neighbouring

@@ -56,9 +56,10 @@ struct Scratch {
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
   float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
   int n_partial;
-  // deterministic mode (fixed-point vertex accumulators, sorted texel sums)
+  // vertex-side adjoint accumulators (float64, or fixed point in
+  // deterministic mode) and the deterministic mode's sort buffers
   bool det;
-  unsigned long long* fix_n;     // [V,3] frame accumulators
+  unsigned long long* fix_n;     // [V,3] frame accumulators (deterministic mode)
   unsigned long long* fix_t;     // [V,3]
   unsigned long long* fix_attr;  // [V,9]
   unsigned long long* fix_clip;  // [B,V,4]
@@ -117,7 +118,7 @@ int64_t radix_hist_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
-hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, hipStream_t st);
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st);
 
 // Number of texture-gradient slots (maps with a gradient buffer).
 int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm);

@@ -86,16 +86,18 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
   for (; i < n; i += stride) p[i] = 0ull;
 }
 
-__global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n) {
+__global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
+                             bool det) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = (float)fix_val(src[i]);
+  for (; i < n; i += stride) dst[i] = (float)acc_val(src[i], det);
 }
 
-__global__ void k_fix_add_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n) {
+__global__ void k_fix_add_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
+                              bool det) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] += (float)fix_val(src[i]);
+  for (; i < n; i += stride) dst[i] += (float)acc_val(src[i], det);
 }
 
 static unsigned grid_for(int64_t n) {
@@ -111,9 +113,9 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, hipStream_t st) {
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n);
+  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n, det);
   return hipGetLastError();
 }
 
@@ -187,8 +189,8 @@ __global__ void k_vertex_bwd(MeshD m, ViewsD v, const float* __restrict__ dclip,
 }
 
 // Per face: adjoint of the face normal (cross product) and face tangent.
-__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __restrict__ gpos,
-                           unsigned long long* __restrict__ fpos) {
+__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, unsigned long long* __restrict__ fpos,
+                           bool det) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= m.n_tri) return;
   int i0 = m.tri[3 * t], i1 = m.tri[3 * t + 1], i2 = m.tri[3 * t + 2];
@@ -203,15 +205,9 @@ __global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, float* __re
     g2 = g2 - (f.d1v * inv) * gtf;
   }
   const d3 g0 = dmk(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z));
-  if (fpos) {
-    fix_add3(fpos, i1, g1);
-    fix_add3(fpos, i2, g2);
-    fix_add3(fpos, i0, g0);
-  } else {
-    fatomic3(gpos, i1, g1);
-    fatomic3(gpos, i2, g2);
-    fatomic3(gpos, i0, g0);
-  }
+  acc_add3(fpos, i1, g1, det);
+  acc_add3(fpos, i2, g2, det);
+  acc_add3(fpos, i0, g0, det);
 }
 
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
@@ -220,16 +216,13 @@ hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, fl
                      s.dattr, s.nacc, s.tacc, gpos, gvnormal);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !gpos || m.n_tri == 0) return e;
-  if (!s.det) {
-    hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos, nullptr);
-    return hipGetLastError();
-  }
-  // deterministic: face terms summed in fixed point, then added once per vertex
+  // face terms summed in float64 (fixed point in deterministic mode), then
+  // added once per vertex
   const int64_t n = 3 * (int64_t)m.n_pos;
   if ((e = launch_fill_u64(s.fix_pos, n, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, gpos, s.fix_pos);
+  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, s.fix_pos, s.det);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fix_add_f32, dim3(grid_for(n)), dim3(256), 0, st, s.fix_pos, gpos, n);
+  hipLaunchKernelGGL(k_fix_add_f32, dim3(grid_for(n)), dim3(256), 0, st, s.fix_pos, gpos, n, s.det);
   return hipGetLastError();
 }
 

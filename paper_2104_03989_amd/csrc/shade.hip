@@ -696,9 +696,8 @@ constexpr int kVtxTable = kVtxAcc * kAccStride;  // floats per wave
 
 __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, bool act, int tri,
                                                     const int* vtx, const float* acc, float* win,
-                                                    float* __restrict__ dclip, float* __restrict__ dattr,
                                                     unsigned long long* __restrict__ fclip,
-                                                    unsigned long long* __restrict__ fattr) {
+                                                    unsigned long long* __restrict__ fattr, bool det) {
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(act);
   if (!todo) return;
@@ -720,8 +719,7 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
         int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
         const int64_t o = comp < 9 ? 9 * (int64_t)vi + comp
                                    : 4 * ((int64_t)b * a.m.n_pos + vi) + (comp == 11 ? 3 : comp - 9);
-        if (fattr) fix_add(comp < 9 ? fattr + o : fclip + o, (double)sum);
-        else atomicAdd(comp < 9 ? dattr + o : dclip + o, sum);
+        acc_add(comp < 9 ? fattr + o : fclip + o, (double)sum, det);
       }
     }
   }
@@ -739,9 +737,8 @@ struct TexSlots {
 };
 
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, const float* __restrict__ gcolor,
-                                                   float4* __restrict__ rec, float* __restrict__ dclip,
-                                                   float* __restrict__ dattr, unsigned long long* __restrict__ fclip,
-                                                   unsigned long long* __restrict__ fattr) {
+                                                   float4* __restrict__ rec, unsigned long long* __restrict__ fclip,
+                                                   unsigned long long* __restrict__ fattr, bool det) {
   __shared__ float table_all[4][kVtxTable];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
@@ -766,7 +763,7 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
     }
     rec[o] = make_float4(act ? ts[0].u : 0.f, act ? ts[0].v : 0.f, __uint_as_float(lv), 0.f);
   }
-  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], dclip, dattr, fclip, fattr);
+  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], fclip, fattr, det);
 }
 
 // Texel-gradient scatter of the recorded samples: a kernel of its own with
@@ -855,8 +852,8 @@ hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Te
   TexSlots sl;
   TexBwdArgs tb;
   make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb);
-  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.dclip, s.dattr,
-                     s.det ? s.fix_clip : nullptr, s.det ? s.fix_attr : nullptr);
+  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip, s.fix_attr,
+                     s.det);
   return hipGetLastError();
 }
 

@@ -281,9 +281,12 @@ class Mesh:
 
 @dataclasses.dataclass
 class Texture:
-    """Level-0 texel data; rows are v, columns are u."""
+    """Level-0 texel data; rows are v, columns are u.  ``chain``: for a map
+    whose mip levels are independent latent variables, all levels
+    (level-major, [sum_l (S>>l)^2, C] float32); None: levels derived."""
     data: np.ndarray     # [S,S,C] float32, or [S,S,4] uint8 for RGBA8
     fmt: str             # "f32" or "rgba8"
+    chain: np.ndarray | None = None
 
 
 @dataclasses.dataclass
@@ -326,6 +329,17 @@ def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> 
 
 def _f32(x):
     return Texture(np.ascontiguousarray(x, dtype=np.float32), "f32")
+
+
+def independent_chain(size: int, channels: int, seed: int, lo: float = 0.0, hi: float = 1.0) -> Texture:
+    """A map whose every mip level is its own seeded value-noise map in
+    [lo, hi) (4x4 lattice cells; a different seed per level)."""
+    levels = []
+    for l in range(int(np.log2(size)) + 1):
+        s = size >> l
+        levels.append((lo + (hi - lo) * value_noise_map(s, channels, seed * 64 + l, cells=4)).reshape(-1, channels))
+    chain = np.concatenate(levels).astype(np.float32)
+    return Texture(chain[:size * size].reshape(size, size, channels).copy(), "f32", chain)
 
 
 def workload_plain_step(views: int = 4, res: int = 256, map_size: int = 256,
