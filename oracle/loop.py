@@ -26,7 +26,7 @@ def _levels(tex, param=None):
     return R.texture_levels(tex.data, tex.fmt, param, getattr(tex, "chain", None))
 
 
-def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True, frozen=None):
+def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True, frozen=None, msaa=1):
     params = params or {}
     if pos is None:
         pos = torch.as_tensor(scene.mesh.pos, dtype=R.F64)
@@ -35,7 +35,8 @@ def render_scene(scene, mvp32, eye, w, pos=None, params=None, aa=True, frozen=No
     orm = _levels(scene.orm, params.get("orm")) if scene.orm is not None else None
     return R.render(scene.mesh, scene.model, kd, nm, orm, pos, mvp32,
                     np.asarray(eye, dtype=np.float64), np.asarray(w.light_dir, dtype=np.float64),
-                    np.asarray(w.light_rgb, dtype=np.float64), w.width, w.height, aa=aa, frozen=frozen)
+                    np.asarray(w.light_rgb, dtype=np.float64), w.width, w.height, aa=aa, frozen=frozen,
+                    msaa=msaa)
 
 
 def tess_table(w):
@@ -54,9 +55,10 @@ def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True
     rounded to it (``round32``), and the adjoint passes through the
     rounding unchanged."""
     params = params or {}
+    msaa = getattr(w, "msaa", 1)
     if not w.tess_levels:
         return render_scene(w.latent, mvp32, eye, w, pos=params.get("pos"), params=params, aa=aa,
-                            frozen=frozen)
+                            frozen=frozen, msaa=msaa)
     table = tess_table(w)
     base = w.latent.mesh
     pos0 = params.get("pos", torch.as_tensor(base.pos, dtype=R.F64))
@@ -67,7 +69,7 @@ def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True
     mesh = types.SimpleNamespace(pos=None, tri=table["tri"], uv=table["uv"], uv_tri=table["uv_tri"])
     scene = types.SimpleNamespace(mesh=mesh, model=w.latent.model, kd=w.latent.kd,
                                   normal=w.latent.normal, orm=w.latent.orm)
-    out = render_scene(scene, mvp32, eye, w, pos=vd, params=params, aa=aa, frozen=frozen)
+    out = render_scene(scene, mvp32, eye, w, pos=vd, params=params, aa=aa, frozen=frozen, msaa=msaa)
     out["pos"] = vd
     return out
 

@@ -505,14 +505,20 @@ def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = 
 def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tensor,
            mvp32: np.ndarray, eye: np.ndarray, light_dir: np.ndarray, light_rgb: np.ndarray,
            W: int, H: int, adj: np.ndarray | None = None, aa: bool = True,
-           keep_gbuf: bool = False, frozen: dict | None = None):
+           keep_gbuf: bool = False, frozen: dict | None = None, msaa: int = 1):
     """Render B views.  ``pos`` is float64 [V,3] (may require grad); the
     visibility uses its float32 rounding (R1).  Returns a dict with
-    image [B,H*W,3] (antialiased), color [B,H*W,3], keys [B,H,W] uint64,
-    coverage [B,H,W] and per-view AA pair lists.  ``frozen``: the output of
+    image [B,H*W,3] (antialiased), color [B,Hs*Ws,3], keys [B,Hs,Ws] uint64,
+    coverage [B,Hs,Ws] and per-view AA pair lists.  ``frozen``: the output of
     an earlier call whose visibility and antialiasing pairs are reused (the
     loss is then a smooth function of the positions, for finite
-    differences)."""
+    differences).
+
+    Multisampling (Sec. 5.2, "Antialiasing"; ``msaa`` = m > 1): visibility is
+    sampled on an m x m grid per pixel (the rasterizer at Ws = m W,
+    Hs = m H), each sample's triangle is shaded once per pixel at the pixel
+    centre, the silhouette antialiasing runs between adjacent samples, and
+    the image is the mean of each pixel's m^2 samples."""
     tri_np = np.asarray(mesh.tri, dtype=np.int64)
     tri = torch.from_numpy(tri_np)
     uv = _t(mesh.uv)
@@ -522,23 +528,26 @@ def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tenso
     nrm = vertex_normals(pos, tri)
     tan = vertex_tangents(pos, tri, uv, uv_tri)
     B = mvp32.shape[0]
+    m = int(msaa)
+    Ws, Hs = W * m, H * m
     pos32 = pos.detach().numpy().astype(np.float32)
     images, colors, keys_all, cov_all, pairs_all, gbufs = [], [], [], [], [], []
     for b in range(B):
         M = _t(mvp32[b].astype(np.float64))
         clip = torch.cat([pos, torch.ones(pos.shape[0], 1, dtype=F64)], dim=1) @ M.T
-        sv = snap(pos32, mvp32[b], W, H)
+        sv = snap(pos32, mvp32[b], Ws, Hs)
         if frozen is None:
-            keys, cov, orient = raster(tri_np, sv, W, H)
+            keys, cov, orient = raster(tri_np, sv, Ws, Hs)
         else:
             keys, cov = frozen["keys"][b], frozen["coverage"][b]
         ids = key_tri(keys).reshape(-1)
         pix = np.nonzero(ids)[0]
-        color = torch.zeros(H * W, 3, dtype=F64)
+        color = torch.zeros(Hs * Ws, 3, dtype=F64)
         if pix.size:
             t_idx = torch.from_numpy(ids[pix] - 1)
-            i = torch.from_numpy((pix % W).astype(np.float64))
-            j = torch.from_numpy((pix // W).astype(np.float64))
+            # the pixel of each sample; shading is evaluated at its centre
+            i = torch.from_numpy(((pix % Ws) // m).astype(np.float64))
+            j = torch.from_numpy(((pix // Ws) // m).astype(np.float64))
             px = 2.0 * (i + 0.5) / W - 1.0
             py = 2.0 * (j + 0.5) / H - 1.0
             corners = tri[t_idx]                      # [N,3]
@@ -583,7 +592,9 @@ def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tenso
                                   uv=uvp.detach(), duv_dx=duv_dx.detach(), duv_dy=duv_dy.detach(),
                                   n=n.detach(), kd=kd.detach()))
         pairs = aa_pairs(keys, tri_np, sv, orient, adj) if frozen is None else frozen["pairs"][b]
-        img = antialias(color, clip, pairs, W, H) if aa else color
+        img = antialias(color, clip, pairs, Ws, Hs) if aa else color
+        if m > 1:
+            img = img.reshape(H, m, W, m, 3).mean(dim=(1, 3)).reshape(H * W, 3)
         images.append(img)
         colors.append(color)
         keys_all.append(keys)

@@ -315,6 +315,7 @@ class Workload:
     optimize: tuple         # names among "pos", "kd", "normal", "orm", "disp"
     disp: Texture | None = None   # [S,S,1] f32 displacement map of a tessellated latent
     tess_levels: int = 0          # midpoint subdivisions of the latent (base) mesh
+    msaa: int = 1                 # latent visibility samples per pixel axis
 
 
 def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> Mesh:
