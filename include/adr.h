@@ -142,6 +142,14 @@ typedef struct adr_fwd_out {
 
 #define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
 #define ADR_FWD_NO_AA 2          /* skip silhouette antialiasing (image = color) */
+#define ADR_MSAA_2X2 16          /* fwd and bwd: multisampled visibility (Sec. 5.2, "Antialiasing"):
+                                    visibility on a 2x2 sample grid per pixel, each sample's
+                                    triangle shaded once per pixel at the pixel centre, silhouette
+                                    antialiasing between adjacent samples, pixel = mean of its
+                                    samples.  vis, color, tri_id, coverage are then per sample
+                                    ([B, 2H, 2W]); image, dimage, the loss and ref_image stay per
+                                    pixel */
+#define ADR_MSAA_4X4 32          /* as ADR_MSAA_2X2 with a 4x4 sample grid */
 #define ADR_INDEPENDENT_MIPS 8   /* every mip level of the F32 maps is its own latent variable
                                     (Sec. 4.2): bwd leaves each level's gradient in place (no
                                     mip adjoint), so levels >= 1 of the gradients are outputs and

@@ -27,7 +27,11 @@ E_INVALID, E_NOMEM, E_HIP, E_OVER_BUDGET, E_NOTFOUND, E_NONFINITE, E_UNIMPL = -1
 TEX_F32, TEX_RGBA8 = 0, 1
 SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
 LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
-FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC, INDEPENDENT_MIPS = 1, 2, 4, 8
+FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC, INDEPENDENT_MIPS, MSAA_2X2, MSAA_4X4 = 1, 2, 4, 8, 16, 32
+
+
+def msaa_factor(flags: int) -> int:
+    return 4 if flags & MSAA_4X4 else (2 if flags & MSAA_2X2 else 1)
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
@@ -323,15 +327,17 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
     """Returns a dict with vis, color, image, dimage, loss, tri_id, coverage
     (``outputs``: a dict returned by an earlier call, reused in place)."""
     B, H, W = views.n, views.height, views.width
+    ms = msaa_factor(flags)
+    Hs, Ws = H * ms, W * ms          # visibility samples (multisampling: per sample)
     dev = mesh.tri.device
     if outputs is not None:
         out = outputs
     else:
-        out = dict(vis=torch.empty(B, H, W, dtype=torch.int64, device=dev),
-                   color=torch.empty(B, H, W, 3, dtype=torch.float32, device=dev))
+        out = dict(vis=torch.empty(B, Hs, Ws, dtype=torch.int64, device=dev),
+                   color=torch.empty(B, Hs, Ws, 3, dtype=torch.float32, device=dev))
         out["image"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if want_image else None
-        out["tri_id"] = torch.empty(B, H, W, dtype=torch.int32, device=dev) if want_tri_id else None
-        out["coverage"] = torch.empty(B, H, W, dtype=torch.int32, device=dev) if want_coverage else None
+        out["tri_id"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_tri_id else None
+        out["coverage"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_coverage else None
         if ref is not None:
             out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
             out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)

@@ -176,6 +176,67 @@ __device__ __forceinline__ Recv recv_stats(const AAArgs& a, int b, int i, int j)
   return r;
 }
 
+// Loss term of one pixel (Sec. 5.3) and its gradient, written to dimage[o].
+__device__ __forceinline__ float pixel_loss(f3 out, f3 r, int loss_kind, float inv_n, float* dimage, int64_t o) {
+  const bool tm = loss_kind == ADR_LOSS_L1_TONEMAP || loss_kind == ADR_LOSS_L2_TONEMAP;
+  const bool l1 = loss_kind == ADR_LOSS_L1 || loss_kind == ADR_LOSS_L1_TONEMAP;
+  float ov[3] = {out.x, out.y, out.z}, rv[3] = {r.x, r.y, r.z}, gd[3];
+  float lsum = 0.f;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    float d = tm ? tmap(ov[ch]) - tmap(rv[ch]) : ov[ch] - rv[ch];
+    float dt = tm ? tmap_d(ov[ch]) : 1.0f;
+    if (l1) {
+      lsum += fabsf(d);
+      gd[ch] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * dt * inv_n;
+    } else {
+      lsum += d * d;
+      gd[ch] = 2.f * d * dt * inv_n;
+    }
+  }
+  st3(dimage, o, mk(gd[0], gd[1], gd[2]));
+  return lsum;
+}
+
+// Multisample resolve (Sec. 5.2, "Antialiasing"): a pixel is the mean of its
+// ms x ms antialiased samples; the loss is taken on the resolved pixels.
+__global__ __launch_bounds__(256) void k_msaa_resolve(ViewsD v, const float* __restrict__ image_s,
+                                                      const float* __restrict__ ref, int loss_kind,
+                                                      float* __restrict__ image, float* __restrict__ dimage,
+                                                      float* __restrict__ partial) {
+  __shared__ float red[4];
+  const int Wp = v.W / v.ms, Hp = v.H / v.ms;
+  const int64_t n = (int64_t)v.B * Hp * Wp;
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float lsum = 0.f;
+  if (o < n) {
+    const int64_t b = o / ((int64_t)Hp * Wp);
+    const int64_t r = o - b * Hp * Wp;
+    const int jp = (int)(r / Wp), ip = (int)(r - (int64_t)jp * Wp);
+    f3 acc = mk(0.f, 0.f, 0.f);
+    for (int sj = 0; sj < v.ms; ++sj)
+      for (int si = 0; si < v.ms; ++si)
+        acc += ldc(image_s, (b * v.H + jp * v.ms + sj) * v.W + ip * v.ms + si);
+    const f3 out = (1.0f / (float)(v.ms * v.ms)) * acc;
+    if (image) st3(image, o, out);
+    if (ref) lsum = pixel_loss(out, ldc(ref, o), loss_kind, 1.0f / (3.0f * (float)n), dimage, o);
+  }
+  if (ref) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// dL/d(antialiased sample): a sample carries 1/ms^2 of its pixel's gradient.
+__device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, int b, int i, int j) {
+  if (a.v.ms == 1) return ldc(dimage, ((int64_t)b * a.v.H + j) * a.v.W + i);
+  const int Wp = a.v.W / a.v.ms, Hp = a.v.H / a.v.ms;
+  const int64_t op = ((int64_t)b * Hp + j / a.v.ms) * Wp + i / a.v.ms;
+  return (1.0f / (float)(a.v.ms * a.v.ms)) * ldc(dimage, op);
+}
+
 __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __restrict__ ref,
                                                      int loss_kind, float* __restrict__ image,
                                                      float* __restrict__ dimage,
@@ -195,24 +256,8 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
     }
     if (image) st3(image, o, out);
     if (ref) {
-      f3 r = ldc(ref, o);
-      bool tm = loss_kind == ADR_LOSS_L1_TONEMAP || loss_kind == ADR_LOSS_L2_TONEMAP;
-      bool l1 = loss_kind == ADR_LOSS_L1 || loss_kind == ADR_LOSS_L1_TONEMAP;
-      float inv_n = 1.0f / (3.0f * (float)a.v.B * (float)a.v.H * (float)a.v.W);
-      float ov[3] = {out.x, out.y, out.z}, rv[3] = {r.x, r.y, r.z}, gd[3];
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        float d = tm ? tmap(ov[ch]) - tmap(rv[ch]) : ov[ch] - rv[ch];
-        float dt = tm ? tmap_d(ov[ch]) : 1.0f;
-        if (l1) {
-          lsum += fabsf(d);
-          gd[ch] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * dt * inv_n;
-        } else {
-          lsum += d * d;
-          gd[ch] = 2.f * d * dt * inv_n;
-        }
-      }
-      st3(dimage, o, mk(gd[0], gd[1], gd[2]));
+      const float inv_n = 1.0f / (3.0f * (float)a.v.B * (float)a.v.H * (float)a.v.W);
+      lsum += pixel_loss(out, ldc(ref, o), loss_kind, inv_n, dimage, o);
     }
   }
   if (ref) {
@@ -255,7 +300,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   float scale = dloss ? dloss[0] : 1.0f;
   int64_t base = (int64_t)p.b * a.v.H * a.v.W;
   int64_t o = base + (int64_t)p.j * a.v.W + p.i;
-  f3 gself = scale * ldc(dimage, o);
+  f3 gself = scale * sample_grad(a, dimage, p.b, p.i, p.j);
   f3 gc = gself;
   if (!a.no_aa) {
     uint64_t k = a.vis[o];
@@ -277,7 +322,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       bool self_recv = recv_Q ? !pr.self_is_P : pr.self_is_P;
       float w = recv_Q ? s - 0.5f : 0.5f - s;
       f3 cn = ldc(a.color, on);
-      f3 gn = scale * ldc(dimage, on);
+      f3 gn = scale * sample_grad(a, dimage, p.b, ni, nj);
       Recv rr = self_recv ? rs : recv_stats(a, p.b, ni, nj);
       float Mr = fmaxf(rr.W, 1.0f);
       f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
@@ -339,14 +384,25 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
   AAArgs a = make_aa(m, v, s, vis, color, no_aa);
   int nb = a.tiles_x * a.tiles_y * v.B;
   if (!image && !ref) return hipSuccess;
-  hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage,
-                     s.partial);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (v.ms > 1) {
+    // antialiased samples, then the resolve and the loss per pixel
+    hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, (const float*)nullptr, loss_kind,
+                       s.image_s, (float*)nullptr, s.partial);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t n = (int64_t)v.B * (v.H / v.ms) * (v.W / v.ms);
+    nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_msaa_resolve, dim3(nb), dim3(256), 0, st, v, s.image_s, ref, loss_kind, image, dimage,
+                       s.partial);
+  } else {
+    hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage,
+                       s.partial);
+  }
+  e = hipGetLastError();
   if (e != hipSuccess || !ref) return e;
-  float inv_n = 1.0f;  // partials hold sums; the mean's 1/N is applied here
-  double n = 3.0 * (double)v.B * v.H * v.W;
-  inv_n = (float)(1.0 / n);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, s.partial, nb, inv_n, loss);
+  // partials hold sums; the mean's 1/N is applied here
+  const double n = 3.0 * (double)v.B * (v.H / v.ms) * (v.W / v.ms);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, s.partial, nb, (float)(1.0 / n), loss);
   return hipGetLastError();
 }
 

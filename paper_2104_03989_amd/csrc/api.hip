@@ -62,7 +62,7 @@ struct Span {
 struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec, image_s;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -196,6 +196,7 @@ adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* 
   v.B = views->n_views;
   v.W = views->width;
   v.H = views->height;
+  v.ms = 1;
   return ADR_OK;
 }
 
@@ -215,6 +216,11 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
         (r = ensure(ctx->dattr, V * 36)))
       return r;
     if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
+  }
+  s.image_s = nullptr;
+  if (v.ms > 1) {
+    if ((r = ensure(ctx->image_s, B * v.W * v.H * 12))) return r;
+    s.image_s = (float*)ctx->image_s.p;
   }
   s.det = det;
   if (bwd) {
@@ -315,7 +321,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
-                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
@@ -325,6 +331,18 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   delete ctx;
   return ADR_OK;
+}
+
+// Multisampling factor from the flags (1, 2 or 4 samples per pixel axis);
+// switches the views to the sample grid.  0 on a bad combination.
+static int apply_msaa(int32_t flags, ViewsD& v) {
+  const bool m2 = flags & ADR_MSAA_2X2, m4 = flags & ADR_MSAA_4X4;
+  if (m2 && m4) return 0;
+  const int ms = m4 ? 4 : (m2 ? 2 : 1);
+  v.ms = ms;
+  v.W *= ms;
+  v.H *= ms;
+  return ms;
 }
 
 adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
@@ -340,10 +358,13 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
     if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
   }
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS))
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
+                ADR_MSAA_4X4))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   if ((flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
     return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
+  if (!apply_msaa(flags, v) || v.W > 16384 || v.H > 16384)
+    return fail(ADR_E_INVALID, "multisampling: one factor, at most 16384 samples per axis");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
@@ -386,8 +407,11 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (!grads) return fail(ADR_E_INVALID, "grads is NULL");
   if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
   if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS))
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
+                ADR_MSAA_4X4))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if (!apply_msaa(flags, v) || v.W > 16384 || v.H > 16384)
+    return fail(ADR_E_INVALID, "multisampling: one factor, at most 16384 samples per axis");
   const bool det = (flags & ADR_DETERMINISTIC) != 0;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");

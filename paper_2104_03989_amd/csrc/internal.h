@@ -36,7 +36,8 @@ struct ViewsD {
   const float* eye;
   const float* light_dir;
   const float* light_rgb;
-  int B, W, H;
+  int B, W, H;  // W, H: visibility samples per row / column (pixels x ms)
+  int ms;       // multisampling: ms x ms visibility samples per pixel (1: none)
 };
 
 // Per-call scratch owned by the context.
@@ -55,6 +56,7 @@ struct Scratch {
   float* dclip;       // [B,V,4]
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
   float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
+  float* image_s;     // [B,H,W,3] antialiased samples before the multisample resolve
   int n_partial;
   // vertex-side adjoint accumulators (float64, or fixed point in
   // deterministic mode) and the deterministic mode's sort buffers

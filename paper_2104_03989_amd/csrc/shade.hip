@@ -46,10 +46,13 @@ struct PixelGeom {
 __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, const double4* clip,
                                            const float* nrm, const float* tan, int b, int i,
                                            int j, int tri, PixelGeom& g) {
-  g.px = 2.0 * ((double)i + 0.5) / (double)vw.W - 1.0;
-  g.py = 2.0 * ((double)j + 0.5) / (double)vw.H - 1.0;
-  g.sx = 2.0f / (float)vw.W;
-  g.sy = 2.0f / (float)vw.H;
+  // (i, j) is a visibility sample; shading is evaluated once per pixel, at
+  // the centre of the sample's pixel, with derivatives per pixel
+  const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
+  g.px = 2.0 * ((double)(i / vw.ms) + 0.5) / (double)Wp - 1.0;
+  g.py = 2.0 * ((double)(j / vw.ms) + 0.5) / (double)Hp - 1.0;
+  g.sx = 2.0f / (float)Wp;
+  g.sy = 2.0f / (float)Hp;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     g.v[c] = m.tri[3 * tri + c];
@@ -75,8 +78,8 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, con
   for (int c = 0; c < 3; ++c) {
     double lam = D[c] * iS;
     g.lam[c] = (float)lam;
-    g.lx[c] = (float)((g.a[c] - lam * A) * iS * (2.0 / vw.W));
-    g.ly[c] = (float)((g.b[c] - lam * Bs) * iS * (2.0 / vw.H));
+    g.lx[c] = (float)((g.a[c] - lam * A) * iS * (2.0 / Wp));
+    g.ly[c] = (float)((g.b[c] - lam * Bs) * iS * (2.0 / Hp));
   }
   // attributes relative to corner 0 (sum lambda = 1, sum of derivatives = 0):
   // a = a0 + sum_c lambda_c (a_c - a0), da = sum_c dlambda_c (a_c - a0)
@@ -636,7 +639,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   double Bs = g.b[0] + g.b[1] + g.b[2];
   double gA = 0.0, gB = 0.0, gS = 0.0;
   double ga[3], gb[3], gD[3], dlam[3], dglam[3];
-  double sxd = 2.0 / a.v.W, syd = 2.0 / a.v.H;
+  double sxd = 2.0 / (a.v.W / a.v.ms), syd = 2.0 / (a.v.H / a.v.ms);  // per pixel
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
