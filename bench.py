@@ -142,6 +142,9 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     mvp_d, eye_d, light_d = dev(np.stack(mvps)), dev(np.stack(eyes)), dev(lights)
     rgb_d = dev(np.ones((n_steps, B, 3)))
     views = [adr.DeviceViews(mvp_d[t], eye_d[t], light_d[t], rgb_d[t], W, H) for t in range(n_steps)]
+    k = w.ref_ssaa   # supersampled reference (prefiltering): same cameras, k times the resolution
+    ref_views = views if k == 1 else [adr.DeviceViews(mvp_d[t], eye_d[t], light_d[t], rgb_d[t], W * k, H * k)
+                                      for t in range(n_steps)]
     # optimised parameters: positions and level 0 of the F32 maps
     params = []
     grads = {"pos": torch.zeros_like(lat_mesh.pos)}
@@ -153,20 +156,29 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         g_base = torch.zeros_like(ts.base.pos)
         g_disp = torch.zeros_like(disp.data)
         params += [(ts.base.pos, g_base), (disp.data, g_disp)]
+    independent = False
     for name in ("kd", "normal", "orm"):
         if name not in w.optimize:
             grads[name] = None
             continue
         tex = getattr(lat_mat, name)
         grads[name] = tex.grad_buffer()
-        n0 = tex.size * tex.size
-        params.append((tex.data[:n0], grads[name][:n0]))
+        if getattr(getattr(w.latent, name), "chain", None) is not None:
+            independent = True       # every mip level is a variable
+            params.append((tex.data, grads[name]))
+        else:
+            n0 = tex.size * tex.size
+            params.append((tex.data[:n0], grads[name][:n0]))
     adam = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
     n_params = sum(p.numel() for p, _ in params)
     dflag = adr.DETERMINISTIC if det else 0
-    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, views[0], flags=dflag)
-    lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_out["image"], loss=w.loss,
-                             flags=adr.FWD_BUILD_MIPS | dflag, want_image=False, want_tri_id=True)
+    if w.msaa > 1:
+        dflag |= adr.MSAA_4X4 if w.msaa == 4 else adr.MSAA_2X2
+    lflag = dflag | (adr.INDEPENDENT_MIPS if independent else adr.FWD_BUILD_MIPS)
+    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], flags=dflag & adr.DETERMINISTIC)
+    ref_img = ref_out["image"] if k == 1 else adr.image_downsample(ctx, ref_out["image"], k)
+    lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_img, loss=w.loss,
+                             flags=lflag, want_image=False, want_tri_id=True)
 
     # uniform Laplacian regularizer (absolute form: the latent starts as a
     # resampled sphere), lambda_0 by the heuristic, then the recursive decay
@@ -188,10 +200,11 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         v = views[t % n_steps]
         if ts is not None:
             adr.tess_fwd(ctx, ts, disp)
-        adr.render_fwd(ctx, ref_mesh, ref_mat, v, outputs=ref_out, flags=dflag)
-        adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_out["image"], loss=w.loss,
-                       flags=adr.FWD_BUILD_MIPS | dflag, outputs=lat_out)
-        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=dflag)
+        adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_out, flags=dflag & adr.DETERMINISTIC)
+        if k > 1:
+            adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
+        adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
+        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
         if lap is not None:
@@ -355,6 +368,8 @@ WORKLOADS = {
                      "and displaced by a 1024^2 map, 1024^2 normal map, 8 views x 512x512, L1, Adam"),
     "plain": ("plain single step: 20,480-tri SH reference, 1,280-tri latent, 256^2 maps, 4 views x 256x256, "
               "Blinn-Phong, L1, Adam"),
+    "prefilter": ("prefiltering: 297,680-tri GGX reference with 8x8 supersampling, 7,220-tri latent with 4x4 "
+                  "multisampled visibility and independent-mip 512^2 maps, 8 views x 128x128, tone-mapped L1, Adam"),
 }
 
 
@@ -364,6 +379,8 @@ def make_workload(name):
         return synth.workload_paper_loop(), 2
     if name == "displacement":
         return synth.workload_displacement(), 3
+    if name == "prefilter":
+        return synth.workload_prefilter(), 6
     return synth.workload_plain_step(), 1
 
 
@@ -430,7 +447,7 @@ def main():
     step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic,
                           laplacian=args.laplacian)
     torch.cuda.synchronize()
-    covered = int((st["lat_out"]["tri_id"] > 0).sum())
+    covered = int((st["lat_out"]["tri_id"] > 0).sum()) // (w.msaa * w.msaa)
     _log(f"warmup {args.warmup}")
     for t in range(args.warmup):
         step(t)

@@ -271,6 +271,14 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
                         const adr_texture* disp, float* g_pos_out, float* g_base_pos,
                         float* g_disp, adr_stream stream);
 
+/* Box filter of a supersampled image: in [n_views, k height, k width, 3],
+ * out [n_views, height, width, 3], each output pixel the mean of its k x k
+ * input samples (device).  The reference of the prefiltering application
+ * (Sec. 4.2) is rendered at k times the resolution and filtered so.
+ * k in 1..64.  Device work on `stream`. */
+adr_status adr_image_downsample(adr_ctx* ctx, const float* in, int32_t n_views, int32_t height, int32_t width,
+                                int32_t k, float* out, adr_stream stream);
+
 /* ------------------------------------------------ Laplacian regularizer */
 
 /* One-ring neighbour lists (CSR) of a mesh's position vertices, device. */

@@ -75,10 +75,19 @@ def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True
 
 
 def reference_image(w, mvp32=None, eye=None):
+    """Reference render; with ``ref_ssaa`` = k it is rendered at k times the
+    resolution (the cameras' aspect is unchanged) and box-filtered (Sec. 4.2)."""
     if mvp32 is None:
         mvp32, eye = cameras(w)
+    k = getattr(w, "ref_ssaa", 1)
     with torch.no_grad():
-        return render_scene(w.ref, mvp32, eye, w)["image"]
+        if k == 1:
+            return render_scene(w.ref, mvp32, eye, w)["image"]
+        big = types.SimpleNamespace(width=w.width * k, height=w.height * k, light_dir=w.light_dir,
+                                    light_rgb=w.light_rgb)
+        img = render_scene(w.ref, mvp32, eye, big)["image"]
+        B, H, W = img.shape[0], w.height, w.width
+        return img.reshape(B, H, k, W, k, 3).mean(dim=(2, 4)).reshape(B, H * W, 3)
 
 
 def latent_params(w):

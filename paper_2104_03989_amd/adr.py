@@ -37,7 +37,7 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
-           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian")
+           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample")
 N_STAGES = 13
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear")
@@ -137,6 +137,7 @@ _lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(Jo
 _lib.adr_ctx_profile.argtypes = [P, I32]
 _lib.adr_ctx_profile_read.argtypes = [P, P, P]
 _lib.adr_mesh_one_ring.argtypes = [P, I32, I32, P, P, P]
+_lib.adr_image_downsample.argtypes = [P, P, I32, I32, I32, I32, P, P]
 _lib.adr_laplacian.argtypes = [P, C.POINTER(OneRing_), P, P, C.c_float, P, P, P, P]
 _lib.adr_mesh_frame.argtypes = [P, C.POINTER(Mesh_), P, P, P]
 _lib.adr_tess_counts.argtypes = [P, I32, I32, I32, P, P, P]
@@ -584,3 +585,12 @@ def laplacian(ctx: Context, ring: DeviceOneRing, pos, delta_ref=None, lam: float
     r = ring.struct()
     _check(_lib.adr_laplacian(ctx.h, C.byref(r), _ptr(pos), _ptr(delta_ref), float(lam), _ptr(delta_out),
                               _ptr(loss), _ptr(g_pos), _stream(stream)))
+
+
+def image_downsample(ctx: Context, img, k: int, out=None, stream=None):
+    """[B, kH, kW, 3] -> [B, H, W, 3] box filter (supersampled reference)."""
+    B, Hs, Ws, _ = img.shape
+    H, W = Hs // k, Ws // k
+    out = torch.empty(B, H, W, 3, dtype=torch.float32, device=img.device) if out is None else out
+    _check(_lib.adr_image_downsample(ctx.h, _ptr(img), B, H, W, k, _ptr(out), _stream(stream)))
+    return out

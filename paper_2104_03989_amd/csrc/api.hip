@@ -564,6 +564,18 @@ adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* po
   return ADR_OK;
 }
 
+adr_status adr_image_downsample(adr_ctx* ctx, const float* in, int32_t n_views, int32_t height, int32_t width,
+                                int32_t k, float* out, adr_stream stream) {
+  if (!ctx || !in || !out) return fail(ADR_E_INVALID, "ctx, in and out are required");
+  if (n_views < 1 || height < 1 || width < 1 || k < 1 || k > 64 || (int64_t)height * k > 65536 ||
+      (int64_t)width * k > 65536)
+    return fail(ADR_E_INVALID, "downsample: bad sizes");
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(12, launch_downsample(in, n_views, height, width, k, out, st), "downsample");
+  return ADR_OK;
+}
+
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
   ctx->prof = enable != 0;

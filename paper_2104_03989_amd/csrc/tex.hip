@@ -208,6 +208,39 @@ hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Box filter of a supersampled image: out[b, j, i] = mean of in[b, k j + y,
+// k i + x] over x, y < k, summed row by row.  Renders the reference of the
+// prefiltering application (Sec. 4.2) with k^2 samples per pixel.
+__global__ __launch_bounds__(256) void k_downsample(const float* __restrict__ in, int B, int H, int W, int k,
+                                                   float* __restrict__ out) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= (int64_t)B * H * W) return;
+  const int64_t b = o / ((int64_t)H * W);
+  const int64_t r = o - b * H * W;
+  const int j = (int)(r / W), i = (int)(r - (int64_t)j * W);
+  const int64_t Ws = (int64_t)W * k;
+  float ax = 0.f, ay = 0.f, az = 0.f;
+  for (int y = 0; y < k; ++y) {
+    const float* row = in + 3 * ((b * H * k + (int64_t)j * k + y) * Ws + (int64_t)i * k);
+    for (int x = 0; x < k; ++x) {
+      ax += row[3 * x];
+      ay += row[3 * x + 1];
+      az += row[3 * x + 2];
+    }
+  }
+  const float s = 1.0f / (float)(k * k);
+  out[3 * o] = ax * s;
+  out[3 * o + 1] = ay * s;
+  out[3 * o + 2] = az * s;
+}
+
+hipError_t launch_downsample(const float* in, int B, int H, int W, int k, float* out, hipStream_t st) {
+  const int64_t n = (int64_t)B * H * W;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_downsample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, B, H, W, k, out);
+  return hipGetLastError();
+}
+
 // RGBA8 chains (read-only maps, built once): one launch per level.
 hipError_t launch_mip_build(const Tex& t, hipStream_t st) {
   if (t.fmt != ADR_TEX_RGBA8) {

@@ -316,6 +316,7 @@ class Workload:
     disp: Texture | None = None   # [S,S,1] f32 displacement map of a tessellated latent
     tess_levels: int = 0          # midpoint subdivisions of the latent (base) mesh
     msaa: int = 1                 # latent visibility samples per pixel axis
+    ref_ssaa: int = 1             # reference rendered at this many times the resolution, box-filtered
 
 
 def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> Mesh:
@@ -399,6 +400,30 @@ def workload_displacement(views: int = 8, res: int = 512, map_size: int = 1024,
     light = random_unit(views, seed_for(c, 3))
     return Workload("displacement", ref, lat, dirs, light, np.ones((views, 3)), res, res,
                     3.0, 45.0, "l1", 1e-3, ("pos", "disp", "normal"), disp, levels)
+
+
+def workload_prefilter(views: int = 8, res: int = 128, ssaa: int = 8, msaa: int = 4, map_size: int = 512,
+                       ref_nu: int = 122, lat_nu: int = 19) -> Workload:
+    """Joint shape and appearance prefiltering (Sec. 4.2): the paper-scale
+    GGX reference rendered with ssaa^2 samples per pixel at a low target
+    resolution; a ~7k-triangle latent with multisampled visibility and base
+    colour and normal maps whose mip levels are independent variables."""
+    c = 6
+    rad = lambda d: fbm_radius(d, seed_for(2, 1))
+    ref_mesh = sphere_mesh(ref_nu, rad)
+    kd_ref = Texture(to_rgba8(value_noise_map(2048, 3, seed_for(2, 2))), "rgba8")
+    ref = Scene(ref_mesh, "ggx", kd_ref, _f32(detail_normal_map(2048, seed_for(2, 3))),
+                _f32(orm_map(2048, seed_for(2, 4))))
+    kd = independent_chain(map_size, 3, seed_for(c, 1), 0.0, 1.0)
+    nm = independent_chain(map_size, 3, seed_for(c, 2), -0.05, 0.05)
+    nm.chain[:, 2] = 1.0
+    nm.data[..., 2] = 1.0
+    orm = independent_chain(map_size, 3, seed_for(c, 3), 0.2, 0.6)
+    lat = Scene(sphere_mesh(lat_nu, rad), "ggx", kd, nm, orm)
+    dirs = random_unit(views, seed_for(c, 4))
+    light = random_unit(views, seed_for(c, 5))
+    return Workload("prefilter", ref, lat, dirs, light, np.ones((views, 3)), res, res, 3.0, 45.0, "l1_tonemap",
+                    2e-3, ("pos", "kd", "normal", "orm"), msaa=msaa, ref_ssaa=ssaa)
 
 
 def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:
