@@ -13,6 +13,7 @@ import numpy as np
 import torch
 
 from . import render as R
+from . import skin as K
 from . import tess as T
 
 
@@ -48,14 +49,32 @@ def tess_table(w):
     return w._oracle_tess[1]
 
 
+def _round32(x, on=True):
+    """The renderer's vertex format is float32: positions computed by a mesh
+    operation are rounded to it, and the adjoint passes through unchanged."""
+    return x + (x.detach().to(torch.float32).to(R.F64) - x.detach()) if on else x
+
+
+def skinned_positions(w, pos, weights, frame=None):
+    """Eq. 2 with the bone transforms of the workload's animation frame."""
+    f = w.frame if frame is None else frame
+    return K.skin(pos, weights, torch.as_tensor(w.rig.bones[f], dtype=R.F64))
+
+
 def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True):
     """Latent render; with tessellation the base positions and the
-    displacement map are mapped to displaced positions first (Eq. 3).
-    The renderer's vertex format is float32: the displaced positions are
-    rounded to it (``round32``), and the adjoint passes through the
-    rounding unchanged."""
+    displacement map are mapped to displaced positions first (Eq. 3); with a
+    rig the bind-pose positions are skinned with the latent weights (Eq. 2).
+    Positions a mesh operation computes are rounded to float32 (``round32``)."""
     params = params or {}
     msaa = getattr(w, "msaa", 1)
+    if getattr(w, "rig", None) is not None:
+        pos0 = params.get("pos", torch.as_tensor(w.latent.mesh.pos, dtype=R.F64))
+        wts = params.get("weights", torch.as_tensor(w.weights, dtype=R.F64))
+        vs = _round32(skinned_positions(w, pos0, wts), round32)
+        out = render_scene(w.latent, mvp32, eye, w, pos=vs, params=params, aa=aa, frozen=frozen, msaa=msaa)
+        out["pos"] = vs
+        return out
     if not w.tess_levels:
         return render_scene(w.latent, mvp32, eye, w, pos=params.get("pos"), params=params, aa=aa,
                             frozen=frozen, msaa=msaa)
@@ -63,9 +82,7 @@ def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True
     base = w.latent.mesh
     pos0 = params.get("pos", torch.as_tensor(base.pos, dtype=R.F64))
     disp = params.get("disp", torch.as_tensor(w.disp.data, dtype=R.F64))
-    vd = T.displaced_positions(pos0, base, table, disp)
-    if round32:
-        vd = vd + (vd.detach().to(torch.float32).to(R.F64) - vd.detach())
+    vd = _round32(T.displaced_positions(pos0, base, table, disp), round32)
     mesh = types.SimpleNamespace(pos=None, tri=table["tri"], uv=table["uv"], uv_tri=table["uv_tri"])
     scene = types.SimpleNamespace(mesh=mesh, model=w.latent.model, kd=w.latent.kd,
                                   normal=w.latent.normal, orm=w.latent.orm)
@@ -81,11 +98,15 @@ def reference_image(w, mvp32=None, eye=None):
         mvp32, eye = cameras(w)
     k = getattr(w, "ref_ssaa", 1)
     with torch.no_grad():
+        pos = None
+        if getattr(w, "rig", None) is not None:
+            pos = _round32(skinned_positions(w, torch.as_tensor(w.ref.mesh.pos, dtype=R.F64),
+                                             torch.as_tensor(w.rig.ref_weights, dtype=R.F64)))
         if k == 1:
-            return render_scene(w.ref, mvp32, eye, w)["image"]
+            return render_scene(w.ref, mvp32, eye, w, pos=pos)["image"]
         big = types.SimpleNamespace(width=w.width * k, height=w.height * k, light_dir=w.light_dir,
                                     light_rgb=w.light_rgb)
-        img = render_scene(w.ref, mvp32, eye, big)["image"]
+        img = render_scene(w.ref, mvp32, eye, big, pos=pos)["image"]
         B, H, W = img.shape[0], w.height, w.width
         return img.reshape(B, H, k, W, k, 3).mean(dim=(2, 4)).reshape(B, H * W, 3)
 
@@ -99,6 +120,8 @@ def latent_params(w):
             out["pos"] = torch.tensor(s.mesh.pos, dtype=R.F64, requires_grad=True)
         elif name == "disp":
             out["disp"] = torch.tensor(w.disp.data, dtype=R.F64, requires_grad=True)
+        elif name == "weights":
+            out["weights"] = torch.tensor(w.weights, dtype=R.F64, requires_grad=True)
         else:
             tex = getattr(s, name)
             assert tex.fmt == "f32", "only float32 maps are optimised"

@@ -317,6 +317,86 @@ class Workload:
     tess_levels: int = 0          # midpoint subdivisions of the latent (base) mesh
     msaa: int = 1                 # latent visibility samples per pixel axis
     ref_ssaa: int = 1             # reference rendered at this many times the resolution, box-filtered
+    rig: "Rig | None" = None      # skeletal animation shared by reference and latent
+    weights: np.ndarray | None = None   # [V_latent, n_bones] float32 initial latent skinning weights
+    frame: int = 0                # animation frame a single step renders
+
+
+@dataclasses.dataclass
+class Rig:
+    """A skeleton with known per-frame bone transforms (constants of the
+    optimisation) and the reference's skinning weights."""
+    joints: np.ndarray       # [B,3] float32 bind-pose pivot of each bone
+    parent: np.ndarray       # [B] int32, -1 for the root
+    bones: np.ndarray        # [F,B,3,4] float32: top rows of each bone's bind-to-frame affine transform
+    ref_weights: np.ndarray  # [V_ref,B] float32, at most four non-zero weights per row, rows sum to 1
+
+
+def _axis_angle(axis: np.ndarray, theta: float) -> np.ndarray:
+    x, y, z = axis
+    c, s, t = math.cos(theta), math.sin(theta), 1.0 - math.cos(theta)
+    return np.array([[t * x * x + c, t * x * y - s * z, t * x * z + s * y],
+                     [t * x * y + s * z, t * y * y + c, t * y * z - s * x],
+                     [t * x * z - s * y, t * y * z + s * x, t * z * z + c]])
+
+
+def synthetic_rig(ref_pos: np.ndarray, n_bones: int, n_frames: int, seed: int, chains: int = 5,
+                  reach: float = 0.8, amplitude: float = 0.25, sigma: float = 0.2) -> Rig:
+    """A root bone and ``chains`` chains of bones radiating from the centre
+    to ``reach``; each non-root bone swings about its own pivot by
+    amplitude * sin(2 pi f / F + phase) around a random axis, composed down
+    its chain (forward kinematics of the input animation), and the root
+    sways about y.  Reference weights: Gaussian falloff (``sigma``) from each
+    bone's segment midpoint, the four largest kept and normalised."""
+    rng = _rng(seed)
+    n_chain = n_bones - 1
+    lengths = [n_chain // chains + (1 if c < n_chain % chains else 0) for c in range(chains)]
+    dirs = random_unit(chains, seed + 1)
+    joints = [np.zeros(3)]
+    parent = [-1]
+    centre = [np.zeros(3)]
+    for c, ln in enumerate(lengths):
+        seg = reach / max(ln, 1)
+        p, d, par = np.zeros(3), dirs[c], 0
+        for k in range(ln):
+            d = d + rng.normal(0.0, 0.15, 3)
+            d = d / np.linalg.norm(d)
+            q = p + seg * d if k > 0 else p + 0.15 * d
+            joints.append(q)
+            parent.append(par)
+            centre.append(q + 0.5 * seg * d)
+            par = len(joints) - 1
+            p = q
+    joints = np.array(joints)
+    centre = np.array(centre)
+    B = joints.shape[0]
+    axes = random_unit(B, seed + 2)
+    phase = rng.uniform(0.0, 2.0 * math.pi, B)
+    bones = np.zeros((n_frames, B, 3, 4))
+    for f in range(n_frames):
+        world = [None] * B
+        for b in range(B):
+            th = amplitude * math.sin(2.0 * math.pi * f / n_frames + phase[b])
+            if parent[b] < 0:
+                local = np.eye(4)
+                local[:3, :3] = _axis_angle(np.array([0.0, 1.0, 0.0]), 0.5 * th)
+                local[:3, 3] = [0.05 * math.sin(2.0 * math.pi * f / n_frames), 0.0, 0.0]
+            else:
+                r = _axis_angle(axes[b], th)
+                local = np.eye(4)
+                local[:3, :3] = r
+                local[:3, 3] = joints[b] - r @ joints[b]       # rotate about the bone's pivot
+            world[b] = local if parent[b] < 0 else world[parent[b]] @ local
+            bones[f, b] = world[b][:3]
+    d2 = ((ref_pos[:, None, :].astype(np.float64) - centre[None]) ** 2).sum(-1)
+    w = np.exp(-d2 / (2.0 * sigma * sigma))
+    keep = np.argsort(-w, axis=1)[:, :4]
+    dense = np.zeros_like(w)
+    rows = np.arange(w.shape[0])[:, None]
+    dense[rows, keep] = w[rows, keep]
+    dense /= dense.sum(1, keepdims=True)
+    return Rig(joints.astype(np.float32), np.array(parent, dtype=np.int32), bones.astype(np.float32),
+               dense.astype(np.float32))
 
 
 def sphere_mesh(nu: int, radius_fn=None, jitter: float = 0.0, seed: int = 0) -> Mesh:
@@ -424,6 +504,32 @@ def workload_prefilter(views: int = 8, res: int = 128, ssaa: int = 8, msaa: int 
     light = random_unit(views, seed_for(c, 5))
     return Workload("prefilter", ref, lat, dirs, light, np.ones((views, 3)), res, res, 3.0, 45.0, "l1_tonemap",
                     2e-3, ("pos", "kd", "normal", "orm"), msaa=msaa, ref_ssaa=ssaa)
+
+
+def workload_animation(views: int = 8, res: int = 512, map_size: int = 1024, ref_nu: int = 31,
+                       lat_nu: int = 16, n_bones: int = 32, n_frames: int = 40) -> Workload:
+    """Animated character (Sec. 4.3): a 19,220-tri SH blob skinned to a
+    32-bone skeleton (a root and five chains) with 40 frames of known bone
+    transforms; a 5,120-tri reduced latent with dense skinning weights
+    initialised to 1/32 per bone, optimised with its bind-pose positions and
+    1024^2 base colour, normal and ORM maps under GGX; 8 views at 512^2 of one
+    frame per step, a light per view, tonemapped L1."""
+    c = 7
+    rad = lambda d: sh_radius(d, seed_for(c, 1), lmax=4, sigma=0.08)
+    ref_mesh = sphere_mesh(ref_nu, rad)
+    rig = synthetic_rig(ref_mesh.pos, n_bones, n_frames, seed_for(c, 2))
+    kd_ref = Texture(to_rgba8(value_noise_map(map_size, 3, seed_for(c, 3))), "rgba8")
+    ref = Scene(ref_mesh, "ggx", kd_ref, _f32(detail_normal_map(map_size, seed_for(c, 4))),
+                _f32(orm_map(map_size, seed_for(c, 5))))
+    lat_mesh = sphere_mesh(lat_nu, rad)
+    kd_lat = _rng(seed_for(c, 6)).uniform(0.0, 1.0, size=(map_size, map_size, 3))
+    orm_lat = np.broadcast_to(np.array([0.0, 0.5, 0.0]), (map_size, map_size, 3))
+    lat = Scene(lat_mesh, "ggx", _f32(kd_lat), _f32(flat_normal_map(map_size)), _f32(orm_lat))
+    weights = np.full((lat_mesh.pos.shape[0], n_bones), 1.0 / n_bones, dtype=np.float32)
+    dirs = random_unit(views, seed_for(c, 7))
+    light = random_unit(views, seed_for(c, 8))
+    return Workload("animation", ref, lat, dirs, light, np.ones((views, 3)), res, res, 3.0, 45.0, "l1_tonemap",
+                    2e-3, ("pos", "weights", "kd", "normal", "orm"), rig=rig, weights=weights)
 
 
 def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:

@@ -80,3 +80,28 @@ def tess_crop_workload(res=32, views=2, disp_size=16, seed=0, levels=3):
     w.disp = disp
     w.tess_levels = levels
     return w
+
+
+def rig_workload(w, n_bones=6, n_frames=4, frame=1, seed=0, identity=False):
+    """Attach a small synthetic rig to a workload: reference weights from the
+    rig's falloff, latent weights random and normalised per vertex.  With
+    ``identity`` every bone transform is the identity."""
+    rig = synth.synthetic_rig(w.ref.mesh.pos, n_bones, n_frames, 800 + seed, chains=2, reach=0.6)
+    g = np.random.default_rng(900 + seed)
+    n_lat = w.latent.mesh.pos.shape[0]
+    if identity:
+        # identity bones, and weights that sum to one exactly: multiples of
+        # 1/64 for the latent, one-hot rows for the reference
+        rig.bones[:] = np.eye(3, 4, dtype=np.float32)
+        rig.ref_weights[:] = 0.0
+        rig.ref_weights[np.arange(rig.ref_weights.shape[0]), g.integers(0, n_bones, rig.ref_weights.shape[0])] = 1.0
+        cuts = np.sort(g.integers(0, 65, size=(n_lat, n_bones - 1)), axis=1)
+        parts = np.diff(np.concatenate([np.zeros((n_lat, 1)), cuts, np.full((n_lat, 1), 64)], 1), axis=1)
+        w.weights = (parts / 64.0).astype(np.float32)
+    else:
+        wt = g.uniform(0.0, 1.0, size=(n_lat, n_bones))
+        w.weights = (wt / wt.sum(1, keepdims=True)).astype(np.float32)
+    w.rig = rig
+    w.frame = frame
+    w.optimize = tuple(w.optimize) + ("weights",)
+    return w
