@@ -305,6 +305,29 @@ adr_status adr_mesh_one_ring(const int32_t* tri, int32_t n_tri, int32_t n_pos, i
 adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* pos, const float* delta_ref,
                          float lambda, float* delta_out, float* loss, float* g_pos, adr_stream stream);
 
+/* ---------------------------------------------------------------- skinning */
+
+/* Dense linear blend skinning (Sec. 5.1, "Animation & skinning", Eq. 2):
+ * pos_out[i] = sum_b weights[i,b] M_b (pos[i], 1), every weight a variable
+ * (no normalisation is applied).  pos [n_pos,3] bind-pose positions,
+ * weights [n_pos,n_bones] row-major, bones [n_bones,3,4] row-major top rows
+ * of each bone's affine transform for the frame (constants), all device.
+ * Outputs (device): pos_out [n_pos,3]; blend_out [n_pos,12] (nullable) the
+ * blended matrix sum_b w_ib M_b of each vertex, which the adjoint needs.
+ * Computed on the matrix cores in float64 and rounded once to float32.
+ * n_bones in 1..4096.  ADR_E_INVALID on bad sizes or missing pointers.
+ * Device work on `stream`; no scratch. */
+adr_status adr_skin_fwd(adr_ctx* ctx, const float* pos, const float* weights, const float* bones, int32_t n_pos,
+                        int32_t n_bones, float* pos_out, float* blend_out, adr_stream stream);
+/* Adjoint of adr_skin_fwd from dL/d pos_out (g_pos_out [n_pos,3], device),
+ * which is consumed (set to zero on exit).  Accumulates g_pos [n_pos,3] +=
+ * dL/d pos and g_weights [n_pos,n_bones] += dL/d weights (each nullable, not
+ * aliasing g_pos_out).  blend: the forward's blend_out for the same weights
+ * and bones.  Each output row is written by one wave: no atomics, the same
+ * bits on every run. */
+adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, const float* blend, int32_t n_pos,
+                        int32_t n_bones, float* g_pos_out, float* g_pos, float* g_weights, adr_stream stream);
+
 /* Stage timing.  When enabled, every render/adam call brackets each of its
  * kernel stages with HIP events on the call's stream; adr_ctx_profile_read
  * waits for them, returns per stage the summed milliseconds and the number
@@ -312,8 +335,9 @@ adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* po
  * 0 vertex frame, 1 transform, 2 raster, 3 shade, 4 antialias+loss,
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
  * 9 adam, 10 mip build, 11 texel adjoint, 12 buffer clears and
- * conversions.  ms and count: host arrays of ADR_N_STAGES. */
-#define ADR_N_STAGES 13
+ * conversions, 13 skinning, 14 skinning adjoint.  ms and count: host arrays
+ * of ADR_N_STAGES. */
+#define ADR_N_STAGES 15
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
 

@@ -37,10 +37,11 @@ JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fwd", "adr_render_bwd",
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
-           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample")
-N_STAGES = 13
+           "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
+           "adr_skin_fwd", "adr_skin_bwd")
+N_STAGES = 15
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
-          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear")
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd")
 
 
 class AdrError(RuntimeError):
@@ -144,6 +145,8 @@ _lib.adr_tess_counts.argtypes = [P, I32, I32, I32, P, P, P]
 _lib.adr_tess_build.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P, P, P, P]
 _lib.adr_tess_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P]
 _lib.adr_tess_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P, P, P]
+_lib.adr_skin_fwd.argtypes = [P, P, P, P, I32, I32, P, P, P]
+_lib.adr_skin_bwd.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
 for _n in EXPORTS[1:]:
     getattr(_lib, _n).restype = I32
 
@@ -594,3 +597,23 @@ def image_downsample(ctx: Context, img, k: int, out=None, stream=None):
     out = torch.empty(B, H, W, 3, dtype=torch.float32, device=img.device) if out is None else out
     _check(_lib.adr_image_downsample(ctx.h, _ptr(img), B, H, W, k, _ptr(out), _stream(stream)))
     return out
+
+
+def skin_fwd(ctx: Context, pos, weights, bones, out=None, blend=None, stream=None):
+    """Dense linear blend skinning (Sec. 5.1, Eq. 2): pos [V,3], weights
+    [V,nb], bones [nb,3,4] device float32 -> (skinned [V,3], blend [V,12])."""
+    V, nb = weights.shape
+    out = torch.empty(V, 3, dtype=torch.float32, device=pos.device) if out is None else out
+    blend = torch.empty(V, 12, dtype=torch.float32, device=pos.device) if blend is None else blend
+    _check(_lib.adr_skin_fwd(ctx.h, _ptr(pos), _ptr(weights), _ptr(bones), V, nb, _ptr(out), _ptr(blend),
+                             _stream(stream)))
+    return out, blend
+
+
+def skin_bwd(ctx: Context, pos, bones, blend, g_out, g_pos=None, g_weights=None, stream=None):
+    """Adjoint of skin_fwd: g_pos += dL/dpos, g_weights += dL/dweights (either
+    may be None); g_out (dL/d skinned positions) is consumed (zeroed)."""
+    V = pos.shape[0]
+    nb = bones.shape[0]
+    _check(_lib.adr_skin_bwd(ctx.h, _ptr(pos), _ptr(bones), _ptr(blend), V, nb, _ptr(g_out), _ptr(g_pos),
+                             _ptr(g_weights), _stream(stream)))

@@ -576,6 +576,38 @@ adr_status adr_image_downsample(adr_ctx* ctx, const float* in, int32_t n_views, 
   return ADR_OK;
 }
 
+static adr_status check_skin(adr_ctx* ctx, int32_t n_pos, int32_t n_bones) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (n_pos < 0) return fail(ADR_E_INVALID, "skin: negative vertex count");
+  if (n_bones < 1 || n_bones > 4096) return fail(ADR_E_INVALID, "skin: n_bones must be in 1..4096");
+  return ADR_OK;
+}
+
+adr_status adr_skin_fwd(adr_ctx* ctx, const float* pos, const float* weights, const float* bones, int32_t n_pos,
+                        int32_t n_bones, float* pos_out, float* blend_out, adr_stream stream) {
+  adr_status r = check_skin(ctx, n_pos, n_bones);
+  if (r != ADR_OK) return r;
+  if (n_pos == 0) return ADR_OK;
+  if (!pos || !weights || !bones || !pos_out) return fail(ADR_E_INVALID, "skin: pos, weights, bones and pos_out are required");
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(13, launch_skin_fwd(n_pos, n_bones, pos, weights, bones, pos_out, blend_out, st), "skinning");
+  return ADR_OK;
+}
+
+adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, const float* blend, int32_t n_pos,
+                        int32_t n_bones, float* g_pos_out, float* g_pos, float* g_weights, adr_stream stream) {
+  adr_status r = check_skin(ctx, n_pos, n_bones);
+  if (r != ADR_OK) return r;
+  if (n_pos == 0) return ADR_OK;
+  if (!pos || !bones || !blend || !g_pos_out) return fail(ADR_E_INVALID, "skin: pos, bones, blend and g_pos_out are required");
+  if (g_pos == g_pos_out) return fail(ADR_E_INVALID, "skin: g_pos must not alias g_pos_out");
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  TIMED(14, launch_skin_bwd(n_pos, n_bones, pos, bones, blend, g_pos_out, g_pos, g_weights, st), "skinning adjoint");
+  return ADR_OK;
+}
+
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
   ctx->prof = enable != 0;

@@ -110,6 +110,10 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st);
+hipError_t launch_skin_fwd(int n, int nb, const float* pos, const float* w, const float* bones, float* out,
+                           float* blend, hipStream_t st);
+hipError_t launch_skin_bwd(int n, int nb, const float* pos, const float* bones, const float* blend, float* gout,
+                           float* gpos, float* gw, hipStream_t st);
 hipError_t launch_downsample(const float* in, int B, int H, int W, int k, float* out, hipStream_t st);
 hipError_t launch_laplacian(int n, const float* pos, const int* offs, const int* nbr, const float* dref,
                             float lambda, float* r, double* part, float* dout, float* loss, float* gpos,

@@ -129,3 +129,64 @@ def oracle_tess_keys(w, mvp32):
         keys.append(k)
         cov.append(c)
     return np.stack(keys), np.stack(cov), vd.numpy()
+
+
+class SkinGpuScene(GpuScene):
+    """A workload with a rig: both meshes are skinned (Eq. 2) with the bone
+    transforms of ``w.frame`` before they are rendered; the latent's
+    gradients end in skin_bwd (bind-pose positions and weights)."""
+
+    def __init__(self, w, ctx, mvp32=None, eye=None):
+        super().__init__(w, ctx, mvp32, eye)
+        self.bones = torch.from_numpy(np.ascontiguousarray(w.rig.bones[w.frame])).cuda()
+        self.ref_bind = torch.from_numpy(w.ref.mesh.pos).cuda()
+        self.ref_w = torch.from_numpy(np.ascontiguousarray(w.rig.ref_weights)).cuda()
+        self.lat_bind = torch.from_numpy(w.latent.mesh.pos).cuda()
+        self.lat_w = torch.from_numpy(np.ascontiguousarray(w.weights)).cuda()
+        self.blend = torch.empty(self.lat_bind.shape[0], 12, dtype=torch.float32, device="cuda")
+
+    def render(self, which="latent", ref=None, flags=0, **kw):
+        if which == "latent":
+            self.adr.skin_fwd(self.ctx, self.lat_bind, self.lat_w, self.bones, out=self.lat_mesh.pos, blend=self.blend)
+        else:
+            self.adr.skin_fwd(self.ctx, self.ref_bind, self.ref_w, self.bones, out=self.ref_mesh.pos)
+        return super().render(which, ref, flags, **kw)
+
+    def grads(self, out, names=("pos", "weights", "kd", "normal"), flags=0):
+        adr = self.adr
+        g = {"pos": torch.zeros_like(self.lat_mesh.pos)}
+        for n in ("kd", "normal", "orm"):
+            tex = getattr(self.lat_mat, n)
+            g[n] = tex.grad_buffer() if (n in names and tex is not None and tex.fmt == adr.TEX_F32) else None
+        adr.render_bwd(self.ctx, self.lat_mesh, self.lat_mat, self.views, out, g, flags=flags)
+        g_bind = torch.zeros_like(self.lat_bind)
+        g_w = torch.zeros_like(self.lat_w)
+        adr.skin_bwd(self.ctx, self.lat_bind, self.bones, self.blend, g["pos"], g_pos=g_bind, g_weights=g_w)
+        torch.cuda.synchronize()
+        res = {"pos": g_bind.cpu().numpy(), "weights": g_w.cpu().numpy(), "g_skinned_max": float(g["pos"].abs().max())}
+        for n in ("kd", "normal", "orm"):
+            t = g[n]
+            if t is None:
+                continue
+            tex = getattr(self.lat_mat, n)
+            res[n] = t[:tex.size * tex.size].cpu().numpy().reshape(tex.size, tex.size, -1)
+        return res
+
+
+def oracle_skinned_keys(w, mvp32, which="latent"):
+    """Oracle visibility of a skinned mesh in every view, and its float64
+    skinned positions."""
+    from oracle import skin as K
+    scene = w.latent if which == "latent" else w.ref
+    wts = w.weights if which == "latent" else w.rig.ref_weights
+    with torch.no_grad():
+        vs = K.skin(torch.as_tensor(scene.mesh.pos, dtype=R.F64), torch.as_tensor(wts, dtype=R.F64),
+                    torch.as_tensor(w.rig.bones[w.frame], dtype=R.F64)).numpy()
+    pos32 = vs.astype(np.float32)
+    keys, cov = [], []
+    for b in range(mvp32.shape[0]):
+        sv = R.snap(pos32, mvp32[b], w.width, w.height)
+        k, c, _ = R.raster(scene.mesh.tri, sv, w.width, w.height)
+        keys.append(k)
+        cov.append(c)
+    return np.stack(keys), np.stack(cov), vs

@@ -28,6 +28,29 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(adr.EXPORTS)
 
 
+def _param_counts():
+    src = open(os.path.join(ROOT, "include", "adr.h")).read()
+    out = {}
+    for m in re.finditer(r"\b(adr_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", src):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_declares_every_signature():
+    # ctypes passes an undeclared argument as a 32-bit int, which cuts a
+    # 64-bit device pointer: every entry point needs its argtypes
+    from paper_2104_03989_amd import adr
+    counts = _param_counts()
+    assert set(counts) == set(adr.EXPORTS)
+    for n, k in counts.items():
+        f = getattr(adr._lib, n)
+        if k == 0:
+            continue
+        assert f.argtypes is not None, n
+        assert len(f.argtypes) == k, (n, len(f.argtypes), k)
+
+
 @pytest.mark.parametrize("nu", [1, 3, 8])
 def test_adjacency_matches_oracle(nu):
     from paper_2104_03989_amd import adr
