@@ -37,6 +37,7 @@ SINGLE_KERNEL_STAGES = {
     "aa_bwd": ("adr::k_aa_bwd", ["aa.hip"]),
     "shade": ("adr::k_shade_fwd", ["shade.hip"]),
     "adam": ("adr::k_adam", ["adam.hip"]),
+    "skin_bwd": ("adr::k_skin_bwd", ["skin.hip"]),
 }
 COMMON_SOURCES = ["dev.h", "internal.h"]
 
@@ -116,7 +117,15 @@ def _log(*a):
 def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False):
     """Upload the workload and return (step(t) closure, state)."""
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
-    ref_mesh.precompute_frame(ctx)          # the reference does not move
+    rig = None
+    if w.rig is None:
+        ref_mesh.precompute_frame(ctx)      # the reference does not move
+    else:
+        # skinned meshes (Eq. 2): bind poses, dense weights and the bone
+        # transforms of every frame stay resident; one frame per step
+        rig = dict(bones=torch.from_numpy(np.ascontiguousarray(w.rig.bones)).cuda(),
+                   ref_bind=ref_mesh.pos.clone(),
+                   ref_w=torch.from_numpy(np.ascontiguousarray(w.rig.ref_weights)).cuda())
     ref_mat = adr.DeviceMaterial(w.ref, ctx=ctx)
     ts = disp = None
     if w.tess_levels:
@@ -148,7 +157,15 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     # optimised parameters: positions and level 0 of the F32 maps
     params = []
     grads = {"pos": torch.zeros_like(lat_mesh.pos)}
-    if ts is None:
+    if rig is not None:
+        rig.update(bind=lat_mesh.pos.clone(), w=torch.from_numpy(np.ascontiguousarray(w.weights)).cuda(),
+                   blend=torch.zeros(lat_mesh.pos.shape[0], 12, device="cuda"))
+        rig.update(g_bind=torch.zeros_like(rig["bind"]), g_w=torch.zeros_like(rig["w"]))
+        params += [(rig["bind"], rig["g_bind"]), (rig["w"], rig["g_w"])]
+        n_frames = rig["bones"].shape[0]
+        adr.skin_fwd(ctx, rig["ref_bind"], rig["ref_w"], rig["bones"][0], out=ref_mesh.pos)
+        adr.skin_fwd(ctx, rig["bind"], rig["w"], rig["bones"][0], out=lat_mesh.pos, blend=rig["blend"])
+    elif ts is None:
         params.append((lat_mesh.pos, grads["pos"]))
     else:
         # base positions and the displacement map (Eq. 3); the tessellated
@@ -185,21 +202,26 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     lap = None
     if laplacian:
         base = ts.base if ts is not None else lat_mesh
+        base_pos = rig["bind"] if rig is not None else base.pos
         ring = adr.DeviceOneRing(base.tri.cpu().numpy(), base.pos.shape[0])
         ld = torch.zeros(1, device="cuda")
-        adr.laplacian(ctx, ring, base.pos, loss=ld)
+        adr.laplacian(ctx, ring, base_pos, loss=ld)
         torch.cuda.synchronize()
         lam0 = 0.25 * float(lat_out["loss"][0]) / max(float(ld[0]), 1e-30)
         lams = [lam0]
         for i in range(1, n_steps):
             lams.append((lams[-1] - 0.02 * lam0) * 10.0 ** (-1e-6 * i) + 0.02 * lam0)
-        g_lap = g_base if ts is not None else grads["pos"]
-        lap = (ring, base, lams, g_lap)
+        g_lap = g_base if ts is not None else (rig["g_bind"] if rig is not None else grads["pos"])
+        lap = (ring, base_pos, lams, g_lap)
 
     def step(t):
         v = views[t % n_steps]
         if ts is not None:
             adr.tess_fwd(ctx, ts, disp)
+        if rig is not None:
+            bones = rig["bones"][t % n_frames]
+            adr.skin_fwd(ctx, rig["ref_bind"], rig["ref_w"], bones, out=ref_mesh.pos)
+            adr.skin_fwd(ctx, rig["bind"], rig["w"], bones, out=lat_mesh.pos, blend=rig["blend"])
         adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_out, flags=dflag & adr.DETERMINISTIC)
         if k > 1:
             adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
@@ -207,14 +229,17 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
+        if rig is not None:
+            adr.skin_bwd(ctx, rig["bind"], bones, rig["blend"], grads["pos"], g_pos=rig["g_bind"], g_weights=rig["g_w"])
         if lap is not None:
-            ring, base, lams, g_lap = lap
-            adr.laplacian(ctx, ring, base.pos, None, lams[t % n_steps], g_pos=g_lap)
+            ring, base_pos, lams, g_lap = lap
+            adr.laplacian(ctx, ring, base_pos, None, lams[t % n_steps], g_pos=g_lap)
         lr = w.lr * 10.0 ** (-0.0002 * t)
         adr.adam_step(ctx, adam, t + 1, lr)
 
     state = dict(ref_mesh=ref_mesh, lat_mesh=lat_mesh, lat_mat=lat_mat, lat_out=lat_out,
-                 ref_out=ref_out, n_params=n_params, views=views, adam=adam)
+                 ref_out=ref_out, n_params=n_params, views=views, adam=adam,
+                 skin=None if rig is None else tuple(rig["w"].shape))
     return step, state
 
 
@@ -256,6 +281,11 @@ def algorithmic_bytes(stage, w, st, covered_latent):
         return px * (8 + 12 + 12 + 12) / 2.0              # per render (two per step, averaged)
     if stage == "shade":
         return px * (8 + 12)                              # key in, colour out
+    if stage == "skin_bwd" and st.get("skin"):
+        V, nb = st["skin"]
+        # per vertex: dL/dskinned read + cleared, bind position, blended
+        # matrix, dL/dweights and dL/dpos read-modify-write; the bones once
+        return V * (12 + 12 + 12 + 48 + 8 * nb + 24) + 48 * nb
     return None
 
 
@@ -368,6 +398,9 @@ WORKLOADS = {
                      "and displaced by a 1024^2 map, 1024^2 normal map, 8 views x 512x512, L1, Adam"),
     "plain": ("plain single step: 20,480-tri SH reference, 1,280-tri latent, 256^2 maps, 4 views x 256x256, "
               "Blinn-Phong, L1, Adam"),
+    "animation": ("animation: 19,220-tri GGX reference skinned to a 32-bone rig (40 frames, one per step), "
+                  "5,120-tri latent with dense 32-bone weights, bind pose and 1024^2 maps optimised, "
+                  "8 views x 512x512, tone-mapped L1, Adam"),
     "prefilter": ("prefiltering: 297,680-tri GGX reference with 8x8 supersampling, 7,220-tri latent with 4x4 "
                   "multisampled visibility and independent-mip 512^2 maps, 8 views x 128x128, tone-mapped L1, Adam"),
 }
@@ -381,6 +414,8 @@ def make_workload(name):
         return synth.workload_displacement(), 3
     if name == "prefilter":
         return synth.workload_prefilter(), 6
+    if name == "animation":
+        return synth.workload_animation(), 7
     return synth.workload_plain_step(), 1
 
 

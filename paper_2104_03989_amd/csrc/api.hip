@@ -62,7 +62,7 @@ struct Span {
 struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, partial, gcolor, dclip, dattr, texrec, image_s;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -209,7 +209,8 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       (r = ensure(ctx->orient, B * T)) || (r = ensure(ctx->nacc, V * 24)) ||
       (r = ensure(ctx->tacc, V * 24)) || (r = ensure(ctx->nrm, V * 12)) ||
       (r = ensure(ctx->tan, V * 12)) || (r = ensure(ctx->big, B * T * 4)) ||
-      (r = ensure(ctx->big_cnt, B * 4)) || (r = ensure(ctx->partial, tiles * 4)))
+      (r = ensure(ctx->big_cnt, (B + 1) * 4)) || (r = ensure(ctx->med, B * T * 4)) ||
+      (r = ensure(ctx->partial, tiles * 4)))
     return r;
   if (bwd) {
     if ((r = ensure(ctx->gcolor, B * v.W * v.H * 12)) || (r = ensure(ctx->dclip, B * V * 16)) ||
@@ -265,6 +266,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
   s.tan = (float*)ctx->tan.p;
   s.big = (uint32_t*)ctx->big.p;
   s.big_cnt = (uint32_t*)ctx->big_cnt.p;
+  s.med = (uint32_t*)ctx->med.p;
   s.partial = (float*)ctx->partial.p;
   s.gcolor = (float*)ctx->gcolor.p;
   s.dclip = (float*)ctx->dclip.p;
@@ -322,7 +324,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
                  &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
-                 &ctx->big, &ctx->big_cnt, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
+                 &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
     (void)hipEventDestroy(sp.a);

@@ -50,7 +50,8 @@ struct Scratch {
   float* nrm;         // [V,3]
   float* tan;         // [V,3]
   uint32_t* big;      // [B,T] big-triangle lists (per view segments of T)
-  uint32_t* big_cnt;  // [B]
+  uint32_t* big_cnt;  // [B + 1]: per-view big-triangle counts, then the medium-queue count
+  uint32_t* med;      // [B * n_tri] medium-triangle queue (view * n_tri + triangle)
   float* partial;     // loss partials
   float* gcolor;      // [B,H,W,3] dL/d(colour before AA)
   float* dclip;       // [B,V,4]

@@ -15,8 +15,9 @@
 //
 // Work split: a triangle whose pixel bounding box holds at most kTinyBBox
 // pixel centres is walked by one thread (most triangles of dense meshes are
-// pixel-sized), one of up to kMedBBox by all lanes of its wave together;
-// larger ones go to a per-view list that a second kernel bins against 16x16
+// pixel-sized); one of up to kMedBBox goes to a queue whose entries a second
+// kernel spreads over all waves of the chip, one triangle per wave at a time;
+// larger ones go to a per-view list that a third kernel bins against 16x16
 // tiles in LDS and resolves one pixel per thread.
 // This file is compiled with -ffp-contract=off.
 #include "dev.h"
@@ -148,7 +149,7 @@ __global__ void k_clear(uint64_t* __restrict__ vis, uint32_t* __restrict__ cov, 
     vis[i] = kKeyEmpty;
     if (cov) cov[i] = 0u;
   }
-  if (gid < B) big_cnt[gid] = 0u;
+  if (gid <= B) big_cnt[gid] = 0u;   // B per-view big counts and the medium-queue count
 }
 
 __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j, int W,
@@ -163,12 +164,11 @@ __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j
 
 // One thread per triangle and view.  A triangle whose pixel bounding box
 // holds at most kTinyBBox pixel centres is walked by its thread; up to
-// kMedBBox the whole wave walks it, one pixel per lane (the triangle's set-up
-// is recomputed from wave-uniform indices); larger ones go to the view's
-// list for the tile kernel.
+// kMedBBox it is queued for k_raster_med (big_cnt[B] counts the queue);
+// larger ones go to the view's list for the tile kernel.
 __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const int4* __restrict__ snap,
                                                       int8_t* __restrict__ orient, uint32_t* __restrict__ big,
-                                                      uint32_t* __restrict__ big_cnt,
+                                                      uint32_t* __restrict__ big_cnt, uint32_t* __restrict__ med,
                                                       unsigned long long* __restrict__ vis,
                                                       uint32_t* __restrict__ cov) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,24 +197,60 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
     for (int j = bb.j0; j <= bb.j1; ++j)
       for (int i = bb.i0; i <= bb.i1; ++i) raster_pixel(s, t, i, j, v.W, vv, cv);
   }
-  // medium triangles of this wave, one after the other, by all its lanes
+  // medium triangles of this wave: one queue reservation per wave
   const int lane = threadIdx.x & 63;
-  unsigned long long todo = __ballot(area > kTinyBBox && area <= kMedBBox);
-  while (todo) {
-    const int leader = __ffsll((long long)todo) - 1;
-    todo &= todo - 1;
-    const int g = __builtin_amdgcn_readlane(gid, leader);
-    const int bw = g / m.n_tri, tw = g - bw * m.n_tri;
-    Setup sw;
-    int3 c = make_int3(m.tri[3 * tw], m.tri[3 * tw + 1], m.tri[3 * tw + 2]);
-    setup_tri(snap + (int64_t)bw * m.n_pos, c, sw);  // succeeded for the leader
-    const BBox bw_ = pixel_bbox(sw, v.W, v.H);
-    const int nx = bw_.i1 - bw_.i0 + 1, n = nx * (bw_.j1 - bw_.j0 + 1);
-    unsigned long long* vv = vis + bw * HW;
-    uint32_t* cv = cov ? cov + bw * HW : nullptr;
-    for (int q = lane; q < n; q += 64) {
-      const int jj = q / nx;
-      raster_pixel(sw, tw, bw_.i0 + (q - jj * nx), bw_.j0 + jj, v.W, vv, cv);
+  const bool is_med = area > kTinyBBox && area <= kMedBBox;
+  const unsigned long long mm = __ballot(is_med);
+  if (mm) {
+    const int leader = __ffsll((long long)mm) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(big_cnt + v.B, (uint32_t)__popcll(mm));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    if (is_med) med[base + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint32_t)gid;
+  }
+}
+
+// Queued medium triangles, one per wave at a time (a grid-stride loop over
+// the queue).  The wave walks the triangle's bounding box in blocks of
+// bw x (64 / bw) pixels, bw in 8..64 chosen per triangle to waste the fewest
+// lanes.
+__global__ __launch_bounds__(256) void k_raster_med(MeshD m, ViewsD v, const int4* __restrict__ snap,
+                                                    const uint32_t* __restrict__ med,
+                                                    const uint32_t* __restrict__ big_cnt,
+                                                    unsigned long long* __restrict__ vis,
+                                                    uint32_t* __restrict__ cov) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t n_waves = gridDim.x * (blockDim.x >> 6);
+  const uint32_t cnt = big_cnt[v.B];
+  const int64_t HW = (int64_t)v.W * v.H;
+  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < cnt; q += n_waves) {
+    const int g = (int)med[q];
+    const int b = g / m.n_tri, t = g - b * m.n_tri;
+    const int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
+    Setup s;
+    if (!setup_tri(snap + (int64_t)b * m.n_pos, c, s)) continue;  // queued triangles always set up
+    const BBox bb = pixel_bbox(s, v.W, v.H);
+    const int nx = bb.i1 - bb.i0 + 1, ny = bb.j1 - bb.j0 + 1;
+    int lb = 3, fewest = 0x7fffffff;
+#pragma unroll
+    for (int l = 3; l <= 6; ++l) {
+      const int bh = 64 >> l;
+      const int blocks = ((nx + (1 << l) - 1) >> l) * ((ny + bh - 1) / bh);
+      if (blocks < fewest) {
+        fewest = blocks;
+        lb = l;
+      }
+    }
+    const int bw = 1 << lb, bh = 64 >> lb;
+    const int lx = lane & (bw - 1), ly = lane >> lb;
+    unsigned long long* vv = vis + b * HW;
+    uint32_t* cv = cov ? cov + b * HW : nullptr;
+    for (int y0 = bb.j0; y0 <= bb.j1; y0 += bh) {
+      const int y = y0 + ly;
+      for (int x0 = bb.i0; x0 <= bb.i1; x0 += bw) {
+        const int x = x0 + lx;
+        if (x <= bb.i1 && y <= bb.j1) raster_pixel(s, t, x, y, v.W, vv, cv);
+      }
     }
   }
 }
@@ -294,7 +330,7 @@ hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* b
                             hipStream_t st) {
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  if (blocks < (B + 255) / 256) blocks = (B + 255) / 256;
+  if (blocks < (B + 256) / 256) blocks = (B + 256) / 256;   // threads for the B + 1 counters
   hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, vis, cov, n, big_cnt, B);
   return hipGetLastError();
 }
@@ -306,9 +342,13 @@ hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint
   const int4* sv = reinterpret_cast<const int4*>(s.snap);
   auto* vk = reinterpret_cast<unsigned long long*>(vis);
   hipLaunchKernelGGL(k_raster_small, dim3((n + 255) / 256), dim3(256), 0, st, m, v, sv, s.orient,
-                     s.big, s.big_cnt, vk, cov);
+                     s.big, s.big_cnt, s.med, vk, cov);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // enough waves to fill the chip; each loops over the queue
+  const int med_blocks = std::min((n + 3) / 4, 4096);
+  hipLaunchKernelGGL(k_raster_med, dim3(med_blocks), dim3(256), 0, st, m, v, sv, s.med, s.big_cnt, vk, cov);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   int tx = (v.W + kBigTile - 1) / kBigTile, ty = (v.H + kBigTile - 1) / kBigTile;
   hipLaunchKernelGGL(k_raster_big, dim3(tx * ty * v.B), dim3(256), 0, st, m, v, sv, s.big,
                      s.big_cnt, vk, cov, tx, ty);
