@@ -12,6 +12,7 @@ import types
 import numpy as np
 import torch
 
+from . import oit as O
 from . import render as R
 from . import skin as K
 from . import tess as T
@@ -68,6 +69,15 @@ def render_latent(w, mvp32, eye, params=None, aa=True, frozen=None, round32=True
     Positions a mesh operation computes are rounded to float32 (``round32``)."""
     params = params or {}
     msaa = getattr(w, "msaa", 1)
+    if getattr(w, "oit_layers", 0):
+        s = w.latent
+        pos = params.get("pos", torch.as_tensor(s.mesh.pos, dtype=R.F64))
+        al = _levels(s.alpha, params.get("alpha")) if s.alpha is not None else None
+        orm = _levels(s.orm, params.get("orm")) if s.orm is not None else None
+        return O.render_oit(s.mesh, s.model, _levels(s.kd, params.get("kd")), _levels(s.normal, params.get("normal")),
+                            orm, al, pos, mvp32, np.asarray(eye, dtype=np.float64),
+                            np.asarray(w.light_dir, dtype=np.float64), np.asarray(w.light_rgb, dtype=np.float64),
+                            w.width, w.height, w.oit_layers, aa=aa, frozen=frozen)
     if getattr(w, "rig", None) is not None:
         pos0 = params.get("pos", torch.as_tensor(w.latent.mesh.pos, dtype=R.F64))
         wts = params.get("weights", torch.as_tensor(w.weights, dtype=R.F64))

@@ -217,6 +217,48 @@ void oracle_raster(const int32_t* tri, int32_t n_tri, const int32_t* snapv, int3
 }
 
 /*
+ * One depth-peeling pass of one view (Sec. 5.2, "Order-independent
+ * transparency"): keys[o] receives the smallest key strictly greater than
+ * floor[o] among the fragments covering pixel o (the two-sided test against
+ * the previous layer), KEY_EMPTY if there is none.  floor: [H*W] or NULL (no
+ * lower bound: the plain front layer).  brute as for oracle_raster.
+ */
+void oracle_raster_peel(const int32_t* tri, int32_t n_tri, const int32_t* snapv, int32_t W, int32_t H,
+                        const uint64_t* floor_keys, uint64_t* keys, int32_t brute) {
+  for (int64_t i = 0; i < (int64_t)W * H; ++i) keys[i] = KEY_EMPTY;
+  for (int32_t t = 0; t < n_tri; ++t) {
+    tri_setup_t s;
+    if (!setup_triangle(snapv, tri + 3 * t, &s)) continue;
+    int64_t i0 = 0, i1 = W - 1, j0 = 0, j1 = H - 1;
+    if (!brute) {
+      int64_t mnx = s.X[0], mxx = s.X[0], mny = s.Y[0], mxy = s.Y[0];
+      for (int k = 1; k < 3; ++k) {
+        if (s.X[k] < mnx) mnx = s.X[k];
+        if (s.X[k] > mxx) mxx = s.X[k];
+        if (s.Y[k] < mny) mny = s.Y[k];
+        if (s.Y[k] > mxy) mxy = s.Y[k];
+      }
+      i0 = floor_div(mnx - 128 + 255, 256); i1 = floor_div(mxx - 128, 256);
+      j0 = floor_div(mny - 128 + 255, 256); j1 = floor_div(mxy - 128, 256);
+      if (i0 < 0) i0 = 0;
+      if (j0 < 0) j0 = 0;
+      if (i1 > W - 1) i1 = W - 1;
+      if (j1 > H - 1) j1 = H - 1;
+    }
+    for (int64_t j = j0; j <= j1; ++j) {
+      for (int64_t i = i0; i <= i1; ++i) {
+        int64_t px = 256 * i + 128, py = 256 * j + 128;
+        if (!covers(&s, px, py)) continue;
+        uint64_t key = ((uint64_t)depth_at(&s, px, py) << 32) | (uint32_t)(t + 1);
+        int64_t o = j * W + i;
+        if (floor_keys && key <= floor_keys[o]) continue;
+        if (key < keys[o]) keys[o] = key;
+      }
+    }
+  }
+}
+
+/*
  * Integer inside test of the oriented edges of triangle t at pixel (i, j):
  * bit k of the result is set if the pixel centre is on the inside of the
  * oriented edge opposite oriented corner k (top-left rule included).  Also

@@ -75,6 +75,7 @@ def _lib():
         lib.oracle_snap.argtypes = [P, I, P, I, I, P]
         lib.oracle_clip32.argtypes = [P, I, P, P]
         lib.oracle_raster.argtypes = [P, I, P, I, I, P, P, P, I]
+        lib.oracle_raster_peel.argtypes = [P, I, P, I, I, P, P, I]
         lib.oracle_edge_inside_batch.argtypes = [P, P, I, P, P, P, P, P]
         _LIB = lib
     return _LIB
@@ -111,6 +112,19 @@ def raster(tri: np.ndarray, snapv: np.ndarray, W: int, H: int, brute: bool = Fal
     _lib().oracle_raster(_ptr(tri), tri.shape[0], _ptr(snapv), W, H, _ptr(keys), _ptr(cov),
                          _ptr(orient), 1 if brute else 0)
     return keys, cov, orient
+
+
+def raster_peel(tri: np.ndarray, snapv: np.ndarray, W: int, H: int, floor_keys: np.ndarray | None,
+                brute: bool = False) -> np.ndarray:
+    """One depth-peeling pass: per pixel the smallest fragment key above
+    ``floor_keys`` (None: the front layer), uint64 [H,W]."""
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    snapv = np.ascontiguousarray(snapv, dtype=np.int32)
+    keys = np.zeros((H, W), dtype=np.uint64)
+    fl = None if floor_keys is None else np.ascontiguousarray(floor_keys, dtype=np.uint64)
+    _lib().oracle_raster_peel(_ptr(tri), tri.shape[0], _ptr(snapv), W, H, None if fl is None else _ptr(fl),
+                              _ptr(keys), 1 if brute else 0)
+    return keys
 
 
 def edge_inside(tri, snapv, t, i, j):
@@ -502,6 +516,72 @@ def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = 
     return mip_chain_f32(base)
 
 
+def shade_view(keys, tri, uv, uv_tri, pos, nrm, tan, clip, model, kd_levels, nrm_levels, orm_levels,
+               eye_b, light_dir_b, light_rgb_b, W, H, m=1, alpha_levels=None, keep_gbuf=False):
+    """Deferred shading of one view's visibility samples (Sec. 5.2): the
+    colour [Hs*Ws,3] of each sample's triangle evaluated at its pixel centre
+    (zero where empty), with ``alpha_levels`` the clamped alpha [Hs*Ws] of
+    the same lookup (Sec. 4.4, transparency; zero where empty), and the
+    G-buffer if asked for."""
+    Hs, Ws = keys.shape
+    gbuf = None
+    alpha = torch.zeros(Hs * Ws, dtype=F64) if alpha_levels is not None else None
+    ids = key_tri(keys).reshape(-1)
+    pix = np.nonzero(ids)[0]
+    color = torch.zeros(Hs * Ws, 3, dtype=F64)
+    if pix.size:
+        t_idx = torch.from_numpy(ids[pix] - 1)
+        # the pixel of each sample; shading is evaluated at its centre
+        i = torch.from_numpy(((pix % Ws) // m).astype(np.float64))
+        j = torch.from_numpy(((pix // Ws) // m).astype(np.float64))
+        px = 2.0 * (i + 0.5) / W - 1.0
+        py = 2.0 * (j + 0.5) / H - 1.0
+        corners = tri[t_idx]                      # [N,3]
+        hh = clip[corners][:, :, [0, 1, 3]]       # [N,3,3] (x, y, w)
+        k = torch.stack([torch.cross(hh[:, 1], hh[:, 2], dim=1),
+                         torch.cross(hh[:, 2], hh[:, 0], dim=1),
+                         torch.cross(hh[:, 0], hh[:, 1], dim=1)], dim=1)  # [N,3,3]
+        D = k[:, :, 0] * px[:, None] + k[:, :, 1] * py[:, None] + k[:, :, 2]
+        S = D.sum(1, keepdim=True)
+        lam = D / S
+        Ka = k[:, :, 0].sum(1, keepdim=True)
+        Kb = k[:, :, 1].sum(1, keepdim=True)
+        dlam_dx = (k[:, :, 0] - lam * Ka) / S * (2.0 / W)
+        dlam_dy = (k[:, :, 1] - lam * Kb) / S * (2.0 / H)
+        def interp(attr, idx):
+            return (lam[:, :, None] * attr[idx]).sum(1)
+        x = interp(pos, corners)
+        N = safe_normalize(interp(nrm, corners))
+        T = interp(tan, corners)
+        tcorn = uv_tri[t_idx]
+        uvc = uv[tcorn]                           # [N,3,2]
+        uvp = (lam[:, :, None] * uvc).sum(1)
+        duv_dx = (dlam_dx[:, :, None] * uvc).sum(1)
+        duv_dy = (dlam_dy[:, :, None] * uvc).sum(1)
+        Tp = safe_normalize(T - _dot(N, T) * N)
+        Bt = torch.cross(N, Tp, dim=1)
+        kd = sample_trilinear(kd_levels, uvp, duv_dx, duv_dy)
+        nt = sample_trilinear(nrm_levels, uvp, duv_dx, duv_dy)
+        n = safe_normalize(nt[:, 0:1] * Tp + nt[:, 1:2] * Bt + nt[:, 2:3] * N)
+        e = _t(eye_b)[None, :]
+        v = safe_normalize(e - x)
+        l = _t(light_dir_b)[None, :].expand_as(n)
+        E = _t(light_rgb_b)[None, :]
+        if model == "blinn_phong":
+            c = shade_blinn_phong(n, l, v, kd, E)
+        else:
+            orm = sample_trilinear(orm_levels, uvp, duv_dx, duv_dy)
+            c = shade_ggx(n, l, v, kd, orm, E)
+        color = color.index_put((torch.from_numpy(pix),), c)
+        if alpha_levels is not None:
+            a = torch.clamp(sample_trilinear(alpha_levels, uvp, duv_dx, duv_dy)[:, 0], 0.0, 1.0)
+            alpha = alpha.index_put((torch.from_numpy(pix),), a)
+        if keep_gbuf:
+            gbuf = dict(pix=pix, lam=lam.detach(), x=x.detach(), N=N.detach(), uv=uvp.detach(),
+                        duv_dx=duv_dx.detach(), duv_dy=duv_dy.detach(), n=n.detach(), kd=kd.detach())
+    return color, alpha, gbuf
+
+
 def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tensor,
            mvp32: np.ndarray, eye: np.ndarray, light_dir: np.ndarray, light_rgb: np.ndarray,
            W: int, H: int, adj: np.ndarray | None = None, aa: bool = True,
@@ -540,57 +620,10 @@ def render(mesh, model: str, kd_levels, nrm_levels, orm_levels, pos: torch.Tenso
             keys, cov, orient = raster(tri_np, sv, Ws, Hs)
         else:
             keys, cov = frozen["keys"][b], frozen["coverage"][b]
-        ids = key_tri(keys).reshape(-1)
-        pix = np.nonzero(ids)[0]
-        color = torch.zeros(Hs * Ws, 3, dtype=F64)
-        if pix.size:
-            t_idx = torch.from_numpy(ids[pix] - 1)
-            # the pixel of each sample; shading is evaluated at its centre
-            i = torch.from_numpy(((pix % Ws) // m).astype(np.float64))
-            j = torch.from_numpy(((pix // Ws) // m).astype(np.float64))
-            px = 2.0 * (i + 0.5) / W - 1.0
-            py = 2.0 * (j + 0.5) / H - 1.0
-            corners = tri[t_idx]                      # [N,3]
-            hh = clip[corners][:, :, [0, 1, 3]]       # [N,3,3] (x, y, w)
-            k = torch.stack([torch.cross(hh[:, 1], hh[:, 2], dim=1),
-                             torch.cross(hh[:, 2], hh[:, 0], dim=1),
-                             torch.cross(hh[:, 0], hh[:, 1], dim=1)], dim=1)  # [N,3,3]
-            D = k[:, :, 0] * px[:, None] + k[:, :, 1] * py[:, None] + k[:, :, 2]
-            S = D.sum(1, keepdim=True)
-            lam = D / S
-            Ka = k[:, :, 0].sum(1, keepdim=True)
-            Kb = k[:, :, 1].sum(1, keepdim=True)
-            dlam_dx = (k[:, :, 0] - lam * Ka) / S * (2.0 / W)
-            dlam_dy = (k[:, :, 1] - lam * Kb) / S * (2.0 / H)
-            def interp(attr, idx):
-                return (lam[:, :, None] * attr[idx]).sum(1)
-            x = interp(pos, corners)
-            N = safe_normalize(interp(nrm, corners))
-            T = interp(tan, corners)
-            tcorn = uv_tri[t_idx]
-            uvc = uv[tcorn]                           # [N,3,2]
-            uvp = (lam[:, :, None] * uvc).sum(1)
-            duv_dx = (dlam_dx[:, :, None] * uvc).sum(1)
-            duv_dy = (dlam_dy[:, :, None] * uvc).sum(1)
-            Tp = safe_normalize(T - _dot(N, T) * N)
-            Bt = torch.cross(N, Tp, dim=1)
-            kd = sample_trilinear(kd_levels, uvp, duv_dx, duv_dy)
-            nt = sample_trilinear(nrm_levels, uvp, duv_dx, duv_dy)
-            n = safe_normalize(nt[:, 0:1] * Tp + nt[:, 1:2] * Bt + nt[:, 2:3] * N)
-            e = _t(eye[b])[None, :]
-            v = safe_normalize(e - x)
-            l = _t(light_dir[b])[None, :].expand_as(n)
-            E = _t(light_rgb[b])[None, :]
-            if model == "blinn_phong":
-                c = shade_blinn_phong(n, l, v, kd, E)
-            else:
-                orm = sample_trilinear(orm_levels, uvp, duv_dx, duv_dy)
-                c = shade_ggx(n, l, v, kd, orm, E)
-            color = color.index_put((torch.from_numpy(pix),), c)
-            if keep_gbuf:
-                gbufs.append(dict(pix=pix, lam=lam.detach(), x=x.detach(), N=N.detach(),
-                                  uv=uvp.detach(), duv_dx=duv_dx.detach(), duv_dy=duv_dy.detach(),
-                                  n=n.detach(), kd=kd.detach()))
+        color, _, gb = shade_view(keys, tri, uv, uv_tri, pos, nrm, tan, clip, model, kd_levels, nrm_levels,
+                                  orm_levels, eye[b], light_dir[b], light_rgb[b], W, H, m, keep_gbuf=keep_gbuf)
+        if gb is not None:
+            gbufs.append(gb)
         pairs = aa_pairs(keys, tri_np, sv, orient, adj) if frozen is None else frozen["pairs"][b]
         img = antialias(color, clip, pairs, Ws, Hs) if aa else color
         if m > 1:

@@ -296,6 +296,7 @@ class Scene:
     kd: Texture
     normal: Texture
     orm: Texture | None
+    alpha: Texture | None = None   # [S,S,1] f32 transparency map (depth-peeled rendering only)
 
 
 @dataclasses.dataclass
@@ -320,6 +321,7 @@ class Workload:
     rig: "Rig | None" = None      # skeletal animation shared by reference and latent
     weights: np.ndarray | None = None   # [V_latent, n_bones] float32 initial latent skinning weights
     frame: int = 0                # animation frame a single step renders
+    oit_layers: int = 0           # latent rendered with this many depth-peeled layers (0: opaque)
 
 
 @dataclasses.dataclass
@@ -530,6 +532,85 @@ def workload_animation(views: int = 8, res: int = 512, map_size: int = 1024, ref
     light = random_unit(views, seed_for(c, 8))
     return Workload("animation", ref, lat, dirs, light, np.ones((views, 3)), res, res, 3.0, 45.0, "l1_tonemap",
                     2e-3, ("pos", "weights", "kd", "normal", "orm"), rig=rig, weights=weights)
+
+
+def leaf_cloud(n_leaves: int, seed: int, radius: float = 1.0, size: float = 0.06, rim: int = 8,
+               uv_extent: float = 0.02) -> Mesh:
+    """Aggregate geometry: n_leaves flat elliptic leaves (a fan of ``rim``
+    triangles each) at uniform positions in a ball, random orientations,
+    each mapping to a small random region of the texture."""
+    g = _rng(seed)
+    c = g.normal(size=(n_leaves, 3))
+    c *= (radius * g.uniform(0.0, 1.0, n_leaves) ** (1.0 / 3.0) / np.linalg.norm(c, axis=1))[:, None]
+    nrm = random_unit(n_leaves, seed + 1)
+    helper = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+    t1 = np.cross(nrm, helper)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    a = size * g.uniform(0.7, 1.3, n_leaves)
+    bb = 0.5 * a
+    ang = 2.0 * np.pi * np.arange(rim) / rim
+    ring = (a[:, None, None] * np.cos(ang)[None, :, None] * t1[:, None, :]
+            + bb[:, None, None] * np.sin(ang)[None, :, None] * t2[:, None, :])
+    pos = np.concatenate([c[:, None, :], c[:, None, :] + ring], axis=1).reshape(-1, 3)
+    uc = g.uniform(uv_extent, 1.0 - uv_extent, size=(n_leaves, 2))
+    uv_ring = np.stack([np.cos(ang), 0.5 * np.sin(ang)], axis=1) * uv_extent
+    uv = np.concatenate([uc[:, None, :], uc[:, None, :] + uv_ring[None]], axis=1).reshape(-1, 2)
+    base = (np.arange(n_leaves) * (rim + 1))[:, None]
+    k = np.arange(rim)
+    tri = np.stack([np.zeros(rim, np.int64), 1 + k, 1 + (k + 1) % rim], axis=1)[None] + base[:, :, None]
+    tri = tri.reshape(-1, 3).astype(np.int32)
+    return Mesh(pos.astype(np.float32), tri, uv.astype(np.float32), tri.copy())
+
+
+def quad_cloud(n_quads: int, seed: int, radius: float = 1.0, size: float = 0.15) -> Mesh:
+    """Billboard quads (two triangles each) at uniform positions in a ball
+    with random orientations, each mapped to its own cell of a square
+    texture atlas (ceil(sqrt(n)) cells per side, half a cell-texel margin)."""
+    g = _rng(seed)
+    c = g.normal(size=(n_quads, 3))
+    c *= (radius * g.uniform(0.0, 1.0, n_quads) ** (1.0 / 3.0) / np.linalg.norm(c, axis=1))[:, None]
+    nrm = random_unit(n_quads, seed + 1)
+    helper = np.where(np.abs(nrm[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]), np.array([[0.0, 1.0, 0.0]]))
+    t1 = np.cross(nrm, helper)
+    t1 /= np.linalg.norm(t1, axis=1, keepdims=True)
+    t2 = np.cross(nrm, t1)
+    h = 0.5 * size
+    corners = np.array([(-1, -1), (1, -1), (-1, 1), (1, 1)], dtype=np.float64)
+    pos = (c[:, None, :] + h * corners[None, :, 0:1] * t1[:, None, :]
+           + h * corners[None, :, 1:2] * t2[:, None, :]).reshape(-1, 3)
+    n = int(math.ceil(math.sqrt(n_quads)))
+    cell = 1.0 / n
+    q = np.arange(n_quads)
+    cu, cv = (q % n) * cell, (q // n) * cell
+    m = 0.02 * cell
+    uvc = (np.array([(0, 0), (1, 0), (0, 1), (1, 1)], dtype=np.float64) * (cell - 2 * m) + m)
+    uv = (np.stack([cu, cv], 1)[:, None, :] + uvc[None]).reshape(-1, 2)
+    base = (4 * q)[:, None, None]
+    tri = (np.array([[0, 1, 3], [0, 3, 2]])[None] + base).reshape(-1, 3).astype(np.int32)
+    return Mesh(pos.astype(np.float32), tri, uv.astype(np.float32), tri.copy())
+
+
+def workload_aggregate(views: int = 8, res: int = 512, map_size: int = 2048, n_leaves: int = 150_000,
+                       n_quads: int = 4800, layers: int = 8) -> Workload:
+    """Aggregate geometry (Sec. 4.4): a foliage stand-in of 150,000 leaves
+    (1.2M triangles) against 4,800 textured quads (9,600 triangles, 0.8%)
+    whose base colour, normal and transparency maps (2048^2 atlases) and
+    positions are optimised; the latent is rendered with 8 depth-peeled
+    layers; 8 views at 512^2, a light per view, Blinn-Phong, squared L2."""
+    c = 8
+    leaves = leaf_cloud(n_leaves, seed_for(c, 1))
+    kd_ref = Texture(to_rgba8(0.15 + 0.6 * value_noise_map(1024, 3, seed_for(c, 2)) * np.array([0.5, 1.0, 0.3])),
+                     "rgba8")
+    ref = Scene(leaves, "blinn_phong", kd_ref, _f32(flat_normal_map(1)), None)
+    quads = quad_cloud(n_quads, seed_for(c, 3))
+    kd_lat = 0.3 + 0.1 * _rng(seed_for(c, 4)).uniform(-1.0, 1.0, size=(map_size, map_size, 3))
+    lat = Scene(quads, "blinn_phong", _f32(kd_lat), _f32(flat_normal_map(map_size)), None,
+                _f32(np.full((map_size, map_size, 1), 0.5)))
+    dirs = random_unit(views, seed_for(c, 5))
+    light = random_unit(views, seed_for(c, 6))
+    return Workload("aggregate", ref, lat, dirs, light, np.ones((views, 3)), res, res, 3.0, 45.0, "l2", 1e-3,
+                    ("pos", "kd", "normal", "alpha"), oit_layers=layers)
 
 
 def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:
