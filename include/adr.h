@@ -109,6 +109,8 @@ typedef struct adr_material {
   adr_texture kd;                /* F32 3 channels or RGBA8 */
   adr_texture normal;            /* F32 3 channels, tangent space (x along T, y along N x T, z along N) */
   adr_texture orm;               /* F32 3 channels (gamma, r, m); GGX only */
+  adr_texture alpha;             /* F32 1 channel transparency, clamped to [0, 1]; optional (data NULL:
+                                    opaque); read by the depth-peeled entry points only */
 } adr_material;
 
 /* B cameras and directional lights (Sec. 3: random camera and light per
@@ -188,6 +190,7 @@ typedef struct adr_grads {
   float* kd;                     /* nullable; F32 kd only */
   float* normal;                 /* nullable */
   float* orm;                    /* nullable; GGX only */
+  float* alpha;                  /* nullable; depth-peeled entry points with an alpha map only */
 } adr_grads;
 
 /* Hand-written adjoint of adr_render_fwd w.r.t. vertex positions and F32
@@ -199,6 +202,46 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
                           const adr_views* views, const adr_fwd_out* saved,
                           const float* dloss, const adr_grads* grads, int32_t flags,
                           adr_stream stream);
+
+/* ------------------------------------ order-independent transparency */
+
+/* Depth-peeled rendering (Sec. 5.2, "Order-independent transparency"; the
+ * aggregate-geometry application, Sec. 4.4).  Layer 0 is the plain
+ * visibility; layer k keeps per pixel the nearest fragment strictly behind
+ * layer k-1's (the two-sided test, on the 64-bit keys: depth, then triangle
+ * id, so layer k is the pixel's k-th smallest fragment key).  Each layer is
+ * shaded (colour c_k, alpha a_k = clamp(alpha map, 0, 1), or 1 without a
+ * map), then the layers are blended back to front from a black background:
+ * B_k = a_k c_k + (1 - a_k) C_{k+1} where layer k covers the pixel, else
+ * C_{k+1}; C_k = silhouette antialiasing of B_k with layer k's keys;
+ * image = C_0.  All buffers are caller-owned device memory, layer-major. */
+typedef struct adr_oit_out {
+  int32_t n_layers;              /* 1..16 */
+  uint64_t* vis;                 /* [L,B,H,W] required: keys of each layer (empty 0xFFFFFFFF00000000) */
+  float* color;                  /* [L,B,H,W,3] required: c_k (0 where empty) */
+  float* alpha;                  /* [L,B,H,W] required: a_k (0 where empty) */
+  float* blend;                  /* [L,B,H,W,3] required: B_k */
+  float* comp;                   /* [L,B,H,W,3] required: C_k; C_0 is the image */
+  float* dimage;                 /* [B,H,W,3] required with a reference: dL/d image */
+  float* loss;                   /* [1] required with a reference */
+} adr_oit_out;
+
+/* Forward of the depth-peeled render and, with ref_image, the image loss of
+ * C_0.  flags: ADR_FWD_BUILD_MIPS (alpha map included), ADR_FWD_NO_AA,
+ * ADR_INDEPENDENT_MIPS; ADR_E_UNIMPL with multisampling or
+ * ADR_DETERMINISTIC.  Scratch as adr_render_fwd. */
+adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                              const adr_views* views, const float* ref_image, int32_t loss_kind,
+                              const adr_oit_out* out, int32_t flags, adr_stream stream);
+/* Adjoint of adr_render_oit_fwd (saved: its outputs; vis, color, alpha,
+ * blend, comp and dimage are read), layer by layer from the front:
+ * antialiasing adjoint of layer k, then the blend adjoint (dc_k = a_k dB_k,
+ * da_k = dB_k . (c_k - C_{k+1}), dC_{k+1} = (1 - a_k) dB_k where covered),
+ * then the shading and texel adjoints of the layer.  grads as adr_render_bwd
+ * plus grads->alpha.  flags: ADR_FWD_NO_AA, ADR_INDEPENDENT_MIPS. */
+adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                              const adr_views* views, const adr_oit_out* saved, const float* dloss,
+                              const adr_grads* grads, int32_t flags, adr_stream stream);
 
 /* One optimised tensor for adr_adam_step: n floats each, device. */
 typedef struct adr_param {
@@ -335,9 +378,9 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * 0 vertex frame, 1 transform, 2 raster, 3 shade, 4 antialias+loss,
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
  * 9 adam, 10 mip build, 11 texel adjoint, 12 buffer clears and
- * conversions, 13 skinning, 14 skinning adjoint.  ms and count: host arrays
- * of ADR_N_STAGES. */
-#define ADR_N_STAGES 15
+ * conversions, 13 skinning, 14 skinning adjoint, 15 layer blending and its
+ * adjoint (depth peeling).  ms and count: host arrays of ADR_N_STAGES. */
+#define ADR_N_STAGES 16
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
 

@@ -38,10 +38,10 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
-           "adr_skin_fwd", "adr_skin_bwd")
-N_STAGES = 15
+           "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd")
+N_STAGES = 16
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
-          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd")
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend")
 
 
 class AdrError(RuntimeError):
@@ -64,7 +64,7 @@ class Mesh_(C.Structure):
 
 
 class Material_(C.Structure):
-    _fields_ = [("model", I32), ("kd", Texture_), ("normal", Texture_), ("orm", Texture_)]
+    _fields_ = [("model", I32), ("kd", Texture_), ("normal", Texture_), ("orm", Texture_), ("alpha", Texture_)]
 
 
 class Views_(C.Structure):
@@ -78,7 +78,12 @@ class FwdOut_(C.Structure):
 
 
 class Grads_(C.Structure):
-    _fields_ = [("pos", P), ("vnormal", P), ("kd", P), ("normal", P), ("orm", P)]
+    _fields_ = [("pos", P), ("vnormal", P), ("kd", P), ("normal", P), ("orm", P), ("alpha", P)]
+
+
+class OitOut_(C.Structure):
+    _fields_ = [("n_layers", I32), ("vis", P), ("color", P), ("alpha", P), ("blend", P), ("comp", P),
+                ("dimage", P), ("loss", P)]
 
 
 class Param_(C.Structure):
@@ -146,6 +151,10 @@ _lib.adr_tess_build.argtypes = [P, P, P, I32, I32, I32, I32, P, P, P, P, P, P]
 _lib.adr_tess_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P]
 _lib.adr_tess_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Tess_), C.POINTER(Texture_), P, P, P, P]
 _lib.adr_skin_fwd.argtypes = [P, P, P, P, I32, I32, P, P, P]
+_lib.adr_render_oit_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_), P, I32,
+                                    C.POINTER(OitOut_), I32, P]
+_lib.adr_render_oit_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_),
+                                    C.POINTER(OitOut_), P, C.POINTER(Grads_), I32, P]
 _lib.adr_skin_bwd.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
 for _n in EXPORTS[1:]:
     getattr(_lib, _n).restype = I32
@@ -297,10 +306,13 @@ class DeviceMaterial:
         self.kd = tex(scene.kd)
         self.normal = tex(scene.normal)
         self.orm = tex(scene.orm) if scene.orm is not None else None
+        al = getattr(scene, "alpha", None)
+        self.alpha = tex(al) if al is not None else None
 
     def struct(self):
         orm = self.orm.struct() if self.orm is not None else Texture_()
-        return Material_(self.model, self.kd.struct(), self.normal.struct(), orm)
+        al = self.alpha.struct() if self.alpha is not None else Texture_()
+        return Material_(self.model, self.kd.struct(), self.normal.struct(), orm, al)
 
 
 class DeviceViews:
@@ -358,7 +370,7 @@ def render_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
                grads: dict, dloss=None, flags: int = 0, pos=None, stream=None):
     """Accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'] (tensors or None)."""
     fo = FwdOut_(*[_ptr(saved.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage")])
-    g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm")])
+    g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
     _check(_lib.adr_render_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(fo),
                                _ptr(dloss), C.byref(g), flags, _stream(stream)))
@@ -617,3 +629,39 @@ def skin_bwd(ctx: Context, pos, bones, blend, g_out, g_pos=None, g_weights=None,
     nb = bones.shape[0]
     _check(_lib.adr_skin_bwd(ctx.h, _ptr(pos), _ptr(bones), _ptr(blend), V, nb, _ptr(g_out), _ptr(g_pos),
                              _ptr(g_weights), _stream(stream)))
+
+
+def render_oit_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, layers: int, ref=None,
+                   loss: str = "l2", flags: int = 0, stream=None, outputs: dict | None = None):
+    """Depth-peeled render (Sec. 5.2, order-independent transparency):
+    returns vis [L,B,H,W], color [L,B,H,W,3], alpha [L,B,H,W], blend and
+    comp [L,B,H,W,3] (comp[0] is the image), dimage, loss."""
+    B, H, W = views.n, views.height, views.width
+    dev = mesh.tri.device
+    if outputs is not None:
+        out = outputs
+    else:
+        out = dict(vis=torch.empty(layers, B, H, W, dtype=torch.int64, device=dev),
+                   color=torch.empty(layers, B, H, W, 3, dtype=torch.float32, device=dev),
+                   alpha=torch.empty(layers, B, H, W, dtype=torch.float32, device=dev),
+                   blend=torch.empty(layers, B, H, W, 3, dtype=torch.float32, device=dev),
+                   comp=torch.empty(layers, B, H, W, 3, dtype=torch.float32, device=dev))
+        out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if ref is not None else None
+        out["loss"] = torch.empty(1, dtype=torch.float32, device=dev) if ref is not None else None
+    out["layers"] = layers
+    oo = OitOut_(layers, *[_ptr(out[k]) for k in ("vis", "color", "alpha", "blend", "comp", "dimage", "loss")])
+    ms, mt, vs = mesh.struct(), mat.struct(), views.struct()
+    _check(_lib.adr_render_oit_fwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref), LOSS[loss],
+                                   C.byref(oo), flags, _stream(stream)))
+    return out
+
+
+def render_oit_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, saved: dict,
+                   grads: dict, dloss=None, flags: int = 0, stream=None):
+    """Adjoint of render_oit_fwd; accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'|'alpha']."""
+    oo = OitOut_(saved["layers"], *[_ptr(saved.get(k)) for k in ("vis", "color", "alpha", "blend", "comp", "dimage",
+                                                                  "loss")])
+    g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
+    ms, mt, vs = mesh.struct(), mat.struct(), views.struct()
+    _check(_lib.adr_render_oit_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(oo), _ptr(dloss), C.byref(g),
+                                   flags, _stream(stream)))

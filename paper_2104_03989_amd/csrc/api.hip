@@ -62,6 +62,7 @@ struct Span {
 struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
+  Buf oit_g, oit_a;  // depth-peeling adjoint: dL/d(composite behind) and dL/d alpha per pixel
   Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
@@ -324,7 +325,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
                  &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
-                 &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
+                 &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
     (void)hipEventDestroy(sp.a);
@@ -442,6 +443,164 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     const Tex* maps[3] = {&kd, &nm, &orm};
     float* gs[3] = {grads->kd, grads->normal, grads->orm};
     for (int k = 0; k < 3; ++k)
+      if (gs[k] && maps[k]->levels > 1) {
+        ms.t[ms.n] = *maps[k];
+        ms.g[ms.n++] = gs[k];
+      }
+    if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+  }
+  if (m.n_pos > 0 && (grads->pos || grads->vnormal))
+    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
+  return ADR_OK;
+}
+
+// ---- depth peeling (order-independent transparency) ----
+
+static adr_status check_alpha(const adr_material* mat, Tex& al, bool& has) {
+  has = mat->alpha.data != nullptr;
+  al = Tex{};
+  if (!has) return ADR_OK;
+  adr_status r = check_tex(mat->alpha, "alpha", false, al);
+  if (r != ADR_OK) return r;
+  if (al.channels != 1) return fail(ADR_E_INVALID, "alpha: needs 1 channel");
+  return ADR_OK;
+}
+
+static adr_status check_oit(const adr_oit_out* o, int32_t flags, bool fwd) {
+  if (!o) return fail(ADR_E_INVALID, "out is NULL");
+  if (o->n_layers < 1 || o->n_layers > 16) return fail(ADR_E_INVALID, "n_layers %d outside [1,16]", o->n_layers);
+  if (!o->vis || !o->color || !o->alpha || !o->blend || !o->comp)
+    return fail(ADR_E_INVALID, "out->vis, color, alpha, blend and comp are required");
+  if (flags & (ADR_MSAA_2X2 | ADR_MSAA_4X4 | ADR_DETERMINISTIC))
+    return fail(ADR_E_UNIMPL, "depth peeling with multisampling or the deterministic mode is not implemented");
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_INDEPENDENT_MIPS))
+    return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if (fwd && (flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
+    return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
+  return ADR_OK;
+}
+
+adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                              const adr_views* views, const float* ref_image, int32_t loss_kind,
+                              const adr_oit_out* out, int32_t flags, adr_stream stream) {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm, al;
+  bool has_al;
+  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if ((r = check_alpha(mat, al, has_al)) != ADR_OK || (r = check_oit(out, flags, true)) != ADR_OK) return r;
+  if (ref_image) {
+    if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
+    if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  if (flags & ADR_FWD_BUILD_MIPS) {
+    const Tex* maps[4] = {&kd, &nm, &orm, &al};
+    MipSet ms{};
+    for (int k = 0; k < 4; ++k) {
+      if (k == 2 && mat->model != ADR_SHADE_GGX) continue;
+      if (k == 3 && !has_al) continue;
+      if (maps[k]->fmt == ADR_TEX_F32 && maps[k]->levels > 1) ms.t[ms.n++] = *maps[k];
+    }
+    TIMED(10, launch_mip_build_set(ms, st), "mip build");
+  }
+  if (mesh->nrm && mesh->tan) {
+    s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
+    s.tan = const_cast<float*>(mesh->tan);
+  } else {
+    TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  }
+  TIMED(1, launch_xform(m, v, s, st), "transform");
+  const int64_t npx = (int64_t)v.B * v.W * v.H;
+  const int L = out->n_layers;
+  const int no_aa = (flags & ADR_FWD_NO_AA) ? 1 : 0;
+  // front to back: peel, then shade each layer
+  for (int k = 0; k < L; ++k) {
+    uint64_t* vk = out->vis + k * npx;
+    TIMED(12, launch_clear_vis(vk, nullptr, npx, s.big_cnt, v.B, st), "clear");
+    TIMED(2, launch_raster(m, v, s, vk, nullptr, st, k > 0 ? out->vis + (k - 1) * npx : nullptr), "raster");
+    TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, vk, out->color + 3 * k * npx, nullptr, st,
+                              has_al ? &al : nullptr, out->alpha + k * npx),
+          "shade");
+  }
+  // back to front: blend over what lies behind, antialias the layer
+  for (int k = L - 1; k >= 0; --k) {
+    const uint64_t* vk = out->vis + k * npx;
+    const float* behind = k + 1 < L ? out->comp + 3 * (k + 1) * npx : nullptr;
+    float* bk = out->blend + 3 * k * npx;
+    TIMED(15, launch_oit_blend(npx, vk, out->color + 3 * k * npx, out->alpha + k * npx, behind, bk, st), "blend");
+    TIMED(4, launch_aa_loss_fwd(m, v, s, vk, bk, k == 0 ? ref_image : nullptr, loss_kind, no_aa,
+                                out->comp + 3 * k * npx, k == 0 ? out->dimage : nullptr, k == 0 ? out->loss : nullptr,
+                                st),
+          "antialias/loss");
+  }
+  return ADR_OK;
+}
+
+adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                              const adr_views* views, const adr_oit_out* saved, const float* dloss,
+                              const adr_grads* grads, int32_t flags, adr_stream stream) {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm, al;
+  bool has_al;
+  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if ((r = check_alpha(mat, al, has_al)) != ADR_OK || (r = check_oit(saved, flags, false)) != ADR_OK) return r;
+  if (!saved->dimage) return fail(ADR_E_INVALID, "saved->dimage is required");
+  if (!grads) return fail(ADR_E_INVALID, "grads is NULL");
+  if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
+  if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
+  if (grads->alpha && !has_al) return fail(ADR_E_INVALID, "alpha gradient needs an alpha map");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  float* gal = has_al ? grads->alpha : nullptr;
+  Scratch s;
+  if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm, gal))) !=
+      ADR_OK)
+    return r;
+  const int64_t npx = (int64_t)v.B * v.W * v.H;
+  if ((r = ensure(ctx->oit_g, npx * 12)) || (r = ensure(ctx->oit_a, npx * 4))) return r;
+  float* gbehind = (float*)ctx->oit_g.p;
+  float* galpha = (float*)ctx->oit_a.p;
+  const int64_t n_clip = 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), n_attr = 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1);
+  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+  TIMED(1, launch_xform(m, v, s, st), "transform");
+  TIMED(1, launch_orient(m, v, s, st), "orientation");
+  TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
+  TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
+  const int L = saved->n_layers;
+  const int no_aa = (flags & ADR_FWD_NO_AA) ? 1 : 0;
+  // front to back: dL/dC_k -> dL/dB_k (antialiasing adjoint) -> dL/dc_k,
+  // dL/da_k and dL/dC_{k+1} (blend adjoint) -> shading and texel adjoints
+  for (int k = 0; k < L; ++k) {
+    const uint64_t* vk = saved->vis + k * npx;
+    const float* ck = saved->color + 3 * k * npx;
+    const float* ak = saved->alpha + k * npx;
+    const float* behind = k + 1 < L ? saved->comp + 3 * (k + 1) * npx : nullptr;
+    TIMED(5, launch_aa_bwd(m, v, s, vk, saved->blend + 3 * k * npx, k == 0 ? saved->dimage : gbehind,
+                           k == 0 ? dloss : nullptr, no_aa, st),
+          "antialias adjoint");
+    TIMED(15, launch_oit_blend_bwd(npx, vk, ck, ak, behind, s.gcolor, galpha, k + 1 < L ? gbehind : nullptr, st),
+          "blend adjoint");
+    TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, vk, st,
+                              has_al ? &al : nullptr, gal, has_al ? galpha : nullptr),
+          "shading adjoint");
+    TIMED(11, launch_tex_bwd(v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, st,
+                             has_al ? &al : nullptr, gal),
+          "texel adjoint");
+  }
+  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, false, st), "accumulator conversion");
+  TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, false, st), "accumulator conversion");
+  {
+    MipSet ms{};
+    const Tex* maps[4] = {&kd, &nm, &orm, &al};
+    float* gs[4] = {grads->kd, grads->normal, grads->orm, gal};
+    for (int k = 0; k < 4; ++k)
       if (gs[k] && maps[k]->levels > 1) {
         ms.t[ms.n] = *maps[k];
         ms.g[ms.n++] = gs[k];

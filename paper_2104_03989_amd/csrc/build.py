@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libadr.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "raster.hip", "mesh.hip", "shade.hip", "aa.hip", "tex.hip", "adam.hip", "jobs.hip", "tess.hip", "detsort.hip", "laplace.hip", "skin.hip"]
+SOURCES = ["api.hip", "raster.hip", "mesh.hip", "shade.hip", "aa.hip", "tex.hip", "adam.hip", "jobs.hip", "tess.hip", "detsort.hip", "laplace.hip", "skin.hip", "oit.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -72,10 +72,10 @@ struct Scratch {
   float4* det_part;              // [2 tiles]
 };
 
-// Up to three texture chains (a material's maps) and their gradient buffers.
+// Up to four texture chains (a material's maps) and their gradient buffers.
 struct MipSet {
-  Tex t[3];
-  float* g[3];
+  Tex t[4];
+  float* g[4];
   int n;
 };
 
@@ -99,11 +99,15 @@ hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipSt
 hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B,
                             hipStream_t st);
 hipError_t launch_orient(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st);
+// floor: keys of the previous depth-peeling layer (NULL: no lower bound).
 hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis,
-                         uint32_t* cov, hipStream_t st);
+                         uint32_t* cov, hipStream_t st, const uint64_t* floor = nullptr);
+// al / alpha: the alpha map and the per-pixel alpha output of a depth-peeled
+// layer (both optional).
 hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
-                            float* color, int32_t* tri_id, hipStream_t st);
+                            float* color, int32_t* tri_id, hipStream_t st, const Tex* al = nullptr,
+                            float* alpha = nullptr);
 hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
@@ -111,6 +115,10 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st);
+hipError_t launch_oit_blend(int64_t n, const uint64_t* vis, const float* color, const float* alpha,
+                            const float* behind, float* blend, hipStream_t st);
+hipError_t launch_oit_blend_bwd(int64_t n, const uint64_t* vis, const float* color, const float* alpha,
+                                const float* behind, float* g, float* galpha, float* gbehind, hipStream_t st);
 hipError_t launch_skin_fwd(int n, int nb, const float* pos, const float* w, const float* bones, float* out,
                            float* blend, hipStream_t st);
 hipError_t launch_skin_bwd(int n, int nb, const float* pos, const float* bones, const float* blend, float* gout,
@@ -129,12 +137,16 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
 hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st);
 
 // Number of texture-gradient slots (maps with a gradient buffer).
-int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm);
+int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm, const float* gal = nullptr);
+// al / gal / galpha: the alpha map, its gradient and dL/d alpha per pixel of
+// a depth-peeled layer (all optional; galpha selects the alpha variant).
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
-                            const Scratch& s, const uint64_t* vis, hipStream_t st);
+                            const Scratch& s, const uint64_t* vis, hipStream_t st, const Tex* al = nullptr,
+                            float* gal = nullptr, const float* galpha = nullptr);
 hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
-                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st);
+                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st,
+                          const Tex* al = nullptr, float* gal = nullptr);
 hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st);
 hipError_t launch_mip_build_set(const MipSet& ms, hipStream_t st);
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,

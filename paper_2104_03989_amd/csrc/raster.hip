@@ -19,6 +19,11 @@
 // kernel spreads over all waves of the chip, one triangle per wave at a time;
 // larger ones go to a per-view list that a third kernel bins against 16x16
 // tiles in LDS and resolves one pixel per thread.
+//
+// Depth peeling (Sec. 5.2, "Order-independent transparency"): with a floor
+// buffer (the previous layer's keys) a fragment counts only if its key is
+// strictly greater than the floor key of its pixel, so a pass keeps the
+// nearest fragment behind the previous layer.
 // This file is compiled with -ffp-contract=off.
 #include "dev.h"
 
@@ -153,11 +158,13 @@ __global__ void k_clear(uint64_t* __restrict__ vis, uint32_t* __restrict__ cov, 
 }
 
 __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j, int W,
-                                             unsigned long long* __restrict__ vv, uint32_t* __restrict__ cv) {
+                                             unsigned long long* __restrict__ vv, uint32_t* __restrict__ cv,
+                                             const unsigned long long* __restrict__ fl) {
   const int px = 256 * i + 128, py = 256 * j + 128;
   if (!covers(s, px, py)) return;
   unsigned long long key = ((unsigned long long)depth_at(s, px, py) << 32) | (uint32_t)(t + 1);
   int64_t o = (int64_t)j * W + i;
+  if (fl && key <= fl[o]) return;
   if (cv) atomicAdd(cv + o, 1u);
   atomicMin(vv + o, key);
 }
@@ -170,7 +177,8 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
                                                       int8_t* __restrict__ orient, uint32_t* __restrict__ big,
                                                       uint32_t* __restrict__ big_cnt, uint32_t* __restrict__ med,
                                                       unsigned long long* __restrict__ vis,
-                                                      uint32_t* __restrict__ cov) {
+                                                      uint32_t* __restrict__ cov,
+                                                      const unsigned long long* __restrict__ floor) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int area = 0, b = 0, t = 0;
   Setup s;
@@ -194,8 +202,9 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
   } else if (area > 0 && area <= kTinyBBox) {
     unsigned long long* vv = vis + b * HW;
     uint32_t* cv = cov ? cov + b * HW : nullptr;
+    const unsigned long long* fl = floor ? floor + b * HW : nullptr;
     for (int j = bb.j0; j <= bb.j1; ++j)
-      for (int i = bb.i0; i <= bb.i1; ++i) raster_pixel(s, t, i, j, v.W, vv, cv);
+      for (int i = bb.i0; i <= bb.i1; ++i) raster_pixel(s, t, i, j, v.W, vv, cv, fl);
   }
   // medium triangles of this wave: one queue reservation per wave
   const int lane = threadIdx.x & 63;
@@ -218,7 +227,8 @@ __global__ __launch_bounds__(256) void k_raster_med(MeshD m, ViewsD v, const int
                                                     const uint32_t* __restrict__ med,
                                                     const uint32_t* __restrict__ big_cnt,
                                                     unsigned long long* __restrict__ vis,
-                                                    uint32_t* __restrict__ cov) {
+                                                    uint32_t* __restrict__ cov,
+                                                    const unsigned long long* __restrict__ floor) {
   const int lane = threadIdx.x & 63;
   const uint32_t n_waves = gridDim.x * (blockDim.x >> 6);
   const uint32_t cnt = big_cnt[v.B];
@@ -245,11 +255,12 @@ __global__ __launch_bounds__(256) void k_raster_med(MeshD m, ViewsD v, const int
     const int lx = lane & (bw - 1), ly = lane >> lb;
     unsigned long long* vv = vis + b * HW;
     uint32_t* cv = cov ? cov + b * HW : nullptr;
+    const unsigned long long* fl = floor ? floor + b * HW : nullptr;
     for (int y0 = bb.j0; y0 <= bb.j1; y0 += bh) {
       const int y = y0 + ly;
       for (int x0 = bb.i0; x0 <= bb.i1; x0 += bw) {
         const int x = x0 + lx;
-        if (x <= bb.i1 && y <= bb.j1) raster_pixel(s, t, x, y, v.W, vv, cv);
+        if (x <= bb.i1 && y <= bb.j1) raster_pixel(s, t, x, y, v.W, vv, cv, fl);
       }
     }
   }
@@ -262,7 +273,7 @@ __global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int
                                                     const uint32_t* __restrict__ big_cnt,
                                                     unsigned long long* __restrict__ vis,
                                                     uint32_t* __restrict__ cov, int tiles_x,
-                                                    int tiles_y) {
+                                                    int tiles_y, const unsigned long long* __restrict__ floor) {
   __shared__ Setup lds[256];
   __shared__ int lds_t[256];
   __shared__ int lds_n;
@@ -281,6 +292,8 @@ __global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int
   unsigned long long best = kKeyEmpty;
   uint32_t hits = 0;
   int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
+  const unsigned long long fk =
+      (floor && i < v.W && j < v.H) ? floor[(int64_t)b * v.W * v.H + (int64_t)j * v.W + i] : 0ull;
   for (uint32_t base = 0; base < n_big; base += 256) {
     if (threadIdx.x == 0) lds_n = 0;
     __syncthreads();
@@ -305,6 +318,7 @@ __global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int
         if (!covers(lds[k], px, py)) continue;
         unsigned long long key =
             ((unsigned long long)depth_at(lds[k], (int)px, (int)py) << 32) | (uint32_t)(lds_t[k] + 1);
+        if (floor && key <= fk) continue;
         ++hits;
         best = key < best ? key : best;
       }
@@ -336,22 +350,23 @@ hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* b
 }
 
 hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis,
-                         uint32_t* cov, hipStream_t st) {
+                         uint32_t* cov, hipStream_t st, const uint64_t* floor) {
+  auto* fl = reinterpret_cast<const unsigned long long*>(floor);
   int n = v.B * m.n_tri;
   if (n == 0) return hipSuccess;
   const int4* sv = reinterpret_cast<const int4*>(s.snap);
   auto* vk = reinterpret_cast<unsigned long long*>(vis);
   hipLaunchKernelGGL(k_raster_small, dim3((n + 255) / 256), dim3(256), 0, st, m, v, sv, s.orient,
-                     s.big, s.big_cnt, s.med, vk, cov);
+                     s.big, s.big_cnt, s.med, vk, cov, fl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // enough waves to fill the chip; each loops over the queue
   const int med_blocks = std::min((n + 3) / 4, 4096);
-  hipLaunchKernelGGL(k_raster_med, dim3(med_blocks), dim3(256), 0, st, m, v, sv, s.med, s.big_cnt, vk, cov);
+  hipLaunchKernelGGL(k_raster_med, dim3(med_blocks), dim3(256), 0, st, m, v, sv, s.med, s.big_cnt, vk, cov, fl);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int tx = (v.W + kBigTile - 1) / kBigTile, ty = (v.H + kBigTile - 1) / kBigTile;
   hipLaunchKernelGGL(k_raster_big, dim3(tx * ty * v.B), dim3(256), 0, st, m, v, sv, s.big,
-                     s.big_cnt, vk, cov, tx, ty);
+                     s.big_cnt, vk, cov, tx, ty, fl);
   return hipGetLastError();
 }
 

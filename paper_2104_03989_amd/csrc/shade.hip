@@ -262,6 +262,8 @@ struct ShadeArgs {
   ViewsD v;
   int model;
   Tex kd, nm, orm;
+  Tex al;                 // alpha map (data NULL: none)
+  const float* galpha;    // dL/d alpha per pixel (adjoint of a depth-peeled layer), or NULL
   const double4* clip;
   const float* nrm;
   const float* tan;
@@ -269,8 +271,15 @@ struct ShadeArgs {
   int tiles_x, tiles_y;
 };
 
+// Alpha of a depth-peeled layer: clamp(alpha map, 0, 1), 1 without a map.
+__device__ __forceinline__ float layer_alpha(const ShadeArgs& a, const PixelGeom& g) {
+  if (!a.al.data) return 1.f;
+  Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
+  return fminf(fmaxf(tex_trilinear(a.al, g.u, g.v_, La).val.x, 0.f), 1.f);
+}
+
 __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restrict__ color,
-                                                   int32_t* __restrict__ tri_id) {
+                                                   int32_t* __restrict__ tri_id, float* __restrict__ alpha) {
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   if (!p.ok) return;
@@ -280,10 +289,12 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
   if (tri_id) tri_id[o] = (int32_t)id;
   if (id == 0u) {
     st3(color, o, mk(0.f, 0.f, 0.f));
+    if (alpha) alpha[o] = 0.f;
     return;
   }
   PixelGeom g;
   pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
+  if (alpha) alpha[o] = layer_alpha(a, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
   f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
   Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
@@ -551,8 +562,10 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
 constexpr int kVtxAcc = 36;
 
 // Adjoint of one pixel.  The vertex gradients are returned in acc and the
-// three texture lookups' sample gradients in ts (kd, normal, orm), both for
-// the wave-level scatter.  Returns false if the pixel contributes nothing.
+// texture lookups' sample gradients in ts (kd, normal, orm and, with ALPHA,
+// the alpha map), both for the wave-level scatter.  Returns false if the
+// pixel contributes nothing.
+template <bool ALPHA>
 __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
                                                 const float* __restrict__ gcolor, float* acc,
                                                 int& tri, int* vtx, TexScatter* ts) {
@@ -560,7 +573,8 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   uint32_t id = (uint32_t)a.vis[o];
   if (id == 0u) return false;
   f3 gc = mk(gcolor[3 * o], gcolor[3 * o + 1], gcolor[3 * o + 2]);
-  if (gc.x == 0.f && gc.y == 0.f && gc.z == 0.f) return false;
+  const float g_alpha = ALPHA ? a.galpha[o] : 0.f;
+  if (gc.x == 0.f && gc.y == 0.f && gc.z == 0.f && g_alpha == 0.f) return false;
   tri = (int)id - 1;
   PixelGeom g;
   pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
@@ -592,6 +606,14 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   f3 gnt = mk(dot(gm, g.Tp), dot(gm, g.Bt), dot(gm, g.N));
   tex_bwd(a.nm, nullptr, g, Ln, gnt, G);
   if (a.model == ADR_SHADE_GGX) tex_bwd(a.orm, nullptr, g, Lo, gormv, G);
+  if (ALPHA && a.al.data) {
+    // alpha = clamp(t, 0, 1): the gradient passes where t is inside [0, 1]
+    Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
+    const float t = tex_trilinear(a.al, g.u, g.v_, La).val.x;
+    const f3 gal = mk(t >= 0.f && t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
+    tex_bwd(a.al, nullptr, g, La, gal, G);
+    ts[3] = TexScatter{g.u, g.v_, La.l0, La.f, La.has1, gal};
+  }
   ts[0] = TexScatter{g.u, g.v_, Lk.l0, Lk.f, Lk.has1, gkdv};
   ts[1] = TexScatter{g.u, g.v_, Ln.l0, Ln.f, Ln.has1, gnt};
   if (a.model == ADR_SHADE_GGX) ts[2] = TexScatter{g.u, g.v_, Lo.l0, Lo.f, Lo.has1, gormv};
@@ -735,10 +757,11 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
 // k (255: no contribution), and rec[1 + k] = (dL/dsample, weight of level
 // l0 + 1) of slot k.
 struct TexSlots {
-  int kd, nm, orm;  // slot of each map, -1 without a gradient buffer
+  int kd, nm, orm, al;  // slot of each map, -1 without a gradient buffer
   int n;
 };
 
+template <bool ALPHA>
 __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, const float* __restrict__ gcolor,
                                                    float4* __restrict__ rec, unsigned long long* __restrict__ fclip,
                                                    unsigned long long* __restrict__ fattr, bool det) {
@@ -748,16 +771,17 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   float acc[kVtxAcc];
   int tri = -1;
   int vtx[3] = {0, 0, 0};
-  TexScatter ts[3];
-  bool act = p.ok && shade_bwd_pixel(a, p, gcolor, acc, tri, vtx, ts);
+  constexpr int kMaps = ALPHA ? 4 : 3;
+  TexScatter ts[kMaps];
+  bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, acc, tri, vtx, ts);
   if (p.ok && sl.n > 0) {
     const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
     const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
     uint32_t lv = 0xFFFFFFFFu;
     if (act) {
-      const int slot[3] = {sl.kd, sl.nm, sl.orm};
+      const int slot[4] = {sl.kd, sl.nm, sl.orm, sl.al};
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
+      for (int m = 0; m < kMaps; ++m) {
         if (slot[m] < 0) continue;
         lv &= ~(0xFFu << (8 * slot[m]));
         lv |= (uint32_t)ts[m].l0 << (8 * slot[m]);
@@ -773,8 +797,8 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
 // few registers, so that enough waves are resident to hide the latency of
 // the LDS atomics of the window accumulation.
 struct TexBwdArgs {
-  Tex t[3];
-  float* g[3];
+  Tex t[4];
+  float* g[4];
   int n;
   const float4* rec;
   ViewsD v;
@@ -801,7 +825,7 @@ __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
 
 static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
                            const Tex& orm, const Scratch& s, const uint64_t* vis) {
-  ShadeArgs a;
+  ShadeArgs a{};
   a.m = m;
   a.v = v;
   a.model = model;
@@ -819,21 +843,22 @@ static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex
 
 hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
-                            float* color, int32_t* tri_id, hipStream_t st) {
+                            float* color, int32_t* tri_id, hipStream_t st, const Tex* al, float* alpha) {
   ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
+  if (al) a.al = *al;
   int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_shade_fwd, dim3(nb), dim3(256), 0, st, a, color, tri_id);
+  hipLaunchKernelGGL(k_shade_fwd, dim3(nb), dim3(256), 0, st, a, color, tri_id, alpha);
   return hipGetLastError();
 }
 
-int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm) {
-  return (gkd ? 1 : 0) + (gnm ? 1 : 0) + ((gorm && model == ADR_SHADE_GGX) ? 1 : 0);
+int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm, const float* gal) {
+  return (gkd ? 1 : 0) + (gnm ? 1 : 0) + ((gorm && model == ADR_SHADE_GGX) ? 1 : 0) + (gal ? 1 : 0);
 }
 
-// Gradient slots in the order kd, normal, orm (maps with a gradient buffer).
+// Gradient slots in the order kd, normal, orm, alpha (maps with a gradient buffer).
 static int make_slots(int model, const Tex& kd, const Tex& nm, const Tex& orm, float* gkd, float* gnm,
-                      float* gorm, TexSlots& sl, TexBwdArgs& tb) {
-  sl = TexSlots{-1, -1, -1, 0};
+                      float* gorm, TexSlots& sl, TexBwdArgs& tb, const Tex* al = nullptr, float* gal = nullptr) {
+  sl = TexSlots{-1, -1, -1, -1, 0};
   tb = TexBwdArgs{};
   auto add = [&](int& slot, const Tex& t, float* g) {
     slot = sl.n++;
@@ -843,20 +868,29 @@ static int make_slots(int model, const Tex& kd, const Tex& nm, const Tex& orm, f
   if (gkd) add(sl.kd, kd, gkd);
   if (gnm) add(sl.nm, nm, gnm);
   if (gorm && model == ADR_SHADE_GGX) add(sl.orm, orm, gorm);
+  if (gal && al && al->data) add(sl.al, *al, gal);
   tb.n = sl.n;
   return sl.n;
 }
 
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
-                            const Scratch& s, const uint64_t* vis, hipStream_t st) {
+                            const Scratch& s, const uint64_t* vis, hipStream_t st, const Tex* al, float* gal,
+                            const float* galpha) {
   ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
   int nb = a.tiles_x * a.tiles_y * v.B;
   TexSlots sl;
   TexBwdArgs tb;
-  make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb);
-  hipLaunchKernelGGL(k_shade_bwd, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip, s.fix_attr,
-                     s.det);
+  make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb, al, gal);
+  if (galpha) {
+    if (al) a.al = *al;
+    a.galpha = galpha;
+    hipLaunchKernelGGL(k_shade_bwd<true>, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip,
+                       s.fix_attr, s.det);
+  } else {
+    hipLaunchKernelGGL(k_shade_bwd<false>, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip,
+                       s.fix_attr, s.det);
+  }
   return hipGetLastError();
 }
 
@@ -1028,11 +1062,12 @@ hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const T
 }
 
 hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
-                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st) {
+                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st, const Tex* al,
+                          float* gal) {
   if (s.det) return launch_tex_bwd_det(v, model, kd, nm, orm, gkd, gnm, gorm, s, st);
   TexSlots sl;
   TexBwdArgs tb;
-  if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb) == 0) return hipSuccess;
+  if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb, al, gal) == 0) return hipSuccess;
   tb.rec = s.texrec;
   tb.v = v;
   tb.tiles_x = (v.W + 15) / 16;

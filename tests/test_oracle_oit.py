@@ -148,27 +148,10 @@ def test_more_layers_than_depth_change_nothing():
     assert float((run(1)["image"] - a["image"]).abs().max()) > 1e-3
 
 
-def aggregate_case(res=24, views=1, n_leaves=60, n_quads=6, tex=8, layers=4, seed=0):
-    """A small aggregate scene: leaves against textured, transparent quads."""
-    g = np.random.default_rng(seed)
-    leaves = synth.leaf_cloud(n_leaves, 1000 + seed, radius=0.6, size=0.15)
-    kd_ref = synth.Texture(g.uniform(0.1, 0.9, size=(tex, tex, 3)).astype(np.float32), "f32")
-    ref = synth.Scene(leaves, "blinn_phong", kd_ref, S.flat_normals(), None)
-    quads = synth.quad_cloud(n_quads, 2000 + seed, radius=0.4, size=0.6)
-    lat = synth.Scene(quads, "blinn_phong", synth.Texture(g.uniform(0.2, 0.8, (tex, tex, 3)).astype(np.float32), "f32"),
-                      synth.Texture(synth.detail_normal_map(tex, 3000 + seed, 0.1).astype(np.float32), "f32"), None,
-                      synth.Texture(g.uniform(0.2, 0.8, (tex, tex, 1)).astype(np.float32), "f32"))
-    dirs = synth.random_unit(views, 4000 + seed) + np.array([0.0, 0.0, 1.5])
-    light = synth.random_unit(views, 5000 + seed) + 1.5 * dirs
-    w = S.workload(ref, lat, dirs, light, res, res, loss="l2", optimize=("pos", "kd", "normal", "alpha"))
-    w.oit_layers = layers
-    return w
-
-
 def test_aggregate_gradients_central_differences():
     # loss with the layers and antialiasing pairs held fixed: central
     # differences w.r.t. alpha and base-colour texels and vertex positions
-    w = aggregate_case()
+    w = S.aggregate_case()
     ref = OL.reference_image(w)
     mvp32, eye = OL.cameras(w)
     params = OL.latent_params(w)
