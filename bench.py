@@ -174,7 +174,7 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         g_disp = torch.zeros_like(disp.data)
         params += [(ts.base.pos, g_base), (disp.data, g_disp)]
     independent = False
-    for name in ("kd", "normal", "orm"):
+    for name in ("kd", "normal", "orm", "alpha"):
         if name not in w.optimize:
             grads[name] = None
             continue
@@ -194,8 +194,13 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     lflag = dflag | (adr.INDEPENDENT_MIPS if independent else adr.FWD_BUILD_MIPS)
     ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], flags=dflag & adr.DETERMINISTIC)
     ref_img = ref_out["image"] if k == 1 else adr.image_downsample(ctx, ref_out["image"], k)
-    lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_img, loss=w.loss,
-                             flags=lflag, want_image=False, want_tri_id=True)
+    L = w.oit_layers
+    if L:
+        # depth-peeled latent (order-independent transparency)
+        lat_out = adr.render_oit_fwd(ctx, lat_mesh, lat_mat, views[0], L, ref=ref_img, loss=w.loss, flags=lflag)
+    else:
+        lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_img, loss=w.loss,
+                                 flags=lflag, want_image=False, want_tri_id=True)
 
     # uniform Laplacian regularizer (absolute form: the latent starts as a
     # resampled sphere), lambda_0 by the heuristic, then the recursive decay
@@ -225,8 +230,12 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_out, flags=dflag & adr.DETERMINISTIC)
         if k > 1:
             adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
-        adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
-        adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
+        if L:
+            adr.render_oit_fwd(ctx, lat_mesh, lat_mat, v, L, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
+            adr.render_oit_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
+        else:
+            adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
+            adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
         if rig is not None:
@@ -249,8 +258,8 @@ TEXEL_C = 1.25   # compulsory texels per covered pixel per mip level at ~1 texel
 def optimised_maps(w):
     """(name, bytes per texel) of the optimised F32 maps larger than 1x1."""
     out = []
-    for name in ("kd", "normal", "orm"):
-        tex = getattr(w.latent, name)
+    for name in ("kd", "normal", "orm", "alpha"):
+        tex = getattr(w.latent, name, None)
         if name in w.optimize and tex is not None and tex.data.shape[0] > 1:
             out.append((name, 4 * tex.data.shape[2]))
     return out
@@ -271,6 +280,17 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     maps = optimised_maps(w)
     if stage == "adam":
         return 32.0 * st["n_params"]                      # read p,g,m,v; write p,m,v,g
+    L = w.oit_layers
+    if L:
+        # depth-peeled latent: one launch per layer; covered_latent counts the
+        # covered pixels of all layers; the average launch is returned
+        if stage == "shade_bwd":
+            return (L * px * (8 + 16 + 4) + covered_latent * (12 + 16 * len(maps))) / L
+        if stage == "tex_bwd":
+            return (L * px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)) / L
+        if stage == "aa_bwd":
+            return px * (8 + 12 + 12 + 12)
+        return None
     if stage == "shade_bwd":
         return px * (8 + 16) + covered_latent * (12 + 16 * len(maps))
     if stage == "tex_bwd":
@@ -401,6 +421,9 @@ WORKLOADS = {
     "animation": ("animation: 19,220-tri GGX reference skinned to a 32-bone rig (40 frames, one per step), "
                   "5,120-tri latent with dense 32-bone weights, bind pose and 1024^2 maps optimised, "
                   "8 views x 512x512, tone-mapped L1, Adam"),
+    "aggregate": ("aggregate geometry: 1.2M-tri leaf cloud reference, 4,800 transparent quads (9,600 tris) "
+                  "with 8 depth-peeled layers, 2048^2 base colour, normal and alpha maps optimised with positions, "
+                  "8 views x 512x512, L2, Adam"),
     "prefilter": ("prefiltering: 297,680-tri GGX reference with 8x8 supersampling, 7,220-tri latent with 4x4 "
                   "multisampled visibility and independent-mip 512^2 maps, 8 views x 128x128, tone-mapped L1, Adam"),
 }
@@ -416,6 +439,8 @@ def make_workload(name):
         return synth.workload_prefilter(), 6
     if name == "animation":
         return synth.workload_animation(), 7
+    if name == "aggregate":
+        return synth.workload_aggregate(), 8
     return synth.workload_plain_step(), 1
 
 
@@ -482,7 +507,10 @@ def main():
     step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic,
                           laplacian=args.laplacian)
     torch.cuda.synchronize()
-    covered = int((st["lat_out"]["tri_id"] > 0).sum()) // (w.msaa * w.msaa)
+    if w.oit_layers:
+        covered = int(((st["lat_out"]["vis"] & 0xFFFFFFFF) != 0).sum())
+    else:
+        covered = int((st["lat_out"]["tri_id"] > 0).sum()) // (w.msaa * w.msaa)
     _log(f"warmup {args.warmup}")
     for t in range(args.warmup):
         step(t)
@@ -508,7 +536,8 @@ def main():
         prof = {k: round(v[0] / max(v[1], 1), 4) for k, v in stages.items() if v[1] > 0}
         per_step = {k: v[0] / args.steps for k, v in stages.items() if v[1] > 0}
         stage_step = {k: round(v, 4) for k, v in per_step.items()}
-        cands = {k: v for k, v in per_step.items() if k in SINGLE_KERNEL_STAGES}
+        cands = {k: v for k, v in per_step.items()
+                 if k in SINGLE_KERNEL_STAGES and algorithmic_bytes(k, w, st, covered) is not None}
         dom = max(cands, key=cands.get)
         ms, cnt = stages[dom]
         avg_ms = ms / cnt

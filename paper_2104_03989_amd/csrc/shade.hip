@@ -463,11 +463,89 @@ __device__ __forceinline__ void merge_step(bool recv, bool send, int& key, float
   if (send && key >= 0 && pk_s == key) key = -1;
 }
 
+// Accumulates the contributions of the selected lanes (sel) at one level
+// into an LDS window over their footprint (at most kWinTex floats), then adds
+// the window's nonzero texel-channels to HBM.  Converged code.
+__device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gtex, float* win, bool sel,
+                                            const Foot& q, float wl, const float (&gsv)[3], int off) {
+  const int BIG = 1 << 20;
+  const int lane = threadIdx.x & 63;
+  const int C = t.channels;
+  const int rmin = wave_min_i(sel ? q.r0 : BIG), rmax = wave_max_i(sel ? q.r1 : -1);
+  const int cmin = wave_min_i(sel ? q.c0 : BIG), cmax = wave_max_i(sel ? q.c0 + 1 : -1);
+  const int ww = cmax - cmin + 1;
+  const int n = (rmax - rmin + 1) * ww * C;
+  for (int k = lane; k < n; k += 64) win[k] = 0.f;
+  // The per-lane contributions (4 corners x 3 channels) of lanes that
+  // share a bilinear cell are first merged across lanes with DPP moves
+  // (pairs, quads and eights along x, then pairs of pixel rows), since
+  // the cost of the LDS atomics grows with the number of active lanes.
+  const float w[4] = {(1.f - q.fx) * (1.f - q.fy), q.fx * (1.f - q.fy), (1.f - q.fx) * q.fy, q.fx * q.fy};
+  int key = sel ? (((q.r0 << 1) | (q.r1 != q.r0 ? 1 : 0)) << 15) | q.c0 : -1;
+  float v[12];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float wk = sel ? wl * w[k] : 0.f;
+    v[3 * k] = wk * gsv[0];
+    v[3 * k + 1] = wk * gsv[1];
+    v[3 * k + 2] = wk * gsv[2];
+  }
+  merge_step<0xB1, 0xB1>((lane & 1) == 0, (lane & 1) == 1, key, v);    // quad_perm [1,0,3,2]
+  merge_step<0x4E, 0x4E>((lane & 3) == 0, (lane & 3) == 2, key, v);    // quad_perm [2,3,0,1]
+  merge_step<0x104, 0x114>((lane & 7) == 0, (lane & 7) == 4, key, v);  // row_shl:4 / row_shr:4
+  merge_step<0x108, 0x118>((lane & 8) == 0, (lane & 8) != 0, key, v);  // row_shl:8 / row_shr:8
+  wave_sync();
+  if (key >= 0) {
+    // Lanes still sharing a cell update its texels and channels in a
+    // rotated order, so that one instruction rarely hits one address
+    // from several lanes.
+    const int px = lane & 7, py = lane >> 3;
+    const int qr = (px & 1) | ((py & 1) << 1);
+    const int rot = C == 3 ? ((px >> 1) & 1) + ((py >> 1) & 1) : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int kk = k ^ qr;
+      const int cell = (((kk & 2 ? q.r1 : q.r0) - rmin) * ww + ((kk & 1 ? q.c0 + 1 : q.c0) - cmin)) * C;
+      const float v0 = kk == 0 ? v[0] : (kk == 1 ? v[3] : (kk == 2 ? v[6] : v[9]));
+      if (C == 3) {
+        const float v1 = kk == 0 ? v[1] : (kk == 1 ? v[4] : (kk == 2 ? v[7] : v[10]));
+        const float v2 = kk == 0 ? v[2] : (kk == 1 ? v[5] : (kk == 2 ? v[8] : v[11]));
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          int c = ch + rot;
+          c = c >= 3 ? c - 3 : c;
+          atomicAdd(win + cell + c, c == 0 ? v0 : (c == 1 ? v1 : v2));
+        }
+      } else {
+        atomicAdd(win + cell, v0);
+      }
+    }
+  }
+  wave_sync();
+  for (int k = lane; k < n; k += 64) {
+    float val = win[k];
+    if (val != 0.f) {
+      int texel = k / C, ch = k - texel * C;
+      int r = rmin + texel / ww, c = cmin + texel % ww;
+      if (c >= q.s) c -= q.s;
+      atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
+    }
+  }
+  wave_sync();
+}
+
+// Texel gradients of one map from the wave's samples, level by level.  When
+// the footprint of all lanes at a level fits one window it is handled in one
+// pass; otherwise (samples from far-apart parts of the map: a UV seam, or
+// depth-peeled layers whose neighbouring pixels lie on different surfaces)
+// the lanes are taken in groups: the first pending lane and every pending
+// lane whose cell lies in a side x side box around it share a pass.
 __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool act, const TexScatter& ts,
                                  float* win) {
   const int BIG = 1 << 20;
   const int lane = threadIdx.x & 63;
   const int C = t.channels;
+  const int side = C == 3 ? 18 : 32;   // side^2 C <= kWinTex
   bool done0 = !act, done1 = !(act && ts.has1);
   while (true) {
     int my = min(done0 ? BIG : ts.l0, done1 ? BIG : ts.l0 + 1);
@@ -479,79 +557,25 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
     float wl = use0 ? (ts.has1 ? 1.f - ts.f : 1.f) : ts.f;
     done0 = done0 || use0;
     done1 = done1 || use1;
-    Foot q = foot_at(t, lev, ts.u, ts.v);
-    int rmin = wave_min_i(part ? q.r0 : BIG), rmax = wave_max_i(part ? q.r1 : -1);
-    int cmin = wave_min_i(part ? q.c0 : BIG), cmax = wave_max_i(part ? q.c0 + 1 : -1);
-    int hh = rmax - rmin + 1, ww = cmax - cmin + 1;
-    float w[4] = {(1.f - q.fx) * (1.f - q.fy), q.fx * (1.f - q.fy), (1.f - q.fx) * q.fy, q.fx * q.fy};
-    int rr[4] = {q.r0, q.r0, q.r1, q.r1}, cc[4] = {q.c0, q.c0 + 1, q.c0, q.c0 + 1};
-    float gsv[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
-    int off = t.off[lev];
-    if (hh * ww * C <= kWinTex) {
-      int n = hh * ww * C;
-      for (int k = lane; k < n; k += 64) win[k] = 0.f;
-      // The per-lane contributions (4 corners x 3 channels) of lanes that
-      // share a bilinear cell are first merged across lanes with DPP moves
-      // (pairs, quads and eights along x, then pairs of pixel rows), since
-      // the cost of the LDS atomics grows with the number of active lanes.
-      int key = part ? (((q.r0 << 1) | (q.r1 != q.r0 ? 1 : 0)) << 15) | q.c0 : -1;
-      float v[12];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const float wk = part ? wl * w[k] : 0.f;
-        v[3 * k] = wk * gsv[0];
-        v[3 * k + 1] = wk * gsv[1];
-        v[3 * k + 2] = wk * gsv[2];
+    const Foot q = foot_at(t, lev, ts.u, ts.v);
+    const float gsv[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
+    const int off = t.off[lev];
+    const int rmin = wave_min_i(part ? q.r0 : BIG), rmax = wave_max_i(part ? q.r1 : -1);
+    const int cmin = wave_min_i(part ? q.c0 : BIG), cmax = wave_max_i(part ? q.c0 + 1 : -1);
+    const bool whole = (rmax - rmin + 1) * (cmax - cmin + 1) * C <= kWinTex;
+    bool pending = part;
+    unsigned long long left = __ballot(pending);
+    while (left) {
+      bool in = pending;
+      if (!whole) {
+        const int leader = __ffsll((long long)left) - 1;
+        const int br = __builtin_amdgcn_readlane(q.r0, leader) - (side / 2 - 1);
+        const int bc = __builtin_amdgcn_readlane(q.c0, leader) - (side / 2 - 1);
+        in = pending && q.r0 >= br && q.r1 <= br + side - 1 && q.c0 >= bc && q.c0 + 1 <= bc + side - 1;
       }
-      merge_step<0xB1, 0xB1>((lane & 1) == 0, (lane & 1) == 1, key, v);    // quad_perm [1,0,3,2]
-      merge_step<0x4E, 0x4E>((lane & 3) == 0, (lane & 3) == 2, key, v);    // quad_perm [2,3,0,1]
-      merge_step<0x104, 0x114>((lane & 7) == 0, (lane & 7) == 4, key, v);  // row_shl:4 / row_shr:4
-      merge_step<0x108, 0x118>((lane & 8) == 0, (lane & 8) != 0, key, v);  // row_shl:8 / row_shr:8
-      wave_sync();
-      if (key >= 0) {
-        // Lanes still sharing a cell update its texels and channels in a
-        // rotated order, so that one instruction rarely hits one address
-        // from several lanes.
-        const int px = lane & 7, py = lane >> 3;
-        const int qr = (px & 1) | ((py & 1) << 1);
-        const int rot = C == 3 ? ((px >> 1) & 1) + ((py >> 1) & 1) : 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int kk = k ^ qr;
-          const int cell = (((kk & 2 ? q.r1 : q.r0) - rmin) * ww + ((kk & 1 ? q.c0 + 1 : q.c0) - cmin)) * C;
-          const float v0 = kk == 0 ? v[0] : (kk == 1 ? v[3] : (kk == 2 ? v[6] : v[9]));
-          if (C == 3) {
-            const float v1 = kk == 0 ? v[1] : (kk == 1 ? v[4] : (kk == 2 ? v[7] : v[10]));
-            const float v2 = kk == 0 ? v[2] : (kk == 1 ? v[5] : (kk == 2 ? v[8] : v[11]));
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-              int c = ch + rot;
-              c = c >= 3 ? c - 3 : c;
-              atomicAdd(win + cell + c, c == 0 ? v0 : (c == 1 ? v1 : v2));
-            }
-          } else {
-            atomicAdd(win + cell, v0);
-          }
-        }
-      }
-      wave_sync();
-      for (int k = lane; k < n; k += 64) {
-        float val = win[k];
-        if (val != 0.f) {
-          int texel = k / C, ch = k - texel * C;
-          int r = rmin + texel / ww, c = cmin + texel % ww;
-          if (c >= q.s) c -= q.s;
-          atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
-        }
-      }
-      wave_sync();
-    } else if (part) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int c = cc[k] >= q.s ? cc[k] - q.s : cc[k];
-        for (int ch = 0; ch < C; ++ch)
-          atomicAdd(gtex + (int64_t)(off + rr[k] * q.s + c) * C + ch, wl * w[k] * gsv[ch]);
-      }
+      window_pass(t, gtex, win, in, q, wl, gsv, off);
+      pending = pending && !in;
+      left = __ballot(pending);
     }
   }
 }
