@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # that kernel and the source files that define it.
 SINGLE_KERNEL_STAGES = {
     "tex_bwd": ("adr::k_tex_bwd", ["shade.hip"]),
-    "shade_bwd": ("adr::k_shade_bwd", ["shade.hip"]),
+    "shade_bwd": ("adr::k_shade_bwd<false>", ["shade.hip"]),
     "aa_bwd": ("adr::k_aa_bwd", ["aa.hip"]),
     "shade": ("adr::k_shade_fwd", ["shade.hip"]),
     "adam": ("adr::k_adam", ["adam.hip"]),
@@ -81,7 +81,7 @@ def summarize_pmc(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir
         for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))):
             if r["Counter_Name"] != counter:
                 continue
-            n = re.sub(r"\(.*", "", r["Kernel_Name"])
+            n = re.sub(r"^void ", "", re.sub(r"\(.*", "", r["Kernel_Name"]))
             out.setdefault(n, []).append(float(r["Counter_Value"]) * 1024.0)
         return out
 
@@ -101,8 +101,12 @@ def summarize_pmc(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir
         kernels[name] = {"stage": stage, "fetch_bytes_per_launch": round(f), "write_bytes_per_launch": round(w),
                          "hbm_bytes_per_launch": round(f + w), "launches": len(fetch[name]),
                          "sources_sha256": kernel_sources_sha(files)}
+    bench = f"python3 /root/repo/bench.py --workload {workload} --steps 2 --warmup 1 --no-cpu-baseline --no-profile"
     out = {"workload": workload, "copy_scale_fetch": round(sf, 4), "copy_scale_write": round(sw, 4),
            "counters": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch)",
+           "commands": [f"cd /tmp && rocprofv3 --pmc {c} -d <dir> -o run --output-format csv -- {b}"
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")
+                        for b in (bench, "python3 /root/repo/bench.py --calibrate-copy")],
            "kernels": kernels}
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
     with open(path, "w") as fh:
