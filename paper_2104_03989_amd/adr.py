@@ -74,7 +74,7 @@ class Views_(C.Structure):
 
 class FwdOut_(C.Structure):
     _fields_ = [("vis", P), ("color", P), ("image", P), ("dimage", P), ("loss", P),
-                ("tri_id", P), ("coverage", P)]
+                ("tri_id", P), ("coverage", P), ("aa", P)]
 
 
 class Grads_(C.Structure):
@@ -83,7 +83,7 @@ class Grads_(C.Structure):
 
 class OitOut_(C.Structure):
     _fields_ = [("n_layers", I32), ("vis", P), ("color", P), ("alpha", P), ("blend", P), ("comp", P),
-                ("dimage", P), ("loss", P)]
+                ("dimage", P), ("loss", P), ("aa", P)]
 
 
 class Param_(C.Structure):
@@ -357,9 +357,12 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
         if ref is not None:
             out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
             out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)
+            # received antialiasing per sample, kept for the backward pass
+            out["aa"] = torch.empty(B, Hs, Ws, 4, dtype=torch.float32, device=dev)
         else:
-            out["dimage"] = out["loss"] = None
-    fo = FwdOut_(*[_ptr(out[k]) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage")])
+            out["dimage"] = out["loss"] = out["aa"] = None
+    fo = FwdOut_(*[_ptr(out.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
+                                              "aa")])
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
     _check(_lib.adr_render_fwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref),
                                LOSS[loss], C.byref(fo), flags, _stream(stream)))
@@ -369,7 +372,8 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
 def render_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, saved: dict,
                grads: dict, dloss=None, flags: int = 0, pos=None, stream=None):
     """Accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'] (tensors or None)."""
-    fo = FwdOut_(*[_ptr(saved.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage")])
+    fo = FwdOut_(*[_ptr(saved.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
+                                                 "aa")])
     g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
     _check(_lib.adr_render_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(fo),
@@ -648,8 +652,10 @@ def render_oit_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: D
                    comp=torch.empty(layers, B, H, W, 3, dtype=torch.float32, device=dev))
         out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if ref is not None else None
         out["loss"] = torch.empty(1, dtype=torch.float32, device=dev) if ref is not None else None
+        out["aa"] = torch.empty(layers, B, H, W, 4, dtype=torch.float32, device=dev) if ref is not None else None
     out["layers"] = layers
-    oo = OitOut_(layers, *[_ptr(out[k]) for k in ("vis", "color", "alpha", "blend", "comp", "dimage", "loss")])
+    oo = OitOut_(layers, *[_ptr(out.get(k)) for k in ("vis", "color", "alpha", "blend", "comp", "dimage", "loss",
+                                                      "aa")])
     ms, mt, vs = mesh.struct(), mat.struct(), views.struct()
     _check(_lib.adr_render_oit_fwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref), LOSS[loss],
                                    C.byref(oo), flags, _stream(stream)))
@@ -660,7 +666,7 @@ def render_oit_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: D
                    grads: dict, dloss=None, flags: int = 0, stream=None):
     """Adjoint of render_oit_fwd; accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'|'alpha']."""
     oo = OitOut_(saved["layers"], *[_ptr(saved.get(k)) for k in ("vis", "color", "alpha", "blend", "comp", "dimage",
-                                                                  "loss")])
+                                                                  "loss", "aa")])
     g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
     ms, mt, vs = mesh.struct(), mat.struct(), views.struct()
     _check(_lib.adr_render_oit_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(oo), _ptr(dloss), C.byref(g),

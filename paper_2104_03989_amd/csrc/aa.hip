@@ -33,6 +33,8 @@ struct AAArgs {
   const float* color;
   int tiles_x, tiles_y;
   int no_aa;
+  float4* stats;  // per (sample) pixel (W, acc) of the received antialiasing: written by the
+                  // forward, read by the adjoint instead of re-evaluating pairs (NULL: none)
 };
 
 // The crossing edge of pair (P, Q) for front triangle F, or false.
@@ -176,6 +178,11 @@ __device__ __forceinline__ Recv recv_stats(const AAArgs& a, int b, int i, int j)
   return r;
 }
 
+__device__ __forceinline__ Recv recv_load(const float4* st, int64_t o) {
+  const float4 q = st[o];
+  return Recv{q.x, mk(q.y, q.z, q.w)};
+}
+
 // Loss term of one pixel (Sec. 5.3) and its gradient, written to dimage[o].
 __device__ __forceinline__ float pixel_loss(f3 out, f3 r, int loss_kind, float inv_n, float* dimage, int64_t o) {
   const bool tm = loss_kind == ADR_LOSS_L1_TONEMAP || loss_kind == ADR_LOSS_L2_TONEMAP;
@@ -253,6 +260,7 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
     if (!a.no_aa) {
       Recv r = recv_stats(a, p.b, p.i, p.j);
       if (r.W > 0.f) out += (1.0f / fmaxf(r.W, 1.0f)) * r.acc;
+      if (a.stats) a.stats[o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
     }
     if (image) st3(image, o, out);
     if (ref) {
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   if (!a.no_aa) {
     uint64_t k = a.vis[o];
     f3 c = ldc(a.color, o);
-    Recv rs = recv_stats(a, p.b, p.i, p.j);
+    Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
     float Ms = fmaxf(rs.W, 1.0f);
     gc = (1.0f - rs.W / Ms) * gself;
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
@@ -323,7 +331,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       float w = recv_Q ? s - 0.5f : 0.5f - s;
       f3 cn = ldc(a.color, on);
       f3 gn = scale * sample_grad(a, dimage, p.b, ni, nj);
-      Recv rr = self_recv ? rs : recv_stats(a, p.b, ni, nj);
+      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, on) : recv_stats(a, p.b, ni, nj));
       float Mr = fmaxf(rr.W, 1.0f);
       f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
       f3 c_r = self_recv ? c : cn, c_src = self_recv ? cn : c;
@@ -362,8 +370,9 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
 }
 
 static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
-                      const float* color, int no_aa) {
+                      const float* color, int no_aa, float* stats) {
   AAArgs a;
+  a.stats = reinterpret_cast<float4*>(stats);
   a.m = m;
   a.v = v;
   a.snap = reinterpret_cast<const int4*>(s.snap);
@@ -380,8 +389,8 @@ static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const u
 hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
-                              hipStream_t st) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa);
+                              hipStream_t st, float* stats) {
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats);
   int nb = a.tiles_x * a.tiles_y * v.B;
   if (!image && !ref) return hipSuccess;
   hipError_t e;
@@ -408,8 +417,8 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
-                         hipStream_t st) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa);
+                         hipStream_t st, const float* stats) {
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats));
   int nb = a.tiles_x * a.tiles_y * v.B;
   hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.fix_clip, s.det);
   return hipGetLastError();

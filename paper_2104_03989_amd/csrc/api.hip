@@ -392,7 +392,7 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
   TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
   TIMED(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
-                            (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st),
+                            (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st, out->aa),
          "antialias/loss");
   return ADR_OK;
 }
@@ -429,7 +429,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
   TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
   TIMED(5, launch_aa_bwd(m, v, s, saved->vis, saved->color, saved->dimage, dloss,
-                       (flags & ADR_FWD_NO_AA) ? 1 : 0, st),
+                       (flags & ADR_FWD_NO_AA) ? 1 : 0, st, saved->aa),
          "antialias adjoint");
   TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
                             saved->vis, st),
@@ -535,7 +535,7 @@ adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     TIMED(15, launch_oit_blend(npx, vk, out->color + 3 * k * npx, out->alpha + k * npx, behind, bk, st), "blend");
     TIMED(4, launch_aa_loss_fwd(m, v, s, vk, bk, k == 0 ? ref_image : nullptr, loss_kind, no_aa,
                                 out->comp + 3 * k * npx, k == 0 ? out->dimage : nullptr, k == 0 ? out->loss : nullptr,
-                                st),
+                                st, out->aa ? out->aa + 4 * k * npx : nullptr),
           "antialias/loss");
   }
   return ADR_OK;
@@ -583,7 +583,7 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     const float* ak = saved->alpha + k * npx;
     const float* behind = k + 1 < L ? saved->comp + 3 * (k + 1) * npx : nullptr;
     TIMED(5, launch_aa_bwd(m, v, s, vk, saved->blend + 3 * k * npx, k == 0 ? saved->dimage : gbehind,
-                           k == 0 ? dloss : nullptr, no_aa, st),
+                           k == 0 ? dloss : nullptr, no_aa, st, saved->aa ? saved->aa + 4 * k * npx : nullptr),
           "antialias adjoint");
     TIMED(15, launch_oit_blend_bwd(npx, vk, ck, ak, behind, s.gcolor, galpha, k + 1 < L ? gbehind : nullptr, st),
           "blend adjoint");

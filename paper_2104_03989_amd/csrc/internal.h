@@ -108,13 +108,15 @@ hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Te
                             const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
                             float* color, int32_t* tri_id, hipStream_t st, const Tex* al = nullptr,
                             float* alpha = nullptr);
+// stats: per-pixel (W, acc) of the received antialiasing, written by the
+// forward and read by the adjoint (optional).
 hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
-                              hipStream_t st);
+                              hipStream_t st, float* stats = nullptr);
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
-                         hipStream_t st);
+                         hipStream_t st, const float* stats = nullptr);
 hipError_t launch_oit_blend(int64_t n, const uint64_t* vis, const float* color, const float* alpha,
                             const float* behind, float* blend, hipStream_t st);
 hipError_t launch_oit_blend_bwd(int64_t n, const uint64_t* vis, const float* color, const float* alpha,

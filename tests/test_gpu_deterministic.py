@@ -85,3 +85,22 @@ def test_deterministic_long_texel_groups(ctx):
         _say(f"  grad {n}: rel-L2 {e:.3g}")
         assert e < GRAD_TOL, (n, e)
         assert np.array_equal(runs[1][n].view(np.uint32), runs[0][n].view(np.uint32)), n
+
+
+def test_cached_antialiasing_stats_give_the_same_bits(ctx):
+    # the backward reads the forward's received-antialiasing statistics when
+    # they are saved; without them it recomputes the neighbours' pairs: the
+    # two paths give identical gradients (deterministic mode: same bits)
+    from paper_2104_03989_amd import adr
+    _say("cached aa stats")
+    w = synth.scaled(synth.workload_paper_loop(map_size=256, ref_nu=40, lat_nu=10), views=2, res=128)
+    mvp32, eye = OL.cameras(w)
+    gs = GpuScene(w, ctx, mvp32, eye)
+    ref = OL.reference_image(w, mvp32, eye)
+    ref_dev = ref.reshape(2, 128, 128, 3).to(torch.float32).cuda().contiguous()
+    out = gs.render("latent", ref=ref_dev, flags=adr.DETERMINISTIC)
+    assert out["aa"] is not None
+    a = gs.grads(out, ("pos", "kd", "normal"), flags=adr.DETERMINISTIC)
+    b = gs.grads(dict(out, aa=None), ("pos", "kd", "normal"), flags=adr.DETERMINISTIC)
+    for n in ("pos", "kd", "normal"):
+        assert np.array_equal(a[n], b[n]), n
