@@ -140,10 +140,11 @@ typedef struct adr_fwd_out {
   float* loss;                   /* [1] required with a reference: the image loss */
   int32_t* tri_id;               /* [B,H,W] nullable: 0 empty, else triangle + 1 */
   uint32_t* coverage;            /* [B,H,W] nullable: covering triangles before the depth test */
-  float* aa;                     /* [B,H,W,4] nullable: per (sample) pixel the antialiasing it
-                                    receives, (W, acc) with out = c + acc / max(1, W); written by
-                                    the forward when set, read by the backward when set (it then
-                                    skips recomputing the neighbours' pairs) */
+  float* aa;                     /* [B,H,W,8] nullable: per (sample) pixel the antialiasing it
+                                    receives, (W, acc) with out = c + acc / max(1, W), then the
+                                    crossing parameters of its pairs with the right and upper
+                                    neighbours; written by the forward when set, read by the
+                                    backward when set (it then evaluates no pair edge twice) */
 } adr_fwd_out;
 
 #define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
@@ -228,7 +229,7 @@ typedef struct adr_oit_out {
   float* comp;                   /* [L,B,H,W,3] required: C_k; C_0 is the image */
   float* dimage;                 /* [B,H,W,3] required with a reference: dL/d image */
   float* loss;                   /* [1] required with a reference */
-  float* aa;                     /* [L,B,H,W,4] nullable: each layer's received antialiasing, as
+  float* aa;                     /* [L,B,H,W,8] nullable: each layer's received antialiasing, as
                                     adr_fwd_out.aa */
 } adr_oit_out;
 

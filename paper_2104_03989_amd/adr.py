@@ -358,7 +358,7 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
             out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
             out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)
             # received antialiasing per sample, kept for the backward pass
-            out["aa"] = torch.empty(B, Hs, Ws, 4, dtype=torch.float32, device=dev)
+            out["aa"] = torch.empty(B, Hs, Ws, 8, dtype=torch.float32, device=dev)
         else:
             out["dimage"] = out["loss"] = out["aa"] = None
     fo = FwdOut_(*[_ptr(out.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
@@ -652,7 +652,7 @@ def render_oit_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: D
                    comp=torch.empty(layers, B, H, W, 3, dtype=torch.float32, device=dev))
         out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if ref is not None else None
         out["loss"] = torch.empty(1, dtype=torch.float32, device=dev) if ref is not None else None
-        out["aa"] = torch.empty(layers, B, H, W, 4, dtype=torch.float32, device=dev) if ref is not None else None
+        out["aa"] = torch.empty(layers, B, H, W, 8, dtype=torch.float32, device=dev) if ref is not None else None
     out["layers"] = layers
     oo = OitOut_(layers, *[_ptr(out.get(k)) for k in ("vis", "color", "alpha", "blend", "comp", "dimage", "loss",
                                                       "aa")])

@@ -35,7 +35,11 @@ struct AAArgs {
   int no_aa;
   float4* stats;  // per (sample) pixel (W, acc) of the received antialiasing: written by the
                   // forward, read by the adjoint instead of re-evaluating pairs (NULL: none)
+  float* codes;   // per pixel, codes of the pairs with the right and the upper neighbour
+  int code_stride;  // floats between two pixels' code pairs (the codes of pixel o start at
+                    // codes[code_stride * o])
 };
+
 
 // The crossing edge of pair (P, Q) for front triangle F, or false.
 struct Cross {
@@ -106,6 +110,11 @@ __device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi
   return false;
 }
 
+// A pair's code: -1 if it does not blend, else its crossing parameter s in
+// [0, 1], plus 2 if s was clamped.  Every pair is evaluated once, by its left
+// or lower pixel; both pixels then read its code.
+__device__ __forceinline__ float pair_code(const Cross& x) { return x.clamped ? x.s + 2.f : x.s; }
+
 // Pair between pixel (i,j) and its neighbour (ni,nj): which side is P and
 // the crossing, or false if the pair does not blend.
 struct Pair {
@@ -140,6 +149,22 @@ __device__ __forceinline__ float tmap_d(float x) {
   return srgb_d(log1pf(a)) / (1.0f + a);
 }
 
+// Code of the pair between pixel (i, j) and its neighbour in direction q
+// (0 left, 1 right, 2 down, 3 up); the neighbour must be inside the image.
+__device__ __forceinline__ float code_of(const AAArgs& a, int64_t base, int i, int j, int q) {
+  const int ci = q == 0 ? i - 1 : i, cj = q == 2 ? j - 1 : j;
+  return a.codes[a.code_stride * (base + (int64_t)cj * a.v.W + ci) + (q >= 2 ? 1 : 0)];
+}
+
+// Weight a pixel receives from a pair with code c, given whether it is the
+// pair's front pixel P.
+__device__ __forceinline__ float received_from(float c, bool self_is_P) {
+  if (c < 0.f) return 0.f;
+  const float s = c >= 2.f ? c - 2.f : c;
+  if (self_is_P) return s < 0.5f ? 0.5f - s : 0.f;
+  return s > 0.5f ? s - 0.5f : 0.f;
+}
+
 // Weight pixel (i, j) receives from the pair with its neighbour, and the
 // neighbour's index; 0 if the pair does not blend into this pixel.
 __device__ __forceinline__ float received(const AAArgs& a, int b, int i, int j, uint64_t k, int ni, int nj,
@@ -169,7 +194,9 @@ __device__ __forceinline__ Recv recv_stats(const AAArgs& a, int b, int i, int j)
     int ni = i + di[q], nj = j + dj[q];
     if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
     int64_t on = base + (int64_t)nj * a.v.W + ni;
-    float w = received(a, b, i, j, k, ni, nj, a.vis[on]);
+    const uint64_t kn = a.vis[on];
+    float w = a.codes ? ((uint32_t)k == (uint32_t)kn ? 0.f : received_from(code_of(a, base, i, j, q), k < kn))
+                      : received(a, b, i, j, k, ni, nj, kn);
     if (w > 0.f) {
       r.W += w;
       r.acc += w * (ldc(a.color, on) - c);
@@ -244,6 +271,26 @@ __device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, 
   return (1.0f / (float)(a.v.ms * a.v.ms)) * ldc(dimage, op);
 }
 
+// Codes of every pixel's pairs with its right and upper neighbours.
+__global__ __launch_bounds__(256) void k_aa_pairs(AAArgs a) {
+  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  if (!p.ok) return;
+  const int64_t base = (int64_t)p.b * a.v.H * a.v.W;
+  const int64_t o = base + (int64_t)p.j * a.v.W + p.i;
+  const uint64_t k = a.vis[o];
+  float code[2] = {-1.f, -1.f};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int ni = p.i + (q == 0 ? 1 : 0), nj = p.j + (q == 1 ? 1 : 0);
+    if (ni >= a.v.W || nj >= a.v.H) continue;
+    Pair pr;
+    if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[base + (int64_t)nj * a.v.W + ni], pr)) code[q] = pair_code(pr.x);
+  }
+  a.codes[a.code_stride * o] = code[0];
+  a.codes[a.code_stride * o + 1] = code[1];
+}
+
 __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __restrict__ ref,
                                                      int loss_kind, float* __restrict__ image,
                                                      float* __restrict__ dimage,
@@ -260,7 +307,7 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
     if (!a.no_aa) {
       Recv r = recv_stats(a, p.b, p.i, p.j);
       if (r.W > 0.f) out += (1.0f / fmaxf(r.W, 1.0f)) * r.acc;
-      if (a.stats) a.stats[o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
+      if (a.stats) a.stats[2 * o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
     }
     if (image) st3(image, o, out);
     if (ref) {
@@ -313,7 +360,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   if (!a.no_aa) {
     uint64_t k = a.vis[o];
     f3 c = ldc(a.color, o);
-    Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
+    Recv rs = a.stats ? recv_load(a.stats, 2 * o) : recv_stats(a, p.b, p.i, p.j);
     float Ms = fmaxf(rs.W, 1.0f);
     gc = (1.0f - rs.W / Ms) * gself;
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
@@ -321,9 +368,24 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       int ni = p.i + di[q], nj = p.j + dj[q];
       if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
       int64_t on = base + (int64_t)nj * a.v.W + ni;
+      const uint64_t kn = a.vis[on];
       Pair pr;
-      if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[on], pr)) continue;
-      float s = pr.x.s;
+      bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
+      float s;
+      if (a.codes) {
+        // the pair's code from the forward; the edge itself is only needed
+        // by the owner, for the gradient of s
+        if ((uint32_t)k == (uint32_t)kn) continue;
+        const float c = code_of(a, base, p.i, p.j, q);
+        if (c < 0.f) continue;
+        pr.self_is_P = k < kn;
+        pr.x.clamped = c >= 2.f;
+        s = c >= 2.f ? c - 2.f : c;
+        pr.x.s = s;
+      } else {
+        if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, kn, pr)) continue;
+        s = pr.x.s;
+      }
       if (s == 0.5f) continue;
       // the receiver is Q for s > 1/2 (w = s - 1/2) and P for s < 1/2 (w = 1/2 - s)
       bool recv_Q = s > 0.5f;
@@ -331,7 +393,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       float w = recv_Q ? s - 0.5f : 0.5f - s;
       f3 cn = ldc(a.color, on);
       f3 gn = scale * sample_grad(a, dimage, p.b, ni, nj);
-      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, on) : recv_stats(a, p.b, ni, nj));
+      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, 2 * on) : recv_stats(a, p.b, ni, nj));
       float Mr = fmaxf(rr.W, 1.0f);
       f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
       f3 c_r = self_recv ? c : cn, c_src = self_recv ? cn : c;
@@ -340,8 +402,8 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       if (rr.W > 1.0f) dw -= (1.0f / (rr.W * rr.W)) * rr.acc;
       float g_w = dot(g_r, dw);
       float g_s = recv_Q ? g_w : -g_w;
-      bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
       if (!owner || pr.x.clamped || g_s == 0.f) continue;
+      if (a.codes && !eval_pair(a, p.b, p.i, p.j, k, ni, nj, kn, pr)) continue;  // the edge (same s)
       // s = eP / (eP - eQ)
       double id2 = 1.0 / (pr.x.den * pr.x.den);
       double g_eP = -g_s * pr.x.eQ * id2, g_eQ = g_s * pr.x.eP * id2;
@@ -369,10 +431,19 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   st3(gcolor, o, gc);
 }
 
+// stats: the caller's [.., 8] buffer, (W, acc) then the pair codes of each
+// pixel; without it the codes go to context scratch (forward) or are not
+// used (adjoint: every pair is re-evaluated).
 static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
-                      const float* color, int no_aa, float* stats) {
+                      const float* color, int no_aa, float* stats, bool fwd) {
   AAArgs a;
   a.stats = reinterpret_cast<float4*>(stats);
+  a.code_stride = 8;
+  a.codes = stats ? stats + 4 : nullptr;
+  if (!stats && fwd) {
+    a.codes = s.aa_codes;
+    a.code_stride = 2;
+  }
   a.m = m;
   a.v = v;
   a.snap = reinterpret_cast<const int4*>(s.snap);
@@ -390,10 +461,14 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
                               hipStream_t st, float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats);
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats, true);
   int nb = a.tiles_x * a.tiles_y * v.B;
   if (!image && !ref) return hipSuccess;
   hipError_t e;
+  if (!no_aa) {
+    hipLaunchKernelGGL(k_aa_pairs, dim3(nb), dim3(256), 0, st, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (v.ms > 1) {
     // antialiased samples, then the resolve and the loss per pixel
     hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, (const float*)nullptr, loss_kind,
@@ -418,7 +493,7 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st, const float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats));
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats), false);
   int nb = a.tiles_x * a.tiles_y * v.B;
   hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.fix_clip, s.det);
   return hipGetLastError();

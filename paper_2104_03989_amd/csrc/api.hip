@@ -63,7 +63,8 @@ struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
   Buf oit_g, oit_a;  // depth-peeling adjoint: dL/d(composite behind) and dL/d alpha per pixel
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s,
+      aa_codes;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -219,6 +220,8 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       return r;
     if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
   }
+  if ((r = ensure(ctx->aa_codes, B * v.W * v.H * 8))) return r;
+  s.aa_codes = (float*)ctx->aa_codes.p;
   s.image_s = nullptr;
   if (v.ms > 1) {
     if ((r = ensure(ctx->image_s, B * v.W * v.H * 12))) return r;
@@ -324,7 +327,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
-                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->aa_codes, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
@@ -535,7 +538,7 @@ adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     TIMED(15, launch_oit_blend(npx, vk, out->color + 3 * k * npx, out->alpha + k * npx, behind, bk, st), "blend");
     TIMED(4, launch_aa_loss_fwd(m, v, s, vk, bk, k == 0 ? ref_image : nullptr, loss_kind, no_aa,
                                 out->comp + 3 * k * npx, k == 0 ? out->dimage : nullptr, k == 0 ? out->loss : nullptr,
-                                st, out->aa ? out->aa + 4 * k * npx : nullptr),
+                                st, out->aa ? out->aa + 8 * k * npx : nullptr),
           "antialias/loss");
   }
   return ADR_OK;
@@ -583,7 +586,7 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     const float* ak = saved->alpha + k * npx;
     const float* behind = k + 1 < L ? saved->comp + 3 * (k + 1) * npx : nullptr;
     TIMED(5, launch_aa_bwd(m, v, s, vk, saved->blend + 3 * k * npx, k == 0 ? saved->dimage : gbehind,
-                           k == 0 ? dloss : nullptr, no_aa, st, saved->aa ? saved->aa + 4 * k * npx : nullptr),
+                           k == 0 ? dloss : nullptr, no_aa, st, saved->aa ? saved->aa + 8 * k * npx : nullptr),
           "antialias adjoint");
     TIMED(15, launch_oit_blend_bwd(npx, vk, ck, ak, behind, s.gcolor, galpha, k + 1 < L ? gbehind : nullptr, st),
           "blend adjoint");
