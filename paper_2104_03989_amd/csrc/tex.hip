@@ -34,6 +34,35 @@ constexpr int kMipTileLevels = 5;  // log2(kMipTile)
 
 __device__ __forceinline__ int ilog2i(int x) { return 31 - __clz(x); }
 
+// Row-major copy of a tile region between global memory and LDS with
+// consecutive threads on consecutive floats: rows of `w` floats, global row
+// stride `gs`; float4 when both are multiples of 4 and the base is aligned.
+template <bool LOAD>
+__device__ __forceinline__ void tile_copy(float* g, int64_t gs, float* l, int rows, int w, bool vec) {
+  const int tid = threadIdx.x;
+  if (vec) {
+    const int w4 = w >> 2, n = rows * w4;
+    for (int e = tid; e < n; e += blockDim.x) {
+      const int r = e / w4, x = e - r * w4;
+      float4* gp = reinterpret_cast<float4*>(g + r * gs) + x;
+      float4* lp = reinterpret_cast<float4*>(l + r * w) + x;
+      if (LOAD) *lp = *gp;
+      else *gp = *lp;
+    }
+  } else {
+    const int n = rows * w;
+    for (int e = tid; e < n; e += blockDim.x) {
+      const int r = e / w, x = e - r * w;
+      if (LOAD) l[e] = g[r * gs + x];
+      else g[r * gs + x] = l[e];
+    }
+  }
+}
+
+__device__ __forceinline__ bool vec_ok(const float* p, int w, int64_t gs) {
+  return (w & 3) == 0 && (gs & 3) == 0 && ((uintptr_t)p & 15) == 0;
+}
+
 __global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
   const Tex& t = ms.t[blockIdx.y];
   const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
@@ -41,21 +70,26 @@ __global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
   if ((int)blockIdx.x >= nt * nt || L <= 0) return;
   const int C = t.channels, tid = threadIdx.x;
   const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
-  __shared__ float lds[2][256 * 4];
+  __shared__ __align__(16) float base[kMipTile * kMipTile * 3];
+  __shared__ __align__(16) float lds[2][256 * 4];
   float* d = (float*)t.data;
+  // level 0 of the tile into LDS, coalesced
+  float* g0 = d + ((int64_t)(by * T) * S + bx * T) * C;
+  tile_copy<true>(g0, (int64_t)S * C, base, T, T * C, vec_ok(g0, T * C, (int64_t)S * C));
+  __syncthreads();
   int s = T >> 1;
   if (tid < s * s) {
     int r = tid / s, c = tid - r * s;
-    int64_t t00 = (int64_t)(by * T + 2 * r) * S + bx * T + 2 * c;
-    int64_t o = (int64_t)t.off[1] + (int64_t)(by * s + r) * (S >> 1) + bx * s + c;
+    int k00 = 2 * r * T + 2 * c;
     for (int ch = 0; ch < C; ++ch) {
-      float a = d[t00 * C + ch], b = d[(t00 + 1) * C + ch];
-      float e = d[(t00 + S) * C + ch], f = d[(t00 + S + 1) * C + ch];
-      float v = ((a + b) + (e + f)) * 0.25f;
-      lds[0][tid * C + ch] = v;
-      d[o * C + ch] = v;
+      float a = base[k00 * C + ch], b = base[(k00 + 1) * C + ch];
+      float e = base[(k00 + T) * C + ch], f = base[(k00 + T + 1) * C + ch];
+      lds[0][tid * C + ch] = ((a + b) + (e + f)) * 0.25f;
     }
   }
+  __syncthreads();
+  float* g1 = d + ((int64_t)t.off[1] + (int64_t)(by * s) * (S >> 1) + bx * s) * C;
+  tile_copy<false>(g1, (int64_t)(S >> 1) * C, lds[0], s, s * C, vec_ok(g1, s * C, (int64_t)(S >> 1) * C));
   for (int l = 2; l <= L; ++l) {
     const int sp = s;
     s >>= 1;
@@ -98,32 +132,22 @@ __global__ __launch_bounds__(256) void k_mip_build_top(MipSet ms) {
   }
 }
 
-// Adjoint of the coarse levels above the tile range: level l pushes a
-// quarter of each texel's gradient to its four children and is cleared.
-__global__ __launch_bounds__(256) void k_mip_adjoint_top(MipSet ms) {
+// Clears the gradients of the levels above the tile range once every tile
+// has folded them (one block per map).
+__global__ __launch_bounds__(256) void k_mip_clear_top(MipSet ms) {
   const Tex& t = ms.t[blockIdx.x];
-  const int S = t.size, C = t.channels;
+  if (t.levels - 1 <= kMipTileLevels) return;
   float* g = ms.g[blockIdx.x];
-  for (int l = t.levels - 1; l > kMipTileLevels; --l) {
-    const int s = S >> l, sc = 2 * s;
-    for (int idx = threadIdx.x; idx < s * s; idx += blockDim.x) {
-      int r = idx / s, c = idx - r * s;
-      int64_t k00 = (int64_t)t.off[l - 1] + (int64_t)(2 * r) * sc + 2 * c;
-      int64_t kids[4] = {k00, k00 + 1, k00 + sc, k00 + sc + 1};
-      int64_t o = (int64_t)t.off[l] + idx;
-      for (int ch = 0; ch < C; ++ch) {
-        float w = 0.25f * g[o * C + ch];
-        for (int k = 0; k < 4; ++k) g[kids[k] * C + ch] += w;
-        g[o * C + ch] = 0.f;
-      }
-    }
-    __syncthreads();
-  }
+  const int64_t a = (int64_t)t.off[kMipTileLevels + 1] * t.channels, b = (int64_t)t.off[t.levels] * t.channels;
+  for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) g[k] = 0.f;
 }
 
-// Adjoint within a level-0 tile: the tile's levels L..1 (L <= 5) folded
-// down through LDS (each level adds a quarter of its parent's folded value)
-// and added to level 0; the tile's coarse texels are cleared.
+// Adjoint within a level-0 tile: the tile's levels 1..L (L <= 5) are read
+// into LDS in one round (and cleared), folded down (each level adds a
+// quarter of its parent's folded value), and a quarter of the folded level 1
+// is added to level 0.
+constexpr int kPyrFloats = (256 + 64 + 16 + 4 + 1) * 3;  // levels 1..5 of a 32^2 tile, 3 channels
+
 __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
   const Tex& t = ms.t[blockIdx.y];
   const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
@@ -132,43 +156,86 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
   const int C = t.channels, tid = threadIdx.x;
   const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
   float* g = ms.g[blockIdx.y];
-  __shared__ float lds[2][256 * 4];
-  // level L of the tile has no parent inside it
-  int s = T >> L;
-  float* cur = lds[L & 1];
-  if (tid < s * s) {
-    int r = tid / s, c = tid - r * s;
-    int64_t o = (int64_t)t.off[L] + (int64_t)(by * s + r) * (S >> L) + bx * s + c;
-    for (int ch = 0; ch < C; ++ch) {
-      cur[tid * C + ch] = g[o * C + ch];
-      g[o * C + ch] = 0.f;
+  __shared__ float pyr[kPyrFloats];
+  // level l of the tile (s_l = T >> l texels a side) sits at pyr + po[l]
+  int po[kMipTileLevels + 2];
+  po[1] = 0;
+  for (int l = 1; l <= L; ++l) po[l + 1] = po[l] + (T >> l) * (T >> l) * C;
+  const int total = po[L + 1];
+  // one round of independent loads (and clears) for all levels of the tile
+  constexpr int kPer = (kPyrFloats + 255) / 256;
+  float v[kPer];
+  int64_t addr[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = tid + 256 * u;
+    addr[u] = -1;
+    if (e < total) {
+      int l = 1;
+      while (e >= po[l + 1]) ++l;
+      const int sl = T >> l, w = sl * C, k = e - po[l], r = k / w, x = k - r * w;
+      addr[u] = ((int64_t)t.off[l] + (int64_t)(by * sl + r) * (S >> l) + bx * sl) * C + x;
+      v[u] = g[addr[u]];
     }
   }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    if (addr[u] >= 0) {
+      pyr[tid + 256 * u] = v[u];
+      g[addr[u]] = 0.f;
+    }
+  }
+  // levels above the tile (a 32^2 tile's level 5 is one texel): its
+  // ancestors' gradients folded from the top, f = g_l + f / 4, added to it
+  // as a quarter of the folded parent (the same arithmetic as level by level)
+  __syncthreads();
+  if (tid < C && T == kMipTile && L == kMipTileLevels && t.levels - 1 > L) {
+    float f = 0.f;
+    for (int l = t.levels - 1; l > L; --l) {
+      const int sl = S >> l, sh = l - L;
+      f = g[((int64_t)t.off[l] + (int64_t)(by >> sh) * sl + (bx >> sh)) * C + tid] + 0.25f * f;
+    }
+    pyr[po[L] + tid] += 0.25f * f;
+  }
+  // fold down: level l += a quarter of level l + 1
   for (int l = L - 1; l >= 1; --l) {
-    const int sp = s;
-    s <<= 1;
     __syncthreads();
-    const float* par = lds[(l + 1) & 1];
-    float* dst = lds[l & 1];
-    if (tid < s * s) {
-      int r = tid / s, c = tid - r * s;
-      int kp = (r >> 1) * sp + (c >> 1);
-      int64_t o = (int64_t)t.off[l] + (int64_t)(by * s + r) * (S >> l) + bx * s + c;
-      for (int ch = 0; ch < C; ++ch) {
-        float v = g[o * C + ch] + 0.25f * par[kp * C + ch];
-        dst[tid * C + ch] = v;
-        g[o * C + ch] = 0.f;
-      }
+    const int sl = T >> l, sp = sl >> 1;
+    for (int k = tid; k < sl * sl * C; k += blockDim.x) {
+      const int texel = k / C, ch = k - texel * C, r = texel / sl, c = texel - r * sl;
+      pyr[po[l] + k] += 0.25f * pyr[po[l + 1] + ((r >> 1) * sp + (c >> 1)) * C + ch];
     }
   }
   __syncthreads();
-  const float* par = lds[1];
-  const int sp = T >> 1;
-  for (int k = tid; k < T * T; k += blockDim.x) {
-    int r = k / T, c = k - r * T;
-    int kp = (r >> 1) * sp + (c >> 1);
-    int64_t o = (int64_t)(by * T + r) * S + bx * T + c;
-    for (int ch = 0; ch < C; ++ch) g[o * C + ch] += 0.25f * par[kp * C + ch];
+  // level 0 += a quarter of the folded level 1, row by row with consecutive
+  // threads on consecutive floats (float4 where aligned)
+  const float* par = pyr + po[1];
+  const int sp = T >> 1, w = T * C;
+  float* g0 = g + ((int64_t)(by * T) * S + bx * T) * C;
+  const int64_t gs = (int64_t)S * C;
+  if (vec_ok(g0, w, gs)) {
+    const int w4 = w >> 2;
+    for (int e = tid; e < T * w4; e += blockDim.x) {
+      const int r = e / w4, x4 = e - r * w4;
+      float4* gp = reinterpret_cast<float4*>(g0 + r * gs) + x4;
+      float4 q4 = *gp;
+      float q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int x = 4 * x4 + u, c = x / C, ch = x - c * C;
+        q[u] = 0.25f * par[((r >> 1) * sp + (c >> 1)) * C + ch];
+      }
+      q4.x += q[0];
+      q4.y += q[1];
+      q4.z += q[2];
+      q4.w += q[3];
+      *gp = q4;
+    }
+  } else {
+    for (int e = tid; e < T * w; e += blockDim.x) {
+      const int r = e / w, x = e - r * w, c = x / C, ch = x - c * C;
+      g0[r * gs + x] += 0.25f * par[((r >> 1) * sp + (c >> 1)) * C + ch];
+    }
   }
 }
 
@@ -199,12 +266,11 @@ hipError_t launch_mip_build_set(const MipSet& ms, hipStream_t st) {
 
 hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st) {
   if (ms.n == 0) return hipSuccess;
-  if (has_top(ms)) {
-    hipLaunchKernelGGL(k_mip_adjoint_top, dim3(ms.n), dim3(256), 0, st, ms);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_mip_adjoint_tiles, dim3(max_tiles(ms), ms.n), dim3(256), 0, st, ms);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !has_top(ms)) return e;
+  // the levels above the tiles, read by every tile, are cleared afterwards
+  hipLaunchKernelGGL(k_mip_clear_top, dim3(ms.n), dim3(256), 0, st, ms);
   return hipGetLastError();
 }
 
