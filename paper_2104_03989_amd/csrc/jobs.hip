@@ -152,6 +152,10 @@ struct JobServer {
   bool started = false;
   adr_ctx* slot_ctx[kSlots] = {nullptr, nullptr, nullptr, nullptr};
   hipStream_t slot_stream[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  // per slot: the latent forward's received antialiasing, read by the
+  // backward that follows it on the slot's stream (grown on demand)
+  float* slot_aa[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  size_t slot_aa_cap[kSlots] = {0, 0, 0, 0};
   int next_slot = 0;
 };
 
@@ -402,7 +406,15 @@ adr_status enqueue_step(JobServer* s, Job& j) {
   adr_fwd_out ro{j.ref_vis, j.ref_color, j.ref_image, nullptr, nullptr, nullptr, nullptr};
   adr_status r = adr_render_fwd(ctx, &j.ref_mesh, &rm, &v, nullptr, 0, &ro, 0, st);
   if (r != ADR_OK) return r;
-  adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr};
+  const size_t aa_bytes = B * (size_t)d.width * d.height * 32;
+  if (s->slot_aa_cap[j.slot] < aa_bytes) {
+    if (s->slot_aa[j.slot] && hipFree(s->slot_aa[j.slot]) != hipSuccess) return ADR_E_HIP;
+    s->slot_aa[j.slot] = nullptr;
+    s->slot_aa_cap[j.slot] = 0;
+    if (hipMalloc(&s->slot_aa[j.slot], aa_bytes) != hipSuccess) return ADR_E_NOMEM;
+    s->slot_aa_cap[j.slot] = aa_bytes;
+  }
+  adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr, s->slot_aa[j.slot]};
   r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, ADR_FWD_BUILD_MIPS, st);
   if (r != ADR_OK) return r;
   adr_grads g{(d.opt_mask & 1) ? j.g_pos : nullptr, nullptr, j.g_kd, j.g_nm, j.g_orm};
@@ -576,6 +588,7 @@ void jobs_destroy(JobServer* s) {
   if (s->th.joinable()) s->th.join();
   for (auto& kv : s->jobs) release_dev(*kv.second);
   for (int k = 0; k < kSlots; ++k) {
+    if (s->slot_aa[k]) (void)hipFree(s->slot_aa[k]);
     if (s->slot_stream[k]) (void)hipStreamDestroy(s->slot_stream[k]);
     if (s->slot_ctx[k]) adr_ctx_destroy(s->slot_ctx[k]);
   }
