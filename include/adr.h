@@ -389,6 +389,13 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * adjoint (depth peeling).  ms and count: host arrays of ADR_N_STAGES. */
 #define ADR_N_STAGES 16
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
+
+/* Raster work split of a context (a tuning knob, results do not change):
+ * a triangle whose pixel bounding box holds at most tiny_bbox pixel centres
+ * is walked by one thread, up to med_bbox by one wave from a chip-wide queue,
+ * larger ones are binned to 16x16 tiles.  Defaults 64 and 4096; ranges
+ * 1 <= tiny_bbox <= 1024, tiny_bbox <= med_bbox <= 65536. */
+adr_status adr_ctx_set_raster(adr_ctx* ctx, int32_t tiny_bbox, int32_t med_bbox);
 adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count);
 
 /* Host helpers (no device work). */

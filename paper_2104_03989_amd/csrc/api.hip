@@ -69,6 +69,7 @@ struct adr_ctx {
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
   bool prof = false;
+  int tiny_bbox = kTinyBBox, med_bbox = kMedBBox;  // raster work split
   std::vector<Span> spans;
   std::vector<hipEvent_t> pool;
 };
@@ -272,6 +273,8 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
   s.big_cnt = (uint32_t*)ctx->big_cnt.p;
   s.med = (uint32_t*)ctx->med.p;
   s.partial = (float*)ctx->partial.p;
+  s.tiny_bbox = ctx->tiny_bbox;
+  s.med_bbox = ctx->med_bbox;
   s.gcolor = (float*)ctx->gcolor.p;
   s.dclip = (float*)ctx->dclip.p;
   s.dattr = (float*)ctx->dattr.p;
@@ -769,6 +772,15 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   TIMED(14, launch_skin_bwd(n_pos, n_bones, pos, bones, blend, g_pos_out, g_pos, g_weights, st), "skinning adjoint");
+  return ADR_OK;
+}
+
+adr_status adr_ctx_set_raster(adr_ctx* ctx, int32_t tiny_bbox, int32_t med_bbox) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (tiny_bbox < 1 || tiny_bbox > 1024 || med_bbox < tiny_bbox || med_bbox > 65536)
+    return fail(ADR_E_INVALID, "raster split: need 1 <= tiny <= 1024 and tiny <= med <= 65536");
+  ctx->tiny_bbox = tiny_bbox;
+  ctx->med_bbox = med_bbox;
   return ADR_OK;
 }
 

@@ -11,8 +11,8 @@ namespace adr {
 constexpr uint64_t kKeyEmpty = 0xFFFFFFFF00000000ull;
 constexpr int kZMax = 16777215;
 constexpr int kMaxLevels = 15;
-constexpr int kTinyBBox = 64;      // pixel bbox up to this: walked by one thread
-constexpr int kMedBBox = 4096;     // up to this: walked by a whole wave; larger: tile-binned
+constexpr int kTinyBBox = 64;      // default: pixel bbox up to this walked by one thread
+constexpr int kMedBBox = 4096;     // default: up to this walked by a whole wave; larger: tile-binned
 constexpr int kBigTile = 16;       // big-triangle tiles are kBigTile x kBigTile pixels
 
 // Texture as the kernels see it: level offsets in texels precomputed.
@@ -52,6 +52,7 @@ struct Scratch {
   uint32_t* big;      // [B,T] big-triangle lists (per view segments of T)
   uint32_t* big_cnt;  // [B + 1]: per-view big-triangle counts, then the medium-queue count
   uint32_t* med;      // [B * n_tri] medium-triangle queue (view * n_tri + triangle)
+  int tiny_bbox, med_bbox;  // raster work split (the context's settings)
   float* partial;     // loss partials
   float* gcolor;      // [B,H,W,3] dL/d(colour before AA)
   float* dclip;       // [B,V,4]

@@ -13,9 +13,10 @@
 // Everything here is integer or correctly rounded float32 in a fixed order,
 // so the visibility buffer is bit-exact and independent of launch order.
 //
-// Work split: a triangle whose pixel bounding box holds at most kTinyBBox
-// pixel centres is walked by one thread (most triangles of dense meshes are
-// pixel-sized); one of up to kMedBBox goes to a queue whose entries a second
+// Work split: a triangle whose pixel bounding box holds at most `tiny` (64
+// by default, a per-context setting) pixel centres is walked by one thread
+// (most triangles of dense meshes are pixel-sized); one of up to `med` (4096)
+// goes to a queue whose entries a second
 // kernel spreads over all waves of the chip, one triangle per wave at a time;
 // larger ones go to a per-view list that a third kernel bins against 16x16
 // tiles in LDS and resolves one pixel per thread.
@@ -170,15 +171,16 @@ __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j
 }
 
 // One thread per triangle and view.  A triangle whose pixel bounding box
-// holds at most kTinyBBox pixel centres is walked by its thread; up to
-// kMedBBox it is queued for k_raster_med (big_cnt[B] counts the queue);
+// holds at most `tiny` pixel centres is walked by its thread; up to `med`
+// it is queued for k_raster_med (big_cnt[B] counts the queue);
 // larger ones go to the view's list for the tile kernel.
 __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const int4* __restrict__ snap,
                                                       int8_t* __restrict__ orient, uint32_t* __restrict__ big,
                                                       uint32_t* __restrict__ big_cnt, uint32_t* __restrict__ med,
                                                       unsigned long long* __restrict__ vis,
                                                       uint32_t* __restrict__ cov,
-                                                      const unsigned long long* __restrict__ floor) {
+                                                      const unsigned long long* __restrict__ floor, int tiny,
+                                                      int med_max) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   int area = 0, b = 0, t = 0;
   Setup s;
@@ -196,10 +198,10 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
     }
   }
   const int64_t HW = (int64_t)v.W * v.H;
-  if (area > kMedBBox) {
+  if (area > med_max) {
     uint32_t slot = atomicAdd(big_cnt + b, 1u);
     big[(int64_t)b * m.n_tri + slot] = (uint32_t)t;
-  } else if (area > 0 && area <= kTinyBBox) {
+  } else if (area > 0 && area <= tiny) {
     unsigned long long* vv = vis + b * HW;
     uint32_t* cv = cov ? cov + b * HW : nullptr;
     const unsigned long long* fl = floor ? floor + b * HW : nullptr;
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
   }
   // medium triangles of this wave: one queue reservation per wave
   const int lane = threadIdx.x & 63;
-  const bool is_med = area > kTinyBBox && area <= kMedBBox;
+  const bool is_med = area > tiny && area <= med_max;
   const unsigned long long mm = __ballot(is_med);
   if (mm) {
     const int leader = __ffsll((long long)mm) - 1;
@@ -357,7 +359,7 @@ hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint
   const int4* sv = reinterpret_cast<const int4*>(s.snap);
   auto* vk = reinterpret_cast<unsigned long long*>(vis);
   hipLaunchKernelGGL(k_raster_small, dim3((n + 255) / 256), dim3(256), 0, st, m, v, sv, s.orient,
-                     s.big, s.big_cnt, s.med, vk, cov, fl);
+                     s.big, s.big_cnt, s.med, vk, cov, fl, s.tiny_bbox, s.med_bbox);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // enough waves to fill the chip; each loops over the queue

@@ -613,6 +613,48 @@ def workload_aggregate(views: int = 8, res: int = 512, map_size: int = 2048, n_l
                     ("pos", "kd", "normal", "alpha"), oit_layers=layers)
 
 
+def workload_batched(n_meshes: int = 64, tris=(1000, 50000), views=(4, 16), res_choices=(256, 512, 1024),
+                     map_sizes=(512, 1024, 2048), max_ref_nu: int = 192, progress=None) -> list:
+    """Batched meshes of uneven size: per mesh a latent of T triangles
+    (log-uniform in ``tris``, a geodesic sphere of frequency round(sqrt(T/20))
+    resampled on its own fbm surface), a reference at four times the
+    frequency (at most ``max_ref_nu``), 4-16 views at one resolution out of
+    ``res_choices``, and maps of one size out of ``map_sizes``: a fixed RGBA8
+    base colour shared with the reference, FP32 normal (flat) and ORM
+    (constant) maps optimised with the positions under GGX; L1 loss.  Maps of
+    one size are shared between meshes."""
+    c = 9
+    g = _rng(seed_for(c, 0))
+    shared = {}
+
+    def ref_maps(S):
+        if S not in shared:
+            shared[S] = (Texture(to_rgba8(value_noise_map(S, 3, seed_for(c, 10 + S))), "rgba8"),
+                         _f32(detail_normal_map(S, seed_for(c, 20 + S))), _f32(orm_map(S, seed_for(c, 30 + S))))
+        return shared[S]
+
+    out = []
+    for k in range(n_meshes):
+        T = math.exp(g.uniform(math.log(tris[0]), math.log(tris[1])))
+        nu = max(3, int(round(math.sqrt(T / 20.0))))
+        nu_ref = min(4 * nu, max_ref_nu)
+        B = int(g.integers(views[0], views[1] + 1))
+        res = int(res_choices[int(g.integers(0, len(res_choices)))])
+        S = int(map_sizes[int(g.integers(0, len(map_sizes)))])
+        rad = lambda d, k=k: fbm_radius(d, seed_for(c, 100 + k))
+        kd, nm, orm = ref_maps(S)
+        ref = Scene(sphere_mesh(nu_ref, rad), "ggx", kd, nm, orm)
+        lat = Scene(sphere_mesh(nu, rad), "ggx", kd, _f32(flat_normal_map(S)),
+                    _f32(np.broadcast_to(np.array([0.0, 0.5, 0.0]), (S, S, 3))))
+        dirs = random_unit(B, seed_for(c, 200 + k))
+        light = random_unit(B, seed_for(c, 300 + k))
+        out.append(Workload(f"batched_{k}", ref, lat, dirs, light, np.ones((B, 3)), res, res, 3.0, 45.0, "l1", 1e-3,
+                            ("pos", "normal", "orm")))
+        if progress is not None:
+            progress(k, out[-1])
+    return out
+
+
 def scaled(w: Workload, views: int | None = None, res: int | None = None) -> Workload:
     """Same scene with fewer views and/or another resolution (test sizes)."""
     out = dataclasses.replace(w)
