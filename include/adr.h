@@ -140,11 +140,12 @@ typedef struct adr_fwd_out {
   float* loss;                   /* [1] required with a reference: the image loss */
   int32_t* tri_id;               /* [B,H,W] nullable: 0 empty, else triangle + 1 */
   uint32_t* coverage;            /* [B,H,W] nullable: covering triangles before the depth test */
-  float* aa;                     /* [B,H,W,8] nullable: per (sample) pixel the antialiasing it
-                                    receives, (W, acc) with out = c + acc / max(1, W), then the
-                                    crossing parameters of its pairs with the right and upper
-                                    neighbours; written by the forward when set, read by the
-                                    backward when set (it then evaluates no pair edge twice) */
+  float* aa;                     /* 8 floats per (sample) pixel, nullable, in two planes: [B,H,W]
+                                    float4 (W, acc), the antialiasing each pixel receives with
+                                    out = c + acc / max(1, W), then [B,H,W] float2, the crossing
+                                    parameters of its pairs with the right and upper neighbours
+                                    (the rest unused); written by the forward when set, read by
+                                    the backward when set (it then evaluates no pair edge twice) */
 } adr_fwd_out;
 
 #define ADR_FWD_BUILD_MIPS 1     /* rebuild levels 1.. of every F32 map from level 0 first */
@@ -229,8 +230,8 @@ typedef struct adr_oit_out {
   float* comp;                   /* [L,B,H,W,3] required: C_k; C_0 is the image */
   float* dimage;                 /* [B,H,W,3] required with a reference: dL/d image */
   float* loss;                   /* [1] required with a reference */
-  float* aa;                     /* [L,B,H,W,8] nullable: each layer's received antialiasing, as
-                                    adr_fwd_out.aa */
+  float* aa;                     /* 8 L B H W floats, nullable: each layer's received antialiasing,
+                                    laid out as adr_fwd_out.aa, layer after layer */
 } adr_oit_out;
 
 /* Forward of the depth-peeled render and, with ref_image, the image loss of

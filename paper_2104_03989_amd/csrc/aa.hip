@@ -36,8 +36,7 @@ struct AAArgs {
   float4* stats;  // per (sample) pixel (W, acc) of the received antialiasing: written by the
                   // forward, read by the adjoint instead of re-evaluating pairs (NULL: none)
   float* codes;   // per pixel, codes of the pairs with the right and the upper neighbour
-  int code_stride;  // floats between two pixels' code pairs (the codes of pixel o start at
-                    // codes[code_stride * o])
+  int code_stride;  // floats between two pixels' code pairs (pixel o's at codes[code_stride * o])
 };
 
 
@@ -307,7 +306,7 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
     if (!a.no_aa) {
       Recv r = recv_stats(a, p.b, p.i, p.j);
       if (r.W > 0.f) out += (1.0f / fmaxf(r.W, 1.0f)) * r.acc;
-      if (a.stats) a.stats[2 * o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
+      if (a.stats) a.stats[o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
     }
     if (image) st3(image, o, out);
     if (ref) {
@@ -360,7 +359,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   if (!a.no_aa) {
     uint64_t k = a.vis[o];
     f3 c = ldc(a.color, o);
-    Recv rs = a.stats ? recv_load(a.stats, 2 * o) : recv_stats(a, p.b, p.i, p.j);
+    Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
     float Ms = fmaxf(rs.W, 1.0f);
     gc = (1.0f - rs.W / Ms) * gself;
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
@@ -393,7 +392,7 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       float w = recv_Q ? s - 0.5f : 0.5f - s;
       f3 cn = ldc(a.color, on);
       f3 gn = scale * sample_grad(a, dimage, p.b, ni, nj);
-      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, 2 * on) : recv_stats(a, p.b, ni, nj));
+      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, on) : recv_stats(a, p.b, ni, nj));
       float Mr = fmaxf(rr.W, 1.0f);
       f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
       f3 c_r = self_recv ? c : cn, c_src = self_recv ? cn : c;
@@ -431,19 +430,18 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
   st3(gcolor, o, gc);
 }
 
-// stats: the caller's [.., 8] buffer, (W, acc) then the pair codes of each
-// pixel; without it the codes go to context scratch (forward) or are not
-// used (adjoint: every pair is re-evaluated).
+// stats: the caller's buffer of 8 floats per pixel, two planes: the pixels'
+// (W, acc) float4s, then their pair codes (2 floats each); without it the
+// codes go to context scratch (forward) or are not used (adjoint: every pair
+// is re-evaluated).
 static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                       const float* color, int no_aa, float* stats, bool fwd) {
   AAArgs a;
+  const int64_t npx = (int64_t)v.B * v.H * v.W;
   a.stats = reinterpret_cast<float4*>(stats);
-  a.code_stride = 8;
-  a.codes = stats ? stats + 4 : nullptr;
-  if (!stats && fwd) {
-    a.codes = s.aa_codes;
-    a.code_stride = 2;
-  }
+  a.code_stride = 2;
+  a.codes = stats ? stats + 4 * npx : nullptr;
+  if (!stats && fwd) a.codes = s.aa_codes;
   a.m = m;
   a.v = v;
   a.snap = reinterpret_cast<const int4*>(s.snap);

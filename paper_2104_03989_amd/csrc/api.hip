@@ -432,8 +432,13 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(1, launch_orient(m, v, s, st), "orientation");
-  TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
-  TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
+  {
+    FillSet f{};
+    f.add(s.fix_clip, n_clip);
+    f.add(s.fix_attr, n_attr);
+    f.add(s.fix_pos, 3 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1));
+    TIMED(12, launch_fill_multi(f, st), "clear");
+  }
   TIMED(5, launch_aa_bwd(m, v, s, saved->vis, saved->color, saved->dimage, dloss,
                        (flags & ADR_FWD_NO_AA) ? 1 : 0, st, saved->aa),
          "antialias adjoint");
@@ -456,7 +461,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
   }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
-    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
+    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st, true), "mesh adjoint");
   return ADR_OK;
 }
 
@@ -577,8 +582,13 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
   TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(1, launch_orient(m, v, s, st), "orientation");
-  TIMED(12, launch_fill_u64(s.fix_clip, n_clip, st), "clear");
-  TIMED(12, launch_fill_u64(s.fix_attr, n_attr, st), "clear");
+  {
+    FillSet f{};
+    f.add(s.fix_clip, n_clip);
+    f.add(s.fix_attr, n_attr);
+    f.add(s.fix_pos, 3 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1));
+    TIMED(12, launch_fill_multi(f, st), "clear");
+  }
   const int L = saved->n_layers;
   const int no_aa = (flags & ADR_FWD_NO_AA) ? 1 : 0;
   // front to back: dL/dC_k -> dL/dB_k (antialiasing adjoint) -> dL/dc_k,
@@ -614,7 +624,7 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
   }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
-    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st), "mesh adjoint");
+    TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st, true), "mesh adjoint");
   return ADR_OK;
 }
 

@@ -138,6 +138,20 @@ int64_t radix_hist_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
+// Zero-fill of several ranges of 8-byte words in one launch.
+constexpr int kFillRanges = 6;
+struct FillSet {
+  unsigned long long* p[kFillRanges];
+  int64_t len[kFillRanges];
+  int n;
+  void add(unsigned long long* q, int64_t l) {
+    if (q && l > 0 && n < kFillRanges) {
+      p[n] = q;
+      len[n++] = l;
+    }
+  }
+};
+hipError_t launch_fill_multi(const FillSet& f, hipStream_t st);
 hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st);
 
 // Number of texture-gradient slots (maps with a gradient buffer).
@@ -153,8 +167,9 @@ hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& 
                           const Tex* al = nullptr, float* gal = nullptr);
 hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st);
 hipError_t launch_mip_build_set(const MipSet& ms, hipStream_t st);
+// pos_cleared: the face-term accumulator (fix_pos) was zeroed by the caller.
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
-                           float* gvnormal, hipStream_t st);
+                           float* gvnormal, hipStream_t st, bool pos_cleared = false);
 hipError_t launch_mip_build(const Tex& t, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_adam(const adr_param* params, int n, int t, float lr, float b1, float b2,

@@ -86,6 +86,13 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
   for (; i < n; i += stride) p[i] = 0ull;
 }
 
+// Zero-fill of up to kFillRanges ranges of 8-byte words in one launch.
+__global__ void k_fill_multi(FillSet f) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int r = 0; r < f.n; ++r)
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.len[r]; i += stride) f.p[r][i] = 0ull;
+}
+
 __global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
                              bool det) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,6 +119,15 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
+
+hipError_t launch_fill_multi(const FillSet& f, hipStream_t st) {
+  int64_t most = 0;
+  for (int r = 0; r < f.n; ++r) most = f.len[r] > most ? f.len[r] : most;
+  if (most == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_multi, dim3(grid_for(most)), dim3(256), 0, st, f);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -140,14 +156,10 @@ hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st)
   if (blocks < 1) blocks = 1;
   unsigned long long* fn = s.det ? s.fix_n : nullptr;
   unsigned long long* ft = s.det ? s.fix_t : nullptr;
-  if (s.det) {
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, fn, n);
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, ft, n);
-  } else {
-    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.nacc, n);
-    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)blocks), dim3(256), 0, st, s.tacc, n);
-  }
-  hipError_t e = hipGetLastError();
+  FillSet f{};
+  f.add(s.det ? fn : reinterpret_cast<unsigned long long*>(s.nacc), n);
+  f.add(s.det ? ft : reinterpret_cast<unsigned long long*>(s.tacc), n);
+  hipError_t e = launch_fill_multi(f, st);
   if (e != hipSuccess) return e;
   if (m.n_tri > 0) {
     hipLaunchKernelGGL(k_face_accum, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.nacc, s.tacc, fn, ft);
@@ -211,7 +223,7 @@ __global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, unsigned lo
 }
 
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
-                           float* gvnormal, hipStream_t st) {
+                           float* gvnormal, hipStream_t st, bool pos_cleared) {
   hipLaunchKernelGGL(k_vertex_bwd, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m, v, s.dclip,
                      s.dattr, s.nacc, s.tacc, gpos, gvnormal);
   hipError_t e = hipGetLastError();
@@ -219,7 +231,7 @@ hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, fl
   // face terms summed in float64 (fixed point in deterministic mode), then
   // added once per vertex
   const int64_t n = 3 * (int64_t)m.n_pos;
-  if ((e = launch_fill_u64(s.fix_pos, n, st)) != hipSuccess) return e;
+  if (!pos_cleared && (e = launch_fill_u64(s.fix_pos, n, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, s.fix_pos, s.det);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fix_add_f32, dim3(grid_for(n)), dim3(256), 0, st, s.fix_pos, gpos, n, s.det);
