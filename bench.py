@@ -178,6 +178,7 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         g_disp = torch.zeros_like(disp.data)
         params += [(ts.base.pos, g_base), (disp.data, g_disp)]
     independent = False
+    maps = []    # mip-mapped maps: Adam fused with the chain's adjoint and rebuild
     for name in ("kd", "normal", "orm", "alpha"):
         if name not in w.optimize:
             grads[name] = None
@@ -189,13 +190,21 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
             params.append((tex.data, grads[name]))
         else:
             n0 = tex.size * tex.size
-            params.append((tex.data[:n0], grads[name][:n0]))
+            maps.append((tex, grads[name], torch.zeros_like(tex.data[:n0]), torch.zeros_like(tex.data[:n0])))
     adam = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
-    n_params = sum(p.numel() for p, _ in params)
+    n_params = sum(p.numel() for p, _ in params) + sum(m.numel() for _, _, m, _ in maps)
+    n_map_params = sum(m.numel() for _, _, m, _ in maps)
+    # map Adam: 32 B per level-0 float as Adam, plus per float of levels >= 1
+    # the gradient read and cleared and the rebuilt texel written
+    map_adam_bytes = sum(32 * m.numel() + 12 * (tex.data.numel() - m.numel()) for tex, _, m, _ in maps)
     dflag = adr.DETERMINISTIC if det else 0
     if w.msaa > 1:
         dflag |= adr.MSAA_4X4 if w.msaa == 4 else adr.MSAA_2X2
     lflag = dflag | (adr.INDEPENDENT_MIPS if independent else adr.FWD_BUILD_MIPS)
+    # in the loop the map Adam keeps the chains built: the forward rebuilds
+    # nothing and the backward leaves the chains' adjoint to it
+    sflag = lflag & ~adr.FWD_BUILD_MIPS
+    bflag = sflag | (adr.BWD_DEFER_MIP_ADJOINT if maps else 0)
     ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], flags=dflag & adr.DETERMINISTIC)
     ref_img = ref_out["image"] if k == 1 else adr.image_downsample(ctx, ref_out["image"], k)
     L = w.oit_layers
@@ -235,11 +244,11 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         if k > 1:
             adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
         if L:
-            adr.render_oit_fwd(ctx, lat_mesh, lat_mat, v, L, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
-            adr.render_oit_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
+            adr.render_oit_fwd(ctx, lat_mesh, lat_mat, v, L, ref=ref_img, loss=w.loss, flags=sflag, outputs=lat_out)
+            adr.render_oit_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=bflag)
         else:
-            adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=lflag, outputs=lat_out)
-            adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=lflag & ~adr.FWD_BUILD_MIPS)
+            adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=sflag, outputs=lat_out)
+            adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=bflag)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
         if rig is not None:
@@ -249,9 +258,12 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
             adr.laplacian(ctx, ring, base_pos, None, lams[t % n_steps], g_pos=g_lap)
         lr = w.lr * 10.0 ** (-0.0002 * t)
         adr.adam_step(ctx, adam, t + 1, lr)
+        if maps:
+            adr.adam_step_maps(ctx, maps, t + 1, lr)
 
     state = dict(ref_mesh=ref_mesh, lat_mesh=lat_mesh, lat_mat=lat_mat, lat_out=lat_out,
-                 ref_out=ref_out, n_params=n_params, views=views, adam=adam,
+                 ref_out=ref_out, n_params=n_params, n_map_params=n_map_params,
+                 map_adam_bytes=map_adam_bytes, views=views, adam=adam,
                  skin=None if rig is None else tuple(rig["w"].shape))
     return step, state
 
@@ -283,7 +295,9 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     px = B * H * W
     maps = optimised_maps(w)
     if stage == "adam":
-        return 32.0 * st["n_params"]                      # read p,g,m,v; write p,m,v,g
+        return 32.0 * (st["n_params"] - st.get("n_map_params", 0))   # read p,g,m,v; write p,m,v,g
+    if stage == "adam_maps":
+        return float(st["map_adam_bytes"]) if st.get("map_adam_bytes") else None
     L = w.oit_layers
     if L:
         # depth-peeled latent: one launch per layer; covered_latent counts the
@@ -627,6 +641,12 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": pmc_traffic(args.workload, dom), "avg_launch_ms": round(avg_ms, 4),
                 "bytes_per_launch": by}
+    # achieved GB/s of every stage with an algorithmic byte count
+    stage_gbs = {}
+    for k, (ms_k, cnt_k) in stages.items():
+        by_k = algorithmic_bytes(k, w, st, covered) if cnt_k else None
+        if by_k:
+            stage_gbs[k] = round(by_k / (ms_k / cnt_k * 1e-3) / 1e9, 1)
     cpu = None
     if not args.no_cpu_baseline:
         _log("oracle baseline")
@@ -644,6 +664,7 @@ def main():
                    "laplacian": bool(args.laplacian),
                    "final_loss": round(loss, 6)},
         "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
+        "stage_gbs": stage_gbs,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()

@@ -9,7 +9,8 @@
  *   adr_render_fwd(latent)     -> latent images I_theta(c, l), image loss
  *   adr_render_bwd(latent)     -> dL/dtheta for vertex positions and texels
  *   adr_adam_step(theta)       -> Adam update (Sec. 5.3)
- * and adr_job_submit / adr_job_poll run whole optimisations (the paper's
+ * (adr_adam_step_maps updates mip-mapped maps with their chains' adjoint
+ * and rebuild in the same launch), and adr_job_submit / adr_job_poll run whole optimisations (the paper's
  * statement of the problem: reference model, view/light distribution and
  * initial latent mesh and maps in, optimised mesh and maps out) inside the
  * library.
@@ -163,6 +164,10 @@ typedef struct adr_fwd_out {
                                     mip adjoint), so levels >= 1 of the gradients are outputs and
                                     Adam runs over whole chains; fwd rejects it together with
                                     ADR_FWD_BUILD_MIPS */
+#define ADR_BWD_DEFER_MIP_ADJOINT 64 /* bwd (plain and depth-peeled): leave the mip adjoint of the
+                                    map gradients to adr_adam_step_maps: each level of a gradient
+                                    chain keeps the gradient w.r.t. its own texels (levels >= 1
+                                    are then non-zero on exit).  Ignored by the forwards */
 #define ADR_DETERMINISTIC 4      /* fwd and bwd: results identical bit for bit from run to run.
                                     Vertex-side sums (frame, clip and attribute adjoints, face
                                     terms) use 64-bit fixed point (2^-40 resolution, |sum| below
@@ -265,6 +270,31 @@ typedef struct adr_param {
  * 1-based step.  params: host array of descriptors.  Zeroes each gradient. */
 adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params, int32_t t,
                          float lr, float beta1, float beta2, float eps, adr_stream stream);
+
+/* One optimised F32 map for adr_adam_step_maps: the variable is level 0 of
+ * `tex`; `grad` has the chain layout of `tex` and holds the per-level
+ * gradients left by a backward with ADR_BWD_DEFER_MIP_ADJOINT (or a folded
+ * level-0 gradient and zero levels >= 1); m and v: Adam moments of level 0,
+ * size^2 x channels floats each.  All device memory. */
+typedef struct adr_map_param {
+  adr_texture tex;
+  float* grad;                   /* whole chain set to zero on exit */
+  float* m;
+  float* v;
+} adr_map_param;
+
+/* Adam on the level-0 texels of mip-mapped maps (Sec. 5.3) fused with the
+ * chain's adjoint before it and its rebuild after it (the mip chain is the
+ * map's texture representation, Sec. 4.2): per map, the level-0 gradient
+ * plus the coarser levels' gradients pushed down by the adjoint of the 2x2
+ * box filter, the same Adam update as adr_adam_step, the gradient chain
+ * cleared, and levels 1.. of the map rebuilt from the new level 0.  Gives
+ * the same bits as adr_render_bwd's mip adjoint, adr_adam_step and a
+ * forward with ADR_FWD_BUILD_MIPS, in two launches per four maps; a
+ * forward after it needs no ADR_FWD_BUILD_MIPS.  maps: host array of n_maps
+ * descriptors (F32 maps only, ADR_E_INVALID otherwise); t: 1-based step. */
+adr_status adr_adam_step_maps(adr_ctx* ctx, const adr_map_param* maps, int32_t n_maps, int32_t t, float lr,
+                              float beta1, float beta2, float eps, adr_stream stream);
 
 /* Smooth vertex normals and UV tangents of a mesh (Sec. 5.1, "Tangent
  * space": normals from area-weighted face normals, tangents from the UV
@@ -387,8 +417,9 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
  * 9 adam, 10 mip build, 11 texel adjoint, 12 buffer clears and
  * conversions, 13 skinning, 14 skinning adjoint, 15 layer blending and its
- * adjoint (depth peeling).  ms and count: host arrays of ADR_N_STAGES. */
-#define ADR_N_STAGES 16
+ * adjoint (depth peeling), 16 map Adam with the chain's adjoint and
+ * rebuild (adr_adam_step_maps).  ms and count: host arrays of ADR_N_STAGES. */
+#define ADR_N_STAGES 17
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 
 /* Raster work split of a context (a tuning knob, results do not change):

@@ -28,6 +28,7 @@ TEX_F32, TEX_RGBA8 = 0, 1
 SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
 LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
 FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC, INDEPENDENT_MIPS, MSAA_2X2, MSAA_4X4 = 1, 2, 4, 8, 16, 32
+BWD_DEFER_MIP_ADJOINT = 64
 
 
 def msaa_factor(flags: int) -> int:
@@ -38,10 +39,12 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_adam_step", "adr_mip_build", "adr_mesh_adjacency", "adr_views_build",
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
-           "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster")
-N_STAGES = 16
+           "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster",
+           "adr_adam_step_maps")
+N_STAGES = 17
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
-          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend")
+          "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend",
+          "adam_maps")
 
 
 class AdrError(RuntimeError):
@@ -90,6 +93,10 @@ class Param_(C.Structure):
     _fields_ = [("param", P), ("grad", P), ("m", P), ("v", P), ("n", C.c_int64)]
 
 
+class MapParam_(C.Structure):
+    _fields_ = [("tex", Texture_), ("grad", P), ("m", P), ("v", P)]
+
+
 class Tess_(C.Structure):
     _fields_ = [("vidx", P), ("w", P), ("duv", P), ("n_vert", I32)]
 
@@ -135,6 +142,8 @@ _lib.adr_render_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POI
                                 C.POINTER(FwdOut_), P, C.POINTER(Grads_), I32, P]
 _lib.adr_adam_step.argtypes = [P, C.POINTER(Param_), I32, I32, C.c_float, C.c_float, C.c_float,
                                C.c_float, P]
+_lib.adr_adam_step_maps.argtypes = [P, C.POINTER(MapParam_), I32, I32, C.c_float, C.c_float, C.c_float,
+                                    C.c_float, P]
 _lib.adr_mip_build.argtypes = [P, C.POINTER(Texture_), P]
 _lib.adr_mesh_adjacency.argtypes = [P, I32, P]
 _lib.adr_views_build.argtypes = [P, I32, C.c_float, C.c_float, I32, I32, P, P]
@@ -392,6 +401,19 @@ def adam_step(ctx: Context, params: list, t: int, lr: float, beta1=0.9, beta2=0.
     for k, (p, g, m, v) in enumerate(params):
         arr[k] = Param_(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel())
     _check(_lib.adr_adam_step(ctx.h, arr, len(params), t, lr, beta1, beta2, eps, _stream(stream)))
+
+
+def adam_step_maps(ctx: Context, maps: list, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+                   stream=None):
+    """maps: list of (DeviceTexture, grad chain, m, v): Adam on each F32
+    map's level 0 with the chain's adjoint before it and its rebuild after
+    it (grad as left by a backward with BWD_DEFER_MIP_ADJOINT; zeroed)."""
+    arr = (MapParam_ * max(len(maps), 1))()
+    for k, (tex, g, m, v) in enumerate(maps):
+        n0 = tex.size * tex.size * tex.channels
+        assert g.numel() == tex.data.numel() and m.numel() == n0 and v.numel() == n0
+        arr[k] = MapParam_(tex.struct(), g.data_ptr(), m.data_ptr(), v.data_ptr())
+    _check(_lib.adr_adam_step_maps(ctx.h, arr, len(maps), t, lr, beta1, beta2, eps, _stream(stream)))
 
 
 class RenderLoss(torch.autograd.Function):

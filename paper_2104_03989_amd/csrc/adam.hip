@@ -19,15 +19,6 @@ struct AdamTable {
   int count;
 };
 
-__device__ __forceinline__ float adam1(float& p, float g, float& m, float& v, float b1, float b2,
-                                       float c1, float c2, float lr, float eps) {
-  m = b1 * m + (1.f - b1) * g;
-  v = b2 * v + (1.f - b2) * g * g;
-  float mh = m * c1, vh = v * c2;
-  p = p - lr * mh / (sqrtf(vh) + eps);
-  return p;
-}
-
 __global__ __launch_bounds__(256) void k_adam(AdamTable T, float b1, float b2, float c1, float c2,
                                               float lr, float eps) {
   int64_t total = T.start[T.count];

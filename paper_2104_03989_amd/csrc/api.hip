@@ -368,7 +368,7 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
   }
   if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
-                ADR_MSAA_4X4))
+                ADR_MSAA_4X4 | ADR_BWD_DEFER_MIP_ADJOINT))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   if ((flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
     return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
@@ -417,7 +417,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if (grads->kd && kd.fmt != ADR_TEX_F32) return fail(ADR_E_INVALID, "kd gradient needs an F32 kd map");
   if (grads->orm && mat->model != ADR_SHADE_GGX) return fail(ADR_E_INVALID, "orm gradient needs GGX");
   if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
-                ADR_MSAA_4X4))
+                ADR_MSAA_4X4 | ADR_BWD_DEFER_MIP_ADJOINT))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   if (!apply_msaa(flags, v) || v.W > 16384 || v.H > 16384)
     return fail(ADR_E_INVALID, "multisampling: one factor, at most 16384 samples per axis");
@@ -458,7 +458,8 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
         ms.t[ms.n] = *maps[k];
         ms.g[ms.n++] = gs[k];
       }
-    if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+    if (!(flags & (ADR_INDEPENDENT_MIPS | ADR_BWD_DEFER_MIP_ADJOINT)))
+      TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
   }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
     TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st, true), "mesh adjoint");
@@ -484,7 +485,7 @@ static adr_status check_oit(const adr_oit_out* o, int32_t flags, bool fwd) {
     return fail(ADR_E_INVALID, "out->vis, color, alpha, blend and comp are required");
   if (flags & (ADR_MSAA_2X2 | ADR_MSAA_4X4 | ADR_DETERMINISTIC))
     return fail(ADR_E_UNIMPL, "depth peeling with multisampling or the deterministic mode is not implemented");
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_INDEPENDENT_MIPS))
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_INDEPENDENT_MIPS | ADR_BWD_DEFER_MIP_ADJOINT))
     return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
   if (fwd && (flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
     return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
@@ -621,7 +622,8 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
         ms.t[ms.n] = *maps[k];
         ms.g[ms.n++] = gs[k];
       }
-    if (!(flags & ADR_INDEPENDENT_MIPS)) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+    if (!(flags & (ADR_INDEPENDENT_MIPS | ADR_BWD_DEFER_MIP_ADJOINT)))
+      TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
   }
   if (m.n_pos > 0 && (grads->pos || grads->vnormal))
     TIMED(8, launch_mesh_bwd(m, v, s, grads->pos, grads->vnormal, st, true), "mesh adjoint");
@@ -835,6 +837,34 @@ adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = (hipStream_t)stream;
   TIMED(9, launch_adam(params, n_params, t, lr, beta1, beta2, eps, st), "adam");
+  return ADR_OK;
+}
+
+adr_status adr_adam_step_maps(adr_ctx* ctx, const adr_map_param* maps, int32_t n_maps, int32_t t, float lr,
+                              float beta1, float beta2, float eps, adr_stream stream) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (n_maps < 0 || (n_maps > 0 && !maps)) return fail(ADR_E_INVALID, "bad maps");
+  if (t < 1) return fail(ADR_E_INVALID, "t must be >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(ADR_E_INVALID, "bad Adam hyper-parameters");
+  std::vector<Tex> ts((size_t)n_maps);
+  for (int k = 0; k < n_maps; ++k) {
+    adr_status r = check_tex(maps[k].tex, "map", false, ts[k]);
+    if (r != ADR_OK) return r;
+    if (!maps[k].grad || !maps[k].m || !maps[k].v) return fail(ADR_E_INVALID, "map %d: NULL grad, m or v", k);
+  }
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  for (int k0 = 0; k0 < n_maps; k0 += 4) {
+    AdamMapSet a{};
+    for (int k = k0; k < n_maps && k < k0 + 4; ++k) {
+      a.ms.t[a.ms.n] = ts[k];
+      a.ms.g[a.ms.n] = maps[k].grad;
+      a.m[a.ms.n] = maps[k].m;
+      a.v[a.ms.n++] = maps[k].v;
+    }
+    TIMED(16, launch_adam_maps(a, t, lr, beta1, beta2, eps, st), "map adam");
+  }
   return ADR_OK;
 }
 

@@ -260,4 +260,14 @@ __device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float 
   return r;
 }
 
+// One bias-corrected Adam update (Sec. 5.3); c1 = 1/(1-b1^t), c2 = 1/(1-b2^t).
+__device__ __forceinline__ float adam1(float& p, float g, float& m, float& v, float b1, float b2,
+                                       float c1, float c2, float lr, float eps) {
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  float mh = m * c1, vh = v * c2;
+  p = p - lr * mh / (sqrtf(vh) + eps);
+  return p;
+}
+
 }  // namespace adr

@@ -81,6 +81,14 @@ struct MipSet {
   int n;
 };
 
+// Optimised maps for the fused adjoint + Adam + rebuild of their chains: the
+// maps and gradient chains, and the Adam moments of each map's level 0.
+struct AdamMapSet {
+  MipSet ms;
+  float* m[4];
+  float* v[4];
+};
+
 struct TessD {
   const int* vidx;    // [Vt,3]
   const float* w;     // [Vt,3]
@@ -172,6 +180,7 @@ hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, fl
                            float* gvnormal, hipStream_t st, bool pos_cleared = false);
 hipError_t launch_mip_build(const Tex& t, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
+hipError_t launch_adam_maps(const AdamMapSet& a, int t, float lr, float b1, float b2, float eps, hipStream_t st);
 hipError_t launch_adam(const adr_param* params, int n, int t, float lr, float b1, float b2,
                        float eps, hipStream_t st);
 

@@ -415,19 +415,26 @@ adr_status enqueue_step(JobServer* s, Job& j) {
     s->slot_aa_cap[j.slot] = aa_bytes;
   }
   adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr, s->slot_aa[j.slot]};
-  r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, ADR_FWD_BUILD_MIPS, st);
+  // the map Adam rebuilds the latent chains after every step; the first
+  // forward builds them
+  r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, j.step == 0 ? ADR_FWD_BUILD_MIPS : 0,
+                     st);
   if (r != ADR_OK) return r;
   adr_grads g{(d.opt_mask & 1) ? j.g_pos : nullptr, nullptr, j.g_kd, j.g_nm, j.g_orm};
-  r = adr_render_bwd(ctx, &j.lat_mesh, &lm, &v, &lo, nullptr, &g, 0, st);
+  r = adr_render_bwd(ctx, &j.lat_mesh, &lm, &v, &lo, nullptr, &g, ADR_BWD_DEFER_MIP_ADJOINT, st);
   if (r != ADR_OK) return r;
-  adr_param prm[4];
-  int np = 0;
-  if (d.opt_mask & 1) prm[np++] = adr_param{(float*)j.lat_mesh.pos, j.g_pos, j.m[0], j.v[0], 3 * (int64_t)d.lat_n_pos};
-  if (j.g_kd) prm[np++] = adr_param{(float*)j.kd.data, j.g_kd, j.m[1], j.v[1], 3 * (int64_t)j.kd.size * j.kd.size};
-  if (j.g_nm) prm[np++] = adr_param{(float*)j.nm.data, j.g_nm, j.m[2], j.v[2], 3 * (int64_t)j.nm.size * j.nm.size};
-  if (j.g_orm) prm[np++] = adr_param{(float*)j.orm.data, j.g_orm, j.m[3], j.v[3], 3 * (int64_t)j.orm.size * j.orm.size};
   float lr = d.lr0 * powf(10.0f, -d.lr_decay_k * (float)j.step);
-  r = adr_adam_step(ctx, prm, np, j.step + 1, lr, 0.9f, 0.999f, 1e-8f, st);
+  if (d.opt_mask & 1) {
+    adr_param prm{(float*)j.lat_mesh.pos, j.g_pos, j.m[0], j.v[0], 3 * (int64_t)d.lat_n_pos};
+    r = adr_adam_step(ctx, &prm, 1, j.step + 1, lr, 0.9f, 0.999f, 1e-8f, st);
+    if (r != ADR_OK) return r;
+  }
+  adr_map_param mp[3];
+  int nm = 0;
+  if (j.g_kd) mp[nm++] = adr_map_param{j.kd.tex(), j.g_kd, j.m[1], j.v[1]};
+  if (j.g_nm) mp[nm++] = adr_map_param{j.nm.tex(), j.g_nm, j.m[2], j.v[2]};
+  if (j.g_orm) mp[nm++] = adr_map_param{j.orm.tex(), j.g_orm, j.m[3], j.v[3]};
+  r = adr_adam_step_maps(ctx, mp, nm, j.step + 1, lr, 0.9f, 0.999f, 1e-8f, st);
   if (r != ADR_OK) return r;
   if (hipMemcpyAsync(j.loss_host, j.loss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess) return ADR_E_HIP;
   if (hipEventRecord(j.done_ev, st) != hipSuccess) return ADR_E_HIP;

@@ -63,20 +63,11 @@ __device__ __forceinline__ bool vec_ok(const float* p, int w, int64_t gs) {
   return (w & 3) == 0 && (gs & 3) == 0 && ((uintptr_t)p & 15) == 0;
 }
 
-__global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
-  const Tex& t = ms.t[blockIdx.y];
-  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
-  const int L = min(t.levels - 1, ilog2i(T));
-  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
-  const int C = t.channels, tid = threadIdx.x;
-  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
-  __shared__ __align__(16) float base[kMipTile * kMipTile * 3];
-  __shared__ __align__(16) float lds[2][256 * 4];
-  float* d = (float*)t.data;
-  // level 0 of the tile into LDS, coalesced
-  float* g0 = d + ((int64_t)(by * T) * S + bx * T) * C;
-  tile_copy<true>(g0, (int64_t)S * C, base, T, T * C, vec_ok(g0, T * C, (int64_t)S * C));
-  __syncthreads();
+// Levels 1..L of a tile from its level 0 held in LDS (`base`, T rows of
+// T*C floats), each level kept in LDS for the next and written to the chain.
+__device__ __forceinline__ void tile_build_levels(const Tex& t, float* d, int by, int bx, int T, int L,
+                                                  const float* base, float (*lds)[256 * 4]) {
+  const int S = t.size, C = t.channels, tid = threadIdx.x;
   int s = T >> 1;
   if (tid < s * s) {
     int r = tid / s, c = tid - r * s;
@@ -111,9 +102,25 @@ __global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
   }
 }
 
-// Levels above the tile range, one block per map, level by level.
-__global__ __launch_bounds__(256) void k_mip_build_top(MipSet ms) {
-  const Tex& t = ms.t[blockIdx.x];
+__global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.y];
+  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
+  const int L = min(t.levels - 1, ilog2i(T));
+  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
+  const int C = t.channels;
+  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
+  __shared__ __align__(16) float base[kMipTile * kMipTile * 3];
+  __shared__ __align__(16) float lds[2][256 * 4];
+  float* d = (float*)t.data;
+  // level 0 of the tile into LDS, coalesced
+  float* g0 = d + ((int64_t)(by * T) * S + bx * T) * C;
+  tile_copy<true>(g0, (int64_t)S * C, base, T, T * C, vec_ok(g0, T * C, (int64_t)S * C));
+  __syncthreads();
+  tile_build_levels(t, d, by, bx, T, L, base, lds);
+}
+
+// Levels above the tile range of map k, level by level (one block).
+__device__ __forceinline__ void build_top(const Tex& t) {
   const int S = t.size, C = t.channels;
   float* d = (float*)t.data;
   for (int l = kMipTileLevels + 1; l < t.levels; ++l) {
@@ -132,37 +139,37 @@ __global__ __launch_bounds__(256) void k_mip_build_top(MipSet ms) {
   }
 }
 
-// Clears the gradients of the levels above the tile range once every tile
-// has folded them (one block per map).
-__global__ __launch_bounds__(256) void k_mip_clear_top(MipSet ms) {
-  const Tex& t = ms.t[blockIdx.x];
+// Clears the gradients of the levels above the tile range (one block).
+__device__ __forceinline__ void clear_top(const Tex& t, float* g) {
   if (t.levels - 1 <= kMipTileLevels) return;
-  float* g = ms.g[blockIdx.x];
   const int64_t a = (int64_t)t.off[kMipTileLevels + 1] * t.channels, b = (int64_t)t.off[t.levels] * t.channels;
   for (int64_t k = a + threadIdx.x; k < b; k += blockDim.x) g[k] = 0.f;
 }
+
+__global__ __launch_bounds__(256) void k_mip_build_top(MipSet ms) { build_top(ms.t[blockIdx.x]); }
+
+// Run once every tile has folded the levels above the tiles.
+__global__ __launch_bounds__(256) void k_mip_clear_top(MipSet ms) { clear_top(ms.t[blockIdx.x], ms.g[blockIdx.x]); }
 
 // Adjoint within a level-0 tile: the tile's levels 1..L (L <= 5) are read
 // into LDS in one round (and cleared), folded down (each level adds a
 // quarter of its parent's folded value), and a quarter of the folded level 1
 // is added to level 0.
 constexpr int kPyrFloats = (256 + 64 + 16 + 4 + 1) * 3;  // levels 1..5 of a 32^2 tile, 3 channels
+constexpr int kAncFloats = (kMaxLevels - 1 - kMipTileLevels) * 3;  // one texel per level above a tile
+constexpr int kPyrLds = kPyrFloats + kAncFloats;
 
-__global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
-  const Tex& t = ms.t[blockIdx.y];
-  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
-  const int L = min(t.levels - 1, ilog2i(T));
-  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
-  const int C = t.channels, tid = threadIdx.x;
-  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
-  float* g = ms.g[blockIdx.y];
-  __shared__ float pyr[kPyrFloats];
-  // level l of the tile (s_l = T >> l texels a side) sits at pyr + po[l]
+// Reads the tile's gradient levels 1..L into `pyr` (kPyrLds floats) in one
+// round (clearing them) together with the tile's ancestors above level L
+// (one texel per level), adds the ancestors folded from the top and folds
+// down, so that pyr holds the folded level 1 at offset 0 on return (after a
+// barrier).  Level l of the tile (T >> l texels a side) sits at pyr + po[l].
+__device__ __forceinline__ void tile_fold_grads(const Tex& t, float* g, int by, int bx, int T, int L, float* pyr) {
+  const int S = t.size, C = t.channels, tid = threadIdx.x;
   int po[kMipTileLevels + 2];
   po[1] = 0;
   for (int l = 1; l <= L; ++l) po[l + 1] = po[l] + (T >> l) * (T >> l) * C;
   const int total = po[L + 1];
-  // one round of independent loads (and clears) for all levels of the tile
   constexpr int kPer = (kPyrFloats + 255) / 256;
   float v[kPer];
   int64_t addr[kPer];
@@ -178,6 +185,14 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
       v[u] = g[addr[u]];
     }
   }
+  // ancestors (levels L+1.. of a full 32^2 tile), one per thread, cleared
+  // only once every tile has read them (a separate launch)
+  const int na = (T == kMipTile && L == kMipTileLevels) ? (t.levels - 1 - L) * C : 0;
+  float anc = 0.f;
+  if (tid < na) {
+    const int l = L + 1 + tid / C, ch = tid - (tid / C) * C, sl = S >> l, sh = l - L;
+    anc = g[((int64_t)t.off[l] + (int64_t)(by >> sh) * sl + (bx >> sh)) * C + ch];
+  }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     if (addr[u] >= 0) {
@@ -185,16 +200,14 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
       g[addr[u]] = 0.f;
     }
   }
+  if (tid < na) pyr[kPyrFloats + tid] = anc;
   // levels above the tile (a 32^2 tile's level 5 is one texel): its
   // ancestors' gradients folded from the top, f = g_l + f / 4, added to it
   // as a quarter of the folded parent (the same arithmetic as level by level)
   __syncthreads();
-  if (tid < C && T == kMipTile && L == kMipTileLevels && t.levels - 1 > L) {
+  if (tid < C && na > 0) {
     float f = 0.f;
-    for (int l = t.levels - 1; l > L; --l) {
-      const int sl = S >> l, sh = l - L;
-      f = g[((int64_t)t.off[l] + (int64_t)(by >> sh) * sl + (bx >> sh)) * C + tid] + 0.25f * f;
-    }
+    for (int l = t.levels - 1; l > L; --l) f = pyr[kPyrFloats + (l - L - 1) * C + tid] + 0.25f * f;
     pyr[po[L] + tid] += 0.25f * f;
   }
   // fold down: level l += a quarter of level l + 1
@@ -207,9 +220,23 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
     }
   }
   __syncthreads();
+}
+
+// Adjoint within a level-0 tile: the folded level 1 (tile_fold_grads), a
+// quarter of which is added to level 0.
+__global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
+  const Tex& t = ms.t[blockIdx.y];
+  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
+  const int L = min(t.levels - 1, ilog2i(T));
+  if ((int)blockIdx.x >= nt * nt || L <= 0) return;
+  const int C = t.channels, tid = threadIdx.x;
+  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
+  float* g = ms.g[blockIdx.y];
+  __shared__ float pyr[kPyrLds];
+  tile_fold_grads(t, g, by, bx, T, L, pyr);
   // level 0 += a quarter of the folded level 1, row by row with consecutive
   // threads on consecutive floats (float4 where aligned)
-  const float* par = pyr + po[1];
+  const float* par = pyr;
   const int sp = T >> 1, w = T * C;
   float* g0 = g + ((int64_t)(by * T) * S + bx * T) * C;
   const int64_t gs = (int64_t)S * C;
@@ -237,6 +264,103 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
       g0[r * gs + x] += 0.25f * par[((r >> 1) * sp + (c >> 1)) * C + ch];
     }
   }
+}
+
+// Adam on level 0 of optimised maps fused with the chain's adjoint before it
+// and the chain's rebuild after it (one block per level-0 tile): the tile's
+// level-0 gradient is completed by the folded coarser levels exactly as
+// k_mip_adjoint_tiles does, Adam updates the tile's texels, the gradient
+// chain of the tile is cleared, and levels 1..5 of the tile are rebuilt from
+// the new level 0 exactly as k_mip_build_tiles does.  The levels above the
+// tiles follow in k_adam_maps_top.  The same bits as the adjoint, Adam and
+// build launched one after another.
+constexpr int kTileF4 = kMipTile * kMipTile * 3 / 4 / 256;  // float4 per thread of a 32^2 x 3 tile
+
+__global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1, float b2, float c1, float c2,
+                                                         float lr, float eps) {
+  const Tex& t = a.ms.t[blockIdx.y];
+  const int S = t.size, T = S < kMipTile ? S : kMipTile, nt = S / T;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int L = min(t.levels - 1, ilog2i(T));
+  const int C = t.channels, tid = threadIdx.x;
+  const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
+  __shared__ float pyr[kPyrLds];
+  __shared__ __align__(16) float base[kMipTile * kMipTile * 3];
+  __shared__ __align__(16) float lds[2][256 * 4];
+  const int64_t o0 = ((int64_t)(by * T) * S + bx * T) * C, gs = (int64_t)S * C;
+  float* d = (float*)t.data;
+  float* g = a.ms.g[blockIdx.y];
+  float *P = d + o0, *G = g + o0, *M = a.m[blockIdx.y] + o0, *V = a.v[blockIdx.y] + o0;
+  const int sp = T >> 1, w = T * C;
+  const bool vec = vec_ok(P, w, gs) && vec_ok(G, w, gs) && vec_ok(M, w, gs) && vec_ok(V, w, gs);
+  const int w4 = w >> 2, n4 = vec ? T * w4 : 0;
+  // the tile's level-0 loads are issued before the fold
+  float4 p4[kTileF4], g4[kTileF4], m4[kTileF4], v4[kTileF4];
+#pragma unroll
+  for (int u = 0; u < kTileF4; ++u) {
+    const int e = tid + 256 * u;
+    if (e < n4) {
+      const int r = e / w4, x4 = e - r * w4;
+      const int64_t q = r * gs + 4 * x4;
+      p4[u] = *reinterpret_cast<const float4*>(P + q);
+      g4[u] = *reinterpret_cast<const float4*>(G + q);
+      m4[u] = *reinterpret_cast<const float4*>(M + q);
+      v4[u] = *reinterpret_cast<const float4*>(V + q);
+    }
+  }
+  if (L > 0) tile_fold_grads(t, g, by, bx, T, L, pyr);
+  // level 0: g += a quarter of the folded level 1, then Adam; the new
+  // texels also go to LDS for the rebuild
+#pragma unroll
+  for (int u = 0; u < kTileF4; ++u) {
+    const int e = tid + 256 * u;
+    if (e < n4) {
+      const int r = e / w4, x4 = e - r * w4;
+      const int64_t q = r * gs + 4 * x4;
+      float gg[4] = {g4[u].x, g4[u].y, g4[u].z, g4[u].w};
+      if (L > 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int x = 4 * x4 + j, c = x / C, ch = x - c * C;
+          gg[j] += 0.25f * pyr[((r >> 1) * sp + (c >> 1)) * C + ch];
+        }
+      }
+      adam1(p4[u].x, gg[0], m4[u].x, v4[u].x, b1, b2, c1, c2, lr, eps);
+      adam1(p4[u].y, gg[1], m4[u].y, v4[u].y, b1, b2, c1, c2, lr, eps);
+      adam1(p4[u].z, gg[2], m4[u].z, v4[u].z, b1, b2, c1, c2, lr, eps);
+      adam1(p4[u].w, gg[3], m4[u].w, v4[u].w, b1, b2, c1, c2, lr, eps);
+      *reinterpret_cast<float4*>(P + q) = p4[u];
+      *reinterpret_cast<float4*>(M + q) = m4[u];
+      *reinterpret_cast<float4*>(V + q) = v4[u];
+      *reinterpret_cast<float4*>(G + q) = make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(base + r * w + 4 * x4) = p4[u];
+    }
+  }
+  if (!vec) {
+    for (int e = tid; e < T * w; e += blockDim.x) {
+      const int r = e / w, x = e - r * w, c = x / C, ch = x - c * C;
+      const int64_t q = r * gs + x;
+      float gg = G[q];
+      if (L > 0) gg += 0.25f * pyr[((r >> 1) * sp + (c >> 1)) * C + ch];
+      float p = P[q], m = M[q], v = V[q];
+      adam1(p, gg, m, v, b1, b2, c1, c2, lr, eps);
+      P[q] = p;
+      M[q] = m;
+      V[q] = v;
+      G[q] = 0.f;
+      base[e] = p;
+    }
+  }
+  if (L <= 0) return;
+  __syncthreads();
+  tile_build_levels(t, d, by, bx, T, L, base, lds);
+}
+
+// After k_adam_maps_tiles: clears the gradient levels above the tiles and
+// rebuilds the data levels above the tiles (one block per map).
+__global__ __launch_bounds__(256) void k_adam_maps_top(MipSet ms) {
+  clear_top(ms.t[blockIdx.x], ms.g[blockIdx.x]);
+  build_top(ms.t[blockIdx.x]);
 }
 
 static int max_tiles(const MipSet& ms) {
@@ -271,6 +395,17 @@ hipError_t launch_mip_adjoint_set(const MipSet& ms, hipStream_t st) {
   if (e != hipSuccess || !has_top(ms)) return e;
   // the levels above the tiles, read by every tile, are cleared afterwards
   hipLaunchKernelGGL(k_mip_clear_top, dim3(ms.n), dim3(256), 0, st, ms);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_maps(const AdamMapSet& a, int t, float lr, float b1, float b2, float eps, hipStream_t st) {
+  if (a.ms.n == 0) return hipSuccess;
+  const double c1 = 1.0 / (1.0 - pow((double)b1, t)), c2 = 1.0 / (1.0 - pow((double)b2, t));
+  hipLaunchKernelGGL(k_adam_maps_tiles, dim3(max_tiles(a.ms), a.ms.n), dim3(256), 0, st, a, b1, b2, (float)c1,
+                     (float)c2, lr, eps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !has_top(a.ms)) return e;
+  hipLaunchKernelGGL(k_adam_maps_top, dim3(a.ms.n), dim3(256), 0, st, a.ms);
   return hipGetLastError();
 }
 

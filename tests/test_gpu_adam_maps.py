@@ -1,0 +1,187 @@
+"""Adam on mip-mapped maps fused with the chain's adjoint and rebuild
+(adr_adam_step_maps): against the oracle (the chain's adjoint taken by
+autograd through its box-filter pyramid, Adam, the rebuilt chain) on chains
+of several shapes, and bit for bit against the unfused sequence (mip
+adjoint in the backward, adr_adam_step, mip build in the next forward) over
+a few steps of a deterministic-mode loop."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import loop as OL
+from oracle import render as R
+from paper_2104_03989_amd import synth
+from tests.gpu_common import GpuScene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2104_03989_amd import adr
+    c = adr.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle(p0, gchain, m, v, levels, t, lr):
+    """Folded level-0 gradient d/dp0 sum_l <g_l, chain_l(p0)> and one Adam
+    step, in float64."""
+    S, C = p0.shape[0], p0.shape[2]
+    x = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    chain = R.mip_chain_f32(x, levels)
+    obj = sum((lv * torch.tensor(gl, dtype=torch.float64)).sum() for lv, gl in zip(chain, gchain))
+    (g0,) = torch.autograd.grad(obj, [x])
+    pn, mn, vn = R.adam(p0, g0.numpy(), m, v, t, lr)
+    return pn, mn, vn
+
+
+def _split(flat, S, C, levels):
+    out, o = [], 0
+    for l in range(levels):
+        s = S >> l
+        out.append(flat[o:o + s * s].reshape(s, s, C))
+        o += s * s
+    return out
+
+
+# (size, channels, levels): full chains with levels above the 32^2 tiles, a
+# chain inside one tile, a truncated chain, one level, a 1x1 map, and tiles
+# whose rows are not float4 multiples (the scalar path)
+CASES = [(2048, 3, 12), (4096, 1, 13), (64, 1, 7), (16, 3, 5), (256, 3, 4), (128, 3, 1), (1, 3, 1), (2, 3, 2),
+         (4, 1, 3)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{s}x{c}x{l}" for s, c, l in CASES])
+def test_adam_maps_matches_oracle(ctx, case):
+    from paper_2104_03989_amd import adr
+    S, C, levels = case
+    _say("adam maps", case)
+    g = np.random.default_rng(S * 7 + C * 3 + levels)
+    p0 = g.normal(size=(S, S, C)).astype(np.float32)
+    tex = adr.DeviceTexture(p0, "f32", levels=levels, ctx=ctx)
+    n = tex.data.shape[0]
+    # per-level gradients as a deferred backward leaves them, scaled per level
+    gflat = np.concatenate([g.normal(size=((S >> l) ** 2, C)) * (0.5 ** l) for l in range(levels)]).astype(np.float32)
+    m = (g.normal(size=(S * S, C)) * 0.1).astype(np.float32)
+    v = (np.abs(g.normal(size=(S * S, C))) * 0.01).astype(np.float32)
+    gd = torch.from_numpy(gflat).cuda()
+    md, vd = torch.from_numpy(m).cuda(), torch.from_numpy(v).cuda()
+    t, lr = 5, 1e-2
+    adr.adam_step_maps(ctx, [(tex, gd, md, vd)], t, lr)
+    torch.cuda.synchronize()
+    pn, mn, vn = _oracle(p0.astype(np.float64), _split(gflat.astype(np.float64), S, C, levels),
+                                  m.reshape(S, S, C).astype(np.float64), v.reshape(S, S, C).astype(np.float64),
+                                  levels, t, lr)
+    got = _split(tex.data.cpu().numpy().astype(np.float64), S, C, levels)
+    mg = md.cpu().numpy().reshape(S, S, C).astype(np.float64)
+    vg = vd.cpu().numpy().reshape(S, S, C).astype(np.float64)
+    em, ev = np.abs(mg - mn).max(), np.abs(vg - vn).max()
+    # the moments against the oracle's; the step against the oracle's step
+    # taken from the kernel's own float32 moments (where the second moment
+    # is tiny the step amplifies their rounding, which says nothing of the
+    # step's arithmetic): a few units in the last place of the texel and of
+    # the step
+    # (the hyper-parameters cross the ABI as float32: beta2 = 0.999 is
+    # 0.99900001 there, which moves the bias correction by 1e-5)
+    b1, b2, lr32, eps32 = (float(np.float32(x)) for x in (0.9, 0.999, lr, 1e-8))
+    step = lr32 * (mg / (1 - b1 ** t)) / (np.sqrt(vg / (1 - b2 ** t)) + eps32)
+    pe = p0.astype(np.float64) - step
+    ulp = lambda x: np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
+    tol0 = 4 * ulp(np.abs(p0) + np.abs(pe)) + 4 * ulp(step)
+    err0 = np.abs(got[0] - pe)
+    _say(f"  level 0 {err0.max():.3g} ({(err0 / tol0).max():.2f} of tol), vs oracle {np.abs(got[0] - pn).max():.3g};"
+         f"  m {em:.3g}  v {ev:.3g}")
+    if not np.all(err0 <= tol0):
+        i = np.unravel_index(np.argmax(err0 / tol0), err0.shape)
+        _say("  worst", i, "p0", repr(p0[i]), "m0", repr(m.reshape(S, S, C)[i]), "v0", repr(v.reshape(S, S, C)[i]),
+             "m'", repr(np.float32(mg[i])), "v'", repr(np.float32(vg[i])), "got", repr(np.float32(got[0][i])),
+             "expected", pe[i], "oracle", pn[i], "step", step[i])
+    assert np.all(err0 <= tol0) and em < 1e-6 and ev < 1e-6
+    # the rebuilt levels: box averages of the kernel's new level 0 (float32
+    # rounding of the pairwise sums, at most a few units of the largest
+    # level-0 magnitude per level)
+    chain = [c.numpy() for c in R.mip_chain_f32(torch.tensor(got[0]), levels)]
+    u0 = float(np.spacing(np.float32(2 * np.abs(got[0]).max())))
+    for l in range(1, levels):
+        el = np.abs(got[l] - chain[l]).max()
+        assert el <= 2 * l * u0, (l, el)
+    assert float(gd.abs().max()) == 0.0
+    assert n == sum((S >> l) ** 2 for l in range(levels))
+
+
+def test_adam_maps_rejects_bad_arguments(ctx):
+    from paper_2104_03989_amd import adr
+    tex = adr.DeviceTexture(np.zeros((8, 8, 4), np.uint8), "rgba8")
+    z = torch.zeros(64 * 4, device="cuda")
+    with pytest.raises(adr.AdrError):
+        adr._check(adr._lib.adr_adam_step_maps(ctx.h, (adr.MapParam_ * 1)(adr.MapParam_(tex.struct(), z.data_ptr(),
+                                                                                        z.data_ptr(), z.data_ptr())),
+                                               1, 1, 1e-3, 0.9, 0.999, 1e-8, None))
+    f = adr.DeviceTexture(np.zeros((8, 8, 3), np.float32), "f32")
+    with pytest.raises(adr.AdrError):
+        adr._check(adr._lib.adr_adam_step_maps(ctx.h, (adr.MapParam_ * 1)(adr.MapParam_(f.struct(), None, None, None)),
+                                               1, 1, 1e-3, 0.9, 0.999, 1e-8, None))
+    with pytest.raises(adr.AdrError):
+        adr._check(adr._lib.adr_adam_step_maps(ctx.h, None, 1, 1, 1e-3, 0.9, 0.999, 1e-8, None))
+    adr._check(adr._lib.adr_adam_step_maps(ctx.h, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None))
+
+
+def _loop(ctx, w, fused, steps):
+    """Deterministic-mode steps of the render loop; returns the final maps
+    (whole chains), positions and Adam moments."""
+    from paper_2104_03989_amd import adr
+    gs = GpuScene(w, ctx)
+    ref = gs.render("reference", flags=adr.DETERMINISTIC)["image"]
+    mat, mesh = gs.lat_mat, gs.lat_mesh
+    grads = {"pos": torch.zeros_like(mesh.pos), "orm": None}
+    maps = []
+    for name in ("kd", "normal"):
+        tex = getattr(mat, name)
+        grads[name] = tex.grad_buffer()
+        n0 = tex.size * tex.size
+        maps.append((tex, grads[name], torch.zeros_like(tex.data[:n0]), torch.zeros_like(tex.data[:n0])))
+    pos_state = (mesh.pos, grads["pos"], torch.zeros_like(mesh.pos), torch.zeros_like(mesh.pos))
+    det = adr.DETERMINISTIC
+    out = None
+    for t in range(steps):
+        fflags = det | (0 if fused else adr.FWD_BUILD_MIPS)
+        out = adr.render_fwd(ctx, mesh, mat, gs.views, ref=ref, loss=w.loss, flags=fflags, want_image=False,
+                             outputs=out)
+        adr.render_bwd(ctx, mesh, mat, gs.views, out, grads, flags=det | (adr.BWD_DEFER_MIP_ADJOINT if fused else 0))
+        lr = w.lr * 10.0 ** (-0.0002 * t)
+        if fused:
+            adr.adam_step(ctx, [pos_state], t + 1, lr)
+            adr.adam_step_maps(ctx, maps, t + 1, lr)
+        else:
+            adr.adam_step(ctx, [pos_state] + [(tex.data[:m.shape[0]], g[:m.shape[0]], m, v) for tex, g, m, v in maps],
+                          t + 1, lr)
+    if not fused:
+        for tex, _, _, _ in maps:
+            adr.mip_build(ctx, tex)
+    torch.cuda.synchronize()
+    res = {"pos": mesh.pos.cpu().numpy(), "loss": out["loss"].cpu().numpy()}
+    for (tex, g, m, v), name in zip(maps, ("kd", "normal")):
+        res[name] = tex.data.cpu().numpy()
+        res[name + "_m"], res[name + "_v"] = m.cpu().numpy(), v.cpu().numpy()
+        res[name + "_g"] = float(g.abs().max())
+    return res
+
+
+def test_fused_loop_is_bit_identical_to_unfused(ctx):
+    _say("fused vs unfused loop")
+    w = synth.scaled(synth.workload_paper_loop(map_size=256, ref_nu=40, lat_nu=10), views=2, res=128)
+    a = _loop(ctx, w, False, 4)
+    b = _loop(ctx, w, True, 4)
+    for k in a:
+        if k.endswith("_g"):
+            assert a[k] == 0.0 and b[k] == 0.0, k
+        else:
+            assert np.array_equal(np.asarray(a[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
