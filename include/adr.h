@@ -421,6 +421,12 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * rebuild (adr_adam_step_maps).  ms and count: host arrays of ADR_N_STAGES. */
 #define ADR_N_STAGES 17
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
+/* As adr_ctx_profile for the stages whose bits (1 << stage) are set in
+ * stage_mask, the others untimed (0 disables).  Each bracketed stage stalls
+ * its stream for a few microseconds at the two event records, so timing one
+ * stage inside a timed loop costs far less than timing all of them.
+ * ADR_E_INVALID for bits at or above ADR_N_STAGES. */
+adr_status adr_ctx_profile_stages(adr_ctx* ctx, uint32_t stage_mask);
 
 /* Raster work split of a context (a tuning knob, results do not change):
  * a triangle whose pixel bounding box holds at most tiny_bbox pixel centres

@@ -40,7 +40,7 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
            "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster",
-           "adr_adam_step_maps")
+           "adr_adam_step_maps", "adr_ctx_profile_stages")
 N_STAGES = 17
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend",
@@ -150,6 +150,7 @@ _lib.adr_views_build.argtypes = [P, I32, C.c_float, C.c_float, I32, I32, P, P]
 _lib.adr_job_submit.argtypes = [P, C.POINTER(JobDesc_), C.POINTER(C.c_uint64)]
 _lib.adr_job_poll.argtypes = [P, C.c_uint64, C.POINTER(JobStatus_), C.POINTER(JobResult_)]
 _lib.adr_ctx_profile.argtypes = [P, I32]
+_lib.adr_ctx_profile_stages.argtypes = [P, C.c_uint32]
 _lib.adr_ctx_set_raster.argtypes = [P, I32, I32]
 _lib.adr_ctx_profile_read.argtypes = [P, P, P]
 _lib.adr_mesh_one_ring.argtypes = [P, I32, I32, P, P, P]
@@ -222,6 +223,13 @@ class Context:
 
     def profile(self, enable: bool = True):
         _check(_lib.adr_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_stages(self, names):
+        """Time only the named stages (see adr_ctx_profile_stages)."""
+        mask = 0
+        for n in names:
+            mask |= 1 << STAGES.index(n)
+        _check(_lib.adr_ctx_profile_stages(self.h, mask))
 
     def profile_read(self) -> dict:
         """{stage: (total ms, launches)} since the last read."""

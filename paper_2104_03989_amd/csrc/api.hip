@@ -68,7 +68,7 @@ struct adr_ctx {
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
-  bool prof = false;
+  uint32_t prof = 0;  // stages bracketed with events (bit per stage)
   int tiny_bbox = kTinyBBox, med_bbox = kMedBBox;  // raster work split
   std::vector<Span> spans;
   std::vector<hipEvent_t> pool;
@@ -82,8 +82,10 @@ hipEvent_t take_event(adr_ctx* c) {
     c->pool.pop_back();
     return e;
   }
+  // timing events without the system-scope release: a plain event record
+  // writes back the L2 and stalls the stream for ~10 us at every stage
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -94,7 +96,7 @@ struct StageTimer {
   hipStream_t st;
   hipEvent_t a = nullptr;
   StageTimer(adr_ctx* c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
-    if (c->prof && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
+    if (((c->prof >> stage) & 1u) && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
   }
   ~StageTimer() {
     if (!a) return;
@@ -798,7 +800,14 @@ adr_status adr_ctx_set_raster(adr_ctx* ctx, int32_t tiny_bbox, int32_t med_bbox)
 
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable) {
   if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
-  ctx->prof = enable != 0;
+  ctx->prof = enable != 0 ? (1u << ADR_N_STAGES) - 1u : 0u;
+  return ADR_OK;
+}
+
+adr_status adr_ctx_profile_stages(adr_ctx* ctx, uint32_t stage_mask) {
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  if (stage_mask >> ADR_N_STAGES) return fail(ADR_E_INVALID, "stage mask 0x%x names no stage", stage_mask);
+  ctx->prof = stage_mask;
   return ADR_OK;
 }
 
