@@ -133,11 +133,19 @@ __device__ __forceinline__ bool eval_pair(const AAArgs& a, int b, int i, int j, 
 
 __device__ __forceinline__ f3 ldc(const float* c, int64_t o) { return mk(c[3 * o], c[3 * o + 1], c[3 * o + 2]); }
 
-__device__ __forceinline__ float srgb(float x) {
-  return x <= 0.0031308f ? 12.92f * x : 1.055f * powf(x, 1.0f / 2.4f) - 0.055f;
+// x^(1/2.4) for the power branch of the sRGB curve (x > 0.0031308, a normal
+// float) through the hardware base-2 logarithm and exponential (each within
+// about one unit in the last place; the general powf costs several times
+// more and is evaluated six times per pixel by the tone-mapped loss).
+__device__ __forceinline__ float pow_inv24(float x) {
+  return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 2.4f));
 }
+__device__ __forceinline__ float srgb(float x) {
+  return x <= 0.0031308f ? 12.92f * x : 1.055f * pow_inv24(x) - 0.055f;
+}
+// d srgb / dx = (1.055 / 2.4) x^(1/2.4 - 1) = (1.055 / 2.4) x^(1/2.4) / x.
 __device__ __forceinline__ float srgb_d(float x) {
-  return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * powf(x, 1.0f / 2.4f - 1.0f);
+  return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * pow_inv24(x) / x;
 }
 // T(x) = sign(x) Gamma(log(1 + |x|)): the paper's tone map for x >= 0,
 // extended as an odd function to the negative radiance that freely optimised
