@@ -377,7 +377,7 @@ __device__ __forceinline__ void tex_bwd(const Tex& t, float* gtex, const PixelGe
 // added to HBM once each.  A footprint larger than the window (a UV seam,
 // very oblique sampling) falls back to direct atomics.
 
-constexpr int kWinTex = 1024;  // per wave: e.g. 18 x 18 texels x 3 channels
+constexpr int kWinTex = 1024;  // window entries per wave: e.g. 18 x 18 texels x 3 channels
 
 struct TexScatter {
   float u, v;
@@ -464,9 +464,25 @@ __device__ __forceinline__ void merge_step(bool recv, bool send, int& key, float
 }
 
 // Accumulates the contributions of the selected lanes (sel) at one level
-// into an LDS window over their footprint (at most kWinTex floats), then adds
-// the window's nonzero texel-channels to HBM.  Converged code.
-__device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gtex, float* win, bool sel,
+// into an LDS window over their footprint (at most kWinTex entries), then
+// adds the window's nonzero texel-channels to HBM.  Converged code.
+//
+// The window sums in 64-bit fixed point: the pass scales every contribution
+// by 2^k, k chosen from the largest magnitude in the wave so that each
+// scaled value stays below 2^29, rounds it to an integer and adds it with an
+// integer LDS atomic (on this chip a float LDS atomic costs some thirty
+// times an integer one).  A window texel-channel is converted back to float
+// once: each contribution carries an error of at most 2^-29 of the wave's
+// largest one, and the sum does not depend on the lanes' order.  A pass with
+// a non-finite contribution adds markers instead and writes NaN to the
+// texels it touches.
+using WinT = unsigned long long;
+
+__device__ __forceinline__ WinT fix_of(float x, int k, bool finite) {
+  return finite ? (WinT)(long long)(int)rintf(ldexpf(x, k)) : 1ull;
+}
+
+__device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gtex, WinT* win, bool sel,
                                             const Foot& q, float wl, const float (&gsv)[3], int off) {
   const int BIG = 1 << 20;
   const int lane = threadIdx.x & 63;
@@ -475,7 +491,7 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   const int cmin = wave_min_i(sel ? q.c0 : BIG), cmax = wave_max_i(sel ? q.c0 + 1 : -1);
   const int ww = cmax - cmin + 1;
   const int n = (rmax - rmin + 1) * ww * C;
-  for (int k = lane; k < n; k += 64) win[k] = 0.f;
+  for (int k = lane; k < n; k += 64) win[k] = 0ull;
   // The per-lane contributions (4 corners x 3 channels) of lanes that
   // share a bilinear cell are first merged across lanes with DPP moves
   // (pairs, quads and eights along x, then pairs of pixel rows), since
@@ -494,8 +510,17 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   merge_step<0x4E, 0x4E>((lane & 3) == 0, (lane & 3) == 2, key, v);    // quad_perm [2,3,0,1]
   merge_step<0x104, 0x114>((lane & 7) == 0, (lane & 7) == 4, key, v);  // row_shl:4 / row_shr:4
   merge_step<0x108, 0x118>((lane & 8) == 0, (lane & 8) != 0, key, v);  // row_shl:8 / row_shr:8
+  // the pass's scale from the largest magnitude still to be added (the bits
+  // of non-negative floats order as the floats); amax < 2^e
+  float amax = 0.f;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) amax = fmaxf(amax, key >= 0 ? fabsf(v[i]) : 0.f);
+  const int mb = wave_max_i(__float_as_int(amax));
+  const bool finite = mb < 0x7F800000;
+  const int e = ((mb >> 23) & 0xFF) - 126;
+  const int ks = finite ? 29 - e : 0;
   wave_sync();
-  if (key >= 0) {
+  if (key >= 0 && mb != 0) {
     // Lanes still sharing a cell update its texels and channels in a
     // rotated order, so that one instruction rarely hits one address
     // from several lanes.
@@ -514,21 +539,24 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
         for (int ch = 0; ch < 3; ++ch) {
           int c = ch + rot;
           c = c >= 3 ? c - 3 : c;
-          atomicAdd(win + cell + c, c == 0 ? v0 : (c == 1 ? v1 : v2));
+          atomicAdd(win + cell + c, fix_of(c == 0 ? v0 : (c == 1 ? v1 : v2), ks, finite));
         }
       } else {
-        atomicAdd(win + cell, v0);
+        atomicAdd(win + cell, fix_of(v0, ks, finite));
       }
     }
   }
   wave_sync();
-  for (int k = lane; k < n; k += 64) {
-    float val = win[k];
-    if (val != 0.f) {
-      int texel = k / C, ch = k - texel * C;
-      int r = rmin + texel / ww, c = cmin + texel % ww;
-      if (c >= q.s) c -= q.s;
-      atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
+  if (mb != 0) {
+    for (int k = lane; k < n; k += 64) {
+      const long long sum = (long long)win[k];
+      if (sum != 0) {
+        const float val = finite ? ldexpf((float)sum, -ks) : __int_as_float(0x7FC00000);
+        int texel = k / C, ch = k - texel * C;
+        int r = rmin + texel / ww, c = cmin + texel % ww;
+        if (c >= q.s) c -= q.s;
+        atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
+      }
     }
   }
   wave_sync();
@@ -541,7 +569,7 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
 // the lanes are taken in groups: the first pending lane and every pending
 // lane whose cell lies in a side x side box around it share a pass.
 __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool act, const TexScatter& ts,
-                                 float* win) {
+                                 WinT* win) {
   const int BIG = 1 << 20;
   const int lane = threadIdx.x & 63;
   const int C = t.channels;
@@ -830,14 +858,14 @@ struct TexBwdArgs {
 };
 
 __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
-  __shared__ float win_all[4][kWinTex];
+  __shared__ WinT win_all[4][kWinTex];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
   const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
   float4 r0 = p.ok ? a.rec[o] : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
   const uint32_t lv = __float_as_uint(r0.z);
-  float* win = win_all[threadIdx.x >> 6];
+  WinT* win = win_all[threadIdx.x >> 6];
   for (int k = 0; k < a.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
