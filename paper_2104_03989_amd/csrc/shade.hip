@@ -435,34 +435,6 @@ __device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
   return q;
 }
 
-// DPP lane moves (converged code): lane i receives x from the lane that the
-// control word CTRL names; a lane without a source keeps its own value.
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
-}
-
-// One merge step between paired lanes: a receiver (recv) adds the values of
-// its partner (reached with TO_RECV) when both hold the same cell key, and
-// that partner (send, reaching the receiver with TO_SEND) then drops out
-// (key -1).  Keys of lanes without a contribution are -1.
-template <int TO_RECV, int TO_SEND>
-__device__ __forceinline__ void merge_step(bool recv, bool send, int& key, float (&v)[12]) {
-  const int pk_r = dpp_i<TO_RECV>(key);
-  const int pk_s = dpp_i<TO_SEND>(key);
-  const bool take = recv && key >= 0 && pk_r == key;
-#pragma unroll
-  for (int i = 0; i < 12; ++i) {
-    const float pv = dpp_f<TO_RECV>(v[i]);
-    v[i] += take ? pv : 0.f;
-  }
-  if (send && key >= 0 && pk_s == key) key = -1;
-}
-
 // Accumulates the contributions of the selected lanes (sel) at one level
 // into an LDS window over their footprint (at most kWinTex entries), then
 // adds the window's nonzero texel-channels to HBM.  Converged code.
@@ -492,12 +464,10 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   const int ww = cmax - cmin + 1;
   const int n = (rmax - rmin + 1) * ww * C;
   for (int k = lane; k < n; k += 64) win[k] = 0ull;
-  // The per-lane contributions (4 corners x 3 channels) of lanes that
-  // share a bilinear cell are first merged across lanes with DPP moves
-  // (pairs, quads and eights along x, then pairs of pixel rows), since
-  // the cost of the LDS atomics grows with the number of active lanes.
+  // Per lane 4 corners x 3 channels.  (Merging lanes that share a bilinear
+  // cell with DPP moves before the atomics paid off with float LDS atomics;
+  // with integer ones it costs more than it saves.)
   const float w[4] = {(1.f - q.fx) * (1.f - q.fy), q.fx * (1.f - q.fy), (1.f - q.fx) * q.fy, q.fx * q.fy};
-  int key = sel ? (((q.r0 << 1) | (q.r1 != q.r0 ? 1 : 0)) << 15) | q.c0 : -1;
   float v[12];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -506,24 +476,20 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
     v[3 * k + 1] = wk * gsv[1];
     v[3 * k + 2] = wk * gsv[2];
   }
-  merge_step<0xB1, 0xB1>((lane & 1) == 0, (lane & 1) == 1, key, v);    // quad_perm [1,0,3,2]
-  merge_step<0x4E, 0x4E>((lane & 3) == 0, (lane & 3) == 2, key, v);    // quad_perm [2,3,0,1]
-  merge_step<0x104, 0x114>((lane & 7) == 0, (lane & 7) == 4, key, v);  // row_shl:4 / row_shr:4
-  merge_step<0x108, 0x118>((lane & 8) == 0, (lane & 8) != 0, key, v);  // row_shl:8 / row_shr:8
   // the pass's scale from the largest magnitude still to be added (the bits
   // of non-negative floats order as the floats); amax < 2^e
   float amax = 0.f;
 #pragma unroll
-  for (int i = 0; i < 12; ++i) amax = fmaxf(amax, key >= 0 ? fabsf(v[i]) : 0.f);
+  for (int i = 0; i < 12; ++i) amax = fmaxf(amax, fabsf(v[i]));
   const int mb = wave_max_i(__float_as_int(amax));
   const bool finite = mb < 0x7F800000;
   const int e = ((mb >> 23) & 0xFF) - 126;
   const int ks = finite ? 29 - e : 0;
   wave_sync();
-  if (key >= 0 && mb != 0) {
-    // Lanes still sharing a cell update its texels and channels in a
-    // rotated order, so that one instruction rarely hits one address
-    // from several lanes.
+  if (sel && mb != 0) {
+    // Lanes sharing a cell update its texels and channels in a rotated
+    // order, so that one instruction rarely hits one address from several
+    // lanes.
     const int px = lane & 7, py = lane >> 3;
     const int qr = (px & 1) | ((py & 1) << 1);
     const int rot = C == 3 ? ((px >> 1) & 1) + ((py >> 1) & 1) : 0;
