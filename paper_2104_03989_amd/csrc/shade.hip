@@ -29,13 +29,44 @@ constexpr float kPi = 3.14159265358979323846f;
 // for pixel-sized or thin triangles the screen derivatives of lambda are
 // ill-conditioned, and float32 clip coordinates alone move the texture LOD
 // by ~1e-4 there.  It is ~60 float64 operations per pixel.
-struct PixelGeom {
-  int v[3];        // position indices
-  int t[3];        // uv indices
-  double w[3];     // clip w
+struct BaryD {
+  double w[3];          // clip w
   double gx[3], gy[3];  // x - w px, y - w py
   double a[3], b[3];    // dD/dpx, dD/dpy
   double S, px, py;
+};
+
+// The float64 barycentric set-up of pixel (i, j) on the triangle with
+// position indices v (the adjoint recomputes it at its end rather than
+// keeping these 30 registers live through the shading).
+__device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, const double4* clip, int b, int i,
+                                           int j, const int* v, BaryD& d) {
+  // (i, j) is a visibility sample; shading is evaluated once per pixel, at
+  // the centre of the sample's pixel, with derivatives per pixel
+  const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
+  d.px = 2.0 * ((double)(i / vw.ms) + 0.5) / (double)Wp - 1.0;
+  d.py = 2.0 * ((double)(j / vw.ms) + 0.5) / (double)Hp - 1.0;
+  double D[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double4 q = clip[(int64_t)b * m.n_pos + v[c]];
+    d.w[c] = q.w;
+    d.gx[c] = q.x - q.w * d.px;
+    d.gy[c] = q.y - q.w * d.py;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
+    D[c] = d.gx[j1] * d.gy[k1] - d.gy[j1] * d.gx[k1];
+    d.a[c] = d.w[k1] * d.gy[j1] - d.w[j1] * d.gy[k1];
+    d.b[c] = d.w[j1] * d.gx[k1] - d.w[k1] * d.gx[j1];
+  }
+  d.S = D[0] + D[1] + D[2];
+}
+
+struct PixelGeom {
+  int v[3];        // position indices
+  int t[3];        // uv indices
   float lam[3], lx[3], ly[3];
   float sx, sy;
   f3 x, Ni, T;
@@ -46,40 +77,26 @@ struct PixelGeom {
 __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, const double4* clip,
                                            const float* nrm, const float* tan, int b, int i,
                                            int j, int tri, PixelGeom& g) {
-  // (i, j) is a visibility sample; shading is evaluated once per pixel, at
-  // the centre of the sample's pixel, with derivatives per pixel
   const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
-  g.px = 2.0 * ((double)(i / vw.ms) + 0.5) / (double)Wp - 1.0;
-  g.py = 2.0 * ((double)(j / vw.ms) + 0.5) / (double)Hp - 1.0;
   g.sx = 2.0f / (float)Wp;
   g.sy = 2.0f / (float)Hp;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     g.v[c] = m.tri[3 * tri + c];
     g.t[c] = m.uv_tri[3 * tri + c];
-    double4 q = clip[(int64_t)b * m.n_pos + g.v[c]];
-    g.w[c] = q.w;
-    g.gx[c] = q.x - q.w * g.px;
-    g.gy[c] = q.y - q.w * g.py;
   }
-  double D[3];
+  BaryD d;
+  bary_setup(m, vw, clip, b, i, j, g.v, d);
+  double iS = 1.0 / d.S;
+  double A = d.a[0] + d.a[1] + d.a[2];
+  double Bs = d.b[0] + d.b[1] + d.b[2];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
-    D[c] = g.gx[j1] * g.gy[k1] - g.gy[j1] * g.gx[k1];
-    g.a[c] = g.w[k1] * g.gy[j1] - g.w[j1] * g.gy[k1];
-    g.b[c] = g.w[j1] * g.gx[k1] - g.w[k1] * g.gx[j1];
-  }
-  g.S = D[0] + D[1] + D[2];
-  double iS = 1.0 / g.S;
-  double A = g.a[0] + g.a[1] + g.a[2];
-  double Bs = g.b[0] + g.b[1] + g.b[2];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    double lam = D[c] * iS;
+    double lam = (d.gx[j1] * d.gy[k1] - d.gy[j1] * d.gx[k1]) * iS;
     g.lam[c] = (float)lam;
-    g.lx[c] = (float)((g.a[c] - lam * A) * iS * (2.0 / Wp));
-    g.ly[c] = (float)((g.b[c] - lam * Bs) * iS * (2.0 / Hp));
+    g.lx[c] = (float)((d.a[c] - lam * A) * iS * (2.0 / Wp));
+    g.ly[c] = (float)((d.b[c] - lam * Bs) * iS * (2.0 / Hp));
   }
   // attributes relative to corner 0 (sum lambda = 1, sum of derivatives = 0):
   // a = a0 + sum_c lambda_c (a_c - a0), da = sum_c dlambda_c (a_c - a0)
@@ -579,14 +596,38 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
 // to d(clip x, y, w) of vertex c in this view.
 constexpr int kVtxAcc = 36;
 
-// Adjoint of one pixel.  The vertex gradients are returned in acc and the
-// texture lookups' sample gradients in ts (kd, normal, orm and, with ALPHA,
-// the alpha map), both for the wave-level scatter.  Returns false if the
+// Column stride of the per-wave LDS table of vertex gradients (one column
+// per lane, kVtxAcc rows; odd, against bank conflicts).
+constexpr int kAccStride = 65;
+constexpr int kVtxTable = kVtxAcc * kAccStride;  // floats per wave
+
+// Where the texture-sample records of a pixel go: record 1 + slot of each
+// map with a gradient buffer (slot < 0: none).
+struct RecOut {
+  float4* rec;
+  int64_t P, o;
+  int slot[4];
+};
+
+__device__ __forceinline__ void put_rec(const RecOut& ro, int m, const Lod& L, f3 gs, uint32_t& lv) {
+  const int sl = ro.slot[m];
+  if (sl < 0) return;
+  lv &= ~(0xFFu << (8 * sl));
+  lv |= (uint32_t)L.l0 << (8 * sl);
+  ro.rec[(1 + sl) * ro.P + ro.o] = make_float4(gs.x, gs.y, gs.z, L.has1 ? L.f : 0.f);
+}
+
+// Adjoint of one pixel.  The vertex gradients are written to the pixel's
+// column of the wave's LDS table (col[k * kAccStride], k < kVtxAcc) as they
+// are computed, and each texture lookup's sample gradient record to HBM as
+// soon as it is formed (neither is held in registers to the end); the maps'
+// levels are returned in lv for the record header.  Returns false if the
 // pixel contributes nothing.
 template <bool ALPHA>
 __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
-                                                const float* __restrict__ gcolor, float* acc,
-                                                int& tri, int* vtx, TexScatter* ts) {
+                                                const float* __restrict__ gcolor, float* col,
+                                                int& tri, int* vtx, const RecOut& ro, uint32_t& lv,
+                                                float& u_out, float& v_out) {
   int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
   uint32_t id = (uint32_t)a.vis[o];
   if (id == 0u) return false;
@@ -630,11 +671,13 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
     const float t = tex_trilinear(a.al, g.u, g.v_, La).val.x;
     const f3 gal = mk(t >= 0.f && t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
     tex_bwd(a.al, nullptr, g, La, gal, G);
-    ts[3] = TexScatter{g.u, g.v_, La.l0, La.f, La.has1, gal};
+    put_rec(ro, 3, La, gal, lv);
   }
-  ts[0] = TexScatter{g.u, g.v_, Lk.l0, Lk.f, Lk.has1, gkdv};
-  ts[1] = TexScatter{g.u, g.v_, Ln.l0, Ln.f, Ln.has1, gnt};
-  if (a.model == ADR_SHADE_GGX) ts[2] = TexScatter{g.u, g.v_, Lo.l0, Lo.f, Lo.has1, gormv};
+  put_rec(ro, 0, Lk, gkdv, lv);
+  put_rec(ro, 1, Ln, gnt, lv);
+  if (a.model == ADR_SHADE_GGX) put_rec(ro, 2, Lo, gormv, lv);
+  u_out = g.u;
+  v_out = g.v_;
   // frame: B = N x T', T' = normalize(T1), T1 = T - (N.T) N, N = normalize(Ni)
   f3 gTp = nt.x * gm;
   f3 gBt = nt.y * gm;
@@ -666,30 +709,32 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
     glx[c] = uu * G.ux + vv * G.vx;
     gly[c] = uu * G.uy + vv * G.vy;
     float lc = g.lam[c];
-    float* da = acc + 12 * c;
-    da[0] = lc * gx.x; da[1] = lc * gx.y; da[2] = lc * gx.z;
-    da[3] = lc * gNi.x; da[4] = lc * gNi.y; da[5] = lc * gNi.z;
-    da[6] = lc * gT.x; da[7] = lc * gT.y; da[8] = lc * gT.z;
+    float* da = col + 12 * c * kAccStride;
+    da[0] = lc * gx.x; da[kAccStride] = lc * gx.y; da[2 * kAccStride] = lc * gx.z;
+    da[3 * kAccStride] = lc * gNi.x; da[4 * kAccStride] = lc * gNi.y; da[5 * kAccStride] = lc * gNi.z;
+    da[6 * kAccStride] = lc * gT.x; da[7 * kAccStride] = lc * gT.y; da[8 * kAccStride] = lc * gT.z;
     vtx[c] = vi;
   }
   // barycentrics (float64, like the forward set-up):
   // lambda_c = D_c / S, lx_c = (a_c - lambda_c A) / S * sx, ly_c likewise
-  double iS = 1.0 / g.S;
-  double A = g.a[0] + g.a[1] + g.a[2];
-  double Bs = g.b[0] + g.b[1] + g.b[2];
+  BaryD d;
+  bary_setup(a.m, a.v, a.clip, p.b, p.i, p.j, g.v, d);
+  double iS = 1.0 / d.S;
+  double A = d.a[0] + d.a[1] + d.a[2];
+  double Bs = d.b[0] + d.b[1] + d.b[2];
   double gA = 0.0, gB = 0.0, gS = 0.0;
   double ga[3], gb[3], gD[3], dlam[3], dglam[3];
   double sxd = 2.0 / (a.v.W / a.v.ms), syd = 2.0 / (a.v.H / a.v.ms);  // per pixel
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
-    dlam[c] = (g.gx[j1] * g.gy[k1] - g.gy[j1] * g.gx[k1]) * iS;
+    dlam[c] = (d.gx[j1] * d.gy[k1] - d.gy[j1] * d.gx[k1]) * iS;
     dglam[c] = glam[c];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     double gu_ = glx[c] * sxd, gw_ = gly[c] * syd;
-    double uc = (g.a[c] - dlam[c] * A) * iS, wc = (g.b[c] - dlam[c] * Bs) * iS;
+    double uc = (d.a[c] - dlam[c] * A) * iS, wc = (d.b[c] - dlam[c] * Bs) * iS;
     ga[c] = gu_ * iS;
     gb[c] = gw_ * iS;
     dglam[c] += -(gu_ * A + gw_ * Bs) * iS;
@@ -710,19 +755,19 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
-    ggx[j1] += gD[c] * g.gy[k1] - gb[c] * g.w[k1];
-    ggx[k1] += -gD[c] * g.gy[j1] + gb[c] * g.w[j1];
-    ggy[j1] += -gD[c] * g.gx[k1] + ga[c] * g.w[k1];
-    ggy[k1] += gD[c] * g.gx[j1] - ga[c] * g.w[j1];
-    gw[k1] += ga[c] * g.gy[j1] - gb[c] * g.gx[j1];
-    gw[j1] += -ga[c] * g.gy[k1] + gb[c] * g.gx[k1];
+    ggx[j1] += gD[c] * d.gy[k1] - gb[c] * d.w[k1];
+    ggx[k1] += -gD[c] * d.gy[j1] + gb[c] * d.w[j1];
+    ggy[j1] += -gD[c] * d.gx[k1] + ga[c] * d.w[k1];
+    ggy[k1] += gD[c] * d.gx[j1] - ga[c] * d.w[j1];
+    gw[k1] += ga[c] * d.gy[j1] - gb[c] * d.gx[j1];
+    gw[j1] += -ga[c] * d.gy[k1] + gb[c] * d.gx[k1];
   }
   // g = (x - w px, y - w py)
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    acc[12 * c + 9] = (float)ggx[c];
-    acc[12 * c + 10] = (float)ggy[c];
-    acc[12 * c + 11] = (float)(gw[c] - ggx[c] * g.px - ggy[c] * g.py);
+    col[(12 * c + 9) * kAccStride] = (float)ggx[c];
+    col[(12 * c + 10) * kAccStride] = (float)ggy[c];
+    col[(12 * c + 11) * kAccStride] = (float)(gw[c] - ggx[c] * d.px - ggy[c] * d.py);
   }
   return true;
 }
@@ -734,18 +779,15 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
 // banks); then, per triangle present in the wave, lane k < 36 sums column
 // entries of row k over the lanes on that triangle and issues one atomic.
 // The member loops of all triangles together visit each lane once.
-constexpr int kAccStride = 65;
-constexpr int kVtxTable = kVtxAcc * kAccStride;  // floats per wave
 
 __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, bool act, int tri,
-                                                    const int* vtx, const float* acc, float* win,
+                                                    const int* vtx, const float* win,
                                                     unsigned long long* __restrict__ fclip,
                                                     unsigned long long* __restrict__ fattr, bool det) {
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(act);
   if (!todo) return;
-#pragma unroll
-  for (int k = 0; k < kVtxAcc; ++k) win[k * kAccStride + lane] = act ? acc[k] : 0.f;
+  // the active lanes' columns of win were filled by the pixel adjoint
   wave_sync();
   while (todo) {
     int leader = __ffsll((long long)todo) - 1;
@@ -786,29 +828,18 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   __shared__ float table_all[4][kVtxTable];
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
-  float acc[kVtxAcc];
+  float* table = table_all[threadIdx.x >> 6];
   int tri = -1;
   int vtx[3] = {0, 0, 0};
-  constexpr int kMaps = ALPHA ? 4 : 3;
-  TexScatter ts[kMaps];
-  bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, acc, tri, vtx, ts);
-  if (p.ok && sl.n > 0) {
-    const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
-    const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
-    uint32_t lv = 0xFFFFFFFFu;
-    if (act) {
-      const int slot[4] = {sl.kd, sl.nm, sl.orm, sl.al};
-#pragma unroll
-      for (int m = 0; m < kMaps; ++m) {
-        if (slot[m] < 0) continue;
-        lv &= ~(0xFFu << (8 * slot[m]));
-        lv |= (uint32_t)ts[m].l0 << (8 * slot[m]);
-        rec[(1 + slot[m]) * P + o] = make_float4(ts[m].gs.x, ts[m].gs.y, ts[m].gs.z, ts[m].has1 ? ts[m].f : 0.f);
-      }
-    }
-    rec[o] = make_float4(act ? ts[0].u : 0.f, act ? ts[0].v : 0.f, __uint_as_float(lv), 0.f);
-  }
-  wave_vertex_scatter(a, p.b, act, tri, vtx, acc, table_all[threadIdx.x >> 6], fclip, fattr, det);
+  const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
+  const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
+  const RecOut ro{rec, P, o, {sl.n > 0 ? sl.kd : -1, sl.n > 0 ? sl.nm : -1, sl.n > 0 ? sl.orm : -1,
+                              ALPHA && sl.n > 0 ? sl.al : -1}};
+  uint32_t lv = 0xFFFFFFFFu;
+  float u = 0.f, v = 0.f;
+  bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, table + (threadIdx.x & 63), tri, vtx, ro, lv, u, v);
+  if (p.ok && sl.n > 0) rec[o] = make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), 0.f);
+  wave_vertex_scatter(a, p.b, act, tri, vtx, table, fclip, fattr, det);
 }
 
 // Texel-gradient scatter of the recorded samples: a kernel of its own with
