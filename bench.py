@@ -271,6 +271,19 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
 TEXEL_C = 1.25   # compulsory texels per covered pixel per mip level at ~1 texel per pixel
 
 
+def lookup_bytes(w):
+    """Compulsory texel bytes of one pixel's trilinear lookups of every
+    latent map larger than 1x1: TEXEL_C texels at each of two levels."""
+    total = 0.0
+    for name in ("kd", "normal", "orm", "alpha"):
+        tex = getattr(w.latent, name, None)
+        if tex is None or tex.data.shape[0] <= 1:
+            continue
+        bt = 4 if getattr(tex, "fmt", "f32") == "rgba8" else 4 * tex.data.shape[2]
+        total += 2 * TEXEL_C * bt
+    return total
+
+
 def optimised_maps(w):
     """(name, bytes per texel) of the optimised F32 maps larger than 1x1."""
     out = []
@@ -285,8 +298,9 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     """Compulsory HBM bytes of one launch of a stage's kernel.
 
     shade_bwd (pixel adjoint): per pixel its visibility key (8 B) and the
-    record header it writes (16 B); per covered pixel dL/dcolour (12 B) and a
-    16-B sample record per optimised map.
+    record header it writes (16 B); per covered pixel dL/dcolour (12 B), a
+    16-B sample record per optimised map and the texels of its trilinear
+    lookups (TEXEL_C per level, two levels, every latent map).
     tex_bwd (texel scatter): the records back (16 B per pixel, 16 B per
     covered pixel and map) and, per covered pixel and map, TEXEL_C texels at
     each of the two trilinear levels, each a read-modify-write of its
@@ -303,14 +317,14 @@ def algorithmic_bytes(stage, w, st, covered_latent):
         # depth-peeled latent: one launch per layer; covered_latent counts the
         # covered pixels of all layers; the average launch is returned
         if stage == "shade_bwd":
-            return (L * px * (8 + 16 + 4) + covered_latent * (12 + 16 * len(maps))) / L
+            return (L * px * (8 + 16 + 4) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w))) / L
         if stage == "tex_bwd":
             return (L * px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)) / L
         if stage == "aa_bwd":
             return px * (8 + 12 + 12 + 12)
         return None
     if stage == "shade_bwd":
-        return px * (8 + 16) + covered_latent * (12 + 16 * len(maps))
+        return px * (8 + 16) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w))
     if stage == "tex_bwd":
         return px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)
     if stage == "aa_bwd":
