@@ -332,7 +332,10 @@ def algorithmic_bytes(stage, w, st, covered_latent):
     if stage == "aa_loss":
         return px * (8 + 12 + 12 + 12) / 2.0              # per render (two per step, averaged)
     if stage == "shade":
-        return px * (8 + 12)                              # key in, colour out
+        # key in, colour out per shaded sample, averaged over the two renders
+        # of a step: the reference at ref_ssaa^2 and the latent at msaa^2
+        # samples per pixel
+        return px * (8 + 12) * (w.ref_ssaa ** 2 + w.msaa ** 2) / 2.0
     if stage == "skin_bwd" and st.get("skin"):
         V, nb = st["skin"]
         # per vertex: dL/dskinned read + cleared, bind position, blended
