@@ -118,7 +118,7 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False):
+def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False, tune=True):
     """Upload the workload and return (step(t) closure, state)."""
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
     rig = None
@@ -215,6 +215,25 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         lat_out = adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_img, loss=w.loss,
                                  flags=lflag, want_image=False, want_tri_id=True)
 
+    # the rasterizer's work split of each render from the autotuner (cached
+    # per shape bucket; the split changes only the speed)
+    from paper_2104_03989_amd.autotune import DEFAULT, Tuner
+    split_ref = split_lat = DEFAULT
+    if tune:
+        tuner = Tuner()
+        split_ref = tuner.pick(ctx, "ref", int(w.ref.mesh.tri.shape[0]), B, W * k,
+                               lambda: adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], outputs=ref_out,
+                                                      flags=dflag & adr.DETERMINISTIC))
+        if L:
+            split_lat = tuner.pick(ctx, f"latent_peel{L}", int(lat_mesh.tri.shape[0]), B, W * w.msaa,
+                                   lambda: adr.render_oit_fwd(ctx, lat_mesh, lat_mat, views[0], L, ref=ref_img,
+                                                              loss=w.loss, flags=sflag, outputs=lat_out))
+        else:
+            split_lat = tuner.pick(ctx, "latent", int(lat_mesh.tri.shape[0]), B, W * w.msaa,
+                                   lambda: adr.render_fwd(ctx, lat_mesh, lat_mat, views[0], ref=ref_img, loss=w.loss,
+                                                          flags=sflag, outputs=lat_out))
+        tuner.save()
+
     # uniform Laplacian regularizer (absolute form: the latent starts as a
     # resampled sphere), lambda_0 by the heuristic, then the recursive decay
     lap = None
@@ -240,7 +259,9 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
             bones = rig["bones"][t % n_frames]
             adr.skin_fwd(ctx, rig["ref_bind"], rig["ref_w"], bones, out=ref_mesh.pos)
             adr.skin_fwd(ctx, rig["bind"], rig["w"], bones, out=lat_mesh.pos, blend=rig["blend"])
+        ctx.set_raster(*split_ref)
         adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_out, flags=dflag & adr.DETERMINISTIC)
+        ctx.set_raster(*split_lat)
         if k > 1:
             adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
         if L:
@@ -263,7 +284,8 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
 
     state = dict(ref_mesh=ref_mesh, lat_mesh=lat_mesh, lat_mat=lat_mat, lat_out=lat_out,
                  ref_out=ref_out, n_params=n_params, n_map_params=n_map_params,
-                 map_adam_bytes=map_adam_bytes, views=views, adam=adam,
+                 map_adam_bytes=map_adam_bytes, raster_split={"ref": list(split_ref), "latent": list(split_lat)},
+                 views=views, adam=adam,
                  skin=None if rig is None else tuple(rig["w"].shape))
     return step, state
 
@@ -581,6 +603,7 @@ def main():
                     help="add the uniform Laplacian regularizer with the heuristic lambda_0 and its schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
+    ap.add_argument("--no-tune", action="store_true", help="default raster work split instead of the autotuner's")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-jobs", type=int, default=16)
@@ -616,7 +639,7 @@ def main():
     ctx = adr.Context(0)
     n_steps = args.warmup + args.steps
     step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic,
-                          laplacian=args.laplacian)
+                          laplacian=args.laplacian, tune=not args.no_tune)
     torch.cuda.synchronize()
     if w.oit_layers:
         covered = int(((st["lat_out"]["vis"] & 0xFFFFFFFF) != 0).sum())
@@ -690,7 +713,7 @@ def main():
                    "views": B, "res": [W, H], "ref_tris": int(w.ref.mesh.tri.shape[0]),
                    "latent_tris": int(st["lat_mesh"].tri.shape[0]), "params": st["n_params"],
                    "gradient_mode": "deterministic" if args.deterministic else "atomic",
-                   "laplacian": bool(args.laplacian),
+                   "laplacian": bool(args.laplacian), "raster_split": st["raster_split"],
                    "final_loss": round(loss, 6)},
         "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
         "stage_gbs": stage_gbs,
