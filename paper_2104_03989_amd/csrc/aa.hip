@@ -278,41 +278,85 @@ __device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, 
   return (1.0f / (float)(a.v.ms * a.v.ms)) * ldc(dimage, op);
 }
 
-// Codes of every pixel's pairs with its right and upper neighbours.
-__global__ __launch_bounds__(256) void k_aa_pairs(AAArgs a) {
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
-  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
-  if (!p.ok) return;
+// Antialiasing, image and loss of one 16x16 tile of pixels (Sec. 5.2, 5.3).
+// Every pair of neighbours is evaluated once: each pixel evaluates its pairs
+// with its right and upper neighbours, and 32 threads the pairs that link
+// the tile to its left and lower neighbours (which the neighbouring tiles
+// evaluate too, with the same arguments and so the same code); the codes
+// meet in LDS, where each pixel gathers its four: hc[r][c] is the code of the
+// pair (x0 + c - 1, x0 + c) in row y0 + r, vc[r][c] that of (y0 + r - 1,
+// y0 + r) in column x0 + c.  With a stats buffer the pixels' own codes also
+// go to it for the adjoint.
+__global__ __launch_bounds__(256) void k_aa_fwd(AAArgs a, const float* __restrict__ ref, int loss_kind,
+                                                float* __restrict__ image, float* __restrict__ dimage,
+                                                float* __restrict__ partial) {
+  __shared__ float hc[16][17], vc[17][16];
+  __shared__ float red[4];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
+  const int x0 = p.i - lx, y0 = p.j - ly;
   const int64_t base = (int64_t)p.b * a.v.H * a.v.W;
   const int64_t o = base + (int64_t)p.j * a.v.W + p.i;
-  const uint64_t k = a.vis[o];
-  float code[2] = {-1.f, -1.f};
+  const uint64_t k = p.ok ? a.vis[o] : 0ull;
+  if (!a.no_aa) {
+    float code[2] = {-1.f, -1.f};
+    if (p.ok) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int ni = p.i + (q == 0 ? 1 : 0), nj = p.j + (q == 1 ? 1 : 0);
-    if (ni >= a.v.W || nj >= a.v.H) continue;
-    Pair pr;
-    if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[base + (int64_t)nj * a.v.W + ni], pr)) code[q] = pair_code(pr.x);
+      for (int q = 0; q < 2; ++q) {
+        const int ni = p.i + (q == 0 ? 1 : 0), nj = p.j + (q == 1 ? 1 : 0);
+        if (ni >= a.v.W || nj >= a.v.H) continue;
+        Pair pr;
+        if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[base + (int64_t)nj * a.v.W + ni], pr))
+          code[q] = pair_code(pr.x);
+      }
+      if (a.stats) {
+        a.codes[a.code_stride * o] = code[0];
+        a.codes[a.code_stride * o + 1] = code[1];
+      }
+    }
+    hc[ly][lx + 1] = code[0];
+    vc[ly + 1][lx] = code[1];
+    if (threadIdx.x < 32) {
+      // the pair's left (lower) pixel (i, j) and its neighbour (ni, nj)
+      const bool left = threadIdx.x < 16;
+      const int r = threadIdx.x & 15;
+      const int i = left ? x0 - 1 : x0 + r, j = left ? y0 + r : y0 - 1;
+      const int ni = left ? i + 1 : i, nj = left ? j : j + 1;
+      float c = -1.f;
+      if (i >= 0 && j >= 0 && ni < a.v.W && nj < a.v.H) {
+        Pair pr;
+        if (eval_pair(a, p.b, i, j, a.vis[base + (int64_t)j * a.v.W + i], ni, nj,
+                      a.vis[base + (int64_t)nj * a.v.W + ni], pr))
+          c = pair_code(pr.x);
+      }
+      if (left) hc[r][0] = c;
+      else vc[0][r] = c;
+    }
+    __syncthreads();
   }
-  a.codes[a.code_stride * o] = code[0];
-  a.codes[a.code_stride * o + 1] = code[1];
-}
-
-__global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __restrict__ ref,
-                                                     int loss_kind, float* __restrict__ image,
-                                                     float* __restrict__ dimage,
-                                                     float* __restrict__ partial) {
-  __shared__ float red[4];
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
-  Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   float lsum = 0.f;
   if (p.ok) {
-    int64_t base = (int64_t)p.b * a.v.H * a.v.W;
-    int64_t o = base + (int64_t)p.j * a.v.W + p.i;
-    f3 c = ldc(a.color, o);
+    const f3 c = ldc(a.color, o);
     f3 out = c;
     if (!a.no_aa) {
-      Recv r = recv_stats(a, p.b, p.i, p.j);
+      // received antialiasing: W and acc = sum_k w_k (c_k - c)
+      Recv r{0.f, mk(0.f, 0.f, 0.f)};
+      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ni = p.i + di[q], nj = p.j + dj[q];
+        if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
+        const int64_t on = base + (int64_t)nj * a.v.W + ni;
+        const uint64_t kn = a.vis[on];
+        const float cq = q == 0 ? hc[ly][lx] : (q == 1 ? hc[ly][lx + 1] : (q == 2 ? vc[ly][lx] : vc[ly + 1][lx]));
+        const float w = (uint32_t)k == (uint32_t)kn ? 0.f : received_from(cq, k < kn);
+        if (w > 0.f) {
+          r.W += w;
+          r.acc += w * (ldc(a.color, on) - c);
+        }
+      }
       if (r.W > 0.f) out += (1.0f / fmaxf(r.W, 1.0f)) * r.acc;
       if (a.stats) a.stats[o] = make_float4(r.W, r.acc.x, r.acc.y, r.acc.z);
     }
@@ -325,7 +369,7 @@ __global__ __launch_bounds__(256) void k_aa_loss_fwd(AAArgs a, const float* __re
   if (ref) {
     // block reduction in a fixed order (deterministic)
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lsum;
+    if (lane == 0) red[wave] = lsum;
     __syncthreads();
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   }
@@ -443,13 +487,12 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
 // codes go to context scratch (forward) or are not used (adjoint: every pair
 // is re-evaluated).
 static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
-                      const float* color, int no_aa, float* stats, bool fwd) {
+                      const float* color, int no_aa, float* stats) {
   AAArgs a;
   const int64_t npx = (int64_t)v.B * v.H * v.W;
   a.stats = reinterpret_cast<float4*>(stats);
   a.code_stride = 2;
   a.codes = stats ? stats + 4 * npx : nullptr;
-  if (!stats && fwd) a.codes = s.aa_codes;
   a.m = m;
   a.v = v;
   a.snap = reinterpret_cast<const int4*>(s.snap);
@@ -467,17 +510,13 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
                               hipStream_t st, float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats, true);
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats);
   int nb = a.tiles_x * a.tiles_y * v.B;
   if (!image && !ref) return hipSuccess;
   hipError_t e;
-  if (!no_aa) {
-    hipLaunchKernelGGL(k_aa_pairs, dim3(nb), dim3(256), 0, st, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   if (v.ms > 1) {
     // antialiased samples, then the resolve and the loss per pixel
-    hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, (const float*)nullptr, loss_kind,
+    hipLaunchKernelGGL(k_aa_fwd, dim3(nb), dim3(256), 0, st, a, (const float*)nullptr, loss_kind,
                        s.image_s, (float*)nullptr, s.partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t n = (int64_t)v.B * (v.H / v.ms) * (v.W / v.ms);
@@ -485,8 +524,7 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
     hipLaunchKernelGGL(k_msaa_resolve, dim3(nb), dim3(256), 0, st, v, s.image_s, ref, loss_kind, image, dimage,
                        s.partial);
   } else {
-    hipLaunchKernelGGL(k_aa_loss_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage,
-                       s.partial);
+    hipLaunchKernelGGL(k_aa_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage, s.partial);
   }
   e = hipGetLastError();
   if (e != hipSuccess || !ref) return e;
@@ -499,7 +537,7 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st, const float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats), false);
+  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats));
   int nb = a.tiles_x * a.tiles_y * v.B;
   hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.fix_clip, s.det);
   return hipGetLastError();

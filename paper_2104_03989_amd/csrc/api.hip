@@ -63,8 +63,7 @@ struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
   Buf oit_g, oit_a;  // depth-peeling adjoint: dL/d(composite behind) and dL/d alpha per pixel
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s,
-      aa_codes;
+  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -223,8 +222,6 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       return r;
     if (tex_slots > 0 && (r = ensure(ctx->texrec, (size_t)(1 + tex_slots) * B * v.W * v.H * 16))) return r;
   }
-  if ((r = ensure(ctx->aa_codes, B * v.W * v.H * 8))) return r;
-  s.aa_codes = (float*)ctx->aa_codes.p;
   s.image_s = nullptr;
   if (v.ms > 1) {
     if ((r = ensure(ctx->image_s, B * v.W * v.H * 12))) return r;
@@ -332,7 +329,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
-                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->aa_codes, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {

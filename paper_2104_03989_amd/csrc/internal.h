@@ -59,7 +59,6 @@ struct Scratch {
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
   float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
   float* image_s;     // [B,H,W,3] antialiased samples before the multisample resolve
-  float* aa_codes;    // [B,H,W,2] antialiasing pair codes of a forward without a caller buffer
   int n_partial;
   // vertex-side adjoint accumulators (float64, or fixed point in
   // deterministic mode) and the deterministic mode's sort buffers
