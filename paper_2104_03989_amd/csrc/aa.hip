@@ -27,7 +27,6 @@ struct AAArgs {
   MeshD m;
   ViewsD v;
   const int4* snap;
-  const double4* clip;
   const int8_t* orient;
   const uint64_t* vis;
   const float* color;
@@ -86,8 +85,8 @@ __device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi
     if (!sil) continue;
     x.va = v[vid[j]];
     x.vb = v[vid[l]];
-    double4 ca = a.clip[(int64_t)b * a.m.n_pos + x.va];
-    double4 cb = a.clip[(int64_t)b * a.m.n_pos + x.vb];
+    double4 ca = clip_d(a.m.pos, a.v.mvp, b, x.va);
+    double4 cb = clip_d(a.m.pos, a.v.mvp, b, x.vb);
     double Px = 2.0 * ((double)Pi + 0.5) / (double)a.v.W - 1.0;
     double Py = 2.0 * ((double)Pj + 0.5) / (double)a.v.H - 1.0;
     double Qx = 2.0 * ((double)Qi + 0.5) / (double)a.v.W - 1.0;
@@ -396,7 +395,8 @@ __global__ void k_loss_reduce(const float* __restrict__ partial, int n, float in
 // its four pairs; a receiver's W and acc are recomputed from its own pairs);
 // the gradient of a pair's crossing parameter s w.r.t. the clip coordinates
 // of its edge is scattered once, by the left (or lower) pixel of the pair.
-__global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
+// (3 waves per SIMD: the compiler's own choice, 170 VGPRs, drops to 2)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
                                                 const float* __restrict__ dloss,
                                                 float* __restrict__ gcolor,
                                                 unsigned long long* __restrict__ fclip, bool det) {
@@ -458,8 +458,8 @@ __global__ __launch_bounds__(256) void k_aa_bwd(AAArgs a, const float* __restric
       // s = eP / (eP - eQ)
       double id2 = 1.0 / (pr.x.den * pr.x.den);
       double g_eP = -g_s * pr.x.eQ * id2, g_eQ = g_s * pr.x.eP * id2;
-      double4 ca = a.clip[(int64_t)p.b * a.m.n_pos + pr.x.va];
-      double4 cb = a.clip[(int64_t)p.b * a.m.n_pos + pr.x.vb];
+      double4 ca = clip_d(a.m.pos, a.v.mvp, p.b, pr.x.va);
+      double4 cb = clip_d(a.m.pos, a.v.mvp, p.b, pr.x.vb);
       double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
       double ax = ca.x * iwa, ay = ca.y * iwa, bx = cb.x * iwb, by = cb.y * iwb;
       // e(X) = a'_x b'_y - a'_y b'_x, a' = a - X, b' = b - X
@@ -496,7 +496,6 @@ static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const u
   a.m = m;
   a.v = v;
   a.snap = reinterpret_cast<const int4*>(s.snap);
-  a.clip = reinterpret_cast<const double4*>(s.clip);
   a.orient = s.orient;
   a.vis = vis;
   a.color = color;

@@ -63,7 +63,7 @@ struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
   Buf oit_g, oit_a;  // depth-peeling adjoint: dL/d(composite behind) and dL/d alpha per pixel
-  Buf clip, snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
+  Buf snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -209,7 +209,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
   size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
   size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
   adr_status r;
-  if ((r = ensure(ctx->clip, B * V * 32)) || (r = ensure(ctx->snap, B * V * 16)) ||
+  if ((r = ensure(ctx->snap, B * V * 16)) ||
       (r = ensure(ctx->orient, B * T)) || (r = ensure(ctx->nacc, V * 24)) ||
       (r = ensure(ctx->tacc, V * 24)) || (r = ensure(ctx->nrm, V * 12)) ||
       (r = ensure(ctx->tan, V * 12)) || (r = ensure(ctx->big, B * T * 4)) ||
@@ -261,7 +261,6 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       }
     }
   }
-  s.clip = (double*)ctx->clip.p;
   s.snap = (int*)ctx->snap.p;
   s.orient = (int8_t*)ctx->orient.p;
   s.nacc = (double*)ctx->nacc.p;
@@ -329,7 +328,7 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
-                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->clip, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
+                 &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
                  &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {

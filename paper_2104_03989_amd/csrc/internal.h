@@ -42,7 +42,6 @@ struct ViewsD {
 
 // Per-call scratch owned by the context.
 struct Scratch {
-  double* clip;       // [B,V,4] clip coordinates in float64 (interpolation, antialiasing)
   int* snap;          // [B,V,4]
   int8_t* orient;     // [B,T]
   double* nacc;       // [V,3] unnormalised vertex normals (float64)

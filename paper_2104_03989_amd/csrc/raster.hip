@@ -38,23 +38,19 @@ __device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b)
 
 // Snapped integer coordinates (from the float32 clip coordinates of the
 // rules above) and float64 clip coordinates for interpolation.
-__global__ void k_xform(MeshD m, ViewsD v, double4* __restrict__ clip, int4* __restrict__ snap) {
+__global__ void k_xform(MeshD m, ViewsD v, int4* __restrict__ snap) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= v.B * m.n_pos) return;
   int b = gid / m.n_pos, vi = gid - b * m.n_pos;
   const float* M = v.mvp + 16 * b;
   float px = m.pos[3 * vi], py = m.pos[3 * vi + 1], pz = m.pos[3 * vi + 2];
   float c[4];
-  double d[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     float t = fadd(fmul(M[4 * r + 0], px), fmul(M[4 * r + 1], py));
     t = fadd(t, fmul(M[4 * r + 2], pz));
     c[r] = fadd(t, M[4 * r + 3]);
-    d[r] = ((double)M[4 * r + 0] * px + (double)M[4 * r + 1] * py) + (double)M[4 * r + 2] * pz +
-           (double)M[4 * r + 3];
   }
-  clip[gid] = make_double4(d[0], d[1], d[2], d[3]);
   int4 s = make_int4(0, 0, 0, 0);
   float w = c[3];
   if (w > 1e-6f) {
@@ -338,7 +334,7 @@ hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipSt
   int n = v.B * m.n_pos;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_xform, dim3((n + 255) / 256), dim3(256), 0, st, m, v,
-                     reinterpret_cast<double4*>(s.clip), reinterpret_cast<int4*>(s.snap));
+                     reinterpret_cast<int4*>(s.snap));
   return hipGetLastError();
 }
 

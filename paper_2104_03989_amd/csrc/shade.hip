@@ -39,7 +39,7 @@ struct BaryD {
 // The float64 barycentric set-up of pixel (i, j) on the triangle with
 // position indices v (the adjoint recomputes it at its end rather than
 // keeping these 30 registers live through the shading).
-__device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, const double4* clip, int b, int i,
+__device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, int b, int i,
                                            int j, const int* v, BaryD& d) {
   // (i, j) is a visibility sample; shading is evaluated once per pixel, at
   // the centre of the sample's pixel, with derivatives per pixel
@@ -49,7 +49,7 @@ __device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, con
   double D[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double4 q = clip[(int64_t)b * m.n_pos + v[c]];
+    double4 q = clip_d(m.pos, vw.mvp, b, v[c]);
     d.w[c] = q.w;
     d.gx[c] = q.x - q.w * d.px;
     d.gy[c] = q.y - q.w * d.py;
@@ -74,7 +74,7 @@ struct PixelGeom {
   f3 N, T1, Tp, Bt;
 };
 
-__device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, const double4* clip,
+__device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
                                            const float* nrm, const float* tan, int b, int i,
                                            int j, int tri, PixelGeom& g) {
   const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
@@ -86,7 +86,7 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw, con
     g.t[c] = m.uv_tri[3 * tri + c];
   }
   BaryD d;
-  bary_setup(m, vw, clip, b, i, j, g.v, d);
+  bary_setup(m, vw, b, i, j, g.v, d);
   double iS = 1.0 / d.S;
   double A = d.a[0] + d.a[1] + d.a[2];
   double Bs = d.b[0] + d.b[1] + d.b[2];
@@ -281,7 +281,6 @@ struct ShadeArgs {
   Tex kd, nm, orm;
   Tex al;                 // alpha map (data NULL: none)
   const float* galpha;    // dL/d alpha per pixel (adjoint of a depth-peeled layer), or NULL
-  const double4* clip;
   const float* nrm;
   const float* tan;
   const uint64_t* vis;
@@ -310,7 +309,7 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
     return;
   }
   PixelGeom g;
-  pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
+  pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
   if (alpha) alpha[o] = layer_alpha(a, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
   f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
@@ -636,7 +635,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   if (gc.x == 0.f && gc.y == 0.f && gc.z == 0.f && g_alpha == 0.f) return false;
   tri = (int)id - 1;
   PixelGeom g;
-  pixel_geom(a.m, a.v, a.clip, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
+  pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
   f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
   Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
@@ -718,7 +717,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   // barycentrics (float64, like the forward set-up):
   // lambda_c = D_c / S, lx_c = (a_c - lambda_c A) / S * sx, ly_c likewise
   BaryD d;
-  bary_setup(a.m, a.v, a.clip, p.b, p.i, p.j, g.v, d);
+  bary_setup(a.m, a.v, p.b, p.i, p.j, g.v, d);
   double iS = 1.0 / d.S;
   double A = d.a[0] + d.a[1] + d.a[2];
   double Bs = d.b[0] + d.b[1] + d.b[2];
@@ -881,7 +880,6 @@ static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex
   a.kd = kd;
   a.nm = nm;
   a.orm = orm;
-  a.clip = reinterpret_cast<const double4*>(s.clip);
   a.nrm = s.nrm;
   a.tan = s.tan;
   a.vis = vis;
