@@ -286,7 +286,8 @@ __device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, 
 // pair (x0 + c - 1, x0 + c) in row y0 + r, vc[r][c] that of (y0 + r - 1,
 // y0 + r) in column x0 + c.  With a stats buffer the pixels' own codes also
 // go to it for the adjoint.
-__global__ __launch_bounds__(256) void k_aa_fwd(AAArgs a, const float* __restrict__ ref, int loss_kind,
+// (6 waves per SIMD: the compiler's own choice, 88 VGPRs, gives 5 and ran 6% slower)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_aa_fwd(AAArgs a, const float* __restrict__ ref, int loss_kind,
                                                 float* __restrict__ image, float* __restrict__ dimage,
                                                 float* __restrict__ partial) {
   __shared__ float hc[16][17], vc[17][16];
