@@ -66,7 +66,7 @@ __device__ __forceinline__ bool vec_ok(const float* p, int w, int64_t gs) {
 // Levels 1..L of a tile from its level 0 held in LDS (`base`, T rows of
 // T*C floats), each level kept in LDS for the next and written to the chain.
 __device__ __forceinline__ void tile_build_levels(const Tex& t, float* d, int by, int bx, int T, int L,
-                                                  const float* base, float (*lds)[256 * 4]) {
+                                                  const float* base, float* odd, float* even) {
   const int S = t.size, C = t.channels, tid = threadIdx.x;
   int s = T >> 1;
   if (tid < s * s) {
@@ -75,18 +75,18 @@ __device__ __forceinline__ void tile_build_levels(const Tex& t, float* d, int by
     for (int ch = 0; ch < C; ++ch) {
       float a = base[k00 * C + ch], b = base[(k00 + 1) * C + ch];
       float e = base[(k00 + T) * C + ch], f = base[(k00 + T + 1) * C + ch];
-      lds[0][tid * C + ch] = ((a + b) + (e + f)) * 0.25f;
+      odd[tid * C + ch] = ((a + b) + (e + f)) * 0.25f;
     }
   }
   __syncthreads();
   float* g1 = d + ((int64_t)t.off[1] + (int64_t)(by * s) * (S >> 1) + bx * s) * C;
-  tile_copy<false>(g1, (int64_t)(S >> 1) * C, lds[0], s, s * C, vec_ok(g1, s * C, (int64_t)(S >> 1) * C));
+  tile_copy<false>(g1, (int64_t)(S >> 1) * C, odd, s, s * C, vec_ok(g1, s * C, (int64_t)(S >> 1) * C));
   for (int l = 2; l <= L; ++l) {
     const int sp = s;
     s >>= 1;
     __syncthreads();
-    const float* src = lds[l & 1];
-    float* dst = lds[(l + 1) & 1];
+    const float* src = (l & 1) ? even : odd;
+    float* dst = (l & 1) ? odd : even;
     if (tid < s * s) {
       int r = tid / s, c = tid - r * s;
       int k00 = 2 * r * sp + 2 * c;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void k_mip_build_tiles(MipSet ms) {
   float* g0 = d + ((int64_t)(by * T) * S + bx * T) * C;
   tile_copy<true>(g0, (int64_t)S * C, base, T, T * C, vec_ok(g0, T * C, (int64_t)S * C));
   __syncthreads();
-  tile_build_levels(t, d, by, bx, T, L, base, lds);
+  tile_build_levels(t, d, by, bx, T, L, base, lds[0], lds[1]);
 }
 
 // Levels above the tile range of map k, level by level (one block).
@@ -284,9 +284,11 @@ __global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1,
   const int L = min(t.levels - 1, ilog2i(T));
   const int C = t.channels, tid = threadIdx.x;
   const int by = blockIdx.x / nt, bx = blockIdx.x - by * nt;
-  __shared__ float pyr[kPyrLds];
+  // LDS: the gradient pyramid, reused for the odd levels of the rebuild once
+  // the level-0 update has read it; the new level 0, reused for the even
+  // levels once level 1 is built from it
+  __shared__ __align__(16) float pyr[kPyrLds];
   __shared__ __align__(16) float base[kMipTile * kMipTile * 3];
-  __shared__ __align__(16) float lds[2][256 * 4];
   const int64_t o0 = ((int64_t)(by * T) * S + bx * T) * C, gs = (int64_t)S * C;
   float* d = (float*)t.data;
   float* g = a.ms.g[blockIdx.y];
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1,
   }
   if (L <= 0) return;
   __syncthreads();
-  tile_build_levels(t, d, by, bx, T, L, base, lds);
+  tile_build_levels(t, d, by, bx, T, L, base, pyr, base);
 }
 
 // After k_adam_maps_tiles: clears the gradient levels above the tiles and
