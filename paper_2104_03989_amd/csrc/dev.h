@@ -183,7 +183,7 @@ __device__ __forceinline__ Bil bil_footprint(const Tex& t, int l, float u, float
   b.fy = y - y0f;
   int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
   int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
-  int c0 = x0 % s; if (c0 < 0) c0 += s;
+  int c0 = x0 & (s - 1);  // x0 mod s (s is a power of two), in [0, s) also for x0 < 0
   int c1 = c0 + 1; if (c1 == s) c1 = 0;
   int r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
   int r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);

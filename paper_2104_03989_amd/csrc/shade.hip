@@ -443,9 +443,7 @@ __device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
   q.fy = y - y0f;
   int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
   int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
-  int c0 = x0 % s;
-  if (c0 < 0) c0 += s;
-  q.c0 = c0;
+  q.c0 = x0 & (s - 1);  // x0 mod s (s is a power of two), in [0, s) also for x0 < 0
   q.r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
   q.r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);
   return q;
@@ -471,12 +469,10 @@ __device__ __forceinline__ WinT fix_of(float x, int k, bool finite) {
 }
 
 __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gtex, WinT* win, bool sel,
-                                            const Foot& q, float wl, const float (&gsv)[3], int off) {
-  const int BIG = 1 << 20;
+                                            const Foot& q, float wl, const float (&gsv)[3], int off, int rmin,
+                                            int rmax, int cmin, int cmax) {
   const int lane = threadIdx.x & 63;
   const int C = t.channels;
-  const int rmin = wave_min_i(sel ? q.r0 : BIG), rmax = wave_max_i(sel ? q.r1 : -1);
-  const int cmin = wave_min_i(sel ? q.c0 : BIG), cmax = wave_max_i(sel ? q.c0 + 1 : -1);
   const int ww = cmax - cmin + 1;
   const int n = (rmax - rmin + 1) * ww * C;
   for (int k = lane; k < n; k += 64) win[k] = 0ull;
@@ -530,14 +526,26 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   }
   wave_sync();
   if (mb != 0) {
+    // entry k = (row * ww + column) * C + channel; the row from a float
+    // reciprocal of ww corrected by one either way (no integer division)
+    const float inv_ww = 1.0f / (float)ww;
     for (int k = lane; k < n; k += 64) {
       const long long sum = (long long)win[k];
       if (sum != 0) {
         const float val = finite ? ldexpf((float)sum, -ks) : __int_as_float(0x7FC00000);
-        int texel = k / C, ch = k - texel * C;
-        int r = rmin + texel / ww, c = cmin + texel % ww;
+        const int texel = C == 3 ? k / 3 : k, ch = k - texel * C;
+        int rr = (int)((float)texel * inv_ww);
+        int cc = texel - rr * ww;
+        if (cc < 0) {
+          --rr;
+          cc += ww;
+        } else if (cc >= ww) {
+          ++rr;
+          cc -= ww;
+        }
+        int c = cmin + cc;
         if (c >= q.s) c -= q.s;
-        atomicAdd(gtex + (int64_t)(off + r * q.s + c) * C + ch, val);
+        atomicAdd(gtex + (int64_t)(off + (rmin + rr) * q.s + c) * C + ch, val);
       }
     }
   }
@@ -577,13 +585,18 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
     unsigned long long left = __ballot(pending);
     while (left) {
       bool in = pending;
+      int r0 = rmin, r1 = rmax, c0 = cmin, c1 = cmax;
       if (!whole) {
         const int leader = __ffsll((long long)left) - 1;
         const int br = __builtin_amdgcn_readlane(q.r0, leader) - (side / 2 - 1);
         const int bc = __builtin_amdgcn_readlane(q.c0, leader) - (side / 2 - 1);
         in = pending && q.r0 >= br && q.r1 <= br + side - 1 && q.c0 >= bc && q.c0 + 1 <= bc + side - 1;
+        r0 = wave_min_i(in ? q.r0 : BIG);
+        r1 = wave_max_i(in ? q.r1 : -1);
+        c0 = wave_min_i(in ? q.c0 : BIG);
+        c1 = wave_max_i(in ? q.c0 + 1 : -1);
       }
-      window_pass(t, gtex, win, in, q, wl, gsv, off);
+      window_pass(t, gtex, win, in, q, wl, gsv, off, r0, r1, c0, c1);
       pending = pending && !in;
       left = __ballot(pending);
     }

@@ -45,7 +45,7 @@ __device__ __forceinline__ DBil disp_footprint(const Tex& t, float u, float v) {
   b.fy = y - y0f;
   int x0 = (int)fmin(fmax(x0f, -1073741824.0), 1073741824.0);
   int y0 = (int)fmin(fmax(y0f, -1073741824.0), 1073741824.0);
-  int c0 = x0 % s; if (c0 < 0) c0 += s;
+  int c0 = x0 & (s - 1);  // x0 mod s (s is a power of two), in [0, s) also for x0 < 0
   int c1 = c0 + 1; if (c1 == s) c1 = 0;
   int r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
   int r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);
