@@ -499,28 +499,16 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   const int ks = finite ? 29 - e : 0;
   wave_sync();
   if (sel && mb != 0) {
-    // Lanes sharing a cell update its texels and channels in a rotated
-    // order, so that one instruction rarely hits one address from several
-    // lanes.
-    const int px = lane & 7, py = lane >> 3;
-    const int qr = (px & 1) | ((py & 1) << 1);
-    const int rot = C == 3 ? ((px >> 1) & 1) + ((py >> 1) & 1) : 0;
+    // corner by corner (lanes sharing a cell add to the same entries in one
+    // instruction: integer LDS atomics absorb that; rotating the corner and
+    // channel order per lane against it cost more in selects than it saved)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int kk = k ^ qr;
-      const int cell = (((kk & 2 ? q.r1 : q.r0) - rmin) * ww + ((kk & 1 ? q.c0 + 1 : q.c0) - cmin)) * C;
-      const float v0 = kk == 0 ? v[0] : (kk == 1 ? v[3] : (kk == 2 ? v[6] : v[9]));
+      const int cell = (((k & 2 ? q.r1 : q.r0) - rmin) * ww + ((k & 1 ? q.c0 + 1 : q.c0) - cmin)) * C;
+      atomicAdd(win + cell, fix_of(v[3 * k], ks, finite));
       if (C == 3) {
-        const float v1 = kk == 0 ? v[1] : (kk == 1 ? v[4] : (kk == 2 ? v[7] : v[10]));
-        const float v2 = kk == 0 ? v[2] : (kk == 1 ? v[5] : (kk == 2 ? v[8] : v[11]));
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-          int c = ch + rot;
-          c = c >= 3 ? c - 3 : c;
-          atomicAdd(win + cell + c, fix_of(c == 0 ? v0 : (c == 1 ? v1 : v2), ks, finite));
-        }
-      } else {
-        atomicAdd(win + cell, fix_of(v0, ks, finite));
+        atomicAdd(win + cell + 1, fix_of(v[3 * k + 1], ks, finite));
+        atomicAdd(win + cell + 2, fix_of(v[3 * k + 2], ks, finite));
       }
     }
   }
