@@ -244,15 +244,17 @@ __device__ __forceinline__ Lod lod_select(const Tex& t, float ux, float vx, floa
 struct TriSample {
   f3 val;
   f3 du, dv;       // d value / d(u, v)
+  f3 dl;           // value at level l0 + 1 minus value at l0 (zero without a second level)
 };
 __device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, const Lod& L) {
   Bil b0 = bil_footprint(t, L.l0, u, v);
   BilVal a = bil_eval(t, b0);
-  TriSample r{a.val, a.du, a.dv};
+  TriSample r{a.val, a.du, a.dv, mk(0.f, 0.f, 0.f)};
   if (L.has1) {
     Bil b1 = bil_footprint(t, L.l0 + 1, u, v);
     BilVal c = bil_eval(t, b1);
     float f = L.f;
+    r.dl = c.val - a.val;
     r.val = a.val + f * (c.val - a.val);
     r.du = a.du + f * (c.du - a.du);
     r.dv = a.dv + f * (c.dv - a.dv);

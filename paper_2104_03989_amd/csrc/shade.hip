@@ -333,53 +333,29 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
 
 // -------------------------------------------------------------- backward
 
-// Adjoint of one trilinear lookup: texel gradients (if gtex != NULL) and the
-// gradients w.r.t. (u, v) and the screen derivatives (ux, vx, uy, vy).
+// Adjoint of one trilinear lookup w.r.t. (u, v) and, through the LOD, the
+// screen derivatives (ux, vx, uy, vy), from the lookup's own derivatives
+// (its texel gradients go to the texel scatter as a sample record).
 struct UVGrad {
   float u, v, ux, vx, uy, vy;
 };
 
-__device__ __forceinline__ void scatter_bil(const Tex& t, float* gtex, const Bil& b, float wl, f3 gs) {
-  float fx = b.fx, fy = b.fy;
-  float w[4] = {(1.f - fx) * (1.f - fy), fx * (1.f - fy), (1.f - fx) * fy, fx * fy};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    f3 gq = (wl * w[q]) * gs;
-    if (t.channels == 3) atomic_add3(gtex, b.idx[q], gq);
-    else atomicAdd(gtex + b.idx[q], gq.x);
-  }
-}
-
-__device__ __forceinline__ void tex_bwd(const Tex& t, float* gtex, const PixelGeom& g,
-                                        const Lod& L, f3 gs, UVGrad& G) {
-  Bil b0 = bil_footprint(t, L.l0, g.u, g.v_);
-  BilVal a = bil_eval(t, b0);
-  f3 du = a.du, dvv = a.dv;
-  float w0 = 1.f;
-  if (L.has1) {
-    Bil b1 = bil_footprint(t, L.l0 + 1, g.u, g.v_);
-    BilVal c = bil_eval(t, b1);
-    float f = L.f;
-    du = a.du + f * (c.du - a.du);
-    dvv = a.dv + f * (c.dv - a.dv);
-    w0 = 1.f - f;
-    if (L.grad) {
-      // lod = 0.5 log2(m), m = max over x/y of |duv * size|^2
-      float g_m = dot(gs, c.val - a.val) * 0.5f / (L.m * 0.69314718055994531f);
-      float S2 = (float)t.size * (float)t.size;
-      if (L.use_x) {
-        G.ux += g_m * 2.f * g.ux * S2;
-        G.vx += g_m * 2.f * g.vx * S2;
-      } else {
-        G.uy += g_m * 2.f * g.uy * S2;
-        G.vy += g_m * 2.f * g.vy * S2;
-      }
+__device__ __forceinline__ void uv_bwd(const Tex& t, const PixelGeom& g, const Lod& L, const TriSample& r, f3 gs,
+                                       UVGrad& G) {
+  if (L.has1 && L.grad) {
+    // lod = 0.5 log2(m), m = max over x/y of |duv * size|^2
+    float g_m = dot(gs, r.dl) * 0.5f / (L.m * 0.69314718055994531f);
+    float S2 = (float)t.size * (float)t.size;
+    if (L.use_x) {
+      G.ux += g_m * 2.f * g.ux * S2;
+      G.vx += g_m * 2.f * g.vx * S2;
+    } else {
+      G.uy += g_m * 2.f * g.uy * S2;
+      G.vy += g_m * 2.f * g.vy * S2;
     }
-    if (gtex) scatter_bil(t, gtex, b1, f, gs);
   }
-  if (gtex) scatter_bil(t, gtex, b0, w0, gs);
-  G.u += dot(gs, du);
-  G.v += dot(gs, dvv);
+  G.u += dot(gs, r.du);
+  G.v += dot(gs, r.dv);
 }
 
 // ---- wave-aggregated texel-gradient scatter ----
@@ -638,9 +614,11 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   PixelGeom g;
   pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
-  f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
+  const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, Lk);
+  f3 kd = sk.val;
   Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
-  f3 nt = tex_trilinear(a.nm, g.u, g.v_, Ln).val;
+  const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, Ln);
+  f3 nt = sn.val;
   f3 mraw = nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N;
   f3 n = safe_normalize(mraw);
   f3 eye = ld3(a.v.eye, p.b);
@@ -650,27 +628,29 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   f3 E = ld3(a.v.light_rgb, p.b);
   f3 gn, gv, gkdv, gormv = mk(0.f, 0.f, 0.f);
   Lod Lo;
+  TriSample so;
   if (a.model == ADR_SHADE_GGX) {
     Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
-    f3 orm = tex_trilinear(a.orm, g.u, g.v_, Lo).val;
-    ggx_bwd(n, vdir, l, kd, orm, E, gc, gn, gv, gkdv, gormv);
+    so = tex_trilinear(a.orm, g.u, g.v_, Lo);
+    ggx_bwd(n, vdir, l, kd, so.val, E, gc, gn, gv, gkdv, gormv);
   } else {
     blinn_phong_bwd(n, vdir, l, kd, E, gc, gn, gv, gkdv);
   }
   // textures
   UVGrad G{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  tex_bwd(a.kd, nullptr, g, Lk, gkdv, G);
+  uv_bwd(a.kd, g, Lk, sk, gkdv, G);
   // normal map: n = normalize(nt.x T' + nt.y B + nt.z N)
   f3 gm = safe_normalize_bwd(mraw, gn);
   f3 gnt = mk(dot(gm, g.Tp), dot(gm, g.Bt), dot(gm, g.N));
-  tex_bwd(a.nm, nullptr, g, Ln, gnt, G);
-  if (a.model == ADR_SHADE_GGX) tex_bwd(a.orm, nullptr, g, Lo, gormv, G);
+  uv_bwd(a.nm, g, Ln, sn, gnt, G);
+  if (a.model == ADR_SHADE_GGX) uv_bwd(a.orm, g, Lo, so, gormv, G);
   if (ALPHA && a.al.data) {
     // alpha = clamp(t, 0, 1): the gradient passes where t is inside [0, 1]
     Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
-    const float t = tex_trilinear(a.al, g.u, g.v_, La).val.x;
+    const TriSample sa = tex_trilinear(a.al, g.u, g.v_, La);
+    const float t = sa.val.x;
     const f3 gal = mk(t >= 0.f && t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
-    tex_bwd(a.al, nullptr, g, La, gal, G);
+    uv_bwd(a.al, g, La, sa, gal, G);
     put_rec(ro, 3, La, gal, lv);
   }
   put_rec(ro, 0, Lk, gkdv, lv);
