@@ -118,8 +118,16 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False, tune=True):
-    """Upload the workload and return (step(t) closure, state)."""
+def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False, tune=True, ctx_ref=None):
+    """Upload the workload and return (step(t) closure, state).
+
+    With ctx_ref (a second context) the reference renders run on a stream of
+    their own, double-buffered: the reference of step t + 1 depends only on
+    that step's cameras, so it overlaps step t's backward and Adam; a
+    latent forward waits for its reference, and a reference render waits
+    until the latent forward that last read its buffer has run."""
+    overlap = ctx_ref is not None
+    rctx = ctx_ref if overlap else ctx
     ref_mesh = adr.DeviceMesh(w.ref.mesh)
     rig = None
     if w.rig is None:
@@ -205,8 +213,14 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     # nothing and the backward leaves the chains' adjoint to it
     sflag = lflag & ~adr.FWD_BUILD_MIPS
     bflag = sflag | (adr.BWD_DEFER_MIP_ADJOINT if maps else 0)
-    ref_out = adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], flags=dflag & adr.DETERMINISTIC)
-    ref_img = ref_out["image"] if k == 1 else adr.image_downsample(ctx, ref_out["image"], k)
+    nbuf = 2 if overlap else 1
+    ref_outs = [adr.render_fwd(rctx, ref_mesh, ref_mat, ref_views[0], flags=dflag & adr.DETERMINISTIC)
+                for _ in range(nbuf)]
+    ref_imgs = [o["image"] if k == 1 else adr.image_downsample(rctx, o["image"], k) for o in ref_outs]
+    ref_out, ref_img = ref_outs[0], ref_imgs[0]
+    s_ref = torch.cuda.Stream() if overlap else None         # default priority
+    ev_ref = [torch.cuda.Event() for _ in range(nbuf)]       # reference i rendered
+    ev_used = [torch.cuda.Event() for _ in range(nbuf)]      # latent forward read reference i
     L = w.oit_layers
     if L:
         # depth-peeled latent (order-independent transparency)
@@ -221,8 +235,8 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     split_ref = split_lat = DEFAULT
     if tune:
         tuner = Tuner()
-        split_ref = tuner.pick(ctx, "ref", int(w.ref.mesh.tri.shape[0]), B, W * k,
-                               lambda: adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[0], outputs=ref_out,
+        split_ref = tuner.pick(rctx, "ref", int(w.ref.mesh.tri.shape[0]), B, W * k,
+                               lambda: adr.render_fwd(rctx, ref_mesh, ref_mat, ref_views[0], outputs=ref_out,
                                                       flags=dflag & adr.DETERMINISTIC))
         if L:
             split_lat = tuner.pick(ctx, f"latent_peel{L}", int(lat_mesh.tri.shape[0]), B, W * w.msaa,
@@ -251,24 +265,41 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         g_lap = g_base if ts is not None else (rig["g_bind"] if rig is not None else grads["pos"])
         lap = (ring, base_pos, lams, g_lap)
 
+    def render_reference(t, i, stream):
+        if rig is not None:
+            adr.skin_fwd(rctx, rig["ref_bind"], rig["ref_w"], rig["bones"][t % n_frames], out=ref_mesh.pos,
+                         stream=stream)
+        rctx.set_raster(*split_ref)
+        adr.render_fwd(rctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_outs[i],
+                       flags=dflag & adr.DETERMINISTIC, stream=stream)
+        if k > 1:
+            adr.image_downsample(rctx, ref_outs[i]["image"], k, out=ref_imgs[i], stream=stream)
+
     def step(t):
         v = views[t % n_steps]
+        i = t % nbuf
+        cur = torch.cuda.current_stream()
+        if overlap:
+            s_ref.wait_event(ev_used[i])
+            render_reference(t, i, s_ref)
+            ev_ref[i].record(s_ref)
+            cur.wait_event(ev_ref[i])
+        else:
+            render_reference(t, i, None)
+        ref_img = ref_imgs[i]
         if ts is not None:
             adr.tess_fwd(ctx, ts, disp)
         if rig is not None:
             bones = rig["bones"][t % n_frames]
-            adr.skin_fwd(ctx, rig["ref_bind"], rig["ref_w"], bones, out=ref_mesh.pos)
             adr.skin_fwd(ctx, rig["bind"], rig["w"], bones, out=lat_mesh.pos, blend=rig["blend"])
-        ctx.set_raster(*split_ref)
-        adr.render_fwd(ctx, ref_mesh, ref_mat, ref_views[t % n_steps], outputs=ref_out, flags=dflag & adr.DETERMINISTIC)
         ctx.set_raster(*split_lat)
-        if k > 1:
-            adr.image_downsample(ctx, ref_out["image"], k, out=ref_img)
         if L:
             adr.render_oit_fwd(ctx, lat_mesh, lat_mat, v, L, ref=ref_img, loss=w.loss, flags=sflag, outputs=lat_out)
+            ev_used[i].record(cur)
             adr.render_oit_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=bflag)
         else:
             adr.render_fwd(ctx, lat_mesh, lat_mat, v, ref=ref_img, loss=w.loss, flags=sflag, outputs=lat_out)
+            ev_used[i].record(cur)
             adr.render_bwd(ctx, lat_mesh, lat_mat, v, lat_out, grads, flags=bflag)
         if ts is not None:
             adr.tess_bwd(ctx, ts, disp, grads["pos"], g_base, g_disp)
@@ -604,6 +635,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without stage events")
     ap.add_argument("--no-tune", action="store_true", help="default raster work split instead of the autotuner's")
+    ap.add_argument("--overlap", action="store_true",
+                    help="render each step's reference on a stream of its own, overlapping the previous step's "
+                         "backward and Adam (kernel times then include the concurrent work)")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-jobs", type=int, default=16)
@@ -637,9 +671,11 @@ def main():
     w, cfg = make_workload(args.workload)
     B, H, W = w.dirs.shape[0], w.height, w.width
     ctx = adr.Context(0)
+    ctx_ref = adr.Context(0) if args.overlap else None
+    ctxs = [c for c in (ctx, ctx_ref) if c is not None]
     n_steps = args.warmup + args.steps
     step, st = build_step(w, ctx, adr, torch, np, n_steps, seed=synth.seed_for(cfg, 100), det=args.deterministic,
-                          laplacian=args.laplacian, tune=not args.no_tune)
+                          laplacian=args.laplacian, tune=not args.no_tune, ctx_ref=ctx_ref)
     torch.cuda.synchronize()
     if w.oit_layers:
         covered = int(((st["lat_out"]["vis"] & 0xFFFFFFFF) != 0).sum())
@@ -654,19 +690,30 @@ def main():
     # In the timed region only the dominant single-kernel stage is bracketed,
     # for its roofline.
     stages, dom, n_prof = {}, None, 0
+    def read_stages():
+        # both contexts' spans, per stage (summed milliseconds, launches)
+        out = {}
+        for c in ctxs:
+            for k_, (ms_, cnt_) in c.profile_read().items():
+                a_, b_ = out.get(k_, (0.0, 0))
+                out[k_] = (a_ + ms_, b_ + cnt_)
+        return out
+
     if not args.no_profile:
-        ctx.profile(True)
-        ctx.profile_read()
+        for c in ctxs:
+            c.profile(True)
+        read_stages()
         n_prof = max(3, min(10, args.warmup))
         _log(f"profiled pass {n_prof}")
         for t in range(n_prof):
             step(t)
-        stages = ctx.profile_read()
+        stages = read_stages()
         cands = {k: v[0] for k, v in stages.items()
                  if v[1] > 0 and k in SINGLE_KERNEL_STAGES and algorithmic_bytes(k, w, st, covered) is not None}
         dom = max(cands, key=cands.get)
-        ctx.profile_stages([dom])
-        ctx.profile_read()
+        for c in ctxs:
+            c.profile_stages([dom])
+        read_stages()
     _log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -674,8 +721,9 @@ def main():
         step(t)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    timed = ctx.profile_read() if dom else {}
-    ctx.profile(False)
+    timed = read_stages() if dom else {}
+    for c in ctxs:
+        c.profile(False)
     loss = float(st["lat_out"]["loss"][0])
     ms_step = dt / args.steps * 1e3
     mpix = B * H * W * args.steps / dt / 1e6
@@ -714,13 +762,15 @@ def main():
                    "latent_tris": int(st["lat_mesh"].tri.shape[0]), "params": st["n_params"],
                    "gradient_mode": "deterministic" if args.deterministic else "atomic",
                    "laplacian": bool(args.laplacian), "raster_split": st["raster_split"],
+                   "reference_stream": "overlapped" if ctx_ref is not None else "same",
                    "final_loss": round(loss, 6)},
         "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
         "stage_gbs": stage_gbs,
         "stage_pass_steps": n_prof if stages else 0,
     }
     print(json.dumps(rec), flush=True)
-    ctx.close()
+    for c in ctxs:
+        c.close()
 
 
 if __name__ == "__main__":
