@@ -207,7 +207,11 @@ typedef struct adr_grads {
 /* Hand-written adjoint of adr_render_fwd w.r.t. vertex positions and F32
  * texels (Sec. 3: gradients of the loss w.r.t. the latent parameters).
  * saved: the adr_fwd_out of the forward call with the same arguments
- * (vis, color and dimage are read).  dloss: device [1] scale of the loss
+ * (vis, color and dimage are read).  When the context's previous call was
+ * that forward (same mesh, views, deterministic flag and stream, and
+ * saved->vis its out->vis), the vertex frame, snapped vertices and triangle
+ * orientations it left in the context's scratch are reused instead of
+ * recomputed; any other call in between makes the backward recompute them.  dloss: device [1] scale of the loss
  * gradient (NULL = 1).  Return values as adr_render_fwd. */
 adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
                           const adr_views* views, const adr_fwd_out* saved,

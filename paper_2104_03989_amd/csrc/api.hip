@@ -59,6 +59,19 @@ struct Span {
   int stage;
 };
 
+// What the geometry a forward leaves in the scratch (vertex frame and its
+// accumulators, snapped vertices, triangle orientations) was computed for.
+struct GeomKey {
+  const void *pos, *tri, *mvp, *vis;
+  int n_pos, n_tri, B, W, H, ms;
+  bool det;
+  hipStream_t st;
+  bool same(const GeomKey& o) const {
+    return pos == o.pos && tri == o.tri && mvp == o.mvp && vis == o.vis && n_pos == o.n_pos && n_tri == o.n_tri &&
+           B == o.B && W == o.W && H == o.H && ms == o.ms && det == o.det && st == o.st;
+  }
+};
+
 struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
@@ -69,11 +82,19 @@ struct adr_ctx {
   adr::JobServer* jobs = nullptr;
   uint32_t prof = 0;  // stages bracketed with events (bit per stage)
   int tiny_bbox = kTinyBBox, med_bbox = kMedBBox;  // raster work split
+  // set by a forward that computed the geometry in the scratch; cleared by
+  // every other call on the context
+  bool geom_ok = false;
+  GeomKey geom{};
   std::vector<Span> spans;
   std::vector<hipEvent_t> pool;
 };
 
 namespace {
+
+GeomKey geom_key(const MeshD& m, const ViewsD& v, const float* mvp, const void* vis, bool det, hipStream_t st) {
+  return GeomKey{m.pos, m.tri, mvp, vis, m.n_pos, m.n_tri, v.B, v.W, v.H, v.ms, det, st};
+}
 
 hipEvent_t take_event(adr_ctx* c) {
   if (!c->pool.empty()) {
@@ -206,6 +227,7 @@ adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* 
 
 adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool bwd, Scratch& s,
                            int tex_slots = 0, bool det = false) {
+  ctx->geom_ok = false;
   size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
   size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
   adr_status r;
@@ -385,7 +407,8 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
     TIMED(10, launch_mip_build_set(ms, st), "mip build");
   }
   int64_t npx = (int64_t)v.B * v.W * v.H;
-  if (mesh->nrm && mesh->tan) {
+  const bool own_frame = !(mesh->nrm && mesh->tan);
+  if (!own_frame) {
     s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
     s.tan = const_cast<float*>(mesh->tan);
   } else {
@@ -394,6 +417,12 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(1, launch_xform(m, v, s, st), "transform");
   TIMED(12, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
   TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
+  // the frame, snapped vertices and orientations now in the scratch (the
+  // raster writes every triangle's orientation) serve a backward that follows
+  if (own_frame) {
+    ctx->geom = geom_key(m, v, views->mvp, out->vis, (flags & ADR_DETERMINISTIC) != 0, st);
+    ctx->geom_ok = true;
+  }
   TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
   TIMED(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
                             (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st, out->aa),
@@ -422,14 +451,17 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   const bool det = (flags & ADR_DETERMINISTIC) != 0;
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  const bool reuse = ctx->geom_ok && ctx->geom.same(geom_key(m, v, views->mvp, saved->vis, det, st));
   Scratch s;
   if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm), det)) !=
       ADR_OK)
     return r;
   const int64_t n_clip = 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), n_attr = 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1);
-  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
-  TIMED(1, launch_xform(m, v, s, st), "transform");
-  TIMED(1, launch_orient(m, v, s, st), "orientation");
+  if (!reuse) {
+    TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+    TIMED(1, launch_xform(m, v, s, st), "transform");
+    TIMED(1, launch_orient(m, v, s, st), "orientation");
+  }
   {
     FillSet f{};
     f.add(s.fix_clip, n_clip);
@@ -518,13 +550,18 @@ adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
     }
     TIMED(10, launch_mip_build_set(ms, st), "mip build");
   }
-  if (mesh->nrm && mesh->tan) {
+  const bool own_frame = !(mesh->nrm && mesh->tan);
+  if (!own_frame) {
     s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
     s.tan = const_cast<float*>(mesh->tan);
   } else {
     TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
   }
   TIMED(1, launch_xform(m, v, s, st), "transform");
+  if (own_frame) {  // orientations: every peeling pass's raster writes them
+    ctx->geom = geom_key(m, v, views->mvp, out->vis, false, st);
+    ctx->geom_ok = true;
+  }
   const int64_t npx = (int64_t)v.B * v.W * v.H;
   const int L = out->n_layers;
   const int no_aa = (flags & ADR_FWD_NO_AA) ? 1 : 0;
@@ -569,6 +606,7 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   float* gal = has_al ? grads->alpha : nullptr;
+  const bool reuse = ctx->geom_ok && ctx->geom.same(geom_key(m, v, views->mvp, saved->vis, false, st));
   Scratch s;
   if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm, gal))) !=
       ADR_OK)
@@ -578,9 +616,11 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
   float* gbehind = (float*)ctx->oit_g.p;
   float* galpha = (float*)ctx->oit_a.p;
   const int64_t n_clip = 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), n_attr = 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1);
-  TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
-  TIMED(1, launch_xform(m, v, s, st), "transform");
-  TIMED(1, launch_orient(m, v, s, st), "orientation");
+  if (!reuse) {
+    TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
+    TIMED(1, launch_xform(m, v, s, st), "transform");
+    TIMED(1, launch_orient(m, v, s, st), "orientation");
+  }
   {
     FillSet f{};
     f.add(s.fix_clip, n_clip);
@@ -657,6 +697,7 @@ static adr_status check_tess(adr_ctx* ctx, const adr_mesh* base, const adr_tess*
 
 adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
                         const adr_texture* disp, float* pos_out, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   MeshD m;
   TessD ts;
   Tex d;
@@ -678,6 +719,7 @@ adr_status adr_tess_fwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
 adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess,
                         const adr_texture* disp, float* g_pos_out, float* g_base_pos,
                         float* g_disp, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   MeshD m;
   TessD ts;
   Tex d;
@@ -701,6 +743,7 @@ adr_status adr_tess_bwd(adr_ctx* ctx, const adr_mesh* base, const adr_tess* tess
 
 adr_status adr_mesh_frame(adr_ctx* ctx, const adr_mesh* mesh, float* nrm_out, float* tan_out,
                           adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !mesh) return fail(ADR_E_INVALID, "ctx and mesh are required");
   if (mesh->n_pos < 0 || mesh->n_tri < 0 || mesh->n_uv < 0) return fail(ADR_E_INVALID, "negative mesh size");
   if (mesh->n_pos > 0 && (!nrm_out || !tan_out)) return fail(ADR_E_INVALID, "nrm_out and tan_out are required");
@@ -724,6 +767,7 @@ adr_status adr_mesh_frame(adr_ctx* ctx, const adr_mesh* mesh, float* nrm_out, fl
 
 adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* pos, const float* delta_ref,
                          float lambda, float* delta_out, float* loss, float* g_pos, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !ring) return fail(ADR_E_INVALID, "ctx and ring are required");
   const int n = ring->n_pos;
   if (n < 0) return fail(ADR_E_INVALID, "negative vertex count");
@@ -743,6 +787,7 @@ adr_status adr_laplacian(adr_ctx* ctx, const adr_one_ring* ring, const float* po
 
 adr_status adr_image_downsample(adr_ctx* ctx, const float* in, int32_t n_views, int32_t height, int32_t width,
                                 int32_t k, float* out, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !in || !out) return fail(ADR_E_INVALID, "ctx, in and out are required");
   if (n_views < 1 || height < 1 || width < 1 || k < 1 || k > 64 || (int64_t)height * k > 65536 ||
       (int64_t)width * k > 65536)
@@ -762,6 +807,7 @@ static adr_status check_skin(adr_ctx* ctx, int32_t n_pos, int32_t n_bones) {
 
 adr_status adr_skin_fwd(adr_ctx* ctx, const float* pos, const float* weights, const float* bones, int32_t n_pos,
                         int32_t n_bones, float* pos_out, float* blend_out, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   adr_status r = check_skin(ctx, n_pos, n_bones);
   if (r != ADR_OK) return r;
   if (n_pos == 0) return ADR_OK;
@@ -774,6 +820,7 @@ adr_status adr_skin_fwd(adr_ctx* ctx, const float* pos, const float* weights, co
 
 adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, const float* blend, int32_t n_pos,
                         int32_t n_bones, float* g_pos_out, float* g_pos, float* g_weights, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   adr_status r = check_skin(ctx, n_pos, n_bones);
   if (r != ADR_OK) return r;
   if (n_pos == 0) return ADR_OK;
@@ -829,6 +876,7 @@ adr_status adr_ctx_profile_read(adr_ctx* ctx, double* ms, int64_t* count) {
 
 adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params, int32_t t,
                          float lr, float beta1, float beta2, float eps, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
   if (n_params < 0 || (n_params > 0 && !params)) return fail(ADR_E_INVALID, "bad params");
   if (t < 1) return fail(ADR_E_INVALID, "t must be >= 1");
@@ -847,6 +895,7 @@ adr_status adr_adam_step(adr_ctx* ctx, const adr_param* params, int32_t n_params
 
 adr_status adr_adam_step_maps(adr_ctx* ctx, const adr_map_param* maps, int32_t n_maps, int32_t t, float lr,
                               float beta1, float beta2, float eps, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
   if (n_maps < 0 || (n_maps > 0 && !maps)) return fail(ADR_E_INVALID, "bad maps");
   if (t < 1) return fail(ADR_E_INVALID, "t must be >= 1");
@@ -874,6 +923,7 @@ adr_status adr_adam_step_maps(adr_ctx* ctx, const adr_map_param* maps, int32_t n
 }
 
 adr_status adr_mip_build(adr_ctx* ctx, const adr_texture* tex, adr_stream stream) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !tex) return fail(ADR_E_INVALID, "ctx and tex are required");
   Tex t;
   adr_status r = check_tex(*tex, "tex", true, t);
@@ -959,6 +1009,7 @@ adr_status adr_views_build(const float* dirs, int32_t n, float dist, float fov_d
 }
 
 adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_id) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !desc || !job_id) return fail(ADR_E_INVALID, "ctx, desc and job_id are required");
   if (!ctx->jobs) {
     ctx->jobs = adr::jobs_create(ctx, ctx->device, ctx->budget);
@@ -971,6 +1022,7 @@ adr_status adr_job_submit(adr_ctx* ctx, const adr_job_desc* desc, uint64_t* job_
 }
 
 adr_status adr_job_poll(adr_ctx* ctx, uint64_t job_id, adr_job_status* st, adr_job_result* out) {
+  if (ctx) ctx->geom_ok = false;
   if (!ctx || !st) return fail(ADR_E_INVALID, "ctx and st are required");
   if (!ctx->jobs) return fail(ADR_E_NOTFOUND, "no jobs");
   char msg[256] = "";

@@ -104,3 +104,22 @@ def test_cached_antialiasing_stats_give_the_same_bits(ctx):
     b = gs.grads(dict(out, aa=None), ("pos", "kd", "normal"), flags=adr.DETERMINISTIC)
     for n in ("pos", "kd", "normal"):
         assert np.array_equal(a[n], b[n]), n
+
+
+def test_backward_reuses_or_recomputes_the_forward_geometry(ctx):
+    # the backward right after its forward reuses the geometry the forward
+    # left in the context's scratch; after another render on the context it
+    # recomputes it: the same bits either way (deterministic mode)
+    from paper_2104_03989_amd import adr
+    _say("geometry reuse")
+    w = synth.scaled(synth.workload_paper_loop(map_size=128, ref_nu=24, lat_nu=8), views=2, res=96)
+    gs = GpuScene(w, ctx)
+    ref = gs.render("reference", flags=adr.DETERMINISTIC)["image"]
+    names = ("pos", "kd", "normal")
+    out = gs.render("latent", ref=ref, flags=adr.DETERMINISTIC)
+    direct = gs.grads(out, names, flags=adr.DETERMINISTIC)
+    out2 = gs.render("latent", ref=ref, flags=adr.DETERMINISTIC)
+    gs.render("reference", flags=adr.DETERMINISTIC)
+    later = gs.grads(out2, names, flags=adr.DETERMINISTIC)
+    for n in names:
+        assert np.array_equal(direct[n].view(np.uint32), later[n].view(np.uint32)), n
