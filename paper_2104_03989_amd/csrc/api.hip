@@ -475,8 +475,8 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   TIMED(6, launch_shade_bwd(m, v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s,
                             saved->vis, st),
         "shading adjoint");
-  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, det, st), "accumulator conversion");
-  TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, det, st), "accumulator conversion");
+  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, det, st, s.fix_attr, s.dattr, n_attr),
+        "accumulator conversion");
   TIMED(11, launch_tex_bwd(v, mat->model, kd, nm, orm, grads->kd, grads->normal, grads->orm, s, st),
         "texel adjoint");
   {
@@ -649,8 +649,8 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
                              has_al ? &al : nullptr, gal),
           "texel adjoint");
   }
-  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, false, st), "accumulator conversion");
-  TIMED(12, launch_fix_to_f32(s.fix_attr, s.dattr, n_attr, false, st), "accumulator conversion");
+  TIMED(12, launch_fix_to_f32(s.fix_clip, s.dclip, n_clip, false, st, s.fix_attr, s.dattr, n_attr),
+        "accumulator conversion");
   {
     MipSet ms{};
     const Tex* maps[4] = {&kd, &nm, &orm, &al};

@@ -158,7 +158,9 @@ struct FillSet {
   }
 };
 hipError_t launch_fill_multi(const FillSet& f, hipStream_t st);
-hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st);
+// src2/dst2 (optional): a second array converted in the same launch.
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st,
+                             const unsigned long long* src2 = nullptr, float* dst2 = nullptr, int64_t n2 = 0);
 
 // Number of texture-gradient slots (maps with a gradient buffer).
 int tex_slots(int model, const float* gkd, const float* gnm, const float* gorm, const float* gal = nullptr);

@@ -93,11 +93,16 @@ __global__ void k_fill_multi(FillSet f) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.len[r]; i += stride) f.p[r][i] = 0ull;
 }
 
+// Two accumulator arrays converted in one launch (the second may be empty).
 __global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
+                             const unsigned long long* __restrict__ src2, float* __restrict__ dst2, int64_t n2,
                              bool det) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] = (float)acc_val(src[i], det);
+  for (; i < n + n2; i += stride) {
+    if (i < n) dst[i] = (float)acc_val(src[i], det);
+    else dst2[i - n] = (float)acc_val(src2[i - n], det);
+  }
 }
 
 __global__ void k_fix_add_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
@@ -129,9 +134,12 @@ hipError_t launch_fill_multi(const FillSet& f, hipStream_t st) {
 }
 
 
-hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n)), dim3(256), 0, st, src, dst, n, det);
+hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st,
+                             const unsigned long long* src2, float* dst2, int64_t n2) {
+  if (n < 0) n = 0;
+  if (n2 < 0 || !src2) n2 = 0;
+  if (n + n2 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n + n2)), dim3(256), 0, st, src, dst, n, src2, dst2, n2, det);
   return hipGetLastError();
 }
 
