@@ -275,11 +275,15 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
         if k > 1:
             adr.image_downsample(rctx, ref_outs[i]["image"], k, out=ref_imgs[i], stream=stream)
 
-    def step(t):
+    def step(t, with_reference=True):
+        """One step; without the reference render it reuses the reference
+        image already in its buffer (the latent-only rate)."""
         v = views[t % n_steps]
         i = t % nbuf
         cur = torch.cuda.current_stream()
-        if overlap:
+        if not with_reference:
+            pass
+        elif overlap:
             s_ref.wait_event(ev_used[i])
             render_reference(t, i, s_ref)
             ev_ref[i].record(s_ref)
@@ -727,6 +731,26 @@ def main():
     loss = float(st["lat_out"]["loss"][0])
     ms_step = dt / args.steps * 1e3
     mpix = B * H * W * args.steps / dt / 1e6
+    # the same steps without the reference render (latent forward, backward
+    # and Adam only, against the last reference images)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for t in range(args.warmup, n_steps):
+        step(t, with_reference=False)
+    torch.cuda.synchronize()
+    dt_lat = time.perf_counter() - t1
+    # a device copy of 1 GiB: the measured HBM ceiling beside the nominal one
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2.0 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
     roof = None
     prof, stage_step = {}, {}
     if stages:
@@ -740,7 +764,8 @@ def main():
         roof = {"bound": "hbm", "kernel": SINGLE_KERNEL_STAGES[dom][0], "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                 "traffic": pmc_traffic(args.workload, dom), "avg_launch_ms": round(avg_ms, 4),
-                "launches": cnt, "bytes_per_launch": by}
+                "launches": cnt, "bytes_per_launch": by,
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4)}
     # achieved GB/s of every stage with an algorithmic byte count (profiled pass)
     stage_gbs = {}
     for k, (ms_k, cnt_k) in stages.items():
@@ -754,6 +779,8 @@ def main():
     rec = {
         "metric": "fwd+bwd Mpix/s (latent pixels per second, reference render and Adam included)",
         "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "mpix_per_s_without_reference": round(B * H * W * args.steps / dt_lat / 1e6, 2),
+        "ms_per_step_without_reference": round(dt_lat / args.steps * 1e3, 3),
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "steps_per_s": round(1e3 / ms_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
