@@ -3,12 +3,14 @@
 Every mesh keeps its own device state (meshes, maps, gradients, Adam state,
 the cameras and lights of every step).  One step renders each mesh's
 reference and latent views, scores the image loss and back-propagates
-(Sec. 3, Eq. 1), then one Adam launch updates the parameters of all meshes
-(Sec. 5.3).  The batched form captures the forward and backward launches of
-all meshes once as a HIP graph (through torch.cuda.CUDAGraph), spread over
-several streams, each with its own library context, so that the graph runs
-small meshes concurrently; a step is then a copy of that step's cameras into
-the buffers the graph reads, one graph launch and one Adam launch.  The
+(Sec. 3, Eq. 1), then Adam updates the parameters of all meshes (Sec. 5.3):
+one launch over every mesh's positions, and the maps four per launch with
+their mip chains' adjoint and rebuild fused in.  The batched form captures
+the forward and backward launches of all meshes once as a HIP graph
+(through torch.cuda.CUDAGraph), spread over several streams, each with its
+own library context, so that the graph runs small meshes concurrently; a
+step is then a copy of that step's cameras into the buffers the graph
+reads, one graph launch and the Adam launches.  The
 plain form steps the same meshes one at a time, each with its own launches.
 The rasterizer's work split of each mesh's renders comes from the autotuner.
 """
@@ -45,12 +47,16 @@ class MeshState:
         self.det = adr.DETERMINISTIC if det else 0
         self.grads = {"pos": torch.zeros_like(self.lat_mesh.pos) if "pos" in w.optimize else None}
         params = [(self.lat_mesh.pos, self.grads["pos"])] if self.grads["pos"] is not None else []
+        # mip-mapped maps: Adam fused with the chain's adjoint and rebuild
+        # (the backward defers the adjoint; the forward needs no rebuild)
+        self.maps = []
         for name in ("kd", "normal", "orm"):
             tex = getattr(self.lat_mat, name)
             if name in w.optimize and tex is not None and tex.fmt == adr.TEX_F32:
                 self.grads[name] = tex.grad_buffer()
                 n0 = tex.size * tex.size
-                params.append((tex.data[:n0], self.grads[name][:n0]))
+                self.maps.append((tex, self.grads[name], torch.zeros_like(tex.data[:n0]),
+                                  torch.zeros_like(tex.data[:n0])))
             else:
                 self.grads[name] = None
         self.params = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
@@ -70,14 +76,14 @@ class MeshState:
     def render_latent(self, ctx, stream=None):
         ctx.set_raster(*self.split_lat)
         self.lat_out = adr.render_fwd(ctx, self.lat_mesh, self.lat_mat, self.views, ref=self.ref_out["image"],
-                                      loss=self.w.loss, flags=adr.FWD_BUILD_MIPS | self.det, want_image=False,
+                                      loss=self.w.loss, flags=self.det, want_image=False,
                                       outputs=self.lat_out, stream=stream)
 
     def fwd_bwd(self, ctx, stream=None):
         self.render_ref(ctx, stream)
         self.render_latent(ctx, stream)
-        adr.render_bwd(ctx, self.lat_mesh, self.lat_mat, self.views, self.lat_out, self.grads, flags=self.det,
-                       stream=stream)
+        adr.render_bwd(ctx, self.lat_mesh, self.lat_mat, self.views, self.lat_out, self.grads,
+                       flags=self.det | adr.BWD_DEFER_MIP_ADJOINT, stream=stream)
 
     def loss(self) -> float:
         return float(self.lat_out["loss"][0])
@@ -115,11 +121,13 @@ class Batch:
                 m.tune(self.ctxs[0], tuner)
             tuner.save()
         self.all_params = [p for m in self.meshes for p in m.params]
+        self.all_maps = [mp for m in self.meshes for mp in m.maps]
         self.graph = None
         self.lr = workloads[0].lr
 
     def _adam(self, t: int):
         adr.adam_step(self.ctxs[0], self.all_params, t + 1, lr_at(self.lr, t))
+        adr.adam_step_maps(self.ctxs[0], self.all_maps, t + 1, lr_at(self.lr, t))
 
     def _launch_all(self):
         cur = torch.cuda.current_stream()
@@ -163,6 +171,7 @@ class Batch:
             m.load_views(t)
             m.fwd_bwd(ctx)
             adr.adam_step(ctx, m.params, t + 1, lr)
+            adr.adam_step_maps(ctx, m.maps, t + 1, lr)
 
     def losses(self):
         return [m.loss() for m in self.meshes]

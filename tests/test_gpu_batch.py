@@ -1,6 +1,7 @@
 """Batched stepping of uneven meshes: the graph-captured batch (all meshes'
 forward and backward over four streams, replayed step after step with the
-cameras of each step copied in, and one Adam launch over every mesh) gives
+cameras of each step copied in, then Adam over every mesh's positions and
+maps, the maps' mip chains adjoined and rebuilt in the same kernel) gives
 the same losses and parameters as stepping the meshes one at a time: bit for
 bit in deterministic mode, at every replay, and within float tolerance with
 atomics.  The autotuner picks and caches a work split per shape bucket."""
@@ -28,7 +29,8 @@ def _workloads(n=5):
 def _state(b):
     out = []
     for m in b.meshes:
-        out.append([p.detach().cpu().numpy().copy() for p, _, _, _ in m.params])
+        out.append([p.detach().cpu().numpy().copy() for p, _, _, _ in m.params] +
+                   [tex.data.detach().cpu().numpy().copy() for tex, _, _, _ in m.maps])
     return out
 
 
