@@ -42,16 +42,41 @@ SINGLE_KERNEL_STAGES = {
 COMMON_SOURCES = ["dev.h", "internal.h"]
 
 
+def _code_only(text):
+    """C++ source without comments and with whitespace runs collapsed (string
+    literals kept as they are): an edit of comments or layout leaves it."""
+    import re
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"':                                       # string literal
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
 def kernel_sources_sha(files):
-    """sha256 over a kernel's source files and the shared headers."""
+    """sha256 over a kernel's source files and the shared headers, comments
+    and layout stripped (a change of the code itself voids stored counters)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2104_03989_amd", "csrc")
-    for f in list(files) + COMMON_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(ROOT, "include", "adr.h"), "rb") as fh:
-        h.update(fh.read())
+    paths = [os.path.join(csrc, f) for f in list(files) + COMMON_SOURCES] + [os.path.join(ROOT, "include", "adr.h")]
+    for path in paths:
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -365,9 +365,11 @@ __device__ __forceinline__ void uv_bwd(const Tex& t, const PixelGeom& g, const L
 // the wave touches roughly (8+1)^2 texels of a level where its lanes would
 // issue 64 x 4 atomics per channel.  Per level present in the wave, the
 // lanes' contributions are summed into an LDS window covering the wave's
-// footprint (LDS atomics), and the window's nonzero texel-channels are then
-// added to HBM once each.  A footprint larger than the window (a UV seam,
-// very oblique sampling) falls back to direct atomics.
+// footprint (integer LDS atomics on fixed-point values, see window_pass), and
+// the window's nonzero texel-channels are then added to HBM once each.  A
+// footprint larger than the window (a UV seam, very oblique sampling,
+// depth-peeled layers) is taken in groups of lanes whose cells fit a box of
+// the window's size, one window pass per group.
 
 constexpr int kWinTex = 1024;  // window entries per wave: e.g. 18 x 18 texels x 3 channels
 
