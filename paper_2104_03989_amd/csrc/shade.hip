@@ -371,7 +371,15 @@ __device__ __forceinline__ void uv_bwd(const Tex& t, const PixelGeom& g, const L
 // depth-peeled layers) is taken in groups of lanes whose cells fit a box of
 // the window's size, one window pass per group.
 
-constexpr int kWinTex = 1024;  // window entries per wave: e.g. 18 x 18 texels x 3 channels
+// Window entries per wave: 14 x 14 texels x 3 channels fit; 4 waves' windows
+// take 20 KB of LDS, so 8 blocks (8 waves per SIMD) are resident per CU.
+constexpr int kWinTex = 640;
+// side of the largest square box of texels whose window fits kWinTex entries
+constexpr int win_side(int C) {
+  int s = 1;
+  while ((s + 1) * (s + 1) * C <= kWinTex) ++s;
+  return s;
+}
 
 struct TexScatter {
   float u, v;
@@ -529,7 +537,7 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
   const int BIG = 1 << 20;
   const int lane = threadIdx.x & 63;
   const int C = t.channels;
-  const int side = C == 3 ? 18 : 32;   // side^2 C <= kWinTex
+  const int side = C == 3 ? win_side(3) : win_side(1);  // side^2 C <= kWinTex
   bool done0 = !act, done1 = !(act && ts.has1);
   while (true) {
     int my = min(done0 ? BIG : ts.l0, done1 ? BIG : ts.l0 + 1);
