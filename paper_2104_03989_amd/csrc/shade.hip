@@ -437,7 +437,8 @@ __device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
 
 // Accumulates the contributions of the selected lanes (sel) at one level
 // into an LDS window over their footprint (at most kWinTex entries), then
-// adds the window's nonzero texel-channels to HBM.  Converged code.
+// adds the window's nonzero texel-channels to HBM and clears them, so the
+// window is all zero again (it starts zeroed).  Converged code.
 //
 // The window sums in 64-bit fixed point: the pass scales every contribution
 // by 2^k, k chosen from the largest magnitude in the wave so that each
@@ -461,7 +462,6 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   const int C = t.channels;
   const int ww = cmax - cmin + 1;
   const int n = (rmax - rmin + 1) * ww * C;
-  for (int k = lane; k < n; k += 64) win[k] = 0ull;
   // Per lane 4 corners x 3 channels.  (Merging lanes that share a bilinear
   // cell with DPP moves before the atomics paid off with float LDS atomics;
   // with integer ones it costs more than it saves.)
@@ -506,6 +506,7 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
     for (int k = lane; k < n; k += 64) {
       const long long sum = (long long)win[k];
       if (sum != 0) {
+        win[k] = 0ull;
         const float val = finite ? ldexpf((float)sum, -ks) : __int_as_float(0x7FC00000);
         const int texel = C == 3 ? k / 3 : k, ch = k - texel * C;
         int rr = (int)((float)texel * inv_ww);
@@ -853,6 +854,7 @@ __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
   float4 r0 = p.ok ? a.rec[o] : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
   const uint32_t lv = __float_as_uint(r0.z);
   WinT* win = win_all[threadIdx.x >> 6];
+  for (int k = threadIdx.x & 63; k < kWinTex; k += 64) win[k] = 0ull;
   for (int k = 0; k < a.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
