@@ -37,6 +37,7 @@ SINGLE_KERNEL_STAGES = {
     "aa_bwd": ("adr::k_aa_bwd", ["aa.hip"]),
     "shade": ("adr::k_shade_fwd", ["shade.hip"]),
     "adam": ("adr::k_adam", ["adam.hip"]),
+    "adam_maps": ("adr::k_adam_maps_tiles", ["tex.hip"]),
     "skin_bwd": ("adr::k_skin_bwd", ["skin.hip"]),
 }
 COMMON_SOURCES = ["dev.h", "internal.h"]
@@ -227,9 +228,14 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
     adam = [(p, gr, torch.zeros_like(p), torch.zeros_like(p)) for p, gr in params]
     n_params = sum(p.numel() for p, _ in params) + sum(m.numel() for _, _, m, _ in maps)
     n_map_params = sum(m.numel() for _, _, m, _ in maps)
-    # map Adam: 32 B per level-0 float as Adam, plus per float of levels >= 1
-    # the gradient read and cleared and the rebuilt texel written
-    map_adam_bytes = sum(32 * m.numel() + 12 * (tex.data.numel() - m.numel()) for tex, _, m, _ in maps)
+    # map Adam's tile kernel: 32 B per level-0 float as Adam, plus per float
+    # of the levels inside a 32x32 level-0 tile (1..5) the gradient read and
+    # cleared and the rebuilt texel written (the levels above the tiles, a
+    # second small launch, are not counted)
+    def tile_level_floats(tex, m):
+        c = m.numel() // (tex.size * tex.size)
+        return c * sum((tex.size >> l) ** 2 for l in range(1, 6) if tex.size >> l)
+    map_adam_bytes = sum(32 * m.numel() + 12 * tile_level_floats(tex, m) for tex, _, m, _ in maps)
     dflag = adr.DETERMINISTIC if det else 0
     if w.msaa > 1:
         dflag |= adr.MSAA_4X4 if w.msaa == 4 else adr.MSAA_2X2

@@ -421,9 +421,11 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * 5 antialias adjoint, 6 shade adjoint, 7 mip adjoint, 8 mesh adjoint,
  * 9 adam, 10 mip build, 11 texel adjoint, 12 buffer clears and
  * conversions, 13 skinning, 14 skinning adjoint, 15 layer blending and its
- * adjoint (depth peeling), 16 map Adam with the chain's adjoint and
- * rebuild (adr_adam_step_maps).  ms and count: host arrays of ADR_N_STAGES. */
-#define ADR_N_STAGES 17
+ * adjoint (depth peeling), 16 map Adam over level 0 with the adjoint and
+ * rebuild of the levels inside its 32x32 tiles, 17 the levels above the
+ * tiles (both adr_adam_step_maps).  ms and count: host arrays of
+ * ADR_N_STAGES. */
+#define ADR_N_STAGES 18
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 /* As adr_ctx_profile for the stages whose bits (1 << stage) are set in
  * stage_mask, the others untimed (0 disables).  Each bracketed stage stalls

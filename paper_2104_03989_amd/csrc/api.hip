@@ -917,7 +917,8 @@ adr_status adr_adam_step_maps(adr_ctx* ctx, const adr_map_param* maps, int32_t n
       a.m[a.ms.n] = maps[k].m;
       a.v[a.ms.n++] = maps[k].v;
     }
-    TIMED(16, launch_adam_maps(a, t, lr, beta1, beta2, eps, st), "map adam");
+    TIMED(16, launch_adam_maps_tiles(a, t, lr, beta1, beta2, eps, st), "map adam");
+    TIMED(17, launch_adam_maps_top(a, st), "map adam (upper levels)");
   }
   return ADR_OK;
 }

@@ -180,7 +180,11 @@ hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, fl
                            float* gvnormal, hipStream_t st, bool pos_cleared = false);
 hipError_t launch_mip_build(const Tex& t, hipStream_t st);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
-hipError_t launch_adam_maps(const AdamMapSet& a, int t, float lr, float b1, float b2, float eps, hipStream_t st);
+// Map Adam in two launches: the level-0 tiles (adjoint of the tile levels,
+// Adam, rebuild of the tile levels), then the levels above the tiles.
+hipError_t launch_adam_maps_tiles(const AdamMapSet& a, int t, float lr, float b1, float b2, float eps,
+                                  hipStream_t st);
+hipError_t launch_adam_maps_top(const AdamMapSet& a, hipStream_t st);
 hipError_t launch_adam(const adr_param* params, int n, int t, float lr, float b1, float b2,
                        float eps, hipStream_t st);
 
