@@ -151,6 +151,19 @@ __device__ __forceinline__ Pix tile_pixel(int tile, int tid, int tiles_x, int ti
   return p;
 }
 
+// Nontemporal float4 accesses (the streaming cache policy) for data that is
+// touched once per step or handed to the next kernel only: they keep such
+// streams from evicting the working sets of the other kernels.
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4* p) {
+  const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float4* p, float4 x) {
+  const nt_f4 v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<nt_f4*>(p));
+}
+
 // ---- textures ----
 
 __device__ __forceinline__ f3 tex_fetch(const Tex& t, int texel) {

@@ -601,7 +601,7 @@ __device__ __forceinline__ void put_rec(const RecOut& ro, int m, const Lod& L, f
   if (sl < 0) return;
   lv &= ~(0xFFu << (8 * sl));
   lv |= (uint32_t)L.l0 << (8 * sl);
-  ro.rec[(1 + sl) * ro.P + ro.o] = make_float4(gs.x, gs.y, gs.z, L.has1 ? L.f : 0.f);
+  st_nt(ro.rec + (1 + sl) * ro.P + ro.o, make_float4(gs.x, gs.y, gs.z, L.has1 ? L.f : 0.f));
 }
 
 // Adjoint of one pixel.  The vertex gradients are written to the pixel's
@@ -829,7 +829,8 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   uint32_t lv = 0xFFFFFFFFu;
   float u = 0.f, v = 0.f;
   bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, table + (threadIdx.x & 63), tri, vtx, ro, lv, u, v);
-  if (p.ok && sl.n > 0) rec[o] = make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), 0.f);
+  if (p.ok && sl.n > 0)
+    st_nt(rec + o, make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), 0.f));
   wave_vertex_scatter(a, p.b, act, tri, vtx, table, fclip, fattr, det);
 }
 
@@ -851,14 +852,14 @@ __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
   const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
-  float4 r0 = p.ok ? a.rec[o] : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
+  float4 r0 = p.ok ? ld_nt(a.rec + o) : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
   const uint32_t lv = __float_as_uint(r0.z);
   WinT* win = win_all[threadIdx.x >> 6];
   for (int k = threadIdx.x & 63; k < kWinTex; k += 64) win[k] = 0ull;
   for (int k = 0; k < a.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
-    float4 rk = act ? a.rec[(1 + k) * P + o] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 rk = act ? ld_nt(a.rec + (1 + k) * P + o) : make_float4(0.f, 0.f, 0.f, 0.f);
     TexScatter ts{r0.x, r0.y, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
     wave_scatter_tex(a.t[k], a.g[k], act, ts, win);
   }

@@ -276,19 +276,6 @@ __global__ __launch_bounds__(256) void k_mip_adjoint_tiles(MipSet ms) {
 // build launched one after another.
 constexpr int kTileF4 = kMipTile * kMipTile * 3 / 4 / 256;  // float4 per thread of a 32^2 x 3 tile
 
-// Streaming float4 accesses for the level-0 Adam streams: every byte is
-// read and written once per step and the step moves far more than the
-// caches hold, so the accesses carry the nontemporal hint.
-typedef float nv4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ntld(const float* p) {
-  const nv4 v = __builtin_nontemporal_load(reinterpret_cast<const nv4*>(p));
-  return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void ntst(float* p, float4 x) {
-  const nv4 v = {x.x, x.y, x.z, x.w};
-  __builtin_nontemporal_store(v, reinterpret_cast<nv4*>(p));
-}
-
 __global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1, float b2, float c1, float c2,
                                                          float lr, float eps) {
   const Tex& t = a.ms.t[blockIdx.y];
@@ -317,10 +304,10 @@ __global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1,
     if (e < n4) {
       const int r = e / w4, x4 = e - r * w4;
       const int64_t q = r * gs + 4 * x4;
-      p4[u] = ntld(P + q);
-      g4[u] = ntld(G + q);
-      m4[u] = ntld(M + q);
-      v4[u] = ntld(V + q);
+      p4[u] = ld_nt(reinterpret_cast<const float4*>(P + q));
+      g4[u] = ld_nt(reinterpret_cast<const float4*>(G + q));
+      m4[u] = ld_nt(reinterpret_cast<const float4*>(M + q));
+      v4[u] = ld_nt(reinterpret_cast<const float4*>(V + q));
     }
   }
   if (L > 0) tile_fold_grads(t, g, by, bx, T, L, pyr);
@@ -344,10 +331,10 @@ __global__ __launch_bounds__(256) void k_adam_maps_tiles(AdamMapSet a, float b1,
       adam1(p4[u].y, gg[1], m4[u].y, v4[u].y, b1, b2, c1, c2, lr, eps);
       adam1(p4[u].z, gg[2], m4[u].z, v4[u].z, b1, b2, c1, c2, lr, eps);
       adam1(p4[u].w, gg[3], m4[u].w, v4[u].w, b1, b2, c1, c2, lr, eps);
-      ntst(P + q, p4[u]);
-      ntst(M + q, m4[u]);
-      ntst(V + q, v4[u]);
-      ntst(G + q, make_float4(0.f, 0.f, 0.f, 0.f));
+      st_nt(reinterpret_cast<float4*>(P + q), p4[u]);
+      st_nt(reinterpret_cast<float4*>(M + q), m4[u]);
+      st_nt(reinterpret_cast<float4*>(V + q), v4[u]);
+      st_nt(reinterpret_cast<float4*>(G + q), make_float4(0.f, 0.f, 0.f, 0.f));
       *reinterpret_cast<float4*>(base + r * w + 4 * x4) = p4[u];
     }
   }
