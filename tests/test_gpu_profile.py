@@ -37,3 +37,30 @@ def test_profile_stage_mask():
         torch.cuda.synchronize()
     finally:
         ctx.close()
+
+
+def test_profile_map_adam_stages():
+    """The map Adam is timed as two stages: the level-0 tiles and the levels
+    above them; each names its own launch."""
+    import numpy as np
+    from paper_2104_03989_amd import adr
+    ctx = adr.Context(0)
+    try:
+        S, C, levels = 128, 3, 8          # levels 6 and 7 lie above the 32x32 tiles
+        g = np.random.default_rng(11)
+        tex = adr.DeviceTexture(g.normal(size=(S, S, C)).astype(np.float32), "f32", levels=levels, ctx=ctx)
+        gd = torch.from_numpy(g.normal(size=tex.data.shape).astype(np.float32)).cuda()
+        md = torch.zeros(S * S, C, device="cuda")
+        vd = torch.zeros(S * S, C, device="cuda")
+        ctx.profile_stages(["adam_maps", "adam_maps_top"])
+        ctx.profile_read()
+        adr.adam_step_maps(ctx, [(tex, gd, md, vd)], 1, 1e-3)
+        got = ctx.profile_read()
+        assert got["adam_maps"][1] == 1 and got["adam_maps_top"][1] == 1, got
+        assert got["adam_maps"][0] > 0.0 and got["adam_maps_top"][0] > 0.0, got
+        assert all(cnt == 0 for k, (_, cnt) in got.items() if k not in ("adam_maps", "adam_maps_top")), got
+        assert float(gd.abs().max()) == 0.0      # the whole gradient chain is cleared
+        ctx.profile(False)
+        torch.cuda.synchronize()
+    finally:
+        ctx.close()
