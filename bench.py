@@ -716,6 +716,7 @@ def main():
         covered = int(((st["lat_out"]["vis"] & 0xFFFFFFFF) != 0).sum())
     else:
         covered = int((st["lat_out"]["tri_id"] > 0).sum()) // (w.msaa * w.msaa)
+        st["lat_out"]["tri_id"] = None     # read for the count above only: the steps do not write it
     _log(f"warmup {args.warmup}")
     for t in range(args.warmup):
         step(t)
