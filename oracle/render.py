@@ -335,22 +335,50 @@ def shade_blinn_phong(n, l, v, kd, light_rgb):
     return light_rgb * diff * (kd + spec)
 
 
+def specular_colour(kd, gamma, metal):
+    """Sec. 5.2: k_s = (1 - m) 0.04 + m k_d, and k_s' = (1 - gamma) k_s, the
+    specular colour scaled down by the specular-occlusion map gamma."""
+    ks = (1.0 - metal) * 0.04 + metal * kd
+    return (1.0 - gamma) * ks
+
+
+def ggx_ndf(nh, alpha):
+    """GGX / Trowbridge-Reitz normal distribution of half vectors at cosine
+    nh = n.h (reading: the Karis 2013 form the paper cites for its shading
+    model), D = alpha^2 / (pi ((n.h)^2 (alpha^2 - 1) + 1)^2)."""
+    a2 = alpha * alpha
+    return a2 / (math.pi * (nh * nh * (a2 - 1.0) + 1.0) ** 2)
+
+
+def smith_g1_schlick(x, alpha):
+    """Schlick's approximation of Smith's masking term for one direction at
+    cosine x, G1(x) = x / (x (1 - k) + k), with k = alpha / 2 (reading: the
+    Karis 2013 remap, chosen to match the Smith GGX term)."""
+    k = alpha * 0.5
+    return x / (x * (1.0 - k) + k)
+
+
+def fresnel_schlick(f0, vh):
+    """Schlick's Fresnel: F = F0 + (1 - F0) (1 - v.h)^5."""
+    return f0 + (1.0 - f0) * (1.0 - vh) ** 5
+
+
 def shade_ggx(n, l, v, kd, orm, light_rgb):
+    """Diffuse + GGX specular under one directional light (Sec. 5.2 gives the
+    specular colour; the microfacet terms are the readings above):
+    c = E (k_d (1 - m) / pi + D F G / (4 max(n.l,1e-4) max(n.v,1e-4))) max(0, n.l),
+    roughness clamped to [0.08, 1] and alpha = r^2."""
     gamma, rough, metal = orm[:, 0:1], orm[:, 1:2], orm[:, 2:3]
     r = torch.clamp(rough, 0.08, 1.0)
     alpha = r * r
-    a2 = alpha * alpha
     h = safe_normalize(l + v)
     nl = torch.clamp(_dot(n, l), min=0.0)
     nv = torch.clamp(_dot(n, v), min=1e-4)
     nh = torch.clamp(_dot(n, h), min=0.0)
     vh = torch.clamp(_dot(v, h), min=0.0)
-    D = a2 / (math.pi * (nh * nh * (a2 - 1.0) + 1.0) ** 2)
-    k = alpha * 0.5
-    G = (nl / (nl * (1.0 - k) + k)) * (nv / (nv * (1.0 - k) + k))
-    ks = (1.0 - metal) * 0.04 + metal * kd
-    F0 = (1.0 - gamma) * ks
-    F = F0 + (1.0 - F0) * (1.0 - vh) ** 5
+    D = ggx_ndf(nh, alpha)
+    G = smith_g1_schlick(nl, alpha) * smith_g1_schlick(nv, alpha)
+    F = fresnel_schlick(specular_colour(kd, gamma, metal), vh)
     spec = D * F * G / (4.0 * torch.clamp(nl, min=1e-4) * nv)
     diffuse = kd * (1.0 - metal) / math.pi
     return light_rgb * (diffuse + spec) * nl
@@ -516,6 +544,18 @@ def texture_levels(tex_data: np.ndarray, fmt: str, param: torch.Tensor | None = 
     return mip_chain_f32(base)
 
 
+def screen_derivatives(k, lam, S, W, H):
+    """Derivatives of the perspective-correct barycentrics w.r.t. the pixel
+    coordinates.  With D_i = k_i . (px, py, 1) and lambda_i = D_i / sum D,
+    d lambda_i / d px = (k_ix - lambda_i sum_j k_jx) / sum D, and one pixel
+    step moves the NDC coordinate by 2/W in x (2/H in y)."""
+    Ka = k[:, :, 0].sum(1, keepdim=True)
+    Kb = k[:, :, 1].sum(1, keepdim=True)
+    dlam_dx = (k[:, :, 0] - lam * Ka) / S * (2.0 / W)
+    dlam_dy = (k[:, :, 1] - lam * Kb) / S * (2.0 / H)
+    return dlam_dx, dlam_dy
+
+
 def shade_view(keys, tri, uv, uv_tri, pos, nrm, tan, clip, model, kd_levels, nrm_levels, orm_levels,
                eye_b, light_dir_b, light_rgb_b, W, H, m=1, alpha_levels=None, keep_gbuf=False):
     """Deferred shading of one view's visibility samples (Sec. 5.2): the
@@ -544,10 +584,7 @@ def shade_view(keys, tri, uv, uv_tri, pos, nrm, tan, clip, model, kd_levels, nrm
         D = k[:, :, 0] * px[:, None] + k[:, :, 1] * py[:, None] + k[:, :, 2]
         S = D.sum(1, keepdim=True)
         lam = D / S
-        Ka = k[:, :, 0].sum(1, keepdim=True)
-        Kb = k[:, :, 1].sum(1, keepdim=True)
-        dlam_dx = (k[:, :, 0] - lam * Ka) / S * (2.0 / W)
-        dlam_dy = (k[:, :, 1] - lam * Kb) / S * (2.0 / H)
+        dlam_dx, dlam_dy = screen_derivatives(k, lam, S, W, H)
         def interp(attr, idx):
             return (lam[:, :, None] * attr[idx]).sum(1)
         x = interp(pos, corners)
