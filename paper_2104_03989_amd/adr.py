@@ -427,13 +427,32 @@ def adam_step_maps(ctx: Context, maps: list, t: int, lr: float, beta1=0.9, beta2
 class RenderLoss(torch.autograd.Function):
     """Image loss of a latent render against a reference image; the backward
     is adr_render_bwd.  Differentiable inputs: pos [V,3], and the level-0
-    slices of the F32 maps ``kd``, ``normal``, ``orm``.
+    slices of the F32 maps ``kd``, ``normal``, ``orm`` (``tex.level0`` of the
+    material's textures, so that the render reads the tensors autograd
+    tracks; pass FWD_BUILD_MIPS when level 0 changed since the chain was
+    built).  The gradient of a map is w.r.t. its level-0 texels with the
+    coarser levels derived from them, so the flags that keep per-level
+    gradients (INDEPENDENT_MIPS, BWD_DEFER_MIP_ADJOINT) are rejected.
     forward(pos, kd0, normal0, orm0, ctx, mesh, mat, views, ref, loss, flags)."""
 
     @staticmethod
     def forward(fctx, pos, kd0, normal0, orm0, ctx, mesh, mat, views, ref, loss, flags):
+        if flags & (INDEPENDENT_MIPS | BWD_DEFER_MIP_ADJOINT):
+            raise ValueError("RenderLoss differentiates level 0 of derived mip chains: "
+                             "INDEPENDENT_MIPS and BWD_DEFER_MIP_ADJOINT are not supported")
+        for name, t in (("kd", kd0), ("normal", normal0), ("orm", orm0)):
+            if t is None:
+                continue
+            tex = getattr(mat, name)
+            if tex is None:
+                raise ValueError(f"RenderLoss: the material has no {name} map")
+            if tex.fmt != TEX_F32:
+                raise ValueError(f"RenderLoss: {name} is not an F32 map and cannot be differentiated")
+            lv0 = tex.level0
+            if t.data_ptr() != lv0.data_ptr() or t.shape != lv0.shape:
+                raise ValueError(f"RenderLoss: {name}0 must be mat.{name}.level0 (the tensor the render reads)")
         out = render_fwd(ctx, mesh, mat, views, ref=ref, loss=loss, flags=flags, pos=pos, want_image=False)
-        fctx.state = (ctx, mesh, mat, views, flags, out)
+        fctx.state = (ctx, mesh, mat, views, flags & ~FWD_BUILD_MIPS, out)
         fctx.save_for_backward(pos)
         return out["loss"][0].clone()
 

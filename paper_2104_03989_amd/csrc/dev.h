@@ -178,24 +178,41 @@ __device__ __forceinline__ f3 tex_fetch(const Tex& t, int texel) {
   return {v, 0.f, 0.f};
 }
 
-// Bilinear footprint of (u, v) at level l: four texel indices and weights.
+// Texture coordinates travel as float32 pairs (u, ul) with u + ul the
+// coordinate to about float64 precision: on a 2048^2 map one float32 unit of
+// u is 1.2e-4 texels, which moves a lookup of a high-frequency map by more
+// than the forward tolerance.  Texel coordinate of u + ul on a level of s
+// texels: the cell x0 and the fraction fx of u s - 1/2 + ul s.  u s is exact
+// (a power-of-two scale) and so is u s - 1/2 when u s >= 1 (otherwise the
+// result is below 1 in magnitude and within 2^-25 of it, or u lies outside
+// the map and wraps); the fraction then gains the low part and is moved back
+// into [0, 1] across a cell boundary.
+__device__ __forceinline__ void texel_coord(float u, float ul, int s, int& x0, float& fx) {
+  const float x = u * (float)s - 0.5f;
+  float xf = floorf(x);
+  float f = (x - xf) + ul * (float)s;
+  const float adj = floorf(f);  // -1 or 0 (or 1 at the upper boundary)
+  f -= adj;
+  xf += adj;
+  fx = f;
+  x0 = (int)fminf(fmaxf(xf, -1073741824.f), 1073741824.f);
+}
+
+// Bilinear footprint of (u + ul, v + vl) at level l: four texel indices and
+// weights.
 struct Bil {
   int idx[4];      // t00, t10, t01, t11
   float fx, fy;    // fractional position
   int s;           // level size
 };
-__device__ __forceinline__ Bil bil_footprint(const Tex& t, int l, float u, float v) {
+__device__ __forceinline__ Bil bil_footprint(const Tex& t, int l, float u, float v, float ul, float vl) {
   Bil b;
   int s = t.size >> l;
   if (s < 1) s = 1;
   b.s = s;
-  float x = u * (float)s - 0.5f;
-  float y = v * (float)s - 0.5f;
-  float x0f = floorf(x), y0f = floorf(y);
-  b.fx = x - x0f;
-  b.fy = y - y0f;
-  int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
-  int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
+  int x0, y0;
+  texel_coord(u, ul, s, x0, b.fx);
+  texel_coord(v, vl, s, y0, b.fy);
   int c0 = x0 & (s - 1);  // x0 mod s (s is a power of two), in [0, s) also for x0 < 0
   int c1 = c0 + 1; if (c1 == s) c1 = 0;
   int r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
@@ -206,6 +223,23 @@ __device__ __forceinline__ Bil bil_footprint(const Tex& t, int l, float u, float
   b.idx[2] = o + r1 * s + c0;
   b.idx[3] = o + r1 * s + c1;
   return b;
+}
+
+// The low parts of a coordinate pair in one float (texture-sample records):
+// two int16 of ul 2^38 and vl 2^38.  |ul| is at most half a float32 unit of
+// u, 2^-25 for u in [0, 1): the scale keeps 2^-38 (1.5e-8 texels of a 4096^2
+// level) and saturates only for coordinates beyond [-2, 2].
+__device__ __forceinline__ float pack_lo(float ul, float vl) {
+  const float k = 274877906944.f;  // 2^38
+  const int a = (int)rintf(fminf(fmaxf(ul * k, -32767.f), 32767.f));
+  const int b = (int)rintf(fminf(fmaxf(vl * k, -32767.f), 32767.f));
+  return __uint_as_float(((uint32_t)a & 0xFFFFu) | ((uint32_t)b << 16));
+}
+__device__ __forceinline__ void unpack_lo(float x, float& ul, float& vl) {
+  const uint32_t q = __float_as_uint(x);
+  const float k = 1.f / 274877906944.f;
+  ul = (float)(int)(int16_t)(q & 0xFFFFu) * k;
+  vl = (float)(int)(int16_t)(q >> 16) * k;
 }
 
 struct BilVal {
@@ -259,12 +293,13 @@ struct TriSample {
   f3 du, dv;       // d value / d(u, v)
   f3 dl;           // value at level l0 + 1 minus value at l0 (zero without a second level)
 };
-__device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, const Lod& L) {
-  Bil b0 = bil_footprint(t, L.l0, u, v);
+__device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, float ul, float vl,
+                                                   const Lod& L) {
+  Bil b0 = bil_footprint(t, L.l0, u, v, ul, vl);
   BilVal a = bil_eval(t, b0);
   TriSample r{a.val, a.du, a.dv, mk(0.f, 0.f, 0.f)};
   if (L.has1) {
-    Bil b1 = bil_footprint(t, L.l0 + 1, u, v);
+    Bil b1 = bil_footprint(t, L.l0 + 1, u, v, ul, vl);
     BilVal c = bil_eval(t, b1);
     float f = L.f;
     r.dl = c.val - a.val;

@@ -71,6 +71,7 @@ struct PixelGeom {
   float sx, sy;
   f3 x, Ni, T;
   float u, v_, ux, vx, uy, vy;
+  float ul, vl;    // low parts: u + ul, v_ + vl are the coordinates to ~float64 precision
   f3 N, T1, Tp, Bt;
 };
 
@@ -90,6 +91,8 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
   double iS = 1.0 / d.S;
   double A = d.a[0] + d.a[1] + d.a[2];
   double Bs = d.b[0] + d.b[1] + d.b[2];
+  const float u0 = m.uv[2 * g.t[0]], v0 = m.uv[2 * g.t[0] + 1];
+  double ud = u0, vd = v0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
@@ -97,15 +100,20 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
     g.lam[c] = (float)lam;
     g.lx[c] = (float)((d.a[c] - lam * A) * iS * (2.0 / Wp));
     g.ly[c] = (float)((d.b[c] - lam * Bs) * iS * (2.0 / Hp));
+    if (c > 0) {
+      ud += lam * ((double)m.uv[2 * g.t[c]] - (double)u0);
+      vd += lam * ((double)m.uv[2 * g.t[c] + 1] - (double)v0);
+    }
   }
+  g.u = (float)ud;
+  g.v_ = (float)vd;
+  g.ul = (float)(ud - (double)g.u);
+  g.vl = (float)(vd - (double)g.v_);
   // attributes relative to corner 0 (sum lambda = 1, sum of derivatives = 0):
   // a = a0 + sum_c lambda_c (a_c - a0), da = sum_c dlambda_c (a_c - a0)
   g.x = ld3(m.pos, g.v[0]);
   g.Ni = ld3(nrm, g.v[0]);
   g.T = ld3(tan, g.v[0]);
-  float u0 = m.uv[2 * g.t[0]], v0 = m.uv[2 * g.t[0] + 1];
-  g.u = u0;
-  g.v_ = v0;
   g.ux = g.vx = g.uy = g.vy = 0.f;
 #pragma unroll
   for (int c = 1; c < 3; ++c) {
@@ -113,8 +121,6 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
     g.Ni += g.lam[c] * (ld3(nrm, g.v[c]) - ld3(nrm, g.v[0]));
     g.T += g.lam[c] * (ld3(tan, g.v[c]) - ld3(tan, g.v[0]));
     float du = m.uv[2 * g.t[c]] - u0, dv = m.uv[2 * g.t[c] + 1] - v0;
-    g.u += g.lam[c] * du;
-    g.v_ += g.lam[c] * dv;
     g.ux += g.lx[c] * du;
     g.vx += g.lx[c] * dv;
     g.uy += g.ly[c] * du;
@@ -291,7 +297,7 @@ struct ShadeArgs {
 __device__ __forceinline__ float layer_alpha(const ShadeArgs& a, const PixelGeom& g) {
   if (!a.al.data) return 1.f;
   Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
-  return fminf(fmaxf(tex_trilinear(a.al, g.u, g.v_, La).val.x, 0.f), 1.f);
+  return fminf(fmaxf(tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La).val.x, 0.f), 1.f);
 }
 
 __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restrict__ color,
@@ -312,9 +318,9 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
   pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
   if (alpha) alpha[o] = layer_alpha(a, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
-  f3 kd = tex_trilinear(a.kd, g.u, g.v_, Lk).val;
+  f3 kd = tex_trilinear(a.kd, g.u, g.v_, g.ul, g.vl, Lk).val;
   Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
-  f3 nt = tex_trilinear(a.nm, g.u, g.v_, Ln).val;
+  f3 nt = tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln).val;
   f3 n = safe_normalize(nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N);
   f3 eye = ld3(a.v.eye, p.b);
   f3 vdir = safe_normalize(eye - g.x);
@@ -323,7 +329,7 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
   f3 c;
   if (a.model == ADR_SHADE_GGX) {
     Lod Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
-    f3 orm = tex_trilinear(a.orm, g.u, g.v_, Lo).val;
+    f3 orm = tex_trilinear(a.orm, g.u, g.v_, g.ul, g.vl, Lo).val;
     c = ggx(n, vdir, l, kd, orm, E);
   } else {
     c = blinn_phong(n, vdir, l, kd, E);
@@ -382,7 +388,7 @@ constexpr int win_side(int C) {
 }
 
 struct TexScatter {
-  float u, v;
+  float u, v, ul, vl;
   int l0;
   float f;
   bool has1;
@@ -418,17 +424,14 @@ struct Foot {
   int r0, r1, c0, s;
   float fx, fy;
 };
-__device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v) {
+__device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v, float ul, float vl) {
   Foot q;
   int s = t.size >> l;
   if (s < 1) s = 1;
   q.s = s;
-  float x = u * (float)s - 0.5f, y = v * (float)s - 0.5f;
-  float x0f = floorf(x), y0f = floorf(y);
-  q.fx = x - x0f;
-  q.fy = y - y0f;
-  int x0 = (int)fminf(fmaxf(x0f, -1073741824.f), 1073741824.f);
-  int y0 = (int)fminf(fmaxf(y0f, -1073741824.f), 1073741824.f);
+  int x0, y0;
+  texel_coord(u, ul, s, x0, q.fx);
+  texel_coord(v, vl, s, y0, q.fy);
   q.c0 = x0 & (s - 1);  // x0 mod s (s is a power of two), in [0, s) also for x0 < 0
   q.r0 = y0 < 0 ? 0 : (y0 > s - 1 ? s - 1 : y0);
   q.r1 = y0 + 1 < 0 ? 0 : (y0 + 1 > s - 1 ? s - 1 : y0 + 1);
@@ -550,7 +553,7 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
     float wl = use0 ? (ts.has1 ? 1.f - ts.f : 1.f) : ts.f;
     done0 = done0 || use0;
     done1 = done1 || use1;
-    const Foot q = foot_at(t, lev, ts.u, ts.v);
+    const Foot q = foot_at(t, lev, ts.u, ts.v, ts.ul, ts.vl);
     const float gsv[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
     const int off = t.off[lev];
     const int rmin = wave_min_i(part ? q.r0 : BIG), rmax = wave_max_i(part ? q.r1 : -1);
@@ -614,7 +617,7 @@ template <bool ALPHA>
 __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
                                                 const float* __restrict__ gcolor, float* col,
                                                 int& tri, int* vtx, const RecOut& ro, uint32_t& lv,
-                                                float& u_out, float& v_out) {
+                                                float& u_out, float& v_out, float& lo_out) {
   int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
   uint32_t id = (uint32_t)a.vis[o];
   if (id == 0u) return false;
@@ -625,10 +628,10 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   PixelGeom g;
   pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
   Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
-  const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, Lk);
+  const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, g.ul, g.vl, Lk);
   f3 kd = sk.val;
   Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
-  const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, Ln);
+  const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln);
   f3 nt = sn.val;
   f3 mraw = nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N;
   f3 n = safe_normalize(mraw);
@@ -642,7 +645,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   TriSample so;
   if (a.model == ADR_SHADE_GGX) {
     Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
-    so = tex_trilinear(a.orm, g.u, g.v_, Lo);
+    so = tex_trilinear(a.orm, g.u, g.v_, g.ul, g.vl, Lo);
     ggx_bwd(n, vdir, l, kd, so.val, E, gc, gn, gv, gkdv, gormv);
   } else {
     blinn_phong_bwd(n, vdir, l, kd, E, gc, gn, gv, gkdv);
@@ -658,7 +661,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   if (ALPHA && a.al.data) {
     // alpha = clamp(t, 0, 1): the gradient passes where t is inside [0, 1]
     Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
-    const TriSample sa = tex_trilinear(a.al, g.u, g.v_, La);
+    const TriSample sa = tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La);
     const float t = sa.val.x;
     const f3 gal = mk(t >= 0.f && t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
     uv_bwd(a.al, g, La, sa, gal, G);
@@ -669,6 +672,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   if (a.model == ADR_SHADE_GGX) put_rec(ro, 2, Lo, gormv, lv);
   u_out = g.u;
   v_out = g.v_;
+  lo_out = pack_lo(g.ul, g.vl);
   // frame: B = N x T', T' = normalize(T1), T1 = T - (N.T) N, N = normalize(Ni)
   f3 gTp = nt.x * gm;
   f3 gBt = nt.y * gm;
@@ -803,10 +807,10 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
 }
 
 // Texture-sample records handed from the pixel adjoint to the texel
-// scatter, per pixel of the view batch: rec[0] = (u, v, packed levels, 0)
-// with byte k of the packed levels the lower mip level l0 of gradient slot
-// k (255: no contribution), and rec[1 + k] = (dL/dsample, weight of level
-// l0 + 1) of slot k.
+// scatter, per pixel of the view batch: rec[0] = (u, v, packed levels,
+// packed low parts of u and v) with byte k of the packed levels the lower
+// mip level l0 of gradient slot k (255: no contribution), and rec[1 + k] =
+// (dL/dsample, weight of level l0 + 1) of slot k.
 struct TexSlots {
   int kd, nm, orm, al;  // slot of each map, -1 without a gradient buffer
   int n;
@@ -827,10 +831,10 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   const RecOut ro{rec, P, o, {sl.n > 0 ? sl.kd : -1, sl.n > 0 ? sl.nm : -1, sl.n > 0 ? sl.orm : -1,
                               ALPHA && sl.n > 0 ? sl.al : -1}};
   uint32_t lv = 0xFFFFFFFFu;
-  float u = 0.f, v = 0.f;
-  bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, table + (threadIdx.x & 63), tri, vtx, ro, lv, u, v);
+  float u = 0.f, v = 0.f, lo = 0.f;
+  bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, table + (threadIdx.x & 63), tri, vtx, ro, lv, u, v, lo);
   if (p.ok && sl.n > 0)
-    st_nt(rec + o, make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), 0.f));
+    st_nt(rec + o, make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), act ? lo : 0.f));
   wave_vertex_scatter(a, p.b, act, tri, vtx, table, fclip, fattr, det);
 }
 
@@ -860,7 +864,9 @@ __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
     float4 rk = act ? ld_nt(a.rec + (1 + k) * P + o) : make_float4(0.f, 0.f, 0.f, 0.f);
-    TexScatter ts{r0.x, r0.y, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
+    float ul, vl;
+    unpack_lo(r0.w, ul, vl);
+    TexScatter ts{r0.x, r0.y, ul, vl, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
     wave_scatter_tex(a.t[k], a.g[k], act, ts, win);
   }
 }
@@ -969,7 +975,9 @@ __global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __
     for (int j = 0; j < 2; ++j) {
       const bool on = l0 != 0xFF && (j == 0 || rk.w > 0.f);
       const float wl = j == 0 ? 1.f - rk.w : rk.w;
-      Foot q = foot_at(t, on ? l0 + j : 0, r0.x, r0.y);
+      float ul, vl;
+      unpack_lo(r0.w, ul, vl);
+      Foot q = foot_at(t, on ? l0 + j : 0, r0.x, r0.y, ul, vl);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t e = (((int64_t)k * P + o) * 2 + j) * 4 + c;

@@ -190,3 +190,83 @@ def oracle_skinned_keys(w, mvp32, which="latent"):
         keys.append(k)
         cov.append(c)
     return np.stack(keys), np.stack(cov), vs
+
+
+def oracle_grads_and_reach(w, ref, mvp32, eye, tau=1e-5, seed=0):
+    """The oracle's loss and gradients of the latent (as OL.loss_and_grads)
+    and, from the same forward pass, the entries of each optimised parameter
+    that receive gradient from a pixel channel whose L1 residual
+    |T(x) - T(ref)| lies within tau (the forward tolerance) of zero.  There
+    float32 and float64 may disagree on the sign of the residual, and so on
+    the sign of that channel's whole contribution to the gradient (L1 is not
+    differentiable at 0); a per-entry bound cannot hold for them.  They are
+    found by a second backward pass, of the sum over those channels of T(x)
+    times a random weight in [1, 2): an entry is reached iff its gradient is
+    non-zero.  Squared losses have no such entries.
+    Returns (loss, grads, render dict, reach, number of such channels)."""
+    params = OL.latent_params(w)
+    out = OL.render_latent(w, mvp32, eye, params)
+    img = out["image"]
+    loss = R.image_loss(img, ref, w.loss)
+    leaves = [params[k] for k in params]
+    gl = torch.autograd.grad(loss, leaves, allow_unused=True, retain_graph=True)
+    grads = {k: (g if g is not None else torch.zeros_like(params[k])) for k, g in zip(params, gl)}
+    reach = {k: np.zeros(tuple(p.shape), dtype=bool) for k, p in params.items()}
+    n_amb = 0
+    if w.loss.startswith("l1"):
+        tm = w.loss.endswith("tonemap")
+        a = R.tonemap(img) if tm else img
+        b = R.tonemap(ref) if tm else ref
+        amb = (a - b).detach().abs() < tau
+        n_amb = int(amb.sum())
+        if n_amb:
+            r = 1.0 + torch.from_numpy(np.random.default_rng(seed).random(tuple(a.shape)))
+            obj = (a * (amb.to(a.dtype) * r)).sum()
+            gl = torch.autograd.grad(obj, leaves, allow_unused=True)
+            for k, g in zip(params, gl):
+                if g is not None:
+                    reach[k] = (g.detach().abs() > 0).numpy()
+    return loss.detach(), grads, out, reach, n_amb
+
+
+def check_adam_first_step(name, p0, p_new, g_o, lr, delta, exempt=None, eps=1e-8, say=print):
+    """A first Adam step from zero moments, p1 = p0 - lr g / (|g| + eps)
+    (the bias corrections cancel), against the oracle's gradient g_o, entry
+    by entry.  If the gradient behind p_new is within delta of g_o, the two
+    steps differ by at most lr min(2, 4 delta / (|g_o| + eps)): the step is
+    smooth in g except at 0, where its sign may flip, so entries whose
+    oracle gradient is within a few delta of zero get a loose bound (at
+    most 2 lr, any valid step).  ``exempt`` entries (see
+    oracle_grads_and_reach) get 2 lr.  float32 rounding adds a few units in the
+    last place of p and of the step."""
+    p0 = np.asarray(p0, dtype=np.float64).reshape(-1)
+    p_new = np.asarray(p_new, dtype=np.float64).reshape(-1)
+    g_o = np.asarray(g_o, dtype=np.float64).reshape(-1)
+    p_o = p0 - lr * g_o / (np.abs(g_o) + eps)
+    bound = lr * np.minimum(2.0, 4.0 * delta / (np.abs(g_o) + eps))
+    if exempt is not None:
+        bound = np.where(np.asarray(exempt).reshape(-1), 2.0 * lr, bound)
+    bound = bound + 4 * np.spacing(np.abs(p0).astype(np.float32)).astype(np.float64) + 1e-6 * lr
+    err = np.abs(p_new - p_o)
+    loose = bound > 1e-2 * lr
+    n_ex = 0 if exempt is None else int(np.asarray(exempt).sum())
+    say(f"  adam {name}: max error {err.max() / lr:.3g} lr; {int(loose.sum())} of {err.size} entries with a "
+        f"loose bound ({n_ex} reached by ambiguous L1 residuals)")
+    bad = err > bound
+    assert not bad.any(), (name, int(bad.sum()), float((err / bound).max()))
+
+
+def check_grad_entries(name, got, exp, rel_tol, sup_tol, exempt=None, say=print):
+    """Relative L2 error within rel_tol, and every entry outside ``exempt``
+    within sup_tol times the largest oracle entry."""
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    exp = np.asarray(exp, dtype=np.float64).reshape(-1)
+    e = rel_l2(got, exp)
+    diff = np.abs(got - exp)
+    if exempt is not None:
+        diff = np.where(np.asarray(exempt).reshape(-1), 0.0, diff)
+    sup = float(diff.max() / max(np.abs(exp).max(), 1e-300)) if diff.size else 0.0
+    n_ex = 0 if exempt is None else int(np.asarray(exempt).sum())
+    say(f"  grad {name}: rel-L2 {e:.3g}, max entry error {sup:.3g} of the largest entry ({n_ex} exempt)")
+    assert e < rel_tol, (name, e)
+    assert sup < sup_tol, (name, sup)

@@ -31,15 +31,17 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _oracle(p0, gchain, m, v, levels, t, lr):
+def _oracle(p0, gchain, m, v, levels, t, lr, b1=0.9, b2=0.999, eps=1e-8, fold_only=False):
     """Folded level-0 gradient d/dp0 sum_l <g_l, chain_l(p0)> and one Adam
-    step, in float64."""
+    step, in float64 (with fold_only: (None, folded gradient, None))."""
     S, C = p0.shape[0], p0.shape[2]
     x = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
     chain = R.mip_chain_f32(x, levels)
     obj = sum((lv * torch.tensor(gl, dtype=torch.float64)).sum() for lv, gl in zip(chain, gchain))
     (g0,) = torch.autograd.grad(obj, [x])
-    pn, mn, vn = R.adam(p0, g0.numpy(), m, v, t, lr)
+    if fold_only:
+        return None, g0.numpy(), None
+    pn, mn, vn = R.adam(p0, g0.numpy(), m, v, t, lr, b1, b2, eps)
     return pn, mn, vn
 
 
@@ -77,34 +79,44 @@ def test_adam_maps_matches_oracle(ctx, case):
     t, lr = 5, 1e-2
     adr.adam_step_maps(ctx, [(tex, gd, md, vd)], t, lr)
     torch.cuda.synchronize()
-    pn, mn, vn = _oracle(p0.astype(np.float64), _split(gflat.astype(np.float64), S, C, levels),
-                                  m.reshape(S, S, C).astype(np.float64), v.reshape(S, S, C).astype(np.float64),
-                                  levels, t, lr)
+    # The oracle takes the hyper-parameters as they cross the ABI (float32:
+    # beta2 = 0.999 arrives as 0.99900001, which moves the bias correction by
+    # 1e-5 relative), so the remaining difference is the kernel's float32
+    # arithmetic.  Forward error bound per texel, in units u = 2^-24 of the
+    # magnitudes involved: the new texel and the step (a few roundings
+    # each), and the first moment's rounding (the folded gradient is a sum
+    # of up to `levels` terms, each rounded) carried through the step's
+    # division by sqrt(v_hat) + eps.
+    b1, b2, lr32, eps32 = (float(np.float32(x)) for x in (0.9, 0.999, lr, 1e-8))
+    m64 = m.reshape(S, S, C).astype(np.float64)
+    v64 = v.reshape(S, S, C).astype(np.float64)
+    gch = _split(gflat.astype(np.float64), S, C, levels)
+    pn, mn, vn = _oracle(p0.astype(np.float64), gch, m64, v64, levels, t, lr32, b1, b2, eps32)
+    _, g_abs, _ = _oracle(p0.astype(np.float64), [np.abs(x) for x in gch], np.zeros_like(m64),
+                          np.zeros_like(v64), levels, t, lr32, b1, b2, eps32, fold_only=True)
     got = _split(tex.data.cpu().numpy().astype(np.float64), S, C, levels)
     mg = md.cpu().numpy().reshape(S, S, C).astype(np.float64)
     vg = vd.cpu().numpy().reshape(S, S, C).astype(np.float64)
-    em, ev = np.abs(mg - mn).max(), np.abs(vg - vn).max()
-    # the moments against the oracle's; the step against the oracle's step
-    # taken from the kernel's own float32 moments (where the second moment
-    # is tiny the step amplifies their rounding, which says nothing of the
-    # step's arithmetic): a few units in the last place of the texel and of
-    # the step
-    # (the hyper-parameters cross the ABI as float32: beta2 = 0.999 is
-    # 0.99900001 there, which moves the bias correction by 1e-5)
-    b1, b2, lr32, eps32 = (float(np.float32(x)) for x in (0.9, 0.999, lr, 1e-8))
-    step = lr32 * (mg / (1 - b1 ** t)) / (np.sqrt(vg / (1 - b2 ** t)) + eps32)
-    pe = p0.astype(np.float64) - step
-    ulp = lambda x: np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
-    tol0 = 4 * ulp(np.abs(p0) + np.abs(pe)) + 4 * ulp(step)
-    err0 = np.abs(got[0] - pe)
-    _say(f"  level 0 {err0.max():.3g} ({(err0 / tol0).max():.2f} of tol), vs oracle {np.abs(got[0] - pn).max():.3g};"
-         f"  m {em:.3g}  v {ev:.3g}")
+    u = 2.0 ** -24
+    step_o = p0.astype(np.float64) - pn
+    vhat = vn / (1 - b2 ** t)
+    m_mag = b1 * np.abs(m64) + (1 - b1) * (levels + 1) * g_abs
+    g_fold = (mn - b1 * m64) / (1 - b1)
+    v_err = 8 * u * (b2 * v64 + (1 - b2) * (g_fold ** 2 + 2 * np.abs(g_fold) * (levels + 1) * g_abs))
+    tol0 = 8 * u * (np.abs(p0) + np.abs(step_o)) + 8 * u * lr32 * m_mag / (1 - b1 ** t) / (np.sqrt(vhat) + eps32)
+    tol0 += 0.5 * np.abs(step_o) * v_err / np.maximum(vn, 1e-300)
+    tol0 += np.spacing(np.abs(pn).astype(np.float32)).astype(np.float64)
+    err0 = np.abs(got[0] - pn)
+    em = np.abs(mg - mn) / (8 * u * m_mag + 1e-30)
+    ev = np.abs(vg - vn) / (v_err + 1e-30)
+    _say(f"  level 0 vs oracle: max {err0.max():.3g} ({(err0 / tol0).max():.2f} of the bound); "
+         f"m {em.max():.2f}, v {ev.max():.2f} of theirs")
     if not np.all(err0 <= tol0):
         i = np.unravel_index(np.argmax(err0 / tol0), err0.shape)
-        _say("  worst", i, "p0", repr(p0[i]), "m0", repr(m.reshape(S, S, C)[i]), "v0", repr(v.reshape(S, S, C)[i]),
-             "m'", repr(np.float32(mg[i])), "v'", repr(np.float32(vg[i])), "got", repr(np.float32(got[0][i])),
-             "expected", pe[i], "oracle", pn[i], "step", step[i])
-    assert np.all(err0 <= tol0) and em < 1e-6 and ev < 1e-6
+        _say("  worst", i, "p0", repr(p0[i]), "m0", repr(m64[i]), "v0", repr(v64[i]), "got", repr(np.float32(got[0][i])),
+             "oracle", pn[i], "bound", tol0[i])
+    assert np.all(err0 <= tol0)
+    assert np.all(em <= 1.0) and np.all(ev <= 1.0)
     # the rebuilt levels: box averages of the kernel's new level 0 (float32
     # rounding of the pairwise sums, at most a few units of the largest
     # level-0 magnitude per level)

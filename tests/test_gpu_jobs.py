@@ -12,8 +12,11 @@ from oracle import loop as OL
 from oracle import render as R
 from oracle import sampling as Sm
 from paper_2104_03989_amd import synth
+from tests.gpu_common import check_adam_first_step, oracle_grads_and_reach
 
 pytestmark = pytest.mark.gpu
+
+GRAD_SUP_TOL = 1e-4
 
 
 def _say(*a):
@@ -83,14 +86,20 @@ def test_job_first_step_matches_oracle():
     w.light_dir = np.array(lights, dtype=np.float32).astype(np.float64)
     mvp32, eye = OL.cameras(w)
     ref = OL.reference_image(w, mvp32, eye)
-    params = OL.latent_params(w)
-    loss, grads, _ = OL.loss_and_grads(w, ref, mvp32, eye, params)
+    loss, grads, _, reach, n_amb = oracle_grads_and_reach(w, ref, mvp32, eye)
     assert abs(st[jid]["loss"] - float(loss)) <= 1e-5 * float(loss)
-    new, _ = OL.adam_update(params, grads, {}, 1, w.lr)
-    for k, name in (("pos", "pos"), ("normal", "normal")):
-        d = np.abs(got[k].reshape(-1) - new[name].reshape(-1))
-        assert np.median(d) < 1e-3 * w.lr, k
-        assert (d < 0.05 * w.lr).mean() > 0.995, k
+    # The job's parameters after one Adam step (t = 1, zero moments) against
+    # the oracle's gradients, entry by entry: the job runs the kernels whose
+    # gradients the parity tests bound entry by entry by GRAD_SUP_TOL of the
+    # largest entry; that bound fixes the step to within
+    # lr min(2, 4 delta / (|g| + eps)), loose only where the oracle gradient
+    # is within a few delta of zero (the step's sign is undetermined there)
+    # or reached by a pixel whose L1 residual is within 1e-5 of zero.
+    p0 = {"pos": w.latent.mesh.pos, "normal": w.latent.normal.data}
+    for k in ("pos", "normal"):
+        g = grads[k].numpy()
+        delta = GRAD_SUP_TOL * float(np.abs(g).max())
+        check_adam_first_step(k, p0[k], got[k], g, w.lr, delta, reach[k], say=_say)
     ctx.close()
 
 
