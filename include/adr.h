@@ -188,6 +188,27 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
                           const adr_views* views, const float* ref_image, int32_t loss_kind,
                           const adr_fwd_out* out, int32_t flags, adr_stream stream);
 
+/* Forward render that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, checks, outputs and
+ * kernels as adr_render_fwd.  Its scratch (snapped vertices, triangle
+ * orientations, lists and queue, the vertex frame and its float64
+ * accumulators, loss partials, the multisampled image) is carved from one
+ * static device array of ADR_NOALLOC_SCRATCH_BYTES that every device the
+ * library runs on holds until the process ends (its address is looked up
+ * by adr_ctx_create).  That covers, e.g., 8 views of a 297,680-triangle mesh
+ * (about 51 MB); an input that needs more returns ADR_E_INVALID before any
+ * launch, with the size in adr_last_error().  All calls on one device share
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (other host threads, or streams not ordered with
+ * each other) race and give wrong results.  Stages are not timed
+ * (adr_ctx_profile), and a following adr_render_bwd recomputes the
+ * geometry instead of reusing this call's scratch. */
+#define ADR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+adr_status adr_render_fwd_noalloc(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                                  const adr_views* views, const float* ref_image, int32_t loss_kind,
+                                  const adr_fwd_out* out, int32_t flags, adr_stream stream);
+
 /* Gradient buffers, caller-owned device memory.  Each is accumulated into
  * (+=).  Map gradients use the full mip-chain layout of their texture:
  * level 0 receives the gradient w.r.t. the level-0 texels (coarser levels

@@ -29,6 +29,7 @@ SHADE_BLINN_PHONG, SHADE_GGX = 0, 1
 LOSS = {"l1": 0, "l1_tonemap": 1, "l2": 2, "l2_tonemap": 3}
 FWD_BUILD_MIPS, FWD_NO_AA, DETERMINISTIC, INDEPENDENT_MIPS, MSAA_2X2, MSAA_4X4 = 1, 2, 4, 8, 16, 32
 BWD_DEFER_MIP_ADJOINT = 64
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def msaa_factor(flags: int) -> int:
@@ -40,7 +41,7 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
            "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster",
-           "adr_adam_step_maps", "adr_ctx_profile_stages")
+           "adr_adam_step_maps", "adr_ctx_profile_stages", "adr_render_fwd_noalloc")
 N_STAGES = 18
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend",
@@ -138,6 +139,7 @@ _lib.adr_ctx_create.argtypes = [I32, C.c_uint64, C.POINTER(P)]
 _lib.adr_ctx_destroy.argtypes = [P]
 _lib.adr_render_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_), P, I32,
                                 C.POINTER(FwdOut_), I32, P]
+_lib.adr_render_fwd_noalloc.argtypes = _lib.adr_render_fwd.argtypes
 _lib.adr_render_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_),
                                 C.POINTER(FwdOut_), P, C.POINTER(Grads_), I32, P]
 _lib.adr_adam_step.argtypes = [P, C.POINTER(Param_), I32, I32, C.c_float, C.c_float, C.c_float,
@@ -361,9 +363,11 @@ def mip_build(ctx: Context, tex: DeviceTexture, stream=None):
 
 def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, ref=None,
                loss: str = "l1", flags: int = 0, pos=None, want_image=True, want_tri_id=False,
-               want_coverage=False, stream=None, outputs: dict | None = None):
+               want_coverage=False, stream=None, outputs: dict | None = None, noalloc: bool = False):
     """Returns a dict with vis, color, image, dimage, loss, tri_id, coverage
-    (``outputs``: a dict returned by an earlier call, reused in place)."""
+    (``outputs``: a dict returned by an earlier call, reused in place).
+    ``noalloc``: call adr_render_fwd_noalloc, whose scratch is the library's
+    static per-device array (no device allocation by the library)."""
     B, H, W = views.n, views.height, views.width
     ms = msaa_factor(flags)
     Hs, Ws = H * ms, W * ms          # visibility samples (multisampling: per sample)
@@ -386,8 +390,9 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
     fo = FwdOut_(*[_ptr(out.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
                                               "aa")])
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
-    _check(_lib.adr_render_fwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref),
-                               LOSS[loss], C.byref(fo), flags, _stream(stream)))
+    fn = _lib.adr_render_fwd_noalloc if noalloc else _lib.adr_render_fwd
+    _check(fn(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref), LOSS[loss], C.byref(fo), flags,
+              _stream(stream)))
     return out
 
 

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -88,6 +89,7 @@ struct adr_ctx {
   GeomKey geom{};
   std::vector<Span> spans;
   std::vector<hipEvent_t> pool;
+  unsigned char* noalloc = nullptr;  // this device's copy of the no-allocation scratch array
 };
 
 namespace {
@@ -317,6 +319,155 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
     HIPCHK(x, where);                            \
   } while (0)
 
+// Multisampling factor from the flags (1, 2 or 4 samples per pixel axis);
+// switches the views to the sample grid.  0 on a bad combination.
+static int apply_msaa(int32_t flags, ViewsD& v) {
+  const bool m2 = flags & ADR_MSAA_2X2, m4 = flags & ADR_MSAA_4X4;
+  if (m2 && m4) return 0;
+  const int ms = m4 ? 4 : (m2 ? 2 : 1);
+  v.ms = ms;
+  v.W *= ms;
+  v.H *= ms;
+  return ms;
+}
+
+// Validation shared by the forward entry points (no device work).
+static adr_status check_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat, const adr_views* views,
+                            const float* ref_image, int32_t loss_kind, const adr_fwd_out* out, int32_t flags,
+                            MeshD& m, ViewsD& v, Tex& kd, Tex& nm, Tex& orm) {
+  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if (!out || !out->vis || !out->color) return fail(ADR_E_INVALID, "out->vis and out->color are required");
+  if (ref_image) {
+    if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
+    if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
+  }
+  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
+                ADR_MSAA_4X4 | ADR_BWD_DEFER_MIP_ADJOINT))
+    return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
+  if ((flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
+    return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
+  if (!apply_msaa(flags, v) || v.W > 16384 || v.H > 16384)
+    return fail(ADR_E_INVALID, "multisampling: one factor, at most 16384 samples per axis");
+  return ADR_OK;
+}
+
+#define STAGE(stage, x, where)      \
+  do {                              \
+    if (timed) {                    \
+      TIMED(stage, x, where);       \
+    } else {                        \
+      HIPCHK(x, where);             \
+    }                               \
+  } while (0)
+
+// The forward's launch sequence on the scratch s; `timed` brackets the
+// stages with events when the context profiles them.
+static adr_status fwd_launches(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat, const MeshD& m,
+                               const ViewsD& v, const Tex& kd, const Tex& nm, const Tex& orm, const float* ref_image,
+                               int32_t loss_kind, const adr_fwd_out* out, int32_t flags, hipStream_t st, Scratch& s,
+                               bool timed) {
+  if (flags & ADR_FWD_BUILD_MIPS) {
+    const Tex* maps[3] = {&kd, &nm, &orm};
+    int nmaps = mat->model == ADR_SHADE_GGX ? 3 : 2;
+    MipSet ms{};
+    for (int k = 0; k < nmaps; ++k)
+      if (maps[k]->fmt == ADR_TEX_F32 && maps[k]->levels > 1) ms.t[ms.n++] = *maps[k];
+    STAGE(10, launch_mip_build_set(ms, st), "mip build");
+  }
+  int64_t npx = (int64_t)v.B * v.W * v.H;
+  const bool own_frame = !(mesh->nrm && mesh->tan);
+  if (!own_frame) {
+    s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
+    s.tan = const_cast<float*>(mesh->tan);
+  } else {
+    STAGE(0, launch_vertex_frame(m, s, st), "vertex frame");
+  }
+  STAGE(1, launch_xform(m, v, s, st), "transform");
+  STAGE(12, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
+  STAGE(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
+  STAGE(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
+  STAGE(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
+                            (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st, out->aa),
+        "antialias/loss");
+  return ADR_OK;
+}
+
+// ---- the no-allocation forward's scratch ----
+//
+// One static device array: every GPU the library runs on holds its own copy
+// (a module global) until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is a stand-in, not a
+// device address): adr_ctx_create looks up each device's address once, with
+// that device current, and the entry point carves its buffers from it.
+static __device__ __align__(256) unsigned char scratch[ADR_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_noalloc_mu;
+static std::unordered_map<int, unsigned char*> g_noalloc_addr;
+
+// Address of the current device's copy (device `device` must be current).
+static adr_status noalloc_address(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_addr.find(device);
+  if (it == g_noalloc_addr.end()) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(no-allocation scratch)");
+    it = g_noalloc_addr.emplace(device, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return ADR_OK;
+}
+
+// The forward's scratch carved from the context's device copy of the array
+// (256-byte aligned pieces, the same sizes prepare_scratch allocates);
+// returns the bytes used, and fills s when it is given.  Nothing here starts
+// at zero: the kernels clear what they accumulate into (the frame
+// accumulators, the triangle counters).
+static size_t noalloc_carve(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool det, Scratch* s) {
+  const size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
+  const size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return s ? ctx->noalloc + o : nullptr;
+  };
+  unsigned char* snap = take(B * V * 16);
+  unsigned char* orient = take(B * T);
+  unsigned char* nacc = take(V * 24);
+  unsigned char* tacc = take(V * 24);
+  unsigned char* nrm = take(V * 12);
+  unsigned char* tan = take(V * 12);
+  unsigned char* big = take(B * T * 4);
+  unsigned char* big_cnt = take((B + 1) * 4);
+  unsigned char* med = take(B * T * 4);
+  unsigned char* partial = take(tiles * 4);
+  unsigned char* image_s = v.ms > 1 ? take(B * v.W * v.H * 12) : nullptr;
+  unsigned char* fix_n = det ? take(V * 24) : nullptr;
+  unsigned char* fix_t = det ? take(V * 24) : nullptr;
+  if (s) {
+    *s = Scratch{};
+    s->snap = (int*)snap;
+    s->orient = (int8_t*)orient;
+    s->nacc = (double*)nacc;
+    s->tacc = (double*)tacc;
+    s->nrm = (float*)nrm;
+    s->tan = (float*)tan;
+    s->big = (uint32_t*)big;
+    s->big_cnt = (uint32_t*)big_cnt;
+    s->med = (uint32_t*)med;
+    s->partial = (float*)partial;
+    s->n_partial = (int)tiles;
+    s->image_s = (float*)image_s;
+    s->det = det;
+    s->fix_n = (unsigned long long*)fix_n;
+    s->fix_t = (unsigned long long*)fix_t;
+    s->tiny_bbox = ctx->tiny_bbox;
+    s->med_bbox = ctx->med_bbox;
+  }
+  return off;
+}
+
 extern "C" {
 
 const char* adr_last_error(void) { return g_err; }
@@ -338,6 +489,12 @@ adr_status adr_ctx_create(int32_t device, uint64_t hbm_budget_bytes, adr_ctx** o
     hbm_budget_bytes = fr > reserve ? fr - reserve : fr / 2;
   }
   c->budget = hbm_budget_bytes;
+  // this device's copy of the no-allocation scratch array (device current)
+  adr_status rs = noalloc_address(device, &c->noalloc);
+  if (rs != ADR_OK) {
+    delete c;
+    return rs;
+  }
   *out = c;
   return ADR_OK;
 }
@@ -362,72 +519,52 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   return ADR_OK;
 }
 
-// Multisampling factor from the flags (1, 2 or 4 samples per pixel axis);
-// switches the views to the sample grid.  0 on a bad combination.
-static int apply_msaa(int32_t flags, ViewsD& v) {
-  const bool m2 = flags & ADR_MSAA_2X2, m4 = flags & ADR_MSAA_4X4;
-  if (m2 && m4) return 0;
-  const int ms = m4 ? 4 : (m2 ? 2 : 1);
-  v.ms = ms;
-  v.W *= ms;
-  v.H *= ms;
-  return ms;
-}
-
 adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
                           const adr_views* views, const float* ref_image, int32_t loss_kind,
                           const adr_fwd_out* out, int32_t flags, adr_stream stream) {
   MeshD m;
   ViewsD v;
   Tex kd, nm, orm;
-  adr_status r = check_common(ctx, mesh, mat, views, m, v, kd, nm, orm);
+  adr_status r = check_fwd(ctx, mesh, mat, views, ref_image, loss_kind, out, flags, m, v, kd, nm, orm);
   if (r != ADR_OK) return r;
-  if (!out || !out->vis || !out->color) return fail(ADR_E_INVALID, "out->vis and out->color are required");
-  if (ref_image) {
-    if (loss_kind < ADR_LOSS_L1 || loss_kind > ADR_LOSS_L2_TONEMAP) return fail(ADR_E_INVALID, "unknown loss kind %d", loss_kind);
-    if (!out->dimage || !out->loss) return fail(ADR_E_INVALID, "out->dimage and out->loss are required with a reference image");
-  }
-  if (flags & ~(ADR_FWD_BUILD_MIPS | ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_MSAA_2X2 |
-                ADR_MSAA_4X4 | ADR_BWD_DEFER_MIP_ADJOINT))
-    return fail(ADR_E_INVALID, "unknown flags 0x%x", flags);
-  if ((flags & ADR_FWD_BUILD_MIPS) && (flags & ADR_INDEPENDENT_MIPS))
-    return fail(ADR_E_INVALID, "independent mip levels are not rebuilt from level 0");
-  if (!apply_msaa(flags, v) || v.W > 16384 || v.H > 16384)
-    return fail(ADR_E_INVALID, "multisampling: one factor, at most 16384 samples per axis");
   hipStream_t st = (hipStream_t)stream;
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
   if ((r = prepare_scratch(ctx, m, v, false, s, 0, (flags & ADR_DETERMINISTIC) != 0)) != ADR_OK) return r;
-  if (flags & ADR_FWD_BUILD_MIPS) {
-    const Tex* maps[3] = {&kd, &nm, &orm};
-    int nmaps = mat->model == ADR_SHADE_GGX ? 3 : 2;
-    MipSet ms{};
-    for (int k = 0; k < nmaps; ++k)
-      if (maps[k]->fmt == ADR_TEX_F32 && maps[k]->levels > 1) ms.t[ms.n++] = *maps[k];
-    TIMED(10, launch_mip_build_set(ms, st), "mip build");
-  }
-  int64_t npx = (int64_t)v.B * v.W * v.H;
   const bool own_frame = !(mesh->nrm && mesh->tan);
-  if (!own_frame) {
-    s.nrm = const_cast<float*>(mesh->nrm);  // read only on this path
-    s.tan = const_cast<float*>(mesh->tan);
-  } else {
-    TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
-  }
-  TIMED(1, launch_xform(m, v, s, st), "transform");
-  TIMED(12, launch_clear_vis(out->vis, out->coverage, npx, s.big_cnt, v.B, st), "clear");
-  TIMED(2, launch_raster(m, v, s, out->vis, out->coverage, st), "raster");
+  if ((r = fwd_launches(ctx, mesh, mat, m, v, kd, nm, orm, ref_image, loss_kind, out, flags, st, s, true)) != ADR_OK)
+    return r;
   // the frame, snapped vertices and orientations now in the scratch (the
   // raster writes every triangle's orientation) serve a backward that follows
   if (own_frame) {
     ctx->geom = geom_key(m, v, views->mvp, out->vis, (flags & ADR_DETERMINISTIC) != 0, st);
     ctx->geom_ok = true;
   }
-  TIMED(3, launch_shade_fwd(m, v, mat->model, kd, nm, orm, s, out->vis, out->color, out->tri_id, st), "shade");
-  TIMED(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
-                            (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st, out->aa),
-         "antialias/loss");
   return ADR_OK;
+}
+
+adr_status adr_render_fwd_noalloc(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
+                                  const adr_views* views, const float* ref_image, int32_t loss_kind,
+                                  const adr_fwd_out* out, int32_t flags, adr_stream stream) {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm;
+  adr_status r = check_fwd(ctx, mesh, mat, views, ref_image, loss_kind, out, flags, m, v, kd, nm, orm);
+  if (r != ADR_OK) return r;
+  if (!ctx->noalloc) return fail(ADR_E_HIP, "no-allocation scratch of device %d was not set up", ctx->device);
+  Scratch s;
+  const size_t need = noalloc_carve(ctx, m, v, (flags & ADR_DETERMINISTIC) != 0, nullptr);
+  if (need > (size_t)ADR_NOALLOC_SCRATCH_BYTES)
+    return fail(ADR_E_INVALID,
+                "adr_render_fwd_noalloc: %d views x %d triangles / %d vertices at %dx%d samples need %zu bytes of "
+                "scratch; the no-allocation forward holds at most %llu",
+                v.B, m.n_tri, m.n_pos, v.W, v.H, need, (unsigned long long)ADR_NOALLOC_SCRATCH_BYTES);
+  noalloc_carve(ctx, m, v, (flags & ADR_DETERMINISTIC) != 0, &s);
+  // the context's own scratch no longer holds this forward's geometry
+  ctx->geom_ok = false;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  return fwd_launches(ctx, mesh, mat, m, v, kd, nm, orm, ref_image, loss_kind, out, flags, st, s, false);
 }
 
 adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* mat,
