@@ -36,6 +36,7 @@ SINGLE_KERNEL_STAGES = {
     "shade_bwd": ("adr::k_shade_bwd<false>", ["shade.hip"]),
     "aa_bwd": ("adr::k_aa_bwd", ["aa.hip"]),
     "shade": ("adr::k_shade_fwd", ["shade.hip"]),
+    "aa_loss": ("adr::k_aa_fwd", ["aa.hip"]),
     "adam": ("adr::k_adam", ["adam.hip"]),
     "adam_maps": ("adr::k_adam_maps_tiles", ["tex.hip"]),
     "skin_bwd": ("adr::k_skin_bwd", ["skin.hip"]),
@@ -135,6 +136,37 @@ def summarize_pmc(workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir
                         for b in (bench, "python3 /root/repo/bench.py --calibrate-copy")],
            "kernels": kernels}
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(path)
+
+
+def summarize_valu(workload, pmc_dir):
+    """Writes profiles/pmc_valu_<workload>.json from a rocprofv3 --pmc
+    SQ_WAVES SQ_INSTS_VALU run: VALU wave-instructions per launch of each
+    single-kernel stage's kernel, with a hash of its sources."""
+    import csv
+    import re
+    acc = {}
+    for r in csv.DictReader(open(os.path.join(pmc_dir, "run_counter_collection.csv"))):
+        n = re.sub(r"^void ", "", re.sub(r"\(.*", "", r["Kernel_Name"]))
+        acc.setdefault(n, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    kernels = {}
+    for stage, (name, files) in SINGLE_KERNEL_STAGES.items():
+        c = acc.get(name)
+        if not c or "SQ_INSTS_VALU" not in c or "SQ_WAVES" not in c:
+            continue
+        valu = sum(c["SQ_INSTS_VALU"]) / len(c["SQ_INSTS_VALU"])
+        waves = sum(c["SQ_WAVES"]) / len(c["SQ_WAVES"])
+        kernels[name] = {"stage": stage, "waves_per_launch": round(waves), "valu_per_wave": round(valu / waves, 1),
+                         "valu_per_launch": round(valu), "launches": len(c["SQ_WAVES"]),
+                         "sources_sha256": kernel_sources_sha(files)}
+    bench = f"python3 /root/repo/bench.py --workload {workload} --steps 2 --warmup 1 --no-cpu-baseline --no-profile"
+    out = {"workload": workload, "counters": "rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU (per dispatch)",
+           "command": f"cd /tmp && rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU -d <dir> -o run --output-format csv -- {bench}",
+           "valu_peak": "256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction = 614.4 G/s",
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", f"pmc_valu_{workload}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(path)
@@ -359,12 +391,12 @@ def build_step(w, ctx, adr, torch, np, n_steps, seed, det=False, laplacian=False
 TEXEL_C = 1.25   # compulsory texels per covered pixel per mip level at ~1 texel per pixel
 
 
-def lookup_bytes(w):
-    """Compulsory texel bytes of one pixel's trilinear lookups of every
-    latent map larger than 1x1: TEXEL_C texels at each of two levels."""
+def lookup_bytes(scene):
+    """Compulsory texel bytes of one pixel's trilinear lookups of every map
+    of a scene larger than 1x1: TEXEL_C texels at each of two levels."""
     total = 0.0
     for name in ("kd", "normal", "orm", "alpha"):
-        tex = getattr(w.latent, name, None)
+        tex = getattr(scene, name, None)
         if tex is None or tex.data.shape[0] <= 1:
             continue
         bt = 4 if getattr(tex, "fmt", "f32") == "rgba8" else 4 * tex.data.shape[2]
@@ -382,9 +414,19 @@ def optimised_maps(w):
     return out
 
 
-def algorithmic_bytes(stage, w, st, covered_latent):
+def algorithmic_bytes(stage, w, st, covered_latent, covered_ref=0):
     """Compulsory HBM bytes of one launch of a stage's kernel.
 
+    shade (k_shade_fwd, one launch per render, averaged over the reference
+    and latent renders of a step): per visibility sample its key (8 B) and
+    colour (12 B); per covered pixel the texels of its trilinear lookups
+    (TEXEL_C per level, two levels, every map of that render's material).
+    aa_loss (k_aa_fwd, averaged over the two renders): per pixel key and
+    colour (20 B); the reference writes its image (12 B); the latent reads
+    the reference image (12 B) and writes dL/dimage (12 B) and the received
+    antialiasing it keeps for the adjoint (24 B).
+    aa_bwd (k_aa_bwd): per pixel key, colour, dL/dimage, the kept
+    antialiasing (8 + 12 + 12 + 24 B) and dL/dcolour written (12 B).
     shade_bwd (pixel adjoint): per pixel its visibility key (8 B) and the
     record header it writes (16 B); per covered pixel dL/dcolour (12 B), a
     16-B sample record per optimised map and the texels of its trilinear
@@ -405,31 +447,89 @@ def algorithmic_bytes(stage, w, st, covered_latent):
         # depth-peeled latent: one launch per layer; covered_latent counts the
         # covered pixels of all layers; the average launch is returned
         if stage == "shade_bwd":
-            return (L * px * (8 + 16 + 4) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w))) / L
+            return (L * px * (8 + 16 + 4) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w.latent))) / L
         if stage == "tex_bwd":
             return (L * px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)) / L
         if stage == "aa_bwd":
-            return px * (8 + 12 + 12 + 12)
+            return px * (8 + 12 + 12 + 24 + 12)
         return None
     if stage == "shade_bwd":
-        return px * (8 + 16) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w))
+        return px * (8 + 16) + covered_latent * (12 + 16 * len(maps) + lookup_bytes(w.latent))
     if stage == "tex_bwd":
         return px * 16 + covered_latent * sum(16 + 2 * TEXEL_C * 2 * bt for _, bt in maps)
     if stage == "aa_bwd":
-        return px * (8 + 12 + 12 + 12)                    # key, colour, dL/dimage, dL/dcolour
+        return px * (8 + 12 + 12 + 24 + 12)
     if stage == "aa_loss":
-        return px * (8 + 12 + 12 + 12) / 2.0              # per render (two per step, averaged)
+        if w.msaa > 1 or w.ref_ssaa > 1:
+            return None                                   # the resolve or downsample is a second kernel
+        return (px * (20 + 12) + px * (20 + 12 + 12 + 24)) / 2.0
     if stage == "shade":
-        # key in, colour out per shaded sample, averaged over the two renders
-        # of a step: the reference at ref_ssaa^2 and the latent at msaa^2
-        # samples per pixel
-        return px * (8 + 12) * (w.ref_ssaa ** 2 + w.msaa ** 2) / 2.0
+        ref = px * w.ref_ssaa ** 2 * (8 + 12) + covered_ref * lookup_bytes(w.ref)
+        lat = px * w.msaa ** 2 * (8 + 12) + covered_latent * lookup_bytes(w.latent)
+        return (ref + lat) / 2.0
     if stage == "skin_bwd" and st.get("skin"):
         V, nb = st["skin"]
         # per vertex: dL/dskinned read + cleared, bind position, blended
         # matrix, dL/dweights and dL/dpos read-modify-write; the bones once
         return V * (12 + 12 + 12 + 48 + 8 * nb + 24) + 48 * nb
     return None
+
+
+TRI_VIEW_BYTES = 100   # per triangle and view: transform, set-up and bin entry (the scope's model)
+
+
+def step_model_bytes(w, st, covered_latent, covered_ref, launches):
+    """Algorithmic bytes of one step: every stage with a byte model, times
+    its launches per step, plus the triangle set-up of both renders."""
+    total = 0.0
+    for stage, n in launches.items():
+        by = algorithmic_bytes(stage, w, st, covered_latent, covered_ref)
+        if by:
+            total += by * n
+    B = w.dirs.shape[0]
+    total += TRI_VIEW_BYTES * B * (int(w.ref.mesh.tri.shape[0]) + int(st["lat_mesh"].tri.shape[0]))
+    return total
+
+
+VALU_PEAK = 256 * 4 * 2.4e9 / 4 / 1e9   # wave64 VALU instructions per second: 16-lane SIMDs, 4 cycles each
+
+
+def pmc_valu(workload, stage):
+    """VALU instructions per launch of a stage's kernel from the committed
+    counter summary (SQ_INSTS_VALU x SQ_WAVES), or None if absent or stale."""
+    path = os.path.join(ROOT, "profiles", f"pmc_valu_{workload}.json")
+    if stage not in SINGLE_KERNEL_STAGES or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    k = d.get("kernels", {}).get(SINGLE_KERNEL_STAGES[stage][0])
+    if not k or k.get("sources_sha256") != kernel_sources_sha(SINGLE_KERNEL_STAGES[stage][1]):
+        return None
+    return k["valu_per_launch"]
+
+
+def stage_rooflines(w, st, covered, covered_ref, stages, workload):
+    """HBM (and, where VALU counters are committed, VALU-issue) fraction of
+    every single-kernel stage from the profiled pass."""
+    out = {}
+    for stage, (ms, cnt) in stages.items():
+        if stage not in SINGLE_KERNEL_STAGES or not cnt:
+            continue
+        avg_ms = ms / cnt
+        rec = {"kernel": SINGLE_KERNEL_STAGES[stage][0], "avg_launch_ms": round(avg_ms, 4)}
+        by = algorithmic_bytes(stage, w, st, covered, covered_ref)
+        if by:
+            ach = by / (avg_ms * 1e-3) / 1e9
+            rec["hbm"] = {"achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": round(by)}
+        # (with multisampling the antialiasing stage also holds the resolve)
+        valu = pmc_valu(workload, stage) if not (stage == "aa_loss" and w.msaa > 1) else None
+        if valu:
+            ach = valu / (avg_ms * 1e-3) / 1e9
+            rec["valu"] = {"achieved": round(ach, 1), "peak": VALU_PEAK, "unit": "G wave-instr/s",
+                           "frac": round(ach / VALU_PEAK, 4), "instr_per_launch": round(valu)}
+        out[stage] = rec
+    return out
 
 
 def cpu_baseline(w, np, torch, views, min_seconds=10.0, max_steps=4):
@@ -665,6 +765,9 @@ def main():
                     help="bit-reproducible gradients (fixed-point vertex sums, sorted texel sums)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/pmc_traffic_<workload>.json from rocprofv3 --pmc output and exit")
+    ap.add_argument("--pmc-valu-summary", metavar="PMC_DIR",
+                    help="write profiles/pmc_valu_<workload>.json from a rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU run "
+                         "and exit")
     ap.add_argument("--laplacian", action="store_true",
                     help="add the uniform Laplacian regularizer with the heuristic lambda_0 and its schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -688,6 +791,9 @@ def main():
         return
     if args.pmc_summary:
         summarize_pmc(args.workload, *args.pmc_summary)
+        return
+    if args.pmc_valu_summary:
+        summarize_valu(args.workload, args.pmc_valu_summary)
         return
     if args.workload == "batched":
         batched(args)
@@ -717,6 +823,7 @@ def main():
     else:
         covered = int((st["lat_out"]["tri_id"] > 0).sum()) // (w.msaa * w.msaa)
         st["lat_out"]["tri_id"] = None     # read for the count above only: the steps do not write it
+    covered_ref = int(((st["ref_out"]["vis"] & 0xFFFFFFFF) != 0).sum())
     _log(f"warmup {args.warmup}")
     for t in range(args.warmup):
         step(t)
@@ -745,7 +852,7 @@ def main():
             step(t)
         stages = read_stages()
         cands = {k: v[0] for k, v in stages.items()
-                 if v[1] > 0 and k in SINGLE_KERNEL_STAGES and algorithmic_bytes(k, w, st, covered) is not None}
+                 if v[1] > 0 and k in SINGLE_KERNEL_STAGES and algorithmic_bytes(k, w, st, covered, covered_ref) is not None}
         dom = max(cands, key=cands.get)
         for c in ctxs:
             c.profile_stages([dom])
@@ -791,7 +898,7 @@ def main():
     if dom:
         ms, cnt = timed[dom]
         avg_ms = ms / cnt
-        by = algorithmic_bytes(dom, w, st, covered)
+        by = algorithmic_bytes(dom, w, st, covered, covered_ref)
         ach = by / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": SINGLE_KERNEL_STAGES[dom][0], "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
@@ -801,9 +908,19 @@ def main():
     # achieved GB/s of every stage with an algorithmic byte count (profiled pass)
     stage_gbs = {}
     for k, (ms_k, cnt_k) in stages.items():
-        by_k = algorithmic_bytes(k, w, st, covered) if cnt_k else None
+        by_k = algorithmic_bytes(k, w, st, covered, covered_ref) if cnt_k else None
         if by_k:
             stage_gbs[k] = round(by_k / (ms_k / cnt_k * 1e-3) / 1e9, 1)
+    # every single-kernel stage against its roofline(s), and the whole step
+    # against the HBM ceiling of its algorithmic bytes
+    roofs = stage_rooflines(w, st, covered, covered_ref, stages, args.workload) if stages else {}
+    step_roof = None
+    if stages:
+        launches = {k: v[1] / n_prof for k, v in stages.items() if v[1] > 0}
+        sb = step_model_bytes(w, st, covered, covered_ref, launches)
+        ach = sb / (ms_step * 1e-3) / 1e9
+        step_roof = {"bytes_per_step": round(sb), "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "ceiling_ms": round(sb / (HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     cpu = None
     if not args.no_cpu_baseline:
         _log("oracle baseline")
@@ -823,8 +940,8 @@ def main():
                    "laplacian": bool(args.laplacian), "raster_split": st["raster_split"],
                    "reference_stream": "overlapped" if ctx_ref is not None else "same",
                    "final_loss": round(loss, 6)},
-        "roofline": roof, "cpu_baseline": cpu, "stage_avg_ms": prof, "stage_ms_per_step": stage_step,
-        "stage_gbs": stage_gbs,
+        "roofline": roof, "cpu_baseline": cpu, "roofline_stages": roofs, "step_roofline": step_roof,
+        "stage_avg_ms": prof, "stage_ms_per_step": stage_step, "stage_gbs": stage_gbs,
         "stage_pass_steps": n_prof if stages else 0,
     }
     print(json.dumps(rec), flush=True)

@@ -444,9 +444,9 @@ adr_status adr_skin_bwd(adr_ctx* ctx, const float* pos, const float* bones, cons
  * conversions, 13 skinning, 14 skinning adjoint, 15 layer blending and its
  * adjoint (depth peeling), 16 map Adam over level 0 with the adjoint and
  * rebuild of the levels inside its 32x32 tiles, 17 the levels above the
- * tiles (both adr_adam_step_maps).  ms and count: host arrays of
- * ADR_N_STAGES. */
-#define ADR_N_STAGES 18
+ * tiles (both adr_adam_step_maps), 18 the image loss's reduction of the
+ * per-block partial sums.  ms and count: host arrays of ADR_N_STAGES. */
+#define ADR_N_STAGES 19
 adr_status adr_ctx_profile(adr_ctx* ctx, int32_t enable);
 /* As adr_ctx_profile for the stages whose bits (1 << stage) are set in
  * stage_mask, the others untimed (0 disables).  Each bracketed stage stalls

@@ -42,10 +42,10 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
            "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster",
            "adr_adam_step_maps", "adr_ctx_profile_stages", "adr_render_fwd_noalloc")
-N_STAGES = 18
+N_STAGES = 19
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend",
-          "adam_maps", "adam_maps_top")
+          "adam_maps", "adam_maps_top", "loss_reduce")
 
 
 class AdrError(RuntimeError):

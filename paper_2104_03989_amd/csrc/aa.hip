@@ -50,9 +50,9 @@ struct Cross {
 
 // Projected corner relative to the NDC point X: (x - w X.x) / w, (y - w X.y) / w
 // (float64, from the float64 clip coordinates: edges of pixel-sized
-// triangles are short, and their edge functions cancel in float32).
-__device__ __forceinline__ void rel_proj(double4 c, double Xx, double Xy, double out[2]) {
-  double iw = 1.0 / c.w;
+// triangles are short, and their edge functions cancel in float32); iw is
+// 1 / w, shared by the corner's two uses.
+__device__ __forceinline__ void rel_proj(double4 c, double iw, double Xx, double Xy, double out[2]) {
   out[0] = (c.x - c.w * Xx) * iw;
   out[1] = (c.y - c.w * Xy) * iw;
 }
@@ -87,15 +87,16 @@ __device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi
     x.vb = v[vid[l]];
     double4 ca = clip_d(a.m.pos, a.v.mvp, b, x.va);
     double4 cb = clip_d(a.m.pos, a.v.mvp, b, x.vb);
-    double Px = 2.0 * ((double)Pi + 0.5) / (double)a.v.W - 1.0;
-    double Py = 2.0 * ((double)Pj + 0.5) / (double)a.v.H - 1.0;
-    double Qx = 2.0 * ((double)Qi + 0.5) / (double)a.v.W - 1.0;
-    double Qy = 2.0 * ((double)Qj + 0.5) / (double)a.v.H - 1.0;
+    double Px = ((double)Pi + 0.5) * a.v.sxs - 1.0;
+    double Py = ((double)Pj + 0.5) * a.v.sys - 1.0;
+    double Qx = ((double)Qi + 0.5) * a.v.sxs - 1.0;
+    double Qy = ((double)Qj + 0.5) * a.v.sys - 1.0;
     // e(X) = (b - a) x (X - a) = a' x b' with a' = a - X, b' = b - X
-    rel_proj(ca, Px, Py, x.aP);
-    rel_proj(cb, Px, Py, x.bP);
-    rel_proj(ca, Qx, Qy, x.aQ);
-    rel_proj(cb, Qx, Qy, x.bQ);
+    const double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
+    rel_proj(ca, iwa, Px, Py, x.aP);
+    rel_proj(cb, iwb, Px, Py, x.bP);
+    rel_proj(ca, iwa, Qx, Qy, x.aQ);
+    rel_proj(cb, iwb, Qx, Qy, x.bQ);
     x.eP = x.aP[0] * x.bP[1] - x.aP[1] * x.bP[0];
     x.eQ = x.aQ[0] * x.bQ[1] - x.aQ[1] * x.bQ[0];
     x.den = x.eP - x.eQ;
@@ -142,17 +143,35 @@ __device__ __forceinline__ float pow_inv24(float x) {
 __device__ __forceinline__ float srgb(float x) {
   return x <= 0.0031308f ? 12.92f * x : 1.055f * pow_inv24(x) - 0.055f;
 }
-// d srgb / dx = (1.055 / 2.4) x^(1/2.4 - 1) = (1.055 / 2.4) x^(1/2.4) / x.
-__device__ __forceinline__ float srgb_d(float x) {
-  return x <= 0.0031308f ? 12.92f : (1.055f / 2.4f) * pow_inv24(x) / x;
+// log(1 + a) for a >= 0: with u = 1 + a rounded, log(u) a / (u - 1) makes up
+// for the rounding of u (D. Goldberg, "What every computer scientist should
+// know about floating-point arithmetic", 1991), a few units in the last
+// place with the hardware logarithm and reciprocal; a itself where u rounds
+// to 1.
+__device__ __forceinline__ float log1p_pos(float a) {
+  const float u = 1.0f + a;
+  const float d = u - 1.0f;
+  return d == 0.f ? a : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (a * __builtin_amdgcn_rcpf(d));
 }
 // T(x) = sign(x) Gamma(log(1 + |x|)): the paper's tone map for x >= 0,
 // extended as an odd function to the negative radiance that freely optimised
 // texels can produce.
-__device__ __forceinline__ float tmap(float x) { return copysignf(srgb(log1pf(fabsf(x))), x); }
-__device__ __forceinline__ float tmap_d(float x) {
-  float a = fabsf(x);
-  return srgb_d(log1pf(a)) / (1.0f + a);
+__device__ __forceinline__ float tmap(float x) { return copysignf(srgb(log1p_pos(fabsf(x))), x); }
+// T(x) and T'(x) together: with y = log(1 + |x|), Gamma'(y) = 12.92 below the
+// knee, else (1.055 / 2.4) y^(1/2.4) / y, and T'(x) = Gamma'(y) / (1 + |x|).
+__device__ __forceinline__ float tmap_and_d(float x, float& d) {
+  const float a = fabsf(x);
+  const float y = log1p_pos(a);
+  float t;
+  if (y <= 0.0031308f) {
+    t = 12.92f * y;
+    d = 12.92f * __builtin_amdgcn_rcpf(1.0f + a);
+  } else {
+    const float p = pow_inv24(y);
+    t = 1.055f * p - 0.055f;
+    d = (1.055f / 2.4f) * p * __builtin_amdgcn_rcpf(y * (1.0f + a));
+  }
+  return copysignf(t, x);
 }
 
 // Code of the pair between pixel (i, j) and its neighbour in direction q
@@ -224,8 +243,9 @@ __device__ __forceinline__ float pixel_loss(f3 out, f3 r, int loss_kind, float i
   float lsum = 0.f;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    float d = tm ? tmap(ov[ch]) - tmap(rv[ch]) : ov[ch] - rv[ch];
-    float dt = tm ? tmap_d(ov[ch]) : 1.0f;
+    float dt = 1.0f, d;
+    if (tm) d = tmap_and_d(ov[ch], dt) - tmap(rv[ch]);
+    else d = ov[ch] - rv[ch];
     if (l1) {
       lsum += fabsf(d);
       gd[ch] = (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f)) * dt * inv_n;
@@ -272,8 +292,7 @@ __global__ __launch_bounds__(256) void k_msaa_resolve(ViewsD v, const float* __r
 // dL/d(antialiased sample): a sample carries 1/ms^2 of its pixel's gradient.
 __device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, int b, int i, int j) {
   if (a.v.ms == 1) return ldc(dimage, ((int64_t)b * a.v.H + j) * a.v.W + i);
-  const int Wp = a.v.W / a.v.ms, Hp = a.v.H / a.v.ms;
-  const int64_t op = ((int64_t)b * Hp + j / a.v.ms) * Wp + i / a.v.ms;
+  const int64_t op = ((int64_t)b * a.v.Hp + (j >> a.v.msh)) * a.v.Wp + (i >> a.v.msh);
   return (1.0f / (float)(a.v.ms * a.v.ms)) * ldc(dimage, op);
 }
 
@@ -526,10 +545,21 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
   } else {
     hipLaunchKernelGGL(k_aa_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage, s.partial);
   }
-  e = hipGetLastError();
-  if (e != hipSuccess || !ref) return e;
+  return hipGetLastError();
+}
+
+// The loss from the per-block partials of launch_aa_loss_fwd (a second,
+// one-block launch; nothing to do without a reference).
+hipError_t launch_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss, hipStream_t st) {
+  if (!ref) return hipSuccess;
+  int nb;
+  if (v.ms > 1) {
+    nb = (int)(((int64_t)v.B * v.Hp * v.Wp + 255) / 256);
+  } else {
+    nb = ((v.W + 15) / 16) * ((v.H + 15) / 16) * v.B;
+  }
   // partials hold sums; the mean's 1/N is applied here
-  const double n = 3.0 * (double)v.B * (v.H / v.ms) * (v.W / v.ms);
+  const double n = 3.0 * (double)v.B * v.Hp * v.Wp;
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, s.partial, nb, (float)(1.0 / n), loss);
   return hipGetLastError();
 }

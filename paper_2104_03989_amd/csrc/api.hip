@@ -224,6 +224,7 @@ adr_status check_common(adr_ctx* ctx, const adr_mesh* mesh, const adr_material* 
   v.W = views->width;
   v.H = views->height;
   v.ms = 1;
+  views_derive(v);
   return ADR_OK;
 }
 
@@ -328,6 +329,7 @@ static int apply_msaa(int32_t flags, ViewsD& v) {
   v.ms = ms;
   v.W *= ms;
   v.H *= ms;
+  views_derive(v);
   return ms;
 }
 
@@ -390,6 +392,7 @@ static adr_status fwd_launches(adr_ctx* ctx, const adr_mesh* mesh, const adr_mat
   STAGE(4, launch_aa_loss_fwd(m, v, s, out->vis, out->color, ref_image, loss_kind,
                             (flags & ADR_FWD_NO_AA) ? 1 : 0, out->image, out->dimage, out->loss, st, out->aa),
         "antialias/loss");
+  if (ref_image) STAGE(18, launch_loss_reduce(v, ref_image, s, out->loss, st), "loss reduction");
   return ADR_OK;
 }
 
@@ -721,6 +724,7 @@ adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
                                 out->comp + 3 * k * npx, k == 0 ? out->dimage : nullptr, k == 0 ? out->loss : nullptr,
                                 st, out->aa ? out->aa + 8 * k * npx : nullptr),
           "antialias/loss");
+    if (k == 0 && ref_image) TIMED(18, launch_loss_reduce(v, ref_image, s, out->loss, st), "loss reduction");
   }
   return ADR_OK;
 }

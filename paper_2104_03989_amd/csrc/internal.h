@@ -38,7 +38,23 @@ struct ViewsD {
   const float* light_rgb;
   int B, W, H;  // W, H: visibility samples per row / column (pixels x ms)
   int ms;       // multisampling: ms x ms visibility samples per pixel (1: none)
+  // derived on the host (views_derive): log2 ms, the pixel grid, and the NDC
+  // step of one pixel and of one sample (uniform divisions kept out of the
+  // per-pixel code)
+  int msh, Wp, Hp;
+  double pxs, pys, sxs, sys;
 };
+
+// Fills the derived fields of v from B, W, H and ms (ms 1, 2 or 4).
+inline void views_derive(ViewsD& v) {
+  v.msh = v.ms == 4 ? 2 : (v.ms == 2 ? 1 : 0);
+  v.Wp = v.W >> v.msh;
+  v.Hp = v.H >> v.msh;
+  v.pxs = v.Wp > 0 ? 2.0 / v.Wp : 0.0;
+  v.pys = v.Hp > 0 ? 2.0 / v.Hp : 0.0;
+  v.sxs = v.W > 0 ? 2.0 / v.W : 0.0;
+  v.sys = v.H > 0 ? 2.0 / v.H : 0.0;
+}
 
 // Per-call scratch owned by the context.
 struct Scratch {
@@ -122,6 +138,8 @@ hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
                               hipStream_t st, float* stats = nullptr);
+// The image loss from the partials the forward above left (ref non-NULL).
+hipError_t launch_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss, hipStream_t st);
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st, const float* stats = nullptr);

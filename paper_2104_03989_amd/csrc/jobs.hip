@@ -3,12 +3,17 @@
 // initial latent model in; optimised mesh and maps out), admitted by HBM
 // budget, kept resident on the device and stepped by one server thread.
 //
-// Continuous batching: between rounds the server admits queued jobs as
-// memory frees; in a round it enqueues one step of every active job, each
-// job on one of kSlots streams (each stream with its own context, so their
-// scratch never races), so steps of different jobs overlap on the device.
-// Per-step latency is host time from a step's enqueue to its completion
-// event; p50/p99 are reported per job.
+// Continuous batching: the server keeps kSlots execution slots (a stream and
+// a context whose scratch serves one step at a time).  Whenever a slot's step
+// completes (polled with hipEventQuery), the slot takes the next ready job
+// (round robin over the active jobs, at most one step of a job in flight),
+// so steps of different jobs overlap on the device and a job never waits for
+// a round of other jobs.  Queued jobs are admitted between any two
+// dispatches as soon as their footprint, plus the slots' scratch for their
+// shapes, fits the budget; their uploads run on an admission stream of
+// their own.  Per-step latency is device time from an event recorded when
+// the step is enqueued to the step's completion event; p50/p99 are reported
+// per job.
 //
 // Cameras and lights of every step are drawn at admission from a
 // counter-based generator (SplitMix64, Steele, Lea and Flood 2014: value i
@@ -108,7 +113,6 @@ struct JobTex {
 struct Job {
   uint64_t id = 0;
   int state = ADR_JOB_QUEUED;
-  int slot = 0;
   int step = 0;
   float last_loss = 0.f;
   size_t footprint = 0;
@@ -128,35 +132,44 @@ struct Job {
   uint64_t *ref_vis = nullptr, *vis = nullptr;
   float *ref_color = nullptr, *ref_image = nullptr, *color = nullptr, *dimage = nullptr, *loss = nullptr;
   float* loss_host = nullptr;  // pinned
-  hipEvent_t done_ev = nullptr;
-  Clock::time_point t_enq;
+  hipEvent_t start_ev = nullptr, done_ev = nullptr;
+  bool in_flight = false;      // a step of this job is on a slot
   std::vector<float> lat_ms;
   // results
   std::vector<float> out_pos, out_normal, out_orm;
   std::vector<uint8_t> out_kd;
 };
 
+// An execution slot: a stream, a context whose scratch serves the step on
+// it, the latent forward's received antialiasing (read by the backward that
+// follows it), and the job whose step it runs.
+struct Slot {
+  adr_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  float* aa = nullptr;
+  size_t aa_cap = 0;
+  Job* job = nullptr;
+};
+
 struct JobServer {
   adr_ctx* owner = nullptr;
   int device = 0;
   uint64_t budget = 0;
-  uint64_t used = 0;
+  uint64_t used = 0;            // resident jobs' footprints
+  uint64_t scratch_hw = 0;      // per-slot scratch the admitted shapes need (grows, never shrinks)
   uint64_t next_id = 1;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<uint64_t> queue;
   std::map<uint64_t, std::unique_ptr<Job>> jobs;
   std::vector<uint64_t> active;
+  size_t rr = 0;                // round-robin cursor over active
   std::thread th;
   bool stop = false;
   bool started = false;
-  adr_ctx* slot_ctx[kSlots] = {nullptr, nullptr, nullptr, nullptr};
-  hipStream_t slot_stream[kSlots] = {nullptr, nullptr, nullptr, nullptr};
-  // per slot: the latent forward's received antialiasing, read by the
-  // backward that follows it on the slot's stream (grown on demand)
-  float* slot_aa[kSlots] = {nullptr, nullptr, nullptr, nullptr};
-  size_t slot_aa_cap[kSlots] = {0, 0, 0, 0};
-  int next_slot = 0;
+  Slot slot[kSlots];
+  adr_ctx* adm_ctx = nullptr;   // admission: uploads, reference frame, mip chains
+  hipStream_t adm_stream = nullptr;
 };
 
 namespace {
@@ -207,11 +220,25 @@ size_t job_bytes(const adr_job_desc& d) {
   add(B * HW * 8 * 2);          // visibility of reference and latent
   add(B * HW * 12 * 4);         // reference colour and image, latent colour and dL/dimage
   add(256);                     // loss
-  // share of the slot context's scratch (float64 clip, snap, orientation, lists,
-  // dL/dcolour, d clip ...) for the larger of the two meshes
-  size_t V = std::max(d.ref_n_pos, d.lat_n_pos), T = std::max(d.ref_n_tri, d.lat_n_tri);
-  add(B * V * (32 + 16 + 16) + B * T * 5 + V * 120 + B * HW * 12);
   return s;
+}
+
+// Scratch a slot needs to step a job of this shape: the slot context's
+// buffers as the render calls size them (for the larger of the two meshes,
+// with the growth margin of a quarter the context allocates), and the
+// slot's received-antialiasing buffer.
+size_t slot_scratch_bytes(const adr_job_desc& d) {
+  const size_t B = d.n_views, HW = (size_t)d.width * d.height;
+  const size_t V = std::max(d.ref_n_pos, d.lat_n_pos), T = std::max(d.ref_n_tri, d.lat_n_tri);
+  const size_t tiles = (size_t)((d.width + 15) / 16) * ((d.height + 15) / 16) * B;
+  const size_t maps = 1 + ((d.opt_mask & 2) ? 1 : 0) + ((d.opt_mask & 4) ? 1 : 0) +
+                      (((d.opt_mask & 8) && d.model == ADR_SHADE_GGX) ? 1 : 0);
+  const size_t parts[] = {B * V * 16, B * T, V * 24, V * 24, V * 12, V * 12, B * T * 4, (B + 1) * 4, B * T * 4,
+                          tiles * 4, B * HW * 12, B * V * 16, V * 36, maps * B * HW * 16, V * 72, B * V * 32,
+                          V * 24};
+  size_t s = 0;
+  for (size_t x : parts) s += align256(x + x / 4);
+  return s + align256(B * HW * 32);
 }
 
 adr_status copy_desc(Job& j, const adr_job_desc& d, char* msg, size_t n) {
@@ -285,7 +312,7 @@ adr_status admit(JobServer* s, Job& j, hipStream_t st, adr_ctx* ctx) {
   const adr_job_desc& d = j.d;
   if (hipMalloc(&j.block, j.footprint) != hipSuccess) return ADR_E_NOMEM;
   if (hipHostMalloc((void**)&j.loss_host, sizeof(float)) != hipSuccess) return ADR_E_NOMEM;
-  if (hipEventCreateWithFlags(&j.done_ev, hipEventDisableTiming) != hipSuccess) return ADR_E_HIP;
+  if (hipEventCreate(&j.start_ev) != hipSuccess || hipEventCreate(&j.done_ev) != hipSuccess) return ADR_E_HIP;
   char* p = (char*)j.block;
   auto take = [&](size_t bytes) {
     void* r = p;
@@ -387,17 +414,21 @@ adr_status admit(JobServer* s, Job& j, hipStream_t st, adr_ctx* ctx) {
 void release_dev(Job& j) {
   if (j.block) (void)hipFree(j.block);
   if (j.loss_host) (void)hipHostFree(j.loss_host);
+  if (j.start_ev) (void)hipEventDestroy(j.start_ev);
   if (j.done_ev) (void)hipEventDestroy(j.done_ev);
   j.block = nullptr;
   j.loss_host = nullptr;
+  j.start_ev = nullptr;
   j.done_ev = nullptr;
 }
 
-// One optimisation step of job j on its slot's stream.
-adr_status enqueue_step(JobServer* s, Job& j) {
+// One optimisation step of job j on slot sl, bracketed by the job's start
+// and completion events.
+adr_status enqueue_step(Slot& sl, Job& j) {
   const adr_job_desc& d = j.d;
-  adr_ctx* ctx = s->slot_ctx[j.slot];
-  hipStream_t st = s->slot_stream[j.slot];
+  adr_ctx* ctx = sl.ctx;
+  hipStream_t st = sl.st;
+  if (hipEventRecord(j.start_ev, st) != hipSuccess) return ADR_E_HIP;
   size_t B = d.n_views;
   adr_views v{j.mvp + 16 * B * j.step, j.eye + 3 * B * j.step, j.light + 3 * B * j.step,
               j.rgb + 3 * B * j.step, (int)B, d.width, d.height};
@@ -407,14 +438,14 @@ adr_status enqueue_step(JobServer* s, Job& j) {
   adr_status r = adr_render_fwd(ctx, &j.ref_mesh, &rm, &v, nullptr, 0, &ro, 0, st);
   if (r != ADR_OK) return r;
   const size_t aa_bytes = B * (size_t)d.width * d.height * 32;
-  if (s->slot_aa_cap[j.slot] < aa_bytes) {
-    if (s->slot_aa[j.slot] && hipFree(s->slot_aa[j.slot]) != hipSuccess) return ADR_E_HIP;
-    s->slot_aa[j.slot] = nullptr;
-    s->slot_aa_cap[j.slot] = 0;
-    if (hipMalloc(&s->slot_aa[j.slot], aa_bytes) != hipSuccess) return ADR_E_NOMEM;
-    s->slot_aa_cap[j.slot] = aa_bytes;
+  if (sl.aa_cap < aa_bytes) {
+    if (sl.aa && hipFree(sl.aa) != hipSuccess) return ADR_E_HIP;
+    sl.aa = nullptr;
+    sl.aa_cap = 0;
+    if (hipMalloc(&sl.aa, aa_bytes) != hipSuccess) return ADR_E_NOMEM;
+    sl.aa_cap = aa_bytes;
   }
-  adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr, s->slot_aa[j.slot]};
+  adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr, sl.aa};
   // the map Adam rebuilds the latent chains after every step; the first
   // forward builds them
   r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, j.step == 0 ? ADR_FWD_BUILD_MIPS : 0,
@@ -441,9 +472,10 @@ adr_status enqueue_step(JobServer* s, Job& j) {
   return ADR_OK;
 }
 
-void finish(JobServer* s, Job& j) {
+// Copies the optimised model to host memory and releases the job's device
+// memory (on a stream the job's steps are complete on).
+void finish(hipStream_t st, Job& j) {
   const adr_job_desc& d = j.d;
-  hipStream_t st = s->slot_stream[j.slot];
   j.out_pos.resize(3 * (size_t)d.lat_n_pos);
   (void)hipMemcpyAsync(j.out_pos.data(), j.lat_mesh.pos, j.out_pos.size() * 4, hipMemcpyDeviceToHost, st);
   size_t kdb = (size_t)j.kd.size * j.kd.size * (j.kd.fmt == ADR_TEX_RGBA8 ? 4 : 12);
@@ -459,103 +491,135 @@ void finish(JobServer* s, Job& j) {
   release_dev(j);
 }
 
+// Admits queued jobs in arrival order while their footprint and the slots'
+// scratch for their shapes fit the budget.  Called with the lock held; drops
+// it while a job uploads.
+void admit_queued(JobServer* s, std::unique_lock<std::mutex>& lk) {
+  while (!s->queue.empty()) {
+    Job& j = *s->jobs.at(s->queue.front());
+    const uint64_t hw = std::max<uint64_t>(s->scratch_hw, slot_scratch_bytes(j.d));
+    if (s->used + j.footprint + (uint64_t)kSlots * hw > s->budget) break;
+    s->queue.pop_front();
+    s->used += j.footprint;
+    s->scratch_hw = hw;
+    lk.unlock();
+    adr_status r = admit(s, j, s->adm_stream, s->adm_ctx);
+    lk.lock();
+    if (r != ADR_OK) {
+      snprintf(j.why, sizeof(j.why), "admission failed (%d): %s", r, adr_last_error());
+      release_dev(j);
+      s->used -= j.footprint;
+      j.state = ADR_JOB_FAILED;
+    } else {
+      j.state = ADR_JOB_RUNNING;
+      s->active.push_back(j.id);
+    }
+  }
+}
+
+// A completed step of the job on slot sl: loss, device latency, and the
+// job's end (done or failed).  Called with the lock held.
+void complete(JobServer* s, Slot& sl) {
+  Job& j = *sl.job;
+  sl.job = nullptr;
+  j.in_flight = false;
+  float ms = 0.f;
+  hipError_t e = hipEventElapsedTime(&ms, j.start_ev, j.done_ev);
+  const float loss = *j.loss_host;
+  if (e != hipSuccess) {
+    snprintf(j.why, sizeof(j.why), "step %d: %s", j.step + 1, hipGetErrorString(e));
+    j.state = ADR_JOB_FAILED;
+  } else if (!std::isfinite(loss)) {
+    snprintf(j.why, sizeof(j.why), "non-finite loss %g at step %d", loss, j.step + 1);
+    j.state = ADR_JOB_FAILED;
+  } else {
+    j.lat_ms.push_back(ms);
+    j.last_loss = loss;
+    j.step += 1;
+  }
+  if (j.state == ADR_JOB_FAILED) {
+    release_dev(j);
+    s->used -= j.footprint;
+  } else if (j.step >= j.d.n_steps) {
+    finish(sl.st, j);
+    s->used -= j.footprint;
+    j.state = ADR_JOB_DONE;
+  } else {
+    return;
+  }
+  s->active.erase(std::find(s->active.begin(), s->active.end(), j.id));
+}
+
+// The next active job with no step in flight, round robin; or null.
+Job* next_ready(JobServer* s) {
+  const size_t n = s->active.size();
+  for (size_t k = 0; k < n; ++k) {
+    const size_t i = (s->rr + k) % n;
+    Job* j = s->jobs.at(s->active[i]).get();
+    if (!j->in_flight) {
+      s->rr = (i + 1) % n;
+      return j;
+    }
+  }
+  return nullptr;
+}
+
 void server_loop(JobServer* s) {
   (void)hipSetDevice(s->device);
-  while (true) {
-    std::vector<Job*> round;
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->stop) break;
-      // admit queued jobs in arrival order while they fit
-      while (!s->queue.empty()) {
-        Job& j = *s->jobs.at(s->queue.front());
-        if (s->used + j.footprint > s->budget) break;
-        s->queue.pop_front();
-        s->used += j.footprint;
-        j.slot = s->next_slot;
-        s->next_slot = (s->next_slot + 1) % kSlots;
-        lk.unlock();
-        adr_status r = admit(s, j, s->slot_stream[j.slot], s->slot_ctx[j.slot]);
-        lk.lock();
-        if (r != ADR_OK) {
-          snprintf(j.why, sizeof(j.why), "admission failed (%d): %s", r, adr_last_error());
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    admit_queued(s, lk);
+    int busy = 0;
+    for (Slot& sl : s->slot) {
+      if (sl.job) {
+        // a finished step frees its slot at once
+        const hipError_t q = hipEventQuery(sl.job->done_ev);
+        if (q == hipErrorNotReady) {
+          ++busy;
+          continue;
+        }
+        if (q != hipSuccess) {
+          Job& j = *sl.job;
+          snprintf(j.why, sizeof(j.why), "step %d: %s", j.step + 1, hipGetErrorString(q));
+          j.state = ADR_JOB_FAILED;
+          j.in_flight = false;
+          sl.job = nullptr;
+          (void)hipStreamSynchronize(sl.st);
           release_dev(j);
           s->used -= j.footprint;
-          j.state = ADR_JOB_FAILED;
-        } else {
-          j.state = ADR_JOB_RUNNING;
-          s->active.push_back(j.id);
+          s->active.erase(std::find(s->active.begin(), s->active.end(), j.id));
+          continue;
         }
+        complete(s, sl);
       }
-      if (s->active.empty()) {
-        if (s->stop) break;
-        s->cv.wait_for(lk, std::chrono::milliseconds(50));
-        continue;
-      }
-      for (uint64_t id : s->active) round.push_back(s->jobs.at(id).get());
-    }
-    // One step of every active job, interleaved over the slot streams.  The
-    // jobs stay RUNNING (so a poll never releases them) until the results of
-    // the round are applied under the lock below.
-    struct Outcome {
-      bool ok;
-      float ms, loss;
-      char why[200];
-    };
-    std::vector<Outcome> res(round.size());
-    for (size_t i = 0; i < round.size(); ++i) {
-      Job* j = round[i];
-      j->t_enq = Clock::now();
-      adr_status r = enqueue_step(s, *j);
-      res[i].ok = r == ADR_OK;
-      if (!res[i].ok)
-        snprintf(res[i].why, sizeof(res[i].why), "step %d could not be launched (%d): %s", j->step + 1, r,
+      // the free slot takes the next ready job
+      Job* j = next_ready(s);
+      if (!j) continue;
+      j->in_flight = true;
+      sl.job = j;
+      adr_status r = enqueue_step(sl, *j);
+      if (r != ADR_OK) {
+        snprintf(j->why, sizeof(j->why), "step %d could not be launched (%d): %s", j->step + 1, r,
                  adr_last_error());
-    }
-    for (size_t i = 0; i < round.size(); ++i) {
-      Job* j = round[i];
-      if (!res[i].ok) continue;
-      hipError_t e = hipEventSynchronize(j->done_ev);
-      if (e != hipSuccess) {
-        res[i].ok = false;
-        snprintf(res[i].why, sizeof(res[i].why), "step %d: %s", j->step + 1, hipGetErrorString(e));
+        j->state = ADR_JOB_FAILED;
+        j->in_flight = false;
+        sl.job = nullptr;
+        (void)hipStreamSynchronize(sl.st);
+        release_dev(*j);
+        s->used -= j->footprint;
+        s->active.erase(std::find(s->active.begin(), s->active.end(), j->id));
         continue;
       }
-      res[i].ms = (float)std::chrono::duration<double, std::milli>(Clock::now() - j->t_enq).count();
-      res[i].loss = *j->loss_host;
-      if (!std::isfinite(res[i].loss)) {
-        res[i].ok = false;
-        snprintf(res[i].why, sizeof(res[i].why), "non-finite loss %g at step %d", res[i].loss, j->step + 1);
-      }
+      ++busy;
     }
-    std::lock_guard<std::mutex> lk(s->mu);
-    for (size_t i = 0; i < round.size(); ++i) {
-      Job* j = round[i];
-      if (res[i].ok) {
-        j->lat_ms.push_back(res[i].ms);
-        j->last_loss = res[i].loss;
-        j->step += 1;
-      } else {
-        memcpy(j->why, res[i].why, sizeof(j->why));
-        j->state = ADR_JOB_FAILED;
-      }
+    if (busy == 0 && s->queue.empty()) {
+      s->cv.wait_for(lk, std::chrono::milliseconds(50));
+    } else {
+      // steps take about a millisecond: poll their events every 20 us
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
     }
-    std::vector<uint64_t> keep;
-    for (uint64_t id : s->active) {
-      Job& j = *s->jobs.at(id);
-      if (j.state == ADR_JOB_FAILED) {
-        (void)hipStreamSynchronize(s->slot_stream[j.slot]);
-        release_dev(j);
-        s->used -= j.footprint;
-      } else if (j.step >= j.d.n_steps) {
-        finish(s, j);
-        s->used -= j.footprint;
-        j.state = ADR_JOB_DONE;
-      } else {
-        keep.push_back(id);
-      }
-    }
-    s->active.swap(keep);
   }
 }
 
@@ -575,11 +639,16 @@ JobServer* jobs_create(adr_ctx* owner, int device, uint64_t budget) {
   s->device = device;
   s->budget = budget;
   for (int k = 0; k < kSlots; ++k) {
-    if (adr_ctx_create(device, budget, &s->slot_ctx[k]) != ADR_OK ||
-        hipStreamCreateWithFlags(&s->slot_stream[k], hipStreamNonBlocking) != hipSuccess) {
+    if (adr_ctx_create(device, budget, &s->slot[k].ctx) != ADR_OK ||
+        hipStreamCreateWithFlags(&s->slot[k].st, hipStreamNonBlocking) != hipSuccess) {
       jobs_destroy(s);
       return nullptr;
     }
+  }
+  if (adr_ctx_create(device, budget, &s->adm_ctx) != ADR_OK ||
+      hipStreamCreateWithFlags(&s->adm_stream, hipStreamNonBlocking) != hipSuccess) {
+    jobs_destroy(s);
+    return nullptr;
   }
   return s;
 }
@@ -593,12 +662,15 @@ void jobs_destroy(JobServer* s) {
   }
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
+  (void)hipDeviceSynchronize();  // steps still in flight
   for (auto& kv : s->jobs) release_dev(*kv.second);
-  for (int k = 0; k < kSlots; ++k) {
-    if (s->slot_aa[k]) (void)hipFree(s->slot_aa[k]);
-    if (s->slot_stream[k]) (void)hipStreamDestroy(s->slot_stream[k]);
-    if (s->slot_ctx[k]) adr_ctx_destroy(s->slot_ctx[k]);
+  for (Slot& sl : s->slot) {
+    if (sl.aa) (void)hipFree(sl.aa);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+    if (sl.ctx) adr_ctx_destroy(sl.ctx);
   }
+  if (s->adm_stream) (void)hipStreamDestroy(s->adm_stream);
+  if (s->adm_ctx) adr_ctx_destroy(s->adm_ctx);
   delete s;
 }
 
@@ -607,8 +679,10 @@ adr_status jobs_submit(JobServer* s, const adr_job_desc* d, uint64_t* id, char* 
   adr_status r = copy_desc(*j, *d, msg, n);
   if (r != ADR_OK) return r;
   j->footprint = job_bytes(j->d);
-  if (j->footprint > s->budget) {
-    snprintf(msg, n, "job needs %zu bytes, budget is %llu", j->footprint, (unsigned long long)s->budget);
+  const uint64_t need = j->footprint + (uint64_t)kSlots * slot_scratch_bytes(j->d);
+  if (need > s->budget) {
+    snprintf(msg, n, "job needs %llu bytes (with the slots' scratch for its shape), budget is %llu",
+             (unsigned long long)need, (unsigned long long)s->budget);
     return ADR_E_OVER_BUDGET;
   }
   std::lock_guard<std::mutex> lk(s->mu);

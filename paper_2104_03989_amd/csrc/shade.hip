@@ -43,9 +43,8 @@ __device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, int
                                            int j, const int* v, BaryD& d) {
   // (i, j) is a visibility sample; shading is evaluated once per pixel, at
   // the centre of the sample's pixel, with derivatives per pixel
-  const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
-  d.px = 2.0 * ((double)(i / vw.ms) + 0.5) / (double)Wp - 1.0;
-  d.py = 2.0 * ((double)(j / vw.ms) + 0.5) / (double)Hp - 1.0;
+  d.px = ((double)(i >> vw.msh) + 0.5) * vw.pxs - 1.0;
+  d.py = ((double)(j >> vw.msh) + 0.5) * vw.pys - 1.0;
   double D[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -78,9 +77,8 @@ struct PixelGeom {
 __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
                                            const float* nrm, const float* tan, int b, int i,
                                            int j, int tri, PixelGeom& g) {
-  const int Wp = vw.W / vw.ms, Hp = vw.H / vw.ms;
-  g.sx = 2.0f / (float)Wp;
-  g.sy = 2.0f / (float)Hp;
+  g.sx = (float)vw.pxs;
+  g.sy = (float)vw.pys;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     g.v[c] = m.tri[3 * tri + c];
@@ -98,8 +96,8 @@ __device__ __forceinline__ void pixel_geom(const MeshD& m, const ViewsD& vw,
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
     double lam = (d.gx[j1] * d.gy[k1] - d.gy[j1] * d.gx[k1]) * iS;
     g.lam[c] = (float)lam;
-    g.lx[c] = (float)((d.a[c] - lam * A) * iS * (2.0 / Wp));
-    g.ly[c] = (float)((d.b[c] - lam * Bs) * iS * (2.0 / Hp));
+    g.lx[c] = (float)((d.a[c] - lam * A) * iS * vw.pxs);
+    g.ly[c] = (float)((d.b[c] - lam * Bs) * iS * vw.pys);
     if (c > 0) {
       ud += lam * ((double)m.uv[2 * g.t[c]] - (double)u0);
       vd += lam * ((double)m.uv[2 * g.t[c] + 1] - (double)v0);
@@ -338,31 +336,6 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
 }
 
 // -------------------------------------------------------------- backward
-
-// Adjoint of one trilinear lookup w.r.t. (u, v) and, through the LOD, the
-// screen derivatives (ux, vx, uy, vy), from the lookup's own derivatives
-// (its texel gradients go to the texel scatter as a sample record).
-struct UVGrad {
-  float u, v, ux, vx, uy, vy;
-};
-
-__device__ __forceinline__ void uv_bwd(const Tex& t, const PixelGeom& g, const Lod& L, const TriSample& r, f3 gs,
-                                       UVGrad& G) {
-  if (L.has1 && L.grad) {
-    // lod = 0.5 log2(m), m = max over x/y of |duv * size|^2
-    float g_m = dot(gs, r.dl) * 0.5f / (L.m * 0.69314718055994531f);
-    float S2 = (float)t.size * (float)t.size;
-    if (L.use_x) {
-      G.ux += g_m * 2.f * g.ux * S2;
-      G.vx += g_m * 2.f * g.vx * S2;
-    } else {
-      G.uy += g_m * 2.f * g.uy * S2;
-      G.vy += g_m * 2.f * g.vy * S2;
-    }
-  }
-  G.u += dot(gs, r.du);
-  G.v += dot(gs, r.dv);
-}
 
 // ---- wave-aggregated texel-gradient scatter ----
 //
@@ -613,6 +586,78 @@ __device__ __forceinline__ void put_rec(const RecOut& ro, int m, const Lod& L, f
 // soon as it is formed (neither is held in registers to the end); the maps'
 // levels are returned in lv for the record header.  Returns false if the
 // pixel contributes nothing.
+// Gradient w.r.t. the texture coordinates and their screen derivatives.
+struct UVGrad {
+  float u, v, ux, vx, uy, vy;
+};
+
+// A lookup's derivatives parked in the pixel's LDS column between the
+// lookups and the shading adjoint (the column is free then: the vertex
+// gradients are written after), 3 rows per channel: d/du, d/dv and the level
+// difference scaled by the LOD's derivative w.r.t. m (zero where the LOD is
+// not differentiated).  Rows: kd 0-8, normal 9-17, orm 18-26, alpha 27-29;
+// rows 30-35 keep the set-up's barycentrics and position indices until the
+// end of the pixel's adjoint.
+constexpr int kParkLam = 30;
+__device__ __forceinline__ void stash_sample(float* col, int row, int ch, const TriSample& s, const Lod& L) {
+  const float k = (L.has1 && L.grad) ? 0.5f / (L.m * 0.69314718055994531f) : 0.f;
+  const float du[3] = {s.du.x, s.du.y, s.du.z}, dv[3] = {s.dv.x, s.dv.y, s.dv.z};
+  const float dl[3] = {s.dl.x, s.dl.y, s.dl.z};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c >= ch) break;
+    col[(row + 3 * c) * kAccStride] = du[c];
+    col[(row + 3 * c + 1) * kAccStride] = dv[c];
+    col[(row + 3 * c + 2) * kAccStride] = dl[c] * k;
+  }
+}
+
+// Adjoint of one trilinear lookup w.r.t. (u, v) and, through the LOD, the
+// screen derivatives, from the derivatives stash_sample parked.
+__device__ __forceinline__ void uv_bwd_parked(const float* col, int row, int ch, const Tex& t, bool use_x,
+                                              const PixelGeom& g, f3 gs, UVGrad& G) {
+  const float gv[3] = {gs.x, gs.y, gs.z};
+  float gu = 0.f, gw = 0.f, gm = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c >= ch) break;
+    gu += gv[c] * col[(row + 3 * c) * kAccStride];
+    gw += gv[c] * col[(row + 3 * c + 1) * kAccStride];
+    gm += gv[c] * col[(row + 3 * c + 2) * kAccStride];
+  }
+  G.u += gu;
+  G.v += gw;
+  // lod = 0.5 log2(m), m = max over x/y of |duv * size|^2 (gm is zero where
+  // the LOD is not differentiated)
+  const float S2 = (float)t.size * (float)t.size;
+  if (use_x) {
+    G.ux += gm * 2.f * g.ux * S2;
+    G.vx += gm * 2.f * g.vx * S2;
+  } else {
+    G.uy += gm * 2.f * g.uy * S2;
+    G.vy += gm * 2.f * g.vy * S2;
+  }
+}
+
+// Adjoint of safe_normalize from the normalised vector y and inv = 1/|x|
+// (0 when safe_normalize passed x through unchanged).
+__device__ __forceinline__ f3 normalize_bwd_y(f3 y, float inv, f3 g) {
+  return inv > 0.f ? inv * (g - dot(g, y) * y) : g;
+}
+__device__ __forceinline__ float inv_norm(f3 x) {
+  float n2 = dot(x, x);
+  return n2 > 1e-20f ? rsqrtf(n2) : 0.f;
+}
+
+// Adjoint of one pixel.  The vertex gradients are written to the pixel's
+// column of the wave's LDS table (col[k * kAccStride], k < kVtxAcc) as they
+// are computed, and each texture lookup's sample gradient record to HBM as
+// soon as it is formed (neither is held in registers to the end); the maps'
+// levels are returned in lv for the record header.  Returns false if the
+// pixel contributes nothing.  Register pressure decides this kernel's
+// speed (it runs latency-bound): the lookups' derivatives wait in LDS during
+// the shading adjoint, and of the tangent frame only N, T', T and the two
+// inverse lengths stay live.
 template <bool ALPHA>
 __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p,
                                                 const float* __restrict__ gcolor, float* col,
@@ -627,49 +672,78 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   tri = (int)id - 1;
   PixelGeom g;
   pixel_geom(a.m, a.v, a.nrm, a.tan, p.b, p.i, p.j, (int)id - 1, g);
-  Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
-  const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, g.ul, g.vl, Lk);
-  f3 kd = sk.val;
-  Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
-  const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln);
-  f3 nt = sn.val;
-  f3 mraw = nt.x * g.Tp + nt.y * g.Bt + nt.z * g.N;
-  f3 n = safe_normalize(mraw);
-  f3 eye = ld3(a.v.eye, p.b);
-  f3 vraw = eye - g.x;
-  f3 vdir = safe_normalize(vraw);
-  f3 l = ld3(a.v.light_dir, p.b);
-  f3 E = ld3(a.v.light_rgb, p.b);
-  f3 gn, gv, gkdv, gormv = mk(0.f, 0.f, 0.f);
-  Lod Lo;
-  TriSample so;
-  if (a.model == ADR_SHADE_GGX) {
-    Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
-    so = tex_trilinear(a.orm, g.u, g.v_, g.ul, g.vl, Lo);
-    ggx_bwd(n, vdir, l, kd, so.val, E, gc, gn, gv, gkdv, gormv);
-  } else {
-    blinn_phong_bwd(n, vdir, l, kd, E, gc, gn, gv, gkdv);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    col[(kParkLam + c) * kAccStride] = g.lam[c];
+    col[(kParkLam + 3 + c) * kAccStride] = __int_as_float(g.v[c]);
   }
+  const bool ggx_m = a.model == ADR_SHADE_GGX;
+  const Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
+  const Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
+  f3 kd, nt, ormv = mk(0.f, 0.f, 0.f);
+  {
+    const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, g.ul, g.vl, Lk);
+    kd = sk.val;
+    stash_sample(col, 0, 3, sk, Lk);
+  }
+  {
+    const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln);
+    nt = sn.val;
+    stash_sample(col, 9, 3, sn, Ln);
+  }
+  Lod Lo{};
+  if (ggx_m) {
+    Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
+    const TriSample so = tex_trilinear(a.orm, g.u, g.v_, g.ul, g.vl, Lo);
+    ormv = so.val;
+    stash_sample(col, 18, 3, so, Lo);
+  }
+  Lod La{};
+  float alpha_t = 0.f;
+  if (ALPHA && a.al.data) {
+    La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
+    const TriSample sa = tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La);
+    alpha_t = sa.val.x;
+    stash_sample(col, 27, 1, sa, La);
+  }
+  // the tangent frame, compact: N, T', T and 1/|Ni|, 1/|T1| (B = N x T')
+  const f3 N = g.N, Tp = g.Tp, T = g.T;
+  const float invNi = inv_norm(g.Ni), invT1 = inv_norm(g.T1);
+  f3 gkdv, gormv = mk(0.f, 0.f, 0.f), gm, gx;
+  {
+    const f3 Bt = cross(N, Tp);
+    const f3 mraw = nt.x * Tp + nt.y * Bt + nt.z * N;
+    const f3 n = safe_normalize(mraw);
+    const f3 vraw = ld3(a.v.eye, p.b) - g.x;
+    const f3 vdir = safe_normalize(vraw);
+    const f3 l = ld3(a.v.light_dir, p.b);
+    const f3 E = ld3(a.v.light_rgb, p.b);
+    f3 gn, gv;
+    if (ggx_m) {
+      ggx_bwd(n, vdir, l, kd, ormv, E, gc, gn, gv, gkdv, gormv);
+    } else {
+      blinn_phong_bwd(n, vdir, l, kd, E, gc, gn, gv, gkdv);
+    }
+    // normal map: n = normalize(nt.x T' + nt.y B + nt.z N); view vector
+    gm = safe_normalize_bwd(mraw, gn);
+    gx = -safe_normalize_bwd(vraw, gv);
+  }
+  const f3 Bt = cross(N, Tp);
+  const f3 gnt = mk(dot(gm, Tp), dot(gm, Bt), dot(gm, N));
   // textures
   UVGrad G{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  uv_bwd(a.kd, g, Lk, sk, gkdv, G);
-  // normal map: n = normalize(nt.x T' + nt.y B + nt.z N)
-  f3 gm = safe_normalize_bwd(mraw, gn);
-  f3 gnt = mk(dot(gm, g.Tp), dot(gm, g.Bt), dot(gm, g.N));
-  uv_bwd(a.nm, g, Ln, sn, gnt, G);
-  if (a.model == ADR_SHADE_GGX) uv_bwd(a.orm, g, Lo, so, gormv, G);
+  uv_bwd_parked(col, 0, 3, a.kd, Lk.use_x, g, gkdv, G);
+  uv_bwd_parked(col, 9, 3, a.nm, Ln.use_x, g, gnt, G);
+  if (ggx_m) uv_bwd_parked(col, 18, 3, a.orm, Lo.use_x, g, gormv, G);
   if (ALPHA && a.al.data) {
     // alpha = clamp(t, 0, 1): the gradient passes where t is inside [0, 1]
-    Lod La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
-    const TriSample sa = tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La);
-    const float t = sa.val.x;
-    const f3 gal = mk(t >= 0.f && t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
-    uv_bwd(a.al, g, La, sa, gal, G);
+    const f3 gal = mk(alpha_t >= 0.f && alpha_t <= 1.f ? g_alpha : 0.f, 0.f, 0.f);
+    uv_bwd_parked(col, 27, 1, a.al, La.use_x, g, gal, G);
     put_rec(ro, 3, La, gal, lv);
   }
   put_rec(ro, 0, Lk, gkdv, lv);
   put_rec(ro, 1, Ln, gnt, lv);
-  if (a.model == ADR_SHADE_GGX) put_rec(ro, 2, Lo, gormv, lv);
+  if (ggx_m) put_rec(ro, 2, Lo, gormv, lv);
   u_out = g.u;
   v_out = g.v_;
   lo_out = pack_lo(g.ul, g.vl);
@@ -677,33 +751,40 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   f3 gTp = nt.x * gm;
   f3 gBt = nt.y * gm;
   f3 gN = nt.z * gm;
-  gN += cross(g.Tp, gBt);
-  gTp += cross(gBt, g.N);
-  f3 gT1 = safe_normalize_bwd(g.T1, gTp);
-  float sNT = dot(g.N, g.T);
+  gN += cross(Tp, gBt);
+  gTp += cross(gBt, N);
+  f3 gT1 = normalize_bwd_y(Tp, invT1, gTp);
+  float sNT = dot(N, T);
   f3 gT = gT1;
-  float g_s = -dot(gT1, g.N);
+  float g_s = -dot(gT1, N);
   gN += (-sNT) * gT1;
-  gN += g_s * g.T;
-  gT += g_s * g.N;
-  f3 gNi = safe_normalize_bwd(g.Ni, gN);
-  // view vector
-  f3 gx = -safe_normalize_bwd(vraw, gv);
+  gN += g_s * T;
+  gT += g_s * N;
+  f3 gNi = normalize_bwd_y(N, invNi, gN);
   // interpolation: attributes -> barycentrics and vertex attribute gradients
   // (relative to corner 0, as in the forward pass: the barycentrics sum to
   // one, so a common offset of the three lambda gradients has no effect)
-  float glam[3], glx[3], gly[3];
-  f3 P0 = ld3(a.m.pos, g.v[0]), N0 = ld3(a.nrm, g.v[0]), T0 = ld3(a.tan, g.v[0]);
-  float u0 = a.m.uv[2 * g.t[0]], v0 = a.m.uv[2 * g.t[0] + 1];
+  // the barycentrics and corner indices parked after the set-up
+  float lam[3];
+  int vid[3], tid[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    int vi = g.v[c];
+    lam[c] = col[(kParkLam + c) * kAccStride];
+    vid[c] = __float_as_int(col[(kParkLam + 3 + c) * kAccStride]);
+    tid[c] = a.m.uv_tri[3 * tri + c];
+  }
+  float glam[3], glx[3], gly[3];
+  f3 P0 = ld3(a.m.pos, vid[0]), N0 = ld3(a.nrm, vid[0]), T0 = ld3(a.tan, vid[0]);
+  float u0 = a.m.uv[2 * tid[0]], v0 = a.m.uv[2 * tid[0] + 1];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int vi = vid[c];
     f3 P = ld3(a.m.pos, vi) - P0, Nv = ld3(a.nrm, vi) - N0, Tv = ld3(a.tan, vi) - T0;
-    float uu = a.m.uv[2 * g.t[c]] - u0, vv = a.m.uv[2 * g.t[c] + 1] - v0;
+    float uu = a.m.uv[2 * tid[c]] - u0, vv = a.m.uv[2 * tid[c] + 1] - v0;
     glam[c] = dot(P, gx) + dot(Nv, gNi) + dot(Tv, gT) + uu * G.u + vv * G.v;
     glx[c] = uu * G.ux + vv * G.vx;
     gly[c] = uu * G.uy + vv * G.vy;
-    float lc = g.lam[c];
+    float lc = lam[c];
     float* da = col + 12 * c * kAccStride;
     da[0] = lc * gx.x; da[kAccStride] = lc * gx.y; da[2 * kAccStride] = lc * gx.z;
     da[3 * kAccStride] = lc * gNi.x; da[4 * kAccStride] = lc * gNi.y; da[5 * kAccStride] = lc * gNi.z;
@@ -713,13 +794,13 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   // barycentrics (float64, like the forward set-up):
   // lambda_c = D_c / S, lx_c = (a_c - lambda_c A) / S * sx, ly_c likewise
   BaryD d;
-  bary_setup(a.m, a.v, p.b, p.i, p.j, g.v, d);
+  bary_setup(a.m, a.v, p.b, p.i, p.j, vid, d);
   double iS = 1.0 / d.S;
   double A = d.a[0] + d.a[1] + d.a[2];
   double Bs = d.b[0] + d.b[1] + d.b[2];
   double gA = 0.0, gB = 0.0, gS = 0.0;
   double ga[3], gb[3], gD[3], dlam[3], dglam[3];
-  double sxd = 2.0 / (a.v.W / a.v.ms), syd = 2.0 / (a.v.H / a.v.ms);  // per pixel
+  const double sxd = a.v.pxs, syd = a.v.pys;  // per pixel
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     int j1 = c == 2 ? 0 : c + 1, k1 = c == 0 ? 2 : c - 1;
@@ -791,9 +872,26 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
     todo &= ~mine;
     int v0 = __shfl(vtx[0], leader), v1 = __shfl(vtx[1], leader), v2 = __shfl(vtx[2], leader);
     if (lane < kVtxAcc) {
+      // four members per round, their LDS reads in flight together (a spent
+      // mask reads the zero padding column kAccStride - 1)
       const float* row = win + lane * kAccStride;
-      float sum = 0.f;
-      for (unsigned long long m = mine; m; m &= m - 1) sum += row[__ffsll((long long)m) - 1];
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+      unsigned long long m = mine;
+      while (m) {
+        const int j0 = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const int j1 = m ? __ffsll((long long)m) - 1 : kAccStride - 1;
+        m &= m - 1;
+        const int j2 = m ? __ffsll((long long)m) - 1 : kAccStride - 1;
+        m &= m - 1;
+        const int j3 = m ? __ffsll((long long)m) - 1 : kAccStride - 1;
+        m &= m - 1;
+        s0 += row[j0];
+        s1 += row[j1];
+        s2 += row[j2];
+        s3 += row[j3];
+      }
+      const float sum = (s0 + s1) + (s2 + s3);
       if (sum != 0.f) {
         int c = lane / 12, comp = lane - 12 * c;
         int vi = c == 0 ? v0 : (c == 1 ? v1 : v2);
@@ -824,6 +922,8 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   int tile = xcd_tile(blockIdx.x, gridDim.x);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   float* table = table_all[threadIdx.x >> 6];
+  // the padding column stays zero (the pixel columns are 0..63)
+  if ((threadIdx.x & 63) < kVtxAcc) table[(threadIdx.x & 63) * kAccStride + kAccStride - 1] = 0.f;
   int tri = -1;
   int vtx[3] = {0, 0, 0};
   const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;

@@ -71,6 +71,33 @@ def test_job_alone_equals_mixed():
     ctx.close()
 
 
+def test_job_submitted_mid_run_is_admitted_between_steps():
+    """Continuous batching: a short job submitted while a long one steps is
+    admitted between two of the long job's steps and finishes first."""
+    from paper_2104_03989_amd import adr
+    _say("job admitted mid-run")
+    ctx = adr.Context(0)
+    long_w = _small(res=64, views=3)
+    a = adr.job_submit(ctx, long_w, n_steps=300, seed=5)
+    t0 = time.time()
+    while True:
+        st, _ = adr.job_poll(ctx, a)
+        if st["step"] >= 2:
+            break
+        assert time.time() - t0 < 60, "the long job did not start"
+        time.sleep(0.002)
+    short_w = _small(1)
+    b = adr.job_submit(ctx, short_w, n_steps=3, seed=6)
+    res, stb = _wait(ctx, {b: short_w})
+    sta, _ = adr.job_poll(ctx, a)
+    _say(f"  short job done while the long one is at step {sta['step']} of 300")
+    assert stb[b]["code"] == adr.OK and stb[b]["step"] == 3
+    assert sta["state"] == adr.JOB_RUNNING and sta["step"] < 300
+    res, sta = _wait(ctx, {a: long_w})
+    assert sta[a]["step"] == 300 and sta[a]["p99_ms"] >= sta[a]["p50_ms"] > 0
+    ctx.close()
+
+
 def test_job_first_step_matches_oracle():
     from paper_2104_03989_amd import adr
     _say("job step vs oracle")
