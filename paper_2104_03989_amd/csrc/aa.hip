@@ -85,8 +85,8 @@ __device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi
     if (!sil) continue;
     x.va = v[vid[j]];
     x.vb = v[vid[l]];
-    double4 ca = clip_d(a.m.pos, a.v.mvp, b, x.va);
-    double4 cb = clip_d(a.m.pos, a.v.mvp, b, x.vb);
+    double4 ca = clip_d(a.m.pos, a.v.mvpd, b, x.va);
+    double4 cb = clip_d(a.m.pos, a.v.mvpd, b, x.vb);
     double Px = ((double)Pi + 0.5) * a.v.sxs - 1.0;
     double Py = ((double)Pj + 0.5) * a.v.sys - 1.0;
     double Qx = ((double)Qi + 0.5) * a.v.sxs - 1.0;
@@ -478,8 +478,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       // s = eP / (eP - eQ)
       double id2 = 1.0 / (pr.x.den * pr.x.den);
       double g_eP = -g_s * pr.x.eQ * id2, g_eQ = g_s * pr.x.eP * id2;
-      double4 ca = clip_d(a.m.pos, a.v.mvp, p.b, pr.x.va);
-      double4 cb = clip_d(a.m.pos, a.v.mvp, p.b, pr.x.vb);
+      double4 ca = clip_d(a.m.pos, a.v.mvpd, p.b, pr.x.va);
+      double4 cb = clip_d(a.m.pos, a.v.mvpd, p.b, pr.x.vb);
       double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
       double ax = ca.x * iwa, ay = ca.y * iwa, bx = cb.x * iwb, by = cb.y * iwb;
       // e(X) = a'_x b'_y - a'_y b'_x, a' = a - X, b' = b - X

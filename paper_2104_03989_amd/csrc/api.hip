@@ -77,7 +77,7 @@ struct adr_ctx {
   int device = 0;
   uint64_t budget = 0;
   Buf oit_g, oit_a;  // depth-peeling adjoint: dL/d(composite behind) and dL/d alpha per pixel
-  Buf snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s;
+  Buf snap, orient, nacc, tacc, nrm, tan, big, big_cnt, med, partial, gcolor, dclip, dattr, texrec, image_s, mvpd;
   Buf fix_n, fix_t, fix_attr, fix_clip, fix_pos, det_k0, det_v0, det_k1, det_v1, det_hist, det_tmp, det_vals,
       det_part, lap_r, lap_part;
   adr::JobServer* jobs = nullptr;
@@ -239,7 +239,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       (r = ensure(ctx->tacc, V * 24)) || (r = ensure(ctx->nrm, V * 12)) ||
       (r = ensure(ctx->tan, V * 12)) || (r = ensure(ctx->big, B * T * 4)) ||
       (r = ensure(ctx->big_cnt, (B + 1) * 4)) || (r = ensure(ctx->med, B * T * 4)) ||
-      (r = ensure(ctx->partial, tiles * 4)))
+      (r = ensure(ctx->partial, tiles * 4)) || (r = ensure(ctx->mvpd, B * 128)))
     return r;
   if (bwd) {
     if ((r = ensure(ctx->gcolor, B * v.W * v.H * 12)) || (r = ensure(ctx->dclip, B * V * 16)) ||
@@ -287,6 +287,7 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
     }
   }
   s.snap = (int*)ctx->snap.p;
+  s.mvpd = (double*)ctx->mvpd.p;
   s.orient = (int8_t*)ctx->orient.p;
   s.nacc = (double*)ctx->nacc.p;
   s.tacc = (double*)ctx->tacc.p;
@@ -445,6 +446,7 @@ static size_t noalloc_carve(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool 
   unsigned char* big_cnt = take((B + 1) * 4);
   unsigned char* med = take(B * T * 4);
   unsigned char* partial = take(tiles * 4);
+  unsigned char* mvpd = take(B * 128);
   unsigned char* image_s = v.ms > 1 ? take(B * v.W * v.H * 12) : nullptr;
   unsigned char* fix_n = det ? take(V * 24) : nullptr;
   unsigned char* fix_t = det ? take(V * 24) : nullptr;
@@ -460,6 +462,7 @@ static size_t noalloc_carve(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool 
     s->big_cnt = (uint32_t*)big_cnt;
     s->med = (uint32_t*)med;
     s->partial = (float*)partial;
+    s->mvpd = (double*)mvpd;
     s->n_partial = (int)tiles;
     s->image_s = (float*)image_s;
     s->det = det;
@@ -511,7 +514,8 @@ adr_status adr_ctx_destroy(adr_ctx* ctx) {
   Buf* bufs[] = {&ctx->fix_n, &ctx->fix_t, &ctx->fix_attr, &ctx->fix_clip, &ctx->fix_pos, &ctx->det_k0,
                  &ctx->det_v0, &ctx->det_k1, &ctx->det_v1, &ctx->det_hist, &ctx->det_tmp, &ctx->det_vals,
                  &ctx->det_part, &ctx->lap_r, &ctx->lap_part, &ctx->texrec, &ctx->image_s, &ctx->snap, &ctx->orient, &ctx->nacc, &ctx->tacc, &ctx->nrm, &ctx->tan,
-                 &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr};
+                 &ctx->big, &ctx->big_cnt, &ctx->med, &ctx->oit_g, &ctx->oit_a, &ctx->partial, &ctx->gcolor, &ctx->dclip, &ctx->dattr,
+                 &ctx->mvpd};
   for (Buf* b : bufs) release(*b);
   for (const Span& sp : ctx->spans) {
     (void)hipEventDestroy(sp.a);
@@ -534,6 +538,7 @@ adr_status adr_render_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
   if ((r = prepare_scratch(ctx, m, v, false, s, 0, (flags & ADR_DETERMINISTIC) != 0)) != ADR_OK) return r;
+  v.mvpd = s.mvpd;
   const bool own_frame = !(mesh->nrm && mesh->tan);
   if ((r = fwd_launches(ctx, mesh, mat, m, v, kd, nm, orm, ref_image, loss_kind, out, flags, st, s, true)) != ADR_OK)
     return r;
@@ -563,6 +568,7 @@ adr_status adr_render_fwd_noalloc(adr_ctx* ctx, const adr_mesh* mesh, const adr_
                 "scratch; the no-allocation forward holds at most %llu",
                 v.B, m.n_tri, m.n_pos, v.W, v.H, need, (unsigned long long)ADR_NOALLOC_SCRATCH_BYTES);
   noalloc_carve(ctx, m, v, (flags & ADR_DETERMINISTIC) != 0, &s);
+  v.mvpd = s.mvpd;
   // the context's own scratch no longer holds this forward's geometry
   ctx->geom_ok = false;
   hipStream_t st = (hipStream_t)stream;
@@ -596,6 +602,7 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
   if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm), det)) !=
       ADR_OK)
     return r;
+  v.mvpd = s.mvpd;
   const int64_t n_clip = 4 * (int64_t)v.B * (m.n_pos > 0 ? m.n_pos : 1), n_attr = 9 * (int64_t)(m.n_pos > 0 ? m.n_pos : 1);
   if (!reuse) {
     TIMED(0, launch_vertex_frame(m, s, st), "vertex frame");
@@ -680,6 +687,7 @@ adr_status adr_render_oit_fwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
   HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
   Scratch s;
   if ((r = prepare_scratch(ctx, m, v, false, s)) != ADR_OK) return r;
+  v.mvpd = s.mvpd;
   if (flags & ADR_FWD_BUILD_MIPS) {
     const Tex* maps[4] = {&kd, &nm, &orm, &al};
     MipSet ms{};
@@ -752,6 +760,7 @@ adr_status adr_render_oit_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_mate
   if ((r = prepare_scratch(ctx, m, v, true, s, tex_slots(mat->model, grads->kd, grads->normal, grads->orm, gal))) !=
       ADR_OK)
     return r;
+  v.mvpd = s.mvpd;
   const int64_t npx = (int64_t)v.B * v.W * v.H;
   if ((r = ensure(ctx->oit_g, npx * 12)) || (r = ensure(ctx->oit_a, npx * 4))) return r;
   float* gbehind = (float*)ctx->oit_g.p;

@@ -321,19 +321,20 @@ __device__ __forceinline__ float adam1(float& p, float g, float& m, float& v, fl
 }
 
 // Clip coordinates of vertex vi in view b in float64 from the float32
-// position and view matrix, as the transform stage computes them for the
+// position and the view matrix (in float64, converted once per call by the
+// transform stage), as the transform stage computes them for the
 // rasterizer: each product of two float32 values is exact in float64, so
 // the sums round the same way whether or not a multiply is fused with them.
 // Recomputed where needed (3 vertices per pixel) instead of gathered from a
 // [views, vertices] float64 array.
-__device__ __forceinline__ double4 clip_d(const float* __restrict__ pos, const float* __restrict__ mvp, int b,
+__device__ __forceinline__ double4 clip_d(const float* __restrict__ pos, const double* __restrict__ mvpd, int b,
                                           int vi) {
-  const float* M = mvp + 16 * b;
+  const double* M = mvpd + 16 * b;
   const double px = pos[3 * vi], py = pos[3 * vi + 1], pz = pos[3 * vi + 2];
   double d[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
-    d[r] = (((double)M[4 * r] * px + (double)M[4 * r + 1] * py) + (double)M[4 * r + 2] * pz) + (double)M[4 * r + 3];
+    d[r] = ((M[4 * r] * px + M[4 * r + 1] * py) + M[4 * r + 2] * pz) + M[4 * r + 3];
   return make_double4(d[0], d[1], d[2], d[3]);
 }
 

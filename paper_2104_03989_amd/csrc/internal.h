@@ -43,6 +43,10 @@ struct ViewsD {
   // per-pixel code)
   int msh, Wp, Hp;
   double pxs, pys, sxs, sys;
+  // [B,16] the view matrices in float64 (exact), written by the transform
+  // stage into the call's scratch for the kernels that rebuild float64 clip
+  // coordinates (NULL outside the render calls)
+  const double* mvpd;
 };
 
 // Fills the derived fields of v from B, W, H and ms (ms 1, 2 or 4).
@@ -74,6 +78,7 @@ struct Scratch {
   float* dattr;       // [V,9] d(world pos), d(normal), d(tangent)
   float4* texrec;     // [1 + maps, B,H,W] texture-sample records of the adjoint
   float* image_s;     // [B,H,W,3] antialiased samples before the multisample resolve
+  double* mvpd;       // [B,16] the view matrices in float64
   int n_partial;
   // vertex-side adjoint accumulators (float64, or fixed point in
   // deterministic mode) and the deterministic mode's sort buffers

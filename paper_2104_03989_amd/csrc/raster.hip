@@ -38,8 +38,9 @@ __device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b)
 
 // Snapped integer coordinates (from the float32 clip coordinates of the
 // rules above) and float64 clip coordinates for interpolation.
-__global__ void k_xform(MeshD m, ViewsD v, int4* __restrict__ snap) {
+__global__ void k_xform(MeshD m, ViewsD v, int4* __restrict__ snap, double* __restrict__ mvpd) {
   int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < 16 * v.B) mvpd[gid] = (double)v.mvp[gid];
   if (gid >= v.B * m.n_pos) return;
   int b = gid / m.n_pos, vi = gid - b * m.n_pos;
   const float* M = v.mvp + 16 * b;
@@ -331,10 +332,11 @@ __global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int
 }
 
 hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st) {
-  int n = v.B * m.n_pos;
+  // one thread per (view, vertex), at least 16 per view for the matrices
+  const int n = m.n_pos > 0 ? (m.n_pos < 16 ? 16 : m.n_pos) * v.B : 0;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_xform, dim3((n + 255) / 256), dim3(256), 0, st, m, v,
-                     reinterpret_cast<int4*>(s.snap));
+                     reinterpret_cast<int4*>(s.snap), s.mvpd);
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ __device__ __forceinline__ void bary_setup(const MeshD& m, const ViewsD& vw, int
   double D[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    double4 q = clip_d(m.pos, vw.mvp, b, v[c]);
+    double4 q = clip_d(m.pos, vw.mvpd, b, v[c]);
     d.w[c] = q.w;
     d.gx[c] = q.x - q.w * d.px;
     d.gy[c] = q.y - q.w * d.py;
