@@ -4,11 +4,13 @@
 // budget, kept resident on the device and stepped by one server thread.
 //
 // Continuous batching: the server keeps kSlots execution slots (a stream and
-// a context whose scratch serves one step at a time).  Whenever a slot's step
-// completes (polled with hipEventQuery), the slot takes the next ready job
-// (round robin over the active jobs, at most one step of a job in flight),
-// so steps of different jobs overlap on the device and a job never waits for
-// a round of other jobs.  Queued jobs are admitted between any two
+// a context whose scratch serves the steps queued on it, in stream order).
+// Each slot keeps kDepth steps queued: whenever one completes (polled with
+// hipEventQuery) the slot enqueues the next step of an active job that has
+// none in flight (round robin, so steps of different jobs interleave and
+// overlap on the device, and a job never waits for a round of other jobs),
+// or else the next step of a job already on it (so a job stepping alone
+// has its next step queued while the current one runs).  Queued jobs are admitted between any two
 // dispatches as soon as their footprint, plus the slots' scratch for their
 // shapes, fits the budget; their uploads run on an admission stream of
 // their own.  Per-step latency is device time from an event recorded when
@@ -43,6 +45,10 @@ namespace adr {
 namespace {
 
 constexpr int kSlots = 4;
+// Steps queued per slot and per job: the host enqueues the next step while
+// the device runs the current one, so a job stepping alone is not bound by
+// the launch latency of its ~30 calls.
+constexpr int kDepth = 2;
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 
 uint64_t splitmix_out(uint64_t z) {
@@ -131,24 +137,28 @@ struct Job {
   float *mvp = nullptr, *eye = nullptr, *light = nullptr, *rgb = nullptr;
   uint64_t *ref_vis = nullptr, *vis = nullptr;
   float *ref_color = nullptr, *ref_image = nullptr, *color = nullptr, *dimage = nullptr, *loss = nullptr;
-  float* loss_host = nullptr;  // pinned
-  hipEvent_t start_ev = nullptr, done_ev = nullptr;
-  bool in_flight = false;      // a step of this job is on a slot
+  // up to kDepth steps of a job in flight, stream-ordered on one slot;
+  // step t uses ring entry t % kDepth
+  float* loss_host = nullptr;  // pinned, kDepth floats
+  hipEvent_t start_ev[kDepth] = {}, done_ev[kDepth] = {};
+  int inflight = 0;            // steps enqueued and not yet completed (all on one slot)
+  bool stopping = false;       // failed: enqueue nothing more, release once the queued steps are done
   std::vector<float> lat_ms;
   // results
   std::vector<float> out_pos, out_normal, out_orm;
   std::vector<uint8_t> out_kd;
 };
 
-// An execution slot: a stream, a context whose scratch serves the step on
-// it, the latent forward's received antialiasing (read by the backward that
-// follows it), and the job whose step it runs.
+// An execution slot: a stream, a context whose scratch serves the steps on
+// it (stream-ordered), the latent forward's received antialiasing (read by
+// the backward that follows it), and the steps queued on it.
 struct Slot {
   adr_ctx* ctx = nullptr;
   hipStream_t st = nullptr;
   float* aa = nullptr;
   size_t aa_cap = 0;
-  Job* job = nullptr;
+  // the steps queued on the stream, oldest first: (job, step)
+  std::deque<std::pair<Job*, int>> q;
 };
 
 struct JobServer {
@@ -311,8 +321,9 @@ adr_status copy_desc(Job& j, const adr_job_desc& d, char* msg, size_t n) {
 adr_status admit(JobServer* s, Job& j, hipStream_t st, adr_ctx* ctx) {
   const adr_job_desc& d = j.d;
   if (hipMalloc(&j.block, j.footprint) != hipSuccess) return ADR_E_NOMEM;
-  if (hipHostMalloc((void**)&j.loss_host, sizeof(float)) != hipSuccess) return ADR_E_NOMEM;
-  if (hipEventCreate(&j.start_ev) != hipSuccess || hipEventCreate(&j.done_ev) != hipSuccess) return ADR_E_HIP;
+  if (hipHostMalloc((void**)&j.loss_host, kDepth * sizeof(float)) != hipSuccess) return ADR_E_NOMEM;
+  for (int k = 0; k < kDepth; ++k)
+    if (hipEventCreate(&j.start_ev[k]) != hipSuccess || hipEventCreate(&j.done_ev[k]) != hipSuccess) return ADR_E_HIP;
   char* p = (char*)j.block;
   auto take = [&](size_t bytes) {
     void* r = p;
@@ -414,24 +425,26 @@ adr_status admit(JobServer* s, Job& j, hipStream_t st, adr_ctx* ctx) {
 void release_dev(Job& j) {
   if (j.block) (void)hipFree(j.block);
   if (j.loss_host) (void)hipHostFree(j.loss_host);
-  if (j.start_ev) (void)hipEventDestroy(j.start_ev);
-  if (j.done_ev) (void)hipEventDestroy(j.done_ev);
+  for (int k = 0; k < kDepth; ++k) {
+    if (j.start_ev[k]) (void)hipEventDestroy(j.start_ev[k]);
+    if (j.done_ev[k]) (void)hipEventDestroy(j.done_ev[k]);
+    j.start_ev[k] = j.done_ev[k] = nullptr;
+  }
   j.block = nullptr;
   j.loss_host = nullptr;
-  j.start_ev = nullptr;
-  j.done_ev = nullptr;
 }
 
-// One optimisation step of job j on slot sl, bracketed by the job's start
-// and completion events.
-adr_status enqueue_step(Slot& sl, Job& j) {
+// Optimisation step t of job j on slot sl, bracketed by the start and
+// completion events of its ring entry.
+adr_status enqueue_step(Slot& sl, Job& j, int t) {
   const adr_job_desc& d = j.d;
   adr_ctx* ctx = sl.ctx;
   hipStream_t st = sl.st;
-  if (hipEventRecord(j.start_ev, st) != hipSuccess) return ADR_E_HIP;
+  const int q = t % kDepth;
+  if (hipEventRecord(j.start_ev[q], st) != hipSuccess) return ADR_E_HIP;
   size_t B = d.n_views;
-  adr_views v{j.mvp + 16 * B * j.step, j.eye + 3 * B * j.step, j.light + 3 * B * j.step,
-              j.rgb + 3 * B * j.step, (int)B, d.width, d.height};
+  adr_views v{j.mvp + 16 * B * t, j.eye + 3 * B * t, j.light + 3 * B * t, j.rgb + 3 * B * t, (int)B, d.width,
+              d.height};
   adr_material rm{d.model, j.rkd.tex(), j.rnm.tex(), d.model == ADR_SHADE_GGX ? j.rorm.tex() : j.rkd.tex()};
   adr_material lm{d.model, j.kd.tex(), j.nm.tex(), d.model == ADR_SHADE_GGX ? j.orm.tex() : j.kd.tex()};
   adr_fwd_out ro{j.ref_vis, j.ref_color, j.ref_image, nullptr, nullptr, nullptr, nullptr};
@@ -448,16 +461,15 @@ adr_status enqueue_step(Slot& sl, Job& j) {
   adr_fwd_out lo{j.vis, j.color, nullptr, j.dimage, j.loss, nullptr, nullptr, sl.aa};
   // the map Adam rebuilds the latent chains after every step; the first
   // forward builds them
-  r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, j.step == 0 ? ADR_FWD_BUILD_MIPS : 0,
-                     st);
+  r = adr_render_fwd(ctx, &j.lat_mesh, &lm, &v, j.ref_image, d.loss_kind, &lo, t == 0 ? ADR_FWD_BUILD_MIPS : 0, st);
   if (r != ADR_OK) return r;
   adr_grads g{(d.opt_mask & 1) ? j.g_pos : nullptr, nullptr, j.g_kd, j.g_nm, j.g_orm};
   r = adr_render_bwd(ctx, &j.lat_mesh, &lm, &v, &lo, nullptr, &g, ADR_BWD_DEFER_MIP_ADJOINT, st);
   if (r != ADR_OK) return r;
-  float lr = d.lr0 * powf(10.0f, -d.lr_decay_k * (float)j.step);
+  float lr = d.lr0 * powf(10.0f, -d.lr_decay_k * (float)t);
   if (d.opt_mask & 1) {
     adr_param prm{(float*)j.lat_mesh.pos, j.g_pos, j.m[0], j.v[0], 3 * (int64_t)d.lat_n_pos};
-    r = adr_adam_step(ctx, &prm, 1, j.step + 1, lr, 0.9f, 0.999f, 1e-8f, st);
+    r = adr_adam_step(ctx, &prm, 1, t + 1, lr, 0.9f, 0.999f, 1e-8f, st);
     if (r != ADR_OK) return r;
   }
   adr_map_param mp[3];
@@ -465,10 +477,11 @@ adr_status enqueue_step(Slot& sl, Job& j) {
   if (j.g_kd) mp[nm++] = adr_map_param{j.kd.tex(), j.g_kd, j.m[1], j.v[1]};
   if (j.g_nm) mp[nm++] = adr_map_param{j.nm.tex(), j.g_nm, j.m[2], j.v[2]};
   if (j.g_orm) mp[nm++] = adr_map_param{j.orm.tex(), j.g_orm, j.m[3], j.v[3]};
-  r = adr_adam_step_maps(ctx, mp, nm, j.step + 1, lr, 0.9f, 0.999f, 1e-8f, st);
+  r = adr_adam_step_maps(ctx, mp, nm, t + 1, lr, 0.9f, 0.999f, 1e-8f, st);
   if (r != ADR_OK) return r;
-  if (hipMemcpyAsync(j.loss_host, j.loss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess) return ADR_E_HIP;
-  if (hipEventRecord(j.done_ev, st) != hipSuccess) return ADR_E_HIP;
+  if (hipMemcpyAsync(j.loss_host + q, j.loss, sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return ADR_E_HIP;
+  if (hipEventRecord(j.done_ev[q], st) != hipSuccess) return ADR_E_HIP;
   return ADR_OK;
 }
 
@@ -517,49 +530,67 @@ void admit_queued(JobServer* s, std::unique_lock<std::mutex>& lk) {
   }
 }
 
-// A completed step of the job on slot sl: loss, device latency, and the
-// job's end (done or failed).  Called with the lock held.
-void complete(JobServer* s, Slot& sl) {
-  Job& j = *sl.job;
-  sl.job = nullptr;
-  j.in_flight = false;
-  float ms = 0.f;
-  hipError_t e = hipEventElapsedTime(&ms, j.start_ev, j.done_ev);
-  const float loss = *j.loss_host;
-  if (e != hipSuccess) {
-    snprintf(j.why, sizeof(j.why), "step %d: %s", j.step + 1, hipGetErrorString(e));
-    j.state = ADR_JOB_FAILED;
-  } else if (!std::isfinite(loss)) {
-    snprintf(j.why, sizeof(j.why), "non-finite loss %g at step %d", loss, j.step + 1);
-    j.state = ADR_JOB_FAILED;
-  } else {
-    j.lat_ms.push_back(ms);
-    j.last_loss = loss;
-    j.step += 1;
-  }
-  if (j.state == ADR_JOB_FAILED) {
-    release_dev(j);
-    s->used -= j.footprint;
-  } else if (j.step >= j.d.n_steps) {
-    finish(sl.st, j);
-    s->used -= j.footprint;
+// Releases a job that ended (done: its results copied out first) once no
+// step of it is in flight.  Called with the lock held.
+void retire(JobServer* s, Job& j) {
+  if (j.state == ADR_JOB_RUNNING && j.step >= j.d.n_steps) {
+    finish(s->adm_stream, j);
     j.state = ADR_JOB_DONE;
   } else {
-    return;
+    release_dev(j);
   }
+  s->used -= j.footprint;
   s->active.erase(std::find(s->active.begin(), s->active.end(), j.id));
 }
 
-// The next active job with no step in flight, round robin; or null.
-Job* next_ready(JobServer* s) {
+// The oldest step queued on slot sl has completed: its loss and device
+// latency.  Called with the lock held.
+void complete_head(JobServer* s, Slot& sl) {
+  Job& j = *sl.q.front().first;
+  const int t = sl.q.front().second;
+  sl.q.pop_front();
+  j.inflight -= 1;
+  const int q = t % kDepth;
+  float ms = 0.f;
+  hipError_t e = hipEventElapsedTime(&ms, j.start_ev[q], j.done_ev[q]);
+  const float loss = j.loss_host[q];
+  if (!j.stopping) {
+    if (e != hipSuccess) {
+      snprintf(j.why, sizeof(j.why), "step %d: %s", t + 1, hipGetErrorString(e));
+      j.stopping = true;
+    } else if (!std::isfinite(loss)) {
+      snprintf(j.why, sizeof(j.why), "non-finite loss %g at step %d", loss, t + 1);
+      j.stopping = true;
+    } else {
+      j.lat_ms.push_back(ms);
+      j.last_loss = loss;
+      j.step = t + 1;
+    }
+  }
+  if (j.stopping && j.inflight == 0) {
+    j.state = ADR_JOB_FAILED;
+    retire(s, j);
+  } else if (j.step >= j.d.n_steps && j.inflight == 0) {
+    retire(s, j);
+  }
+}
+
+// The job slot k enqueues next: an active job with no step in flight (round
+// robin: steps of different jobs interleave), else the next step of a job
+// already queued on this slot (its steps must stay on one stream).
+Job* next_for_slot(JobServer* s, int k) {
   const size_t n = s->active.size();
-  for (size_t k = 0; k < n; ++k) {
-    const size_t i = (s->rr + k) % n;
-    Job* j = s->jobs.at(s->active[i]).get();
-    if (!j->in_flight) {
-      s->rr = (i + 1) % n;
+  for (size_t i = 0; i < n; ++i) {
+    const size_t c = (s->rr + i) % n;
+    Job* j = s->jobs.at(s->active[c]).get();
+    if (j->inflight == 0 && !j->stopping && j->step < j->d.n_steps) {
+      s->rr = (c + 1) % n;
       return j;
     }
+  }
+  for (auto& e : s->slot[k].q) {
+    Job* j = e.first;
+    if (j->inflight < kDepth && !j->stopping && j->step + j->inflight < j->d.n_steps) return j;
   }
   return nullptr;
 }
@@ -570,47 +601,42 @@ void server_loop(JobServer* s) {
   while (!s->stop) {
     admit_queued(s, lk);
     int busy = 0;
-    for (Slot& sl : s->slot) {
-      if (sl.job) {
-        // a finished step frees its slot at once
-        const hipError_t q = hipEventQuery(sl.job->done_ev);
-        if (q == hipErrorNotReady) {
-          ++busy;
-          continue;
-        }
-        if (q != hipSuccess) {
-          Job& j = *sl.job;
-          snprintf(j.why, sizeof(j.why), "step %d: %s", j.step + 1, hipGetErrorString(q));
-          j.state = ADR_JOB_FAILED;
-          j.in_flight = false;
-          sl.job = nullptr;
+    for (int k = 0; k < kSlots; ++k) {
+      Slot& sl = s->slot[k];
+      // completed steps, oldest first
+      while (!sl.q.empty()) {
+        Job& j = *sl.q.front().first;
+        const hipError_t q = hipEventQuery(j.done_ev[sl.q.front().second % kDepth]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess && !j.stopping) {
+          snprintf(j.why, sizeof(j.why), "step %d: %s", sl.q.front().second + 1, hipGetErrorString(q));
+          j.stopping = true;
           (void)hipStreamSynchronize(sl.st);
-          release_dev(j);
-          s->used -= j.footprint;
-          s->active.erase(std::find(s->active.begin(), s->active.end(), j.id));
+        }
+        complete_head(s, sl);
+      }
+      // keep kDepth steps queued on the slot
+      while ((int)sl.q.size() < kDepth) {
+        Job* j = next_for_slot(s, k);
+        if (!j) break;
+        const int t = j->step + j->inflight;
+        adr_status r = enqueue_step(sl, *j, t);
+        if (r != ADR_OK) {
+          snprintf(j->why, sizeof(j->why), "step %d could not be launched (%d): %s", t + 1, r, adr_last_error());
+          j->stopping = true;
+          (void)hipStreamSynchronize(sl.st);
+          // the steps of the job already queued have completed; retire it
+          // when the loop drains them (at once if none)
+          if (j->inflight == 0) {
+            j->state = ADR_JOB_FAILED;
+            retire(s, *j);
+          }
           continue;
         }
-        complete(s, sl);
+        j->inflight += 1;
+        sl.q.emplace_back(j, t);
       }
-      // the free slot takes the next ready job
-      Job* j = next_ready(s);
-      if (!j) continue;
-      j->in_flight = true;
-      sl.job = j;
-      adr_status r = enqueue_step(sl, *j);
-      if (r != ADR_OK) {
-        snprintf(j->why, sizeof(j->why), "step %d could not be launched (%d): %s", j->step + 1, r,
-                 adr_last_error());
-        j->state = ADR_JOB_FAILED;
-        j->in_flight = false;
-        sl.job = nullptr;
-        (void)hipStreamSynchronize(sl.st);
-        release_dev(*j);
-        s->used -= j->footprint;
-        s->active.erase(std::find(s->active.begin(), s->active.end(), j->id));
-        continue;
-      }
-      ++busy;
+      busy += (int)sl.q.size();
     }
     if (busy == 0 && s->queue.empty()) {
       s->cv.wait_for(lk, std::chrono::milliseconds(50));
