@@ -552,9 +552,85 @@ def cpu_baseline(w, np, torch, views, min_seconds=10.0, max_steps=4):
     dt = time.perf_counter() - t0
     B = w.dirs.shape[0]
     return dict(value=round(steps * views * w1.width * w1.height / dt / 1e6, 4), unit="Mpix/s",
-                cores=torch.get_num_threads(), kind="oracle",
+                cores=torch.get_num_threads(), kind="oracle", host=host_cpu(),
                 sample=f"{steps} full steps ({views} of the {B} views each, full-size meshes and maps): "
                        "reference render, latent render, loss, backward, Adam", seconds=round(dt, 2))
+
+
+def host_cpu():
+    """nproc and the CPU model line of lscpu (the oracle's host)."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True).stdout.strip())
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Thread(s) per core", "Core(s) per socket", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except OSError:
+        pass
+    return info
+
+
+def oracle_step_seconds(w, np, torch, steps):
+    """Seconds per whole oracle step (reference render, latent render, loss,
+    backward, Adam) of a workload, one value per step."""
+    from oracle import loop as OL
+    params = OL.latent_params(w)
+    state, out = {}, []
+    for t in range(steps):
+        t0 = time.perf_counter()
+        mvp32, eye = OL.cameras(w)
+        ref = OL.reference_image(w, mvp32, eye)
+        loss, grads, _ = OL.loss_and_grads(w, ref, mvp32, eye, params)
+        new, state = OL.adam_update(params, grads, state, t + 1, w.lr)
+        params = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in new.items()}
+        out.append(time.perf_counter() - t0)
+        _log(f"  oracle step {t + 1}/{steps}: {out[-1]:.2f} s")
+    return out
+
+
+def oracle_timing(args):
+    """The FP64 oracle's per-step time on this host: the plain step as a
+    median of 5, the paper-scale and displacement loops over 3 steps, one
+    mesh-step of the batched and of the served mixes, each at one thread and
+    at every core; writes profiles/oracle_timing.md."""
+    import numpy as np
+    import torch
+
+    from paper_2104_03989_amd import synth
+    host = host_cpu()
+    n_all = host["nproc"]
+    disp = synth.workload_displacement()
+    disp.disp = synth.Texture(np.random.default_rng(12).normal(0.0, 0.01, size=(1024, 1024, 1)).astype(np.float32), "f32")
+    batched = synth.workload_batched(n_meshes=1)[0]
+    served = serve_pool(1, np.random.Generator(np.random.PCG64(synth.seed_for(5, 0))))[0]
+    cases = [("plain step (4 x 256^2, 1,280 / 20,480 tris)", synth.workload_plain_step(), 5, "median"),
+             ("paper-scale loop (8 x 512^2, 7,220 / 297,680 tris, 2048^2 maps)", synth.workload_paper_loop(), 3, "mean"),
+             ("displacement loop (8 x 512^2, 62,720 / 369,920 tris)", disp, 3, "mean"),
+             ("batched: one mesh-step (mesh 0 of the 64)", batched, 1, "mean"),
+             ("served: one job-step (job 0 of the pool)", served, 1, "mean")]
+    lines = ["# FP64 oracle timing on the host (a baseline, not a target)", "",
+             "Command: `python3 bench.py --oracle-timing` on the GPU box's host.  Host: " +
+             ", ".join(f"{k} {v}" for k, v in host.items()) + ".", "",
+             "A step is the whole oracle step: reference render, latent render, image loss, backward (autograd of "
+             "the float64 forward) and Adam.  The integer rasterizer is single-threaded C; the float64 stages use "
+             "torch's CPU threads.", "",
+             "| workload | threads | steps | s per step | Mpix/s |", "|---|---|---|---|---|"]
+    print("\n".join(lines), flush=True)
+    for name, w, steps, how in cases:
+        px = w.dirs.shape[0] * w.width * w.height
+        for threads in (1, n_all):
+            torch.set_num_threads(threads)
+            _log(f"oracle timing: {name}, {threads} thread(s)")
+            ts = oracle_step_seconds(w, np, torch, steps)
+            sec = float(np.median(ts)) if how == "median" else float(np.mean(ts))
+            lines.append(f"| {name} | {torch.get_num_threads()} | {steps} ({how}) | {sec:.3f} | {px / sec / 1e6:.4f} |")
+            print(lines[-1], flush=True)
+    path = args.oracle_timing_out or os.path.join(ROOT, "profiles", "oracle_timing.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(path)
 
 
 def serve_pool(n, g):
@@ -776,6 +852,10 @@ def main():
     ap.add_argument("--overlap", action="store_true",
                     help="render each step's reference on a stream of its own, overlapping the previous step's "
                          "backward and Adam (kernel times then include the concurrent work)")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 oracle per step on this host (1 thread and all cores) and write "
+                         "profiles/oracle_timing.md")
+    ap.add_argument("--oracle-timing-out", metavar="PATH", help="where --oracle-timing writes its table")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-jobs", type=int, default=16)
@@ -788,6 +868,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve(args)
+        return
+    if args.oracle_timing:
+        oracle_timing(args)
         return
     if args.pmc_summary:
         summarize_pmc(args.workload, *args.pmc_summary)
