@@ -722,7 +722,8 @@ WORKLOADS = {
                   "8 views x 512x512, tone-mapped L1, Adam"),
     "batched": ("batched: 64 meshes, latent 1k-50k tris (log-uniform), reference at 4x the sphere frequency "
                 "(at most 737k tris), 4-16 views at 256^2-1024^2, 512^2-2048^2 FP32 normal and ORM maps, GGX, L1, "
-                "graph-captured over 4 streams with one Adam launch, against the same meshes one at a time"),
+                "one launch per render stage over all meshes, graph-captured, with one Adam launch, against the "
+                "same meshes one at a time"),
     "aggregate": ("aggregate geometry: 1.2M-tri leaf cloud reference, 4,800 transparent quads (9,600 tris) "
                   "with 8 depth-peeled layers, 2048^2 base colour, normal and alpha maps optimised with positions, "
                   "8 views x 512x512, L2, Adam"),
@@ -748,8 +749,10 @@ def make_workload(name):
 
 def batched(args):
     """Batched form: 64 uneven meshes stepped one at a time (plain) and as a
-    graph-captured batch over 4 streams with one Adam launch, from the same
-    state; reports mesh-steps/s of both and their losses."""
+    graph-captured batch (--batch-form launch: one launch per render stage
+    over all meshes; streams: every mesh's launches over 4 streams) with one
+    Adam launch, from the same state; reports mesh-steps/s of both and their
+    losses."""
     import numpy as np
     import torch
 
@@ -764,7 +767,8 @@ def batched(args):
     W, K = args.warmup, args.steps
     n_steps = 2 * W + 2 * K + 1
     _log("uploading and tuning")
-    b = Batch(ws, n_steps, n_streams=4, det=args.deterministic, tune=True, progress=lambda k: None)
+    b = Batch(ws, n_steps, n_streams=4, det=args.deterministic, tune=True, progress=lambda k: None,
+              form=args.batch_form)
     px = sum(w.dirs.shape[0] * w.width * w.height for w in ws)
     t = 0
     _log("plain warm-up")
@@ -809,7 +813,8 @@ def batched(args):
         "config": {"workload": WORKLOADS["batched"], "meshes": n, "latent_tris": int(sum(w.latent.mesh.tri.shape[0] for w in ws)),
                    "ref_tris": int(sum(w.ref.mesh.tri.shape[0] for w in ws)), "pixels_per_step": px,
                    "gradient_mode": "deterministic" if args.deterministic else "atomic",
-                   "streams": 4, "mean_loss_last_step": round(loss_b, 6),
+                   "form": args.batch_form, "streams": 1 if args.batch_form == "launch" else 4,
+                   "batch_scratch_gib": round(b.scratch_bytes() / 2**30, 2), "mean_loss_last_step": round(loss_b, 6),
                    "raster_splits": sorted({str(m.split_ref) + "/" + str(m.split_lat) for m in b.meshes})},
     }
     print(json.dumps(rec), flush=True)
@@ -856,6 +861,9 @@ def main():
                     help="time the FP64 oracle per step on this host (1 thread and all cores) and write "
                          "profiles/oracle_timing.md")
     ap.add_argument("--oracle-timing-out", metavar="PATH", help="where --oracle-timing writes its table")
+    ap.add_argument("--batch-form", choices=("launch", "streams"), default="launch",
+                    help="batched workload: one launch per render stage over all meshes (launch) or every mesh's "
+                         "launches over 4 streams (streams), both graph-captured")
     ap.add_argument("--serve", action="store_true", help="served mode (job server, Poisson arrivals)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
     ap.add_argument("--serve-jobs", type=int, default=16)

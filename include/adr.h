@@ -239,6 +239,66 @@ adr_status adr_render_bwd(adr_ctx* ctx, const adr_mesh* mesh, const adr_material
                           const float* dloss, const adr_grads* grads, int32_t flags,
                           adr_stream stream);
 
+/* ----------------------------------------------------------------- batches */
+
+/* Many renders of uneven size stepped together: the paper's optimisation
+ * (Sec. 3, Eq. 1) run for independent meshes at once, each with its own
+ * views, reference images and parameters.  A batch runs each stage of
+ * adr_render_fwd (and of adr_render_bwd) as ONE launch over the work of all
+ * its items: item k owns a contiguous range of the launch's blocks, found by
+ * the blocks from a per-stage device table of argument blocks and block
+ * offsets, so a small item costs a few blocks of a launch instead of
+ * launches of its own, and the small and large items of a stage share the
+ * chip.  Everything is planned and allocated at creation: adr_batch_fwd and
+ * adr_batch_bwd only launch kernels (no allocation, no host
+ * synchronisation), so a caller can capture them into a HIP graph.  Results
+ * are those of adr_render_fwd / adr_render_bwd called item by item with the
+ * same arguments (the same bits with ADR_DETERMINISTIC). */
+typedef struct adr_batch adr_batch;
+
+typedef struct adr_batch_item {
+  const adr_mesh* mesh;          /* as adr_render_fwd; a precomputed frame (nrm, tan) is used by
+                                    forward-only items */
+  const adr_material* mat;
+  const adr_views* views;
+  const float* ref_image;        /* device [B,H,W,3] or NULL (no loss) */
+  int32_t loss_kind;             /* ADR_LOSS_*, with ref_image */
+  const adr_fwd_out* out;        /* as adr_render_fwd */
+  const adr_grads* grads;        /* NULL: forward only; else as adr_render_bwd (needs ref_image) */
+  const float* dloss;            /* device [1] scale of the loss gradient, NULL = 1 */
+  int32_t flags;                 /* ADR_FWD_NO_AA, ADR_DETERMINISTIC, ADR_INDEPENDENT_MIPS,
+                                    ADR_BWD_DEFER_MIP_ADJOINT */
+  int32_t tiny_bbox, med_bbox;   /* the item's raster work split as adr_ctx_set_raster (0: the
+                                    context's) */
+} adr_batch_item;
+
+/* Validates n items (host array; the structures are copied, the device
+ * buffers they name are not: they must outlive the batch, and each call
+ * reads their contents at that time), allocates every item's scratch and the
+ * launch tables (device memory held until adr_batch_destroy) and uploads the
+ * tables (synchronous).  ADR_E_INVALID for an item adr_render_fwd or
+ * adr_render_bwd would reject, for multisampling or ADR_FWD_BUILD_MIPS
+ * (rebuild chains with adr_mip_build or adr_adam_step_maps instead), or a
+ * stage of 2^31 blocks or more; ADR_E_NOMEM when the scratch does not fit. */
+adr_status adr_batch_create(adr_ctx* ctx, int32_t n, const adr_batch_item* items, adr_batch** out);
+/* The forward of every item (adr_render_fwd with the item's arguments), in
+ * 9 to 11 launches on `stream`. */
+adr_status adr_batch_fwd(adr_batch* b, adr_stream stream);
+/* The backward of every item with gradients (adr_render_bwd with the item's
+ * arguments; gradients are accumulated into).  It reuses the vertex frame,
+ * snapped vertices and triangle orientations that the batch's last
+ * adr_batch_fwd left in the items' scratch, so it must follow that forward
+ * on the same stream with the meshes and views unchanged in between;
+ * ADR_E_INVALID before any forward or when no item has gradients.  The
+ * texel adjoint of ADR_DETERMINISTIC items (a sort per item) and the mip
+ * adjoint of items without ADR_BWD_DEFER_MIP_ADJOINT or
+ * ADR_INDEPENDENT_MIPS run item after item. */
+adr_status adr_batch_bwd(adr_batch* b, adr_stream stream);
+/* Items and device bytes (scratch and tables) of a batch; either out may be NULL. */
+adr_status adr_batch_info(const adr_batch* b, int32_t* n_items, uint64_t* scratch_bytes);
+/* Frees the batch's device memory (waits for the device). */
+adr_status adr_batch_destroy(adr_batch* b);
+
 /* ------------------------------------ order-independent transparency */
 
 /* Depth-peeled rendering (Sec. 5.2, "Order-independent transparency"; the

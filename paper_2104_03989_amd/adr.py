@@ -41,7 +41,8 @@ EXPORTS = ("adr_last_error", "adr_ctx_create", "adr_ctx_destroy", "adr_render_fw
            "adr_job_submit", "adr_job_poll", "adr_ctx_profile", "adr_ctx_profile_read", "adr_job_views",
            "adr_tess_counts", "adr_tess_build", "adr_tess_fwd", "adr_tess_bwd", "adr_mesh_frame", "adr_mesh_one_ring", "adr_laplacian", "adr_image_downsample",
            "adr_skin_fwd", "adr_skin_bwd", "adr_render_oit_fwd", "adr_render_oit_bwd", "adr_ctx_set_raster",
-           "adr_adam_step_maps", "adr_ctx_profile_stages", "adr_render_fwd_noalloc")
+           "adr_adam_step_maps", "adr_ctx_profile_stages", "adr_render_fwd_noalloc", "adr_batch_create",
+           "adr_batch_fwd", "adr_batch_bwd", "adr_batch_info", "adr_batch_destroy")
 N_STAGES = 19
 STAGES = ("vertex_frame", "transform", "raster", "shade", "aa_loss", "aa_bwd", "shade_bwd",
           "mip_adjoint", "mesh_bwd", "adam", "mip_build", "tex_bwd", "clear", "skin", "skin_bwd", "blend",
@@ -134,6 +135,12 @@ class JobResult_(C.Structure):
     _fields_ = [("pos", P), ("kd", P), ("normal", P), ("orm", P)]
 
 
+class BatchItem_(C.Structure):
+    _fields_ = [("mesh", C.POINTER(Mesh_)), ("mat", C.POINTER(Material_)), ("views", C.POINTER(Views_)),
+                ("ref_image", P), ("loss_kind", I32), ("out", C.POINTER(FwdOut_)), ("grads", C.POINTER(Grads_)),
+                ("dloss", P), ("flags", I32), ("tiny_bbox", I32), ("med_bbox", I32)]
+
+
 _lib.adr_last_error.restype = C.c_char_p
 _lib.adr_ctx_create.argtypes = [I32, C.c_uint64, C.POINTER(P)]
 _lib.adr_ctx_destroy.argtypes = [P]
@@ -169,6 +176,11 @@ _lib.adr_render_oit_fwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C
 _lib.adr_render_oit_bwd.argtypes = [P, C.POINTER(Mesh_), C.POINTER(Material_), C.POINTER(Views_),
                                     C.POINTER(OitOut_), P, C.POINTER(Grads_), I32, P]
 _lib.adr_skin_bwd.argtypes = [P, P, P, P, I32, I32, P, P, P, P]
+_lib.adr_batch_create.argtypes = [P, I32, C.POINTER(BatchItem_), C.POINTER(P)]
+_lib.adr_batch_fwd.argtypes = [P, P]
+_lib.adr_batch_bwd.argtypes = [P, P]
+_lib.adr_batch_info.argtypes = [P, C.POINTER(I32), C.POINTER(C.c_uint64)]
+_lib.adr_batch_destroy.argtypes = [P]
 for _n in EXPORTS[1:]:
     getattr(_lib, _n).restype = I32
 
@@ -361,6 +373,37 @@ def mip_build(ctx: Context, tex: DeviceTexture, stream=None):
     _check(_lib.adr_mip_build(ctx.h, C.byref(t), _stream(stream)))
 
 
+def fwd_outputs(views: DeviceViews, dev, with_ref: bool, want_image=True, want_tri_id=False, want_coverage=False,
+                flags: int = 0) -> dict:
+    """Output buffers of a forward render: vis, color, image, dimage, loss,
+    tri_id, coverage and aa (the received antialiasing the backward reads)."""
+    B, H, W = views.n, views.height, views.width
+    ms = msaa_factor(flags)
+    Hs, Ws = H * ms, W * ms          # visibility samples (multisampling: per sample)
+    out = dict(vis=torch.empty(B, Hs, Ws, dtype=torch.int64, device=dev),
+               color=torch.empty(B, Hs, Ws, 3, dtype=torch.float32, device=dev))
+    out["image"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if want_image else None
+    out["tri_id"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_tri_id else None
+    out["coverage"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_coverage else None
+    if with_ref:
+        out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
+        out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)
+        # received antialiasing per sample, kept for the backward pass
+        out["aa"] = torch.empty(B, Hs, Ws, 8, dtype=torch.float32, device=dev)
+    else:
+        out["dimage"] = out["loss"] = out["aa"] = None
+    return out
+
+
+def _fwd_out(out: dict):
+    return FwdOut_(*[_ptr(out.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
+                                                "aa")])
+
+
+def _grads(grads: dict):
+    return Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
+
+
 def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, ref=None,
                loss: str = "l1", flags: int = 0, pos=None, want_image=True, want_tri_id=False,
                want_coverage=False, stream=None, outputs: dict | None = None, noalloc: bool = False):
@@ -368,27 +411,9 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
     (``outputs``: a dict returned by an earlier call, reused in place).
     ``noalloc``: call adr_render_fwd_noalloc, whose scratch is the library's
     static per-device array (no device allocation by the library)."""
-    B, H, W = views.n, views.height, views.width
-    ms = msaa_factor(flags)
-    Hs, Ws = H * ms, W * ms          # visibility samples (multisampling: per sample)
-    dev = mesh.tri.device
-    if outputs is not None:
-        out = outputs
-    else:
-        out = dict(vis=torch.empty(B, Hs, Ws, dtype=torch.int64, device=dev),
-                   color=torch.empty(B, Hs, Ws, 3, dtype=torch.float32, device=dev))
-        out["image"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev) if want_image else None
-        out["tri_id"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_tri_id else None
-        out["coverage"] = torch.empty(B, Hs, Ws, dtype=torch.int32, device=dev) if want_coverage else None
-        if ref is not None:
-            out["dimage"] = torch.empty(B, H, W, 3, dtype=torch.float32, device=dev)
-            out["loss"] = torch.empty(1, dtype=torch.float32, device=dev)
-            # received antialiasing per sample, kept for the backward pass
-            out["aa"] = torch.empty(B, Hs, Ws, 8, dtype=torch.float32, device=dev)
-        else:
-            out["dimage"] = out["loss"] = out["aa"] = None
-    fo = FwdOut_(*[_ptr(out.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
-                                              "aa")])
+    out = outputs if outputs is not None else fwd_outputs(views, mesh.tri.device, ref is not None, want_image,
+                                                          want_tri_id, want_coverage, flags)
+    fo = _fwd_out(out)
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
     fn = _lib.adr_render_fwd_noalloc if noalloc else _lib.adr_render_fwd
     _check(fn(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), _ptr(ref), LOSS[loss], C.byref(fo), flags,
@@ -399,12 +424,54 @@ def render_fwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: Devic
 def render_bwd(ctx: Context, mesh: DeviceMesh, mat: DeviceMaterial, views: DeviceViews, saved: dict,
                grads: dict, dloss=None, flags: int = 0, pos=None, stream=None):
     """Accumulates into grads['pos'|'vnormal'|'kd'|'normal'|'orm'] (tensors or None)."""
-    fo = FwdOut_(*[_ptr(saved.get(k)) for k in ("vis", "color", "image", "dimage", "loss", "tri_id", "coverage",
-                                                 "aa")])
-    g = Grads_(*[_ptr(grads.get(k)) for k in ("pos", "vnormal", "kd", "normal", "orm", "alpha")])
+    fo, g = _fwd_out(saved), _grads(grads)
     ms, mt, vs = mesh.struct(pos), mat.struct(), views.struct()
     _check(_lib.adr_render_bwd(ctx.h, C.byref(ms), C.byref(mt), C.byref(vs), C.byref(fo),
                                _ptr(dloss), C.byref(g), flags, _stream(stream)))
+
+
+class RenderBatch:
+    """adr_batch_*: the forward (and backward) of many renders, one launch
+    per stage over all of them.  ``items``: dicts with mesh, mat, views
+    (DeviceMesh / DeviceMaterial / DeviceViews), out (a fwd_outputs dict) and
+    optionally ref (reference image tensor), loss ('l1'...), grads (dict as
+    render_bwd's; needs ref), dloss, flags, split ((tiny, med) raster work
+    split).  The tensors are read at every call and must stay alive."""
+
+    def __init__(self, ctx: Context, items: list):
+        self.ctx = ctx
+        arr = (BatchItem_ * len(items))()
+        for k, it in enumerate(items):
+            split = it.get("split") or (0, 0)
+            grads = it.get("grads")
+            arr[k] = BatchItem_(C.pointer(it["mesh"].struct()), C.pointer(it["mat"].struct()),
+                                C.pointer(it["views"].struct()), _ptr(it.get("ref")), LOSS[it.get("loss", "l1")],
+                                C.pointer(_fwd_out(it["out"])), C.pointer(_grads(grads)) if grads else None,
+                                _ptr(it.get("dloss")), it.get("flags", 0), split[0], split[1])
+        self.h = P()
+        _check(_lib.adr_batch_create(ctx.h, len(items), arr, C.byref(self.h)))
+
+    def fwd(self, stream=None):
+        _check(_lib.adr_batch_fwd(self.h, _stream(stream)))
+
+    def bwd(self, stream=None):
+        _check(_lib.adr_batch_bwd(self.h, _stream(stream)))
+
+    def info(self) -> dict:
+        n, b = I32(), C.c_uint64()
+        _check(_lib.adr_batch_info(self.h, C.byref(n), C.byref(b)))
+        return {"items": n.value, "bytes": b.value}
+
+    def close(self):
+        if self.h:
+            _check(_lib.adr_batch_destroy(self.h))
+            self.h = P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def adam_step(ctx: Context, params: list, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,

@@ -5,13 +5,18 @@ the cameras and lights of every step).  One step renders each mesh's
 reference and latent views, scores the image loss and back-propagates
 (Sec. 3, Eq. 1), then Adam updates the parameters of all meshes (Sec. 5.3):
 one launch over every mesh's positions, and the maps four per launch with
-their mip chains' adjoint and rebuild fused in.  The batched form captures
-the forward and backward launches of all meshes once as a HIP graph
-(through torch.cuda.CUDAGraph), spread over several streams, each with its
-own library context, so that the graph runs small meshes concurrently; a
-step is then a copy of that step's cameras into the buffers the graph
-reads, one graph launch and the Adam launches.  The
-plain form steps the same meshes one at a time, each with its own launches.
+their mip chains' adjoint and rebuild fused in.
+
+Three forms of the same step:
+- ``launch`` (the batched form): two library batches (adr_batch_*), one of
+  every mesh's reference render and one of every latent render with its
+  backward, so that each stage of the render runs as one launch over the
+  work of all meshes; the three calls are captured once as a HIP graph
+  (through torch.cuda.CUDAGraph) and a step is a copy of that step's cameras
+  into the buffers the graph reads, one graph launch and the Adam launches.
+- ``streams``: the per-mesh launches of every mesh captured as one graph,
+  spread over several streams, each with its own library context.
+- plain (``step_plain``): one mesh at a time, each with its own launches.
 The rasterizer's work split of each mesh's renders comes from the autotuner.
 """
 from __future__ import annotations
@@ -88,6 +93,25 @@ class MeshState:
     def loss(self) -> float:
         return float(self.lat_out["loss"][0])
 
+    def alloc_outputs(self):
+        dev = self.lat_mesh.pos.device
+        if self.ref_out is None:
+            self.ref_out = adr.fwd_outputs(self.views, dev, False, want_image=True)
+        if self.lat_out is None:
+            self.lat_out = adr.fwd_outputs(self.views, dev, True, want_image=False)
+
+    def batch_items(self):
+        """This mesh's reference render and its latent render (with
+        gradients) as batch items."""
+        self.alloc_outputs()
+        ref = dict(mesh=self.ref_mesh, mat=self.ref_mat, views=self.views, out=self.ref_out, flags=self.det,
+                   split=self.split_ref)
+        grads = {k: g for k, g in self.grads.items() if g is not None}
+        lat = dict(mesh=self.lat_mesh, mat=self.lat_mat, views=self.views, out=self.lat_out,
+                   ref=self.ref_out["image"], loss=self.w.loss, grads=grads,
+                   flags=self.det | adr.BWD_DEFER_MIP_ADJOINT, split=self.split_lat)
+        return ref, lat
+
     def tune(self, ctx, tuner: Tuner):
         w = self.w
         B, res = w.dirs.shape[0], w.width
@@ -104,10 +128,16 @@ def lr_at(lr0: float, t: int) -> float:
 
 class Batch:
     """Meshes stepped either one at a time (``step_plain``) or as one
-    graph-captured batch (``capture`` then ``step``)."""
+    graph-captured batch (``capture`` then ``step``) of the given form
+    ("launch": one launch per stage over all meshes; "streams": per-mesh
+    launches over several streams)."""
 
     def __init__(self, workloads, n_steps: int, n_streams: int = 4, det: bool = False, tune: bool = True,
-                 seed: int = 0, tuner: Tuner | None = None, progress=None):
+                 seed: int = 0, tuner: Tuner | None = None, progress=None, form: str = "launch"):
+        assert form in ("launch", "streams")
+        self.form = form
+        if form == "launch":
+            n_streams = 1
         self.ctxs = [adr.Context(0) for _ in range(n_streams)]
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]   # default priority
         self.meshes = []
@@ -124,12 +154,22 @@ class Batch:
         self.all_maps = [mp for m in self.meshes for mp in m.maps]
         self.graph = None
         self.lr = workloads[0].lr
+        self.ref_batch = self.lat_batch = None
+        if form == "launch":
+            items = [m.batch_items() for m in self.meshes]
+            self.ref_batch = adr.RenderBatch(self.ctxs[0], [r for r, _ in items])
+            self.lat_batch = adr.RenderBatch(self.ctxs[0], [lt for _, lt in items])
 
     def _adam(self, t: int):
         adr.adam_step(self.ctxs[0], self.all_params, t + 1, lr_at(self.lr, t))
         adr.adam_step_maps(self.ctxs[0], self.all_maps, t + 1, lr_at(self.lr, t))
 
     def _launch_all(self):
+        if self.form == "launch":
+            self.ref_batch.fwd()
+            self.lat_batch.fwd()
+            self.lat_batch.bwd()
+            return
         cur = torch.cuda.current_stream()
         for s in self.streams:
             s.wait_stream(cur)
@@ -176,7 +216,15 @@ class Batch:
     def losses(self):
         return [m.loss() for m in self.meshes]
 
+    def scratch_bytes(self) -> int:
+        """Device bytes of the two library batches (launch form)."""
+        return sum(b.info()["bytes"] for b in (self.ref_batch, self.lat_batch) if b is not None)
+
     def close(self):
         self.graph = None
+        for b in (self.ref_batch, self.lat_batch):
+            if b is not None:
+                b.close()
+        self.ref_batch = self.lat_batch = None
         for c in self.ctxs:
             c.close()

@@ -23,21 +23,6 @@
 
 namespace adr {
 
-struct AAArgs {
-  MeshD m;
-  ViewsD v;
-  const int4* snap;
-  const int8_t* orient;
-  const uint64_t* vis;
-  const float* color;
-  int tiles_x, tiles_y;
-  int no_aa;
-  float4* stats;  // per (sample) pixel (W, acc) of the received antialiasing: written by the
-                  // forward, read by the adjoint instead of re-evaluating pairs (NULL: none)
-  float* codes;   // per pixel, codes of the pairs with the right and the upper neighbour
-  int code_stride;  // floats between two pixels' code pairs (pixel o's at codes[code_stride * o])
-};
-
 
 // The crossing edge of pair (P, Q) for front triangle F, or false.
 struct Cross {
@@ -305,13 +290,15 @@ __device__ __forceinline__ f3 sample_grad(const AAArgs& a, const float* dimage, 
 // pair (x0 + c - 1, x0 + c) in row y0 + r, vc[r][c] that of (y0 + r - 1,
 // y0 + r) in column x0 + c.  With a stats buffer the pixels' own codes also
 // go to it for the adjoint.
-// (6 waves per SIMD: the compiler's own choice, 88 VGPRs, gives 5 and ran 6% slower)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_aa_fwd(AAArgs a, const float* __restrict__ ref, int loss_kind,
-                                                float* __restrict__ image, float* __restrict__ dimage,
-                                                float* __restrict__ partial) {
+__device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb) {
   __shared__ float hc[16][17], vc[17][16];
   __shared__ float red[4];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const AAArgs& a = f.a;
+  const float* __restrict__ ref = f.ref;
+  const int loss_kind = f.loss_kind;
+  float* __restrict__ image = f.image;
+  float* __restrict__ dimage = f.dimage;
+  const int tile = xcd_tile(bid, nb);
   const Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lx = (wave & 1) * 8 + (lane & 7), ly = (wave >> 1) * 8 + (lane >> 3);
@@ -390,23 +377,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
     if (lane == 0) red[wave] = lsum;
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) f.partial[bid] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
+// (6 waves per SIMD: the compiler's own choice, 88 VGPRs, gives 5 and ran 6% slower)
+ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
 
-__global__ void k_loss_reduce(const float* __restrict__ partial, int n, float inv_n,
-                              float* __restrict__ loss) {
+__device__ __forceinline__ void loss_reduce_body(const LossReduceArgs& a, int, int) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += (double)partial[i];
+  for (int i = threadIdx.x; i < a.n; i += 256) acc += (double)a.partial[i];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) loss[0] = (float)(red[0] * (double)inv_n);
+  if (threadIdx.x == 0) a.loss[0] = (float)(red[0] * (double)a.inv_n);
 }
+ADR_KERNEL(__launch_bounds__(256), k_loss_reduce, LossReduceArgs, loss_reduce_body)
 
 // Adjoint.  With out(r) = c(r) + acc(r) / M(r), M = max(1, W):
 //   d out(r) / d c(r) = 1 - W(r)/M(r),  d out(r) / d c(k) = w_k / M(r),
@@ -415,12 +404,13 @@ __global__ void k_loss_reduce(const float* __restrict__ partial, int n, float in
 // its four pairs; a receiver's W and acc are recomputed from its own pairs);
 // the gradient of a pair's crossing parameter s w.r.t. the clip coordinates
 // of its edge is scattered once, by the left (or lower) pixel of the pair.
-// (3 waves per SIMD: the compiler's own choice, 170 VGPRs, drops to 2)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_aa_bwd(AAArgs a, const float* __restrict__ dimage,
-                                                const float* __restrict__ dloss,
-                                                float* __restrict__ gcolor,
-                                                unsigned long long* __restrict__ fclip, bool det) {
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void aa_bwd_body(const AABwdArgs& b, int bid, int nb) {
+  const AAArgs& a = b.a;
+  const float* __restrict__ dimage = b.dimage;
+  const float* __restrict__ dloss = b.dloss;
+  unsigned long long* __restrict__ fclip = b.fclip;
+  const bool det = b.det;
+  int tile = xcd_tile(bid, nb);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   if (!p.ok) return;
   float scale = dloss ? dloss[0] : 1.0f;
@@ -499,8 +489,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
   }
-  st3(gcolor, o, gc);
+  st3(b.gcolor, o, gc);
 }
+// (3 waves per SIMD: the compiler's own choice, 170 VGPRs, drops to 2)
+ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))), k_aa_bwd, AABwdArgs, aa_bwd_body)
 
 // stats: the caller's buffer of 8 floats per pixel, two planes: the pixels'
 // (W, acc) float4s, then their pair codes (2 floats each); without it the
@@ -525,33 +517,44 @@ static AAArgs make_aa(const MeshD& m, const ViewsD& v, const Scratch& s, const u
   return a;
 }
 
+// The antialiasing and loss forward of one-sample pixels (0 blocks when there
+// is neither an image nor a reference).
+Plan<AAFwdArgs> plan_aa_fwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                            const float* color, const float* ref, int loss_kind, int no_aa, float* image,
+                            float* dimage, float* stats) {
+  AAFwdArgs f{};
+  f.a = make_aa(m, v, s, vis, color, no_aa, stats);
+  f.ref = ref;
+  f.loss_kind = loss_kind;
+  f.image = image;
+  f.dimage = dimage;
+  f.partial = s.partial;
+  return {f, (!image && !ref) ? 0u : (unsigned)(f.a.tiles_x * f.a.tiles_y * v.B)};
+}
+
 hipError_t launch_aa_loss_fwd(const MeshD& m, const ViewsD& v, const Scratch& s,
                               const uint64_t* vis, const float* color, const float* ref,
                               int loss_kind, int no_aa, float* image, float* dimage, float* loss,
                               hipStream_t st, float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, stats);
-  int nb = a.tiles_x * a.tiles_y * v.B;
   if (!image && !ref) return hipSuccess;
   hipError_t e;
   if (v.ms > 1) {
     // antialiased samples, then the resolve and the loss per pixel
-    hipLaunchKernelGGL(k_aa_fwd, dim3(nb), dim3(256), 0, st, a, (const float*)nullptr, loss_kind,
-                       s.image_s, (float*)nullptr, s.partial);
+    ADR_LAUNCH_1(k_aa_fwd, plan_aa_fwd(m, v, s, vis, color, nullptr, loss_kind, no_aa, s.image_s, nullptr, stats), st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t n = (int64_t)v.B * (v.H / v.ms) * (v.W / v.ms);
-    nb = (int)((n + 255) / 256);
+    const int nb = (int)((n + 255) / 256);
     hipLaunchKernelGGL(k_msaa_resolve, dim3(nb), dim3(256), 0, st, v, s.image_s, ref, loss_kind, image, dimage,
                        s.partial);
   } else {
-    hipLaunchKernelGGL(k_aa_fwd, dim3(nb), dim3(256), 0, st, a, ref, loss_kind, image, dimage, s.partial);
+    ADR_LAUNCH_1(k_aa_fwd, plan_aa_fwd(m, v, s, vis, color, ref, loss_kind, no_aa, image, dimage, stats), st);
   }
   return hipGetLastError();
 }
 
 // The loss from the per-block partials of launch_aa_loss_fwd (a second,
 // one-block launch; nothing to do without a reference).
-hipError_t launch_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss, hipStream_t st) {
-  if (!ref) return hipSuccess;
+Plan<LossReduceArgs> plan_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss) {
   int nb;
   if (v.ms > 1) {
     nb = (int)(((int64_t)v.B * v.Hp * v.Wp + 255) / 256);
@@ -560,16 +563,45 @@ hipError_t launch_loss_reduce(const ViewsD& v, const float* ref, const Scratch& 
   }
   // partials hold sums; the mean's 1/N is applied here
   const double n = 3.0 * (double)v.B * v.Hp * v.Wp;
-  hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, s.partial, nb, (float)(1.0 / n), loss);
+  return {LossReduceArgs{s.partial, nb, (float)(1.0 / n), loss}, ref ? 1u : 0u};
+}
+
+hipError_t launch_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss, hipStream_t st) {
+  ADR_LAUNCH_1(k_loss_reduce, plan_loss_reduce(v, ref, s, loss), st);
   return hipGetLastError();
+}
+
+Plan<AABwdArgs> plan_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                            const float* color, const float* dimage, const float* dloss, int no_aa,
+                            const float* stats) {
+  AABwdArgs b{};
+  b.a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats));
+  b.dimage = dimage;
+  b.dloss = dloss;
+  b.gcolor = s.gcolor;
+  b.fclip = s.fix_clip;
+  b.det = s.det;
+  return {b, (unsigned)(b.a.tiles_x * b.a.tiles_y * v.B)};
 }
 
 hipError_t launch_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
                          const float* color, const float* dimage, const float* dloss, int no_aa,
                          hipStream_t st, const float* stats) {
-  AAArgs a = make_aa(m, v, s, vis, color, no_aa, const_cast<float*>(stats));
-  int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_aa_bwd, dim3(nb), dim3(256), 0, st, a, dimage, dloss, s.gcolor, s.fix_clip, s.det);
+  ADR_LAUNCH_1(k_aa_bwd, plan_aa_bwd(m, v, s, vis, color, dimage, dloss, no_aa, stats), st);
+  return hipGetLastError();
+}
+
+// ---- batched launches ----
+hipError_t launch_aa_fwd_n(const Stage<AAFwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_aa_fwd, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_loss_reduce_n(const Stage<LossReduceArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_loss_reduce, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_aa_bwd_n(const Stage<AABwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_aa_bwd, s, st);
   return hipGetLastError();
 }
 

@@ -1183,3 +1183,463 @@ adr_status adr_job_poll(adr_ctx* ctx, uint64_t job_id, adr_job_status* st, adr_j
 }
 
 }  // extern "C"
+
+// ---- batches: one launch per stage over the work of every item ----
+//
+// Each item keeps its own scratch (one device allocation for the batch,
+// carved per item); at creation every stage's launch is planned per item
+// (argument block and grid, as the single entry points plan it) and the
+// non-empty plans are written to device tables: the argument blocks, and the
+// first block of each item's range with the launch's total at the end.  A
+// call then launches each stage once over all items.
+
+namespace {
+
+template <class A>
+struct HostStage {
+  std::vector<A> args;
+  std::vector<int> start{0};
+  size_t tab_off = 0, start_off = 0;
+  bool too_big = false;
+  void add(const Plan<A>& p) {
+    if (p.blocks == 0) return;
+    const int64_t total = (int64_t)start.back() + p.blocks;
+    if (total > 0x7fffffffLL) {
+      too_big = true;
+      return;
+    }
+    args.push_back(p.a);
+    start.push_back((int)total);
+  }
+  // offsets of the two tables from `off` (256-byte aligned); the bytes used
+  size_t place(size_t off) {
+    tab_off = (off + 255) & ~(size_t)255;
+    start_off = (tab_off + sizeof(A) * args.size() + 255) & ~(size_t)255;
+    return start_off + sizeof(int) * start.size();
+  }
+  void write(std::vector<unsigned char>& host) const {
+    if (!args.empty()) memcpy(host.data() + tab_off, args.data(), sizeof(A) * args.size());
+    memcpy(host.data() + start_off, start.data(), sizeof(int) * start.size());
+  }
+  Stage<A> device(unsigned char* base) const {
+    Stage<A> s;
+    s.tab = reinterpret_cast<const A*>(base + tab_off);
+    s.start = reinterpret_cast<const int*>(base + start_off);
+    s.n = (int)args.size();
+    s.total = start.back();
+    return s;
+  }
+};
+
+struct BatchItem {
+  MeshD m;
+  ViewsD v;
+  Tex kd, nm, orm;
+  int model = 0;
+  const float* ref = nullptr;
+  int32_t loss_kind = 0;
+  const float* dloss = nullptr;
+  adr_fwd_out out{};
+  adr_grads grads{};
+  bool bwd = false;
+  int32_t flags = 0;
+  int slots = 0;
+  Scratch s{};
+};
+
+// The scratch of one item carved from `base` (nullptr: sizes only); returns
+// the bytes used.  Sizes as prepare_scratch allocates them.
+size_t batch_carve(const MeshD& m, const ViewsD& v, bool bwd, int slots, bool det, unsigned char* base, Scratch* s) {
+  const size_t B = v.B, V = m.n_pos > 0 ? m.n_pos : 1, T = m.n_tri > 0 ? m.n_tri : 1;
+  const size_t px = B * (size_t)v.W * v.H;
+  const size_t tiles = (size_t)((v.W + 15) / 16) * ((v.H + 15) / 16) * B;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> unsigned char* {
+    const size_t o = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return base ? base + o : nullptr;
+  };
+  Scratch t{};
+  t.snap = (int*)take(B * V * 16);
+  t.orient = (int8_t*)take(B * T);
+  t.nacc = (double*)take(V * 24);
+  t.tacc = (double*)take(V * 24);
+  t.nrm = (float*)take(V * 12);
+  t.tan = (float*)take(V * 12);
+  t.big = (uint32_t*)take(B * T * 4);
+  t.big_cnt = (uint32_t*)take((B + 1) * 4);
+  t.med = (uint32_t*)take(B * T * 4);
+  t.partial = (float*)take(tiles * 4);
+  t.mvpd = (double*)take(B * 128);
+  t.n_partial = (int)tiles;
+  t.det = det;
+  if (det) {
+    t.fix_n = (unsigned long long*)take(V * 24);
+    t.fix_t = (unsigned long long*)take(V * 24);
+  }
+  if (bwd) {
+    t.gcolor = (float*)take(px * 12);
+    t.dclip = (float*)take(B * V * 16);
+    t.dattr = (float*)take(V * 36);
+    if (slots > 0) t.texrec = (float4*)take((size_t)(1 + slots) * px * 16);
+    t.fix_attr = (unsigned long long*)take(V * 72);
+    t.fix_clip = (unsigned long long*)take(B * V * 32);
+    t.fix_pos = (unsigned long long*)take(V * 24);
+  }
+  if (s) *s = t;
+  return off;
+}
+
+}  // namespace
+
+struct adr_batch {
+  adr_ctx* ctx = nullptr;
+  std::vector<BatchItem> items;
+  void* arena = nullptr;    // every item's scratch
+  void* det_arena = nullptr;  // the deterministic texel sort's buffers, shared by the items in turn
+  void* tables = nullptr;
+  bool fwd_done = false, any_bwd = false;
+  uint64_t scratch_bytes = 0;  // device bytes the batch holds
+  // forward
+  Stage<FillSet> frame_fill;
+  Stage<FaceAccumArgs> faces;
+  Stage<VertexNormalizeArgs> verts;
+  Stage<XformArgs> xform;
+  Stage<ClearArgs> clear;
+  Stage<RasterArgs> r_small, r_med, r_big;
+  Stage<ShadeFwdArgs> shade;
+  Stage<AAFwdArgs> aa;
+  Stage<LossReduceArgs> loss;
+  // backward
+  Stage<FillSet> bwd_fill;
+  Stage<AABwdArgs> aa_bwd;
+  Stage<ShadeBwdArgs> shade_bwd;
+  Stage<FixToF32Args> conv;
+  Stage<TexBwdArgs> tex;
+  Stage<VertexBwdArgs> vbwd;
+  Stage<FaceBwdArgs> fbwd;
+  Stage<FixAddArgs> fadd;
+  std::vector<int> det_tex;  // items whose texel adjoint is the deterministic sort
+  std::vector<int> mips;     // items whose mip adjoint runs in the backward
+};
+
+static void batch_free(adr_batch* b) {
+  if (!b) return;
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->det_arena) (void)hipFree(b->det_arena);
+  if (b->tables) (void)hipFree(b->tables);
+  delete b;
+}
+
+extern "C" {
+
+adr_status adr_batch_create(adr_ctx* ctx, int32_t n, const adr_batch_item* items, adr_batch** out) {
+  if (!out) return fail(ADR_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(ADR_E_INVALID, "ctx is NULL");
+  ctx->geom_ok = false;
+  if (n < 1 || !items) return fail(ADR_E_INVALID, "a batch needs 1 or more items (n = %d)", n);
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  adr_batch* b = new (std::nothrow) adr_batch();
+  if (!b) return fail(ADR_E_NOMEM, "batch");
+  b->ctx = ctx;
+  b->items.resize(n);
+  size_t arena = 0, det_bytes = 0;
+  int64_t det_E = 0, det_hw = 0;
+  std::vector<size_t> offs(n);
+  for (int i = 0; i < n; ++i) {
+    const adr_batch_item& it = items[i];
+    BatchItem& bi = b->items[i];
+    adr_status r = check_fwd(ctx, it.mesh, it.mat, it.views, it.ref_image, it.loss_kind, it.out, it.flags, bi.m,
+                             bi.v, bi.kd, bi.nm, bi.orm);
+    if (r != ADR_OK) {
+      batch_free(b);
+      return fail(r, "batch item %d: %s", i, adr_last_error());
+    }
+    if (it.flags & ~(ADR_FWD_NO_AA | ADR_DETERMINISTIC | ADR_INDEPENDENT_MIPS | ADR_BWD_DEFER_MIP_ADJOINT)) {
+      batch_free(b);
+      return fail(ADR_E_INVALID,
+                  "batch item %d: flags 0x%x (a batch takes ADR_FWD_NO_AA, ADR_DETERMINISTIC, "
+                  "ADR_INDEPENDENT_MIPS and ADR_BWD_DEFER_MIP_ADJOINT; build mip chains with adr_mip_build)",
+                  i, it.flags);
+    }
+    const bool det = (it.flags & ADR_DETERMINISTIC) != 0;
+    bi.model = it.mat->model;
+    bi.ref = it.ref_image;
+    bi.loss_kind = it.loss_kind;
+    bi.dloss = it.dloss;
+    bi.out = *it.out;
+    bi.flags = it.flags;
+    bi.bwd = it.grads != nullptr;
+    if (bi.bwd) {
+      bi.grads = *it.grads;
+      if (!it.ref_image) {
+        batch_free(b);
+        return fail(ADR_E_INVALID, "batch item %d: gradients need a reference image", i);
+      }
+      if (bi.grads.kd && bi.kd.fmt != ADR_TEX_F32) {
+        batch_free(b);
+        return fail(ADR_E_INVALID, "batch item %d: kd gradient needs an F32 kd map", i);
+      }
+      if (bi.grads.orm && bi.model != ADR_SHADE_GGX) {
+        batch_free(b);
+        return fail(ADR_E_INVALID, "batch item %d: orm gradient needs GGX", i);
+      }
+      bi.slots = tex_slots(bi.model, bi.grads.kd, bi.grads.normal, bi.grads.orm);
+      b->any_bwd = true;
+      if (det && bi.slots > 0) {
+        const int64_t E = det_entries(bi.v, bi.slots);
+        if (E >= (int64_t)0xFFFFFFFF) {
+          batch_free(b);
+          return fail(ADR_E_INVALID, "batch item %d: deterministic mode: view batch too large", i);
+        }
+        det_E = std::max(det_E, E);
+        det_hw = std::max(det_hw, radix_hist_words(E));
+      }
+    }
+    offs[i] = arena;
+    arena += batch_carve(bi.m, bi.v, bi.bwd, bi.slots, det, nullptr, nullptr);
+  }
+  hipError_t e = hipMalloc(&b->arena, arena);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return fail(ADR_E_NOMEM, "batch scratch: hipMalloc(%zu): %s", arena, hipGetErrorString(e));
+  }
+  // the deterministic sort's buffers, sized for the largest item
+  Scratch det{};
+  if (det_E > 0) {
+    const int64_t tiles = (det_E + 2047) / 2048;
+    const size_t parts[8] = {(size_t)det_E * 4, (size_t)det_E * 4, (size_t)det_E * 4, (size_t)det_E * 4,
+                             (size_t)det_E * 16, (size_t)det_hw * 4, (size_t)scan_tmp_words(det_hw) * 4 + 4,
+                             (size_t)tiles * 32};
+    size_t o[8];
+    for (int k = 0; k < 8; ++k) {
+      o[k] = det_bytes;
+      det_bytes += (parts[k] + 255) & ~(size_t)255;
+    }
+    if ((e = hipMalloc(&b->det_arena, det_bytes)) != hipSuccess) {
+      batch_free(b);
+      return fail(ADR_E_NOMEM, "batch sort buffers: hipMalloc(%zu): %s", det_bytes, hipGetErrorString(e));
+    }
+    unsigned char* d = static_cast<unsigned char*>(b->det_arena);
+    det.det_k0 = (uint32_t*)(d + o[0]);
+    det.det_v0 = (uint32_t*)(d + o[1]);
+    det.det_k1 = (uint32_t*)(d + o[2]);
+    det.det_v1 = (uint32_t*)(d + o[3]);
+    det.det_vals = (float4*)(d + o[4]);
+    det.det_hist = (uint32_t*)(d + o[5]);
+    det.det_tmp = (uint32_t*)(d + o[6]);
+    det.det_part = (float4*)(d + o[7]);
+  }
+  // plan every stage of every item
+  HostStage<FillSet> frame_fill, bwd_fill;
+  HostStage<FaceAccumArgs> faces;
+  HostStage<VertexNormalizeArgs> verts;
+  HostStage<XformArgs> xform;
+  HostStage<ClearArgs> clear;
+  HostStage<RasterArgs> r_small, r_med, r_big;
+  HostStage<ShadeFwdArgs> shade;
+  HostStage<AAFwdArgs> aa;
+  HostStage<LossReduceArgs> loss;
+  HostStage<AABwdArgs> aa_bwd;
+  HostStage<ShadeBwdArgs> shade_bwd;
+  HostStage<FixToF32Args> conv;
+  HostStage<TexBwdArgs> tex;
+  HostStage<VertexBwdArgs> vbwd;
+  HostStage<FaceBwdArgs> fbwd;
+  HostStage<FixAddArgs> fadd;
+  for (int i = 0; i < n; ++i) {
+    BatchItem& bi = b->items[i];
+    const adr_batch_item& it = items[i];
+    const bool det_i = (bi.flags & ADR_DETERMINISTIC) != 0;
+    batch_carve(bi.m, bi.v, bi.bwd, bi.slots, det_i, static_cast<unsigned char*>(b->arena) + offs[i], &bi.s);
+    Scratch& s = bi.s;
+    s.tiny_bbox = it.tiny_bbox > 0 ? it.tiny_bbox : ctx->tiny_bbox;
+    s.med_bbox = it.med_bbox > 0 ? it.med_bbox : ctx->med_bbox;
+    if (s.tiny_bbox > s.med_bbox) {
+      batch_free(b);
+      return fail(ADR_E_INVALID, "batch item %d: raster split %d > %d", i, s.tiny_bbox, s.med_bbox);
+    }
+    if (det_i && bi.slots > 0) {
+      s.det_k0 = det.det_k0;
+      s.det_v0 = det.det_v0;
+      s.det_k1 = det.det_k1;
+      s.det_v1 = det.det_v1;
+      s.det_vals = det.det_vals;
+      s.det_hist = det.det_hist;
+      s.det_tmp = det.det_tmp;
+      s.det_part = det.det_part;
+    }
+    bi.v.mvpd = s.mvpd;
+    const MeshD& m = bi.m;
+    const ViewsD& v = bi.v;
+    const int64_t npx = (int64_t)v.B * v.W * v.H;
+    // a forward-only item with a precomputed frame skips the frame stage
+    if (!bi.bwd && it.mesh->nrm && it.mesh->tan) {
+      s.nrm = const_cast<float*>(it.mesh->nrm);
+      s.tan = const_cast<float*>(it.mesh->tan);
+    } else {
+      const FramePlans fp = plan_vertex_frame(m, s);
+      frame_fill.add(fp.fill);
+      faces.add(fp.faces);
+      verts.add(fp.verts);
+    }
+    xform.add(plan_xform(m, v, s));
+    clear.add(plan_clear_vis(bi.out.vis, bi.out.coverage, npx, s.big_cnt, v.B));
+    const RasterPlans rp = plan_raster(m, v, s, bi.out.vis, bi.out.coverage, nullptr);
+    r_small.add({rp.a, rp.small});
+    r_med.add({rp.a, rp.med});
+    r_big.add({rp.a, rp.big});
+    shade.add(plan_shade_fwd(m, v, bi.model, bi.kd, bi.nm, bi.orm, s, bi.out.vis, bi.out.color, bi.out.tri_id,
+                             nullptr, nullptr));
+    aa.add(plan_aa_fwd(m, v, s, bi.out.vis, bi.out.color, bi.ref, bi.loss_kind, (bi.flags & ADR_FWD_NO_AA) ? 1 : 0,
+                       bi.out.image, bi.out.dimage, bi.out.aa));
+    if (bi.ref) loss.add(plan_loss_reduce(v, bi.ref, s, bi.out.loss));
+    if (!bi.bwd) continue;
+    const adr_grads& g = bi.grads;
+    const int64_t V = m.n_pos > 0 ? m.n_pos : 1;
+    const int64_t n_clip = 4 * (int64_t)v.B * V, n_attr = 9 * V;
+    FillSet f{};
+    f.add(s.fix_clip, n_clip);
+    f.add(s.fix_attr, n_attr);
+    f.add(s.fix_pos, 3 * V);
+    bwd_fill.add(plan_fill_multi(f));
+    aa_bwd.add(plan_aa_bwd(m, v, s, bi.out.vis, bi.out.color, bi.out.dimage, bi.dloss,
+                           (bi.flags & ADR_FWD_NO_AA) ? 1 : 0, bi.out.aa));
+    shade_bwd.add(plan_shade_bwd(m, v, bi.model, bi.kd, bi.nm, bi.orm, g.kd, g.normal, g.orm, s, bi.out.vis, nullptr,
+                                 nullptr, nullptr));
+    conv.add(plan_fix_to_f32(s.fix_clip, s.dclip, n_clip, det_i, s.fix_attr, s.dattr, n_attr));
+    if (det_i) {
+      if (bi.slots > 0) b->det_tex.push_back(i);
+    } else {
+      tex.add(plan_tex_bwd(v, bi.model, bi.kd, bi.nm, bi.orm, g.kd, g.normal, g.orm, s, nullptr, nullptr));
+    }
+    if (!(bi.flags & (ADR_INDEPENDENT_MIPS | ADR_BWD_DEFER_MIP_ADJOINT))) b->mips.push_back(i);
+    const MeshBwdPlans mp = plan_mesh_bwd(m, v, s, g.pos, g.vnormal);
+    vbwd.add(mp.verts);
+    fbwd.add(mp.faces);
+    fadd.add(mp.add);
+  }
+  // the tables, uploaded once
+  bool too_big = false;
+  size_t bytes = 0;
+  auto place = [&](auto& hs) {
+    too_big |= hs.too_big;
+    bytes = hs.place(bytes);
+  };
+  place(frame_fill), place(faces), place(verts), place(xform), place(clear), place(r_small), place(r_med);
+  place(r_big), place(shade), place(aa), place(loss), place(bwd_fill), place(aa_bwd), place(shade_bwd);
+  place(conv), place(tex), place(vbwd), place(fbwd), place(fadd);
+  if (too_big) {
+    batch_free(b);
+    return fail(ADR_E_INVALID, "batch: a stage needs 2^31 or more blocks");
+  }
+  std::vector<unsigned char> host(bytes);
+  auto write = [&](const auto& hs) { hs.write(host); };
+  write(frame_fill), write(faces), write(verts), write(xform), write(clear), write(r_small), write(r_med);
+  write(r_big), write(shade), write(aa), write(loss), write(bwd_fill), write(aa_bwd), write(shade_bwd);
+  write(conv), write(tex), write(vbwd), write(fbwd), write(fadd);
+  if ((e = hipMalloc(&b->tables, bytes)) != hipSuccess) {
+    batch_free(b);
+    return fail(ADR_E_NOMEM, "batch tables: hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(b->tables, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+    batch_free(b);
+    return hip_fail(e, "batch tables: hipMemcpy");
+  }
+  unsigned char* t = static_cast<unsigned char*>(b->tables);
+  b->frame_fill = frame_fill.device(t);
+  b->faces = faces.device(t);
+  b->verts = verts.device(t);
+  b->xform = xform.device(t);
+  b->clear = clear.device(t);
+  b->r_small = r_small.device(t);
+  b->r_med = r_med.device(t);
+  b->r_big = r_big.device(t);
+  b->shade = shade.device(t);
+  b->aa = aa.device(t);
+  b->loss = loss.device(t);
+  b->bwd_fill = bwd_fill.device(t);
+  b->aa_bwd = aa_bwd.device(t);
+  b->shade_bwd = shade_bwd.device(t);
+  b->conv = conv.device(t);
+  b->tex = tex.device(t);
+  b->vbwd = vbwd.device(t);
+  b->fbwd = fbwd.device(t);
+  b->fadd = fadd.device(t);
+  b->scratch_bytes = arena + det_bytes + bytes;
+  *out = b;
+  return ADR_OK;
+}
+
+adr_status adr_batch_fwd(adr_batch* b, adr_stream stream) {
+  if (!b) return fail(ADR_E_INVALID, "batch is NULL");
+  adr_ctx* ctx = b->ctx;
+  ctx->geom_ok = false;
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  TIMED(0, launch_fill_multi_n(b->frame_fill, st), "vertex frame");
+  TIMED(0, launch_face_accum_n(b->faces, st), "vertex frame");
+  TIMED(0, launch_vertex_normalize_n(b->verts, st), "vertex frame");
+  TIMED(1, launch_xform_n(b->xform, st), "transform");
+  TIMED(12, launch_clear_vis_n(b->clear, st), "clear");
+  TIMED(2, launch_raster_n(b->r_small, b->r_med, b->r_big, st), "raster");
+  TIMED(3, launch_shade_fwd_n(b->shade, st), "shade");
+  TIMED(4, launch_aa_fwd_n(b->aa, st), "antialias/loss");
+  TIMED(18, launch_loss_reduce_n(b->loss, st), "loss reduction");
+  b->fwd_done = true;
+  return ADR_OK;
+}
+
+adr_status adr_batch_bwd(adr_batch* b, adr_stream stream) {
+  if (!b) return fail(ADR_E_INVALID, "batch is NULL");
+  adr_ctx* ctx = b->ctx;
+  ctx->geom_ok = false;
+  if (!b->any_bwd) return fail(ADR_E_INVALID, "batch: no item has gradients");
+  if (!b->fwd_done) return fail(ADR_E_INVALID, "batch: the backward needs a forward of the batch first");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHK(hipSetDevice(ctx->device), "hipSetDevice");
+  TIMED(12, launch_fill_multi_n(b->bwd_fill, st), "clear");
+  TIMED(5, launch_aa_bwd_n(b->aa_bwd, st), "antialias adjoint");
+  TIMED(6, launch_shade_bwd_n(b->shade_bwd, st), "shading adjoint");
+  TIMED(12, launch_fix_to_f32_n(b->conv, st), "accumulator conversion");
+  TIMED(11, launch_tex_bwd_n(b->tex, st), "texel adjoint");
+  for (int i : b->det_tex) {
+    const BatchItem& bi = b->items[i];
+    TIMED(11, launch_tex_bwd(bi.v, bi.model, bi.kd, bi.nm, bi.orm, bi.grads.kd, bi.grads.normal, bi.grads.orm,
+                             bi.s, st),
+          "texel adjoint");
+  }
+  for (int i : b->mips) {
+    const BatchItem& bi = b->items[i];
+    MipSet ms{};
+    const Tex* maps[3] = {&bi.kd, &bi.nm, &bi.orm};
+    float* gs[3] = {bi.grads.kd, bi.grads.normal, bi.grads.orm};
+    for (int k = 0; k < 3; ++k)
+      if (gs[k] && maps[k]->levels > 1 && (k < 2 || bi.model == ADR_SHADE_GGX)) {
+        ms.t[ms.n] = *maps[k];
+        ms.g[ms.n++] = gs[k];
+      }
+    if (ms.n) TIMED(7, launch_mip_adjoint_set(ms, st), "mip adjoint");
+  }
+  TIMED(8, launch_vertex_bwd_n(b->vbwd, st), "mesh adjoint");
+  TIMED(8, launch_face_bwd_n(b->fbwd, st), "mesh adjoint");
+  TIMED(8, launch_fix_add_n(b->fadd, st), "mesh adjoint");
+  return ADR_OK;
+}
+
+adr_status adr_batch_info(const adr_batch* b, int32_t* n_items, uint64_t* scratch_bytes) {
+  if (!b) return fail(ADR_E_INVALID, "batch is NULL");
+  if (n_items) *n_items = (int32_t)b->items.size();
+  if (scratch_bytes) *scratch_bytes = b->scratch_bytes;
+  return ADR_OK;
+}
+
+adr_status adr_batch_destroy(adr_batch* b) {
+  if (!b) return ADR_OK;
+  HIPCHK(hipSetDevice(b->ctx->device), "hipSetDevice");
+  batch_free(b);  // hipFree waits for the device
+  return ADR_OK;
+}
+
+}  // extern "C"

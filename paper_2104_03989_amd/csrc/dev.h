@@ -122,6 +122,55 @@ __device__ __forceinline__ double acc_val(unsigned long long x, bool det) {
   return det ? fix_val(x) : __longlong_as_double((long long)x);
 }
 
+// Batched launches: one grid over the blocks of n items, item k owning
+// blocks [start[k], start[k+1]) (an item may own none).  The item of block
+// bid is the last k with start[k] <= bid, found by a binary search on
+// values that are the same for the whole block.  The tables are read through
+// the constant address space (they do not change while a kernel runs), so
+// the argument blocks load into scalar registers once and the pointers in
+// them are known to be global, as with kernel arguments.
+#define ADR_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ int batch_item(const ADR_CONST int* start, int n, int bid) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <class T>
+inline const ADR_CONST T* const_tab(const T* p) {
+  return (const ADR_CONST T*)p;
+}
+
+// A kernel written as a body BODY(args, block, blocks) with two entry
+// points: NAME runs one argument block over its grid, NAME_n the batched
+// launch over the items of a stage (each block runs its item's body with
+// the block's index within the item's range).
+#define ADR_KERNEL(ATTR, NAME, ARGS, BODY)                                                             \
+  __global__ ATTR void NAME(ARGS a) { BODY(a, (int)blockIdx.x, (int)gridDim.x); }                   \
+  __global__ ATTR void NAME##_n(const ADR_CONST ARGS* tab, const ADR_CONST int* start, int n) {     \
+    const int it_ = batch_item(start, n, (int)blockIdx.x);                                            \
+    const int s0_ = start[it_];                                                                       \
+    BODY(*(const ARGS*)&tab[it_], (int)blockIdx.x - s0_, start[it_ + 1] - s0_);                       \
+  }
+
+// Launches the single entry point of a kernel with a plan's argument block.
+#define ADR_LAUNCH_1(NAME, PLAN, ST)                                                          \
+  do {                                                                                        \
+    if ((PLAN).blocks > 0) hipLaunchKernelGGL(NAME, dim3((PLAN).blocks), dim3(256), 0, ST, (PLAN).a); \
+  } while (0)
+
+// Launches the batched entry point of a kernel over a stage.
+#define ADR_LAUNCH_N(NAME, STAGE, ST)                                                                 \
+  do {                                                                                                 \
+    if ((STAGE).total > 0)                                                                             \
+      hipLaunchKernelGGL(NAME##_n, dim3((unsigned)(STAGE).total), dim3(256), 0, ST,                    \
+                         const_tab((STAGE).tab), const_tab((STAGE).start), (STAGE).n);                 \
+  } while (0)
+
 // Blocks are dispatched round-robin over the 8 XCDs of an MI355X; each XCD
 // has its own L2.  This maps the hardware block id to a logical tile id so
 // that every XCD works through one contiguous range of tiles (neighbouring

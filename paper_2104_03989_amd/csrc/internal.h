@@ -115,6 +115,190 @@ struct TessD {
   int n;
 };
 
+// Zero-fill of several ranges of 8-byte words in one launch.
+constexpr int kFillRanges = 6;
+struct FillSet {
+  unsigned long long* p[kFillRanges];
+  int64_t len[kFillRanges];
+  int n;
+  void add(unsigned long long* q, int64_t l) {
+    if (q && l > 0 && n < kFillRanges) {
+      p[n] = q;
+      len[n++] = l;
+    }
+  }
+};
+// ---- batched launches ----
+// A kernel launch as a batch takes it: the kernel's argument block and its
+// grid (0 blocks: nothing to launch).
+template <class A>
+struct Plan {
+  A a;
+  unsigned blocks;
+};
+// One stage of a batch: the argument blocks of n items in device memory and
+// the first block of each item's range, start[n] = the launch's blocks.
+template <class A>
+struct Stage {
+  const A* tab = nullptr;
+  const int* start = nullptr;
+  int n = 0, total = 0;
+};
+
+// Argument blocks of the kernels a batch launches.
+struct FaceAccumArgs {
+  MeshD m;
+  double *nacc, *tacc;
+  unsigned long long *fn, *ft;
+};
+struct VertexNormalizeArgs {
+  int n;
+  double *nacc, *tacc;
+  const unsigned long long *fn, *ft;
+  float *nrm, *tan;
+};
+struct FixToF32Args {
+  const unsigned long long* src;
+  float* dst;
+  int64_t n;
+  const unsigned long long* src2;
+  float* dst2;
+  int64_t n2;
+  bool det;
+};
+struct FixAddArgs {
+  const unsigned long long* src;
+  float* dst;
+  int64_t n;
+  bool det;
+};
+struct VertexBwdArgs {
+  MeshD m;
+  ViewsD v;
+  const float* dclip;
+  float* dattr;
+  const double *nacc, *tacc;
+  float *gpos, *gvn;
+};
+struct FaceBwdArgs {
+  MeshD m;
+  const float* dattr;
+  unsigned long long* fpos;
+  bool det;
+};
+struct FramePlans {
+  Plan<FillSet> fill;
+  Plan<FaceAccumArgs> faces;
+  Plan<VertexNormalizeArgs> verts;
+};
+struct MeshBwdPlans {
+  Plan<VertexBwdArgs> verts;
+  Plan<FaceBwdArgs> faces;
+  Plan<FixAddArgs> add;
+};
+struct XformArgs {
+  MeshD m;
+  ViewsD v;
+  int4* snap;
+  double* mvpd;
+};
+struct ClearArgs {
+  uint64_t* vis;
+  uint32_t* cov;
+  int64_t n;
+  uint32_t* big_cnt;
+  int B;
+};
+// The three raster kernels share one argument block.
+struct RasterArgs {
+  MeshD m;
+  ViewsD v;
+  const int4* snap;
+  int8_t* orient;
+  uint32_t *big, *big_cnt, *med;
+  unsigned long long* vis;
+  uint32_t* cov;
+  const unsigned long long* floor;
+  int tiny, med_max;
+  int tiles_x, tiles_y;  // kBigTile tiles
+};
+struct RasterPlans {
+  RasterArgs a;
+  unsigned small, med, big;  // blocks of the three kernels
+};
+struct ShadeArgs {
+  MeshD m;
+  ViewsD v;
+  int model;
+  Tex kd, nm, orm;
+  Tex al;                 // alpha map (data NULL: none)
+  const float* galpha;    // dL/d alpha per pixel (adjoint of a depth-peeled layer), or NULL
+  const float* nrm;
+  const float* tan;
+  const uint64_t* vis;
+  int tiles_x, tiles_y;
+};
+struct ShadeFwdArgs {
+  ShadeArgs s;
+  float* color;
+  int32_t* tri_id;
+  float* alpha;
+};
+// Gradient slots of the texture-sample records (maps with a gradient buffer).
+struct TexSlots {
+  int kd, nm, orm, al;  // slot of each map, -1 without a gradient buffer
+  int n;
+};
+struct ShadeBwdArgs {
+  ShadeArgs s;
+  TexSlots sl;
+  const float* gcolor;
+  float4* rec;
+  unsigned long long *fclip, *fattr;
+  bool det;
+};
+struct TexBwdArgs {
+  Tex t[4];
+  float* g[4];
+  int n;
+  const float4* rec;
+  ViewsD v;
+  int tiles_x, tiles_y;
+};
+struct AAArgs {
+  MeshD m;
+  ViewsD v;
+  const int4* snap;
+  const int8_t* orient;
+  const uint64_t* vis;
+  const float* color;
+  int tiles_x, tiles_y;
+  int no_aa;
+  float4* stats;  // per (sample) pixel (W, acc) of the received antialiasing: written by the
+                  // forward, read by the adjoint instead of re-evaluating pairs (NULL: none)
+  float* codes;   // per pixel, codes of the pairs with the right and the upper neighbour
+  int code_stride;  // floats between two pixels' code pairs (pixel o's at codes[code_stride * o])
+};
+struct AAFwdArgs {
+  AAArgs a;
+  const float* ref;
+  int loss_kind;
+  float *image, *dimage, *partial;
+};
+struct AABwdArgs {
+  AAArgs a;
+  const float *dimage, *dloss;
+  float* gcolor;
+  unsigned long long* fclip;
+  bool det;
+};
+struct LossReduceArgs {
+  const float* partial;
+  int n;
+  float inv_n;
+  float* loss;
+};
+
 // Records `msg` as the calling thread's last error and returns `code`.
 adr_status report(adr_status code, const char* msg);
 
@@ -167,19 +351,6 @@ int64_t radix_hist_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st);
-// Zero-fill of several ranges of 8-byte words in one launch.
-constexpr int kFillRanges = 6;
-struct FillSet {
-  unsigned long long* p[kFillRanges];
-  int64_t len[kFillRanges];
-  int n;
-  void add(unsigned long long* q, int64_t l) {
-    if (q && l > 0 && n < kFillRanges) {
-      p[n] = q;
-      len[n++] = l;
-    }
-  }
-};
 hipError_t launch_fill_multi(const FillSet& f, hipStream_t st);
 // src2/dst2 (optional): a second array converted in the same launch.
 hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st,
@@ -210,5 +381,49 @@ hipError_t launch_adam_maps_tiles(const AdamMapSet& a, int t, float lr, float b1
 hipError_t launch_adam_maps_top(const AdamMapSet& a, hipStream_t st);
 hipError_t launch_adam(const adr_param* params, int n, int t, float lr, float b1, float b2,
                        float eps, hipStream_t st);
+
+// ---- plans (argument block and grid of one launch) and batched launchers ----
+Plan<FillSet> plan_fill_multi(const FillSet& f);
+Plan<FixToF32Args> plan_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det,
+                                   const unsigned long long* src2, float* dst2, int64_t n2);
+FramePlans plan_vertex_frame(const MeshD& m, const Scratch& s);
+MeshBwdPlans plan_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos, float* gvnormal);
+Plan<XformArgs> plan_xform(const MeshD& m, const ViewsD& v, const Scratch& s);
+Plan<ClearArgs> plan_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B);
+RasterPlans plan_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis, uint32_t* cov,
+                        const uint64_t* floor);
+Plan<ShadeFwdArgs> plan_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
+                                   const Tex& orm, const Scratch& s, const uint64_t* vis, float* color,
+                                   int32_t* tri_id, const Tex* al, float* alpha);
+Plan<ShadeBwdArgs> plan_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
+                                   const Tex& orm, float* gkd, float* gnm, float* gorm, const Scratch& s,
+                                   const uint64_t* vis, const Tex* al, float* gal, const float* galpha);
+Plan<TexBwdArgs> plan_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm, float* gkd,
+                              float* gnm, float* gorm, const Scratch& s, const Tex* al, float* gal);
+Plan<AAFwdArgs> plan_aa_fwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                            const float* color, const float* ref, int loss_kind, int no_aa, float* image,
+                            float* dimage, float* stats);
+Plan<LossReduceArgs> plan_loss_reduce(const ViewsD& v, const float* ref, const Scratch& s, float* loss);
+Plan<AABwdArgs> plan_aa_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, const uint64_t* vis,
+                            const float* color, const float* dimage, const float* dloss, int no_aa,
+                            const float* stats);
+
+hipError_t launch_fill_multi_n(const Stage<FillSet>& s, hipStream_t st);
+hipError_t launch_face_accum_n(const Stage<FaceAccumArgs>& s, hipStream_t st);
+hipError_t launch_vertex_normalize_n(const Stage<VertexNormalizeArgs>& s, hipStream_t st);
+hipError_t launch_fix_to_f32_n(const Stage<FixToF32Args>& s, hipStream_t st);
+hipError_t launch_vertex_bwd_n(const Stage<VertexBwdArgs>& s, hipStream_t st);
+hipError_t launch_face_bwd_n(const Stage<FaceBwdArgs>& s, hipStream_t st);
+hipError_t launch_fix_add_n(const Stage<FixAddArgs>& s, hipStream_t st);
+hipError_t launch_xform_n(const Stage<XformArgs>& s, hipStream_t st);
+hipError_t launch_clear_vis_n(const Stage<ClearArgs>& s, hipStream_t st);
+hipError_t launch_raster_n(const Stage<RasterArgs>& small, const Stage<RasterArgs>& med,
+                           const Stage<RasterArgs>& big, hipStream_t st);
+hipError_t launch_shade_fwd_n(const Stage<ShadeFwdArgs>& s, hipStream_t st);
+hipError_t launch_shade_bwd_n(const Stage<ShadeBwdArgs>& s, hipStream_t st);
+hipError_t launch_tex_bwd_n(const Stage<TexBwdArgs>& s, hipStream_t st);
+hipError_t launch_aa_fwd_n(const Stage<AAFwdArgs>& s, hipStream_t st);
+hipError_t launch_loss_reduce_n(const Stage<LossReduceArgs>& s, hipStream_t st);
+hipError_t launch_aa_bwd_n(const Stage<AABwdArgs>& s, hipStream_t st);
 
 }  // namespace adr

@@ -38,41 +38,40 @@ __device__ __forceinline__ FaceFrame face_frame(const MeshD& m, int t) {
 }
 
 // fn/ft non-null: deterministic mode, fixed-point accumulators.
-__global__ void k_face_accum(MeshD m, double* __restrict__ nacc, double* __restrict__ tacc,
-                             unsigned long long* __restrict__ fn, unsigned long long* __restrict__ ft) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_accum_body(const FaceAccumArgs& a, int bid, int) {
+  const MeshD& m = a.m;
+  int t = bid * 256 + threadIdx.x;
   if (t >= m.n_tri) return;
   FaceFrame f = face_frame(m, t);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     int v = m.tri[3 * t + k];
-    if (fn) {
-      fix_add3(fn, v, f.fn);
-      if (f.tan_ok) fix_add3(ft, v, f.tf);
+    if (a.fn) {
+      fix_add3(a.fn, v, f.fn);
+      if (f.tan_ok) fix_add3(a.ft, v, f.tf);
     } else {
-      datomic3(nacc, v, f.fn);
-      if (f.tan_ok) datomic3(tacc, v, f.tf);
+      datomic3(a.nacc, v, f.fn);
+      if (f.tan_ok) datomic3(a.tacc, v, f.tf);
     }
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_face_accum, FaceAccumArgs, face_accum_body)
 
-__global__ void k_vertex_normalize(int n, double* __restrict__ nacc, double* __restrict__ tacc,
-                                   const unsigned long long* __restrict__ fn,
-                                   const unsigned long long* __restrict__ ft, float* __restrict__ nrm,
-                                   float* __restrict__ tan) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  if (fn) {  // the adjoint reads the unnormalised sums as float64
+__device__ __forceinline__ void vertex_normalize_body(const VertexNormalizeArgs& a, int bid, int) {
+  int v = bid * 256 + threadIdx.x;
+  if (v >= a.n) return;
+  if (a.fn) {  // the adjoint reads the unnormalised sums as float64
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      nacc[3 * v + k] = fix_val(fn[3 * v + k]);
-      tacc[3 * v + k] = fix_val(ft[3 * v + k]);
+      a.nacc[3 * v + k] = fix_val(a.fn[3 * v + k]);
+      a.tacc[3 * v + k] = fix_val(a.ft[3 * v + k]);
     }
   }
-  d3 a = dnormalize(dld3(nacc, v)), b = dnormalize(dld3(tacc, v));
-  st3(nrm, v, mk((float)a.x, (float)a.y, (float)a.z));
-  st3(tan, v, mk((float)b.x, (float)b.y, (float)b.z));
+  d3 x = dnormalize(dld3(a.nacc, v)), y = dnormalize(dld3(a.tacc, v));
+  st3(a.nrm, v, mk((float)x.x, (float)x.y, (float)x.z));
+  st3(a.tan, v, mk((float)y.x, (float)y.y, (float)y.z));
 }
+ADR_KERNEL(__launch_bounds__(256), k_vertex_normalize, VertexNormalizeArgs, vertex_normalize_body)
 
 __global__ void k_fill_f64(double* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -87,30 +86,30 @@ __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
 }
 
 // Zero-fill of up to kFillRanges ranges of 8-byte words in one launch.
-__global__ void k_fill_multi(FillSet f) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+__device__ __forceinline__ void fill_multi_body(const FillSet& f, int bid, int nb) {
+  const int64_t stride = (int64_t)nb * 256;
   for (int r = 0; r < f.n; ++r)
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.len[r]; i += stride) f.p[r][i] = 0ull;
+    for (int64_t i = (int64_t)bid * 256 + threadIdx.x; i < f.len[r]; i += stride) f.p[r][i] = 0ull;
 }
+ADR_KERNEL(__launch_bounds__(256), k_fill_multi, FillSet, fill_multi_body)
 
 // Two accumulator arrays converted in one launch (the second may be empty).
-__global__ void k_fix_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
-                             const unsigned long long* __restrict__ src2, float* __restrict__ dst2, int64_t n2,
-                             bool det) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n + n2; i += stride) {
-    if (i < n) dst[i] = (float)acc_val(src[i], det);
-    else dst2[i - n] = (float)acc_val(src2[i - n], det);
+__device__ __forceinline__ void fix_to_f32_body(const FixToF32Args& a, int bid, int nb) {
+  int64_t i = (int64_t)bid * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)nb * 256;
+  for (; i < a.n + a.n2; i += stride) {
+    if (i < a.n) a.dst[i] = (float)acc_val(a.src[i], a.det);
+    else a.dst2[i - a.n] = (float)acc_val(a.src2[i - a.n], a.det);
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_fix_to_f32, FixToF32Args, fix_to_f32_body)
 
-__global__ void k_fix_add_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, int64_t n,
-                              bool det) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) dst[i] += (float)acc_val(src[i], det);
+__device__ __forceinline__ void fix_add_body(const FixAddArgs& a, int bid, int nb) {
+  int64_t i = (int64_t)bid * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)nb * 256;
+  for (; i < a.n; i += stride) a.dst[i] += (float)acc_val(a.src[i], a.det);
 }
+ADR_KERNEL(__launch_bounds__(256), k_fix_add_f32, FixAddArgs, fix_add_body)
 
 static unsigned grid_for(int64_t n) {
   int64_t blocks = (n + 255) / 256;
@@ -125,21 +124,27 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fill_multi(const FillSet& f, hipStream_t st) {
+Plan<FillSet> plan_fill_multi(const FillSet& f) {
   int64_t most = 0;
   for (int r = 0; r < f.n; ++r) most = f.len[r] > most ? f.len[r] : most;
-  if (most == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_multi, dim3(grid_for(most)), dim3(256), 0, st, f);
+  return {f, most == 0 ? 0u : grid_for(most)};
+}
+
+hipError_t launch_fill_multi(const FillSet& f, hipStream_t st) {
+  ADR_LAUNCH_1(k_fill_multi, plan_fill_multi(f), st);
   return hipGetLastError();
 }
 
+Plan<FixToF32Args> plan_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det,
+                                   const unsigned long long* src2, float* dst2, int64_t n2) {
+  if (n < 0) n = 0;
+  if (n2 < 0 || !src2) n2 = 0;
+  return {FixToF32Args{src, dst, n, src2, dst2, n2, det}, n + n2 <= 0 ? 0u : grid_for(n + n2)};
+}
 
 hipError_t launch_fix_to_f32(const unsigned long long* src, float* dst, int64_t n, bool det, hipStream_t st,
                              const unsigned long long* src2, float* dst2, int64_t n2) {
-  if (n < 0) n = 0;
-  if (n2 < 0 || !src2) n2 = 0;
-  if (n + n2 <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fix_to_f32, dim3(grid_for(n + n2)), dim3(256), 0, st, src, dst, n, src2, dst2, n2, det);
+  ADR_LAUNCH_1(k_fix_to_f32, plan_fix_to_f32(src, dst, n, det, src2, dst2, n2), st);
   return hipGetLastError();
 }
 
@@ -157,24 +162,27 @@ hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st) {
-  int64_t n = 3 * (int64_t)m.n_pos;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
+// The vertex frame in three launches: clear the accumulators, sum the face
+// terms, normalize.
+FramePlans plan_vertex_frame(const MeshD& m, const Scratch& s) {
+  const int64_t n = 3 * (int64_t)m.n_pos;
   unsigned long long* fn = s.det ? s.fix_n : nullptr;
   unsigned long long* ft = s.det ? s.fix_t : nullptr;
+  FramePlans p;
   FillSet f{};
   f.add(s.det ? fn : reinterpret_cast<unsigned long long*>(s.nacc), n);
   f.add(s.det ? ft : reinterpret_cast<unsigned long long*>(s.tacc), n);
-  hipError_t e = launch_fill_multi(f, st);
-  if (e != hipSuccess) return e;
-  if (m.n_tri > 0) {
-    hipLaunchKernelGGL(k_face_accum, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.nacc, s.tacc, fn, ft);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(k_vertex_normalize, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m.n_pos,
-                     s.nacc, s.tacc, fn, ft, s.nrm, s.tan);
+  p.fill = plan_fill_multi(f);
+  p.faces = {FaceAccumArgs{m, s.nacc, s.tacc, fn, ft}, (unsigned)((m.n_tri + 255) / 256)};
+  p.verts = {VertexNormalizeArgs{m.n_pos, s.nacc, s.tacc, fn, ft, s.nrm, s.tan}, (unsigned)((m.n_pos + 255) / 256)};
+  return p;
+}
+
+hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st) {
+  const FramePlans p = plan_vertex_frame(m, s);
+  ADR_LAUNCH_1(k_fill_multi, p.fill, st);
+  ADR_LAUNCH_1(k_face_accum, p.faces, st);
+  ADR_LAUNCH_1(k_vertex_normalize, p.verts, st);
   return hipGetLastError();
 }
 
@@ -183,35 +191,37 @@ hipError_t launch_vertex_frame(const MeshD& m, const Scratch& s, hipStream_t st)
 // Per vertex: the clip-space gradient of every view through its MVP, the
 // gradient of the interpolated world position, and the normalize adjoints
 // of the vertex normal and tangent (stored back into dattr for the face pass).
-__global__ void k_vertex_bwd(MeshD m, ViewsD v, const float* __restrict__ dclip,
-                             float* __restrict__ dattr, const double* __restrict__ nacc,
-                             const double* __restrict__ tacc, float* __restrict__ gpos,
-                             float* __restrict__ gvn) {
-  int vi = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void vertex_bwd_body(const VertexBwdArgs& a, int bid, int) {
+  const MeshD& m = a.m;
+  const ViewsD& v = a.v;
+  float* __restrict__ dattr = a.dattr;
+  int vi = bid * 256 + threadIdx.x;
   if (vi >= m.n_pos) return;
   f3 g = ld3(dattr, 3 * vi);  // d(world position)
   for (int b = 0; b < v.B; ++b) {
     const float* M = v.mvp + 16 * b;
-    const float* dc = dclip + 4 * ((int64_t)b * m.n_pos + vi);
+    const float* dc = a.dclip + 4 * ((int64_t)b * m.n_pos + vi);
     float c0 = dc[0], c1 = dc[1], c2 = dc[2], c3 = dc[3];
     g.x += M[0] * c0 + M[4] * c1 + M[8] * c2 + M[12] * c3;
     g.y += M[1] * c0 + M[5] * c1 + M[9] * c2 + M[13] * c3;
     g.z += M[2] * c0 + M[6] * c1 + M[10] * c2 + M[14] * c3;
   }
-  if (gpos) atomic_add3(gpos, vi, g);
+  if (a.gpos) atomic_add3(a.gpos, vi, g);
   f3 gn = ld3(dattr, 3 * vi + 1);
   f3 gt = ld3(dattr, 3 * vi + 2);
-  if (gvn) st3(gvn, vi, gn);
-  d3 an = dnormalize_bwd(dld3(nacc, vi), dmk(gn.x, gn.y, gn.z));
-  d3 at = dnormalize_bwd(dld3(tacc, vi), dmk(gt.x, gt.y, gt.z));
+  if (a.gvn) st3(a.gvn, vi, gn);
+  d3 an = dnormalize_bwd(dld3(a.nacc, vi), dmk(gn.x, gn.y, gn.z));
+  d3 at = dnormalize_bwd(dld3(a.tacc, vi), dmk(gt.x, gt.y, gt.z));
   st3(dattr, 3 * vi + 1, mk((float)an.x, (float)an.y, (float)an.z));
   st3(dattr, 3 * vi + 2, mk((float)at.x, (float)at.y, (float)at.z));
 }
+ADR_KERNEL(__launch_bounds__(256), k_vertex_bwd, VertexBwdArgs, vertex_bwd_body)
 
 // Per face: adjoint of the face normal (cross product) and face tangent.
-__global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, unsigned long long* __restrict__ fpos,
-                           bool det) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void face_bwd_body(const FaceBwdArgs& a, int bid, int) {
+  const MeshD& m = a.m;
+  const float* __restrict__ dattr = a.dattr;
+  int t = bid * 256 + threadIdx.x;
   if (t >= m.n_tri) return;
   int i0 = m.tri[3 * t], i1 = m.tri[3 * t + 1], i2 = m.tri[3 * t + 2];
   FaceFrame f = face_frame(m, t);
@@ -225,24 +235,66 @@ __global__ void k_face_bwd(MeshD m, const float* __restrict__ dattr, unsigned lo
     g2 = g2 - (f.d1v * inv) * gtf;
   }
   const d3 g0 = dmk(-(g1.x + g2.x), -(g1.y + g2.y), -(g1.z + g2.z));
-  acc_add3(fpos, i1, g1, det);
-  acc_add3(fpos, i2, g2, det);
-  acc_add3(fpos, i0, g0, det);
+  acc_add3(a.fpos, i1, g1, a.det);
+  acc_add3(a.fpos, i2, g2, a.det);
+  acc_add3(a.fpos, i0, g0, a.det);
+}
+ADR_KERNEL(__launch_bounds__(256), k_face_bwd, FaceBwdArgs, face_bwd_body)
+
+// The mesh adjoint in three launches: per vertex, per face (face terms summed
+// in float64, fixed point in deterministic mode, into s.fix_pos, which the
+// caller has cleared), then the face sums added once per vertex.
+MeshBwdPlans plan_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos, float* gvnormal) {
+  MeshBwdPlans p;
+  const bool any = m.n_pos > 0 && (gpos || gvnormal);
+  p.verts = {VertexBwdArgs{m, v, s.dclip, s.dattr, s.nacc, s.tacc, gpos, gvnormal},
+             any ? (unsigned)((m.n_pos + 255) / 256) : 0u};
+  const bool faces = gpos && m.n_pos > 0 && m.n_tri > 0;
+  const int64_t n = 3 * (int64_t)m.n_pos;
+  p.faces = {FaceBwdArgs{m, s.dattr, s.fix_pos, s.det}, faces ? (unsigned)((m.n_tri + 255) / 256) : 0u};
+  p.add = {FixAddArgs{s.fix_pos, gpos, n, s.det}, faces ? grid_for(n) : 0u};
+  return p;
 }
 
 hipError_t launch_mesh_bwd(const MeshD& m, const ViewsD& v, const Scratch& s, float* gpos,
                            float* gvnormal, hipStream_t st, bool pos_cleared) {
-  hipLaunchKernelGGL(k_vertex_bwd, dim3((m.n_pos + 255) / 256), dim3(256), 0, st, m, v, s.dclip,
-                     s.dattr, s.nacc, s.tacc, gpos, gvnormal);
+  const MeshBwdPlans p = plan_mesh_bwd(m, v, s, gpos, gvnormal);
+  ADR_LAUNCH_1(k_vertex_bwd, p.verts, st);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !gpos || m.n_tri == 0) return e;
-  // face terms summed in float64 (fixed point in deterministic mode), then
-  // added once per vertex
-  const int64_t n = 3 * (int64_t)m.n_pos;
-  if (!pos_cleared && (e = launch_fill_u64(s.fix_pos, n, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_face_bwd, dim3((m.n_tri + 255) / 256), dim3(256), 0, st, m, s.dattr, s.fix_pos, s.det);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fix_add_f32, dim3(grid_for(n)), dim3(256), 0, st, s.fix_pos, gpos, n, s.det);
+  if (e != hipSuccess || p.faces.blocks == 0) return e;
+  if (!pos_cleared && (e = launch_fill_u64(s.fix_pos, p.add.a.n, st)) != hipSuccess) return e;
+  ADR_LAUNCH_1(k_face_bwd, p.faces, st);
+  ADR_LAUNCH_1(k_fix_add_f32, p.add, st);
+  return hipGetLastError();
+}
+
+// ---- batched launches ----
+hipError_t launch_fill_multi_n(const Stage<FillSet>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_fill_multi, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_face_accum_n(const Stage<FaceAccumArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_face_accum, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_vertex_normalize_n(const Stage<VertexNormalizeArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_vertex_normalize, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_fix_to_f32_n(const Stage<FixToF32Args>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_fix_to_f32, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_vertex_bwd_n(const Stage<VertexBwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_vertex_bwd, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_face_bwd_n(const Stage<FaceBwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_face_bwd, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_fix_add_n(const Stage<FixAddArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_fix_add_f32, s, st);
   return hipGetLastError();
 }
 

@@ -38,9 +38,11 @@ __device__ __forceinline__ float fsub(float a, float b) { return __fsub_rn(a, b)
 
 // Snapped integer coordinates (from the float32 clip coordinates of the
 // rules above) and float64 clip coordinates for interpolation.
-__global__ void k_xform(MeshD m, ViewsD v, int4* __restrict__ snap, double* __restrict__ mvpd) {
-  int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < 16 * v.B) mvpd[gid] = (double)v.mvp[gid];
+__device__ __forceinline__ void xform_body(const XformArgs& a, int bid, int) {
+  const MeshD& m = a.m;
+  const ViewsD& v = a.v;
+  int gid = bid * 256 + threadIdx.x;
+  if (gid < 16 * v.B) a.mvpd[gid] = (double)v.mvp[gid];
   if (gid >= v.B * m.n_pos) return;
   int b = gid / m.n_pos, vi = gid - b * m.n_pos;
   const float* M = v.mvp + 16 * b;
@@ -67,8 +69,9 @@ __global__ void k_xform(MeshD m, ViewsD v, int4* __restrict__ snap, double* __re
       s.w = 1;
     }
   }
-  snap[gid] = s;
+  a.snap[gid] = s;
 }
+ADR_KERNEL(__launch_bounds__(256), k_xform, XformArgs, xform_body)
 
 // Oriented integer setup of one triangle in one view.
 struct Setup {
@@ -144,16 +147,16 @@ __device__ __forceinline__ BBox pixel_bbox(const Setup& s, int W, int H) {
   return b;
 }
 
-__global__ void k_clear(uint64_t* __restrict__ vis, uint32_t* __restrict__ cov, int64_t n,
-                        uint32_t* __restrict__ big_cnt, int B) {
-  int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = gid; i < n; i += stride) {
-    vis[i] = kKeyEmpty;
-    if (cov) cov[i] = 0u;
+__device__ __forceinline__ void clear_body(const ClearArgs& a, int bid, int nb) {
+  int64_t gid = (int64_t)bid * 256 + threadIdx.x;
+  int64_t stride = (int64_t)nb * 256;
+  for (int64_t i = gid; i < a.n; i += stride) {
+    a.vis[i] = kKeyEmpty;
+    if (a.cov) a.cov[i] = 0u;
   }
-  if (gid <= B) big_cnt[gid] = 0u;   // B per-view big counts and the medium-queue count
+  if (gid <= a.B) a.big_cnt[gid] = 0u;   // B per-view big counts and the medium-queue count
 }
+ADR_KERNEL(__launch_bounds__(256), k_clear, ClearArgs, clear_body)
 
 __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j, int W,
                                              unsigned long long* __restrict__ vv, uint32_t* __restrict__ cv,
@@ -171,14 +174,16 @@ __device__ __forceinline__ void raster_pixel(const Setup& s, int t, int i, int j
 // holds at most `tiny` pixel centres is walked by its thread; up to `med`
 // it is queued for k_raster_med (big_cnt[B] counts the queue);
 // larger ones go to the view's list for the tile kernel.
-__global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const int4* __restrict__ snap,
-                                                      int8_t* __restrict__ orient, uint32_t* __restrict__ big,
-                                                      uint32_t* __restrict__ big_cnt, uint32_t* __restrict__ med,
-                                                      unsigned long long* __restrict__ vis,
-                                                      uint32_t* __restrict__ cov,
-                                                      const unsigned long long* __restrict__ floor, int tiny,
-                                                      int med_max) {
-  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void raster_small_body(const RasterArgs& a, int bid, int) {
+  const MeshD& m = a.m;
+  const ViewsD& v = a.v;
+  const int4* __restrict__ snap = a.snap;
+  uint32_t* __restrict__ big_cnt = a.big_cnt;
+  unsigned long long* __restrict__ vis = a.vis;
+  uint32_t* __restrict__ cov = a.cov;
+  const unsigned long long* __restrict__ floor = a.floor;
+  const int tiny = a.tiny, med_max = a.med_max;
+  const int gid = bid * 256 + threadIdx.x;
   int area = 0, b = 0, t = 0;
   Setup s;
   BBox bb{0, -1, 0, -1};
@@ -187,17 +192,17 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
     t = gid - b * m.n_tri;
     int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
     if (setup_tri(snap + (int64_t)b * m.n_pos, c, s)) {
-      orient[gid] = s.flip ? -1 : 1;
+      a.orient[gid] = s.flip ? -1 : 1;
       bb = pixel_bbox(s, v.W, v.H);
       if (bb.i1 >= bb.i0 && bb.j1 >= bb.j0) area = (bb.i1 - bb.i0 + 1) * (bb.j1 - bb.j0 + 1);
     } else {
-      orient[gid] = 0;
+      a.orient[gid] = 0;
     }
   }
   const int64_t HW = (int64_t)v.W * v.H;
   if (area > med_max) {
     uint32_t slot = atomicAdd(big_cnt + b, 1u);
-    big[(int64_t)b * m.n_tri + slot] = (uint32_t)t;
+    a.big[(int64_t)b * m.n_tri + slot] = (uint32_t)t;
   } else if (area > 0 && area <= tiny) {
     unsigned long long* vv = vis + b * HW;
     uint32_t* cv = cov ? cov + b * HW : nullptr;
@@ -214,26 +219,28 @@ __global__ __launch_bounds__(256) void k_raster_small(MeshD m, ViewsD v, const i
     uint32_t base = 0;
     if (lane == leader) base = atomicAdd(big_cnt + v.B, (uint32_t)__popcll(mm));
     base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-    if (is_med) med[base + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint32_t)gid;
+    if (is_med) a.med[base + (uint32_t)__popcll(mm & ((1ull << lane) - 1ull))] = (uint32_t)gid;
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_raster_small, RasterArgs, raster_small_body)
 
 // Queued medium triangles, one per wave at a time (a grid-stride loop over
 // the queue).  The wave walks the triangle's bounding box in blocks of
 // bw x (64 / bw) pixels, bw in 8..64 chosen per triangle to waste the fewest
 // lanes.
-__global__ __launch_bounds__(256) void k_raster_med(MeshD m, ViewsD v, const int4* __restrict__ snap,
-                                                    const uint32_t* __restrict__ med,
-                                                    const uint32_t* __restrict__ big_cnt,
-                                                    unsigned long long* __restrict__ vis,
-                                                    uint32_t* __restrict__ cov,
-                                                    const unsigned long long* __restrict__ floor) {
+__device__ __forceinline__ void raster_med_body(const RasterArgs& a, int bid, int nb) {
+  const MeshD& m = a.m;
+  const ViewsD& v = a.v;
+  const int4* __restrict__ snap = a.snap;
+  unsigned long long* __restrict__ vis = a.vis;
+  uint32_t* __restrict__ cov = a.cov;
+  const unsigned long long* __restrict__ floor = a.floor;
   const int lane = threadIdx.x & 63;
-  const uint32_t n_waves = gridDim.x * (blockDim.x >> 6);
-  const uint32_t cnt = big_cnt[v.B];
+  const uint32_t n_waves = (uint32_t)nb * 4u;
+  const uint32_t cnt = a.big_cnt[v.B];
   const int64_t HW = (int64_t)v.W * v.H;
-  for (uint32_t q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < cnt; q += n_waves) {
-    const int g = (int)med[q];
+  for (uint32_t q = (uint32_t)bid * 4u + (threadIdx.x >> 6); q < cnt; q += n_waves) {
+    const int g = (int)a.med[q];
     const int b = g / m.n_tri, t = g - b * m.n_tri;
     const int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
     Setup s;
@@ -264,30 +271,32 @@ __global__ __launch_bounds__(256) void k_raster_med(MeshD m, ViewsD v, const int
     }
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_raster_med, RasterArgs, raster_med_body)
 
 // One 16x16 tile of one view per block: stage the view's big triangles that
 // overlap the tile into LDS, then resolve one pixel per thread.
-__global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int4* __restrict__ snap,
-                                                    const uint32_t* __restrict__ big,
-                                                    const uint32_t* __restrict__ big_cnt,
-                                                    unsigned long long* __restrict__ vis,
-                                                    uint32_t* __restrict__ cov, int tiles_x,
-                                                    int tiles_y, const unsigned long long* __restrict__ floor) {
+__device__ __forceinline__ void raster_big_body(const RasterArgs& a, int bid, int nb) {
   __shared__ Setup lds[256];
   __shared__ int lds_t[256];
   __shared__ int lds_n;
-  int nb = gridDim.x;
-  int tile = xcd_tile(blockIdx.x, nb);
+  const MeshD& m = a.m;
+  const ViewsD& v = a.v;
+  const uint32_t* __restrict__ big = a.big;
+  unsigned long long* __restrict__ vis = a.vis;
+  uint32_t* __restrict__ cov = a.cov;
+  const unsigned long long* __restrict__ floor = a.floor;
+  const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
+  int tile = xcd_tile(bid, nb);
   int per_view = tiles_x * tiles_y;
   int b = tile / per_view;
   int r = tile - b * per_view;
   int ty = r / tiles_x, tx = r - ty * tiles_x;
-  uint32_t n_big = big_cnt[b];
+  uint32_t n_big = a.big_cnt[b];
   if (n_big == 0) return;
   int i = tx * kBigTile + (threadIdx.x & 15), j = ty * kBigTile + (threadIdx.x >> 4);
   int ti0 = tx * kBigTile, ti1 = min(ti0 + kBigTile, v.W) - 1;
   int tj0 = ty * kBigTile, tj1 = min(tj0 + kBigTile, v.H) - 1;
-  const int4* sv = snap + (int64_t)b * m.n_pos;
+  const int4* sv = a.snap + (int64_t)b * m.n_pos;
   unsigned long long best = kKeyEmpty;
   uint32_t hits = 0;
   int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
@@ -330,43 +339,82 @@ __global__ __launch_bounds__(256) void k_raster_big(MeshD m, ViewsD v, const int
     if (cov && hits) atomicAdd(cov + o, hits);
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_raster_big, RasterArgs, raster_big_body)
 
-hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st) {
+Plan<XformArgs> plan_xform(const MeshD& m, const ViewsD& v, const Scratch& s) {
   // one thread per (view, vertex), at least 16 per view for the matrices
   const int n = m.n_pos > 0 ? (m.n_pos < 16 ? 16 : m.n_pos) * v.B : 0;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_xform, dim3((n + 255) / 256), dim3(256), 0, st, m, v,
-                     reinterpret_cast<int4*>(s.snap), s.mvpd);
+  return {XformArgs{m, v, reinterpret_cast<int4*>(s.snap), s.mvpd}, (unsigned)((n + 255) / 256)};
+}
+
+hipError_t launch_xform(const MeshD& m, const ViewsD& v, const Scratch& s, hipStream_t st) {
+  ADR_LAUNCH_1(k_xform, plan_xform(m, v, s), st);
   return hipGetLastError();
+}
+
+Plan<ClearArgs> plan_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < (B + 256) / 256) blocks = (B + 256) / 256;   // threads for the B + 1 counters
+  return {ClearArgs{vis, cov, n, big_cnt, B}, (unsigned)blocks};
 }
 
 hipError_t launch_clear_vis(uint64_t* vis, uint32_t* cov, int64_t n, uint32_t* big_cnt, int B,
                             hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks < (B + 256) / 256) blocks = (B + 256) / 256;   // threads for the B + 1 counters
-  hipLaunchKernelGGL(k_clear, dim3((unsigned)blocks), dim3(256), 0, st, vis, cov, n, big_cnt, B);
+  ADR_LAUNCH_1(k_clear, plan_clear_vis(vis, cov, n, big_cnt, B), st);
   return hipGetLastError();
+}
+
+RasterPlans plan_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis, uint32_t* cov,
+                        const uint64_t* floor) {
+  RasterArgs a{};
+  a.m = m;
+  a.v = v;
+  a.snap = reinterpret_cast<const int4*>(s.snap);
+  a.orient = s.orient;
+  a.big = s.big;
+  a.big_cnt = s.big_cnt;
+  a.med = s.med;
+  a.vis = reinterpret_cast<unsigned long long*>(vis);
+  a.cov = cov;
+  a.floor = reinterpret_cast<const unsigned long long*>(floor);
+  a.tiny = s.tiny_bbox;
+  a.med_max = s.med_bbox;
+  a.tiles_x = (v.W + kBigTile - 1) / kBigTile;
+  a.tiles_y = (v.H + kBigTile - 1) / kBigTile;
+  const int n = v.B * m.n_tri;
+  RasterPlans p;
+  p.a = a;
+  p.small = n > 0 ? (unsigned)((n + 255) / 256) : 0u;
+  // enough waves to fill the chip; each loops over the queue
+  p.med = n > 0 ? (unsigned)std::min((n + 3) / 4, 4096) : 0u;
+  p.big = n > 0 ? (unsigned)(a.tiles_x * a.tiles_y * v.B) : 0u;
+  return p;
 }
 
 hipError_t launch_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint64_t* vis,
                          uint32_t* cov, hipStream_t st, const uint64_t* floor) {
-  auto* fl = reinterpret_cast<const unsigned long long*>(floor);
-  int n = v.B * m.n_tri;
-  if (n == 0) return hipSuccess;
-  const int4* sv = reinterpret_cast<const int4*>(s.snap);
-  auto* vk = reinterpret_cast<unsigned long long*>(vis);
-  hipLaunchKernelGGL(k_raster_small, dim3((n + 255) / 256), dim3(256), 0, st, m, v, sv, s.orient,
-                     s.big, s.big_cnt, s.med, vk, cov, fl, s.tiny_bbox, s.med_bbox);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // enough waves to fill the chip; each loops over the queue
-  const int med_blocks = std::min((n + 3) / 4, 4096);
-  hipLaunchKernelGGL(k_raster_med, dim3(med_blocks), dim3(256), 0, st, m, v, sv, s.med, s.big_cnt, vk, cov, fl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  int tx = (v.W + kBigTile - 1) / kBigTile, ty = (v.H + kBigTile - 1) / kBigTile;
-  hipLaunchKernelGGL(k_raster_big, dim3(tx * ty * v.B), dim3(256), 0, st, m, v, sv, s.big,
-                     s.big_cnt, vk, cov, tx, ty, fl);
+  const RasterPlans p = plan_raster(m, v, s, vis, cov, floor);
+  ADR_LAUNCH_1(k_raster_small, (Plan<RasterArgs>{p.a, p.small}), st);
+  ADR_LAUNCH_1(k_raster_med, (Plan<RasterArgs>{p.a, p.med}), st);
+  ADR_LAUNCH_1(k_raster_big, (Plan<RasterArgs>{p.a, p.big}), st);
+  return hipGetLastError();
+}
+
+// ---- batched launches ----
+hipError_t launch_xform_n(const Stage<XformArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_xform, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_clear_vis_n(const Stage<ClearArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_clear, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_raster_n(const Stage<RasterArgs>& small, const Stage<RasterArgs>& med,
+                           const Stage<RasterArgs>& big, hipStream_t st) {
+  ADR_LAUNCH_N(k_raster_small, small, st);
+  ADR_LAUNCH_N(k_raster_med, med, st);
+  ADR_LAUNCH_N(k_raster_big, big, st);
   return hipGetLastError();
 }
 

@@ -278,19 +278,6 @@ __device__ __forceinline__ void ggx_bwd(f3 n, f3 v, f3 l, f3 kd, f3 orm, f3 E, f
 
 // -------------------------------------------------------------- forward
 
-struct ShadeArgs {
-  MeshD m;
-  ViewsD v;
-  int model;
-  Tex kd, nm, orm;
-  Tex al;                 // alpha map (data NULL: none)
-  const float* galpha;    // dL/d alpha per pixel (adjoint of a depth-peeled layer), or NULL
-  const float* nrm;
-  const float* tan;
-  const uint64_t* vis;
-  int tiles_x, tiles_y;
-};
-
 // Alpha of a depth-peeled layer: clamp(alpha map, 0, 1), 1 without a map.
 __device__ __forceinline__ float layer_alpha(const ShadeArgs& a, const PixelGeom& g) {
   if (!a.al.data) return 1.f;
@@ -298,9 +285,12 @@ __device__ __forceinline__ float layer_alpha(const ShadeArgs& a, const PixelGeom
   return fminf(fmaxf(tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La).val.x, 0.f), 1.f);
 }
 
-__global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restrict__ color,
-                                                   int32_t* __restrict__ tri_id, float* __restrict__ alpha) {
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void shade_fwd_body(const ShadeFwdArgs& f, int bid, int nb) {
+  const ShadeArgs& a = f.s;
+  float* __restrict__ color = f.color;
+  int32_t* __restrict__ tri_id = f.tri_id;
+  float* __restrict__ alpha = f.alpha;
+  int tile = xcd_tile(bid, nb);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   if (!p.ok) return;
   int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
@@ -334,6 +324,7 @@ __global__ __launch_bounds__(256) void k_shade_fwd(ShadeArgs a, float* __restric
   }
   st3(color, o, c);
 }
+ADR_KERNEL(__launch_bounds__(256), k_shade_fwd, ShadeFwdArgs, shade_fwd_body)
 
 // -------------------------------------------------------------- backward
 
@@ -909,17 +900,14 @@ __device__ __forceinline__ void wave_vertex_scatter(const ShadeArgs& a, int b, b
 // packed low parts of u and v) with byte k of the packed levels the lower
 // mip level l0 of gradient slot k (255: no contribution), and rec[1 + k] =
 // (dL/dsample, weight of level l0 + 1) of slot k.
-struct TexSlots {
-  int kd, nm, orm, al;  // slot of each map, -1 without a gradient buffer
-  int n;
-};
-
 template <bool ALPHA>
-__global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, const float* __restrict__ gcolor,
-                                                   float4* __restrict__ rec, unsigned long long* __restrict__ fclip,
-                                                   unsigned long long* __restrict__ fattr, bool det) {
+__device__ __forceinline__ void shade_bwd_body(const ShadeBwdArgs& b, int bid, int nb) {
   __shared__ float table_all[4][kVtxTable];
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const ShadeArgs& a = b.s;
+  const TexSlots& sl = b.sl;
+  const float* __restrict__ gcolor = b.gcolor;
+  float4* __restrict__ rec = b.rec;
+  int tile = xcd_tile(bid, nb);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   float* table = table_all[threadIdx.x >> 6];
   // the padding column stays zero (the pixel columns are 0..63)
@@ -935,24 +923,25 @@ __global__ __launch_bounds__(256) void k_shade_bwd(ShadeArgs a, TexSlots sl, con
   bool act = p.ok && shade_bwd_pixel<ALPHA>(a, p, gcolor, table + (threadIdx.x & 63), tri, vtx, ro, lv, u, v, lo);
   if (p.ok && sl.n > 0)
     st_nt(rec + o, make_float4(act ? u : 0.f, act ? v : 0.f, __uint_as_float(act ? lv : 0xFFFFFFFFu), act ? lo : 0.f));
-  wave_vertex_scatter(a, p.b, act, tri, vtx, table, fclip, fattr, det);
+  wave_vertex_scatter(a, p.b, act, tri, vtx, table, b.fclip, b.fattr, b.det);
 }
+
+template <bool ALPHA>
+__global__ __launch_bounds__(256) void k_shade_bwd(ShadeBwdArgs b) {
+  shade_bwd_body<ALPHA>(b, (int)blockIdx.x, (int)gridDim.x);
+}
+// the batched form (no alpha variant)
+__device__ __forceinline__ void shade_bwd_body_opaque(const ShadeBwdArgs& b, int bid, int nb) {
+  shade_bwd_body<false>(b, bid, nb);
+}
+ADR_KERNEL(__launch_bounds__(256), k_shade_bwd_opaque, ShadeBwdArgs, shade_bwd_body_opaque)
 
 // Texel-gradient scatter of the recorded samples: a kernel of its own with
 // few registers, so that enough waves are resident to hide the latency of
 // the LDS atomics of the window accumulation.
-struct TexBwdArgs {
-  Tex t[4];
-  float* g[4];
-  int n;
-  const float4* rec;
-  ViewsD v;
-  int tiles_x, tiles_y;
-};
-
-__global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
+__device__ __forceinline__ void tex_bwd_body(const TexBwdArgs& a, int bid, int nb) {
   __shared__ WinT win_all[4][kWinTex];
-  int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int tile = xcd_tile(bid, nb);
   Pix p = tile_pixel(tile, threadIdx.x, a.tiles_x, a.tiles_y, a.v.W, a.v.H);
   const int64_t P = (int64_t)a.v.B * a.v.H * a.v.W;
   const int64_t o = ((int64_t)p.b * a.v.H + p.j) * a.v.W + p.i;
@@ -970,6 +959,7 @@ __global__ __launch_bounds__(256) void k_tex_bwd(TexBwdArgs a) {
     wave_scatter_tex(a.t[k], a.g[k], act, ts, win);
   }
 }
+ADR_KERNEL(__launch_bounds__(256), k_tex_bwd, TexBwdArgs, tex_bwd_body)
 
 static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
                            const Tex& orm, const Scratch& s, const uint64_t* vis) {
@@ -988,13 +978,22 @@ static ShadeArgs make_args(const MeshD& m, const ViewsD& v, int model, const Tex
   return a;
 }
 
+Plan<ShadeFwdArgs> plan_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
+                                   const Tex& orm, const Scratch& s, const uint64_t* vis, float* color,
+                                   int32_t* tri_id, const Tex* al, float* alpha) {
+  ShadeFwdArgs f{};
+  f.s = make_args(m, v, model, kd, nm, orm, s, vis);
+  if (al) f.s.al = *al;
+  f.color = color;
+  f.tri_id = tri_id;
+  f.alpha = alpha;
+  return {f, (unsigned)(f.s.tiles_x * f.s.tiles_y * v.B)};
+}
+
 hipError_t launch_shade_fwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, const Scratch& s, const uint64_t* vis,
                             float* color, int32_t* tri_id, hipStream_t st, const Tex* al, float* alpha) {
-  ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
-  if (al) a.al = *al;
-  int nb = a.tiles_x * a.tiles_y * v.B;
-  hipLaunchKernelGGL(k_shade_fwd, dim3(nb), dim3(256), 0, st, a, color, tri_id, alpha);
+  ADR_LAUNCH_1(k_shade_fwd, plan_shade_fwd(m, v, model, kd, nm, orm, s, vis, color, tri_id, al, alpha), st);
   return hipGetLastError();
 }
 
@@ -1020,24 +1019,32 @@ static int make_slots(int model, const Tex& kd, const Tex& nm, const Tex& orm, f
   return sl.n;
 }
 
+Plan<ShadeBwdArgs> plan_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd, const Tex& nm,
+                                   const Tex& orm, float* gkd, float* gnm, float* gorm, const Scratch& s,
+                                   const uint64_t* vis, const Tex* al, float* gal, const float* galpha) {
+  ShadeBwdArgs b{};
+  b.s = make_args(m, v, model, kd, nm, orm, s, vis);
+  TexBwdArgs tb;
+  make_slots(model, kd, nm, orm, gkd, gnm, gorm, b.sl, tb, al, gal);
+  if (galpha) {
+    if (al) b.s.al = *al;
+    b.s.galpha = galpha;
+  }
+  b.gcolor = s.gcolor;
+  b.rec = s.texrec;
+  b.fclip = s.fix_clip;
+  b.fattr = s.fix_attr;
+  b.det = s.det;
+  return {b, (unsigned)(b.s.tiles_x * b.s.tiles_y * v.B)};
+}
+
 hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Tex& kd,
                             const Tex& nm, const Tex& orm, float* gkd, float* gnm, float* gorm,
                             const Scratch& s, const uint64_t* vis, hipStream_t st, const Tex* al, float* gal,
                             const float* galpha) {
-  ShadeArgs a = make_args(m, v, model, kd, nm, orm, s, vis);
-  int nb = a.tiles_x * a.tiles_y * v.B;
-  TexSlots sl;
-  TexBwdArgs tb;
-  make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb, al, gal);
-  if (galpha) {
-    if (al) a.al = *al;
-    a.galpha = galpha;
-    hipLaunchKernelGGL(k_shade_bwd<true>, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip,
-                       s.fix_attr, s.det);
-  } else {
-    hipLaunchKernelGGL(k_shade_bwd<false>, dim3(nb), dim3(256), 0, st, a, sl, s.gcolor, s.texrec, s.fix_clip,
-                       s.fix_attr, s.det);
-  }
+  const Plan<ShadeBwdArgs> p = plan_shade_bwd(m, v, model, kd, nm, orm, gkd, gnm, gorm, s, vis, al, gal, galpha);
+  if (galpha) ADR_LAUNCH_1(k_shade_bwd<true>, p, st);
+  else ADR_LAUNCH_1(k_shade_bwd<false>, p, st);
   return hipGetLastError();
 }
 
@@ -1210,19 +1217,38 @@ hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const T
   return hipGetLastError();
 }
 
-hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
-                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st, const Tex* al,
-                          float* gal) {
-  if (s.det) return launch_tex_bwd_det(v, model, kd, nm, orm, gkd, gnm, gorm, s, st);
+// The atomic texel scatter (0 blocks without a gradient buffer).
+Plan<TexBwdArgs> plan_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm, float* gkd,
+                              float* gnm, float* gorm, const Scratch& s, const Tex* al, float* gal) {
   TexSlots sl;
   TexBwdArgs tb;
-  if (make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb, al, gal) == 0) return hipSuccess;
+  const int n = make_slots(model, kd, nm, orm, gkd, gnm, gorm, sl, tb, al, gal);
   tb.rec = s.texrec;
   tb.v = v;
   tb.tiles_x = (v.W + 15) / 16;
   tb.tiles_y = (v.H + 15) / 16;
-  int nb = tb.tiles_x * tb.tiles_y * v.B;
-  hipLaunchKernelGGL(k_tex_bwd, dim3(nb), dim3(256), 0, st, tb);
+  return {tb, n == 0 ? 0u : (unsigned)(tb.tiles_x * tb.tiles_y * v.B)};
+}
+
+hipError_t launch_tex_bwd(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
+                          float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st, const Tex* al,
+                          float* gal) {
+  if (s.det) return launch_tex_bwd_det(v, model, kd, nm, orm, gkd, gnm, gorm, s, st);
+  ADR_LAUNCH_1(k_tex_bwd, plan_tex_bwd(v, model, kd, nm, orm, gkd, gnm, gorm, s, al, gal), st);
+  return hipGetLastError();
+}
+
+// ---- batched launches ----
+hipError_t launch_shade_fwd_n(const Stage<ShadeFwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_shade_fwd, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_shade_bwd_n(const Stage<ShadeBwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_shade_bwd_opaque, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_tex_bwd_n(const Stage<TexBwdArgs>& s, hipStream_t st) {
+  ADR_LAUNCH_N(k_tex_bwd, s, st);
   return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
-"""Batched stepping of uneven meshes: the graph-captured batch (all meshes'
-forward and backward over four streams, replayed step after step with the
-cameras of each step copied in, then Adam over every mesh's positions and
-maps, the maps' mip chains adjoined and rebuilt in the same kernel) gives
+"""Batched stepping of uneven meshes: the graph-captured batch, in either
+form (one launch per stage over all meshes through the library batch, or
+every mesh's own launches over four streams), replayed step after step with
+the cameras of each step copied in, then Adam over every mesh's positions and
+maps (the maps' mip chains adjoined and rebuilt in the same kernel), gives
 the same losses and parameters as stepping the meshes one at a time: bit for
 bit in deterministic mode, at every replay, and within float tolerance with
 atomics.  The autotuner picks and caches a work split per shape bucket."""
@@ -34,14 +35,15 @@ def _state(b):
     return out
 
 
+@pytest.mark.parametrize("form", ["launch", "streams"])
 @pytest.mark.parametrize("det", [True, False])
-def test_graph_batch_equals_plain(det):
+def test_graph_batch_equals_plain(det, form):
     from paper_2104_03989_amd.batch import Batch
-    _say("batched vs plain, deterministic" if det else "batched vs plain, atomic")
+    _say(f"batched ({form}) vs plain, " + ("deterministic" if det else "atomic"))
     ws = _workloads()
     steps = 4
-    plain = Batch(ws, steps, det=det, tune=False)
-    batched = Batch(ws, steps, det=det, tune=False)
+    plain = Batch(ws, steps, det=det, tune=False, form="streams")
+    batched = Batch(ws, steps, det=det, tune=False, form=form)
     batched.step_eager(0)                 # warm-up sizes the scratch
     plain.step_plain(0)
     torch.cuda.synchronize()
