@@ -269,17 +269,17 @@ adr_status prepare_scratch(adr_ctx* ctx, const MeshD& m, const ViewsD& v, bool b
       if (tex_slots > 0) {
         const int64_t E = det_entries(v, tex_slots);
         if (E >= (int64_t)0xFFFFFFFF) return fail(ADR_E_INVALID, "deterministic mode: view batch too large (%lld texel terms)", (long long)E);
-        const int64_t hw = radix_hist_words(E), tiles = (E + 2047) / 2048;
+        const int64_t hw = radix_hist_words(E);
         if ((r = ensure(ctx->det_k0, E * 4)) || (r = ensure(ctx->det_v0, E * 4)) || (r = ensure(ctx->det_k1, E * 4)) ||
-            (r = ensure(ctx->det_v1, E * 4)) || (r = ensure(ctx->det_vals, E * 16)) ||
+            (r = ensure(ctx->det_v1, E * 4)) || (r = ensure(ctx->det_vals, det_vals_bytes(E))) ||
             (r = ensure(ctx->det_hist, hw * 4)) || (r = ensure(ctx->det_tmp, scan_tmp_words(hw) * 4 + 4)) ||
-            (r = ensure(ctx->det_part, tiles * 32)))
+            (r = ensure(ctx->det_part, det_part_bytes(E))))
           return r;
         s.det_k0 = (uint32_t*)ctx->det_k0.p;
         s.det_v0 = (uint32_t*)ctx->det_v0.p;
         s.det_k1 = (uint32_t*)ctx->det_k1.p;
         s.det_v1 = (uint32_t*)ctx->det_v1.p;
-        s.det_vals = (float4*)ctx->det_vals.p;
+        det_carve(ctx->det_vals.p, E, s);
         s.det_hist = (uint32_t*)ctx->det_hist.p;
         s.det_tmp = (uint32_t*)ctx->det_tmp.p;
         s.det_part = (float4*)ctx->det_part.p;
@@ -1408,10 +1408,9 @@ adr_status adr_batch_create(adr_ctx* ctx, int32_t n, const adr_batch_item* items
   // the deterministic sort's buffers, sized for the largest item
   Scratch det{};
   if (det_E > 0) {
-    const int64_t tiles = (det_E + 2047) / 2048;
     const size_t parts[8] = {(size_t)det_E * 4, (size_t)det_E * 4, (size_t)det_E * 4, (size_t)det_E * 4,
-                             (size_t)det_E * 16, (size_t)det_hw * 4, (size_t)scan_tmp_words(det_hw) * 4 + 4,
-                             (size_t)tiles * 32};
+                             det_vals_bytes(det_E), (size_t)det_hw * 4, (size_t)scan_tmp_words(det_hw) * 4 + 4,
+                             det_part_bytes(det_E)};
     size_t o[8];
     for (int k = 0; k < 8; ++k) {
       o[k] = det_bytes;
@@ -1426,7 +1425,7 @@ adr_status adr_batch_create(adr_ctx* ctx, int32_t n, const adr_batch_item* items
     det.det_v0 = (uint32_t*)(d + o[1]);
     det.det_k1 = (uint32_t*)(d + o[2]);
     det.det_v1 = (uint32_t*)(d + o[3]);
-    det.det_vals = (float4*)(d + o[4]);
+    det_carve(d + o[4], det_E, det);
     det.det_hist = (uint32_t*)(d + o[5]);
     det.det_tmp = (uint32_t*)(d + o[6]);
     det.det_part = (float4*)(d + o[7]);
@@ -1466,6 +1465,8 @@ adr_status adr_batch_create(adr_ctx* ctx, int32_t n, const adr_batch_item* items
       s.det_k1 = det.det_k1;
       s.det_v1 = det.det_v1;
       s.det_vals = det.det_vals;
+      s.det_fy = det.det_fy;
+      s.det_gsum = det.det_gsum;
       s.det_hist = det.det_hist;
       s.det_tmp = det.det_tmp;
       s.det_part = det.det_part;

@@ -89,8 +89,10 @@ struct Scratch {
   unsigned long long* fix_clip;  // [B,V,4]
   unsigned long long* fix_pos;   // [V,3]
   uint32_t *det_k0, *det_v0, *det_k1, *det_v1, *det_hist, *det_tmp;
-  float4* det_vals;              // [entries]
-  float4* det_part;              // [2 tiles]
+  float4* det_vals;              // [entries] (level-weighted adjoint, fx)
+  float* det_fy;                 // [entries]
+  float4* det_gsum;              // [3 entries] corner sums of the groups, at their first positions
+  float4* det_part;              // [3 x 2 tiles]
 };
 
 // Up to four texture chains (a material's maps) and their gradient buffers.
@@ -347,6 +349,11 @@ hipError_t launch_laplacian(int n, const float* pos, const int* offs, const int*
 
 // Deterministic-mode sizes and helpers.
 int64_t det_entries(const ViewsD& v, int slots);
+// Bytes of the value buffers of E entries (det_vals, det_fy and det_gsum,
+// carved from one allocation by det_carve) and of the tile partials.
+size_t det_vals_bytes(int64_t E);
+size_t det_part_bytes(int64_t E);
+void det_carve(void* p, int64_t E, Scratch& s);
 int64_t radix_hist_words(int64_t n);
 int64_t scan_tmp_words(int64_t n);
 hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp, hipStream_t st);

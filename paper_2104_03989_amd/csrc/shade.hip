@@ -1048,24 +1048,71 @@ hipError_t launch_shade_bwd(const MeshD& m, const ViewsD& v, int model, const Te
   return hipGetLastError();
 }
 
-// ---- deterministic texel gradients: segmented reduction ----
+// ---- deterministic texel gradients: segmented reduction by bilinear cell ----
 //
-// Every (pixel, map, level, corner) contribution is written at a position
-// fixed by those four indices, with its texel as key (texels of the slots'
-// chains numbered one after the other; pixels without it get the key
-// `total`).  A stable radix sort by key groups each texel's contributions in
-// that fixed order; each group is summed in that order: within a tile of
-// 2048 sorted entries by one thread per piece, and a group that crosses tile
-// boundaries by adding its pieces tile after tile.
+// Every (pixel, map, level) sample is one entry, written at a position fixed
+// by those three indices and keyed by the bilinear cell of the sample: the
+// 2x2 texels (x0, y0) .. (x0 + 1, y0 + 1) it reads, x0 wrapped and y0 in
+// [-1, s - 1] (a row outside the level clamps to its edge, so a lower y0
+// reads the same texels as -1 and a higher one the same as s - 1).  A level
+// of size s has s (s + 1) cells, numbered (y0 + 1) s + x0 after the cells of
+// the coarser... finer levels before it, the slots' chains one after the
+// other; entries without a sample get the key `total`.  The value of an
+// entry is the sample's adjoint times its level weight, a (3 floats), and
+// its bilinear fractions fx, fy.  A stable radix sort by key groups each
+// cell's entries in the fixed order of their positions; each group's four
+// corner sums, c(cx, cy) = sum of (cx ? fx : 1 - fx) (cy ? fy : 1 - fy) a,
+// are formed in that order (pieces within a tile of 2048 sorted entries by
+// one thread each, groups that cross tiles joined tile after tile) and
+// stored at the group's first sorted position.  Four passes then add corner
+// (cx, cy) of every group to its texel (x0 + cx, y0 + cy).  Within one pass
+// no two cells reach the same texel: a cell on row -1 holds both its rows'
+// sums in its lower corners and one on row s - 1 in its upper corners (their
+// two rows are the same texels), so each texel adds its at most four corner
+// sums in pass order.  Keying by cell instead of by texel sorts a quarter of
+// the entries.
 
 struct TexDetArgs {
   TexBwdArgs tb;
-  uint32_t base[4];  // first key of each slot; base[n] = total
-  int64_t E;         // entries = n * P * 8
+  uint32_t base[5];               // first key of each slot; base[n] = total
+  int coff[4][kMaxLevels + 1];    // first cell of each level within its slot
+  int64_t E;                      // entries = n * P * 2
 };
 
+// Corner sums of a group, corner-major: (cx, cy) at 3 (2 cy + cx).
+struct Corners {
+  float v[12];
+};
+
+__device__ __forceinline__ void corners_add(Corners& c, float4 e, float fy) {
+  const float wx[2] = {1.f - e.w, e.w}, wy[2] = {1.f - fy, fy};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float w = wx[q & 1] * wy[q >> 1];
+    c.v[3 * q] += w * e.x;
+    c.v[3 * q + 1] += w * e.y;
+    c.v[3 * q + 2] += w * e.z;
+  }
+}
+
+__device__ __forceinline__ void corners_store(float4* __restrict__ p, const Corners& c) {
+  p[0] = make_float4(c.v[0], c.v[1], c.v[2], c.v[3]);
+  p[1] = make_float4(c.v[4], c.v[5], c.v[6], c.v[7]);
+  p[2] = make_float4(c.v[8], c.v[9], c.v[10], c.v[11]);
+}
+
+__device__ __forceinline__ Corners corners_load(const float4* __restrict__ p) {
+  Corners c;
+  const float4 a = p[0], b = p[1], d = p[2];
+  c.v[0] = a.x; c.v[1] = a.y; c.v[2] = a.z; c.v[3] = a.w;
+  c.v[4] = b.x; c.v[5] = b.y; c.v[6] = b.z; c.v[7] = b.w;
+  c.v[8] = d.x; c.v[9] = d.y; c.v[10] = d.z; c.v[11] = d.w;
+  return c;
+}
+
 __global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __restrict__ keys,
-                                                      uint32_t* __restrict__ idx, float4* __restrict__ vals) {
+                                                      uint32_t* __restrict__ idx, float4* __restrict__ vals,
+                                                      float* __restrict__ vfy) {
   const TexBwdArgs& tb = a.tb;
   const int64_t P = (int64_t)tb.v.B * tb.v.H * tb.v.W;
   const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1073,6 +1120,8 @@ __global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __
   const float4 r0 = tb.rec[o];
   const uint32_t lv = __float_as_uint(r0.z);
   const uint32_t none = a.base[tb.n];
+  float ul, vl;
+  unpack_lo(r0.w, ul, vl);
   for (int k = 0; k < tb.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     float4 rk = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1081,53 +1130,43 @@ __global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const bool on = l0 != 0xFF && (j == 0 || rk.w > 0.f);
-      const float wl = j == 0 ? 1.f - rk.w : rk.w;
-      float ul, vl;
-      unpack_lo(r0.w, ul, vl);
-      Foot q = foot_at(t, on ? l0 + j : 0, r0.x, r0.y, ul, vl);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int64_t e = (((int64_t)k * P + o) * 2 + j) * 4 + c;
-        uint32_t key = none;
-        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (on) {
-          const int r = c & 2 ? q.r1 : q.r0;
-          int cc = c & 1 ? q.c0 + 1 : q.c0;
-          cc = cc >= q.s ? cc - q.s : cc;
-          const float w = wl * (c & 1 ? q.fx : 1.f - q.fx) * (c & 2 ? q.fy : 1.f - q.fy);
-          key = a.base[k] + (uint32_t)(t.off[l0 + j] + r * q.s + cc);
-          val = make_float4(w * rk.x, w * rk.y, w * rk.z, 0.f);
-        }
-        keys[e] = key;
-        idx[e] = (uint32_t)e;
-        vals[e] = val;
+      const int64_t e = ((int64_t)k * P + o) * 2 + j;
+      uint32_t key = none;
+      float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+      float fy = 0.f;
+      if (on) {
+        const int l = l0 + j;
+        int sz = t.size >> l;
+        if (sz < 1) sz = 1;
+        int x0, y0;
+        float fx;
+        texel_coord(r0.x, ul, sz, x0, fx);
+        texel_coord(r0.y, vl, sz, y0, fy);
+        y0 = y0 < -1 ? -1 : (y0 > sz - 1 ? sz - 1 : y0);
+        const float wl = j == 0 ? 1.f - rk.w : rk.w;
+        key = a.base[k] + (uint32_t)(a.coff[k][l] + (y0 + 1) * sz + (x0 & (sz - 1)));
+        val = make_float4(wl * rk.x, wl * rk.y, wl * rk.z, fx);
       }
+      keys[e] = key;
+      idx[e] = (uint32_t)e;
+      vals[e] = val;
+      vfy[e] = fy;
     }
   }
 }
 
-__device__ __forceinline__ void det_store(const TexDetArgs& a, uint32_t key, float4 sum) {
-  int k = 0;
-  while (k + 1 < a.tb.n && key >= a.base[k + 1]) ++k;
-  const Tex& t = a.tb.t[k];
-  float* g = a.tb.g[k] + (int64_t)(key - a.base[k]) * t.channels;
-  g[0] += sum.x;
-  if (t.channels == 3) {
-    g[1] += sum.y;
-    g[2] += sum.z;
-  }
-}
-
-// Pieces of groups within each tile of 2048 sorted entries.  part[2 tile]
-// receives the sum of the tile's first piece when its group began in an
-// earlier tile, part[2 tile + 1] that of its last piece when its group
-// began in this tile and goes on into the next one.
+// Pieces of groups within each tile of 2048 sorted entries.  A piece that is
+// a whole group stores its corner sums at its first position; part[2 tile]
+// receives the sums of the tile's first piece when its group began in an
+// earlier tile, part[2 tile + 1] those of its last piece when its group
+// began in this tile and goes on into the next one (3 float4 each).
 constexpr int kDetTile = 2048;
 
 __global__ __launch_bounds__(256) void k_tex_det_pieces(TexDetArgs a, const uint32_t* __restrict__ sk,
                                                         const uint32_t* __restrict__ si,
                                                         const float4* __restrict__ vals,
-                                                        float4* __restrict__ part) {
+                                                        const float* __restrict__ vfy,
+                                                        float4* __restrict__ gsum, float4* __restrict__ part) {
   const int64_t tb0 = (int64_t)blockIdx.x * kDetTile;
   const int64_t te = min(tb0 + kDetTile, a.E);
   const uint32_t none = a.base[a.tb.n];
@@ -1135,26 +1174,28 @@ __global__ __launch_bounds__(256) void k_tex_det_pieces(TexDetArgs a, const uint
     const uint32_t key = sk[i];
     if (key >= none) continue;
     if (i > tb0 && sk[i - 1] == key) continue;  // not the start of a piece
-    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+    Corners c;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) c.v[q] = 0.f;
     int64_t j = i;
     for (; j < te && sk[j] == key; ++j) {
-      const float4 v = vals[si[j]];
-      sum.x += v.x;
-      sum.y += v.y;
-      sum.z += v.z;
+      const uint32_t e = si[j];
+      corners_add(c, vals[e], vfy[e]);
     }
     const bool from_prev = i == tb0 && i > 0 && sk[i - 1] == key;
     const bool into_next = j == te && te < a.E && sk[te] == key;
-    if (from_prev) part[2 * blockIdx.x] = sum;
-    else if (into_next) part[2 * blockIdx.x + 1] = sum;
-    else det_store(a, key, sum);
+    if (from_prev) corners_store(part + 3 * (2 * blockIdx.x), c);
+    else if (into_next) corners_store(part + 3 * (2 * blockIdx.x + 1), c);
+    else corners_store(gsum + 3 * i, c);
   }
 }
 
 // Groups that cross tiles: started in tile b, continued by the first pieces
-// of the following tiles, added in tile order.
+// of the following tiles, added in tile order; stored at the group's first
+// position.
 __global__ __launch_bounds__(256) void k_tex_det_join(TexDetArgs a, const uint32_t* __restrict__ sk,
-                                                      const float4* __restrict__ part, int64_t tiles) {
+                                                      const float4* __restrict__ part, float4* __restrict__ gsum,
+                                                      int64_t tiles) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= tiles) return;
   const int64_t te = min((b + 1) * kDetTile, a.E);
@@ -1165,22 +1206,75 @@ __global__ __launch_bounds__(256) void k_tex_det_join(TexDetArgs a, const uint32
   // before the tile is the same, the whole tile continues an earlier group
   const int64_t tb0 = b * kDetTile;
   if (tb0 > 0 && sk[tb0 - 1] == key) return;
-  float4 sum = part[2 * b + 1];
-  for (int64_t c = b + 1; c < tiles; ++c) {
-    const float4 v = part[2 * c];
-    sum.x += v.x;
-    sum.y += v.y;
-    sum.z += v.z;
-    const int64_t ce = min((c + 1) * kDetTile, a.E);
+  Corners c = corners_load(part + 3 * (2 * b + 1));
+  for (int64_t t = b + 1; t < tiles; ++t) {
+    const Corners d = corners_load(part + 3 * (2 * t));
+#pragma unroll
+    for (int q = 0; q < 12; ++q) c.v[q] += d.v[q];
+    const int64_t ce = min((t + 1) * kDetTile, a.E);
     if (ce >= a.E || sk[ce] != key) break;
   }
-  det_store(a, key, sum);
+  int64_t i = te - 1;
+  while (i > tb0 && sk[i - 1] == key) --i;
+  corners_store(gsum + 3 * i, c);
+}
+
+// Pass `corner` = 2 cy + cx: every group adds its corner (cx, cy) to its
+// texel (see above for why no two groups of a pass reach the same texel).
+__global__ __launch_bounds__(256) void k_tex_det_corner(TexDetArgs a, const uint32_t* __restrict__ sk,
+                                                        const float4* __restrict__ gsum, int corner) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.E) return;
+  const uint32_t key = sk[i];
+  if (key >= a.base[a.tb.n] || (i > 0 && sk[i - 1] == key)) return;
+  int k = 0;
+  while (k + 1 < a.tb.n && key >= a.base[k + 1]) ++k;
+  const Tex& t = a.tb.t[k];
+  const int rel = (int)(key - a.base[k]);
+  int l = 0;
+  while (l + 1 < t.levels && rel >= a.coff[k][l + 1]) ++l;
+  int sz = t.size >> l;
+  if (sz < 1) sz = 1;
+  const int cell = rel - a.coff[k][l];
+  const int y0 = cell / sz - 1, x0 = cell - (y0 + 1) * sz;
+  const int cx = corner & 1, cy = corner >> 1;
+  const Corners c = corners_load(gsum + 3 * i);
+  float g0 = c.v[3 * corner], g1 = c.v[3 * corner + 1], g2 = c.v[3 * corner + 2];
+  if (y0 == -1 || y0 == sz - 1) {
+    // both rows are one row of texels: the lower corners of row -1, the
+    // upper ones of row s - 1 carry the cell (row -1 wins when s = 1)
+    const int keep = y0 == -1 ? 1 : 0;
+    if (cy != keep) return;
+    const int q0 = cx, q1 = 2 + cx;
+    g0 = c.v[3 * q0] + c.v[3 * q1];
+    g1 = c.v[3 * q0 + 1] + c.v[3 * q1 + 1];
+    g2 = c.v[3 * q0 + 2] + c.v[3 * q1 + 2];
+  }
+  int row = y0 + cy;
+  row = row < 0 ? 0 : (row > sz - 1 ? sz - 1 : row);
+  const int col = (x0 + cx) & (sz - 1);
+  float* g = a.tb.g[k] + (int64_t)(t.off[l] + row * sz + col) * t.channels;
+  g[0] += g0;
+  if (t.channels == 3) {
+    g[1] += g1;
+    g[2] += g2;
+  }
 }
 
 hipError_t launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
                              uint32_t* hist, uint32_t* tmp, bool* in_first, hipStream_t st);
 
-int64_t det_entries(const ViewsD& v, int slots) { return (int64_t)slots * v.B * v.H * v.W * 8; }
+int64_t det_entries(const ViewsD& v, int slots) { return (int64_t)slots * v.B * v.H * v.W * 2; }
+
+size_t det_vals_bytes(int64_t E) { return (size_t)E * 16 + (((size_t)E * 4 + 255) & ~(size_t)255) + (size_t)E * 48; }
+size_t det_part_bytes(int64_t E) { return (size_t)((E + kDetTile - 1) / kDetTile) * 96; }
+
+void det_carve(void* p, int64_t E, Scratch& s) {
+  unsigned char* b = static_cast<unsigned char*>(p);
+  s.det_vals = reinterpret_cast<float4*>(b);
+  s.det_fy = reinterpret_cast<float*>(b + (size_t)E * 16);
+  s.det_gsum = reinterpret_cast<float4*>(b + (size_t)E * 16 + (((size_t)E * 4 + 255) & ~(size_t)255));
+}
 
 hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const Tex& nm, const Tex& orm,
                               float* gkd, float* gnm, float* gorm, const Scratch& s, hipStream_t st) {
@@ -1191,14 +1285,23 @@ hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const T
   a.tb.v = v;
   uint32_t total = 0;
   for (int k = 0; k < a.tb.n; ++k) {
+    const Tex& t = a.tb.t[k];
     a.base[k] = total;
-    total += (uint32_t)a.tb.t[k].off[a.tb.t[k].levels];
+    int c = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) {
+      a.coff[k][l] = c;
+      if (l < t.levels) {
+        const int sz = (t.size >> l) < 1 ? 1 : (t.size >> l);
+        c += sz * (sz + 1);
+      }
+    }
+    total += (uint32_t)c;
   }
   a.base[a.tb.n] = total;
   a.E = det_entries(v, a.tb.n);
   const int64_t P = (int64_t)v.B * v.H * v.W;
   hipLaunchKernelGGL(k_tex_det_emit, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, a, s.det_k0, s.det_v0,
-                     s.det_vals);
+                     s.det_vals, s.det_fy);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int bits = 1;
@@ -1210,11 +1313,18 @@ hipError_t launch_tex_bwd_det(const ViewsD& v, int model, const Tex& kd, const T
   const uint32_t* sk = first ? s.det_k0 : s.det_k1;
   const uint32_t* si = first ? s.det_v0 : s.det_v1;
   const int64_t tiles = (a.E + kDetTile - 1) / kDetTile;
-  hipLaunchKernelGGL(k_tex_det_pieces, dim3((unsigned)tiles), dim3(256), 0, st, a, sk, si, s.det_vals, s.det_part);
+  hipLaunchKernelGGL(k_tex_det_pieces, dim3((unsigned)tiles), dim3(256), 0, st, a, sk, si, s.det_vals, s.det_fy,
+                     s.det_gsum, s.det_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tex_det_join, dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, st, a, sk, s.det_part,
-                     tiles);
-  return hipGetLastError();
+                     s.det_gsum, tiles);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int c = 0; c < 4; ++c) {
+    hipLaunchKernelGGL(k_tex_det_corner, dim3((unsigned)((a.E + 255) / 256)), dim3(256), 0, st, a, sk, s.det_gsum,
+                       c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // The atomic texel scatter (0 blocks without a gradient buffer).
