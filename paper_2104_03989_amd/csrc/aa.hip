@@ -305,17 +305,25 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
   const int x0 = p.i - lx, y0 = p.j - ly;
   const int64_t base = (int64_t)p.b * a.v.H * a.v.W;
   const int64_t o = base + (int64_t)p.j * a.v.W + p.i;
+  // every load of the pixel issued up front, so that their latencies overlap:
+  // its key, its four neighbours' keys (a missing neighbour takes the
+  // pixel's own key, which pairs with nothing), its colour and reference
   const uint64_t k = p.ok ? a.vis[o] : 0ull;
+  const bool aa_on = p.ok && !a.no_aa;
+  const uint64_t kl = aa_on && p.i > 0 ? a.vis[o - 1] : k;
+  const uint64_t kr = aa_on && p.i + 1 < a.v.W ? a.vis[o + 1] : k;
+  const uint64_t kd = aa_on && p.j > 0 ? a.vis[o - a.v.W] : k;
+  const uint64_t ku = aa_on && p.j + 1 < a.v.H ? a.vis[o + a.v.W] : k;
+  const f3 c = p.ok ? ldc(a.color, o) : mk(0.f, 0.f, 0.f);
+  const f3 rv = p.ok && ref ? ldc(ref, o) : mk(0.f, 0.f, 0.f);
   if (!a.no_aa) {
     float code[2] = {-1.f, -1.f};
     if (p.ok) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int ni = p.i + (q == 0 ? 1 : 0), nj = p.j + (q == 1 ? 1 : 0);
-        if (ni >= a.v.W || nj >= a.v.H) continue;
         Pair pr;
-        if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, a.vis[base + (int64_t)nj * a.v.W + ni], pr))
-          code[q] = pair_code(pr.x);
+        if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, q == 0 ? kr : ku, pr)) code[q] = pair_code(pr.x);
       }
       if (a.stats) {
         a.codes[a.code_stride * o] = code[0];
@@ -330,32 +338,29 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
       const int r = threadIdx.x & 15;
       const int i = left ? x0 - 1 : x0 + r, j = left ? y0 + r : y0 - 1;
       const int ni = left ? i + 1 : i, nj = left ? j : j + 1;
-      float c = -1.f;
+      float hcode = -1.f;
       if (i >= 0 && j >= 0 && ni < a.v.W && nj < a.v.H) {
         Pair pr;
         if (eval_pair(a, p.b, i, j, a.vis[base + (int64_t)j * a.v.W + i], ni, nj,
                       a.vis[base + (int64_t)nj * a.v.W + ni], pr))
-          c = pair_code(pr.x);
+          hcode = pair_code(pr.x);
       }
-      if (left) hc[r][0] = c;
-      else vc[0][r] = c;
+      if (left) hc[r][0] = hcode;
+      else vc[0][r] = hcode;
     }
     __syncthreads();
   }
   float lsum = 0.f;
   if (p.ok) {
-    const f3 c = ldc(a.color, o);
     f3 out = c;
     if (!a.no_aa) {
       // received antialiasing: W and acc = sum_k w_k (c_k - c)
       Recv r{0.f, mk(0.f, 0.f, 0.f)};
-      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+      const int64_t dn[4] = {-1, 1, -(int64_t)a.v.W, (int64_t)a.v.W};
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int ni = p.i + di[q], nj = p.j + dj[q];
-        if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
-        const int64_t on = base + (int64_t)nj * a.v.W + ni;
-        const uint64_t kn = a.vis[on];
+        const int64_t on = o + dn[q];
+        const uint64_t kn = q == 0 ? kl : (q == 1 ? kr : (q == 2 ? kd : ku));
         const float cq = q == 0 ? hc[ly][lx] : (q == 1 ? hc[ly][lx + 1] : (q == 2 ? vc[ly][lx] : vc[ly + 1][lx]));
         const float w = (uint32_t)k == (uint32_t)kn ? 0.f : received_from(cq, k < kn);
         if (w > 0.f) {
@@ -369,7 +374,7 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
     if (image) st3(image, o, out);
     if (ref) {
       const float inv_n = 1.0f / (3.0f * (float)a.v.B * (float)a.v.H * (float)a.v.W);
-      lsum += pixel_loss(out, ldc(ref, o), loss_kind, inv_n, dimage, o);
+      lsum += pixel_loss(out, rv, loss_kind, inv_n, dimage, o);
     }
   }
   if (ref) {
@@ -380,8 +385,9 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
     if (threadIdx.x == 0) f.partial[bid] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
-// (6 waves per SIMD: the compiler's own choice, 88 VGPRs, gives 5 and ran 6% slower)
-ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
+// (7 waves per SIMD, 72 VGPRs and 48 bytes of spills: the compiler's own choice, 93 VGPRs, gives 5:
+// 0.120 -> 0.112 ms per step for the two renders of the paper loop; more spills cost far more)
+ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
 
 __device__ __forceinline__ void loss_reduce_body(const LossReduceArgs& a, int, int) {
   __shared__ double red[256];
@@ -419,24 +425,27 @@ __device__ __forceinline__ void aa_bwd_body(const AABwdArgs& b, int bid, int nb)
   f3 gself = scale * sample_grad(a, dimage, p.b, p.i, p.j);
   f3 gc = gself;
   if (!a.no_aa) {
-    uint64_t k = a.vis[o];
+    // the keys of the pixel and of its four neighbours, loaded together (a
+    // missing neighbour takes the pixel's own key, which pairs with nothing)
+    const uint64_t k = a.vis[o];
+    const uint64_t kl = p.i > 0 ? a.vis[o - 1] : k, kr = p.i + 1 < a.v.W ? a.vis[o + 1] : k;
+    const uint64_t kd = p.j > 0 ? a.vis[o - a.v.W] : k, ku = p.j + 1 < a.v.H ? a.vis[o + a.v.W] : k;
     f3 c = ldc(a.color, o);
     Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
     float Ms = fmaxf(rs.W, 1.0f);
     gc = (1.0f - rs.W / Ms) * gself;
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
     for (int q = 0; q < 4; ++q) {
+      const uint64_t kn = q == 0 ? kl : (q == 1 ? kr : (q == 2 ? kd : ku));
+      if ((uint32_t)k == (uint32_t)kn) continue;
       int ni = p.i + di[q], nj = p.j + dj[q];
-      if (ni < 0 || nj < 0 || ni >= a.v.W || nj >= a.v.H) continue;
       int64_t on = base + (int64_t)nj * a.v.W + ni;
-      const uint64_t kn = a.vis[on];
       Pair pr;
       bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
       float s;
       if (a.codes) {
         // the pair's code from the forward; the edge itself is only needed
         // by the owner, for the gradient of s
-        if ((uint32_t)k == (uint32_t)kn) continue;
         const float c = code_of(a, base, p.i, p.j, q);
         if (c < 0.f) continue;
         pr.self_is_P = k < kn;
