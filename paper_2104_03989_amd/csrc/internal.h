@@ -14,6 +14,7 @@ constexpr int kMaxLevels = 15;
 constexpr int kTinyBBox = 64;      // default: pixel bbox up to this walked by one thread
 constexpr int kMedBBox = 4096;     // default: up to this walked by a whole wave; larger: tile-binned
 constexpr int kBigTile = 16;       // big-triangle tiles are kBigTile x kBigTile pixels
+constexpr int kBigBlocks = 1024;   // most blocks of one big-triangle raster launch (4 per CU)
 
 // Texture as the kernels see it: level offsets in texels precomputed.
 struct Tex {

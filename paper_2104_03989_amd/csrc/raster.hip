@@ -286,57 +286,64 @@ __device__ __forceinline__ void raster_big_body(const RasterArgs& a, int bid, in
   uint32_t* __restrict__ cov = a.cov;
   const unsigned long long* __restrict__ floor = a.floor;
   const int tiles_x = a.tiles_x, tiles_y = a.tiles_y;
-  int tile = xcd_tile(bid, nb);
-  int per_view = tiles_x * tiles_y;
-  int b = tile / per_view;
-  int r = tile - b * per_view;
-  int ty = r / tiles_x, tx = r - ty * tiles_x;
-  uint32_t n_big = a.big_cnt[b];
-  if (n_big == 0) return;
-  int i = tx * kBigTile + (threadIdx.x & 15), j = ty * kBigTile + (threadIdx.x >> 4);
-  int ti0 = tx * kBigTile, ti1 = min(ti0 + kBigTile, v.W) - 1;
-  int tj0 = ty * kBigTile, tj1 = min(tj0 + kBigTile, v.H) - 1;
-  const int4* sv = a.snap + (int64_t)b * m.n_pos;
-  unsigned long long best = kKeyEmpty;
-  uint32_t hits = 0;
-  int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
-  const unsigned long long fk =
-      (floor && i < v.W && j < v.H) ? floor[(int64_t)b * v.W * v.H + (int64_t)j * v.W + i] : 0ull;
-  for (uint32_t base = 0; base < n_big; base += 256) {
-    if (threadIdx.x == 0) lds_n = 0;
-    __syncthreads();
-    uint32_t q = base + threadIdx.x;
-    if (q < n_big) {
-      int t = (int)big[(int64_t)b * m.n_tri + q];
-      int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
-      Setup s;
-      if (setup_tri(sv, c, s)) {
-        BBox bb = pixel_bbox(s, v.W, v.H);
-        if (bb.i0 <= ti1 && bb.i1 >= ti0 && bb.j0 <= tj1 && bb.j1 >= tj0) {
-          int slot = atomicAdd(&lds_n, 1);
-          lds[slot] = s;
-          lds_t[slot] = t;
+  const int per_view = tiles_x * tiles_y, n_tiles = per_view * v.B;
+  // a grid-stride loop over the tiles of all views: a view without big
+  // triangles is stepped over at once instead of costing a block per tile
+  for (int tile = bid; tile < n_tiles; tile += nb) {
+    const int b = tile / per_view;
+    const uint32_t n_big = a.big_cnt[b];
+    if (n_big == 0) {
+      // on to this block's first tile in a later view
+      tile += ((b + 1) * per_view - tile + nb - 1) / nb * nb - nb;
+      continue;
+    }
+    int r = tile - b * per_view;
+    int ty = r / tiles_x, tx = r - ty * tiles_x;
+    int i = tx * kBigTile + (threadIdx.x & 15), j = ty * kBigTile + (threadIdx.x >> 4);
+    int ti0 = tx * kBigTile, ti1 = min(ti0 + kBigTile, v.W) - 1;
+    int tj0 = ty * kBigTile, tj1 = min(tj0 + kBigTile, v.H) - 1;
+    const int4* sv = a.snap + (int64_t)b * m.n_pos;
+    unsigned long long best = kKeyEmpty;
+    uint32_t hits = 0;
+    int64_t px = 256 * (int64_t)i + 128, py = 256 * (int64_t)j + 128;
+    const unsigned long long fk =
+        (floor && i < v.W && j < v.H) ? floor[(int64_t)b * v.W * v.H + (int64_t)j * v.W + i] : 0ull;
+    for (uint32_t base = 0; base < n_big; base += 256) {
+      if (threadIdx.x == 0) lds_n = 0;
+      __syncthreads();
+      uint32_t q = base + threadIdx.x;
+      if (q < n_big) {
+        int t = (int)big[(int64_t)b * m.n_tri + q];
+        int3 c = make_int3(m.tri[3 * t], m.tri[3 * t + 1], m.tri[3 * t + 2]);
+        Setup s;
+        if (setup_tri(sv, c, s)) {
+          BBox bb = pixel_bbox(s, v.W, v.H);
+          if (bb.i0 <= ti1 && bb.i1 >= ti0 && bb.j0 <= tj1 && bb.j1 >= tj0) {
+            int slot = atomicAdd(&lds_n, 1);
+            lds[slot] = s;
+            lds_t[slot] = t;
+          }
         }
       }
-    }
-    __syncthreads();
-    int n = lds_n;
-    if (i < v.W && j < v.H) {
-      for (int k = 0; k < n; ++k) {
-        if (!covers(lds[k], px, py)) continue;
-        unsigned long long key =
-            ((unsigned long long)depth_at(lds[k], (int)px, (int)py) << 32) | (uint32_t)(lds_t[k] + 1);
-        if (floor && key <= fk) continue;
-        ++hits;
-        best = key < best ? key : best;
+      __syncthreads();
+      int n = lds_n;
+      if (i < v.W && j < v.H) {
+        for (int k = 0; k < n; ++k) {
+          if (!covers(lds[k], px, py)) continue;
+          unsigned long long key =
+              ((unsigned long long)depth_at(lds[k], (int)px, (int)py) << 32) | (uint32_t)(lds_t[k] + 1);
+          if (floor && key <= fk) continue;
+          ++hits;
+          best = key < best ? key : best;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  if (i < v.W && j < v.H) {
-    int64_t o = (int64_t)b * v.W * v.H + (int64_t)j * v.W + i;
-    if (best != kKeyEmpty) atomicMin(vis + o, best);
-    if (cov && hits) atomicAdd(cov + o, hits);
+    if (i < v.W && j < v.H) {
+      int64_t o = (int64_t)b * v.W * v.H + (int64_t)j * v.W + i;
+      if (best != kKeyEmpty) atomicMin(vis + o, best);
+      if (cov && hits) atomicAdd(cov + o, hits);
+    }
   }
 }
 ADR_KERNEL(__launch_bounds__(256), k_raster_big, RasterArgs, raster_big_body)
@@ -388,7 +395,8 @@ RasterPlans plan_raster(const MeshD& m, const ViewsD& v, const Scratch& s, uint6
   p.small = n > 0 ? (unsigned)((n + 255) / 256) : 0u;
   // enough waves to fill the chip; each loops over the queue
   p.med = n > 0 ? (unsigned)std::min((n + 3) / 4, 4096) : 0u;
-  p.big = n > 0 ? (unsigned)(a.tiles_x * a.tiles_y * v.B) : 0u;
+  // the big-triangle tiles: at most kBigBlocks blocks, each looping over tiles
+  p.big = n > 0 ? (unsigned)std::min(a.tiles_x * a.tiles_y * v.B, kBigBlocks) : 0u;
   return p;
 }
 
