@@ -209,6 +209,38 @@ def test_adam_matches_oracle(ctx):
     assert np.abs(Q[0].cpu().numpy() - pq).max() < 1e-6
 
 
+def test_adam_many_ragged_and_unaligned_tensors(ctx):
+    """More tensors than one launch takes (16), ragged sizes (whole float4
+    chunks plus 1-3 floats, and tensors of 1-3 floats) and tensors that are
+    not 16-byte aligned (views one float into a buffer): every element gets
+    the oracle's Adam update."""
+    from paper_2104_03989_amd import adr
+    _say("adam, many tensors")
+    g = np.random.default_rng(3)
+    sizes = [1, 2, 3, 4, 5, 7, 8, 9, 63, 64, 65, 1001, 1002, 1003, 1004, 17, 33, 4097, 6, 11, 250]
+    params, ref = [], []
+    for k, n in enumerate(sizes):
+        host = [g.normal(size=n), g.normal(size=n), g.normal(size=n) * 0.1, np.abs(g.normal(size=n)) * 0.01]
+        if k % 3 == 1:
+            # a view one float into its buffer: not 16-byte aligned
+            bufs = [torch.zeros(n + 1, dtype=torch.float32, device="cuda") for _ in range(4)]
+            T = [b[1:] for b in bufs]
+            for t, x in zip(T, host):
+                t.copy_(torch.tensor(x, dtype=torch.float32))
+        else:
+            T = [torch.tensor(x, dtype=torch.float32, device="cuda") for x in host]
+        params.append(tuple(T))
+        ref.append([x.astype(np.float32).astype(np.float64) for x in host])
+    adr.adam_step(ctx, params, 3, 2e-3)
+    torch.cuda.synchronize()
+    for k, (T, (p32, g32, m32, v32)) in enumerate(zip(params, ref)):
+        pe, me, ve = R.adam(p32, g32, m32, v32, 3, 2e-3)
+        assert np.abs(T[0].cpu().numpy() - pe).max() < 1e-6, (k, sizes[k])
+        assert np.abs(T[2].cpu().numpy() - me).max() < 1e-6, (k, sizes[k])
+        assert np.abs(T[3].cpu().numpy() - ve).max() < 1e-6, (k, sizes[k])
+        assert float(T[1].abs().max()) == 0.0, (k, sizes[k])
+
+
 def test_mip_chains(ctx):
     from paper_2104_03989_amd import adr
     _say("mips")
