@@ -765,11 +765,15 @@ def batched(args):
                                                             f"{w.ref.mesh.tri.shape[0]} tris, {w.dirs.shape[0]} x "
                                                             f"{w.width}^2"))
     W, K = args.warmup, args.steps
-    n_steps = 2 * W + 2 * K + 1
+    n_steps = W + K + 1
     _log("uploading and tuning")
     b = Batch(ws, n_steps, n_streams=4, det=args.deterministic, tune=True, progress=lambda k: None,
               form=args.batch_form)
     px = sum(w.dirs.shape[0] * w.width * w.height for w in ws)
+    # both forms run steps 0 .. W+K-1 from the same state (the optimised
+    # parameters, maps and Adam moments restored in between), so their last
+    # losses are comparable
+    snap = b.snapshot()
     t = 0
     _log("plain warm-up")
     for _ in range(W):
@@ -785,10 +789,13 @@ def batched(args):
     dt_plain = time.perf_counter() - t0
     loss_plain = float(np.mean(b.losses()))
     _log("batched: warm-up and capture")
+    b.restore(snap)
+    del snap
+    t = 0
     b.step_eager(t)
     t += 1
     b.capture()
-    for _ in range(W):
+    for _ in range(W - 1):
         b.step(t)
         t += 1
     torch.cuda.synchronize()

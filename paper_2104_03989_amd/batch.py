@@ -216,6 +216,25 @@ class Batch:
     def losses(self):
         return [m.loss() for m in self.meshes]
 
+    def snapshot(self):
+        """Copies of every mesh's optimised state (positions, maps with their
+        chains, gradients and Adam moments), for ``restore``."""
+        return [[t.clone() for t in self._state(m)] for m in self.meshes]
+
+    def restore(self, snap):
+        for m, saved in zip(self.meshes, snap):
+            for t, x in zip(self._state(m), saved):
+                t.copy_(x)
+
+    @staticmethod
+    def _state(m):
+        out = [m.lat_mesh.pos]
+        for p, g, mm, vv in m.params:
+            out += [g, mm, vv]
+        for tex, g, mm, vv in m.maps:
+            out += [tex.data, g, mm, vv]
+        return out
+
     def scratch_bytes(self) -> int:
         """Device bytes of the two library batches (launch form)."""
         return sum(b.info()["bytes"] for b in (self.ref_batch, self.lat_batch) if b is not None)
