@@ -1242,19 +1242,25 @@ __global__ __launch_bounds__(256) void k_tex_det_corner(TexDetArgs a, const uint
   int sz = t.size >> l;
   if (sz < 1) sz = 1;
   const int cell = rel - a.coff[k][l];
-  const int y0 = cell / sz - 1, x0 = cell - (y0 + 1) * sz;
+  // sz is a power of two: the cell's row and column by shift and mask
+  const int y0 = (cell >> __builtin_ctz((unsigned)sz)) - 1, x0 = cell & (sz - 1);
   const int cx = corner & 1, cy = corner >> 1;
-  const Corners c = corners_load(gsum + 3 * i);
-  float g0 = c.v[3 * corner], g1 = c.v[3 * corner + 1], g2 = c.v[3 * corner + 2];
+  // only this pass's corner sums are read (two corners on a folded row)
+  const float* cs = reinterpret_cast<const float*>(gsum + 3 * i);
+  float g0, g1, g2;
   if (y0 == -1 || y0 == sz - 1) {
     // both rows are one row of texels: the lower corners of row -1, the
     // upper ones of row s - 1 carry the cell (row -1 wins when s = 1)
     const int keep = y0 == -1 ? 1 : 0;
     if (cy != keep) return;
     const int q0 = cx, q1 = 2 + cx;
-    g0 = c.v[3 * q0] + c.v[3 * q1];
-    g1 = c.v[3 * q0 + 1] + c.v[3 * q1 + 1];
-    g2 = c.v[3 * q0 + 2] + c.v[3 * q1 + 2];
+    g0 = cs[3 * q0] + cs[3 * q1];
+    g1 = cs[3 * q0 + 1] + cs[3 * q1 + 1];
+    g2 = cs[3 * q0 + 2] + cs[3 * q1 + 2];
+  } else {
+    g0 = cs[3 * corner];
+    g1 = cs[3 * corner + 1];
+    g2 = cs[3 * corner + 2];
   }
   int row = y0 + cy;
   row = row < 0 ? 0 : (row > sz - 1 ? sz - 1 : row);
