@@ -344,9 +344,10 @@ ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))), k_sha
 // depth-peeled layers) is taken in groups of lanes whose cells fit a box of
 // the window's size, one window pass per group.
 
-// Window entries per wave: 14 x 14 texels x 3 channels fit; 4 waves' windows
-// take 20 KB of LDS, so 8 blocks (8 waves per SIMD) are resident per CU.
-constexpr int kWinTex = 640;
+// Window entries per wave (32-bit): 20 x 20 texels x 3 channels fit; 4 waves'
+// windows take 20 KB of LDS, so 8 blocks (8 waves per SIMD) are resident per
+// CU.
+constexpr int kWinTex = 1280;
 // side of the largest square box of texels whose window fits kWinTex entries
 constexpr int win_side(int C) {
   int s = 1;
@@ -410,19 +411,20 @@ __device__ __forceinline__ Foot foot_at(const Tex& t, int l, float u, float v, f
 // adds the window's nonzero texel-channels to HBM and clears them, so the
 // window is all zero again (it starts zeroed).  Converged code.
 //
-// The window sums in 64-bit fixed point: the pass scales every contribution
+// The window sums in 32-bit fixed point: the pass scales every contribution
 // by 2^k, k chosen from the largest magnitude in the wave so that each
-// scaled value stays below 2^29, rounds it to an integer and adds it with an
+// scaled value stays below 2^22, rounds it to an integer and adds it with an
 // integer LDS atomic (on this chip a float LDS atomic costs some thirty
-// times an integer one).  A window texel-channel is converted back to float
-// once: each contribution carries an error of at most 2^-29 of the wave's
-// largest one, and the sum does not depend on the lanes' order.  A pass with
-// a non-finite contribution adds markers instead and writes NaN to the
-// texels it touches.
-using WinT = unsigned long long;
+// times an integer one, a 64-bit one about twice a 32-bit one).  At most
+// 64 lanes x 4 corners add to one entry, so its sum stays below 2^30.  A
+// window texel-channel is converted back to float once: each contribution
+// carries an error of at most 2^-23 of the wave's largest one, and the sum
+// does not depend on the lanes' order.  A pass with a non-finite
+// contribution adds markers instead and writes NaN to the texels it touches.
+using WinT = unsigned int;
 
 __device__ __forceinline__ WinT fix_of(float x, int k, bool finite) {
-  return finite ? (WinT)(long long)(int)rintf(ldexpf(x, k)) : 1ull;
+  return finite ? (WinT)(int)rintf(ldexpf(x, k)) : 1u;
 }
 
 __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gtex, WinT* win, bool sel,
@@ -452,7 +454,7 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
   const int mb = wave_max_i(__float_as_int(amax));
   const bool finite = mb < 0x7F800000;
   const int e = ((mb >> 23) & 0xFF) - 126;
-  const int ks = finite ? 29 - e : 0;
+  const int ks = finite ? 22 - e : 0;
   wave_sync();
   if (sel && mb != 0) {
     // corner by corner (lanes sharing a cell add to the same entries in one
@@ -474,9 +476,9 @@ __device__ __forceinline__ void window_pass(const Tex& t, float* __restrict__ gt
     // reciprocal of ww corrected by one either way (no integer division)
     const float inv_ww = 1.0f / (float)ww;
     for (int k = lane; k < n; k += 64) {
-      const long long sum = (long long)win[k];
+      const long long sum = (long long)(int)win[k];
       if (sum != 0) {
-        win[k] = 0ull;
+        win[k] = 0u;
         const float val = finite ? ldexpf((float)sum, -ks) : __int_as_float(0x7FC00000);
         const int texel = C == 3 ? k / 3 : k, ch = k - texel * C;
         int rr = (int)((float)texel * inv_ww);
@@ -954,7 +956,7 @@ __device__ __forceinline__ void tex_bwd_body(const TexBwdArgs& a, int bid, int n
   float4 r0 = p.ok ? ld_nt(a.rec + o) : make_float4(0.f, 0.f, __uint_as_float(0xFFFFFFFFu), 0.f);
   const uint32_t lv = __float_as_uint(r0.z);
   WinT* win = win_all[threadIdx.x >> 6];
-  for (int k = threadIdx.x & 63; k < kWinTex; k += 64) win[k] = 0ull;
+  for (int k = threadIdx.x & 63; k < kWinTex; k += 64) win[k] = 0u;
   for (int k = 0; k < a.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
