@@ -73,12 +73,6 @@ __device__ __forceinline__ void vertex_normalize_body(const VertexNormalizeArgs&
 }
 ADR_KERNEL(__launch_bounds__(256), k_vertex_normalize, VertexNormalizeArgs, vertex_normalize_body)
 
-__global__ void k_fill_f64(double* __restrict__ p, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = 0.0;
-}
-
 __global__ void k_fill_u64(unsigned long long* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
