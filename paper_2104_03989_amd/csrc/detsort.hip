@@ -91,8 +91,13 @@ hipError_t launch_exscan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint3
 // One pass per 8-bit digit.  Tiles of 2048 pairs per block, in array order.
 //  hist:    per tile, digit counts -> hist[digit * tiles + tile]
 //  scan:    exclusive scan of hist (digit-major): each (digit, tile) start
-//  scatter: the tile is sorted by the digit in LDS with eight stable one-bit
-//           splits, then each pair goes to its digit's start plus its rank.
+//  scatter: the tile's pairs in eight rounds of 256 (round r, thread t: tile
+//           position 256 r + t); a pair goes to its digit's start in this
+//           tile plus the number of pairs of that digit before it in the
+//           tile: those of earlier rounds (a running count per digit), of
+//           earlier waves in this round (per-wave digit counts) and of lower
+//           lanes in its wave (the lanes whose digit matches, from eight
+//           ballots).  Equal digits keep their order: the sort is stable.
 
 __global__ __launch_bounds__(kScanBlock) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                         int64_t tiles, uint32_t* __restrict__ hist) {
@@ -113,58 +118,39 @@ __global__ __launch_bounds__(kScanBlock) void k_rs_scatter(const uint32_t* __res
                                                            int64_t tiles, const uint32_t* __restrict__ start,
                                                            uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout) {
-  __shared__ uint32_t sk[2][kScanTile];
-  __shared__ uint32_t sv[2][kScanTile];
-  __shared__ uint32_t lds[kScanBlock];
-  __shared__ uint32_t dstart[256];
-  const int t = threadIdx.x;
+  __shared__ uint32_t run[256];    // per digit: where its next pair goes
+  __shared__ uint32_t wc[4][256];  // per wave: this round's pairs of each digit
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  const int cnt = (int)min((int64_t)kScanTile, n - base);
-  // blocked arrangement: thread t owns tile positions t*8 .. t*8+7
-  for (int k = t; k < kScanTile; k += kScanBlock) {
-    const int64_t i = base + k;
-    sk[0][k] = k < cnt ? kin[i] : 0xFFFFFFFFu;  // padding sorts last and is dropped
-    sv[0][k] = k < cnt ? vin[i] : 0u;
-  }
+  run[t] = start[(int64_t)t * tiles + blockIdx.x];
+  wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0u;
   __syncthreads();
-  int cur = 0;
-  for (int b = 0; b < 8; ++b) {
-    uint32_t zeros = 0;
-    uint32_t kk[kScanItems], vv[kScanItems];
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      kk[j] = sk[cur][t * kScanItems + j];
-      vv[j] = sv[cur][t * kScanItems + j];
-      zeros += ((kk[j] >> (shift + b)) & 1u) ? 0u : 1u;
-    }
-    uint32_t total_zeros;
-    uint32_t z = block_exscan(zeros, lds, &total_zeros);
-    uint32_t o = (uint32_t)t * kScanItems - z;  // ones before this thread's items
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-      const bool one = (kk[j] >> (shift + b)) & 1u;
-      const uint32_t pos = one ? total_zeros + o : z;
-      sk[cur ^ 1][pos] = kk[j];
-      sv[cur ^ 1][pos] = vv[j];
-      if (one) ++o; else ++z;
-    }
-    cur ^= 1;
-    __syncthreads();
-  }
-  // first local position of each digit, from the tile's sorted keys
-  dstart[t] = 0xFFFFFFFFu;
-  __syncthreads();
-  for (int k = t; k < cnt; k += kScanBlock) {
-    const uint32_t d = (sk[cur][k] >> shift) & 0xFFu;
-    if (k == 0 || ((sk[cur][k - 1] >> shift) & 0xFFu) != d) dstart[d] = (uint32_t)k;
-  }
-  __syncthreads();
-  for (int k = t; k < cnt; k += kScanBlock) {
-    const uint32_t key = sk[cur][k];
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t i = base + (int64_t)r * kScanBlock + t;
+    const bool ok = i < n;
+    const uint32_t key = ok ? kin[i] : 0u, val = ok ? vin[i] : 0u;
     const uint32_t d = (key >> shift) & 0xFFu;
-    const uint32_t pos = start[(int64_t)d * tiles + blockIdx.x] + ((uint32_t)k - dstart[d]);
-    kout[pos] = key;
-    vout[pos] = sv[cur][k];
+    // the lanes of this wave holding a pair of the same digit
+    unsigned long long m = __ballot(ok);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const unsigned long long bb = __ballot((d >> bit) & 1u);
+      m &= ((d >> bit) & 1u) ? bb : ~bb;
+    }
+    const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (ok && before == 0) wc[w][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (ok) {
+      uint32_t pos = run[d] + before;
+      for (int w2 = 0; w2 < w; ++w2) pos += wc[w2][d];
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    // thread t advances digit t's running count and clears its wave counts
+    run[t] += (wc[0][t] + wc[1][t]) + (wc[2][t] + wc[3][t]);
+    wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0u;
+    __syncthreads();
   }
 }
 

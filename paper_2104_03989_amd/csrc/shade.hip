@@ -1163,38 +1163,120 @@ __global__ __launch_bounds__(256) void k_tex_det_emit(TexDetArgs a, uint32_t* __
   }
 }
 
-// Pieces of groups within each tile of 2048 sorted entries.  A piece that is
-// a whole group stores its corner sums at its first position; part[2 tile]
-// receives the sums of the tile's first piece when its group began in an
-// earlier tile, part[2 tile + 1] those of its last piece when its group
-// began in this tile and goes on into the next one (3 float4 each).
+// Pieces of groups within each tile of 2048 sorted entries.  Each thread
+// takes 8 consecutive entries (their value gathers issued together) and sums
+// the runs of equal keys among them in order; a group whose entries all lie
+// in one thread is stored at its first position.  A group that crosses
+// threads is summed by the thread it starts in: its own run, then the first
+// run of each following thread, in thread order.  part[2 tile] receives the
+// sums of the tile's first piece when its group began in an earlier tile,
+// part[2 tile + 1] those of its last piece when its group began in this tile
+// and goes on into the next one (3 float4 each).
 constexpr int kDetTile = 2048;
+constexpr int kDetRun = kDetTile / 256;  // entries per thread
 
 __global__ __launch_bounds__(256) void k_tex_det_pieces(TexDetArgs a, const uint32_t* __restrict__ sk,
                                                         const uint32_t* __restrict__ si,
                                                         const float4* __restrict__ vals,
                                                         const float* __restrict__ vfy,
                                                         float4* __restrict__ gsum, float4* __restrict__ part) {
+  __shared__ float first_run[256][13];  // a thread's first run, when it continues an earlier thread's group
+  __shared__ float last_run[256][13];   // a thread's last run, when its group starts there and goes on
+  __shared__ int first_ends[256];       // first run: -1 none, 1 the group ends in this thread, 0 it goes on
+  const int t = threadIdx.x;
   const int64_t tb0 = (int64_t)blockIdx.x * kDetTile;
   const int64_t te = min(tb0 + kDetTile, a.E);
   const uint32_t none = a.base[a.tb.n];
-  for (int64_t i = tb0 + threadIdx.x; i < te; i += blockDim.x) {
-    const uint32_t key = sk[i];
-    if (key >= none) continue;
-    if (i > tb0 && sk[i - 1] == key) continue;  // not the start of a piece
-    Corners c;
+  const int64_t p0 = tb0 + (int64_t)kDetRun * t;
+  uint32_t key[kDetRun], ix[kDetRun];
 #pragma unroll
-    for (int q = 0; q < 12; ++q) c.v[q] = 0.f;
-    int64_t j = i;
-    for (; j < te && sk[j] == key; ++j) {
-      const uint32_t e = si[j];
-      corners_add(c, vals[e], vfy[e]);
+  for (int j = 0; j < kDetRun; ++j) {
+    const int64_t q = p0 + j;
+    key[j] = q < te ? sk[q] : none;
+    ix[j] = q < te ? si[q] : 0u;
+  }
+  float4 v[kDetRun];
+  float fy[kDetRun];
+#pragma unroll
+  for (int j = 0; j < kDetRun; ++j) {
+    const bool on = key[j] < none;
+    v[j] = on ? vals[ix[j]] : make_float4(0.f, 0.f, 0.f, 0.f);
+    fy[j] = on ? vfy[ix[j]] : 0.f;
+  }
+  // the keys just before and just after this thread's entries
+  const uint32_t kbefore = p0 > 0 && p0 < te ? sk[p0 - 1] : none;
+  const uint32_t kafter = p0 + kDetRun < a.E ? sk[p0 + kDetRun] : none;
+  Corners c;
+#pragma unroll
+  for (int q = 0; q < 12; ++q) c.v[q] = 0.f;
+  int64_t run0 = p0;       // first position of the current run
+  bool first = true;       // the current run is this thread's first
+  bool open = false;       // a run is being summed
+  int fend = -1;
+#pragma unroll
+  for (int j = 0; j < kDetRun; ++j) {
+    if (key[j] < none) {
+      corners_add(c, v[j], fy[j]);
+      open = true;
+      const uint32_t knext = j + 1 < kDetRun ? key[j + 1] : kafter;
+      if (knext != key[j]) {  // the run ends here, and so does its group
+        if (first && key[0] == kbefore) {
+#pragma unroll
+          for (int q = 0; q < 12; ++q) first_run[t][q] = c.v[q];
+          fend = 1;
+        } else {
+          corners_store(gsum + 3 * run0, c);
+        }
+#pragma unroll
+        for (int q = 0; q < 12; ++q) c.v[q] = 0.f;
+        first = false;
+        open = false;
+        run0 = p0 + j + 1;
+      }
     }
-    const bool from_prev = i == tb0 && i > 0 && sk[i - 1] == key;
-    const bool into_next = j == te && te < a.E && sk[te] == key;
-    if (from_prev) corners_store(part + 3 * (2 * blockIdx.x), c);
-    else if (into_next) corners_store(part + 3 * (2 * blockIdx.x + 1), c);
-    else corners_store(gsum + 3 * i, c);
+  }
+  bool owner = false;  // a group that starts here goes on into the next thread
+  if (open) {
+    if (first && key[0] == kbefore) {
+      // every entry of this thread continues an earlier group, which goes on
+#pragma unroll
+      for (int q = 0; q < 12; ++q) first_run[t][q] = c.v[q];
+      fend = 0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) last_run[t][q] = c.v[q];
+      owner = true;
+    }
+  }
+  first_ends[t] = fend;
+  __syncthreads();
+  // the tile's first piece, when its group began in an earlier tile: thread 0
+  // adds the continuing first runs in thread order
+  if (t == 0 && fend >= 0) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) c.v[q] = first_run[0][q];
+    bool ended = fend == 1;
+    for (int u = 1; !ended && u < 256; ++u) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) c.v[q] += first_run[u][q];
+      ended = first_ends[u] == 1;
+    }
+    corners_store(part + 3 * (2 * blockIdx.x), c);
+  }
+  // a group that starts in this thread and goes on: its runs in thread
+  // order, stored at its first position, or as the tile's last piece when it
+  // goes on into the next tile
+  if (owner) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) c.v[q] = last_run[t][q];
+    bool ended = false;
+    for (int u = t + 1; !ended && u < 256; ++u) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) c.v[q] += first_run[u][q];
+      ended = first_ends[u] == 1;
+    }
+    if (ended) corners_store(gsum + 3 * run0, c);
+    else corners_store(part + 3 * (2 * blockIdx.x + 1), c);
   }
 }
 
