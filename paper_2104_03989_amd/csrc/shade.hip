@@ -763,11 +763,13 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   // the barycentrics and corner indices parked after the set-up
   float lam[3];
   int vid[3], tid[3];
+  int tri_o = tri;  // opaque, as the pixel below: no address kept live from the set-up
+  asm volatile("" : "+v"(tri_o));
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     lam[c] = col[(kParkLam + c) * kAccStride];
     vid[c] = __float_as_int(col[(kParkLam + 3 + c) * kAccStride]);
-    tid[c] = a.m.uv_tri[3 * tri + c];
+    tid[c] = a.m.uv_tri[3 * tri_o + c];
   }
   float glam[3], glx[3], gly[3];
   f3 P0 = ld3(a.m.pos, vid[0]), N0 = ld3(a.nrm, vid[0]), T0 = ld3(a.tan, vid[0]);
@@ -790,7 +792,11 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
   // barycentrics (float64, like the forward set-up):
   // lambda_c = D_c / S, lx_c = (a_c - lambda_c A) / S * sx, ly_c likewise
   BaryD d;
-  bary_setup(a.m, a.v, p.b, p.i, p.j, vid, d);
+  // the pixel made opaque to the compiler, which would otherwise keep the
+  // set-up's pixel centre live from the first set-up to this one
+  int pi = p.i, pj = p.j;
+  asm volatile("" : "+v"(pi), "+v"(pj));
+  bary_setup(a.m, a.v, p.b, pi, pj, vid, d);
   double iS = 1.0 / d.S;
   double A = d.a[0] + d.a[1] + d.a[2];
   double Bs = d.b[0] + d.b[1] + d.b[2];
