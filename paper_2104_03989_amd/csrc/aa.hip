@@ -42,56 +42,99 @@ __device__ __forceinline__ void rel_proj(double4 c, double iw, double Xx, double
   out[1] = (c.y - c.w * Xy) * iw;
 }
 
-__device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi, int Pj, int Qi,
-                                           int Qj, Cross& x) {
+// The front triangle F of a pair as read from memory: its vertex indices and
+// their snapped coordinates in this view, its orientation and, for each
+// vertex c, the orientation of the neighbour across the edge opposite c (2,
+// which no orientation takes, where there is none).
+struct Front {
+  int v[3];
+  int2 s[3];
+  int of, on[3];
+};
+// The accesses that depend on F only, then those that depend on them.
+__device__ __forceinline__ void front_ids(const AAArgs& a, int b, int F, Front& f, int nb[3]) {
   const int* tri = a.m.tri + 3 * F;
-  int v[3] = {tri[0], tri[1], tri[2]};
-  const int4* sv = a.snap + (int64_t)b * a.m.n_pos;
-  int4 s0 = sv[v[0]], s1 = sv[v[1]], s2 = sv[v[2]];
-  int64_t A = (int64_t)(s1.x - s0.x) * (s2.y - s0.y) - (int64_t)(s1.y - s0.y) * (s2.x - s0.x);
-  int vid[3] = {0, 1, 2};
-  int X[3] = {s0.x, s1.x, s2.x}, Y[3] = {s0.y, s1.y, s2.y};
-  if (A < 0) {
-    vid[1] = 2; vid[2] = 1;
-    X[1] = s2.x; X[2] = s1.x;
-    Y[1] = s2.y; Y[2] = s1.y;
+  const int* adj = a.m.adj + 3 * F;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    f.v[c] = tri[c];
+    nb[c] = adj[c];
   }
-  int64_t qx = 256 * (int64_t)Qi + 128, qy = 256 * (int64_t)Qj + 128;
-  int8_t of = a.orient[(int64_t)b * a.m.n_tri + F];
+  f.of = a.orient[(int64_t)b * a.m.n_tri + F];
+}
+__device__ __forceinline__ void front_coords(const AAArgs& a, int b, const int nb[3], Front& f) {
+  const int2* sv = reinterpret_cast<const int2*>(a.snap + (int64_t)b * a.m.n_pos);
+  const int8_t* ov = a.orient + (int64_t)b * a.m.n_tri;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    f.s[c] = sv[2 * f.v[c]];
+    f.on[c] = nb[c] < 0 ? 2 : (int)ov[nb[c]];
+  }
+}
+
+// Among F's edges 0, 1, 2 (counter-clockwise order) the first one that pixel
+// (Qi, Qj) lies outside of and that is a silhouette edge: its vertices a -> b
+// with F on the left, or false.
+__device__ __forceinline__ bool cross_edge(const Front& f, int Qi, int Qj, int& va, int& vb) {
+  const int64_t A = (int64_t)(f.s[1].x - f.s[0].x) * (f.s[2].y - f.s[0].y) -
+                    (int64_t)(f.s[1].y - f.s[0].y) * (f.s[2].x - f.s[0].x);
+  // vertices 1 and 2 exchanged for a clockwise F (the edge opposite a vertex
+  // goes with it); every index below is then a constant
+  const bool sw = A < 0;
+  const int V[3] = {f.v[0], sw ? f.v[2] : f.v[1], sw ? f.v[1] : f.v[2]};
+  const int O[3] = {f.on[0], sw ? f.on[2] : f.on[1], sw ? f.on[1] : f.on[2]};
+  const int X[3] = {f.s[0].x, sw ? f.s[2].x : f.s[1].x, sw ? f.s[1].x : f.s[2].x};
+  const int Y[3] = {f.s[0].y, sw ? f.s[2].y : f.s[1].y, sw ? f.s[1].y : f.s[2].y};
+  const int64_t qx = 256 * (int64_t)Qi + 128, qy = 256 * (int64_t)Qj + 128;
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
-    int j = k == 2 ? 0 : k + 1, l = k == 0 ? 2 : k - 1;
-    int64_t dx = (int64_t)X[l] - X[j], dy = (int64_t)Y[l] - Y[j];
-    int64_t e = dx * (qy - Y[j]) - dy * (qx - X[j]);
-    bool tl = dy < 0 || (dy == 0 && dx < 0);
-    bool inside = e > 0 || (e == 0 && tl);
+    const int j = k == 2 ? 0 : k + 1, l = k == 0 ? 2 : k - 1;
+    const int64_t dx = (int64_t)X[l] - X[j], dy = (int64_t)Y[l] - Y[j];
+    const int64_t e = dx * (qy - Y[j]) - dy * (qx - X[j]);
+    const bool tl = dy < 0 || (dy == 0 && dx < 0);
+    const bool inside = e > 0 || (e == 0 && tl);
     if (inside) continue;
-    int nb = a.m.adj[3 * F + vid[k]];
-    bool sil = nb < 0 || a.orient[(int64_t)b * a.m.n_tri + nb] != of;
-    if (!sil) continue;
-    x.va = v[vid[j]];
-    x.vb = v[vid[l]];
-    double4 ca = clip_d(a.m.pos, a.v.mvpd, b, x.va);
-    double4 cb = clip_d(a.m.pos, a.v.mvpd, b, x.vb);
-    double Px = ((double)Pi + 0.5) * a.v.sxs - 1.0;
-    double Py = ((double)Pj + 0.5) * a.v.sys - 1.0;
-    double Qx = ((double)Qi + 0.5) * a.v.sxs - 1.0;
-    double Qy = ((double)Qj + 0.5) * a.v.sys - 1.0;
-    // e(X) = (b - a) x (X - a) = a' x b' with a' = a - X, b' = b - X
-    const double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
-    rel_proj(ca, iwa, Px, Py, x.aP);
-    rel_proj(cb, iwb, Px, Py, x.bP);
-    rel_proj(ca, iwa, Qx, Qy, x.aQ);
-    rel_proj(cb, iwb, Qx, Qy, x.bQ);
-    x.eP = x.aP[0] * x.bP[1] - x.aP[1] * x.bP[0];
-    x.eQ = x.aQ[0] * x.bQ[1] - x.aQ[1] * x.bQ[0];
-    x.den = x.eP - x.eQ;
-    if (x.den == 0.0) return false;
-    double s = x.eP / x.den;
-    x.clamped = !(s >= 0.0 && s <= 1.0);
-    x.s = (float)fmin(fmax(s, 0.0), 1.0);
+    if (O[k] == f.of) continue;  // both sides face the same way: no silhouette
+    va = V[j];
+    vb = V[l];
     return true;
   }
   return false;
+}
+
+// The crossing parameter of pair (P, Q) on the projected edge with clip
+// coordinates ca -> cb; false if the edge is parallel to the pair.
+__device__ __forceinline__ bool cross_param(const AAArgs& a, double4 ca, double4 cb, int Pi, int Pj, int Qi,
+                                            int Qj, Cross& x) {
+  const double Px = ((double)Pi + 0.5) * a.v.sxs - 1.0;
+  const double Py = ((double)Pj + 0.5) * a.v.sys - 1.0;
+  const double Qx = ((double)Qi + 0.5) * a.v.sxs - 1.0;
+  const double Qy = ((double)Qj + 0.5) * a.v.sys - 1.0;
+  // e(X) = (b - a) x (X - a) = a' x b' with a' = a - X, b' = b - X
+  const double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
+  rel_proj(ca, iwa, Px, Py, x.aP);
+  rel_proj(cb, iwb, Px, Py, x.bP);
+  rel_proj(ca, iwa, Qx, Qy, x.aQ);
+  rel_proj(cb, iwb, Qx, Qy, x.bQ);
+  x.eP = x.aP[0] * x.bP[1] - x.aP[1] * x.bP[0];
+  x.eQ = x.aQ[0] * x.bQ[1] - x.aQ[1] * x.bQ[0];
+  x.den = x.eP - x.eQ;
+  if (x.den == 0.0) return false;
+  const double s = x.eP / x.den;
+  x.clamped = !(s >= 0.0 && s <= 1.0);
+  x.s = (float)fmin(fmax(s, 0.0), 1.0);
+  return true;
+}
+
+__device__ __forceinline__ bool find_cross(const AAArgs& a, int b, int F, int Pi, int Pj, int Qi, int Qj,
+                                           Cross& x) {
+  Front f;
+  int nb[3];
+  front_ids(a, b, F, f, nb);
+  front_coords(a, b, nb, f);
+  if (!cross_edge(f, Qi, Qj, x.va, x.vb)) return false;
+  return cross_param(a, clip_d(a.m.pos, a.v.mvpd, b, x.va), clip_d(a.m.pos, a.v.mvpd, b, x.vb), Pi, Pj, Qi,
+                     Qj, x);
 }
 
 // A pair's code: -1 if it does not blend, else its crossing parameter s in
@@ -316,37 +359,79 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
   const uint64_t ku = aa_on && p.j + 1 < a.v.H ? a.vis[o + a.v.W] : k;
   const f3 c = p.ok ? ldc(a.color, o) : mk(0.f, 0.f, 0.f);
   const f3 rv = p.ok && ref ? ldc(ref, o) : mk(0.f, 0.f, 0.f);
+  // the pair that links the tile to its left (threads 0..15) or lower
+  // (16..31) neighbour tile: its left (lower) pixel and that pixel's
+  // neighbour, with their keys loaded up front as well
+  const bool edge_thread = !a.no_aa && threadIdx.x < 32;  // whether or not its own pixel is inside
+  const bool left = threadIdx.x < 16;
+  const int er = threadIdx.x & 15;
+  const int ei = left ? x0 - 1 : x0 + er, ej = left ? y0 + er : y0 - 1;
+  const int eni = left ? ei + 1 : ei, enj = left ? ej : ej + 1;
+  const bool e_ok = edge_thread && ei >= 0 && ej >= 0 && eni < a.v.W && enj < a.v.H;
+  const uint64_t ke = e_ok ? a.vis[base + (int64_t)ej * a.v.W + ei] : 0ull;
+  const uint64_t ken = e_ok ? a.vis[base + (int64_t)enj * a.v.W + eni] : 0ull;
   if (!a.no_aa) {
-    float code[2] = {-1.f, -1.f};
-    if (p.ok) {
+    // A thread's pairs (with its right and its upper neighbour, and the
+    // linking pair above) go through their memory accesses together, one
+    // stage after the other, so that their latencies overlap: the front
+    // triangle, its vertices and neighbours, the crossing edge, the edge's
+    // positions.  PI, PJ is the front pixel P, QI, QJ the other one, F = -1
+    // for a pair that does not blend.
+    int PI[3], PJ[3], QI[3], QJ[3], F[3];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int ni = p.i + (q == 0 ? 1 : 0), nj = p.j + (q == 1 ? 1 : 0);
-        Pair pr;
-        if (eval_pair(a, p.b, p.i, p.j, k, ni, nj, q == 0 ? kr : ku, pr)) code[q] = pair_code(pr.x);
+    for (int q = 0; q < 3; ++q) {
+      const int si = q < 2 ? p.i : ei, sj = q < 2 ? p.j : ej;
+      const int ni = q == 0 ? p.i + 1 : (q == 1 ? p.i : eni), nj = q == 0 ? p.j : (q == 1 ? p.j + 1 : enj);
+      const uint64_t ks = q < 2 ? k : ke, kn = q == 0 ? kr : (q == 1 ? ku : ken);
+      const bool on = (q < 2 ? aa_on : e_ok) && (uint32_t)ks != (uint32_t)kn;
+      const bool selfP = ks < kn;
+      F[q] = on ? (int)(uint32_t)(selfP ? ks : kn) - 1 : -1;
+      PI[q] = selfP ? si : ni;
+      PJ[q] = selfP ? sj : nj;
+      QI[q] = selfP ? ni : si;
+      QJ[q] = selfP ? nj : sj;
+    }
+    Front fr[3];
+    int nb[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (F[q] >= 0) front_ids(a, p.b, F[q], fr[q], nb[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (F[q] >= 0) front_coords(a, p.b, nb[q], fr[q]);
+    int va[3], vb[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (F[q] >= 0 && !cross_edge(fr[q], QI[q], QJ[q], va[q], vb[q])) F[q] = -1;
+    float pa[3][3], pb[3][3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (F[q] >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pa[q][c] = a.m.pos[3 * va[q] + c];
+          pb[q][c] = a.m.pos[3 * vb[q] + c];
+        }
       }
-      if (a.stats) {
-        a.codes[a.code_stride * o] = code[0];
-        a.codes[a.code_stride * o + 1] = code[1];
-      }
+    float code[3];
+    const double* M = a.v.mvpd + 16 * p.b;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      code[q] = -1.f;
+      Cross x;
+      if (F[q] >= 0 && cross_param(a, clip_from(M, pa[q][0], pa[q][1], pa[q][2]),
+                                   clip_from(M, pb[q][0], pb[q][1], pb[q][2]), PI[q], PJ[q], QI[q], QJ[q], x))
+        code[q] = pair_code(x);
+    }
+    if (p.ok && a.stats) {
+      a.codes[a.code_stride * o] = code[0];
+      a.codes[a.code_stride * o + 1] = code[1];
     }
     hc[ly][lx + 1] = code[0];
     vc[ly + 1][lx] = code[1];
     if (threadIdx.x < 32) {
-      // the pair's left (lower) pixel (i, j) and its neighbour (ni, nj)
-      const bool left = threadIdx.x < 16;
-      const int r = threadIdx.x & 15;
-      const int i = left ? x0 - 1 : x0 + r, j = left ? y0 + r : y0 - 1;
-      const int ni = left ? i + 1 : i, nj = left ? j : j + 1;
-      float hcode = -1.f;
-      if (i >= 0 && j >= 0 && ni < a.v.W && nj < a.v.H) {
-        Pair pr;
-        if (eval_pair(a, p.b, i, j, a.vis[base + (int64_t)j * a.v.W + i], ni, nj,
-                      a.vis[base + (int64_t)nj * a.v.W + ni], pr))
-          hcode = pair_code(pr.x);
-      }
-      if (left) hc[r][0] = hcode;
-      else vc[0][r] = hcode;
+      if (left) hc[er][0] = code[2];
+      else vc[0][er] = code[2];
     }
     __syncthreads();
   }
@@ -385,9 +470,9 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
     if (threadIdx.x == 0) f.partial[bid] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
-// (7 waves per SIMD, 72 VGPRs and 48 bytes of spills: the compiler's own choice, 93 VGPRs, gives 5:
-// 0.120 -> 0.112 ms per step for the two renders of the paper loop; more spills cost far more)
-ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
+// (5 waves per SIMD, 96 VGPRs: the three pairs' loads in flight together need the registers; at 6 or 7
+// waves the spills double the time)
+ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
 
 __device__ __forceinline__ void loss_reduce_body(const LossReduceArgs& a, int, int) {
   __shared__ double red[256];

@@ -376,15 +376,16 @@ __device__ __forceinline__ float adam1(float& p, float g, float& m, float& v, fl
 // the sums round the same way whether or not a multiply is fused with them.
 // Recomputed where needed (3 vertices per pixel) instead of gathered from a
 // [views, vertices] float64 array.
-__device__ __forceinline__ double4 clip_d(const float* __restrict__ pos, const double* __restrict__ mvpd, int b,
-                                          int vi) {
-  const double* M = mvpd + 16 * b;
-  const double px = pos[3 * vi], py = pos[3 * vi + 1], pz = pos[3 * vi + 2];
+__device__ __forceinline__ double4 clip_from(const double* __restrict__ M, double px, double py, double pz) {
   double d[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     d[r] = ((M[4 * r] * px + M[4 * r + 1] * py) + M[4 * r + 2] * pz) + M[4 * r + 3];
   return make_double4(d[0], d[1], d[2], d[3]);
+}
+__device__ __forceinline__ double4 clip_d(const float* __restrict__ pos, const double* __restrict__ mvpd, int b,
+                                          int vi) {
+  return clip_from(mvpd + 16 * b, pos[3 * vi], pos[3 * vi + 1], pos[3 * vi + 2]);
 }
 
 }  // namespace adr
