@@ -513,80 +513,136 @@ __device__ __forceinline__ void aa_bwd_body(const AABwdArgs& b, int bid, int nb)
     // the keys of the pixel and of its four neighbours, loaded together (a
     // missing neighbour takes the pixel's own key, which pairs with nothing)
     const uint64_t k = a.vis[o];
-    const uint64_t kl = p.i > 0 ? a.vis[o - 1] : k, kr = p.i + 1 < a.v.W ? a.vis[o + 1] : k;
-    const uint64_t kd = p.j > 0 ? a.vis[o - a.v.W] : k, ku = p.j + 1 < a.v.H ? a.vis[o + a.v.W] : k;
-    f3 c = ldc(a.color, o);
-    Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
-    float Ms = fmaxf(rs.W, 1.0f);
-    gc = (1.0f - rs.W / Ms) * gself;
+    const uint64_t kn[4] = {p.i > 0 ? a.vis[o - 1] : k, p.i + 1 < a.v.W ? a.vis[o + 1] : k,
+                            p.j > 0 ? a.vis[o - a.v.W] : k, p.j + 1 < a.v.H ? a.vis[o + a.v.W] : k};
+    const f3 c = ldc(a.color, o);
+    const Recv rs = a.stats ? recv_load(a.stats, o) : recv_stats(a, p.b, p.i, p.j);
     const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+    // The four pairs go through their memory accesses together, one stage
+    // after the other: their codes (from the forward, else the pairs
+    // re-evaluated), then the neighbours' colours, gradients and sums for the
+    // pairs that blend, then the edges of the two pairs this pixel owns.
+    float cq[4];
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint64_t kn = q == 0 ? kl : (q == 1 ? kr : (q == 2 ? kd : ku));
-      if ((uint32_t)k == (uint32_t)kn) continue;
-      int ni = p.i + di[q], nj = p.j + dj[q];
-      int64_t on = base + (int64_t)nj * a.v.W + ni;
-      Pair pr;
-      bool owner = q == 1 || q == 3;  // right and upper neighbours: this pixel is the lower/left one
-      float s;
+      cq[q] = -1.f;
+      if ((uint32_t)k == (uint32_t)kn[q]) continue;
       if (a.codes) {
-        // the pair's code from the forward; the edge itself is only needed
-        // by the owner, for the gradient of s
-        const float c = code_of(a, base, p.i, p.j, q);
-        if (c < 0.f) continue;
-        pr.self_is_P = k < kn;
-        pr.x.clamped = c >= 2.f;
-        s = c >= 2.f ? c - 2.f : c;
-        pr.x.s = s;
+        cq[q] = code_of(a, base, p.i, p.j, q);
       } else {
-        if (!eval_pair(a, p.b, p.i, p.j, k, ni, nj, kn, pr)) continue;
-        s = pr.x.s;
+        Pair pr;
+        if (eval_pair(a, p.b, p.i, p.j, k, p.i + di[q], p.j + dj[q], kn[q], pr)) cq[q] = pair_code(pr.x);
       }
-      if (s == 0.5f) continue;
+    }
+    f3 cn[4], gn[4];
+    Recv rr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float s = cq[q] >= 2.f ? cq[q] - 2.f : cq[q];
+      if (cq[q] < 0.f || s == 0.5f) continue;
+      const int ni = p.i + di[q], nj = p.j + dj[q];
+      const int64_t on = base + (int64_t)nj * a.v.W + ni;
+      cn[q] = ldc(a.color, on);
+      gn[q] = sample_grad(a, dimage, p.b, ni, nj);
+      const bool selfP = k < kn[q];
+      const bool self_recv = s > 0.5f ? !selfP : selfP;
+      rr[q] = self_recv ? rs : (a.stats ? recv_load(a.stats, on) : recv_stats(a, p.b, ni, nj));
+    }
+    const float Ms = fmaxf(rs.W, 1.0f);
+    gc = (1.0f - rs.W / Ms) * gself;
+    float gs_own[2] = {0.f, 0.f};  // dL/ds of the pairs with the right and the upper neighbour
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float cc = cq[q];
+      const float s = cc >= 2.f ? cc - 2.f : cc;
+      if (cc < 0.f || s == 0.5f) continue;
       // the receiver is Q for s > 1/2 (w = s - 1/2) and P for s < 1/2 (w = 1/2 - s)
-      bool recv_Q = s > 0.5f;
-      bool self_recv = recv_Q ? !pr.self_is_P : pr.self_is_P;
-      float w = recv_Q ? s - 0.5f : 0.5f - s;
-      f3 cn = ldc(a.color, on);
-      f3 gn = scale * sample_grad(a, dimage, p.b, ni, nj);
-      Recv rr = self_recv ? rs : (a.stats ? recv_load(a.stats, on) : recv_stats(a, p.b, ni, nj));
-      float Mr = fmaxf(rr.W, 1.0f);
-      f3 g_r = self_recv ? gself : gn;          // dL/d out(receiver)
-      f3 c_r = self_recv ? c : cn, c_src = self_recv ? cn : c;
-      if (!self_recv) gc += (w / Mr) * gn;      // this pixel is the source
+      const bool selfP = k < kn[q];
+      const bool recv_Q = s > 0.5f;
+      const bool self_recv = recv_Q ? !selfP : selfP;
+      const float w = recv_Q ? s - 0.5f : 0.5f - s;
+      const f3 gnq = scale * gn[q];
+      const float Mr = fmaxf(rr[q].W, 1.0f);
+      const f3 g_r = self_recv ? gself : gnq;   // dL/d out(receiver)
+      const f3 c_r = self_recv ? c : cn[q], c_src = self_recv ? cn[q] : c;
+      if (!self_recv) gc += (w / Mr) * gnq;     // this pixel is the source
       f3 dw = (1.0f / Mr) * (c_src - c_r);
-      if (rr.W > 1.0f) dw -= (1.0f / (rr.W * rr.W)) * rr.acc;
-      float g_w = dot(g_r, dw);
-      float g_s = recv_Q ? g_w : -g_w;
-      if (!owner || pr.x.clamped || g_s == 0.f) continue;
-      if (a.codes && !eval_pair(a, p.b, p.i, p.j, k, ni, nj, kn, pr)) continue;  // the edge (same s)
-      // s = eP / (eP - eQ)
-      double id2 = 1.0 / (pr.x.den * pr.x.den);
-      double g_eP = -g_s * pr.x.eQ * id2, g_eQ = g_s * pr.x.eP * id2;
-      double4 ca = clip_d(a.m.pos, a.v.mvpd, p.b, pr.x.va);
-      double4 cb = clip_d(a.m.pos, a.v.mvpd, p.b, pr.x.vb);
-      double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
-      double ax = ca.x * iwa, ay = ca.y * iwa, bx = cb.x * iwb, by = cb.y * iwb;
+      if (rr[q].W > 1.0f) dw -= (1.0f / (rr[q].W * rr[q].W)) * rr[q].acc;
+      const float g_w = dot(g_r, dw);
+      // s is taken from the edge only where it was not clamped
+      if ((q == 1 || q == 3) && cc < 2.f) gs_own[q >> 1] = recv_Q ? g_w : -g_w;
+    }
+    // the gradient of s = eP / (eP - eQ) w.r.t. the clip coordinates of the
+    // crossing edge of each pair this pixel owns (its edge found again, the
+    // same s as the forward's)
+    int F[2], PI[2], PJ[2], QI[2], QJ[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int q = 2 * t + 1, ni = p.i + di[q], nj = p.j + dj[q];
+      const bool selfP = k < kn[q];
+      F[t] = gs_own[t] != 0.f ? (int)(uint32_t)(selfP ? k : kn[q]) - 1 : -1;
+      PI[t] = selfP ? p.i : ni;
+      PJ[t] = selfP ? p.j : nj;
+      QI[t] = selfP ? ni : p.i;
+      QJ[t] = selfP ? nj : p.j;
+    }
+    Front fr[2];
+    int nbr[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      if (F[t] >= 0) front_ids(a, p.b, F[t], fr[t], nbr[t]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      if (F[t] >= 0) front_coords(a, p.b, nbr[t], fr[t]);
+    int va[2], vb[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      if (F[t] >= 0 && !cross_edge(fr[t], QI[t], QJ[t], va[t], vb[t])) F[t] = -1;
+    float pa[2][3], pb[2][3];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      if (F[t] >= 0) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          pa[t][cc] = a.m.pos[3 * va[t] + cc];
+          pb[t][cc] = a.m.pos[3 * vb[t] + cc];
+        }
+      }
+    const double* M = a.v.mvpd + 16 * p.b;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (F[t] < 0) continue;
+      const double4 ca = clip_from(M, pa[t][0], pa[t][1], pa[t][2]);
+      const double4 cb = clip_from(M, pb[t][0], pb[t][1], pb[t][2]);
+      Cross x;
+      if (!cross_param(a, ca, cb, PI[t], PJ[t], QI[t], QJ[t], x)) continue;
+      const double g_s = gs_own[t];
+      const double id2 = 1.0 / (x.den * x.den);
+      const double g_eP = -g_s * x.eQ * id2, g_eQ = g_s * x.eP * id2;
+      const double iwa = 1.0 / ca.w, iwb = 1.0 / cb.w;
+      const double ax = ca.x * iwa, ay = ca.y * iwa, bx = cb.x * iwb, by = cb.y * iwb;
       // e(X) = a'_x b'_y - a'_y b'_x, a' = a - X, b' = b - X
-      double g_ax = g_eP * pr.x.bP[1] + g_eQ * pr.x.bQ[1];
-      double g_ay = -g_eP * pr.x.bP[0] - g_eQ * pr.x.bQ[0];
-      double g_bx = -g_eP * pr.x.aP[1] - g_eQ * pr.x.aQ[1];
-      double g_by = g_eP * pr.x.aP[0] + g_eQ * pr.x.aQ[0];
-      const int64_t oa = 4 * ((int64_t)p.b * a.m.n_pos + pr.x.va);
-      const int64_t ob = 4 * ((int64_t)p.b * a.m.n_pos + pr.x.vb);
+      const double g_ax = g_eP * x.bP[1] + g_eQ * x.bQ[1];
+      const double g_ay = -g_eP * x.bP[0] - g_eQ * x.bQ[0];
+      const double g_bx = -g_eP * x.aP[1] - g_eQ * x.aQ[1];
+      const double g_by = g_eP * x.aP[0] + g_eQ * x.aQ[0];
+      const int64_t oa = 4 * ((int64_t)p.b * a.m.n_pos + va[t]);
+      const int64_t ob = 4 * ((int64_t)p.b * a.m.n_pos + vb[t]);
       const double ga[3] = {g_ax * iwa, g_ay * iwa, -(g_ax * ax + g_ay * ay) * iwa};
       const double gb[3] = {g_bx * iwb, g_by * iwb, -(g_bx * bx + g_by * by) * iwb};
       const int comp[3] = {0, 1, 3};
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        acc_add(fclip + oa + comp[k], ga[k], det);
-        acc_add(fclip + ob + comp[k], gb[k], det);
+      for (int m = 0; m < 3; ++m) {
+        acc_add(fclip + oa + comp[m], ga[m], det);
+        acc_add(fclip + ob + comp[m], gb[m], det);
       }
     }
   }
   st3(b.gcolor, o, gc);
 }
-// (3 waves per SIMD: the compiler's own choice, 170 VGPRs, drops to 2)
-ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))), k_aa_bwd, AABwdArgs, aa_bwd_body)
+// (4 waves per SIMD, 128 VGPRs and 24 bytes of spills: 0.051 ms per step on the paper loop at 3 waves,
+// 0.047 at 4; at 5 the spills double it)
+ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))), k_aa_bwd, AABwdArgs, aa_bwd_body)
 
 // stats: the caller's buffer of 8 floats per pixel, two planes: the pixels'
 // (W, acc) float4s, then their pair codes (2 floats each); without it the
