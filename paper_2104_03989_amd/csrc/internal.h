@@ -264,6 +264,7 @@ struct TexBwdArgs {
   Tex t[4];
   float* g[4];
   int n;
+  int pair;   // slots 0 and 1 are 3-channel maps of one size and layout: one window serves both
   const float4* rec;
   ViewsD v;
   int tiles_x, tiles_y;

@@ -550,6 +550,127 @@ __device__ void wave_scatter_tex(const Tex& t, float* __restrict__ gtex, bool ac
   }
 }
 
+// The same for two 3-channel maps A and B of one size and layout whose
+// lookups share level and weights: window entry (texel, c) holds channel c
+// of A for c < 3 and channel c - 3 of B otherwise, and each map keeps a
+// fixed-point scale of its own (from its own largest contribution), so each
+// sum is what the map's own pass would give.
+__device__ __forceinline__ void window_pass2(const Tex& t, float* __restrict__ ga, float* __restrict__ gb,
+                                             WinT* win, bool sel, const Foot& q, float wl, const float (&gsa)[3],
+                                             const float (&gsb)[3], int off, int rmin, int rmax, int cmin,
+                                             int cmax) {
+  const int lane = threadIdx.x & 63;
+  const int ww = cmax - cmin + 1;
+  const int n = (rmax - rmin + 1) * ww * 6;
+  const float w[4] = {(1.f - q.fx) * (1.f - q.fy), q.fx * (1.f - q.fy), (1.f - q.fx) * q.fy, q.fx * q.fy};
+  float va[12], vb[12];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float wk = sel ? wl * w[k] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      va[3 * k + c] = wk * gsa[c];
+      vb[3 * k + c] = wk * gsb[c];
+    }
+  }
+  float amax_a = 0.f, amax_b = 0.f;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    amax_a = fmaxf(amax_a, fabsf(va[i]));
+    amax_b = fmaxf(amax_b, fabsf(vb[i]));
+  }
+  const int mba = wave_max_i(__float_as_int(amax_a)), mbb = wave_max_i(__float_as_int(amax_b));
+  const bool fin_a = mba < 0x7F800000, fin_b = mbb < 0x7F800000;
+  const int ks_a = fin_a ? 22 - (((mba >> 23) & 0xFF) - 126) : 0;
+  const int ks_b = fin_b ? 22 - (((mbb >> 23) & 0xFF) - 126) : 0;
+  wave_sync();
+  if (sel && (mba | mbb) != 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int cell = (((k & 2 ? q.r1 : q.r0) - rmin) * ww + ((k & 1 ? q.c0 + 1 : q.c0) - cmin)) * 6;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        atomicAdd(win + cell + c, fix_of(va[3 * k + c], ks_a, fin_a));
+        atomicAdd(win + cell + 3 + c, fix_of(vb[3 * k + c], ks_b, fin_b));
+      }
+    }
+  }
+  wave_sync();
+  if ((mba | mbb) != 0) {
+    const float inv_ww = 1.0f / (float)ww;
+    for (int k = lane; k < n; k += 64) {
+      const long long sum = (long long)(int)win[k];
+      if (sum != 0) {
+        win[k] = 0u;
+        const int texel = k / 6, c6 = k - texel * 6;
+        const bool is_b = c6 >= 3;
+        const int ch = is_b ? c6 - 3 : c6;
+        const bool fin = is_b ? fin_b : fin_a;
+        const float val = fin ? ldexpf((float)sum, -(is_b ? ks_b : ks_a)) : __int_as_float(0x7FC00000);
+        int rr = (int)((float)texel * inv_ww);
+        int cc = texel - rr * ww;
+        if (cc < 0) {
+          --rr;
+          cc += ww;
+        } else if (cc >= ww) {
+          ++rr;
+          cc -= ww;
+        }
+        int c = cmin + cc;
+        if (c >= q.s) c -= q.s;
+        atomicAdd((is_b ? gb : ga) + (int64_t)(off + (rmin + rr) * q.s + c) * 3 + ch, val);
+      }
+    }
+  }
+  wave_sync();
+}
+
+// wave_scatter_tex for such a pair: one walk over the levels and lane
+// groups for both maps (gsb: the lane's sample gradient of map B).
+__device__ void wave_scatter_tex2(const Tex& t, float* __restrict__ ga, float* __restrict__ gb, bool act,
+                                  const TexScatter& ts, f3 gsb, WinT* win) {
+  const int BIG = 1 << 20;
+  const int side = win_side(6);
+  bool done0 = !act, done1 = !(act && ts.has1);
+  while (true) {
+    int my = min(done0 ? BIG : ts.l0, done1 ? BIG : ts.l0 + 1);
+    int lev = wave_min_i(my);
+    if (lev >= BIG) break;
+    bool use0 = !done0 && ts.l0 == lev;
+    bool use1 = !done1 && ts.l0 + 1 == lev;
+    bool part = use0 || use1;
+    float wl = use0 ? (ts.has1 ? 1.f - ts.f : 1.f) : ts.f;
+    done0 = done0 || use0;
+    done1 = done1 || use1;
+    const Foot q = foot_at(t, lev, ts.u, ts.v, ts.ul, ts.vl);
+    const float gsa_[3] = {ts.gs.x, ts.gs.y, ts.gs.z};
+    const float gsb_[3] = {gsb.x, gsb.y, gsb.z};
+    const int off = t.off[lev];
+    const int rmin = wave_min_i(part ? q.r0 : BIG), rmax = wave_max_i(part ? q.r1 : -1);
+    const int cmin = wave_min_i(part ? q.c0 : BIG), cmax = wave_max_i(part ? q.c0 + 1 : -1);
+    const bool whole = (rmax - rmin + 1) * (cmax - cmin + 1) * 6 <= kWinTex;
+    bool pending = part;
+    unsigned long long left = __ballot(pending);
+    while (left) {
+      bool in = pending;
+      int r0 = rmin, r1 = rmax, c0 = cmin, c1 = cmax;
+      if (!whole) {
+        const int leader = __ffsll((long long)left) - 1;
+        const int br = __builtin_amdgcn_readlane(q.r0, leader) - (side / 2 - 1);
+        const int bc = __builtin_amdgcn_readlane(q.c0, leader) - (side / 2 - 1);
+        in = pending && q.r0 >= br && q.r1 <= br + side - 1 && q.c0 >= bc && q.c0 + 1 <= bc + side - 1;
+        r0 = wave_min_i(in ? q.r0 : BIG);
+        r1 = wave_max_i(in ? q.r1 : -1);
+        c0 = wave_min_i(in ? q.c0 : BIG);
+        c1 = wave_max_i(in ? q.c0 + 1 : -1);
+      }
+      window_pass2(t, ga, gb, win, in, q, wl, gsa_, gsb_, off, r0, r1, c0, c1);
+      pending = pending && !in;
+      left = __ballot(pending);
+    }
+  }
+}
+
 // Per-corner vertex gradients of one pixel: for corner c, acc[12c + 0..8]
 // go to d(world position, normal, tangent) of vertex c and acc[12c + 9..11]
 // to d(clip x, y, w) of vertex c in this view.
@@ -963,12 +1084,26 @@ __device__ __forceinline__ void tex_bwd_body(const TexBwdArgs& a, int bid, int n
   const uint32_t lv = __float_as_uint(r0.z);
   WinT* win = win_all[threadIdx.x >> 6];
   for (int k = threadIdx.x & 63; k < kWinTex; k += 64) win[k] = 0u;
-  for (int k = 0; k < a.n; ++k) {
+  float ul, vl;
+  unpack_lo(r0.w, ul, vl);
+  int k = 0;
+  if (a.pair) {
+    // slots 0 and 1 together where every lane looked both up at the same
+    // level with the same weight (always, for maps of one size)
+    const int l0 = (int)(lv & 0xFFu), l0b = (int)((lv >> 8) & 0xFFu);
+    const bool act = p.ok && l0 != 0xFF, actb = p.ok && l0b != 0xFF;
+    const float4 rk = act ? ld_nt(a.rec + P + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 rb = actb ? ld_nt(a.rec + 2 * P + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (__ballot(act != actb || (act && (l0 != l0b || rk.w != rb.w))) == 0ull) {
+      const TexScatter ts{r0.x, r0.y, ul, vl, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
+      wave_scatter_tex2(a.t[0], a.g[0], a.g[1], act, ts, mk(rb.x, rb.y, rb.z), win);
+      k = 2;
+    }
+  }
+  for (; k < a.n; ++k) {
     const int l0 = (int)((lv >> (8 * k)) & 0xFFu);
     const bool act = p.ok && l0 != 0xFF;
     float4 rk = act ? ld_nt(a.rec + (1 + k) * P + o) : make_float4(0.f, 0.f, 0.f, 0.f);
-    float ul, vl;
-    unpack_lo(r0.w, ul, vl);
     TexScatter ts{r0.x, r0.y, ul, vl, l0, rk.w, rk.w > 0.f, mk(rk.x, rk.y, rk.z)};
     wave_scatter_tex(a.t[k], a.g[k], act, ts, win);
   }
@@ -1030,6 +1165,15 @@ static int make_slots(int model, const Tex& kd, const Tex& nm, const Tex& orm, f
   if (gorm && model == ADR_SHADE_GGX) add(sl.orm, orm, gorm);
   if (gal && al && al->data) add(sl.al, *al, gal);
   tb.n = sl.n;
+  // two maps of one size and level layout are looked up at the same levels
+  // with the same weights (the level depends on the size only), so their
+  // texel gradients can share the scatter's footprint
+  tb.pair = 0;
+  if (tb.n >= 2 && tb.t[0].size == tb.t[1].size && tb.t[0].levels == tb.t[1].levels && tb.t[0].channels == 3 &&
+      tb.t[1].channels == 3) {
+    tb.pair = 1;
+    for (int l = 0; l <= tb.t[0].levels; ++l) tb.pair &= tb.t[0].off[l] == tb.t[1].off[l];
+  }
   return sl.n;
 }
 
