@@ -342,14 +342,27 @@ struct TriSample {
   f3 du, dv;       // d value / d(u, v)
   f3 dl;           // value at level l0 + 1 minus value at l0 (zero without a second level)
 };
-__device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, float ul, float vl,
-                                                   const Lod& L) {
-  Bil b0 = bil_footprint(t, L.l0, u, v, ul, vl);
-  BilVal a = bil_eval(t, b0);
+// The bilinear footprints of a trilinear lookup: level l0, and l0 + 1 when
+// the lookup has it.  They depend on the map's size and level count only, so
+// maps of one size share them.
+struct TriFoot {
+  Bil b0, b1;
+};
+__device__ __forceinline__ TriFoot tri_foot(const Tex& t, float u, float v, float ul, float vl, const Lod& L) {
+  TriFoot F;
+  F.b0 = bil_footprint(t, L.l0, u, v, ul, vl);
+  if (L.has1) F.b1 = bil_footprint(t, L.l0 + 1, u, v, ul, vl);
+  return F;
+}
+__device__ __forceinline__ TriSample tri_eval(const Tex& t, const TriFoot& F, const Lod& L) {
+  // a one-texel map (a constant material channel): every footprint is that
+  // texel, with zero derivatives and no second level -- what the general
+  // path computes, without its arithmetic
+  if (t.size == 1) return TriSample{tex_fetch(t, t.off[0]), mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f), mk(0.f, 0.f, 0.f)};
+  BilVal a = bil_eval(t, F.b0);
   TriSample r{a.val, a.du, a.dv, mk(0.f, 0.f, 0.f)};
   if (L.has1) {
-    Bil b1 = bil_footprint(t, L.l0 + 1, u, v, ul, vl);
-    BilVal c = bil_eval(t, b1);
+    BilVal c = bil_eval(t, F.b1);
     float f = L.f;
     r.dl = c.val - a.val;
     r.val = a.val + f * (c.val - a.val);
@@ -357,6 +370,16 @@ __device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float 
     r.dv = a.dv + f * (c.dv - a.dv);
   }
   return r;
+}
+__device__ __forceinline__ TriSample tex_trilinear(const Tex& t, float u, float v, float ul, float vl,
+                                                   const Lod& L) {
+  if (t.size == 1) return tri_eval(t, TriFoot{}, L);
+  return tri_eval(t, tri_foot(t, u, v, ul, vl, L), L);
+}
+// Two maps of one size and level count share their level selection and
+// footprints.
+__device__ __forceinline__ bool same_layout(const Tex& a, const Tex& b) {
+  return a.size == b.size && a.levels == b.levels;
 }
 
 // One bias-corrected Adam update (Sec. 5.3); c1 = 1/(1-b1^t), c2 = 1/(1-b2^t).

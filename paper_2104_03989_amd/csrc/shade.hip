@@ -733,6 +733,7 @@ __device__ __forceinline__ void stash_sample(float* col, int row, int ch, const 
 // screen derivatives, from the derivatives stash_sample parked.
 __device__ __forceinline__ void uv_bwd_parked(const float* col, int row, int ch, const Tex& t, bool use_x,
                                               const PixelGeom& g, f3 gs, UVGrad& G) {
+  if (t.size == 1) return;  // a one-texel map: nothing parked, no dependence on (u, v)
   const float gv[3] = {gs.x, gs.y, gs.z};
   float gu = 0.f, gw = 0.f, gm = 0.f;
 #pragma unroll
@@ -795,25 +796,29 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
     col[(kParkLam + 3 + c) * kAccStride] = __int_as_float(g.v[c]);
   }
   const bool ggx_m = a.model == ADR_SHADE_GGX;
+  // base colour and normal map: one level selection and one pair of
+  // footprints when the two maps have one size
+  const bool kn_same = same_layout(a.kd, a.nm);
   const Lod Lk = lod_select(a.kd, g.ux, g.vx, g.uy, g.vy);
-  const Lod Ln = lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
+  const Lod Ln = kn_same ? Lk : lod_select(a.nm, g.ux, g.vx, g.uy, g.vy);
   f3 kd, nt, ormv = mk(0.f, 0.f, 0.f);
+  const TriFoot Fk = a.kd.size > 1 ? tri_foot(a.kd, g.u, g.v_, g.ul, g.vl, Lk) : TriFoot{};
   {
-    const TriSample sk = tex_trilinear(a.kd, g.u, g.v_, g.ul, g.vl, Lk);
+    const TriSample sk = tri_eval(a.kd, Fk, Lk);
     kd = sk.val;
-    stash_sample(col, 0, 3, sk, Lk);
+    if (a.kd.size > 1) stash_sample(col, 0, 3, sk, Lk);
   }
   {
-    const TriSample sn = tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln);
+    const TriSample sn = kn_same ? tri_eval(a.nm, Fk, Ln) : tex_trilinear(a.nm, g.u, g.v_, g.ul, g.vl, Ln);
     nt = sn.val;
-    stash_sample(col, 9, 3, sn, Ln);
+    if (a.nm.size > 1) stash_sample(col, 9, 3, sn, Ln);
   }
   Lod Lo{};
   if (ggx_m) {
     Lo = lod_select(a.orm, g.ux, g.vx, g.uy, g.vy);
     const TriSample so = tex_trilinear(a.orm, g.u, g.v_, g.ul, g.vl, Lo);
     ormv = so.val;
-    stash_sample(col, 18, 3, so, Lo);
+    if (a.orm.size > 1) stash_sample(col, 18, 3, so, Lo);
   }
   Lod La{};
   float alpha_t = 0.f;
@@ -821,7 +826,7 @@ __device__ __forceinline__ bool shade_bwd_pixel(const ShadeArgs& a, const Pix& p
     La = lod_select(a.al, g.ux, g.vx, g.uy, g.vy);
     const TriSample sa = tex_trilinear(a.al, g.u, g.v_, g.ul, g.vl, La);
     alpha_t = sa.val.x;
-    stash_sample(col, 27, 1, sa, La);
+    if (a.al.size > 1) stash_sample(col, 27, 1, sa, La);
   }
   // the tangent frame, compact: N, T', T and 1/|Ni|, 1/|T1| (B = N x T')
   const f3 N = g.N, Tp = g.Tp, T = g.T;
