@@ -475,16 +475,23 @@ __device__ __forceinline__ void aa_fwd_body(const AAFwdArgs& f, int bid, int nb)
 ADR_KERNEL(__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))), k_aa_fwd, AAFwdArgs, aa_fwd_body)
 
 __device__ __forceinline__ void loss_reduce_body(const LossReduceArgs& a, int, int) {
-  __shared__ double red[256];
+  __shared__ double red[4];
+  // each thread's partials in a fixed order, sixteen loads in flight at a time
   double acc = 0.0;
-  for (int i = threadIdx.x; i < a.n; i += 256) acc += (double)a.partial[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
+  int i = threadIdx.x;
+  for (; i + 15 * 256 < a.n; i += 16 * 256) {
+    float x[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) x[q] = a.partial[i + q * 256];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += (double)x[q];
   }
-  if (threadIdx.x == 0) a.loss[0] = (float)(red[0] * (double)a.inv_n);
+  for (; i < a.n; i += 256) acc += (double)a.partial[i];
+  // then a fixed tree: within each wave, then the four waves
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) a.loss[0] = (float)(((red[0] + red[1]) + (red[2] + red[3])) * (double)a.inv_n);
 }
 ADR_KERNEL(__launch_bounds__(256), k_loss_reduce, LossReduceArgs, loss_reduce_body)
 
