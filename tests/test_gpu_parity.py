@@ -178,6 +178,20 @@ def test_gradients_blinn_phong_l2(ctx):
     _grad_case(ctx, w, ("pos", "kd", "normal"))
 
 
+def test_gradients_one_texel_maps(ctx):
+    """A latent with constant (one-texel) base-colour and ORM maps, all its
+    maps optimised: a one-texel map is looked up without the trilinear
+    arithmetic and receives every sample's gradient on its one texel; the
+    base colour and the 16^2 normal map (sizes differ) are looked up apart."""
+    _say("gradients one-texel maps")
+    import dataclasses
+    w = S.tiny_sphere_workload("ggx", nu=3, res=40, views=2, tex=16, loss="l1_tonemap", seed=5)
+    kd1 = synth.Texture(np.full((1, 1, 3), 0.45, np.float32), "f32")
+    orm1 = synth.Texture(np.array([[[0.1, 0.5, 0.2]]], np.float32), "f32")
+    w = dataclasses.replace(w, latent=dataclasses.replace(w.latent, kd=kd1, orm=orm1))
+    _grad_case(ctx, w, ("pos", "kd", "normal", "orm"))
+
+
 def test_gradients_paper_loop_reduced(ctx):
     _say("gradients paper reduced")
     w = synth.scaled(synth.workload_paper_loop(map_size=256, ref_nu=40, lat_nu=10), views=2, res=128)
